@@ -1,0 +1,280 @@
+"""FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+ctypes wrapper around liboracle.so (built from peo.c by oracle/build.py).
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package; the GPU library never does. All arrays are float64 numpy
+arrays; FP32/complex64 event inputs are promoted exactly before the call.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+PARAMS_4D = 0
+PARAMS_11D = 1
+PHASE_MARG = 0
+PHASE_EXPLICIT = 1
+MAX_DET = 4
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _Event(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int), ("n_bins", ctypes.c_long), ("f_lo", ctypes.c_double),
+                ("df", ctypes.c_double), ("data", _dp), ("psd", _dp), ("strain_scale", ctypes.c_double),
+                ("params", ctypes.c_int), ("phase", ctypes.c_int), ("amp0", ctypes.c_double),
+                ("gmst", ctypes.c_double), ("chi_max", ctypes.c_double), ("dl_max", ctypes.c_double),
+                ("det_geom", (ctypes.c_double * 3) * MAX_DET)]
+
+
+class _Source(ctypes.Structure):
+    _fields_ = [("in_support", ctypes.c_int), ("mc", ctypes.c_double), ("M", ctypes.c_double),
+                ("eta", ctypes.c_double), ("delta", ctypes.c_double), ("chi1", ctypes.c_double),
+                ("chi2", ctypes.c_double), ("tc", ctypes.c_double), ("phic", ctypes.c_double),
+                ("rre", ctypes.c_double * MAX_DET), ("rim", ctypes.c_double * MAX_DET),
+                ("dt", ctypes.c_double * MAX_DET), ("fisco", ctypes.c_double), ("kcut", ctypes.c_long),
+                ("phi", ctypes.c_double * 8), ("phil", ctypes.c_double * 8)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            _build.build()
+        L = ctypes.CDLL(path)
+        L.peo_t_sun.restype = ctypes.c_double
+        L.peo_mpc_m.restype = ctypes.c_double
+        L.peo_c_si.restype = ctypes.c_double
+        L.peo_r_earth.restype = ctypes.c_double
+        L.peo_psi.restype = ctypes.c_double
+        L.peo_psi.argtypes = [ctypes.POINTER(_Source), ctypes.c_double]
+        L.peo_f_isco.restype = ctypes.c_double
+        L.peo_f_isco.argtypes = [ctypes.c_double]
+        L.peo_kcut.restype = ctypes.c_long
+        L.peo_kcut.argtypes = [ctypes.POINTER(_Event), ctypes.c_double]
+        L.peo_pn_coeffs.argtypes = [ctypes.c_double] * 4 + [_dp, _dp]
+        L.peo_antenna.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  _dp, _dp, _dp]
+        L.peo_source_from_theta.restype = ctypes.c_int
+        L.peo_source_from_theta.argtypes = [ctypes.POINTER(_Event), _dp, ctypes.POINTER(_Source)]
+        L.peo_waveform.argtypes = [ctypes.POINTER(_Event), _dp, ctypes.c_long, _dp]
+        L.peo_inner.restype = ctypes.c_double
+        L.peo_inner.argtypes = [ctypes.POINTER(_Event), ctypes.c_int, _dp, _dp]
+        L.peo_log_i0.restype = ctypes.c_double
+        L.peo_log_i0.argtypes = [ctypes.c_double]
+        L.peo_loglike.argtypes = [ctypes.POINTER(_Event), _dp, ctypes.c_long, _dp, _dp, ctypes.c_int]
+        L.peo_default_steps.argtypes = [ctypes.POINTER(_Event), _dp, _dp]
+        L.peo_metric_fd.restype = ctypes.c_int
+        L.peo_metric_fd.argtypes = [ctypes.POINTER(_Event), _dp, _dp, ctypes.c_int, _dp]
+        L.peo_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                        ctypes.POINTER(ctypes.c_uint32)]
+        L.peo_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_long, ctypes.c_int, _dp]
+        L.peo_draw.restype = ctypes.c_int
+        L.peo_draw.argtypes = [ctypes.POINTER(_Event), _dp, _dp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_long,
+                               _dp, _dp, _dp]
+        L.peo_logq_theta.restype = ctypes.c_int
+        L.peo_logq_theta.argtypes = [ctypes.POINTER(_Event), _dp, _dp, _dp, ctypes.c_long, _dp]
+        L.peo_logprior.restype = ctypes.c_double
+        L.peo_logprior.argtypes = [ctypes.POINTER(_Event), _dp]
+        L.peo_weights_ess.argtypes = [_dp, _dp, _dp, ctypes.c_long, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def t_sun():
+    return lib().peo_t_sun()
+
+
+def mpc_m():
+    return lib().peo_mpc_m()
+
+
+def c_si():
+    return lib().peo_c_si()
+
+
+def r_earth():
+    return lib().peo_r_earth()
+
+
+class Event:
+    """An event for the oracle. data: complex [n_det, K] (any complex dtype, promoted exactly),
+    psd: real [n_det, K]. data/psd may be None for template-only use (psd needed for inner products)."""
+
+    def __init__(self, n_det, n_bins, f_lo, df, data=None, psd=None, strain_scale=1.0, params=PARAMS_11D,
+                 phase=PHASE_EXPLICIT, amp0=0.0, gmst=0.0, chi_max=0.4, dl_max=1e4, det_geom=None):
+        self.n_det = int(n_det)
+        self.n_bins = int(n_bins)
+        self.f_lo = float(f_lo)
+        self.df = float(df)
+        self.params = int(params)
+        self.phase = int(phase)
+        self.dim = 4 if self.params == PARAMS_4D else 11
+        if data is not None:
+            d = np.asarray(data)
+            assert d.shape == (self.n_det, self.n_bins)
+            self._data = np.ascontiguousarray(np.stack([d.real.astype(np.float64), d.imag.astype(np.float64)], -1))
+        else:
+            self._data = None
+        self._psd = _f64(psd) if psd is not None else None
+        if self._psd is not None:
+            assert self._psd.shape == (self.n_det, self.n_bins)
+        s = _Event()
+        s.n_det = self.n_det
+        s.n_bins = self.n_bins
+        s.f_lo = self.f_lo
+        s.df = self.df
+        s.data = _p(self._data) if self._data is not None else _dp()
+        s.psd = _p(self._psd) if self._psd is not None else _dp()
+        s.strain_scale = float(strain_scale)
+        s.params = self.params
+        s.phase = self.phase
+        s.amp0 = float(amp0)
+        s.gmst = float(gmst)
+        s.chi_max = float(chi_max)
+        s.dl_max = float(dl_max)
+        if det_geom is not None:
+            g = np.asarray(det_geom, dtype=np.float64).reshape(-1, 3)
+            for i in range(g.shape[0]):
+                for j in range(3):
+                    s.det_geom[i][j] = g[i, j]
+        self._s = s
+
+    @property
+    def ref(self):
+        return ctypes.byref(self._s)
+
+    # ---- model pieces ----
+    def source(self, theta):
+        th = _f64(theta)
+        src = _Source()
+        ok = lib().peo_source_from_theta(self.ref, _p(th), ctypes.byref(src))
+        return bool(ok), src
+
+    def psi(self, theta, f):
+        _, src = self.source(theta)
+        return np.array([lib().peo_psi(ctypes.byref(src), float(x)) for x in np.atleast_1d(f)])
+
+    def kcut(self, fisco):
+        return lib().peo_kcut(self.ref, float(fisco))
+
+    def waveform(self, theta, kcut_override=-1):
+        th = _f64(theta)
+        h = np.zeros((self.n_det, self.n_bins, 2))
+        lib().peo_waveform(self.ref, _p(th), int(kcut_override), _p(h))
+        return h[..., 0] + 1j * h[..., 1]
+
+    def inner(self, d, a, b):
+        """(a|b) for detector d; a, b complex [n_det, K]."""
+        A = np.ascontiguousarray(np.stack([a.real, a.imag], -1).astype(np.float64))
+        B = np.ascontiguousarray(np.stack([b.real, b.imag], -1).astype(np.float64))
+        return lib().peo_inner(self.ref, int(d), _p(A), _p(B))
+
+    # ---- likelihood ----
+    def loglike(self, theta, n_threads=0, return_zh=False):
+        th = _f64(theta)
+        D, n = th.shape
+        assert D == self.dim
+        ll = np.empty(n)
+        zh = np.empty((n, 3))
+        lib().peo_loglike(self.ref, _p(th), n, _p(ll), _p(zh), int(n_threads))
+        return (ll, zh) if return_zh else ll
+
+    def default_steps(self, theta0):
+        th = _f64(theta0)
+        st = np.zeros(self.dim)
+        lib().peo_default_steps(self.ref, _p(th), _p(st))
+        return st
+
+    def metric(self, theta0, steps=None, flags=0):
+        th = _f64(theta0)
+        st = self.default_steps(th) if steps is None else _f64(steps)
+        n = self.dim + (1 if (flags & 2) and self.params == PARAMS_4D else 0)
+        g = np.zeros((n, n))
+        lib().peo_metric_fd(self.ref, _p(th), _p(st), int(flags), _p(g))
+        return g
+
+    def draw(self, theta0, g, seed, stream, n):
+        th0 = _f64(theta0)
+        gg = _f64(g)
+        theta = np.zeros((self.dim, n))
+        lq = np.zeros(n)
+        lp = np.zeros(n)
+        rc = lib().peo_draw(self.ref, _p(th0), _p(gg), int(seed), int(stream), int(n), _p(theta), _p(lq), _p(lp))
+        return rc, theta, lq, lp
+
+    def logq_theta(self, theta0, g, theta):
+        th0 = _f64(theta0)
+        gg = _f64(g)
+        th = _f64(theta)
+        n = th.shape[1]
+        lq = np.zeros(n)
+        rc = lib().peo_logq_theta(self.ref, _p(th0), _p(gg), _p(th), n, _p(lq))
+        return rc, lq
+
+    def logprior(self, theta):
+        th = _f64(theta)
+        return lib().peo_logprior(self.ref, _p(th))
+
+
+def pn_coeffs(eta, delta, chi1, chi2):
+    phi = np.zeros(8)
+    phil = np.zeros(8)
+    lib().peo_pn_coeffs(float(eta), float(delta), float(chi1), float(chi2), _p(phi), _p(phil))
+    return phi, phil
+
+
+def f_isco(M):
+    return lib().peo_f_isco(float(M))
+
+
+def antenna(geom, ra, dec, psi, gmst=0.0):
+    g = _f64(geom)
+    fp = np.zeros(1)
+    fc = np.zeros(1)
+    dt = np.zeros(1)
+    lib().peo_antenna(_p(g), float(ra), float(dec), float(psi), float(gmst), _p(fp), _p(fc), _p(dt))
+    return fp[0], fc[0], dt[0]
+
+
+def log_i0(x):
+    return lib().peo_log_i0(float(x))
+
+
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().peo_philox4x32_10(c, k, o)
+    return [int(o[i]) for i in range(4)]
+
+
+def uniforms(seed, stream, n, npairs):
+    u = np.zeros((n, npairs, 2))
+    lib().peo_uniforms(int(seed), int(stream), int(n), int(npairs), _p(u))
+    return u
+
+
+def weights_ess(loglike, logprior, logq):
+    ll = _f64(loglike)
+    lp = _f64(logprior)
+    lq = _f64(logq)
+    n = ll.shape[0]
+    w = np.zeros(n)
+    st = np.zeros(4)
+    lib().peo_weights_ess(_p(ll), _p(lp), _p(lq), n, _p(w), _p(st))
+    return w, st

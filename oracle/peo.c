@@ -1,0 +1,775 @@
+/*
+ * peo.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY; see peo.h).
+ *
+ * Nitz, "Robust, Rapid, and Simple Gravitational-wave Parameter Estimation",
+ * arXiv:2410.05190. Each function names the passage of the paper it follows,
+ * or the published source of the model piece the paper leaves open.
+ * Built with gcc -O2 (no fast-math); OpenMP only splits independent draws.
+ */
+#include "peo.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const double PI = 3.14159265358979323846;
+static const double EULER_GAMMA = 0.5772156649015329;
+
+/* Physical constants (the paper fixes none): IAU nominal GM_sun, exact c,
+ * the IAU parsec, and a spherical Earth of the mean radius. */
+static const double GM_SUN = 1.32712440018e20; /* m^3 s^-2 */
+static const double C_SI = 299792458.0;         /* m/s */
+static const double MPC_M = 3.0856775814913673e22;
+static const double R_EARTH = 6.371e6;
+
+double peo_t_sun(void) { return GM_SUN / (C_SI * C_SI * C_SI); }
+double peo_mpc_m(void) { return MPC_M; }
+double peo_c_si(void) { return C_SI; }
+double peo_r_earth(void) { return R_EARTH; }
+
+int peo_dim(int params) { return params == PEO_PARAMS_4D ? 4 : 11; }
+
+/* Neumaier compensated summation. */
+typedef struct {
+    double s, c;
+} nsum;
+static void nadd(nsum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x))
+        a->c += (a->s - t) + x;
+    else
+        a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double nval(const nsum *a) { return a->s + a->c; }
+
+/*
+ * TaylorF2 phase coefficients (stationary-phase approximation of the
+ * inspiral). Non-spinning terms to 3.5PN: Buonanno, Iyer, Ochsner, Pan,
+ * Sathyaprakash, PRD 80, 084043 (2009), TaylorF2 phase. Aligned-spin terms:
+ * spin-orbit at 1.5, 2.5, 3 and 3.5PN and spin-spin at 2PN (black-hole
+ * quadrupole), as compiled by Mishra, Kela, Arun, Faye, PRD 93, 084054 (2016);
+ * here written per body, with S = x1^2 chi1 + x2^2 chi2 and
+ * Sig = x2 chi2 - x1 chi1 (x_i = m_i / M).
+ * The 5th-order term carries (1 + 3 ln v) with the reference velocity 1: the
+ * constant belongs to the coalescence phase.
+ */
+void peo_pn_coeffs(double eta, double delta, double chi1, double chi2, double phi[8], double phil[8])
+{
+    const double x1 = 0.5 * (1.0 + delta), x2 = 0.5 * (1.0 - delta);
+    const double S = x1 * x1 * chi1 + x2 * x2 * chi2;
+    const double Sig = x2 * chi2 - x1 * chi1;
+    const double eta2 = eta * eta, eta3 = eta2 * eta;
+    const double pi2 = PI * PI;
+    int j;
+    for (j = 0; j < 8; j++) {
+        phi[j] = 0.0;
+        phil[j] = 0.0;
+    }
+    phi[0] = 1.0;
+    phi[1] = 0.0;
+    phi[2] = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
+    /* 1.5PN: tail + spin-orbit */
+    phi[3] = -16.0 * PI + 188.0 / 3.0 * S + 25.0 * delta * Sig;
+    /* 2PN: point mass + spin-spin sigma */
+    {
+        double sigma = 79.0 / 8.0 * eta * chi1 * chi2 + 81.0 / 16.0 * (x1 * x1 * chi1 * chi1 + x2 * x2 * chi2 * chi2);
+        phi[4] = 15293365.0 / 508032.0 + 27145.0 / 504.0 * eta + 3085.0 / 72.0 * eta2 - 10.0 * sigma;
+    }
+    /* 2.5PN: point mass + spin-orbit gamma; log term 3x */
+    {
+        double gam = (554345.0 / 1134.0 + 110.0 / 9.0 * eta) * S + (13915.0 / 84.0 - 10.0 / 3.0 * eta) * delta * Sig;
+        phi[5] = PI * (38645.0 / 756.0 - 65.0 / 9.0 * eta) - gam;
+        phil[5] = 3.0 * phi[5];
+    }
+    /* 3PN: point mass (with ln(4v) split into ln 4 + ln v) + spin-orbit tail */
+    phi[6] = 11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * pi2 - 6848.0 / 21.0 * EULER_GAMMA -
+             6848.0 / 21.0 * log(4.0) + (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * pi2) * eta +
+             76055.0 / 1728.0 * eta2 - 127825.0 / 1296.0 * eta3 + PI * (3760.0 * S + 1490.0 * delta * Sig) / 3.0;
+    phil[6] = -6848.0 / 21.0;
+    /* 3.5PN: point mass + spin-orbit */
+    phi[7] = PI * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * eta2) +
+             (-8980424995.0 / 762048.0 + 6586595.0 / 756.0 * eta - 305.0 / 36.0 * eta2) * S -
+             (170978035.0 / 48384.0 - 2876425.0 / 672.0 * eta - 4735.0 / 144.0 * eta2) * delta * Sig;
+}
+
+/* Psi(f) = 2 pi f tc - phic - pi/4 + 3/(128 eta v^5) sum_j (phi_j + phil_j ln v) v^j,
+ * v = (pi M f)^(1/3), M in seconds. */
+double peo_psi(const peo_source *s, double f)
+{
+    const double v = cbrt(PI * s->M * peo_t_sun() * f);
+    const double lnv = log(v);
+    double sum = 0.0, vk = 1.0;
+    int j;
+    for (j = 0; j < 8; j++) {
+        sum += (s->phi[j] + s->phil[j] * lnv) * vk;
+        vk *= v;
+    }
+    return 2.0 * PI * f * s->tc - s->phic - PI / 4.0 + 3.0 / (128.0 * s->eta * pow(v, 5.0)) * sum;
+}
+
+/* Test-mass ISCO of the total mass: f = 1/(6^(3/2) pi M). */
+double peo_f_isco(double M) { return 1.0 / (pow(6.0, 1.5) * PI * M * peo_t_sun()); }
+
+/* Number of bins with f_k < f_isco (brute force). */
+long peo_kcut(const peo_event *ev, double fisco)
+{
+    long k = 0;
+    while (k < ev->n_bins && ev->f_lo + (double)k * ev->df < fisco)
+        k++;
+    return k;
+}
+
+/* Long-wavelength response of an L-shaped detector on a spherical Earth.
+ * Detector tensor D = (x x^T - y y^T)/2 with the y arm 90 degrees east of x;
+ * polarisation tensors from the sky basis rotated by psi. */
+void peo_antenna(const double geom[3], double ra, double dec, double psi, double gmst, double *fplus,
+                 double *fcross, double *dt)
+{
+    const double lat = geom[0], lon = geom[1], az = geom[2];
+    double up[3], east[3], north[3], xa[3], ya[3], Dt[3][3];
+    double n[3], u[3], w[3], X[3], Y[3];
+    double lam = ra - gmst;
+    double fp = 0.0, fc = 0.0, rn = 0.0;
+    int i, j;
+    up[0] = cos(lat) * cos(lon);
+    up[1] = cos(lat) * sin(lon);
+    up[2] = sin(lat);
+    east[0] = -sin(lon);
+    east[1] = cos(lon);
+    east[2] = 0.0;
+    north[0] = -sin(lat) * cos(lon);
+    north[1] = -sin(lat) * sin(lon);
+    north[2] = cos(lat);
+    for (i = 0; i < 3; i++) {
+        xa[i] = cos(az) * north[i] + sin(az) * east[i];
+        ya[i] = -sin(az) * north[i] + cos(az) * east[i];
+    }
+    for (i = 0; i < 3; i++)
+        for (j = 0; j < 3; j++)
+            Dt[i][j] = 0.5 * (xa[i] * xa[j] - ya[i] * ya[j]);
+    n[0] = cos(dec) * cos(lam);
+    n[1] = cos(dec) * sin(lam);
+    n[2] = sin(dec);
+    u[0] = -sin(lam);
+    u[1] = cos(lam);
+    u[2] = 0.0;
+    w[0] = -sin(dec) * cos(lam);
+    w[1] = -sin(dec) * sin(lam);
+    w[2] = cos(dec);
+    for (i = 0; i < 3; i++) {
+        X[i] = cos(psi) * u[i] + sin(psi) * w[i];
+        Y[i] = -sin(psi) * u[i] + cos(psi) * w[i];
+    }
+    for (i = 0; i < 3; i++)
+        for (j = 0; j < 3; j++) {
+            fp += Dt[i][j] * (X[i] * X[j] - Y[i] * Y[j]);
+            fc += Dt[i][j] * (X[i] * Y[j] + Y[i] * X[j]);
+        }
+    for (i = 0; i < 3; i++)
+        rn += up[i] * n[i];
+    *fplus = fp;
+    *fcross = fc;
+    *dt = -R_EARTH * rn / C_SI;
+}
+
+int peo_source_from_theta(const peo_event *ev, const double *th, peo_source *s)
+{
+    int d, ok;
+    memset(s, 0, sizeof(*s));
+    if (ev->params == PEO_PARAMS_4D) {
+        double mc = th[0], eta = th[1], chi = th[2];
+        s->mc = mc;
+        s->eta = eta;
+        s->M = mc * pow(eta, -0.6);
+        s->delta = sqrt(fmax(0.0, 1.0 - 4.0 * eta));
+        s->chi1 = chi;
+        s->chi2 = chi;
+        s->tc = th[3];
+        s->phic = 0.0;
+        for (d = 0; d < ev->n_det; d++) {
+            s->rre[d] = ev->amp0 * ev->strain_scale;
+            s->rim[d] = 0.0;
+            s->dt[d] = 0.0;
+        }
+        ok = (mc > 0.0) && (eta > 0.0) && (eta <= 0.25) && (fabs(chi) <= ev->chi_max);
+    } else {
+        double mc = th[0], q = th[1], ra = th[4], dec = th[5], iota = th[6], psi = th[7], dl = th[8];
+        double amp, ci = cos(iota);
+        s->mc = mc;
+        s->eta = q / ((1.0 + q) * (1.0 + q));
+        s->M = mc * pow(1.0 + q, 1.2) * pow(q, -0.6);
+        s->delta = (1.0 - q) / (1.0 + q);
+        s->chi1 = th[2];
+        s->chi2 = th[3];
+        s->tc = th[9];
+        s->phic = (ev->phase == PEO_PHASE_EXPLICIT) ? th[10] : 0.0;
+        /* Newtonian SPA amplitude: sqrt(5/24) pi^(-2/3) Mc^(5/6) / dL (G = c = 1) */
+        amp = sqrt(5.0 / 24.0) * pow(PI, -2.0 / 3.0) * pow(mc * peo_t_sun(), 5.0 / 6.0) / (dl * MPC_M / C_SI);
+        amp *= ev->strain_scale;
+        for (d = 0; d < ev->n_det; d++) {
+            double fp, fc, dt;
+            peo_antenna(ev->det_geom[d], ra, dec, psi, ev->gmst, &fp, &fc, &dt);
+            /* h_d = F+ h+ + Fx hx, h+ = A (1+cos^2 i)/2 e^{-i Phi}, hx = -i A cos i e^{-i Phi} */
+            s->rre[d] = amp * fp * 0.5 * (1.0 + ci * ci);
+            s->rim[d] = -amp * fc * ci;
+            s->dt[d] = dt;
+        }
+        ok = (mc > 0.0) && (q > 0.0) && (q <= 1.0) && (fabs(th[2]) <= ev->chi_max) &&
+             (fabs(th[3]) <= ev->chi_max) && (fabs(dec) <= 0.5 * PI) && (iota >= 0.0) && (iota <= PI) &&
+             (dl > 0.0) && (dl <= ev->dl_max);
+    }
+    peo_pn_coeffs(s->eta, s->delta, s->chi1, s->chi2, s->phi, s->phil);
+    s->fisco = peo_f_isco(s->M);
+    s->kcut = ok ? peo_kcut(ev, s->fisco) : 0;
+    s->in_support = ok;
+    return ok;
+}
+
+/* Model waveform of detector d at bin k: R_d f^-7/6 exp(-i [Psi(f) + 2 pi f dt_d]). */
+static void wf_bin(const peo_event *ev, const peo_source *s, int d, long k, double *hr, double *hi)
+{
+    const double f = ev->f_lo + (double)k * ev->df;
+    const double ph = peo_psi(s, f) + 2.0 * PI * f * s->dt[d];
+    const double a = pow(f, -7.0 / 6.0);
+    const double c = cos(ph), sn = sin(ph);
+    /* (rre + i rim)(c - i sn) */
+    *hr = a * (s->rre[d] * c + s->rim[d] * sn);
+    *hi = a * (s->rim[d] * c - s->rre[d] * sn);
+}
+
+void peo_waveform(const peo_event *ev, const double *theta, long kcut_override, double *h)
+{
+    peo_source s;
+    long k, kc;
+    int d;
+    peo_source_from_theta(ev, theta, &s);
+    kc = kcut_override >= 0 ? kcut_override : peo_kcut(ev, s.fisco);
+    if (kc > ev->n_bins)
+        kc = ev->n_bins;
+    for (d = 0; d < ev->n_det; d++)
+        for (k = 0; k < ev->n_bins; k++) {
+            double *o = h + 2 * ((long)d * ev->n_bins + k);
+            if (k < kc)
+                wf_bin(ev, &s, d, k, &o[0], &o[1]);
+            else
+                o[0] = o[1] = 0.0;
+        }
+}
+
+/* Eq. 1 discretised: (a|b) = 4 df Re sum_k conj(a_k) b_k / S_k. */
+double peo_inner(const peo_event *ev, int d, const double *a, const double *b)
+{
+    nsum acc = {0.0, 0.0};
+    long k;
+    const double *S = ev->psd + (long)d * ev->n_bins;
+    const double *ad = a + 2 * (long)d * ev->n_bins, *bd = b + 2 * (long)d * ev->n_bins;
+    for (k = 0; k < ev->n_bins; k++)
+        nadd(&acc, 4.0 * ev->df * (ad[2 * k] * bd[2 * k] + ad[2 * k + 1] * bd[2 * k + 1]) / S[k]);
+    return nval(&acc);
+}
+
+/* ln I0(x) from the integral representation I0(x) = (1/pi) int_0^pi exp(x cos t) dt
+ * (DLMF 10.32.1), trapezoid rule: exponentially convergent for this periodic
+ * analytic integrand. exp(x (cos t - 1)) is written as exp(-2 x sin^2(t/2)); the
+ * range is cut where that factor falls below e^-750 (it is even about t = 0, so the
+ * truncated rule keeps its exponential convergence). */
+double peo_log_i0(double x)
+{
+    const long m = 4096;
+    long i;
+    double tmax = PI, s;
+    nsum acc = {0.0, 0.0};
+    x = fabs(x);
+    if (x == 0.0)
+        return 0.0;
+    s = sqrt(375.0 / x);
+    if (s < 1.0)
+        tmax = 2.0 * asin(s);
+    for (i = 0; i <= m; i++) {
+        double t = tmax * (double)i / (double)m;
+        double sh = sin(0.5 * t);
+        double wgt = (i == 0 || i == m) ? 0.5 : 1.0;
+        nadd(&acc, wgt * exp(-2.0 * x * sh * sh));
+    }
+    return x + log(nval(&acc) * tmax / (PI * (double)m));
+}
+
+/* Eq. 3 with Eq. 1: Z = sum_d (d_d|h_d) as a complex overlap, H = sum_d (h_d|h_d).
+ * Explicit phase: ln L = Re Z - H/2. Marginalised over a uniform coalescence
+ * phase: ln L = ln I0(|Z|) - H/2. */
+static double loglike_one(const peo_event *ev, const double *th, double *zh)
+{
+    peo_source s;
+    nsum zr = {0, 0}, zi = {0, 0}, hh = {0, 0};
+    int d;
+    long k;
+    double Zr, Zi, H;
+    if (!peo_source_from_theta(ev, th, &s)) {
+        if (zh)
+            zh[0] = zh[1] = zh[2] = 0.0;
+        return -INFINITY;
+    }
+    for (d = 0; d < ev->n_det; d++) {
+        const double *S = ev->psd + (long)d * ev->n_bins;
+        const double *dd = ev->data + 2 * (long)d * ev->n_bins;
+        for (k = 0; k < s.kcut; k++) {
+            double hr, hi, w;
+            wf_bin(ev, &s, d, k, &hr, &hi);
+            w = 4.0 * ev->df / S[k];
+            /* conj(d) h */
+            nadd(&zr, w * (dd[2 * k] * hr + dd[2 * k + 1] * hi));
+            nadd(&zi, w * (dd[2 * k] * hi - dd[2 * k + 1] * hr));
+            nadd(&hh, w * (hr * hr + hi * hi));
+        }
+    }
+    Zr = nval(&zr);
+    Zi = nval(&zi);
+    H = nval(&hh);
+    if (zh) {
+        zh[0] = Zr;
+        zh[1] = Zi;
+        zh[2] = H;
+    }
+    if (ev->phase == PEO_PHASE_EXPLICIT)
+        return Zr - 0.5 * H;
+    return peo_log_i0(hypot(Zr, Zi)) - 0.5 * H;
+}
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+void peo_loglike(const peo_event *ev, const double *theta, long n, double *loglike, double *zh, int n_threads)
+{
+    const int D = peo_dim(ev->params);
+    long i;
+#ifdef _OPENMP
+    if (n_threads > 0)
+        omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (i = 0; i < n; i++) {
+        double th[PEO_MAX_DIM];
+        int j;
+        for (j = 0; j < D; j++)
+            th[j] = theta[(long)j * n + i];
+        loglike[i] = loglike_one(ev, th, zh ? zh + 3 * i : NULL);
+    }
+    (void)n_threads;
+}
+
+/* Finite-difference steps (a reading of the method; the paper fixes none):
+ * each step moves the waveform phase by about 1e-3 rad at the band edge that
+ * is most sensitive to it, from the Newtonian phase Phi_N(f) = 3/128 (pi Mc f)^(-5/3);
+ * amplitude-only angles use 1e-4 rad and the distance 1e-4 dL. */
+void peo_default_steps(const peo_event *ev, const double *th, double *st)
+{
+    peo_source s;
+    double fhi = ev->f_lo + (double)ev->n_bins * ev->df;
+    double ftop, phin, mc = th[0];
+    peo_source_from_theta(ev, th, &s);
+    ftop = s.fisco < fhi ? s.fisco : fhi;
+    phin = 3.0 / 128.0 * pow(PI * mc * peo_t_sun() * ev->f_lo, -5.0 / 3.0);
+    if (ev->params == PEO_PARAMS_4D) {
+        st[0] = 1e-3 * mc / (5.0 / 3.0 * phin);
+        st[1] = 1e-3 / phin;
+        st[2] = 1e-3 / phin;
+        st[3] = 1e-3 / (2.0 * PI * ftop);
+    } else {
+        double sky = 1e-3 / (2.0 * PI * ftop * R_EARTH / C_SI);
+        st[0] = 1e-3 * mc / (5.0 / 3.0 * phin);
+        st[1] = 1e-3 / phin;
+        st[2] = 1e-3 / phin;
+        st[3] = 1e-3 / phin;
+        st[4] = sky;
+        st[5] = sky;
+        st[6] = 1e-4;
+        st[7] = 1e-4;
+        st[8] = 1e-4 * th[8];
+        st[9] = 1e-3 / (2.0 * PI * ftop);
+        st[10] = 0.0; /* coalescence phase: analytic column */
+    }
+}
+
+/* Prior regularisation 12/range^2 (the precision of a uniform distribution
+ * over the prior range) for bounded and periodic coordinates. */
+static void prior_reg(const peo_event *ev, double *reg)
+{
+    if (ev->params == PEO_PARAMS_4D) {
+        reg[0] = 0.0;
+        reg[1] = 12.0 / (0.25 * 0.25);
+        reg[2] = 12.0 / (4.0 * ev->chi_max * ev->chi_max);
+        reg[3] = 0.0;
+    } else {
+        reg[0] = 0.0;
+        reg[1] = 12.0;
+        reg[2] = reg[3] = 12.0 / (4.0 * ev->chi_max * ev->chi_max);
+        reg[4] = 12.0 / (4.0 * PI * PI);
+        reg[5] = 12.0 / (PI * PI);
+        reg[6] = 12.0 / (PI * PI);
+        reg[7] = 12.0 / (PI * PI);
+        reg[8] = 12.0 / (ev->dl_max * ev->dl_max);
+        reg[9] = 0.0;
+        reg[10] = 12.0 / (4.0 * PI * PI);
+    }
+}
+
+/*
+ * Fisher metric of the network waveform, g_ij = sum_d (d_i h_d | d_j h_d)
+ * (the metric induced by the inner product, Sec. II.A), with the cut frozen at
+ * theta0, central differences for every sampled coordinate except the
+ * coalescence phase, whose derivative is exactly i h. For the marginalised
+ * likelihood the phase direction is projected out (Schur complement).
+ */
+int peo_metric_fd(const peo_event *ev, const double *th0, const double *steps, int flags, double *g)
+{
+    const int D = peo_dim(ev->params);
+    const int is4 = (ev->params == PEO_PARAMS_4D);
+    const int Dp = is4 ? D + 1 : D;  /* with the phase column */
+    const int iphi = is4 ? D : 10;   /* index of the phase coordinate */
+    peo_source s0, sp[PEO_MAX_DIM], sm[PEO_MAX_DIM];
+    double den[PEO_MAX_DIM];
+    int fd[PEO_MAX_DIM + 1];
+    nsum G[PEO_MAX_DIM + 1][PEO_MAX_DIM + 1];
+    double Gd[PEO_MAX_DIM + 1][PEO_MAX_DIM + 1];
+    double reg[PEO_MAX_DIM];
+    int a, b, d;
+    long k;
+    peo_source_from_theta(ev, th0, &s0);
+    /* frozen cut */
+    s0.kcut = peo_kcut(ev, s0.fisco);
+    memset(G, 0, sizeof(G));
+    for (a = 0; a < Dp; a++)
+        fd[a] = (a != iphi);
+    for (a = 0; a < D; a++) {
+        double tp[PEO_MAX_DIM], tm[PEO_MAX_DIM];
+        if (!fd[a])
+            continue;
+        memcpy(tp, th0, sizeof(double) * D);
+        memcpy(tm, th0, sizeof(double) * D);
+        tp[a] = th0[a] + steps[a];
+        tm[a] = th0[a] - steps[a];
+        den[a] = (tp[a] - th0[a]) + (th0[a] - tm[a]);
+        peo_source_from_theta(ev, tp, &sp[a]);
+        peo_source_from_theta(ev, tm, &sm[a]);
+    }
+    for (d = 0; d < ev->n_det; d++) {
+        const double *S = ev->psd + (long)d * ev->n_bins;
+        for (k = 0; k < s0.kcut; k++) {
+            double dr[PEO_MAX_DIM + 1], di[PEO_MAX_DIM + 1];
+            double w = 4.0 * ev->df / S[k];
+            for (a = 0; a < Dp; a++) {
+                if (fd[a]) {
+                    double pr, pi_, mr, mi;
+                    wf_bin(ev, &sp[a], d, k, &pr, &pi_);
+                    wf_bin(ev, &sm[a], d, k, &mr, &mi);
+                    dr[a] = (pr - mr) / den[a];
+                    di[a] = (pi_ - mi) / den[a];
+                } else {
+                    double hr, hi;
+                    wf_bin(ev, &s0, d, k, &hr, &hi);
+                    /* d h / d phic = i h */
+                    dr[a] = -hi;
+                    di[a] = hr;
+                }
+            }
+            for (a = 0; a < Dp; a++)
+                for (b = a; b < Dp; b++)
+                    nadd(&G[a][b], w * (dr[a] * dr[b] + di[a] * di[b]));
+        }
+    }
+    for (a = 0; a < Dp; a++)
+        for (b = a; b < Dp; b++)
+            Gd[a][b] = Gd[b][a] = nval(&G[a][b]);
+
+    if (flags & 2) {
+        for (a = 0; a < Dp; a++)
+            for (b = 0; b < Dp; b++)
+                g[a * Dp + b] = Gd[a][b];
+        return 0;
+    }
+    /* project out the phase for the marginalised likelihood */
+    if (ev->phase == PEO_PHASE_MARG) {
+        double gpp = Gd[iphi][iphi];
+        double P[PEO_MAX_DIM + 1][PEO_MAX_DIM + 1];
+        for (a = 0; a < Dp; a++)
+            for (b = 0; b < Dp; b++)
+                P[a][b] = (a == iphi || b == iphi) ? 0.0 : Gd[a][b] - Gd[a][iphi] * Gd[iphi][b] / gpp;
+        memcpy(Gd, P, sizeof(P));
+    }
+    for (a = 0; a < D; a++)
+        for (b = 0; b < D; b++)
+            g[a * D + b] = Gd[a][b];
+    if (!(flags & 1)) {
+        prior_reg(ev, reg);
+        for (a = 0; a < D; a++)
+            g[a * D + a] += reg[a];
+    }
+    return 0;
+}
+
+/* ---------------- draws (proposal N(theta0, g^-1)) ---------------- */
+
+static uint32_t mulhilo32(uint32_t a, uint32_t b, uint32_t *hi)
+{
+    uint64_t p = (uint64_t)a * (uint64_t)b;
+    *hi = (uint32_t)(p >> 32);
+    return (uint32_t)p;
+}
+
+/* Philox4x32 with 10 rounds, as defined by Salmon et al. (SC'11): two 32x32->64
+ * multiplies per round, Weyl-sequence key schedule. */
+void peo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    int r;
+    for (r = 0; r < 10; r++) {
+        uint32_t hi0, hi1;
+        uint32_t lo0 = mulhilo32(0xD2511F53u, x0, &hi0);
+        uint32_t lo1 = mulhilo32(0xCD9E8D57u, x2, &hi1);
+        uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+/* 53-bit uniform on (0, 1] from two words: 27 high bits of a, 26 of b. */
+static double u53(uint32_t a, uint32_t b)
+{
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 1.0) * (1.0 / 9007199254740992.0);
+}
+
+/* Block (i, j): counter (i lo, i hi, j, stream), key (seed lo, seed hi). */
+static void block_uniforms(uint64_t seed, uint32_t stream, uint64_t i, uint32_t j, double *ua, double *ub)
+{
+    uint32_t ctr[4], key[2], o[4];
+    ctr[0] = (uint32_t)i;
+    ctr[1] = (uint32_t)(i >> 32);
+    ctr[2] = j;
+    ctr[3] = stream;
+    key[0] = (uint32_t)seed;
+    key[1] = (uint32_t)(seed >> 32);
+    peo_philox4x32_10(ctr, key, o);
+    *ua = u53(o[0], o[1]);
+    *ub = u53(o[2], o[3]);
+}
+
+void peo_uniforms(uint64_t seed, uint32_t stream, long n, int npairs, double *u)
+{
+    long i;
+    int j;
+    for (i = 0; i < n; i++)
+        for (j = 0; j < npairs; j++)
+            block_uniforms(seed, stream, (uint64_t)i, (uint32_t)j, &u[i * 2 * npairs + 2 * j],
+                           &u[i * 2 * npairs + 2 * j + 1]);
+}
+
+/* Cholesky g = L L^T (row-major lower L). Returns 0, or 3 if not positive definite. */
+static int cholesky(const double *g, int D, double *L)
+{
+    int i, j, k;
+    memset(L, 0, sizeof(double) * D * D);
+    for (i = 0; i < D; i++)
+        for (j = 0; j <= i; j++) {
+            double s = g[i * D + j];
+            for (k = 0; k < j; k++)
+                s -= L[i * D + k] * L[j * D + k];
+            if (i == j) {
+                if (!(s > 0.0))
+                    return 3;
+                L[i * D + i] = sqrt(s);
+            } else
+                L[i * D + j] = s / L[j * D + j];
+        }
+    return 0;
+}
+
+static int periodic_dims(const peo_event *ev, int *idx, double *per)
+{
+    if (ev->params == PEO_PARAMS_4D)
+        return 0;
+    idx[0] = 4;
+    per[0] = 2.0 * PI; /* ra */
+    idx[1] = 7;
+    per[1] = PI; /* psi */
+    idx[2] = 10;
+    per[2] = 2.0 * PI; /* phic */
+    return 3;
+}
+
+/* Prior (App. A.3 weights need log pi; the paper's priors are "natural"):
+ * flat in Mc, eta or q, spins, tc, ra, psi, phic; cos(dec); sin(iota); dL^2.
+ * Normalisations are dropped. */
+double peo_logprior(const peo_event *ev, const double *th)
+{
+    peo_source s;
+    if (!peo_source_from_theta(ev, th, &s))
+        return -INFINITY;
+    if (ev->params == PEO_PARAMS_4D)
+        return 0.0;
+    return log(cos(th[5])) + log(sin(th[6])) + 2.0 * log(th[8]);
+}
+
+/* Density of the wrapped Gaussian at theta: log sum over images k in {-1,0,1}^p of
+ * N(theta + k P; theta0, g^-1), with the quadratic form evaluated as |L^T x|^2. */
+static double logq_one(int D, const double *L, const double *th0, const double *th, int np, const int *pidx,
+                       const double *per)
+{
+    int nimg = 1, m, a, r, c;
+    double lq[27], mx = -INFINITY, acc = 0.0, logdet = 0.0;
+    for (a = 0; a < np; a++)
+        nimg *= 3;
+    for (m = 0; m < nimg; m++) {
+        double x[PEO_MAX_DIM], q = 0.0;
+        int code = m;
+        for (a = 0; a < D; a++)
+            x[a] = th[a] - th0[a];
+        for (a = 0; a < np; a++) {
+            int kk = code % 3 - 1;
+            code /= 3;
+            x[pidx[a]] += kk * per[a];
+        }
+        for (r = 0; r < D; r++) {
+            double y = 0.0;
+            for (c = r; c < D; c++)
+                y += L[c * D + r] * x[c];
+            q += y * y;
+        }
+        lq[m] = -0.5 * q;
+        if (lq[m] > mx)
+            mx = lq[m];
+    }
+    for (m = 0; m < nimg; m++)
+        acc += exp(lq[m] - mx);
+    for (r = 0; r < D; r++)
+        logdet += log(L[r * D + r]);
+    return mx + log(acc) + logdet - 0.5 * D * log(2.0 * PI);
+}
+
+int peo_draw(const peo_event *ev, const double *th0, const double *g, uint64_t seed, uint32_t stream, long n,
+             double *theta, double *logq, double *logprior)
+{
+    const int D = peo_dim(ev->params);
+    double L[PEO_MAX_DIM * PEO_MAX_DIM];
+    int pidx[3], np, rc;
+    double per[3];
+    long i;
+    np = periodic_dims(ev, pidx, per);
+    rc = cholesky(g, D, L);
+    if (rc) {
+        for (i = 0; i < n; i++) {
+            int a;
+            for (a = 0; a < D; a++)
+                theta[(long)a * n + i] = th0[a];
+            logq[i] = 0.0;
+            logprior[i] = -INFINITY;
+        }
+        return rc;
+    }
+    for (i = 0; i < n; i++) {
+        double z[PEO_MAX_DIM + 1], y[PEO_MAX_DIM], th[PEO_MAX_DIM];
+        int j, r, c, a;
+        for (j = 0; 2 * j < D; j++) {
+            double ua, ub, rad;
+            block_uniforms(seed, stream, (uint64_t)i, (uint32_t)j, &ua, &ub);
+            /* Box-Muller */
+            rad = sqrt(-2.0 * log(ua));
+            z[2 * j] = rad * cos(2.0 * PI * ub);
+            z[2 * j + 1] = rad * sin(2.0 * PI * ub);
+        }
+        /* theta = theta0 + L^-T z: back substitution with L^T */
+        for (r = D - 1; r >= 0; r--) {
+            double s = z[r];
+            for (c = r + 1; c < D; c++)
+                s -= L[c * D + r] * y[c];
+            y[r] = s / L[r * D + r];
+        }
+        for (a = 0; a < D; a++)
+            th[a] = th0[a] + y[a];
+        for (a = 0; a < np; a++) {
+            double P = per[a], v = th[pidx[a]];
+            th[pidx[a]] = v - P * floor(v / P);
+        }
+        for (a = 0; a < D; a++)
+            theta[(long)a * n + i] = th[a];
+        logq[i] = logq_one(D, L, th0, th, np, pidx, per);
+        logprior[i] = peo_logprior(ev, th);
+    }
+    return 0;
+}
+
+int peo_logq_theta(const peo_event *ev, const double *th0, const double *g, const double *theta, long n,
+                   double *logq)
+{
+    const int D = peo_dim(ev->params);
+    double L[PEO_MAX_DIM * PEO_MAX_DIM], per[3];
+    int pidx[3], np, rc;
+    long i;
+    np = periodic_dims(ev, pidx, per);
+    rc = cholesky(g, D, L);
+    if (rc)
+        return rc;
+    for (i = 0; i < n; i++) {
+        double th[PEO_MAX_DIM];
+        int a;
+        for (a = 0; a < D; a++)
+            th[a] = theta[(long)a * n + i];
+        logq[i] = logq_one(D, L, th0, th, np, pidx, per);
+    }
+    return 0;
+}
+
+/* Eq. 5: w_i = L_i pi_i / g_i, in logs; Eq. 6: ESS = (sum w)^2 / sum w^2.
+ * Weights are normalised; lnZ = ln mean(w). Draws with -inf log weight count in N. */
+void peo_weights_ess(const double *ll, const double *lp, const double *lq, long n, double *w, double *stats)
+{
+    long i, nin = 0;
+    double m = -INFINITY;
+    nsum s1 = {0, 0}, s2 = {0, 0};
+    for (i = 0; i < n; i++) {
+        double l = ll[i] + lp[i] - lq[i];
+        if (isfinite(l)) {
+            nin++;
+            if (l > m)
+                m = l;
+        }
+    }
+    if (nin == 0) {
+        if (w)
+            for (i = 0; i < n; i++)
+                w[i] = 0.0;
+        stats[0] = 0.0;
+        stats[1] = -INFINITY;
+        stats[2] = -INFINITY;
+        stats[3] = 0.0;
+        return;
+    }
+    for (i = 0; i < n; i++) {
+        double l = ll[i] + lp[i] - lq[i];
+        if (isfinite(l)) {
+            double e = exp(l - m);
+            nadd(&s1, e);
+            nadd(&s2, e * e);
+        }
+    }
+    if (w)
+        for (i = 0; i < n; i++) {
+            double l = ll[i] + lp[i] - lq[i];
+            w[i] = isfinite(l) ? exp(l - m) / nval(&s1) : 0.0;
+        }
+    stats[0] = nval(&s1) * nval(&s1) / nval(&s2);
+    stats[1] = m + log(nval(&s1)) - log((double)n);
+    stats[2] = m;
+    stats[3] = (double)nin;
+}

@@ -1,0 +1,134 @@
+/*
+ * peo.h -- plain FP64 CPU oracle for metric-based importance sampling of
+ * compact-binary gravitational-wave signals (Nitz, arXiv:2410.05190).
+ *
+ * THIS IS TEST INFRASTRUCTURE. It exists only to check the GPU library
+ * against the paper's definitions. Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it. The GPU library never
+ * includes, links or calls anything here, and this file includes nothing
+ * of the GPU library: the two implement the same definitions independently.
+ *
+ * Every quantity is evaluated the slow, obvious way, in double precision:
+ *   - noise-weighted inner product (Sec. II.A, Eq. 1), left-point sum on the
+ *     half-open grid f_k = f_lo + k*df, k = 0..K-1;
+ *   - log-likelihood ratio against noise (Sec. II.A, Eq. 3), optionally
+ *     marginalised over the coalescence phase with a uniform prior;
+ *   - importance weights (App. A.3, Eq. 5) and effective sample size (Eq. 6);
+ *   - the waveform-manifold metric (Sec. II.A, the metric induced by the
+ *     inner product) as the Fisher matrix of the network waveform.
+ * The waveform model is TaylorF2 (stationary-phase inspiral, 3.5PN phase,
+ * aligned spins, Newtonian amplitude) cut at the test-mass ISCO frequency of
+ * the total mass; the paper itself uses IMRPhenom models, which are not
+ * available here.
+ *
+ * Units: masses in solar masses (detector frame), distance in Mpc, times in
+ * seconds, angles in radians. Stored data and PSD may carry a unit scale s:
+ * data = s * physical strain, psd = s^2 * physical PSD; inner products are
+ * invariant, the model waveform is multiplied by s.
+ */
+#ifndef PEO_H
+#define PEO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PEO_MAX_DET 4
+#define PEO_MAX_DIM 11
+
+/* parameter sets */
+#define PEO_PARAMS_4D 0  /* Mc, eta, chi_eff, tc ; fixed real amplitude amp0, one response */
+#define PEO_PARAMS_11D 1 /* Mc, q, chi1z, chi2z, ra, dec, iota, psi, dL, tc, phic */
+/* likelihood forms */
+#define PEO_PHASE_MARG 0     /* ln I0(|Z|) - H/2, coalescence phase marginalised */
+#define PEO_PHASE_EXPLICIT 1 /* Re Z - H/2 */
+
+typedef struct {
+    int n_det;
+    long n_bins;
+    double f_lo, df;
+    const double *data; /* [n_det][n_bins][2] (re, im); NULL for template-only use */
+    const double *psd;  /* [n_det][n_bins] */
+    double strain_scale;
+    int params;
+    int phase;
+    double amp0;    /* 4-D only: physical amplitude A0 of A0 f^-7/6 */
+    double gmst;    /* rad */
+    double chi_max; /* |chi| bound of the prior */
+    double dl_max;  /* Mpc, upper bound of the distance prior (11-D) */
+    double det_geom[PEO_MAX_DET][3]; /* latitude, longitude, x-arm azimuth (from north to east) */
+} peo_event;
+
+/* Per-draw source quantities derived from theta. */
+typedef struct {
+    int in_support;
+    double mc, M, eta, delta, chi1, chi2;
+    double tc, phic;
+    double rre[PEO_MAX_DET], rim[PEO_MAX_DET]; /* complex response incl. amplitude and scale */
+    double dt[PEO_MAX_DET];                     /* arrival delay w.r.t. geocentre, s */
+    double fisco;
+    long kcut;
+    double phi[8], phil[8]; /* TaylorF2 coefficients */
+} peo_source;
+
+int peo_dim(int params);
+double peo_t_sun(void);
+double peo_mpc_m(void);
+double peo_c_si(void);
+double peo_r_earth(void);
+
+/* TaylorF2 coefficients phi_j and log coefficients phil_j, j = 0..7, of
+ * Psi = 2 pi f tc - phic - pi/4 + 3/(128 eta v^5) sum_j (phi_j + phil_j ln v) v^j.
+ * delta = (m1 - m2)/M, chi1/chi2 aligned spins of the heavier/lighter body. */
+void peo_pn_coeffs(double eta, double delta, double chi1, double chi2, double phi[8], double phil[8]);
+/* Phase Psi(f) in radians of the source (no detector delay). */
+double peo_psi(const peo_source *s, double f);
+double peo_f_isco(double M);
+long peo_kcut(const peo_event *ev, double fisco);
+void peo_antenna(const double geom[3], double ra, double dec, double psi, double gmst,
+                 double *fplus, double *fcross, double *dt);
+/* theta: D contiguous values. Returns in_support. Always fills s. */
+int peo_source_from_theta(const peo_event *ev, const double *theta, peo_source *s);
+
+/* h[d][k][2] for k < n_bins (zero above the cut) at theta, physical*scale units.
+ * kcut_override < 0 uses the draw's own cut. */
+void peo_waveform(const peo_event *ev, const double *theta, long kcut_override, double *h);
+/* 4 df Re sum_k conj(a_k) b_k / S_k over all bins of detector d. */
+double peo_inner(const peo_event *ev, int d, const double *a, const double *b);
+
+double peo_log_i0(double x);
+
+/* theta: [D][n] (row j holds parameter j of every draw). zh: [n][3] = Re Z, Im Z, H, may be NULL.
+ * Out-of-support draws get -inf. n_threads <= 0: OpenMP default. */
+void peo_loglike(const peo_event *ev, const double *theta, long n, double *loglike, double *zh, int n_threads);
+
+/* Default finite-difference steps at theta0 (D values). */
+void peo_default_steps(const peo_event *ev, const double *theta0, double *steps);
+/* Fisher metric. flags: bit0 = do not add the prior regularisation,
+ * bit1 = raw (no coalescence-phase projection, 4-D returns 5x5 with phic last).
+ * g is (D or D+1)^2 row-major. Returns 0. */
+int peo_metric_fd(const peo_event *ev, const double *theta0, const double *steps, int flags, double *g);
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
+void peo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* u[i*2*npairs + 2j + {0,1}] = the two 53-bit uniforms of block (i, j). */
+void peo_uniforms(uint64_t seed, uint32_t stream, long n, int npairs, double *u);
+/* Draws from N(theta0, g^-1), periodic coordinates wrapped. theta [D][n]. Returns 0, or 3 if
+ * g is not positive definite. logq uses the image sum over the wrapped coordinates. */
+int peo_draw(const peo_event *ev, const double *theta0, const double *g, uint64_t seed, uint32_t stream,
+             long n, double *theta, double *logq, double *logprior);
+/* Proposal log-density of wrapped draws from theta alone (quadratic-form route). */
+int peo_logq_theta(const peo_event *ev, const double *theta0, const double *g, const double *theta,
+                   long n, double *logq);
+double peo_logprior(const peo_event *ev, const double *theta);
+
+/* stats = {ESS, lnZ, max log w, n_in_support}. w may be NULL. */
+void peo_weights_ess(const double *loglike, const double *logprior, const double *logq, long n,
+                     double *w, double *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
