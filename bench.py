@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark of the metric-importance-sampling likelihood path on one MI355X.
+
+One step = the whole hot path for one event of the benchmark workload (default: the
+3-detector BNS shape, 11-D, 519168 bins per detector, complex64 data and FP32 PSD,
+65536 proposal draws, split precision):
+  event-table preparation -> metric at the proposal centre -> Gaussian draws ->
+  log-likelihoods -> importance weights and ESS,
+with every input already resident in HBM. Prints one JSON line.
+
+Synthetic data: the seeded coloured-noise workload of paper_2410_05190_amd.synth with a
+TaylorF2 injection made by the library's own waveform call.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU issue model of the hot-loop kernels, in lane-cycles of the minimal
+# instruction sequence: the phase polynomial (10 FP64 ops) is shared by the
+# detectors of a bin; each term (draw, detector, bin) of the split kernel costs
+# FP64 FMA + fract, FP64->FP32 convert, FP32 add and two FP32 FMAs at full rate
+# plus v_sin_f32 and v_cos_f32, which issue at half rate on gfx950 (the counters
+# give SQ_ACTIVE_INST_VALU - SQ_INSTS_VALU = SQ_INSTS_VALU_TRANS_F32). The FP64
+# kernel's term: FMA + fract, the 26-op FP64 sincos, four FMAs.
+PSI_OPS_PER_DRAW_BIN = 10
+SPLIT_OPS_PER_TERM = 6 + 2 * 2
+FP64_OPS_PER_TERM = 2 + 26 + 4
+# HBM bytes per launch of the split kernel at the benchmark shape, from rocprofv3
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors read off a 1 GiB device copy
+# in the same run; None when the kernel has changed since the counters were taken.
+SPLIT_TRAFFIC_BYTES = None
+VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--precision", choices=["split", "fp64"], default="split")
+    ap.add_argument("--chunks", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this size first (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def host_terms(theta, cfg, f_lo, df, K, n_det):
+    """Algorithmic term count: sum over in-support draws of n_det x #{k : f_k < f_isco(M)}."""
+    import numpy as np
+    tsun = 1.32712440018e20 / 299792458.0 ** 3
+    mc = theta[0]
+    with np.errstate(all="ignore"):
+        if cfg["params"] == "4d":
+            M = mc * theta[1] ** -0.6
+        else:
+            q = theta[1]
+            M = mc * (1 + q) ** 1.2 * q ** -0.6
+        fisco = 1.0 / (6.0 ** 1.5 * math.pi * M * tsun)
+        kc = np.clip(np.ceil((fisco - f_lo) / df), 0, K)
+    return np.nan_to_num(kc)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only: run bench.py with --gpus 1 "
+                                   "(multi-GPU sharding is a design note, not built)"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2410_05190_amd import binding, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
+        del src, dst
+    c = args.config
+    cfg = synth.CONFIGS[c]
+    f_lo, df, K = synth.grid(c)
+    nd = cfg["n_det"]
+    N = cfg["n_draws"] or 65536
+    four_d = cfg["params"] == "4d"
+    params = binding.PE_PARAMS_4D if four_d else binding.PE_PARAMS_11D
+    phase = binding.PE_PHASE_MARG if cfg["phase"] == "marg" else binding.PE_PHASE_EXPLICIT
+    f = synth.frequencies(f_lo, df, K)
+    S = np.tile(synth.psd_analytic(f), (nd, 1))
+    geom = synth.detectors(c, nd)
+    inj = synth.injection(c, 0)
+    f32 = cfg["storage"] == "f32"
+    s = synth.F32_STRAIN_SCALE if f32 else 1.0
+    psd_t = torch.from_numpy((S * s * s).astype(np.float32 if f32 else np.float64)).cuda()
+    dl_max = cfg["dl_max"] or 1e4
+    common = dict(f_lo=f_lo, df=df, strain_scale=s, params=params, phase=phase, gmst=0.0,
+                  chi_max=cfg["chi_max"], dl_max=dl_max, det_geom=geom)
+    pdt = binding.PE_F32 if f32 else binding.PE_F64
+    ddt = binding.PE_C64 if f32 else binding.PE_C128
+
+    # injection at the target SNR, made by the library's waveform
+    theta_inj = inj["theta"].copy()
+    h = torch.empty((nd, K, 2), dtype=torch.float64, device="cuda")
+    snr2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    desc1 = binding.make_desc(nd, K, data_dtype=ddt, psd_dtype=pdt, amp0=1.0, **common)
+    binding.pe_waveform(desc1, torch.from_numpy(theta_inj).cuda(), psd_t, h, snr2)
+    rho1 = math.sqrt(float(snr2.item()))
+    amp0 = 0.0
+    if four_d:
+        amp0 = inj["snr"] / rho1
+    else:
+        theta_inj[8] = rho1 / inj["snr"]
+    desc = binding.make_desc(nd, K, data_dtype=ddt, psd_dtype=pdt, amp0=amp0, **common)
+    binding.pe_waveform(desc, torch.from_numpy(theta_inj).cuda(), psd_t, h, snr2)
+    noise = torch.from_numpy(synth.noise(c, 0, S, df) * s).cuda()
+    data = torch.view_as_complex(h) + noise
+    data = data.to(torch.complex64 if f32 else torch.complex128).contiguous()
+    del noise
+
+    if args.chunks:
+        binding.pe_set_chunks(args.chunks)
+    ev = binding.Event(data, psd_t, amp0=amp0, **common)
+    ev.reserve(N)
+    D = ev.dim
+    theta0 = torch.from_numpy(theta_inj).cuda()
+    g = torch.empty((D, D), dtype=torch.float64, device="cuda")
+    theta = torch.empty((D, N), dtype=torch.float64, device="cuda")
+    lq = torch.empty(N, dtype=torch.float64, device="cuda")
+    lp = torch.empty(N, dtype=torch.float64, device="cuda")
+    ll = torch.empty(N, dtype=torch.float64, device="cuda")
+    w = torch.empty(N, dtype=torch.float64, device="cuda")
+    stats = torch.zeros((max(args.steps, 1), 4), dtype=torch.float64, device="cuda")
+    prec = binding.PE_PREC_SPLIT if args.precision == "split" else binding.PE_PREC_FP64
+    kname = "loglike_split" if prec == binding.PE_PREC_SPLIT else "loglike_fp64"
+    seed = synth.draw_seed(c, 0)
+    h_ = ev.handle
+
+    def step(i, st_row):
+        binding.pe_event_update(h_, data, psd_t)
+        binding.pe_metric(h_, theta0, None, 0, g)
+        binding.pe_draw(h_, theta0, g, seed, i, N, theta, lq, lp)
+        binding.pe_loglike_batch(h_, theta, N, prec, ll, None)
+        binding.pe_weights_ess(ll, lp, lq, N, w, st_row)
+
+    for i in range(args.warmup):
+        step(1000 + i, stats[0])
+    torch.cuda.synchronize()
+    ev.status()
+
+    binding.pe_profile_enable(True)
+    binding.pe_profile_read(kname)
+    ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev_a[i].record()
+        step(i, stats[i])
+        ev_b[i].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    binding.pe_profile_enable(False)
+    k_ms, k_n = binding.pe_profile_read(kname)
+    ev.status()
+    lat = sorted(a.elapsed_time(b) for a, b in zip(ev_a, ev_b))
+    wall = t1 - t0
+    st = stats.cpu().numpy()[: args.steps]
+    n_live = st[:, 3].sum()
+    ess = st[:, 0].sum()
+    # terms of the last step (its draws are still in `theta`)
+    th_h = theta.cpu().numpy()
+    kc = host_terms(th_h, cfg, f_lo, df, K, nd)
+    live_last = np.isfinite(ll.cpu().numpy())
+    terms_last = float(nd * kc[live_last].sum())
+    db_last = terms_last / nd
+    ops_per_term = SPLIT_OPS_PER_TERM if prec == binding.PE_PREC_SPLIT else FP64_OPS_PER_TERM
+    k_avg_s = k_ms / max(k_n, 1) / 1e3
+    ops_last = db_last * PSI_OPS_PER_DRAW_BIN + terms_last * ops_per_term
+    achieved = ops_last / k_avg_s if k_avg_s > 0 else float("nan")
+
+    out = {
+        "metric": "likelihood evals/s and ESS/s per event; p50/p99 event latency under load",
+        "value": n_live / wall,
+        "unit": "likelihood evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 phase + f32" if prec == binding.PE_PREC_SPLIT else "f64",
+        "data": "synthetic (seeded coloured Gaussian noise + TaylorF2 injection)",
+        "config": {"workload": cfg["name"], "n_det": nd, "n_bins": K, "draws_per_event": N, "dim": D,
+                   "precision": args.precision, "chunks": args.chunks or "auto"},
+        "draws_per_s": N * args.steps / wall,
+        "in_support_fraction": n_live / (N * args.steps),
+        "ess_per_s": ess / wall,
+        "ess_per_event_mean": ess / args.steps,
+        "terms_per_s_hot_kernel": terms_last / k_avg_s if k_avg_s > 0 else None,
+        "event_latency_ms": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(0.99 * len(lat)))],
+                             "kind": "isolated events, one at a time"},
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK,
+                     "traffic": SPLIT_TRAFFIC_BYTES if prec == binding.PE_PREC_SPLIT else None,
+                     "kernel_ms_avg": k_avg_s * 1e3, "kernel_launches": k_n, "ops_per_launch": ops_last},
+    }
+    ev.close()
+
+    if not args.no_cpu_baseline and c != 2:
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_sample, data, psd_t, theta_inj, amp0, common)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(c, n_sample, data, psd_t, theta_inj, amp0, common):
+    """The FP64 oracle as it stands, on the host cores: its own metric and draws for the same
+    event, then the log-likelihood of n_sample draws (timed) and the weights."""
+    import numpy as np
+
+    import oracle
+
+    threads = os.cpu_count() or 1
+    d_h = data.cpu().numpy()
+    p_h = psd_t.cpu().numpy()
+    ev = oracle.Event(d_h.shape[0], d_h.shape[1], common["f_lo"], common["df"], data=d_h, psd=p_h,
+                      strain_scale=common["strain_scale"], params=common["params"], phase=common["phase"],
+                      amp0=amp0, gmst=common["gmst"], chi_max=common["chi_max"], dl_max=common["dl_max"],
+                      det_geom=common["det_geom"])
+    t0 = time.perf_counter()
+    g = ev.metric(theta_inj)
+    t1 = time.perf_counter()
+    rc, th, lq, lp = ev.draw(theta_inj, g, 12345, 0, 4 * n_sample)
+    live = np.flatnonzero(np.isfinite(lp))[:n_sample]
+    th = np.ascontiguousarray(th[:, live])
+    t2 = time.perf_counter()
+    ll = ev.loglike(th, n_threads=threads)
+    t3 = time.perf_counter()
+    oracle.weights_ess(ll, lp[live], lq[live])
+    return {"value": live.size / (t3 - t2), "unit": "likelihood evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{live.size} in-support draws of the same event (oracle's own metric and draws); "
+                      f"oracle metric {t1 - t0:.1f} s single-threaded, not in value"}
+
+
+if __name__ == "__main__":
+    main()

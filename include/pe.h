@@ -1,0 +1,219 @@
+/*
+ * pe.h -- C ABI of the MI355X (gfx950) likelihood engine for metric-based
+ * importance sampling of compact-binary gravitational-wave signals
+ * (A. H. Nitz, "Robust, Rapid, and Simple Gravitational-wave Parameter
+ * Estimation", arXiv:2410.05190).
+ *
+ * The library evaluates, for a large batch of proposal draws theta_i:
+ *   - the noise-weighted inner product (a|b) = 4 Re int a* b / S_n df
+ *     (Sec. II.A, Eq. 1), as a left-point sum over the half-open grid
+ *     f_k = f_lo + k df, k = 0 .. n_bins-1;
+ *   - the log-likelihood ratio against noise ln(L/L_n) = (d|h) - (h|h)/2
+ *     (Sec. II.A, Eq. 3), either with an explicit coalescence phase or
+ *     marginalised over a uniform one (ln I0(|Z|) - H/2);
+ *   - the importance weights w_i = L_i pi_i / g_i (App. A.3, Eq. 5) and the
+ *     effective sample size ESS = (sum w)^2 / sum w^2 (App. A.3, Eq. 6);
+ *   - the waveform metric induced by the inner product (Sec. II.A), as the
+ *     network Fisher matrix g_ij = sum_d (d_i h_d | d_j h_d) from central
+ *     finite differences, and Gaussian proposal draws N(theta0, g^-1)
+ *     (the local-metric proposal the paper names as its refinement, Sec. III.A).
+ * The waveform is TaylorF2 (3.5PN phase, aligned spins, Newtonian amplitude)
+ * cut at the test-mass ISCO of the total mass, projected onto long-wavelength
+ * L-shaped detectors with light-travel delays.
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments named *_dev are device pointers (HBM), owned by the
+ *     caller; the library never frees them. Scalars are passed by value.
+ *   - Every call enqueues work on `stream` (a hipStream_t; NULL = the null
+ *     stream) and returns without synchronising, except pe_event_create and
+ *     pe_event_status, which synchronise that stream.
+ *   - Argument errors are detected on the host and returned at once; nothing
+ *     is enqueued then. Errors found by kernels (bad PSD values, a metric that
+ *     is not positive definite) are recorded in the event and returned by
+ *     pe_event_status. A HIP error returns PE_ERR_HIP.
+ *   - pe_last_error() gives a message for the last failing call of the
+ *     calling thread.
+ *   - An event handle is used by one host thread at a time. Results are
+ *     bitwise reproducible for fixed inputs, precision and tile shape: no
+ *     floating-point atomics are used.
+ *
+ * Parameters (units: solar masses, detector frame; Mpc; s; rad):
+ *   PE_PARAMS_4D : theta = (Mc, eta, chi_eff, tc); one common real amplitude
+ *                  amp0 on every detector, no delay. Always phase-marginalised.
+ *   PE_PARAMS_11D: theta = (Mc, q, chi1z, chi2z, ra, dec, iota, psi, dL, tc,
+ *                  phic), q = m2/m1 <= 1. ra, psi, phic are periodic
+ *                  (2 pi, pi, 2 pi).
+ * theta batches are structure-of-arrays: theta_dev[j*n + i] is parameter j of
+ * draw i.
+ */
+#ifndef PE_H
+#define PE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PE_MAX_DET 4
+#define PE_MAX_DIM 11
+
+typedef struct pe_event_s *pe_event_t;
+
+typedef enum {
+    PE_OK = 0,
+    PE_ERR_ARG = 1,       /* invalid argument, or invalid data/PSD values */
+    PE_ERR_OOM = 2,       /* device allocation failed */
+    PE_ERR_HIP = 3,       /* a HIP runtime call failed */
+    PE_ERR_SINGULAR = 4,  /* the metric given to pe_draw is not positive definite */
+    PE_ERR_NONFINITE = 5, /* data contains inf or nan */
+    PE_ERR_BUDGET = 6     /* request exceeds a fixed capacity */
+} pe_status_t;
+
+typedef enum { PE_PREC_FP64 = 0, PE_PREC_SPLIT = 1 } pe_precision_t;
+typedef enum { PE_PHASE_MARG = 0, PE_PHASE_EXPLICIT = 1 } pe_phase_t;
+typedef enum { PE_PARAMS_4D = 0, PE_PARAMS_11D = 1 } pe_params_t;
+typedef enum { PE_C128 = 0, PE_C64 = 1 } pe_data_dtype_t;
+typedef enum { PE_F64 = 0, PE_F32 = 1 } pe_psd_dtype_t;
+
+/* Event description. det_geom[d] = {latitude, longitude, azimuth of the x arm
+ * measured from north toward east}; the y arm is 90 degrees east of x. */
+typedef struct {
+    int32_t n_det;        /* 1 .. PE_MAX_DET */
+    int64_t n_bins;       /* K >= 1 */
+    double f_lo, df;      /* Hz; f_lo > 0, df > 0 */
+    int32_t data_dtype;   /* pe_data_dtype_t: complex128 or complex64, interleaved re, im */
+    int32_t psd_dtype;    /* pe_psd_dtype_t */
+    double strain_scale;  /* stored data = s * physical strain; stored PSD = s^2 * physical PSD */
+    int32_t params;       /* pe_params_t */
+    int32_t phase;        /* pe_phase_t (4-D requires PE_PHASE_MARG) */
+    double amp0;          /* 4-D: physical amplitude A0 of A0 f^-7/6 */
+    double gmst;          /* rad */
+    double chi_max;       /* prior bound |chi| <= chi_max */
+    double dl_max;        /* 11-D prior bound 0 < dL <= dl_max (Mpc) */
+    double det_geom[PE_MAX_DET][3];
+} pe_event_desc_t;
+
+/* Dimension D of theta for a parameter set (4 or 11); 0 if unknown. */
+int32_t pe_dim(int32_t params);
+
+/*
+ * Create an event: allocate its device tables and prepare them from the data
+ * d[n_det][n_bins] and PSD S[n_det][n_bins] (layout as desc says) on `stream`,
+ * then synchronise and check the inputs. Prepared per bin: f, f^(1/3),
+ * f^(-5/3), ln(f)/3, the folded weights w = 4 df f^(-7/6) d / S (Eq. 1 with
+ * the TaylorF2 amplitude), and the prefix sums C_k = sum_{j<k} 4 df f^(-7/3)/S
+ * that give (h|h) for any cut. The inputs may be freed after the call.
+ * Errors: PE_ERR_ARG (bad desc, S <= 0 or not finite), PE_ERR_NONFINITE (d not
+ * finite), PE_ERR_OOM, PE_ERR_HIP. On error *out is NULL.
+ */
+pe_status_t pe_event_create(const pe_event_desc_t *desc, const void *data_dev, const void *psd_dev, void *stream,
+                            pe_event_t *out);
+
+/* Re-prepare an existing event from new data/PSD of the same shape (no
+ * allocation; asynchronous). Input errors are reported by pe_event_status. */
+pe_status_t pe_event_update(pe_event_t ev, const void *data_dev, const void *psd_dev, void *stream);
+
+/* Synchronise `stream` and return the first error recorded by the event's
+ * kernels since the last call (and clear it). */
+pe_status_t pe_event_status(pe_event_t ev, void *stream);
+
+/* Pre-size the per-draw workspace for batches of up to max_draws (allocates).
+ * pe_loglike_batch grows it on demand otherwise. */
+pe_status_t pe_event_reserve(pe_event_t ev, int64_t max_draws);
+
+pe_status_t pe_event_destroy(pe_event_t ev);
+
+/*
+ * Metric at theta0 (Sec. II.A: the inner product defines a metric on the
+ * waveform manifold): g_ij = sum_d (d_i h_d | d_j h_d) with central
+ * differences h(theta0 +- eps_i e_i), the cut frozen at theta0, and the exact
+ * derivative i h for the coalescence phase.
+ *   theta0_dev : D doubles (device).
+ *   fd_step_dev: D doubles (device) or NULL for the default steps (each moves
+ *                the phase by ~1e-3 rad at the most sensitive band edge).
+ *   flags      : bit0 = do not add the prior precision 12/range^2 on bounded
+ *                and periodic coordinates.
+ *   g_dev      : D*D doubles, row-major (device). For the marginalised
+ *                likelihood the phase direction is projected out (Schur
+ *                complement); in 11-D its row and column are then zero before
+ *                the prior precision is added.
+ */
+pe_status_t pe_metric(pe_event_t ev, const double *theta0_dev, const double *fd_step_dev, int32_t flags,
+                      double *g_dev, void *stream);
+
+/*
+ * n draws from N(theta0, g^-1) (the proposal of App. A.3, centred on theta0
+ * with the metric as precision). Normals come from Philox4x32-10 (Salmon et
+ * al., SC'11) with key (seed lo, seed hi) and counter (i lo, i hi, pair j,
+ * stream_id), two 53-bit uniforms per block, Box-Muller. Periodic coordinates
+ * are wrapped; logq is the log-density of the wrapped Gaussian (sum over the
+ * images -1, 0, +1 of each periodic coordinate). logprior is the log prior
+ * (flat in Mc, eta or q, spins, tc, ra, psi, phic; cos dec; sin iota; dL^2;
+ * unnormalised) or -inf outside the support.
+ *   theta0_dev: D doubles; g_dev: D*D doubles (device).
+ *   theta_dev: [D][n]; logq_dev, logprior_dev: [n] (device, caller-owned).
+ * If g is not positive definite every draw is theta0 with logprior = -inf and
+ * pe_event_status reports PE_ERR_SINGULAR.
+ */
+pe_status_t pe_draw(pe_event_t ev, const double *theta0_dev, const double *g_dev, uint64_t seed, uint32_t stream_id,
+                    int64_t n, double *theta_dev, double *logq_dev, double *logprior_dev, void *stream);
+
+/*
+ * Log-likelihood ratio (Eq. 3) of n draws. Per draw and detector the kernel
+ * reduces Z_d = sum_{k < kcut} conj(w_k) exp(-i Phi_d(f_k)) with
+ * Phi_d = Psi(f) + 2 pi f (tc + dt_d) evaluated in FP64, then
+ * Z = sum_d R_d Z_d, H = sum_d |R_d|^2 C_{d,kcut} and
+ * ln L = Re Z - H/2 (explicit) or ln I0(|Z|) - H/2 (marginalised).
+ *   precision: PE_PREC_FP64 (every step in FP64) or PE_PREC_SPLIT (phase in
+ *              FP64; reduced-phase sincos, products and partial sums in FP32
+ *              with compensated accumulation; final combination in FP64).
+ *   loglike_dev: [n]; out-of-support draws get -inf.
+ *   aux_dev: NULL or [n][3] = Re Z, Im Z, H (zeros out of support).
+ */
+pe_status_t pe_loglike_batch(pe_event_t ev, const double *theta_dev, int64_t n, int32_t precision, double *loglike_dev,
+                             double *aux_dev, void *stream);
+
+/*
+ * Importance weights (Eq. 5) and ESS (Eq. 6) of n draws, with
+ * ln w_i = loglike_i + logprior_i - logq_i and max-shifted sums in FP64.
+ *   w_dev: NULL or [n] normalised weights (sum 1; 0 where ln w = -inf).
+ *   stats_dev: 4 doubles = {ESS, ln Z = ln mean(w), max ln w, number of
+ *              finite ln w}. With no finite ln w: {0, -inf, -inf, 0}.
+ * Needs no event; launches one workgroup.
+ */
+pe_status_t pe_weights_ess(const double *loglike_dev, const double *logprior_dev, const double *logq_dev, int64_t n,
+                           double *w_dev, double *stats_dev, void *stream);
+
+/*
+ * Model waveform of one parameter point on the event grid, FP64:
+ * h_dev[d][k] = s R_d f_k^(-7/6) exp(-i Phi_d(f_k)) for f_k < f_isco, else 0,
+ * interleaved complex128. If psd_dev is not NULL (layout as desc), also writes
+ * snr2_dev[0] = sum_d (h_d|h_d). No event needed; used to make injections.
+ */
+pe_status_t pe_waveform(const pe_event_desc_t *desc, const double *theta_dev, const void *psd_dev, double *h_dev,
+                        double *snr2_dev, void *stream);
+
+/* The proposal's uniforms: u_dev[(i*npairs + j)*2 + {0,1}] for draw i and
+ * block j < npairs, exactly the values pe_draw uses. */
+pe_status_t pe_rng_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int32_t npairs, double *u_dev,
+                            void *stream);
+
+/* Kernel timing with HIP events on the launch stream. enable != 0 starts
+ * recording around the hot-loop kernel launches; pe_profile_read synchronises
+ * the recorded events and returns the summed milliseconds and launch count of
+ * the named kernel ("loglike_split", "loglike_fp64"), then clears it. */
+pe_status_t pe_profile_enable(int32_t enable);
+pe_status_t pe_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
+/* Tile shape of the hot-loop kernels: draws per workgroup is fixed (256);
+ * n_chunks splits the frequency axis (0 = automatic, else a multiple of 8 up
+ * to 256). Global setting, read at launch time. */
+pe_status_t pe_set_chunks(int32_t n_chunks);
+
+const char *pe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

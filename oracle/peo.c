@@ -222,7 +222,7 @@ int peo_source_from_theta(const peo_event *ev, const double *th, peo_source *s)
     }
     peo_pn_coeffs(s->eta, s->delta, s->chi1, s->chi2, s->phi, s->phil);
     s->fisco = peo_f_isco(s->M);
-    s->kcut = ok ? peo_kcut(ev, s->fisco) : 0;
+    s->kcut = -1; /* filled by the callers that need the cut */
     s->in_support = ok;
     return ok;
 }
@@ -311,6 +311,7 @@ static double loglike_one(const peo_event *ev, const double *th, double *zh)
             zh[0] = zh[1] = zh[2] = 0.0;
         return -INFINITY;
     }
+    s.kcut = peo_kcut(ev, s.fisco);
     for (d = 0; d < ev->n_det; d++) {
         const double *S = ev->psd + (long)d * ev->n_bins;
         const double *dd = ev->data + 2 * (long)d * ev->n_bins;

@@ -69,7 +69,7 @@ typedef struct {
     double rre[PEO_MAX_DET], rim[PEO_MAX_DET]; /* complex response incl. amplitude and scale */
     double dt[PEO_MAX_DET];                     /* arrival delay w.r.t. geocentre, s */
     double fisco;
-    long kcut;
+    long kcut; /* -1 until a caller computes it */
     double phi[8], phil[8]; /* TaylorF2 coefficients */
 } peo_source;
 

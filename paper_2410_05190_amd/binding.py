@@ -1,0 +1,298 @@
+"""Thin ctypes binding of libpe.so (include/pe.h), same names as the C ABI.
+
+Argument marshalling only: torch tensors supply device memory (data_ptr) and
+the current HIP stream; every computation runs in the library's kernels.
+There is no CPU fallback: if libpe.so is missing or no GPU is visible the
+calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpe.so")
+
+PE_OK = 0
+STATUS_NAMES = {0: "PE_OK", 1: "PE_ERR_ARG", 2: "PE_ERR_OOM", 3: "PE_ERR_HIP", 4: "PE_ERR_SINGULAR",
+                5: "PE_ERR_NONFINITE", 6: "PE_ERR_BUDGET"}
+PE_PREC_FP64 = 0
+PE_PREC_SPLIT = 1
+PE_PHASE_MARG = 0
+PE_PHASE_EXPLICIT = 1
+PE_PARAMS_4D = 0
+PE_PARAMS_11D = 1
+PE_C128 = 0
+PE_C64 = 1
+PE_F64 = 0
+PE_F32 = 1
+MAX_DET = 4
+
+EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
+           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_weights_ess", "pe_waveform",
+           "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_last_error"]
+
+
+class PeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class EventDesc(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int32), ("n_bins", ctypes.c_int64), ("f_lo", ctypes.c_double),
+                ("df", ctypes.c_double), ("data_dtype", ctypes.c_int32), ("psd_dtype", ctypes.c_int32),
+                ("strain_scale", ctypes.c_double), ("params", ctypes.c_int32), ("phase", ctypes.c_int32),
+                ("amp0", ctypes.c_double), ("gmst", ctypes.c_double), ("chi_max", ctypes.c_double),
+                ("dl_max", ctypes.c_double), ("det_geom", (ctypes.c_double * 3) * MAX_DET)]
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libpe.so and declare the signatures (no GPU call is made)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2410_05190_amd/build.py (no CPU fallback exists)")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, u64, u32, dp = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+                                  ctypes.c_void_p)
+    sig = {
+        "pe_dim": (i32, [i32]),
+        "pe_event_create": (i32, [ctypes.POINTER(EventDesc), vp, vp, vp, ctypes.POINTER(vp)]),
+        "pe_event_update": (i32, [vp, vp, vp, vp]),
+        "pe_event_status": (i32, [vp, vp]),
+        "pe_event_reserve": (i32, [vp, i64]),
+        "pe_event_destroy": (i32, [vp]),
+        "pe_metric": (i32, [vp, dp, dp, i32, dp, vp]),
+        "pe_draw": (i32, [vp, dp, dp, u64, u32, i64, dp, dp, dp, vp]),
+        "pe_loglike_batch": (i32, [vp, dp, i64, i32, dp, dp, vp]),
+        "pe_weights_ess": (i32, [dp, dp, dp, i64, dp, dp, vp]),
+        "pe_waveform": (i32, [ctypes.POINTER(EventDesc), dp, vp, dp, dp, vp]),
+        "pe_rng_uniforms": (i32, [u64, u32, i64, i32, dp, vp]),
+        "pe_profile_enable": (i32, [i32]),
+        "pe_profile_read": (i32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+        "pe_set_chunks": (i32, [i32]),
+        "pe_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != PE_OK:
+        raise PeError(status, _lib.pe_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t, dtype=None, name="tensor", allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_desc(n_det, n_bins, f_lo, df, data_dtype=PE_C128, psd_dtype=PE_F64, strain_scale=1.0,
+              params=PE_PARAMS_11D, phase=PE_PHASE_EXPLICIT, amp0=0.0, gmst=0.0, chi_max=0.4, dl_max=1e4,
+              det_geom=None):
+    d = EventDesc()
+    d.n_det = int(n_det)
+    d.n_bins = int(n_bins)
+    d.f_lo = float(f_lo)
+    d.df = float(df)
+    d.data_dtype = int(data_dtype)
+    d.psd_dtype = int(psd_dtype)
+    d.strain_scale = float(strain_scale)
+    d.params = int(params)
+    d.phase = int(phase)
+    d.amp0 = float(amp0)
+    d.gmst = float(gmst)
+    d.chi_max = float(chi_max)
+    d.dl_max = float(dl_max)
+    if det_geom is not None:
+        g = np.asarray(det_geom, dtype=np.float64).reshape(-1, 3)
+        for i in range(g.shape[0]):
+            for j in range(3):
+                d.det_geom[i][j] = g[i, j]
+    return d
+
+
+def dtypes_of(data, psd):
+    import torch
+    dd = {torch.complex128: PE_C128, torch.complex64: PE_C64}[data.dtype]
+    pd = {torch.float64: PE_F64, torch.float32: PE_F32}[psd.dtype]
+    return dd, pd
+
+
+# ---------------------------------------------------------------- C-ABI mirror
+def pe_dim(params):
+    return load().pe_dim(int(params))
+
+
+def pe_event_create(desc, data, psd, stream=None):
+    load()
+    h = ctypes.c_void_p()
+    _check(_lib.pe_event_create(ctypes.byref(desc), _ptr(data, name="data"), _ptr(psd, name="psd"), _stream(stream),
+                                ctypes.byref(h)))
+    return h
+
+
+def pe_event_update(ev, data, psd, stream=None):
+    _check(_lib.pe_event_update(ev, _ptr(data, name="data"), _ptr(psd, name="psd"), _stream(stream)))
+
+
+def pe_event_status(ev, stream=None):
+    _check(load().pe_event_status(ev, _stream(stream)))
+
+
+def pe_event_reserve(ev, max_draws):
+    _check(load().pe_event_reserve(ev, int(max_draws)))
+
+
+def pe_event_destroy(ev):
+    _check(load().pe_event_destroy(ev))
+
+
+def pe_metric(ev, theta0, fd_step, flags, g, stream=None):
+    import torch
+    _check(_lib.pe_metric(ev, _ptr(theta0, torch.float64, "theta0"),
+                          _ptr(fd_step, torch.float64, "fd_step", allow_none=True), int(flags),
+                          _ptr(g, torch.float64, "g"), _stream(stream)))
+
+
+def pe_draw(ev, theta0, g, seed, stream_id, n, theta, logq, logprior, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(_lib.pe_draw(ev, _ptr(theta0, f64, "theta0"), _ptr(g, f64, "g"), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                        int(stream_id) & 0xFFFFFFFF, int(n), _ptr(theta, f64, "theta"), _ptr(logq, f64, "logq"),
+                        _ptr(logprior, f64, "logprior"), _stream(stream)))
+
+
+def pe_loglike_batch(ev, theta, n, precision, loglike, aux=None, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(_lib.pe_loglike_batch(ev, _ptr(theta, f64, "theta"), int(n), int(precision), _ptr(loglike, f64, "loglike"),
+                                 _ptr(aux, f64, "aux", allow_none=True), _stream(stream)))
+
+
+def pe_weights_ess(loglike, logprior, logq, n, w, stats, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(load().pe_weights_ess(_ptr(loglike, f64, "loglike"), _ptr(logprior, f64, "logprior"),
+                                 _ptr(logq, f64, "logq"), int(n), _ptr(w, f64, "w", allow_none=True),
+                                 _ptr(stats, f64, "stats"), _stream(stream)))
+
+
+def pe_waveform(desc, theta, psd, h, snr2=None, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(load().pe_waveform(ctypes.byref(desc), _ptr(theta, f64, "theta"), _ptr(psd, name="psd", allow_none=True),
+                              _ptr(h, None, "h"), _ptr(snr2, f64, "snr2", allow_none=True), _stream(stream)))
+
+
+def pe_rng_uniforms(seed, stream_id, n, npairs, u, stream=None):
+    import torch
+    _check(load().pe_rng_uniforms(int(seed) & 0xFFFFFFFFFFFFFFFF, int(stream_id) & 0xFFFFFFFF, int(n), int(npairs),
+                                  _ptr(u, torch.float64, "u"), _stream(stream)))
+
+
+def pe_profile_enable(enable):
+    _check(load().pe_profile_enable(1 if enable else 0))
+
+
+def pe_profile_read(kernel):
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(load().pe_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def pe_set_chunks(n_chunks):
+    _check(load().pe_set_chunks(int(n_chunks)))
+
+
+def pe_last_error():
+    return load().pe_last_error().decode()
+
+
+# ---------------------------------------------------------------- convenience
+class Event:
+    """Owns a pe_event_t. data: complex128/complex64 [n_det, K] device tensor; psd: float64/float32."""
+
+    def __init__(self, data, psd, stream=None, **desc_kw):
+        dd, pd = dtypes_of(data, psd)
+        n_det, K = psd.shape
+        self.desc = make_desc(n_det, K, data_dtype=dd, psd_dtype=pd, **desc_kw)
+        self.dim = pe_dim(self.desc.params)
+        self.handle = pe_event_create(self.desc, data, psd, stream)
+
+    def close(self):
+        if self.handle is not None:
+            pe_event_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, data, psd, stream=None):
+        pe_event_update(self.handle, data, psd, stream)
+
+    def status(self, stream=None):
+        pe_event_status(self.handle, stream)
+
+    def reserve(self, n):
+        pe_event_reserve(self.handle, n)
+
+    def metric(self, theta0, fd_step=None, flags=0, stream=None):
+        import torch
+        g = torch.empty((self.dim, self.dim), dtype=torch.float64, device=theta0.device)
+        pe_metric(self.handle, theta0, fd_step, flags, g, stream)
+        return g
+
+    def draw(self, theta0, g, seed, stream_id, n, stream=None):
+        import torch
+        dev = theta0.device
+        theta = torch.empty((self.dim, n), dtype=torch.float64, device=dev)
+        lq = torch.empty(n, dtype=torch.float64, device=dev)
+        lp = torch.empty(n, dtype=torch.float64, device=dev)
+        pe_draw(self.handle, theta0, g, seed, stream_id, n, theta, lq, lp, stream)
+        return theta, lq, lp
+
+    def loglike(self, theta, precision=PE_PREC_SPLIT, aux=False, stream=None):
+        import torch
+        n = theta.shape[1]
+        ll = torch.empty(n, dtype=torch.float64, device=theta.device)
+        ax = torch.empty((n, 3), dtype=torch.float64, device=theta.device) if aux else None
+        pe_loglike_batch(self.handle, theta, n, precision, ll, ax, stream)
+        return (ll, ax) if aux else ll
+
+
+def weights_ess(loglike, logprior, logq, want_w=True, stream=None):
+    import torch
+    n = loglike.shape[0]
+    w = torch.empty(n, dtype=torch.float64, device=loglike.device) if want_w else None
+    st = torch.empty(4, dtype=torch.float64, device=loglike.device)
+    pe_weights_ess(loglike, logprior, logq, n, w, st, stream)
+    return w, st

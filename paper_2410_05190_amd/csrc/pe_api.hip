@@ -1,0 +1,400 @@
+// pe_api.hip -- host runtime of the likelihood engine: the C ABI of include/pe.h,
+// argument validation, device tables and workspace, stream ordering, profiling.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "pe_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+pe_status_t fail(pe_status_t s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define PE_HIP(call)                                                                                  \
+    do {                                                                                              \
+        hipError_t _e = (call);                                                                       \
+        if (_e != hipSuccess) return fail(PE_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+int g_chunks = 0;  // 0 = automatic
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+pe_status_t validate_desc(const pe_event_desc_t* d) {
+    if (!d) return fail(PE_ERR_ARG, "desc is NULL");
+    if (d->n_det < 1 || d->n_det > PE_MAX_DET) return fail(PE_ERR_ARG, "n_det must be in 1..4");
+    if (d->n_bins < 1 || d->n_bins > (int64_t)1 << 30) return fail(PE_ERR_ARG, "n_bins must be in 1..2^30");
+    if (!(d->f_lo > 0.0) || !std::isfinite(d->f_lo)) return fail(PE_ERR_ARG, "f_lo must be > 0");
+    if (!(d->df > 0.0) || !std::isfinite(d->df)) return fail(PE_ERR_ARG, "df must be > 0");
+    if (d->data_dtype != PE_C128 && d->data_dtype != PE_C64) return fail(PE_ERR_ARG, "bad data_dtype");
+    if (d->psd_dtype != PE_F64 && d->psd_dtype != PE_F32) return fail(PE_ERR_ARG, "bad psd_dtype");
+    if (!(d->strain_scale > 0.0) || !std::isfinite(d->strain_scale)) return fail(PE_ERR_ARG, "strain_scale must be > 0");
+    if (d->params != PE_PARAMS_4D && d->params != PE_PARAMS_11D) return fail(PE_ERR_ARG, "bad params");
+    if (d->phase != PE_PHASE_MARG && d->phase != PE_PHASE_EXPLICIT) return fail(PE_ERR_ARG, "bad phase");
+    if (d->params == PE_PARAMS_4D && d->phase != PE_PHASE_MARG)
+        return fail(PE_ERR_ARG, "the 4-D parameter set is always phase-marginalised");
+    if (d->params == PE_PARAMS_4D && !(d->amp0 > 0.0)) return fail(PE_ERR_ARG, "4-D needs amp0 > 0");
+    if (!(d->chi_max >= 0.0)) return fail(PE_ERR_ARG, "chi_max must be >= 0");
+    if (d->params == PE_PARAMS_11D && !(d->dl_max > 0.0)) return fail(PE_ERR_ARG, "11-D needs dl_max > 0");
+    return PE_OK;
+}
+
+// Detector tensor D = (x x^T - y y^T)/2 from latitude, longitude and the
+// x-arm azimuth (north toward east); y arm 90 degrees east of x.
+void build_const(const pe_event_desc_t& d, pe::EvConst& ec) {
+    std::memset(&ec, 0, sizeof(ec));
+    ec.n_det = d.n_det;
+    ec.params = d.params;
+    ec.phase = d.phase;
+    ec.dim = pe_dim(d.params);
+    ec.K = d.n_bins;
+    ec.f_lo = d.f_lo;
+    ec.df = d.df;
+    ec.scale = d.strain_scale;
+    ec.amp0 = d.amp0;
+    ec.gmst = d.gmst;
+    ec.chi_max = d.chi_max;
+    ec.dl_max = d.dl_max;
+    for (int i = 0; i < d.n_det; ++i) {
+        const double lat = d.det_geom[i][0], lon = d.det_geom[i][1], az = d.det_geom[i][2];
+        const double up[3] = {std::cos(lat) * std::cos(lon), std::cos(lat) * std::sin(lon), std::sin(lat)};
+        const double east[3] = {-std::sin(lon), std::cos(lon), 0.0};
+        const double north[3] = {-std::sin(lat) * std::cos(lon), -std::sin(lat) * std::sin(lon), std::cos(lat)};
+        double x[3], y[3];
+        for (int a = 0; a < 3; ++a) {
+            x[a] = std::cos(az) * north[a] + std::sin(az) * east[a];
+            y[a] = -std::sin(az) * north[a] + std::cos(az) * east[a];
+        }
+        auto T = [&](int a, int b) { return 0.5 * (x[a] * x[b] - y[a] * y[b]); };
+        ec.dtensor[i][0] = T(0, 0);
+        ec.dtensor[i][1] = T(0, 1);
+        ec.dtensor[i][2] = T(0, 2);
+        ec.dtensor[i][3] = T(1, 1);
+        ec.dtensor[i][4] = T(1, 2);
+        ec.dtensor[i][5] = T(2, 2);
+        for (int a = 0; a < 3; ++a) ec.up[i][a] = up[a];
+    }
+}
+
+template <typename T>
+pe_status_t dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(PE_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    return PE_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_draw_ws(pe_event_s* ev) {
+    dfree(ev->flags);
+    dfree(ev->idx);
+    dfree(ev->n_active);
+    dfree(ev->coef);
+    dfree(ev->kcut);
+    dfree(ev->resp);
+    dfree(ev->hh);
+    dfree(ev->partial);
+    ev->npad = 0;
+    ev->n_chunks_alloc = 0;
+}
+
+void free_event(pe_event_s* ev) {
+    if (!ev) return;
+    free_draw_ws(ev);
+    dfree(ev->rec32);
+    dfree(ev->rec64);
+    dfree(ev->pw);
+    dfree(ev->pfx);
+    dfree(ev->status);
+    dfree(ev->mws);
+    delete ev;
+}
+
+// Frequency chunks of the hot loop, a multiple of 8: consecutive workgroups go to
+// different XCDs, so chunk c runs on XCD c mod 8 and each XCD's L2 holds only its
+// own chunks. At least 32 chunks, so that every XCD gets chunks from the whole
+// band (draws stop at their ISCO cut, which empties the top chunks), at least
+// ~2048 workgroups, and chunks of at least 256 bins.
+int auto_chunks(int64_t n, int64_t K) {
+    const int64_t tiles = (n + pe::kTile - 1) / pe::kTile;
+    const int64_t want = (2048 + tiles - 1) / (tiles > 0 ? tiles : 1);
+    int c = (int)(((want + 7) / 8) * 8);
+    if (c < 32) c = 32;
+    if (c > 256) c = 256;
+    while (c > 8 && (K + c - 1) / c < 256) c -= 8;
+    return c;
+}
+
+int chunks_for(int64_t n, int64_t K) { return g_chunks > 0 ? g_chunks : auto_chunks(n, K); }
+
+pe_status_t ensure_ws(pe_event_s* ev, int64_t n, int chunks) {
+    const int64_t npad = ((n + pe::kTile - 1) / pe::kTile) * pe::kTile;
+    if (npad <= ev->npad && chunks <= ev->n_chunks_alloc) return PE_OK;
+    PE_HIP(hipDeviceSynchronize());
+    const int64_t np = npad > ev->npad ? npad : ev->npad;
+    const int ch = chunks > ev->n_chunks_alloc ? chunks : ev->n_chunks_alloc;
+    free_draw_ws(ev);
+    const int nd = ev->desc.n_det;
+    pe_status_t s;
+    if ((s = dalloc(&ev->flags, (size_t)np)) != PE_OK) return s;
+    if ((s = dalloc(&ev->idx, (size_t)np)) != PE_OK) return s;
+    if ((s = dalloc(&ev->n_active, 1)) != PE_OK) return s;
+    if ((s = dalloc(&ev->coef, (size_t)pe::kNCoef * np)) != PE_OK) return s;
+    if ((s = dalloc(&ev->kcut, (size_t)np)) != PE_OK) return s;
+    if ((s = dalloc(&ev->resp, (size_t)2 * nd * np)) != PE_OK) return s;
+    if ((s = dalloc(&ev->hh, (size_t)np)) != PE_OK) return s;
+    if ((s = dalloc(&ev->partial, (size_t)ch * nd * np)) != PE_OK) return s;
+    ev->npad = np;
+    ev->n_chunks_alloc = ch;
+    return PE_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> g_prof;
+std::map<std::string, hipEvent_t> g_prof_open;
+
+}  // namespace
+
+namespace pe {
+
+void prof_begin(const char* name, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    hipEvent_t a;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    (void)hipEventRecord(a, st);
+    g_prof_open[name] = a;
+}
+
+void prof_end(const char* name, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    auto it = g_prof_open.find(name);
+    if (it == g_prof_open.end()) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) return;
+    (void)hipEventRecord(b, st);
+    g_prof[name].push_back({it->second, b});
+    g_prof_open.erase(it);
+}
+
+}  // namespace pe
+
+extern "C" {
+
+int32_t pe_dim(int32_t params) {
+    return params == PE_PARAMS_4D ? 4 : (params == PE_PARAMS_11D ? 11 : 0);
+}
+
+const char* pe_last_error(void) { return g_err.c_str(); }
+
+pe_status_t pe_event_create(const pe_event_desc_t* desc, const void* data_dev, const void* psd_dev, void* stream,
+                            pe_event_t* out) {
+    if (!out) return fail(PE_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    pe_status_t s = validate_desc(desc);
+    if (s != PE_OK) return s;
+    if (!data_dev || !psd_dev) return fail(PE_ERR_ARG, "data and psd must be device pointers");
+    pe_event_s* ev = new (std::nothrow) pe_event_s();
+    if (!ev) return fail(PE_ERR_OOM, "host allocation failed");
+    ev->desc = *desc;
+    build_const(*desc, ev->ec);
+    const int64_t K = desc->n_bins;
+    const int nd = desc->n_det;
+    if ((s = dalloc(&ev->rec32, (size_t)K)) != PE_OK || (s = dalloc(&ev->rec64, (size_t)K)) != PE_OK ||
+        (s = dalloc(&ev->pw, (size_t)nd * K)) != PE_OK || (s = dalloc(&ev->pfx, (size_t)nd * (K + 1))) != PE_OK ||
+        (s = dalloc(&ev->status, 1)) != PE_OK || (s = dalloc(&ev->mws, (size_t)pe::kMwsTotal)) != PE_OK) {
+        free_event(ev);
+        return s;
+    }
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemsetAsync(ev->status, 0, sizeof(int), st);
+    if (e == hipSuccess) e = hipMemsetAsync(ev->mws, 0, sizeof(double) * pe::kMwsTotal, st);
+    if (e == hipSuccess) e = pe::launch_prep(ev, data_dev, psd_dev, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_event(ev);
+        return fail(PE_ERR_HIP, std::string("event preparation: ") + hipGetErrorString(e));
+    }
+    s = pe_event_status(ev, stream);
+    if (s != PE_OK) {
+        std::string msg = g_err;
+        free_event(ev);
+        return fail(s, msg);
+    }
+    *out = ev;
+    return PE_OK;
+}
+
+pe_status_t pe_event_update(pe_event_t ev, const void* data_dev, const void* psd_dev, void* stream) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (!data_dev || !psd_dev) return fail(PE_ERR_ARG, "data and psd must be device pointers");
+    PE_HIP(pe::launch_prep(ev, data_dev, psd_dev, as_stream(stream)));
+    return PE_OK;
+}
+
+pe_status_t pe_event_status(pe_event_t ev, void* stream) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    hipStream_t st = as_stream(stream);
+    PE_HIP(hipStreamSynchronize(st));
+    int flags = 0;
+    PE_HIP(hipMemcpy(&flags, ev->status, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags) PE_HIP(hipMemset(ev->status, 0, sizeof(int)));
+    if (flags & pe::kStBadPsd) return fail(PE_ERR_ARG, "PSD values must be positive and finite");
+    if (flags & pe::kStNonfinite) return fail(PE_ERR_NONFINITE, "data contains inf or nan");
+    if (flags & pe::kStSingular) return fail(PE_ERR_SINGULAR, "metric is not positive definite");
+    return PE_OK;
+}
+
+pe_status_t pe_event_reserve(pe_event_t ev, int64_t max_draws) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (max_draws < 0 || max_draws > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "max_draws must be in 0..2^30");
+    return ensure_ws(ev, max_draws, chunks_for(max_draws, ev->desc.n_bins));
+}
+
+pe_status_t pe_event_destroy(pe_event_t ev) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    (void)hipDeviceSynchronize();
+    free_event(ev);
+    return PE_OK;
+}
+
+pe_status_t pe_metric(pe_event_t ev, const double* theta0_dev, const double* fd_step_dev, int32_t flags,
+                      double* g_dev, void* stream) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (!theta0_dev || !g_dev) return fail(PE_ERR_ARG, "theta0 and g must be device pointers");
+    if (flags & ~1) return fail(PE_ERR_ARG, "unknown metric flags");
+    PE_HIP(pe::launch_metric(ev, theta0_dev, fd_step_dev, flags, g_dev, as_stream(stream)));
+    return PE_OK;
+}
+
+pe_status_t pe_draw(pe_event_t ev, const double* theta0_dev, const double* g_dev, uint64_t seed, uint32_t stream_id,
+                    int64_t n, double* theta_dev, double* logq_dev, double* logprior_dev, void* stream) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (n < 0 || n > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "n must be in 0..2^30");
+    if (!theta0_dev || !g_dev) return fail(PE_ERR_ARG, "theta0 and g must be device pointers");
+    if (n > 0 && (!theta_dev || !logq_dev || !logprior_dev)) return fail(PE_ERR_ARG, "output pointers are NULL");
+    PE_HIP(pe::launch_draw(ev, theta0_dev, g_dev, seed, stream_id, n, theta_dev, logq_dev, logprior_dev,
+                           as_stream(stream)));
+    return PE_OK;
+}
+
+pe_status_t pe_loglike_batch(pe_event_t ev, const double* theta_dev, int64_t n, int32_t precision,
+                             double* loglike_dev, double* aux_dev, void* stream) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (n < 0 || n > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "n must be in 0..2^30");
+    if (precision != PE_PREC_FP64 && precision != PE_PREC_SPLIT) return fail(PE_ERR_ARG, "bad precision");
+    if (n == 0) return PE_OK;
+    if (!theta_dev || !loglike_dev) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
+    const int chunks = chunks_for(n, ev->desc.n_bins);
+    pe_status_t s = ensure_ws(ev, n, chunks);
+    if (s != PE_OK) return s;
+    PE_HIP(pe::launch_loglike(ev, theta_dev, n, precision, chunks, loglike_dev, aux_dev, as_stream(stream)));
+    return PE_OK;
+}
+
+pe_status_t pe_weights_ess(const double* loglike_dev, const double* logprior_dev, const double* logq_dev, int64_t n,
+                           double* w_dev, double* stats_dev, void* stream) {
+    if (n < 0) return fail(PE_ERR_ARG, "n must be >= 0");
+    if (!stats_dev) return fail(PE_ERR_ARG, "stats must be a device pointer");
+    if (n > 0 && (!loglike_dev || !logprior_dev || !logq_dev)) return fail(PE_ERR_ARG, "inputs are NULL");
+    PE_HIP(pe::launch_weights(loglike_dev, logprior_dev, logq_dev, n, w_dev, stats_dev, as_stream(stream)));
+    return PE_OK;
+}
+
+pe_status_t pe_waveform(const pe_event_desc_t* desc, const double* theta_dev, const void* psd_dev, double* h_dev,
+                        double* snr2_dev, void* stream) {
+    pe_event_desc_t d2;
+    if (!desc) return fail(PE_ERR_ARG, "desc is NULL");
+    d2 = *desc;
+    if (d2.params == PE_PARAMS_4D && !(d2.amp0 > 0.0)) d2.amp0 = 1.0;
+    pe_status_t s = validate_desc(&d2);
+    if (s != PE_OK) return s;
+    if (!theta_dev || !h_dev) return fail(PE_ERR_ARG, "theta and h must be device pointers");
+    if (snr2_dev && !psd_dev) return fail(PE_ERR_ARG, "snr2 needs the PSD");
+    pe::EvConst ec;
+    build_const(*desc, ec);
+    const int64_t nb = (ec.K + 255) / 256;
+    double* scratch = nullptr;
+    if ((s = dalloc(&scratch, (size_t)(32 + nb))) != PE_OK) return s;
+    hipStream_t st = as_stream(stream);
+    hipError_t e = pe::launch_waveform(ec, desc->psd_dtype, theta_dev, psd_dev, h_dev, snr2_dev, scratch, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(scratch);
+    if (e != hipSuccess) return fail(PE_ERR_HIP, std::string("waveform: ") + hipGetErrorString(e));
+    return PE_OK;
+}
+
+pe_status_t pe_rng_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int32_t npairs, double* u_dev,
+                            void* stream) {
+    if (n < 0 || npairs < 0 || npairs > 64) return fail(PE_ERR_ARG, "bad n or npairs");
+    if (n * npairs > 0 && !u_dev) return fail(PE_ERR_ARG, "u must be a device pointer");
+    PE_HIP(pe::launch_uniforms(seed, stream_id, n, npairs, u_dev, as_stream(stream)));
+    return PE_OK;
+}
+
+pe_status_t pe_profile_enable(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = enable != 0;
+    return PE_OK;
+}
+
+pe_status_t pe_profile_read(const char* kernel, double* total_ms, int64_t* launches) {
+    if (!kernel || !total_ms || !launches) return fail(PE_ERR_ARG, "NULL argument");
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> v;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        auto it = g_prof.find(kernel);
+        if (it != g_prof.end()) {
+            v.swap(it->second);
+            g_prof.erase(it);
+        }
+    }
+    double tot = 0.0;
+    pe_status_t s = PE_OK;
+    for (auto& p : v) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(p.second) != hipSuccess || hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess)
+            s = fail(PE_ERR_HIP, "profiling event failed");
+        tot += ms;
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    *total_ms = tot;
+    *launches = (int64_t)v.size();
+    return s;
+}
+
+pe_status_t pe_set_chunks(int32_t n_chunks) {
+    if (n_chunks != 0 && (n_chunks < 8 || n_chunks > 256 || n_chunks % 8 != 0))
+        return fail(PE_ERR_ARG, "n_chunks must be 0 or a multiple of 8 in 8..256");
+    g_chunks = n_chunks;
+    return PE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// pe_internal.h -- shared declarations of the library's host runtime and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pe.h"
+
+namespace pe {
+
+// Physical constants (the paper fixes none): IAU nominal GM_sun, exact c,
+// IAU parsec, mean Earth radius (spherical Earth).
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kTwoPi = 6.283185307179586476925286766559005768;
+constexpr double kInvTwoPi = 0.159154943091895335768883763372514362;
+constexpr double kLn4 = 1.386294361119890618834464242916353136;
+constexpr double kEulerGamma = 0.577215664901532860606512090082402431;
+constexpr double kGMsun = 1.32712440018e20;
+constexpr double kC = 299792458.0;
+constexpr double kTsun = kGMsun / (kC * kC * kC);
+constexpr double kMpc = 3.0856775814913673e22;
+constexpr double kREarth = 6.371e6;
+constexpr double kSix32 = 14.69693845669906858918;    // 6^(3/2)
+constexpr double kAmpNewt = 0.21278751013966339916;   // sqrt(5/24) pi^(-2/3)
+
+// Per-event constants, passed to kernels by value.
+struct EvConst {
+    int32_t n_det, params, phase, dim;
+    int64_t K;
+    double f_lo, df, scale, amp0, gmst, chi_max, dl_max;
+    double dtensor[PE_MAX_DET][6];  // detector tensor (x x^T - y y^T)/2: xx xy xz yy yz zz
+    double up[PE_MAX_DET][3];       // unit vector to the detector from the geocentre
+};
+
+// Per-bin table records, one 64-byte (split) or 96-byte (FP64) record per bin
+// so that a wave reads a bin with one scalar load.
+struct alignas(64) Rec32 {
+    double f, x, xm5, lnx;  // f, f^(1/3), f^(-5/3), ln(f)/3
+    float2 w[PE_MAX_DET];   // |w|, arg(w)/(2 pi) in [0, 1)
+};
+struct alignas(32) Rec64 {
+    double f, x, xm5, lnx;
+    double2 w[PE_MAX_DET];  // w = 4 df f^(-7/6) d / S
+};
+static_assert(sizeof(Rec32) == 64, "Rec32 must be one 64-byte scalar load");
+static_assert(sizeof(Rec64) == 96, "Rec64 must be 96 bytes");
+
+// Per-draw coefficient rows (structure of arrays, row stride = npad).
+constexpr int kCoefA = 0;     // A0..A7
+constexpr int kCoefB5 = 8;
+constexpr int kCoefB6 = 9;
+constexpr int kCoefTau = 10;  // tau_d = tc + dt_d, PE_MAX_DET rows
+constexpr int kNCoef = 14;
+
+constexpr int kTile = 256;    // draws per workgroup of the hot loop
+constexpr int kBlk = 32;      // bins per FP32 partial before the compensated fold
+
+// Device status bits (event status word).
+constexpr int kStBadPsd = 1;
+constexpr int kStNonfinite = 2;
+constexpr int kStSingular = 4;
+
+// Workspace of the metric: per FD source, coefficients, response and delays.
+constexpr int kMetricSrcStride = 32;  // doubles: A[8], B5, B6, rre[4], rim[4], tau[4], pad
+constexpr int kMetricMaxDp = PE_MAX_DIM + 1;
+constexpr int kMetricNG = kMetricMaxDp * (kMetricMaxDp + 1) / 2;  // 78 >= 66
+constexpr int kMetricBlocks = 512;
+
+}  // namespace pe
+
+struct pe_event_s {
+    pe_event_desc_t desc;
+    pe::EvConst ec;
+    // tables
+    pe::Rec32 *rec32 = nullptr;
+    pe::Rec64 *rec64 = nullptr;
+    double *pw = nullptr;   // [n_det][K] 4 df f^(-7/3) / S
+    double *pfx = nullptr;  // [n_det][K+1] exclusive prefix of pw
+    int *status = nullptr;  // device status word
+    // per-draw workspace
+    int64_t npad = 0;
+    int n_chunks_alloc = 0;
+    int *flags = nullptr;
+    int *idx = nullptr;
+    int *n_active = nullptr;
+    double *coef = nullptr;  // [kNCoef][npad]
+    int *kcut = nullptr;     // [npad]
+    double *resp = nullptr;  // [2*n_det][npad] Re/Im R_d
+    double *hh = nullptr;    // [npad] (h|h)
+    double2 *partial = nullptr;
+    // metric + draw workspace
+    double *mws = nullptr;
+};
+
+namespace pe {
+
+// kernel launchers (pe_kernels.hip)
+hipError_t launch_prep(const pe_event_s *ev, const void *data, const void *psd, hipStream_t st);
+hipError_t launch_loglike(const pe_event_s *ev, const double *theta, int64_t n, int precision, int n_chunks,
+                          double *loglike, double *aux, hipStream_t st);
+hipError_t launch_metric(const pe_event_s *ev, const double *theta0, const double *steps, int flags, double *g,
+                         hipStream_t st);
+hipError_t launch_draw(const pe_event_s *ev, const double *theta0, const double *g, uint64_t seed, uint32_t stream_id,
+                       int64_t n, double *theta, double *logq, double *logprior, hipStream_t st);
+hipError_t launch_weights(const double *ll, const double *lp, const double *lq, int64_t n, double *w, double *stats,
+                          hipStream_t st);
+hipError_t launch_waveform(const EvConst &ec, int data_psd_dtype, const double *theta, const void *psd, double *h,
+                           double *snr2, double *scratch, hipStream_t st);
+hipError_t launch_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int npairs, double *u, hipStream_t st);
+
+// metric workspace layout (doubles)
+constexpr int64_t kMwsSteps = 0;                                     // D steps
+constexpr int64_t kMwsDen = 16;                                      // D step sums
+constexpr int64_t kMwsSrc = 32;                                      // (2D+1) sources
+constexpr int64_t kMwsPart = kMwsSrc + (2 * PE_MAX_DIM + 1) * kMetricSrcStride;
+constexpr int64_t kMwsChol = kMwsPart + (int64_t)kMetricBlocks * kMetricNG;  // L (D*D) + logdet + flag
+constexpr int kScanSeg = 256;                                        // segments of the prefix scan
+constexpr int64_t kMwsScan = kMwsChol + PE_MAX_DIM * PE_MAX_DIM + 8;  // segment sums [n_det][kScanSeg]
+constexpr int64_t kMwsTotal = kMwsScan + (int64_t)PE_MAX_DET * kScanSeg;
+constexpr int64_t kMwsKcut = kMwsSrc - 4;  // frozen cut of the metric (stored as double)
+
+// profiling hooks (pe_api.hip)
+void prof_begin(const char *name, hipStream_t st);
+void prof_end(const char *name, hipStream_t st);
+
+}  // namespace pe

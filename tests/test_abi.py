@@ -1,0 +1,50 @@
+"""The C ABI: libpe.so loads without a GPU and exports every entry point that
+include/pe.h declares (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+from paper_2410_05190_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "pe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pe_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("pe_metric", "pe_draw", "pe_loglike_batch", "pe_weights_ess", "pe_event_create",
+                 "pe_event_destroy", "pe_last_error"):
+        assert must in names
+    assert set(names) == set(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_loads_and_pure_host_calls():
+    L = binding.load()
+    assert binding.pe_dim(binding.PE_PARAMS_4D) == 4
+    assert binding.pe_dim(binding.PE_PARAMS_11D) == 11
+    assert binding.pe_dim(7) == 0
+    # argument errors are caught on the host before any device work
+    d = binding.make_desc(0, 10, 20.0, 0.25)
+    h = ctypes.c_void_p()
+    st = L.pe_event_create(ctypes.byref(d), None, None, None, ctypes.byref(h))
+    assert st == 1 and h.value is None
+    assert "n_det" in binding.pe_last_error()
+    assert L.pe_set_chunks(12) == 1
+    assert L.pe_set_chunks(0) == 0
+    assert L.pe_loglike_batch(None, None, 0, 0, None, None, None) == 1
+
+
+def test_event_desc_layout_matches_header():
+    # pe_event_desc_t: int32, int64, 2 double, 2 int32, double, 2 int32, 4 double, double[4][3]
+    assert ctypes.sizeof(binding.EventDesc) == 8 + 8 + 16 + 8 + 8 + 8 + 32 + 96

@@ -1,0 +1,284 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on the same
+seeded inputs (element by element), plus edge cases and error paths.
+
+Tolerances (derivations in the design doc):
+  - FP64 path: |d ln L| <= 32 u Phi_N(f_lo) sum_k |t_k| (gpu_util.fp64_tol: both sides round the
+    phase differently by ~u |Phi| per bin, summed coherently over the band), relative 1e-10 on
+    Z and H;
+  - split path: |d ln L| <= 1e-3 absolute (the stated bound); the internal target is 2.5e-4,
+    which keeps ESS and the weights within 1e-3 relative;
+  - metric: 1e-6 of sqrt(g_ii g_jj) (finite differences of phases computed in two different
+    algebraic forms);
+  - draws: uniforms bit-exact; theta within 1e-9 proposal standard deviations (and in the
+    whitened coordinates L^T dtheta); log q 1e-8; weights/ESS 1e-12 relative on identical inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from events import build_event
+from gpu_util import desc_kwargs, dev, fp64_tol, host, note, torch_cuda, upload_event
+from paper_2410_05190_amd import binding
+from paper_2410_05190_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_draws(b, n, seed=11, stream=0, g=None):
+    g = b.ev.metric(b.theta_inj) if g is None else g
+    rc, th, lq, lp = b.ev.draw(b.theta_inj, g, seed, stream, n)
+    assert rc == 0
+    return g, th, lq, lp
+
+
+def test_library_loads_on_gpu():
+    torch = torch_cuda()
+    binding.load()
+    assert binding.pe_dim(binding.PE_PARAMS_11D) == 11
+    assert torch.cuda.device_count() >= 1
+
+
+def test_uniforms_bit_exact():
+    torch = torch_cuda()
+    for seed, stream, n, npairs in ((1, 0, 1000, 6), (2 ** 63 + 12345, 77, 257, 2), (0, 2 ** 32 - 1, 3, 1)):
+        u = torch.empty((n, npairs, 2), dtype=torch.float64, device="cuda")
+        binding.pe_rng_uniforms(seed, stream, n, npairs, u)
+        want = oracle.uniforms(seed, stream, n, npairs)
+        np.testing.assert_array_equal(host(u), want)
+
+
+@pytest.mark.parametrize("cfg,K", [(0, 31488), (1, 30000), (1, 519168), (2, 8032)])
+def test_waveform_parity(cfg, K):
+    torch = torch_cuda()
+    note(f"waveform cfg={cfg} K={K}")
+    b = build_event(cfg, 0, n_bins=K)
+    d = binding.make_desc(b.n_det, b.n_bins, data_dtype=binding.PE_C128,
+                          psd_dtype=binding.PE_F64 if b.psd.dtype == np.float64 else binding.PE_F32,
+                          **desc_kwargs(b))
+    h = torch.empty((b.n_det, b.n_bins, 2), dtype=torch.float64, device="cuda")
+    snr2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    psd = torch.from_numpy(b.psd).cuda()
+    binding.pe_waveform(d, dev(b.theta_inj), psd, h, snr2)
+    hg = host(h)
+    hg = hg[..., 0] + 1j * hg[..., 1]
+    ho = b.ev.waveform(b.theta_inj)
+    scale = np.abs(ho).max()
+    err = np.abs(hg - ho).max() / scale
+    note(f"  max |dh|/max|h| = {err:.3e}")
+    assert err < 1e-9
+    want = sum(b.ev.inner(i, ho, ho) for i in range(b.n_det))
+    assert host(snr2)[0] == pytest.approx(want, rel=1e-10)
+
+
+def test_loglike_fp64_parity_c0_full():
+    """Config 0 at full size: 4096 draws, 31488 bins, FP64 path."""
+    torch_cuda()
+    b = build_event(0, 0)
+    g, th, lq, lp = _oracle_draws(b, 4096)
+    note("oracle loglike c0 (4096 draws x 31488 bins)")
+    ll_o, zh_o = b.ev.loglike(th, return_zh=True)
+    ev, data, psd = upload_event(b)
+    ll, aux = ev.loglike(dev(th), precision=binding.PE_PREC_FP64, aux=True)
+    ev.status()
+    ll = host(ll)
+    aux = host(aux)
+    fin = np.isfinite(ll_o)
+    assert np.array_equal(fin, np.isfinite(ll))
+    assert fin.sum() > 100 and (~fin).sum() > 100  # both live and out-of-support draws present
+    d = np.abs(ll[fin] - ll_o[fin])
+    tol = fp64_tol(b)
+    note(f"  c0 fp64 max |dlnL| = {d.max():.3e} (bound {tol:.2e}; live {fin.sum()})")
+    assert d.max() <= tol
+    np.testing.assert_allclose(aux[fin], zh_o[fin], rtol=1e-10, atol=1e-9)
+
+
+@pytest.mark.parametrize("K,n,event", [(40000, 1500, 0), (100003, 777, 1)])
+def test_loglike_split_and_fp64_parity_c1_small(K, n, event):
+    """Config-1 shape (3 detectors, 11-D, complex64/FP32 storage) on a truncated grid, ragged sizes."""
+    torch_cuda()
+    b = build_event(1, event, n_bins=K)
+    g, th, lq, lp = _oracle_draws(b, n, seed=5 + event)
+    note(f"oracle loglike c1 K={K} n={n}")
+    ll_o, zh_o = b.ev.loglike(th, return_zh=True)
+    ev, data, psd = upload_event(b)
+    ths = dev(th)
+    ll_s = host(ev.loglike(ths, precision=binding.PE_PREC_SPLIT))
+    ll_d = host(ev.loglike(ths, precision=binding.PE_PREC_FP64))
+    ev.status()
+    fin = np.isfinite(ll_o)
+    assert np.array_equal(fin, np.isfinite(ll_s)) and np.array_equal(fin, np.isfinite(ll_d))
+    ds = np.abs(ll_s[fin] - ll_o[fin]).max()
+    dd = np.abs(ll_d[fin] - ll_o[fin]).max()
+    tol = fp64_tol(b)
+    note(f"  split max |dlnL| = {ds:.3e}; fp64 max |dlnL| = {dd:.3e} (bound {tol:.2e}); live {fin.sum()}/{n}")
+    assert dd <= tol
+    assert ds <= 1e-3
+
+
+def test_loglike_split_parity_c1_full_size_sampled():
+    """Config 1 at full size in the benchmark's launch shape (65536 draws, 519168 bins), checked
+    on draws sampled for the oracle."""
+    torch_cuda()
+    b = build_event(1, 0)
+    N = 65536
+    g, th, lq, lp = _oracle_draws(b, N, seed=synth.draw_seed(1, 0))
+    ev, data, psd = upload_event(b)
+    ev.reserve(N)
+    note("gpu split loglike c1 full size")
+    ll_s = host(ev.loglike(dev(th), precision=binding.PE_PREC_SPLIT))
+    ev.status()
+    rng = np.random.default_rng(3)
+    live = np.flatnonzero(np.isfinite(ll_s))
+    pick = np.sort(np.concatenate([rng.choice(live, 40, replace=False), live[:4], live[-4:]]))
+    note(f"oracle loglike on {pick.size} sampled draws")
+    ll_o = b.ev.loglike(th[:, pick])
+    d = np.abs(ll_s[pick] - ll_o)
+    note(f"  c1 full split max |dlnL| = {d.max():.3e}")
+    assert d.max() <= 1e-3
+    # support decisions are exact for every draw (the oracle's prior is finite exactly on the support)
+    assert np.array_equal(np.isfinite(lp), np.isfinite(ll_s))
+
+
+def test_metric_parity():
+    torch = torch_cuda()
+    for cfg, K in ((0, 31488), (1, 60000), (2, 8032)):
+        b = build_event(cfg, 1, n_bins=K)
+        ev, data, psd = upload_event(b)
+        st = b.ev.default_steps(b.theta_inj)
+        for flags in (0, 1):
+            go = b.ev.metric(b.theta_inj, steps=st, flags=flags)
+            gg = host(ev.metric(dev(b.theta_inj), fd_step=dev(st), flags=flags))
+            gd = host(ev.metric(dev(b.theta_inj), fd_step=None, flags=flags))
+            norm = np.sqrt(np.outer(np.abs(np.diag(go)), np.abs(np.diag(go))))
+            norm[norm == 0] = 1.0
+            e1 = np.max(np.abs(gg - go) / norm)
+            e2 = np.max(np.abs(gd - go) / norm)
+            note(f"metric cfg={cfg} flags={flags}: explicit steps {e1:.2e}, default steps {e2:.2e}")
+            assert e1 < 1e-6 and e2 < 1e-6
+        ev.status()
+
+
+def test_draw_parity():
+    torch = torch_cuda()
+    for cfg in (0, 1):
+        b = build_event(cfg, 2, n_bins=20000)
+        g = b.ev.metric(b.theta_inj)
+        n = 3001
+        rc, th_o, lq_o, lp_o = b.ev.draw(b.theta_inj, g, 987654321, 3, n)
+        ev, data, psd = upload_event(b)
+        th, lq, lp = ev.draw(dev(b.theta_inj), dev(g), 987654321, 3, n)
+        ev.status()
+        th, lq, lp = host(th), host(lq), host(lp)
+        dth = th - th_o
+        if cfg == 1:  # periodic coordinates compared on the circle
+            for i, P in ((4, 2 * math.pi), (7, math.pi), (10, 2 * math.pi)):
+                dth[i] = (dth[i] + P / 2) % P - P / 2
+        sd = np.sqrt(np.diag(np.linalg.inv(g)))
+        err = np.max(np.abs(dth) / sd[:, None])
+        white = np.max(np.abs(np.linalg.cholesky(g).T @ dth))
+        note(f"draws cfg={cfg}: max |dtheta|/sd {err:.2e}, whitened {white:.2e}, logq {np.abs(lq - lq_o).max():.2e}")
+        assert err < 1e-9 and white < 1e-9
+        np.testing.assert_allclose(lq, lq_o, rtol=0, atol=1e-8)
+        fin = np.isfinite(lp_o)
+        assert np.array_equal(fin, np.isfinite(lp))
+        # theta agrees to ~1e-11 sd, so ln dL, ln cos(dec), ln sin(iota) agree to ~1e-11
+        np.testing.assert_allclose(lp[fin], lp_o[fin], rtol=0, atol=1e-9)
+
+
+def test_weights_parity_and_identities():
+    torch = torch_cuda()
+    rng = np.random.default_rng(9)
+    for n in (1, 1000, 65536, 262144 + 3):
+        ll = rng.normal(0, 4, n)
+        ll[rng.random(n) < 0.3] = -np.inf
+        lp = rng.normal(0, 1, n)
+        lq = rng.normal(0, 1, n)
+        w, st = binding.weights_ess(dev(ll), dev(lp), dev(lq))
+        w_o, st_o = oracle.weights_ess(ll, lp, lq)
+        np.testing.assert_allclose(host(w), w_o, rtol=1e-12, atol=1e-300)
+        np.testing.assert_allclose(host(st), st_o, rtol=1e-12)
+    # equal weights: ESS = N exactly; all -inf: ESS = 0
+    w, st = binding.weights_ess(dev(np.full(4096, -2.0)), dev(np.zeros(4096)), dev(np.zeros(4096)))
+    assert host(st)[0] == 4096.0
+    w, st = binding.weights_ess(dev(np.full(10, -np.inf)), dev(np.zeros(10)), dev(np.zeros(10)))
+    s = host(st)
+    assert s[0] == 0 and s[3] == 0 and s[1] == -np.inf and np.all(host(w) == 0)
+
+
+def test_split_weights_and_ess_within_tolerance():
+    """Whole chain at config-1 shape: ESS and normalised weights from the split path agree with the
+    oracle's within 1e-3 relative (on weights above 1e-6 of the largest)."""
+    torch = torch_cuda()
+    b = build_event(1, 3, n_bins=60000)
+    g = b.ev.metric(b.theta_inj)
+    n = 2000
+    seed = 424242
+    rc, th_o, lq_o, lp_o = b.ev.draw(b.theta_inj, g, seed, 1, n)
+    ll_o = b.ev.loglike(th_o)
+    w_o, st_o = oracle.weights_ess(ll_o, lp_o, lq_o)
+    ev, data, psd = upload_event(b)
+    th, lq, lp = ev.draw(dev(b.theta_inj), dev(g), seed, 1, n)
+    ll = ev.loglike(dev(th_o), precision=binding.PE_PREC_SPLIT)
+    w, st = binding.weights_ess(ll, lp, lq)
+    ev.status()
+    w, st = host(w), host(st)
+    note(f"ESS gpu {st[0]:.6f} oracle {st_o[0]:.6f}")
+    assert st[0] == pytest.approx(st_o[0], rel=1e-3)
+    big = w_o > 1e-6 * w_o.max()
+    np.testing.assert_allclose(w[big], w_o[big], rtol=1e-3)
+
+
+def test_edge_cases_and_determinism():
+    torch = torch_cuda()
+    b = build_event(1, 0, n_bins=5000)
+    ev, data, psd = upload_event(b)
+    # n = 0 is a no-op
+    e = torch.empty((11, 0), dtype=torch.float64, device="cuda")
+    binding.pe_loglike_batch(ev.handle, e, 0, binding.PE_PREC_SPLIT, torch.empty(0, dtype=torch.float64,
+                                                                                  device="cuda"))
+    # single draw at the injection
+    th1 = b.theta_inj[:, None].copy()
+    tol64 = fp64_tol(b)
+    for prec in (binding.PE_PREC_SPLIT, binding.PE_PREC_FP64):
+        ll = host(ev.loglike(dev(th1), precision=prec))
+        assert abs(ll[0] - b.ev.loglike(th1)[0]) < (1e-3 if prec == binding.PE_PREC_SPLIT else tol64)
+    # every draw out of support
+    bad = np.repeat(b.theta_inj[:, None], 300, axis=1)
+    bad[1] = 1.5
+    ll = host(ev.loglike(dev(bad)))
+    assert np.all(ll == -np.inf)
+    # bitwise reproducible
+    g = b.ev.metric(b.theta_inj)
+    rc, th, lq, lp = b.ev.draw(b.theta_inj, g, 5, 0, 1000)
+    a1 = host(ev.loglike(dev(th)))
+    a2 = host(ev.loglike(dev(th)))
+    assert np.array_equal(a1, a2, equal_nan=True)
+    ev.status()
+
+
+def test_event_input_errors():
+    torch = torch_cuda()
+    b = build_event(1, 0, n_bins=2000)
+    psd = b.psd.copy()
+    psd[0, 17] = 0.0
+    data = torch.from_numpy(b.data).cuda()
+    with pytest.raises(binding.PeError) as ei:
+        binding.Event(data, torch.from_numpy(psd).cuda(), **desc_kwargs(b))
+    assert ei.value.status == 1
+    dat = b.data.copy()
+    dat[2, 5] = np.nan
+    with pytest.raises(binding.PeError) as ei:
+        binding.Event(torch.from_numpy(dat).cuda(), torch.from_numpy(b.psd).cuda(),
+                      **desc_kwargs(b))
+    assert ei.value.status == 5
+    ev, d_, p_ = upload_event(b)
+    gbad = np.eye(11)
+    gbad[3, 3] = -1.0
+    th, lq, lp = ev.draw(dev(b.theta_inj), dev(gbad), 1, 0, 100)
+    with pytest.raises(binding.PeError) as ei:
+        ev.status()
+    assert ei.value.status == 4
+    assert np.all(host(lp) == -np.inf)
+    ev.status()  # cleared

@@ -28,7 +28,7 @@ def test_hh_constant_psd_is_hurwitz_zeta(K, mc, eta):
     th = np.array([mc, eta, 0.0, 0.0])
     h = ev.waveform(th)
     ok, src = ev.source(th)
-    kc = src.kcut
+    kc = ev.kcut(src.fisco)
     hh = ev.inner(0, h, h)
     a = mpmath.mpf(f_lo) / mpmath.mpf(df)
     want = 4 * mpmath.mpf(A) ** 2 * mpmath.mpf(df) ** (-mpmath.mpf(4) / 3) / mpmath.mpf(S0) * (
@@ -48,7 +48,7 @@ def test_hh_config_psd_matches_snr_integral():
     h = ev.waveform(th)
     hh = ev.inner(0, h, h)
     ok, src = ev.source(th)
-    b = f_lo + src.kcut * df
+    b = f_lo + ev.kcut(src.fisco) * df
 
     def g(x):
         return 4.0 * A * A * x ** (-7.0 / 3.0) / synth.psd_analytic(x)
