@@ -34,7 +34,7 @@ FP64_OPS_PER_TERM = 2 + 26 + 4
 # HBM bytes per launch of the split kernel at the benchmark shape, from rocprofv3
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors read off a 1 GiB device copy
 # in the same run; None when the kernel has changed since the counters were taken.
-SPLIT_TRAFFIC_BYTES = None
+SPLIT_TRAFFIC_BYTES = 826085683  # profiles/loglike_split_config1.md
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 
 

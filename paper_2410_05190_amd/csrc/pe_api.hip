@@ -109,9 +109,11 @@ void dfree(T*& p) {
 }
 
 void free_draw_ws(pe_event_s* ev) {
-    dfree(ev->flags);
+    dfree(ev->kc_all);
+    dfree(ev->hist);
     dfree(ev->idx);
     dfree(ev->n_active);
+    dfree(ev->queue);
     dfree(ev->coef);
     dfree(ev->kcut);
     dfree(ev->resp);
@@ -133,22 +135,23 @@ void free_event(pe_event_s* ev) {
     delete ev;
 }
 
-// Frequency chunks of the hot loop, a multiple of 8: consecutive workgroups go to
-// different XCDs, so chunk c runs on XCD c mod 8 and each XCD's L2 holds only its
-// own chunks. At least 32 chunks, so that every XCD gets chunks from the whole
-// band (draws stop at their ISCO cut, which empties the top chunks), at least
-// ~2048 workgroups, and chunks of at least 256 bins.
-int auto_chunks(int64_t n, int64_t K) {
-    const int64_t tiles = (n + pe::kTile - 1) / pe::kTile;
-    const int64_t want = (2048 + tiles - 1) / (tiles > 0 ? tiles : 1);
-    int c = (int)(((want + 7) / 8) * 8);
-    if (c < 32) c = 32;
-    if (c > 256) c = 256;
-    while (c > 8 && (K + c - 1) / c < 256) c -= 8;
+// Groups of fine frequency chunks in the hot loop (= FP64 partials per draw and
+// detector): a multiple of 8, one per fine chunk up to 64, fewer if the partials
+// (n_det x groups x draws x 16 B) would pass 1 GiB. Depends on the event only
+// (given a reserved capacity), so a draw's result does not depend on its batch.
+int auto_groups(int64_t K, int n_det, int64_t npad) {
+    const int64_t n_fine = (K + pe::kFine - 1) / pe::kFine;
+    int c = (int)(((n_fine + 7) / 8) * 8);
+    if (c > 64) c = 64;
+    const int64_t cap = ((int64_t)1 << 30) / (16 * (int64_t)n_det * (npad > 0 ? npad : 1));
+    while (c > 8 && c > cap) c -= 8;
     return c;
 }
 
-int chunks_for(int64_t n, int64_t K) { return g_chunks > 0 ? g_chunks : auto_chunks(n, K); }
+int groups_for(int64_t n, int64_t K, int n_det, int64_t npad_now) {
+    const int64_t npad = ((n + pe::kTile - 1) / pe::kTile) * pe::kTile;
+    return g_chunks > 0 ? g_chunks : auto_groups(K, n_det, npad > npad_now ? npad : npad_now);
+}
 
 pe_status_t ensure_ws(pe_event_s* ev, int64_t n, int chunks) {
     const int64_t npad = ((n + pe::kTile - 1) / pe::kTile) * pe::kTile;
@@ -159,9 +162,11 @@ pe_status_t ensure_ws(pe_event_s* ev, int64_t n, int chunks) {
     free_draw_ws(ev);
     const int nd = ev->desc.n_det;
     pe_status_t s;
-    if ((s = dalloc(&ev->flags, (size_t)np)) != PE_OK) return s;
+    if ((s = dalloc(&ev->kc_all, (size_t)np)) != PE_OK) return s;
+    if ((s = dalloc(&ev->hist, (size_t)pe::kBuckets)) != PE_OK) return s;
     if ((s = dalloc(&ev->idx, (size_t)np)) != PE_OK) return s;
     if ((s = dalloc(&ev->n_active, 1)) != PE_OK) return s;
+    if ((s = dalloc(&ev->queue, 8)) != PE_OK) return s;
     if ((s = dalloc(&ev->coef, (size_t)pe::kNCoef * np)) != PE_OK) return s;
     if ((s = dalloc(&ev->kcut, (size_t)np)) != PE_OK) return s;
     if ((s = dalloc(&ev->resp, (size_t)2 * nd * np)) != PE_OK) return s;
@@ -226,7 +231,8 @@ pe_status_t pe_event_create(const pe_event_desc_t* desc, const void* data_dev, c
     build_const(*desc, ev->ec);
     const int64_t K = desc->n_bins;
     const int nd = desc->n_det;
-    if ((s = dalloc(&ev->rec32, (size_t)K)) != PE_OK || (s = dalloc(&ev->rec64, (size_t)K)) != PE_OK ||
+    if ((s = dalloc(&ev->rec32, (size_t)(K + pe::kTabPad))) != PE_OK ||
+        (s = dalloc(&ev->rec64, (size_t)(K + pe::kTabPad))) != PE_OK ||
         (s = dalloc(&ev->pw, (size_t)nd * K)) != PE_OK || (s = dalloc(&ev->pfx, (size_t)nd * (K + 1))) != PE_OK ||
         (s = dalloc(&ev->status, 1)) != PE_OK || (s = dalloc(&ev->mws, (size_t)pe::kMwsTotal)) != PE_OK) {
         free_event(ev);
@@ -234,6 +240,8 @@ pe_status_t pe_event_create(const pe_event_desc_t* desc, const void* data_dev, c
     }
     hipStream_t st = as_stream(stream);
     hipError_t e = hipMemsetAsync(ev->status, 0, sizeof(int), st);
+    if (e == hipSuccess) e = hipMemsetAsync(ev->rec32 + K, 0, sizeof(pe::Rec32) * pe::kTabPad, st);
+    if (e == hipSuccess) e = hipMemsetAsync(ev->rec64 + K, 0, sizeof(pe::Rec64) * pe::kTabPad, st);
     if (e == hipSuccess) e = hipMemsetAsync(ev->mws, 0, sizeof(double) * pe::kMwsTotal, st);
     if (e == hipSuccess) e = pe::launch_prep(ev, data_dev, psd_dev, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -274,7 +282,7 @@ pe_status_t pe_event_status(pe_event_t ev, void* stream) {
 pe_status_t pe_event_reserve(pe_event_t ev, int64_t max_draws) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
     if (max_draws < 0 || max_draws > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "max_draws must be in 0..2^30");
-    return ensure_ws(ev, max_draws, chunks_for(max_draws, ev->desc.n_bins));
+    return ensure_ws(ev, max_draws, groups_for(max_draws, ev->desc.n_bins, ev->desc.n_det, ev->npad));
 }
 
 pe_status_t pe_event_destroy(pe_event_t ev) {
@@ -311,7 +319,7 @@ pe_status_t pe_loglike_batch(pe_event_t ev, const double* theta_dev, int64_t n, 
     if (precision != PE_PREC_FP64 && precision != PE_PREC_SPLIT) return fail(PE_ERR_ARG, "bad precision");
     if (n == 0) return PE_OK;
     if (!theta_dev || !loglike_dev) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
-    const int chunks = chunks_for(n, ev->desc.n_bins);
+    const int chunks = groups_for(n, ev->desc.n_bins, ev->desc.n_det, ev->npad);
     pe_status_t s = ensure_ws(ev, n, chunks);
     if (s != PE_OK) return s;
     PE_HIP(pe::launch_loglike(ev, theta_dev, n, precision, chunks, loglike_dev, aux_dev, as_stream(stream)));

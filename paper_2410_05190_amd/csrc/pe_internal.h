@@ -54,6 +54,9 @@ constexpr int kNCoef = 14;
 
 constexpr int kTile = 256;    // draws per workgroup of the hot loop
 constexpr int kBlk = 32;      // bins per FP32 partial before the compensated fold
+constexpr int kBuckets = 4096;  // ISCO-cut buckets of the draw ordering
+constexpr int kTabPad = 8;      // zeroed records past the last bin
+constexpr int kFine = 2048;     // bins per fine chunk of the hot loop (a multiple of kBlk)
 
 // Device status bits (event status word).
 constexpr int kStBadPsd = 1;
@@ -80,9 +83,11 @@ struct pe_event_s {
     // per-draw workspace
     int64_t npad = 0;
     int n_chunks_alloc = 0;
-    int *flags = nullptr;
+    int *kc_all = nullptr;  // [npad] cut per draw, -1 out of support
+    int *hist = nullptr;    // [kBuckets] bucket counts, then offsets
     int *idx = nullptr;
     int *n_active = nullptr;
+    int *queue = nullptr;   // [8] per-XCD item counters of the hot loop
     double *coef = nullptr;  // [kNCoef][npad]
     int *kcut = nullptr;     // [npad]
     double *resp = nullptr;  // [2*n_det][npad] Re/Im R_d
@@ -96,7 +101,7 @@ namespace pe {
 
 // kernel launchers (pe_kernels.hip)
 hipError_t launch_prep(const pe_event_s *ev, const void *data, const void *psd, hipStream_t st);
-hipError_t launch_loglike(const pe_event_s *ev, const double *theta, int64_t n, int precision, int n_chunks,
+hipError_t launch_loglike(const pe_event_s *ev, const double *theta, int64_t n, int precision, int n_groups,
                           double *loglike, double *aux, hipStream_t st);
 hipError_t launch_metric(const pe_event_s *ev, const double *theta0, const double *steps, int flags, double *g,
                          hipStream_t st);
