@@ -1,9 +1,10 @@
 #!/usr/bin/env python3
 """Benchmark of the metric-importance-sampling likelihood path on one MI355X.
 
-One step = the whole hot path for one event of the benchmark workload (default: the
-3-detector BNS shape, 11-D, 519168 bins per detector, complex64 data and FP32 PSD,
-65536 proposal draws, split precision):
+One step = the whole hot path for the events of the benchmark workload (default: one
+event of the 3-detector BNS shape, 11-D, 519168 bins per detector, complex64 data and
+FP32 PSD, 65536 proposal draws, split precision; --config 2: 64 BBH events of uneven
+draw counts whose log-likelihoods share one multi-event batch):
   event-table preparation -> metric at the proposal centre -> Gaussian draws ->
   log-likelihoods -> importance weights and ESS,
 with every input already resident in HBM. Prints one JSON line.
@@ -31,10 +32,11 @@ sys.path.insert(0, ROOT)
 PSI_OPS_PER_DRAW_BIN = 10
 SPLIT_OPS_PER_TERM = 6 + 2 * 2
 FP64_OPS_PER_TERM = 2 + 26 + 4
-# HBM bytes per launch of the split kernel at the benchmark shape, from rocprofv3
+# HBM bytes per launch of the split kernel at the benchmark shape (config 1, automatic
+# groups), from rocprofv3
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors read off a 1 GiB device copy
 # in the same run; None when the kernel has changed since the counters were taken.
-SPLIT_TRAFFIC_BYTES = 826085683  # profiles/loglike_split_config1.md
+SPLIT_TRAFFIC_BYTES = None
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 
 
@@ -96,71 +98,36 @@ def main():
     cfg = synth.CONFIGS[c]
     f_lo, df, K = synth.grid(c)
     nd = cfg["n_det"]
-    N = cfg["n_draws"] or 65536
-    four_d = cfg["params"] == "4d"
-    params = binding.PE_PARAMS_4D if four_d else binding.PE_PARAMS_11D
-    phase = binding.PE_PHASE_MARG if cfg["phase"] == "marg" else binding.PE_PHASE_EXPLICIT
-    f = synth.frequencies(f_lo, df, K)
-    S = np.tile(synth.psd_analytic(f), (nd, 1))
-    geom = synth.detectors(c, nd)
-    inj = synth.injection(c, 0)
-    f32 = cfg["storage"] == "f32"
-    s = synth.F32_STRAIN_SCALE if f32 else 1.0
-    psd_t = torch.from_numpy((S * s * s).astype(np.float32 if f32 else np.float64)).cuda()
-    dl_max = cfg["dl_max"] or 1e4
-    common = dict(f_lo=f_lo, df=df, strain_scale=s, params=params, phase=phase, gmst=0.0,
-                  chi_max=cfg["chi_max"], dl_max=dl_max, det_geom=geom)
-    pdt = binding.PE_F32 if f32 else binding.PE_F64
-    ddt = binding.PE_C64 if f32 else binding.PE_C128
-
-    # injection at the target SNR, made by the library's waveform
-    theta_inj = inj["theta"].copy()
-    h = torch.empty((nd, K, 2), dtype=torch.float64, device="cuda")
-    snr2 = torch.zeros(1, dtype=torch.float64, device="cuda")
-    desc1 = binding.make_desc(nd, K, data_dtype=ddt, psd_dtype=pdt, amp0=1.0, **common)
-    binding.pe_waveform(desc1, torch.from_numpy(theta_inj).cuda(), psd_t, h, snr2)
-    rho1 = math.sqrt(float(snr2.item()))
-    amp0 = 0.0
-    if four_d:
-        amp0 = inj["snr"] / rho1
-    else:
-        theta_inj[8] = rho1 / inj["snr"]
-    desc = binding.make_desc(nd, K, data_dtype=ddt, psd_dtype=pdt, amp0=amp0, **common)
-    binding.pe_waveform(desc, torch.from_numpy(theta_inj).cuda(), psd_t, h, snr2)
-    noise = torch.from_numpy(synth.noise(c, 0, S, df) * s).cuda()
-    data = torch.view_as_complex(h) + noise
-    data = data.to(torch.complex64 if f32 else torch.complex128).contiguous()
-    del noise
-
-    if args.chunks:
-        binding.pe_set_chunks(args.chunks)
-    ev = binding.Event(data, psd_t, amp0=amp0, **common)
-    ev.reserve(N)
-    D = ev.dim
-    theta0 = torch.from_numpy(theta_inj).cuda()
-    g = torch.empty((D, D), dtype=torch.float64, device="cuda")
-    theta = torch.empty((D, N), dtype=torch.float64, device="cuda")
-    lq = torch.empty(N, dtype=torch.float64, device="cuda")
-    lp = torch.empty(N, dtype=torch.float64, device="cuda")
-    ll = torch.empty(N, dtype=torch.float64, device="cuda")
-    w = torch.empty(N, dtype=torch.float64, device="cuda")
-    stats = torch.zeros((max(args.steps, 1), 4), dtype=torch.float64, device="cuda")
+    n_events = cfg.get("batch", 1)
+    Ns = synth.n_draws_batch(c, n_events) if cfg["n_draws"] is None else [cfg["n_draws"]] * n_events
     prec = binding.PE_PREC_SPLIT if args.precision == "split" else binding.PE_PREC_FP64
     kname = "loglike_split" if prec == binding.PE_PREC_SPLIT else "loglike_fp64"
-    seed = synth.draw_seed(c, 0)
-    h_ = ev.handle
+    if args.chunks:
+        binding.pe_set_chunks(args.chunks)
+    evs = [make_event(c, e, N) for e, N in enumerate(Ns)]
+    D = evs[0]["ev"].dim
+    stats = torch.zeros((max(args.steps, 1), n_events, 4), dtype=torch.float64, device="cuda")
 
-    def step(i, st_row):
-        binding.pe_event_update(h_, data, psd_t)
-        binding.pe_metric(h_, theta0, None, 0, g)
-        binding.pe_draw(h_, theta0, g, seed, i, N, theta, lq, lp)
-        binding.pe_loglike_batch(h_, theta, N, prec, ll, None)
-        binding.pe_weights_ess(ll, lp, lq, N, w, st_row)
+    def step(i, st_rows):
+        for x in evs:
+            h_ = x["ev"].handle
+            binding.pe_event_update(h_, x["data"], x["psd"])
+            binding.pe_metric(h_, x["theta0"], None, 0, x["g"])
+            binding.pe_draw(h_, x["theta0"], x["g"], x["seed"], i, x["N"], x["theta"], x["lq"], x["lp"])
+        if n_events == 1:
+            x = evs[0]
+            binding.pe_loglike_batch(x["ev"].handle, x["theta"], x["N"], prec, x["ll"], None)
+        else:
+            binding.pe_loglike_multi([x["ev"] for x in evs], [x["theta"] for x in evs], [x["N"] for x in evs],
+                                     prec, [x["ll"] for x in evs])
+        for e, x in enumerate(evs):
+            binding.pe_weights_ess(x["ll"], x["lp"], x["lq"], x["N"], x["w"], st_rows[e])
 
     for i in range(args.warmup):
         step(1000 + i, stats[0])
     torch.cuda.synchronize()
-    ev.status()
+    for x in evs:
+        x["ev"].status()
 
     binding.pe_profile_enable(True)
     binding.pe_profile_read(kname)
@@ -176,22 +143,27 @@ def main():
     t1 = time.perf_counter()
     binding.pe_profile_enable(False)
     k_ms, k_n = binding.pe_profile_read(kname)
-    ev.status()
+    for x in evs:
+        x["ev"].status()
     lat = sorted(a.elapsed_time(b) for a, b in zip(ev_a, ev_b))
     wall = t1 - t0
     st = stats.cpu().numpy()[: args.steps]
-    n_live = st[:, 3].sum()
-    ess = st[:, 0].sum()
+    n_live = st[:, :, 3].sum()
+    ess = st[:, :, 0].sum()
+    n_draws = sum(Ns) * args.steps
     # terms of the last step (its draws are still in `theta`)
-    th_h = theta.cpu().numpy()
-    kc = host_terms(th_h, cfg, f_lo, df, K, nd)
-    live_last = np.isfinite(ll.cpu().numpy())
-    terms_last = float(nd * kc[live_last].sum())
+    terms_last = 0.0
+    for x in evs:
+        kc = host_terms(x["theta"].cpu().numpy(), cfg, f_lo, df, K, nd)
+        live_last = np.isfinite(x["ll"].cpu().numpy())
+        terms_last += float(nd * kc[live_last].sum())
     db_last = terms_last / nd
     ops_per_term = SPLIT_OPS_PER_TERM if prec == binding.PE_PREC_SPLIT else FP64_OPS_PER_TERM
+    # one hot-loop launch per step: its average duration
     k_avg_s = k_ms / max(k_n, 1) / 1e3
     ops_last = db_last * PSI_OPS_PER_DRAW_BIN + terms_last * ops_per_term
     achieved = ops_last / k_avg_s if k_avg_s > 0 else float("nan")
+    traffic = SPLIT_TRAFFIC_BYTES if (prec == binding.PE_PREC_SPLIT and c == 1 and not args.chunks) else None
 
     out = {
         "metric": "likelihood evals/s and ESS/s per event; p50/p99 event latency under load",
@@ -206,25 +178,82 @@ def main():
         "vs_baseline": None,
         "dtype": "f64 phase + f32" if prec == binding.PE_PREC_SPLIT else "f64",
         "data": "synthetic (seeded coloured Gaussian noise + TaylorF2 injection)",
-        "config": {"workload": cfg["name"], "n_det": nd, "n_bins": K, "draws_per_event": N, "dim": D,
+        "config": {"workload": cfg["name"], "n_det": nd, "n_bins": K, "events_per_step": n_events,
+                   "draws_per_event": Ns[0] if n_events == 1 else Ns, "dim": D,
                    "precision": args.precision, "chunks": args.chunks or "auto"},
-        "draws_per_s": N * args.steps / wall,
-        "in_support_fraction": n_live / (N * args.steps),
+        "draws_per_s": n_draws / wall,
+        "in_support_fraction": n_live / n_draws,
         "ess_per_s": ess / wall,
-        "ess_per_event_mean": ess / args.steps,
+        "ess_per_event_mean": ess / (args.steps * n_events),
         "terms_per_s_hot_kernel": terms_last / k_avg_s if k_avg_s > 0 else None,
         "event_latency_ms": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(0.99 * len(lat)))],
-                             "kind": "isolated events, one at a time"},
+                             "kind": "isolated events, one at a time" if n_events == 1 else
+                             f"one batch of {n_events} events, one batch at a time"},
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK,
-                     "traffic": SPLIT_TRAFFIC_BYTES if prec == binding.PE_PREC_SPLIT else None,
+                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": traffic,
                      "kernel_ms_avg": k_avg_s * 1e3, "kernel_launches": k_n, "ops_per_launch": ops_last},
     }
-    ev.close()
+    first = evs[0]
+    for x in evs:
+        x["ev"].close()
 
-    if not args.no_cpu_baseline and c != 2:
-        out["cpu_baseline"] = cpu_baseline(c, args.cpu_sample, data, psd_t, theta_inj, amp0, common)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_sample, first["data"], first["psd"], first["theta_inj"],
+                                           first["amp0"], first["common"])
     print(json.dumps(out), flush=True)
+
+
+def make_event(c, e, N):
+    """Event e of configuration c with its device buffers for N draws: the injection is made by the
+    library's own waveform (amplitude or distance set to the target SNR), plus seeded noise."""
+    import numpy as np
+    import torch
+
+    from paper_2410_05190_amd import binding, synth
+
+    cfg = synth.CONFIGS[c]
+    f_lo, df, K = synth.grid(c)
+    nd = cfg["n_det"]
+    four_d = cfg["params"] == "4d"
+    params = binding.PE_PARAMS_4D if four_d else binding.PE_PARAMS_11D
+    phase = binding.PE_PHASE_MARG if cfg["phase"] == "marg" else binding.PE_PHASE_EXPLICIT
+    f = synth.frequencies(f_lo, df, K)
+    S = np.tile(synth.psd_analytic(f), (nd, 1))
+    geom = synth.detectors(c, nd)
+    inj = synth.injection(c, e)
+    f32 = cfg["storage"] == "f32"
+    s = synth.F32_STRAIN_SCALE if f32 else 1.0
+    psd_t = torch.from_numpy((S * s * s).astype(np.float32 if f32 else np.float64)).cuda()
+    dl_max = cfg["dl_max"] or 1e4
+    common = dict(f_lo=f_lo, df=df, strain_scale=s, params=params, phase=phase, gmst=0.0,
+                  chi_max=cfg["chi_max"], dl_max=dl_max, det_geom=geom)
+    pdt = binding.PE_F32 if f32 else binding.PE_F64
+    ddt = binding.PE_C64 if f32 else binding.PE_C128
+    theta_inj = inj["theta"].copy()
+    h = torch.empty((nd, K, 2), dtype=torch.float64, device="cuda")
+    snr2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    desc1 = binding.make_desc(nd, K, data_dtype=ddt, psd_dtype=pdt, amp0=1.0, **common)
+    binding.pe_waveform(desc1, torch.from_numpy(theta_inj).cuda(), psd_t, h, snr2)
+    rho1 = math.sqrt(float(snr2.item()))
+    amp0 = 0.0
+    if four_d:
+        amp0 = inj["snr"] / rho1
+    else:
+        theta_inj[8] = rho1 / inj["snr"]
+    desc = binding.make_desc(nd, K, data_dtype=ddt, psd_dtype=pdt, amp0=amp0, **common)
+    binding.pe_waveform(desc, torch.from_numpy(theta_inj).cuda(), psd_t, h, snr2)
+    noise = torch.from_numpy(synth.noise(c, e, S, df) * s).cuda()
+    data = torch.view_as_complex(h) + noise
+    data = data.to(torch.complex64 if f32 else torch.complex128).contiguous()
+    del noise, h
+    ev = binding.Event(data, psd_t, amp0=amp0, **common)
+    ev.reserve(N)
+    D = ev.dim
+    f64 = dict(dtype=torch.float64, device="cuda")
+    return {"ev": ev, "data": data, "psd": psd_t, "theta_inj": theta_inj, "amp0": amp0, "common": common, "N": N,
+            "theta0": torch.from_numpy(theta_inj).cuda(), "g": torch.empty((D, D), **f64),
+            "theta": torch.empty((D, N), **f64), "lq": torch.empty(N, **f64), "lp": torch.empty(N, **f64),
+            "ll": torch.empty(N, **f64), "w": torch.empty(N, **f64), "seed": synth.draw_seed(c, e)}
 
 
 def cpu_baseline(c, n_sample, data, psd_t, theta_inj, amp0, common):

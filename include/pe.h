@@ -175,6 +175,27 @@ pe_status_t pe_loglike_batch(pe_event_t ev, const double *theta_dev, int64_t n, 
                              double *aux_dev, void *stream);
 
 /*
+ * Log-likelihood ratios (Eq. 3) of several events' draws in one batch: event e
+ * evaluates its n[e] draws theta_dev[e] into loglike_dev[e] (and aux_dev[e] if
+ * aux_dev and aux_dev[e] are not NULL), exactly as pe_loglike_batch would
+ * (same layouts, same results bit for bit, independent of the other events in
+ * the batch). Events of equal n_det share one set of launches (the batch
+ * costs a fixed number of launches per detector count, whatever its size),
+ * so many small events fill the GPU together (the per-event analyses of
+ * Sec. 4 are independent). Each event may appear once. Like pe_loglike_batch,
+ * work on an event must not overlap other work on the same event (other
+ * streams, other threads): such calls race.
+ * n_events: 0 .. 65535; events, theta_dev, n, loglike_dev (and aux_dev if not
+ * NULL): host arrays of n_events entries; the pointers in them are device
+ * pointers as in pe_loglike_batch. Entries with n[e] = 0 are skipped.
+ * Errors: PE_ERR_ARG (bad arrays, duplicate event, bad n or precision),
+ * PE_ERR_OOM, PE_ERR_HIP.
+ */
+pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t *events, const double *const *theta_dev,
+                             const int64_t *n, int32_t precision, double *const *loglike_dev, double *const *aux_dev,
+                             void *stream);
+
+/*
  * Importance weights (Eq. 5) and ESS (Eq. 6) of n draws, with
  * ln w_i = loglike_i + logprior_i - logq_i and max-shifted sums in FP64.
  *   w_dev: NULL or [n] normalised weights (sum 1; 0 where ln w = -inf).
@@ -206,9 +227,10 @@ pe_status_t pe_rng_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int32_
 pe_status_t pe_profile_enable(int32_t enable);
 pe_status_t pe_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
-/* Tile shape of the hot-loop kernels: draws per workgroup is fixed (256);
- * n_chunks splits the frequency axis (0 = automatic, else a multiple of 8 up
- * to 256). Global setting, read at launch time. */
+/* Work split of the hot loop: draws per tile are fixed (256); n_chunks caps
+ * the number of groups of frequency chunks one event's tile is spread over
+ * (0 = automatic, at most 64; 1 = one group walks the whole band). Results do
+ * not depend on it. Global setting, read at launch time. */
 pe_status_t pe_set_chunks(int32_t n_chunks);
 
 const char *pe_last_error(void);

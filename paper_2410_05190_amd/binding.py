@@ -29,7 +29,7 @@ PE_F32 = 1
 MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
-           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_weights_ess", "pe_waveform",
+           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_weights_ess", "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_last_error"]
 
 
@@ -70,6 +70,7 @@ def load(path=LIB_PATH):
         "pe_metric": (i32, [vp, dp, dp, i32, dp, vp]),
         "pe_draw": (i32, [vp, dp, dp, u64, u32, i64, dp, dp, dp, vp]),
         "pe_loglike_batch": (i32, [vp, dp, i64, i32, dp, dp, vp]),
+        "pe_loglike_multi": (i32, [i32, vp, vp, vp, i32, vp, vp, vp]),
         "pe_weights_ess": (i32, [dp, dp, dp, i64, dp, dp, vp]),
         "pe_waveform": (i32, [ctypes.POINTER(EventDesc), dp, vp, dp, dp, vp]),
         "pe_rng_uniforms": (i32, [u64, u32, i64, i32, dp, vp]),
@@ -194,6 +195,23 @@ def pe_loglike_batch(ev, theta, n, precision, loglike, aux=None, stream=None):
                                  _ptr(aux, f64, "aux", allow_none=True), _stream(stream)))
 
 
+def pe_loglike_multi(events, thetas, ns, precision, loglikes, auxs=None, stream=None):
+    """One batch over several events: events[e] evaluates ns[e] draws thetas[e] into loglikes[e]."""
+    import torch
+    f64 = torch.float64
+    ne = len(events)
+    if not (len(thetas) == len(ns) == len(loglikes) == ne) or (auxs is not None and len(auxs) != ne):
+        raise ValueError("events, thetas, ns, loglikes (and auxs) must have one entry per event")
+    ev_a = (ctypes.c_void_p * max(ne, 1))(*[e.handle if isinstance(e, Event) else e for e in events])
+    th_a = (ctypes.c_void_p * max(ne, 1))(*[_ptr(t, f64, "theta") for t in thetas])
+    n_a = (ctypes.c_int64 * max(ne, 1))(*[int(n) for n in ns])
+    ll_a = (ctypes.c_void_p * max(ne, 1))(*[_ptr(t, f64, "loglike") for t in loglikes])
+    ax_a = None
+    if auxs is not None:
+        ax_a = (ctypes.c_void_p * max(ne, 1))(*[_ptr(t, f64, "aux", allow_none=True) for t in auxs])
+    _check(load().pe_loglike_multi(ne, ev_a, th_a, n_a, int(precision), ll_a, ax_a, _stream(stream)))
+
+
 def pe_weights_ess(loglike, logprior, logq, n, w, stats, stream=None):
     import torch
     f64 = torch.float64
@@ -296,3 +314,13 @@ def weights_ess(loglike, logprior, logq, want_w=True, stream=None):
     st = torch.empty(4, dtype=torch.float64, device=loglike.device)
     pe_weights_ess(loglike, logprior, logq, n, w, st, stream)
     return w, st
+
+
+def loglike_multi(events, thetas, precision=PE_PREC_SPLIT, aux=False, stream=None):
+    """pe_loglike_multi over Event objects; returns a list of loglike tensors (and aux tensors)."""
+    import torch
+    ns = [t.shape[1] for t in thetas]
+    lls = [torch.empty(n, dtype=torch.float64, device=t.device) for n, t in zip(ns, thetas)]
+    axs = [torch.empty((n, 3), dtype=torch.float64, device=t.device) for n, t in zip(ns, thetas)] if aux else None
+    pe_loglike_multi(events, thetas, ns, precision, lls, axs, stream)
+    return (lls, axs) if aux else lls

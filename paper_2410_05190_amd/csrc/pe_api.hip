@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
@@ -29,7 +30,7 @@ pe_status_t fail(pe_status_t s, const std::string& msg) {
         if (_e != hipSuccess) return fail(PE_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
     } while (0)
 
-int g_chunks = 0;  // 0 = automatic
+int g_chunks = 0;  // cap on the hot loop's groups of chunks per event; 0 = automatic (64)
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -108,24 +109,45 @@ void dfree(T*& p) {
     p = nullptr;
 }
 
+void free_batch(pe::BatchDev& b) {
+    dfree(b.evs);
+    dfree(b.doff);
+    dfree(b.ioff);
+    dfree(b.hdr);
+    b.cap = 0;
+}
+
+pe_status_t ensure_batch(pe::BatchDev& b, int n_events) {
+    if (n_events <= b.cap) return PE_OK;
+    if (b.cap > 0) PE_HIP(hipDeviceSynchronize());  // earlier batches may still read the old buffers
+    free_batch(b);
+    pe_status_t s;
+    if ((s = dalloc(&b.evs, (size_t)n_events)) != PE_OK) return s;
+    if ((s = dalloc(&b.doff, (size_t)n_events + 1)) != PE_OK) return s;
+    if ((s = dalloc(&b.ioff, (size_t)n_events + 1)) != PE_OK) return s;
+    if ((s = dalloc(&b.hdr, 4)) != PE_OK) return s;
+    b.cap = n_events;
+    return PE_OK;
+}
+
 void free_draw_ws(pe_event_s* ev) {
     dfree(ev->kc_all);
     dfree(ev->hist);
+    dfree(ev->plan);
     dfree(ev->idx);
-    dfree(ev->n_active);
-    dfree(ev->queue);
     dfree(ev->coef);
     dfree(ev->kcut);
     dfree(ev->resp);
     dfree(ev->hh);
     dfree(ev->partial);
     ev->npad = 0;
-    ev->n_chunks_alloc = 0;
+    ev->partial_cap = 0;
 }
 
 void free_event(pe_event_s* ev) {
     if (!ev) return;
     free_draw_ws(ev);
+    free_batch(ev->self);
     dfree(ev->rec32);
     dfree(ev->rec64);
     dfree(ev->pw);
@@ -135,45 +157,72 @@ void free_event(pe_event_s* ev) {
     delete ev;
 }
 
-// Groups of fine frequency chunks in the hot loop (= FP64 partials per draw and
-// detector): a multiple of 8, one per fine chunk up to 64, fewer if the partials
-// (n_det x groups x draws x 16 B) would pass 1 GiB. Depends on the event only
-// (given a reserved capacity), so a draw's result does not depend on its batch.
-int auto_groups(int64_t K, int n_det, int64_t npad) {
-    const int64_t n_fine = (K + pe::kFine - 1) / pe::kFine;
-    int c = (int)(((n_fine + 7) / 8) * 8);
-    if (c > 64) c = 64;
-    const int64_t cap = ((int64_t)1 << 30) / (16 * (int64_t)n_det * (npad > 0 ? npad : 1));
-    while (c > 8 && c > cap) c -= 8;
-    return c;
-}
-
-int groups_for(int64_t n, int64_t K, int n_det, int64_t npad_now) {
+// Per-draw workspace for batches of up to n draws. The hot loop keeps up to 64
+// groups of partials per draw and detector; min(64 npad, 2^22) slots per
+// detector bound the groups of large batches (16 at 2^18 draws), where the plan
+// asks for few groups anyway (it aims at ~16k work items per event).
+pe_status_t ensure_ws(pe_event_s* ev, int64_t n) {
     const int64_t npad = ((n + pe::kTile - 1) / pe::kTile) * pe::kTile;
-    return g_chunks > 0 ? g_chunks : auto_groups(K, n_det, npad > npad_now ? npad : npad_now);
-}
-
-pe_status_t ensure_ws(pe_event_s* ev, int64_t n, int chunks) {
-    const int64_t npad = ((n + pe::kTile - 1) / pe::kTile) * pe::kTile;
-    if (npad <= ev->npad && chunks <= ev->n_chunks_alloc) return PE_OK;
+    if (npad <= ev->npad && ev->partial) return PE_OK;
     PE_HIP(hipDeviceSynchronize());
     const int64_t np = npad > ev->npad ? npad : ev->npad;
-    const int ch = chunks > ev->n_chunks_alloc ? chunks : ev->n_chunks_alloc;
     free_draw_ws(ev);
     const int nd = ev->desc.n_det;
+    const int64_t cap = std::min<int64_t>(64 * np, (int64_t)1 << 22);
     pe_status_t s;
     if ((s = dalloc(&ev->kc_all, (size_t)np)) != PE_OK) return s;
     if ((s = dalloc(&ev->hist, (size_t)pe::kBuckets)) != PE_OK) return s;
+    if ((s = dalloc(&ev->plan, 1)) != PE_OK) return s;
     if ((s = dalloc(&ev->idx, (size_t)np)) != PE_OK) return s;
-    if ((s = dalloc(&ev->n_active, 1)) != PE_OK) return s;
-    if ((s = dalloc(&ev->queue, 8)) != PE_OK) return s;
     if ((s = dalloc(&ev->coef, (size_t)pe::kNCoef * np)) != PE_OK) return s;
     if ((s = dalloc(&ev->kcut, (size_t)np)) != PE_OK) return s;
     if ((s = dalloc(&ev->resp, (size_t)2 * nd * np)) != PE_OK) return s;
     if ((s = dalloc(&ev->hh, (size_t)np)) != PE_OK) return s;
-    if ((s = dalloc(&ev->partial, (size_t)ch * nd * np)) != PE_OK) return s;
+    if ((s = dalloc(&ev->partial, (size_t)nd * cap)) != PE_OK) return s;
     ev->npad = np;
-    ev->n_chunks_alloc = ch;
+    ev->partial_cap = cap;
+    return PE_OK;
+}
+
+pe::EvDev make_evdev(const pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux) {
+    pe::EvDev d;
+    std::memset(&d, 0, sizeof(d));
+    d.ec = ev->ec;
+    d.rec32 = ev->rec32;
+    d.rec64 = ev->rec64;
+    d.pfx = ev->pfx;
+    d.kc_all = ev->kc_all;
+    d.hist = ev->hist;
+    d.idx = ev->idx;
+    d.kcut = ev->kcut;
+    d.coef = ev->coef;
+    d.resp = ev->resp;
+    d.hh = ev->hh;
+    d.partial = ev->partial;
+    d.plan = ev->plan;
+    d.npad = ev->npad;
+    int64_t mg = ev->partial_cap / (ev->npad > 0 ? ev->npad : 1);
+    if (mg > 64) mg = 64;
+    if (g_chunks > 0 && mg > g_chunks) mg = g_chunks;
+    d.max_groups = (int)(mg < 1 ? 1 : mg);
+    d.theta = theta;
+    d.n = n;
+    d.loglike = loglike;
+    d.aux = aux;
+    return d;
+}
+
+// Upload the descriptors of ne events (same n_det) and launch the batch.
+pe_status_t run_batch(pe::BatchDev& b, const std::vector<pe::EvDev>& evs, int n_det, int precision,
+                      hipStream_t st) {
+    const int ne = (int)evs.size();
+    pe_status_t s = ensure_batch(b, ne);
+    if (s != PE_OK) return s;
+    std::vector<int64_t> off(ne + 1, 0);
+    for (int e = 0; e < ne; ++e) off[e + 1] = off[e] + evs[e].n;
+    PE_HIP(hipMemcpyAsync(b.evs, evs.data(), sizeof(pe::EvDev) * ne, hipMemcpyHostToDevice, st));
+    PE_HIP(hipMemcpyAsync(b.doff, off.data(), sizeof(int64_t) * (ne + 1), hipMemcpyHostToDevice, st));
+    PE_HIP(pe::launch_batch(b, ne, n_det, off[ne], precision, st));
     return PE_OK;
 }
 
@@ -282,7 +331,7 @@ pe_status_t pe_event_status(pe_event_t ev, void* stream) {
 pe_status_t pe_event_reserve(pe_event_t ev, int64_t max_draws) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
     if (max_draws < 0 || max_draws > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "max_draws must be in 0..2^30");
-    return ensure_ws(ev, max_draws, groups_for(max_draws, ev->desc.n_bins, ev->desc.n_det, ev->npad));
+    return ensure_ws(ev, max_draws);
 }
 
 pe_status_t pe_event_destroy(pe_event_t ev) {
@@ -319,10 +368,41 @@ pe_status_t pe_loglike_batch(pe_event_t ev, const double* theta_dev, int64_t n, 
     if (precision != PE_PREC_FP64 && precision != PE_PREC_SPLIT) return fail(PE_ERR_ARG, "bad precision");
     if (n == 0) return PE_OK;
     if (!theta_dev || !loglike_dev) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
-    const int chunks = groups_for(n, ev->desc.n_bins, ev->desc.n_det, ev->npad);
-    pe_status_t s = ensure_ws(ev, n, chunks);
+    pe_status_t s = ensure_ws(ev, n);
     if (s != PE_OK) return s;
-    PE_HIP(pe::launch_loglike(ev, theta_dev, n, precision, chunks, loglike_dev, aux_dev, as_stream(stream)));
+    std::vector<pe::EvDev> one(1, make_evdev(ev, theta_dev, n, loglike_dev, aux_dev));
+    return run_batch(ev->self, one, ev->desc.n_det, precision, as_stream(stream));
+}
+
+pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t* events, const double* const* theta_dev,
+                             const int64_t* n, int32_t precision, double* const* loglike_dev,
+                             double* const* aux_dev, void* stream) {
+    if (n_events < 0 || n_events > 65535 || (n_events > 0 && (!events || !theta_dev || !n || !loglike_dev)))
+        return fail(PE_ERR_ARG, "bad batch arrays (n_events must be in 0..65535)");
+    if (precision != PE_PREC_FP64 && precision != PE_PREC_SPLIT) return fail(PE_ERR_ARG, "bad precision");
+    // One batch per detector count; its descriptor buffers are those of its
+    // first event, so two calls race only where they share an event.
+    std::vector<pe::EvDev> cls[PE_MAX_DET + 1];
+    pe_event_s* owner[PE_MAX_DET + 1] = {};
+    for (int e = 0; e < n_events; ++e) {
+        pe_event_s* ev = events[e];
+        if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+        for (int f = 0; f < e; ++f)
+            if (events[f] == ev) return fail(PE_ERR_ARG, "an event appears twice in the batch");
+        if (n[e] < 0 || n[e] > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "n must be in 0..2^30");
+        if (n[e] == 0) continue;
+        if (!theta_dev[e] || !loglike_dev[e]) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
+        pe_status_t s = ensure_ws(ev, n[e]);
+        if (s != PE_OK) return s;
+        const int nd = ev->desc.n_det;
+        if (!owner[nd]) owner[nd] = ev;
+        cls[nd].push_back(make_evdev(ev, theta_dev[e], n[e], loglike_dev[e], aux_dev ? aux_dev[e] : nullptr));
+    }
+    for (int nd = 1; nd <= PE_MAX_DET; ++nd) {
+        if (cls[nd].empty()) continue;
+        pe_status_t s = run_batch(owner[nd]->self, cls[nd], nd, precision, as_stream(stream));
+        if (s != PE_OK) return s;
+    }
     return PE_OK;
 }
 
@@ -399,8 +479,7 @@ pe_status_t pe_profile_read(const char* kernel, double* total_ms, int64_t* launc
 }
 
 pe_status_t pe_set_chunks(int32_t n_chunks) {
-    if (n_chunks != 0 && (n_chunks < 8 || n_chunks > 256 || n_chunks % 8 != 0))
-        return fail(PE_ERR_ARG, "n_chunks must be 0 or a multiple of 8 in 8..256");
+    if (n_chunks < 0 || n_chunks > 64) return fail(PE_ERR_ARG, "n_chunks must be in 0..64");
     g_chunks = n_chunks;
     return PE_OK;
 }

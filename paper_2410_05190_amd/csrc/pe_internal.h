@@ -56,7 +56,6 @@ constexpr int kTile = 256;    // draws per workgroup of the hot loop
 constexpr int kBlk = 32;      // bins per FP32 partial before the compensated fold
 constexpr int kBuckets = 4096;  // ISCO-cut buckets of the draw ordering
 constexpr int kTabPad = 8;      // zeroed records past the last bin
-constexpr int kFine = 2048;     // bins per fine chunk of the hot loop (a multiple of kBlk)
 
 // Device status bits (event status word).
 constexpr int kStBadPsd = 1;
@@ -68,6 +67,43 @@ constexpr int kMetricSrcStride = 32;  // doubles: A[8], B5, B6, rre[4], rim[4], 
 constexpr int kMetricMaxDp = PE_MAX_DIM + 1;
 constexpr int kMetricNG = kMetricMaxDp * (kMetricMaxDp + 1) / 2;  // 78 >= 66
 constexpr int kMetricBlocks = 512;
+
+// Device-side plan of one event in a batch (written by the batch kernels).
+struct EvPlan {
+    int n_active;  // live draws
+    int kmax;      // largest cut among them
+    int fine;      // bins per chunk (a multiple of kBlk)
+    int n_fine;    // chunks over [0, kmax)
+    int n_groups;  // groups of chunks = partials per draw and detector
+    int tiles;     // tiles of kTile live draws
+};
+
+// Device-side descriptor of one event in a batch.
+struct EvDev {
+    EvConst ec;
+    const Rec32 *rec32;
+    const Rec64 *rec64;
+    const double *pfx;
+    int *kc_all, *hist, *idx, *kcut;
+    double *coef, *resp, *hh;
+    double2 *partial;
+    EvPlan *plan;
+    int64_t npad;
+    int max_groups;  // partial capacity / npad
+    const double *theta;
+    int64_t n;
+    double *loglike, *aux;
+};
+
+// Device buffers of a batch: descriptors, draw offsets [ne+1], item offsets
+// [ne+1], header {item counter, item total}.
+struct BatchDev {
+    EvDev *evs = nullptr;
+    int64_t *doff = nullptr;
+    int64_t *ioff = nullptr;
+    int *hdr = nullptr;
+    int cap = 0;
+};
 
 }  // namespace pe
 
@@ -82,12 +118,12 @@ struct pe_event_s {
     int *status = nullptr;  // device status word
     // per-draw workspace
     int64_t npad = 0;
-    int n_chunks_alloc = 0;
     int *kc_all = nullptr;  // [npad] cut per draw, -1 out of support
     int *hist = nullptr;    // [kBuckets] bucket counts, then offsets
     int *idx = nullptr;
-    int *n_active = nullptr;
-    int *queue = nullptr;   // [8] per-XCD item counters of the hot loop
+    pe::EvPlan *plan = nullptr;
+    int64_t partial_cap = 0;  // double2 entries per detector
+    pe::BatchDev self;        // one-event batch of pe_loglike_batch
     double *coef = nullptr;  // [kNCoef][npad]
     int *kcut = nullptr;     // [npad]
     double *resp = nullptr;  // [2*n_det][npad] Re/Im R_d
@@ -101,8 +137,7 @@ namespace pe {
 
 // kernel launchers (pe_kernels.hip)
 hipError_t launch_prep(const pe_event_s *ev, const void *data, const void *psd, hipStream_t st);
-hipError_t launch_loglike(const pe_event_s *ev, const double *theta, int64_t n, int precision, int n_groups,
-                          double *loglike, double *aux, hipStream_t st);
+hipError_t launch_batch(const BatchDev &b, int ne, int n_det, int64_t max_draws, int precision, hipStream_t st);
 hipError_t launch_metric(const pe_event_s *ev, const double *theta0, const double *steps, int flags, double *g,
                          hipStream_t st);
 hipError_t launch_draw(const pe_event_s *ev, const double *theta0, const double *g, uint64_t seed, uint32_t stream_id,

@@ -2,14 +2,8 @@
 //
 // Hot path, per event and batch of draws:
 //   k_prep, k_seg_*        event tables and the (h|h) prefix sums (once per event)
-//   k_support, k_scatter   support mask; live draws grouped by ISCO-cut bucket
-//   k_coeffs               per-draw phase polynomial, delays, responses, (h|h)
-//   k_loglike_split/_f64   Z_d = sum_k conj(w_k) exp(-2 pi i Phi_d(f_k)) per draw and
-//                          group of frequency chunks: lanes = draws, the bin
-//                          stream is wave-uniform (scalar loads) and reused by the
-//                          64 draws of a wave and the 256 of a workgroup;
-//                          persistent workgroups take items off per-XCD queues
-//   k_finalize             fixed-order chunk combine, ln L (Eq. 3)
+//   (pe_loglike.hip)       per-draw scalars, the hot loop and ln L for batches of
+//                          draws of one or many events
 //   k_weights              log-sum-exp weights and ESS (Eqs. 5-6)
 // plus the metric (finite-difference Fisher matrix) and the Gaussian draws.
 #include <math.h>
@@ -140,452 +134,6 @@ hipError_t launch_prep(const pe_event_s* ev, const void* data, const void* psd, 
     k_seg_sums<<<dim3(kScanSeg, ec.n_det), 256, 0, st>>>(ev->pw, ec.K, seg, tot);
     k_seg_scan<<<dim3(kScanSeg, ec.n_det), 256, 0, st>>>(ev->pw, ec.K, seg, tot, ev->pfx);
     return hipGetLastError();
-}
-
-// ===========================================================================
-// per-draw scalars
-// ===========================================================================
-__device__ __forceinline__ void gather_theta(const EvConst& ev, const double* __restrict__ theta, int64_t n,
-                                             int64_t i, double th[PE_MAX_DIM]) {
-#pragma unroll
-    for (int j = 0; j < PE_MAX_DIM; ++j) th[j] = (j < ev.dim) ? theta[(int64_t)j * n + i] : 0.0;
-}
-
-// Support mask, ISCO cut and cut bucket of every draw. Buckets run from the
-// longest cut down, so a wave of the hot loop holds draws whose cuts differ by
-// less than one bucket (2^shift bins) and its masked tail is short.
-__global__ __launch_bounds__(256) void k_support(EvConst ev, const double* __restrict__ theta, int64_t n, int shift,
-                                                 int* __restrict__ kc_all, int* __restrict__ hist,
-                                                 double* __restrict__ loglike, double* __restrict__ aux) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double th[PE_MAX_DIM];
-    gather_theta(ev, theta, n, i, th);
-    Src s;
-    if (!source_from_theta(ev, th, s)) {
-        kc_all[i] = -1;
-        loglike[i] = -INFINITY;
-        if (aux) {
-            aux[3 * i] = 0.0;
-            aux[3 * i + 1] = 0.0;
-            aux[3 * i + 2] = 0.0;
-        }
-        return;
-    }
-    const int kc = (int)kcut_of(ev, s.fisco);
-    kc_all[i] = kc;
-    atomicAdd(&hist[(kBuckets - 1) - (kc >> shift)], 1);
-}
-
-__global__ __launch_bounds__(256) void k_zero_int(int* __restrict__ p, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
-// Exclusive scan of the bucket counts in place (one workgroup, 4 buckets per
-// thread); the total is the number of live draws.
-__global__ __launch_bounds__(1024) void k_bucket_scan(int* __restrict__ hist, int* __restrict__ n_active) {
-    __shared__ int sh[1024];
-    const int t = threadIdx.x;
-    const int a0 = hist[4 * t], a1 = hist[4 * t + 1], a2 = hist[4 * t + 2], a3 = hist[4 * t + 3];
-    const int c = a0 + a1 + a2 + a3;
-    sh[t] = c;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = (t >= off) ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += v;
-        __syncthreads();
-    }
-    const int e = sh[t] - c;
-    hist[4 * t] = e;
-    hist[4 * t + 1] = e + a0;
-    hist[4 * t + 2] = e + a0 + a1;
-    hist[4 * t + 3] = e + a0 + a1 + a2;
-    if (t == 1023) *n_active = sh[1023];
-}
-
-// Live draws into their buckets. The order inside a bucket is immaterial: a
-// draw's result does not depend on which draws share its wave.
-__global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ kc_all, int64_t n, int shift,
-                                                 int* __restrict__ offsets, int* __restrict__ idx) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int kc = kc_all[i];
-    if (kc < 0) return;
-    const int pos = atomicAdd(&offsets[(kBuckets - 1) - (kc >> shift)], 1);
-    idx[pos] = (int)i;
-}
-
-__global__ __launch_bounds__(256) void k_coeffs(EvConst ev, const double* __restrict__ theta, int64_t n,
-                                                const int* __restrict__ idx, const int* __restrict__ n_active,
-                                                const int* __restrict__ kc_all, const double* __restrict__ pfx,
-                                                int64_t npad,
-                                                double* __restrict__ coef, int* __restrict__ kcut,
-                                                double* __restrict__ resp, double* __restrict__ hh) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= *n_active) return;
-    const int64_t i = idx[j];
-    double th[PE_MAX_DIM];
-    gather_theta(ev, theta, n, i, th);
-    Src s;
-    source_from_theta(ev, th, s);
-    PhaseCoef pc;
-    phase_coeffs(s, pc);
-#pragma unroll
-    for (int a = 0; a < 8; ++a) coef[(kCoefA + a) * npad + j] = pc.A[a];
-    coef[kCoefB5 * npad + j] = pc.B5;
-    coef[kCoefB6 * npad + j] = pc.B6;
-    const int64_t kc = kc_all[i];
-    kcut[j] = (int)kc;
-    double h = 0.0;
-    for (int d = 0; d < ev.n_det; ++d) {
-        coef[(kCoefTau + d) * npad + j] = s.tc + s.dt[d];
-        resp[(2 * d) * npad + j] = s.rre[d];
-        resp[(2 * d + 1) * npad + j] = s.rim[d];
-        h += (s.rre[d] * s.rre[d] + s.rim[d] * s.rim[d]) * pfx[(int64_t)d * (ev.K + 1) + kc];
-    }
-    hh[j] = h;
-}
-
-// ===========================================================================
-// hot loop
-// ===========================================================================
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-// Kahan step: s + c tracks the sum with c holding the lost low part (negated).
-__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
-
-struct DrawRow {
-    double A[8];
-    double B5, B6;
-};
-
-__device__ __forceinline__ void load_row(const double* __restrict__ coef, int64_t npad, int64_t j, DrawRow& r) {
-#pragma unroll
-    for (int a = 0; a < 8; ++a) r.A[a] = coef[(kCoefA + a) * npad + j];
-    r.B5 = coef[kCoefB5 * npad + j];
-    r.B6 = coef[kCoefB6 * npad + j];
-}
-
-// Split precision: FP64 phase in turns, fract in FP64, then FP32 from the
-// reduced phase on: sin/cos of 2 pi (r + alpha) by the hardware's
-// turn-based v_sin_f32/v_cos_f32, |w|-weighted products summed over kBlk bins
-// in FP32 and folded into Kahan-compensated FP32 accumulators.
-template <int NDET, bool MASK>
-__device__ __forceinline__ void bin_split(const Rec32& r, const DrawRow& row, const double (&tau)[NDET], bool live,
-                                          float (&br)[NDET], float (&bi)[NDET]) {
-    const double psi = psi_turns(row.A, row.B5, row.B6, r.x, r.xm5, r.lnx);
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-        const double ph = fma(r.f, tau[d], psi);
-        const float t = (float)fract64(ph) + r.w[d].y;
-        const float sn = __builtin_amdgcn_sinf(t);
-        const float cs = __builtin_amdgcn_cosf(t);
-        const float m = MASK ? (live ? r.w[d].x : 0.0f) : r.w[d].x;
-        br[d] = fmaf(m, cs, br[d]);
-        bi[d] = fmaf(-m, sn, bi[d]);
-    }
-}
-
-// Work decomposition of the hot loop. The band is cut into fine chunks of
-// kFine bins; fine chunk c belongs to group c mod G (G a multiple of 8), so a
-// group holds chunks spread over the whole band. An item is (tile of 256 live
-// draws, group): one workgroup sums the group's chunks, in increasing order, for
-// its 256 draws into one partial per draw and detector. Items of the groups
-// g = x (mod 8) form queue x; workgroup b serves queue b mod 8 (consecutive
-// workgroups are dispatched to consecutive XCDs, so an XCD reads only its own
-// chunks through its L2) and takes items off an atomic counter until the queue
-// is empty. G and kFine depend on the event only.
-struct HotCtx {
-    int64_t K;
-    int n_fine, n_groups;
-    int64_t npad;
-};
-
-// Per-item prologue shared by both precisions: the lane's draw, its coefficient
-// row and delays, its cut, and the wave's range of cuts.
-template <int NDET>
-__device__ __forceinline__ bool item_setup(const double* __restrict__ coef, const int* __restrict__ kcut, int nact,
-                                           int64_t npad, int tile, int& j, bool& valid, DrawRow& row,
-                                           double (&tau)[NDET], int& kc, int& wmin, int& wmax) {
-    j = tile * kTile + (int)threadIdx.x;
-    valid = j < nact;
-    const int jl = valid ? j : nact - 1;
-    load_row(coef, npad, jl, row);
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) tau[d] = coef[(kCoefTau + d) * npad + jl];
-    kc = kcut[jl];
-    wmin = wave_min(valid ? kc : 0x7fffffff);
-    wmax = wave_max(valid ? kc : 0);
-    return true;
-}
-
-template <int NDET>
-__device__ __forceinline__ void split_item(const Rec32* __restrict__ tab, const HotCtx& hc, int g, int tile,
-                                           const double* __restrict__ coef, const int* __restrict__ kcut, int nact,
-                                           double2* __restrict__ partial) {
-    int j, kc, wmin, wmax;
-    bool valid;
-    DrawRow row;
-    double tau[NDET];
-    item_setup<NDET>(coef, kcut, nact, hc.npad, tile, j, valid, row, tau, kc, wmin, wmax);
-    float sr[NDET], cr[NDET], si[NDET], ci[NDET];
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) sr[d] = cr[d] = si[d] = ci[d] = 0.0f;
-    // Blocks of kBlk bins sit on multiples of kBlk (chunks start on one), and a
-    // lane folds a block only if the block starts below its own cut: every draw
-    // goes through the same operations whichever draws share its wave.
-    for (int c = g; c < hc.n_fine; c += hc.n_groups) {
-        const int k0 = c * kFine;
-        if (k0 >= wmax) break;  // this and the later chunks lie above every cut of the wave
-        const int k1 = (int)min<int64_t>((int64_t)k0 + kFine, hc.K);
-        // [k0, kA): whole blocks below every lane's cut; [kA, kB): masked blocks
-        const int kA = k0 + (max(0, min(wmin, k1) - k0) / kBlk) * kBlk;
-        const int kB = max(kA, min(k1, wmax));
-        int kb = k0;
-        for (; kb < kA; kb += kBlk) {
-            float br[NDET], bi[NDET];
-#pragma unroll
-            for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
-#pragma unroll 4
-            for (int q = 0; q < kBlk; ++q) bin_split<NDET, false>(tab[kb + q], row, tau, true, br, bi);
-#pragma unroll
-            for (int d = 0; d < NDET; ++d) {
-                kahan_add(sr[d], cr[d], br[d]);
-                kahan_add(si[d], ci[d], bi[d]);
-            }
-        }
-        for (; kb < kB; kb += kBlk) {
-            const int ke = min(kb + kBlk, kB);
-            float br[NDET], bi[NDET];
-#pragma unroll
-            for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
-            for (int k = kb; k < ke; ++k) bin_split<NDET, true>(tab[k], row, tau, k < kc, br, bi);
-            if (kb < kc) {
-#pragma unroll
-                for (int d = 0; d < NDET; ++d) {
-                    kahan_add(sr[d], cr[d], br[d]);
-                    kahan_add(si[d], ci[d], bi[d]);
-                }
-            }
-        }
-    }
-    if (valid) {
-#pragma unroll
-        for (int d = 0; d < NDET; ++d)
-            partial[((int64_t)g * NDET + d) * hc.npad + j] =
-                make_double2((double)sr[d] - (double)cr[d], (double)si[d] - (double)ci[d]);
-    }
-}
-
-// Takes the next item of this workgroup's queue; false when the queue is empty.
-__device__ __forceinline__ bool next_item(int* __restrict__ queue, int x, int items, int gx, int& tile, int& g) {
-    __shared__ int s_item;
-    __syncthreads();  // every wave is done with the previous s_item
-    if (threadIdx.x == 0) s_item = atomicAdd(&queue[x], 1);
-    __syncthreads();
-    const int it = s_item;
-    if (it >= items) return false;
-    tile = it / gx;
-    g = x + 8 * (it % gx);
-    return true;
-}
-
-template <int NDET>
-__global__ __launch_bounds__(256) void k_loglike_split(const Rec32* __restrict__ tab, HotCtx hc,
-                                                       const double* __restrict__ coef, const int* __restrict__ kcut,
-                                                       const int* __restrict__ n_active, double2* __restrict__ partial,
-                                                       int* __restrict__ queue) {
-    const int x = blockIdx.x & 7;
-    const int nact = *n_active;
-    const int gx = hc.n_groups / 8;
-    const int items = ((nact + kTile - 1) / kTile) * gx;
-    int tile, g;
-    while (next_item(queue, x, items, gx, tile, g)) split_item<NDET>(tab, hc, g, tile, coef, kcut, nact, partial);
-}
-
-// Plain FP64: the same loop with complex128 weights and an FP64 sincos.
-template <int NDET, bool MASK>
-__device__ __forceinline__ void bin_f64(const Rec64& r, const DrawRow& row, const double (&tau)[NDET], bool live,
-                                        double (&zr)[NDET], double (&zi)[NDET]) {
-    const double psi = psi_turns(row.A, row.B5, row.B6, r.x, r.xm5, r.lnx);
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-        const double ph = fma(r.f, tau[d], psi);
-        double sn, cs;
-        sincos_turns(fract64(ph), sn, cs);
-        const double wr = MASK ? (live ? r.w[d].x : 0.0) : r.w[d].x;
-        const double wi = MASK ? (live ? r.w[d].y : 0.0) : r.w[d].y;
-        // conj(w) (cos - i sin)
-        zr[d] = fma(wr, cs, zr[d]);
-        zr[d] = fma(-wi, sn, zr[d]);
-        zi[d] = fma(-wr, sn, zi[d]);
-        zi[d] = fma(-wi, cs, zi[d]);
-    }
-}
-
-template <int NDET>
-__device__ __forceinline__ void f64_item(const Rec64* __restrict__ tab, const HotCtx& hc, int g, int tile,
-                                         const double* __restrict__ coef, const int* __restrict__ kcut, int nact,
-                                         double2* __restrict__ partial) {
-    int j, kc, wmin, wmax;
-    bool valid;
-    DrawRow row;
-    double tau[NDET];
-    item_setup<NDET>(coef, kcut, nact, hc.npad, tile, j, valid, row, tau, kc, wmin, wmax);
-    double zr[NDET], zi[NDET];
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) zr[d] = zi[d] = 0.0;
-    for (int c = g; c < hc.n_fine; c += hc.n_groups) {
-        const int k0 = c * kFine;
-        if (k0 >= wmax) break;
-        const int k1 = (int)min<int64_t>((int64_t)k0 + kFine, hc.K);
-        const int kA = max(k0, min(k1, wmin));
-        const int kB = max(kA, min(k1, wmax));
-        int k = k0;
-#pragma unroll 2
-        for (; k < kA; ++k) bin_f64<NDET, false>(tab[k], row, tau, true, zr, zi);
-        for (; k < kB; ++k) bin_f64<NDET, true>(tab[k], row, tau, k < kc, zr, zi);
-    }
-    if (valid) {
-#pragma unroll
-        for (int d = 0; d < NDET; ++d) partial[((int64_t)g * NDET + d) * hc.npad + j] = make_double2(zr[d], zi[d]);
-    }
-}
-
-template <int NDET>
-__global__ __launch_bounds__(256) void k_loglike_f64(const Rec64* __restrict__ tab, HotCtx hc,
-                                                     const double* __restrict__ coef, const int* __restrict__ kcut,
-                                                     const int* __restrict__ n_active, double2* __restrict__ partial,
-                                                     int* __restrict__ queue) {
-    const int x = blockIdx.x & 7;
-    const int nact = *n_active;
-    const int gx = hc.n_groups / 8;
-    const int items = ((nact + kTile - 1) / kTile) * gx;
-    int tile, g;
-    while (next_item(queue, x, items, gx, tile, g)) f64_item<NDET>(tab, hc, g, tile, coef, kcut, nact, partial);
-}
-
-// Fixed-order combine of the group partials (8 interleaved accumulators, then a
-// pairwise tree), then ln L of Eq. 3.
-template <int NDET>
-__global__ __launch_bounds__(256) void k_finalize(EvConst ev, const double2* __restrict__ partial, int n_chunks,
-                                                  int64_t npad, const int* __restrict__ idx,
-                                                  const int* __restrict__ n_active, const double* __restrict__ resp,
-                                                  const double* __restrict__ hh, double* __restrict__ loglike,
-                                                  double* __restrict__ aux) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= *n_active) return;
-    double zr = 0.0, zi = 0.0;
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-        double ar[8], ai[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0.0;
-        for (int c = 0; c < n_chunks; ++c) {
-            const double2 v = partial[((int64_t)c * NDET + d) * npad + j];
-            ar[c & 7] += v.x;
-            ai[c & 7] += v.y;
-        }
-#pragma unroll
-        for (int w = 4; w > 0; w >>= 1)
-#pragma unroll
-            for (int q = 0; q < w; ++q) {
-                ar[q] += ar[q + w];
-                ai[q] += ai[q + w];
-            }
-        const double rr = resp[(2 * d) * npad + j], ri = resp[(2 * d + 1) * npad + j];
-        zr += rr * ar[0] - ri * ai[0];
-        zi += rr * ai[0] + ri * ar[0];
-    }
-    const double h = hh[j];
-    const double ll = (ev.phase == PE_PHASE_EXPLICIT) ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
-    const int64_t i = idx[j];
-    loglike[i] = ll;
-    if (aux) {
-        aux[3 * i] = zr;
-        aux[3 * i + 1] = zi;
-        aux[3 * i + 2] = h;
-    }
-}
-
-// Workgroups that fit on the GPU at once for a hot-loop kernel (a multiple of 8).
-template <typename K>
-static unsigned resident_grid(K kernel) {
-    int per_cu = 0, dev = 0, n_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 2048;
-    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 2048;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTile, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    const unsigned g = (unsigned)(per_cu * n_cu);
-    return ((g + 7) / 8) * 8;
-}
-
-template <int NDET>
-static hipError_t launch_loglike_nd(const pe_event_s* ev, int64_t n, int precision, int n_groups, double* loglike,
-                                    double* aux, hipStream_t st) {
-    const EvConst& ec = ev->ec;
-    HotCtx hc;
-    hc.K = ec.K;
-    hc.n_fine = (int)((ec.K + kFine - 1) / kFine);
-    hc.n_groups = n_groups;
-    hc.npad = ev->npad;
-    k_zero_int<<<1, 256, 0, st>>>(ev->queue, 8);
-    if (precision == PE_PREC_SPLIT) {
-        static const unsigned grid = resident_grid(k_loglike_split<NDET>);
-        prof_begin("loglike_split", st);
-        k_loglike_split<NDET><<<grid, kTile, 0, st>>>(ev->rec32, hc, ev->coef, ev->kcut, ev->n_active, ev->partial,
-                                                      ev->queue);
-        prof_end("loglike_split", st);
-    } else {
-        static const unsigned grid = resident_grid(k_loglike_f64<NDET>);
-        prof_begin("loglike_fp64", st);
-        k_loglike_f64<NDET><<<grid, kTile, 0, st>>>(ev->rec64, hc, ev->coef, ev->kcut, ev->n_active, ev->partial,
-                                                    ev->queue);
-        prof_end("loglike_fp64", st);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_finalize<NDET><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(ec, ev->partial, n_groups, ev->npad, ev->idx,
-                                                                  ev->n_active, ev->resp, ev->hh, loglike, aux);
-    return hipGetLastError();
-}
-
-hipError_t launch_loglike(const pe_event_s* ev, const double* theta, int64_t n, int precision, int n_groups,
-                          double* loglike, double* aux, hipStream_t st) {
-    const EvConst& ec = ev->ec;
-    const unsigned nb = (unsigned)((n + 255) / 256);
-    int shift = 0;
-    while ((ec.K >> shift) >= kBuckets) ++shift;
-    k_zero_int<<<kBuckets / 256, 256, 0, st>>>(ev->hist, kBuckets);
-    k_support<<<nb, 256, 0, st>>>(ec, theta, n, shift, ev->kc_all, ev->hist, loglike, aux);
-    k_bucket_scan<<<1, 1024, 0, st>>>(ev->hist, ev->n_active);
-    k_scatter<<<nb, 256, 0, st>>>(ev->kc_all, n, shift, ev->hist, ev->idx);
-    k_coeffs<<<nb, 256, 0, st>>>(ec, theta, n, ev->idx, ev->n_active, ev->kc_all, ev->pfx, ev->npad, ev->coef,
-                                 ev->kcut, ev->resp, ev->hh);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    switch (ec.n_det) {
-        case 1: return launch_loglike_nd<1>(ev, n, precision, n_groups, loglike, aux, st);
-        case 2: return launch_loglike_nd<2>(ev, n, precision, n_groups, loglike, aux, st);
-        case 3: return launch_loglike_nd<3>(ev, n, precision, n_groups, loglike, aux, st);
-        default: return launch_loglike_nd<4>(ev, n, precision, n_groups, loglike, aux, st);
-    }
 }
 
 // ===========================================================================

@@ -1,0 +1,544 @@
+// pe_loglike.hip -- log-likelihoods of batches of draws of one or many events
+// (Eq. 3), eight launches per batch whatever the number of events.
+//
+//   k_b_reset     clear the events' cut histograms, plans and the item queue
+//   k_b_support   support mask, ISCO cut and cut bucket of every draw
+//   k_b_plan      per event: bucket offsets, live count, frequency decomposition
+//   k_b_items     per event: offset of its work items in the batch's queue
+//   k_b_scatter   live draws into their cut buckets
+//   k_b_coeffs    per live draw: phase polynomial, delays, responses, (h|h)
+//   k_b_split / k_b_f64   hot loop: persistent workgroups take (event, tile of
+//                 256 draws, group of frequency chunks) items off one queue;
+//                 lanes = draws; the bin record is wave-uniform (scalar loads)
+//                 and reused by the 64 draws of a wave and the 256 of a workgroup
+//   k_b_finalize  fixed-order combine of the group partials, ln L
+//
+// An event's decomposition (chunk length, groups) is planned on the device from
+// its own live draws only (their largest cut and their number), so its results
+// do not depend on the other events of the batch.
+#include <math.h>
+
+#include "pe_device.h"
+
+namespace pe {
+
+__device__ __forceinline__ int find_slot(const int64_t* __restrict__ off, int n, int64_t x) {
+    int lo = 0, hi = n;  // off[lo] <= x < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Loads from read-only device memory. The hot loop reaches its tables through
+// pointers held in device memory, so the compiler cannot prove on its own that
+// the kernel's stores leave them unchanged; the constant address space says so
+// and lets wave-uniform loads go through the scalar unit (s_load). Records are
+// copied as 32-bit words, which the compiler merges into wide scalar loads.
+typedef const __attribute__((address_space(4))) uint32_t* cwords;
+typedef const __attribute__((address_space(1))) double* gdoubles;
+typedef const __attribute__((address_space(1))) int* gints;
+
+template <typename T>
+__device__ __forceinline__ T load_const(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "record size must be a multiple of 4 bytes");
+    const cwords w = (cwords)p;
+    uint32_t buf[sizeof(T) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) buf[i] = w[i];
+    T r;
+    __builtin_memcpy(&r, buf, sizeof(T));
+    return r;
+}
+
+__device__ __forceinline__ int bucket_shift(int64_t K) {
+    int s = 0;
+    while ((K >> s) >= kBuckets) ++s;
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_b_reset(const EvDev* __restrict__ evs, int* __restrict__ hdr) {
+    const EvDev& E = evs[blockIdx.y];
+    E.hist[blockIdx.x * 256 + threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        EvPlan z = {};
+        *E.plan = z;
+        if (blockIdx.y == 0) hdr[0] = 0;  // item counter
+    }
+}
+
+__device__ __forceinline__ void gather_theta(const EvDev& E, int64_t i, double th[PE_MAX_DIM]) {
+#pragma unroll
+    for (int j = 0; j < PE_MAX_DIM; ++j) th[j] = (j < E.ec.dim) ? E.theta[(int64_t)j * E.n + i] : 0.0;
+}
+
+// Support mask, ISCO cut and cut bucket. Buckets run from the longest cut down,
+// so a wave of the hot loop holds draws whose cuts differ by less than one bucket.
+__global__ __launch_bounds__(256) void k_b_support(const EvDev* __restrict__ evs, const int64_t* __restrict__ doff,
+                                                   int ne) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= doff[ne]) return;
+    const int e = find_slot(doff, ne, gid);
+    const EvDev& E = evs[e];
+    const int64_t i = gid - doff[e];
+    double th[PE_MAX_DIM];
+    gather_theta(E, i, th);
+    Src s;
+    if (!source_from_theta(E.ec, th, s)) {
+        E.kc_all[i] = -1;
+        E.loglike[i] = -INFINITY;
+        if (E.aux) {
+            E.aux[3 * i] = 0.0;
+            E.aux[3 * i + 1] = 0.0;
+            E.aux[3 * i + 2] = 0.0;
+        }
+        return;
+    }
+    const int kc = (int)kcut_of(E.ec, s.fisco);
+    E.kc_all[i] = kc;
+    atomicAdd(&E.hist[(kBuckets - 1) - (kc >> bucket_shift(E.ec.K))], 1);
+    atomicMax(&E.plan->kmax, kc);
+}
+
+// One workgroup per event: exclusive scan of the bucket counts in place (4 per
+// thread), the live count, and the frequency decomposition of the hot loop:
+// ~16k work items for the event alone (groups a power of two up to 64), at least
+// 1024 bins per group, 8 chunks per group spread over [0, largest cut), chunk
+// length a multiple of kBlk.
+__global__ __launch_bounds__(1024) void k_b_plan(const EvDev* __restrict__ evs) {
+    __shared__ int sh[1024];
+    const EvDev& E = evs[blockIdx.x];
+    int* hist = E.hist;
+    const int t = threadIdx.x;
+    const int a0 = hist[4 * t], a1 = hist[4 * t + 1], a2 = hist[4 * t + 2], a3 = hist[4 * t + 3];
+    const int c = a0 + a1 + a2 + a3;
+    sh[t] = c;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    const int ex = sh[t] - c;
+    hist[4 * t] = ex;
+    hist[4 * t + 1] = ex + a0;
+    hist[4 * t + 2] = ex + a0 + a1;
+    hist[4 * t + 3] = ex + a0 + a1 + a2;
+    if (t != 1023) return;
+    EvPlan p = *E.plan;
+    p.n_active = sh[1023];
+    p.tiles = (p.n_active + kTile - 1) / kTile;
+    if (p.n_active == 0 || p.kmax == 0) {
+        p.n_groups = 0;
+        p.fine = kBlk;
+        p.n_fine = 0;
+    } else {
+        const int want = (16384 + p.tiles - 1) / p.tiles;
+        int G = 1;
+        while (G < want && G < 64) G <<= 1;
+        const int by_bins = max(1, p.kmax / 1024);
+        G = min(G, min(by_bins, E.max_groups));
+        const int target = 8 * G;
+        int fine = ((p.kmax + target - 1) / target + kBlk - 1) / kBlk * kBlk;
+        fine = max(fine, kBlk);
+        p.n_groups = G;
+        p.fine = fine;
+        p.n_fine = (p.kmax + fine - 1) / fine;
+    }
+    *E.plan = p;
+}
+
+// Offsets of every event's items in the batch queue (items = tiles x groups).
+__global__ void k_b_items(const EvDev* __restrict__ evs, int ne, int64_t* __restrict__ ioff,
+                          int* __restrict__ hdr) {
+    if (threadIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int e = 0; e < ne; ++e) {
+        ioff[e] = acc;
+        const EvPlan p = *evs[e].plan;
+        acc += (int64_t)p.tiles * p.n_groups;
+    }
+    ioff[ne] = acc;
+    hdr[1] = (int)acc;
+}
+
+// Live draws into their buckets; the order inside a bucket is immaterial.
+__global__ __launch_bounds__(256) void k_b_scatter(const EvDev* __restrict__ evs, const int64_t* __restrict__ doff,
+                                                   int ne) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= doff[ne]) return;
+    const int e = find_slot(doff, ne, gid);
+    const EvDev& E = evs[e];
+    const int64_t i = gid - doff[e];
+    const int kc = E.kc_all[i];
+    if (kc < 0) return;
+    const int pos = atomicAdd(&E.hist[(kBuckets - 1) - (kc >> bucket_shift(E.ec.K))], 1);
+    E.idx[pos] = (int)i;
+}
+
+__global__ __launch_bounds__(256) void k_b_coeffs(const EvDev* __restrict__ evs, const int64_t* __restrict__ doff,
+                                                  int ne) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= doff[ne]) return;
+    const int e = find_slot(doff, ne, gid);
+    const EvDev& E = evs[e];
+    const int64_t j = gid - doff[e];
+    if (j >= E.plan->n_active) return;
+    const int64_t i = E.idx[j];
+    const int64_t np = E.npad;
+    double th[PE_MAX_DIM];
+    gather_theta(E, i, th);
+    Src s;
+    source_from_theta(E.ec, th, s);
+    PhaseCoef pc;
+    phase_coeffs(s, pc);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) E.coef[(kCoefA + a) * np + j] = pc.A[a];
+    E.coef[kCoefB5 * np + j] = pc.B5;
+    E.coef[kCoefB6 * np + j] = pc.B6;
+    const int64_t kc = E.kc_all[i];
+    E.kcut[j] = (int)kc;
+    double h = 0.0;
+    for (int d = 0; d < E.ec.n_det; ++d) {
+        E.coef[(kCoefTau + d) * np + j] = s.tc + s.dt[d];
+        E.resp[(2 * d) * np + j] = s.rre[d];
+        E.resp[(2 * d + 1) * np + j] = s.rim[d];
+        h += (s.rre[d] * s.rre[d] + s.rim[d] * s.rim[d]) * E.pfx[(int64_t)d * (E.ec.K + 1) + kc];
+    }
+    E.hh[j] = h;
+}
+
+// ---------------------------------------------------------------------------
+// hot loop
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Kahan step: s - c tracks the sum, c holds the lost low part.
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+struct DrawRow {
+    double A[8];
+    double B5, B6;
+};
+
+// Split precision: FP64 phase in turns and its fract in FP64; from the reduced
+// phase on FP32: sin/cos of 2 pi (r + alpha) by the hardware's turn-based
+// v_sin_f32/v_cos_f32, |w|-weighted products summed over kBlk bins in FP32.
+template <int NDET, bool MASK>
+__device__ __forceinline__ void bin_split(const Rec32& r, const DrawRow& row, const double (&tau)[NDET], bool live,
+                                          float (&br)[NDET], float (&bi)[NDET]) {
+    const double psi = psi_turns(row.A, row.B5, row.B6, r.x, r.xm5, r.lnx);
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+        const double ph = fma(r.f, tau[d], psi);
+        const float t = (float)fract64(ph) + r.w[d].y;
+        const float sn = __builtin_amdgcn_sinf(t);
+        const float cs = __builtin_amdgcn_cosf(t);
+        const float m = MASK ? (live ? r.w[d].x : 0.0f) : r.w[d].x;
+        br[d] = fmaf(m, cs, br[d]);
+        bi[d] = fmaf(-m, sn, bi[d]);
+    }
+}
+
+// Plain FP64: complex128 weights and the FP64 sincos of the reduced phase.
+template <int NDET, bool MASK>
+__device__ __forceinline__ void bin_f64(const Rec64& r, const DrawRow& row, const double (&tau)[NDET], bool live,
+                                        double (&zr)[NDET], double (&zi)[NDET]) {
+    const double psi = psi_turns(row.A, row.B5, row.B6, r.x, r.xm5, r.lnx);
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+        const double ph = fma(r.f, tau[d], psi);
+        double sn, cs;
+        sincos_turns(fract64(ph), sn, cs);
+        const double wr = MASK ? (live ? r.w[d].x : 0.0) : r.w[d].x;
+        const double wi = MASK ? (live ? r.w[d].y : 0.0) : r.w[d].y;
+        // conj(w) (cos - i sin)
+        zr[d] = fma(wr, cs, zr[d]);
+        zr[d] = fma(-wi, sn, zr[d]);
+        zi[d] = fma(-wr, sn, zi[d]);
+        zi[d] = fma(-wi, cs, zi[d]);
+    }
+}
+
+struct Item {
+    int e, tile, g;
+};
+
+// Next item of the batch queue; false when the queue is empty (every workgroup
+// reaches that exit).
+__device__ __forceinline__ bool next_item(int* __restrict__ hdr, const int64_t* __restrict__ ioff, int ne,
+                                          const EvDev* __restrict__ evs, Item& it) {
+    __shared__ int s_item;
+    __syncthreads();  // every wave is done with the previous s_item
+    if (threadIdx.x == 0) s_item = atomicAdd(&hdr[0], 1);
+    __syncthreads();
+    const int x = __builtin_amdgcn_readfirstlane(s_item);
+    if (x >= hdr[1]) return false;
+    it.e = find_slot(ioff, ne, x);
+    const int loc = x - (int)ioff[it.e];
+    const int G = load_const(evs[it.e].plan).n_groups;
+    it.tile = loc / G;
+    it.g = loc - it.tile * G;
+    return true;
+}
+
+// The lane's draw, its row and delays, its cut, and the wave's range of cuts.
+template <int NDET>
+__device__ __forceinline__ void item_setup(const EvDev& E, int nact, int tile, int& j, bool& valid, DrawRow& row,
+                                           double (&tau)[NDET], int& kc, int& wmin, int& wmax) {
+    j = tile * kTile + (int)threadIdx.x;
+    valid = j < nact;
+    const int64_t jl = valid ? j : nact - 1;
+    const int64_t np = E.npad;
+    const gdoubles coef = (gdoubles)E.coef;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) row.A[a] = coef[(kCoefA + a) * np + jl];
+    row.B5 = coef[kCoefB5 * np + jl];
+    row.B6 = coef[kCoefB6 * np + jl];
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) tau[d] = coef[(kCoefTau + d) * np + jl];
+    kc = ((gints)E.kcut)[jl];
+    wmin = wave_min(valid ? kc : 0x7fffffff);
+    wmax = wave_max(valid ? kc : 0);
+}
+
+template <int NDET>
+__device__ __forceinline__ void split_item(const EvDev& E, const EvPlan& p, int tile, int g) {
+    int j, kc, wmin, wmax;
+    bool valid;
+    DrawRow row;
+    double tau[NDET];
+    item_setup<NDET>(E, p.n_active, tile, j, valid, row, tau, kc, wmin, wmax);
+    const Rec32* tab = E.rec32;
+    const int K = (int)E.ec.K;
+    float sr[NDET], cr[NDET], si[NDET], ci[NDET];
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) sr[d] = cr[d] = si[d] = ci[d] = 0.0f;
+    // Blocks of kBlk bins sit on multiples of kBlk (chunks start on one), and a
+    // lane folds a block only if the block starts below its own cut: a draw's
+    // operations do not depend on the draws sharing its wave.
+    for (int c = g; c < p.n_fine; c += p.n_groups) {
+        const int k0 = c * p.fine;
+        if (k0 >= wmax) break;  // this and the later chunks lie above every cut of the wave
+        const int k1 = min(k0 + p.fine, K);
+        // [k0, kA): whole blocks below every lane's cut; [kA, kB): masked blocks
+        const int kA = k0 + (max(0, min(wmin, k1) - k0) / kBlk) * kBlk;
+        const int kB = max(kA, min(k1, wmax));
+        int kb = k0;
+        for (; kb < kA; kb += kBlk) {
+            float br[NDET], bi[NDET];
+#pragma unroll
+            for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
+#pragma unroll 4
+            for (int q = 0; q < kBlk; ++q) {
+                const Rec32 r = load_const(tab + kb + q);
+                bin_split<NDET, false>(r, row, tau, true, br, bi);
+            }
+#pragma unroll
+            for (int d = 0; d < NDET; ++d) {
+                kahan_add(sr[d], cr[d], br[d]);
+                kahan_add(si[d], ci[d], bi[d]);
+            }
+        }
+        for (; kb < kB; kb += kBlk) {
+            const int ke = min(kb + kBlk, kB);
+            float br[NDET], bi[NDET];
+#pragma unroll
+            for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
+            for (int k = kb; k < ke; ++k) {
+                const Rec32 r = load_const(tab + k);
+                bin_split<NDET, true>(r, row, tau, k < kc, br, bi);
+            }
+            if (kb < kc) {
+#pragma unroll
+                for (int d = 0; d < NDET; ++d) {
+                    kahan_add(sr[d], cr[d], br[d]);
+                    kahan_add(si[d], ci[d], bi[d]);
+                }
+            }
+        }
+    }
+    if (valid) {
+#pragma unroll
+        for (int d = 0; d < NDET; ++d)
+            E.partial[((int64_t)g * NDET + d) * E.npad + j] =
+                make_double2((double)sr[d] - (double)cr[d], (double)si[d] - (double)ci[d]);
+    }
+}
+
+template <int NDET>
+__device__ __forceinline__ void f64_item(const EvDev& E, const EvPlan& p, int tile, int g) {
+    int j, kc, wmin, wmax;
+    bool valid;
+    DrawRow row;
+    double tau[NDET];
+    item_setup<NDET>(E, p.n_active, tile, j, valid, row, tau, kc, wmin, wmax);
+    const Rec64* tab = E.rec64;
+    const int K = (int)E.ec.K;
+    double zr[NDET], zi[NDET];
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) zr[d] = zi[d] = 0.0;
+    for (int c = g; c < p.n_fine; c += p.n_groups) {
+        const int k0 = c * p.fine;
+        if (k0 >= wmax) break;
+        const int k1 = min(k0 + p.fine, K);
+        const int kA = max(k0, min(k1, wmin));
+        const int kB = max(kA, min(k1, wmax));
+        int k = k0;
+#pragma unroll 2
+        for (; k < kA; ++k) {
+            const Rec64 r = load_const(tab + k);
+            bin_f64<NDET, false>(r, row, tau, true, zr, zi);
+        }
+        for (; k < kB; ++k) {
+            const Rec64 r = load_const(tab + k);
+            bin_f64<NDET, true>(r, row, tau, k < kc, zr, zi);
+        }
+    }
+    if (valid) {
+#pragma unroll
+        for (int d = 0; d < NDET; ++d) E.partial[((int64_t)g * NDET + d) * E.npad + j] = make_double2(zr[d], zi[d]);
+    }
+}
+
+template <int NDET>
+__global__ __launch_bounds__(256) void k_b_split(const EvDev* __restrict__ evs, const int64_t* __restrict__ ioff,
+                                                 int ne, int* __restrict__ hdr) {
+    Item it;
+    while (next_item(hdr, ioff, ne, evs, it)) {
+        const EvDev& E = evs[it.e];
+        const EvPlan p = load_const(E.plan);
+        split_item<NDET>(E, p, it.tile, it.g);
+    }
+}
+
+template <int NDET>
+__global__ __launch_bounds__(256) void k_b_f64(const EvDev* __restrict__ evs, const int64_t* __restrict__ ioff,
+                                               int ne, int* __restrict__ hdr) {
+    Item it;
+    while (next_item(hdr, ioff, ne, evs, it)) {
+        const EvDev& E = evs[it.e];
+        const EvPlan p = load_const(E.plan);
+        f64_item<NDET>(E, p, it.tile, it.g);
+    }
+}
+
+// Fixed-order combine of the group partials (8 interleaved accumulators, then a
+// pairwise tree), then ln L of Eq. 3.
+template <int NDET>
+__global__ __launch_bounds__(256) void k_b_finalize(const EvDev* __restrict__ evs, const int64_t* __restrict__ doff,
+                                                    int ne) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= doff[ne]) return;
+    const int e = find_slot(doff, ne, gid);
+    const EvDev& E = evs[e];
+    const int64_t j = gid - doff[e];
+    const EvPlan p = *E.plan;
+    if (j >= p.n_active) return;
+    const int64_t np = E.npad;
+    double zr = 0.0, zi = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+        double ar[8], ai[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0.0;
+        for (int c = 0; c < p.n_groups; ++c) {
+            const double2 v = E.partial[((int64_t)c * NDET + d) * np + j];
+            ar[c & 7] += v.x;
+            ai[c & 7] += v.y;
+        }
+#pragma unroll
+        for (int w = 4; w > 0; w >>= 1)
+#pragma unroll
+            for (int q = 0; q < w; ++q) {
+                ar[q] += ar[q + w];
+                ai[q] += ai[q + w];
+            }
+        const double rr = E.resp[(2 * d) * np + j], ri = E.resp[(2 * d + 1) * np + j];
+        zr += rr * ar[0] - ri * ai[0];
+        zi += rr * ai[0] + ri * ar[0];
+    }
+    const double h = E.hh[j];
+    const double ll = (E.ec.phase == PE_PHASE_EXPLICIT) ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
+    const int64_t i = E.idx[j];
+    E.loglike[i] = ll;
+    if (E.aux) {
+        E.aux[3 * i] = zr;
+        E.aux[3 * i + 1] = zi;
+        E.aux[3 * i + 2] = h;
+    }
+}
+
+// Workgroups that fit on the GPU at once for a hot-loop kernel.
+template <typename Kern>
+static unsigned resident_grid(Kern kernel) {
+    int per_cu = 0, dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 2048;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 2048;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTile, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return (unsigned)(per_cu * n_cu);
+}
+
+template <int NDET>
+static hipError_t launch_hot(const BatchDev& b, int ne, int precision, hipStream_t st) {
+    if (precision == PE_PREC_SPLIT) {
+        static const unsigned grid = resident_grid(k_b_split<NDET>);
+        prof_begin("loglike_split", st);
+        k_b_split<NDET><<<grid, kTile, 0, st>>>(b.evs, b.ioff, ne, b.hdr);
+        prof_end("loglike_split", st);
+    } else {
+        static const unsigned grid = resident_grid(k_b_f64<NDET>);
+        prof_begin("loglike_fp64", st);
+        k_b_f64<NDET><<<grid, kTile, 0, st>>>(b.evs, b.ioff, ne, b.hdr);
+        prof_end("loglike_fp64", st);
+    }
+    return hipGetLastError();
+}
+
+template <int NDET>
+static void launch_finalize(const BatchDev& b, int ne, int64_t max_draws, hipStream_t st) {
+    k_b_finalize<NDET><<<(unsigned)((max_draws + 255) / 256), 256, 0, st>>>(b.evs, b.doff, ne);
+}
+
+hipError_t launch_batch(const BatchDev& b, int ne, int n_det, int64_t max_draws, int precision, hipStream_t st) {
+    if (ne <= 0 || max_draws <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((max_draws + 255) / 256);
+    k_b_reset<<<dim3(kBuckets / 256, ne), 256, 0, st>>>(b.evs, b.hdr);
+    k_b_support<<<nb, 256, 0, st>>>(b.evs, b.doff, ne);
+    k_b_plan<<<ne, 1024, 0, st>>>(b.evs);
+    k_b_items<<<1, 64, 0, st>>>(b.evs, ne, b.ioff, b.hdr);
+    k_b_scatter<<<nb, 256, 0, st>>>(b.evs, b.doff, ne);
+    k_b_coeffs<<<nb, 256, 0, st>>>(b.evs, b.doff, ne);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (n_det) {
+        case 1: e = launch_hot<1>(b, ne, precision, st); launch_finalize<1>(b, ne, max_draws, st); break;
+        case 2: e = launch_hot<2>(b, ne, precision, st); launch_finalize<2>(b, ne, max_draws, st); break;
+        case 3: e = launch_hot<3>(b, ne, precision, st); launch_finalize<3>(b, ne, max_draws, st); break;
+        default: e = launch_hot<4>(b, ne, precision, st); launch_finalize<4>(b, ne, max_draws, st); break;
+    }
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+}  // namespace pe

@@ -40,9 +40,14 @@ def test_binding_loads_and_pure_host_calls():
     st = L.pe_event_create(ctypes.byref(d), None, None, None, ctypes.byref(h))
     assert st == 1 and h.value is None
     assert "n_det" in binding.pe_last_error()
-    assert L.pe_set_chunks(12) == 1
+    assert L.pe_set_chunks(65) == 1
+    assert L.pe_set_chunks(-1) == 1
     assert L.pe_set_chunks(0) == 0
     assert L.pe_loglike_batch(None, None, 0, 0, None, None, None) == 1
+    # an empty multi-event batch is a no-op; bad arrays are rejected on the host
+    assert L.pe_loglike_multi(0, None, None, None, 1, None, None, None) == 0
+    assert L.pe_loglike_multi(2, None, None, None, 1, None, None, None) == 1
+    assert L.pe_loglike_multi(0, None, None, None, 7, None, None, None) == 1
 
 
 def test_event_desc_layout_matches_header():
