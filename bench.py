@@ -109,19 +109,22 @@ def main():
     stats = torch.zeros((max(args.steps, 1), n_events, 4), dtype=torch.float64, device="cuda")
 
     def step(i, st_rows):
-        for x in evs:
+        if n_events == 1:
+            # the single-event calls of the path
+            x = evs[0]
             h_ = x["ev"].handle
             binding.pe_event_update(h_, x["data"], x["psd"])
             binding.pe_metric(h_, x["theta0"], None, 0, x["g"])
             binding.pe_draw(h_, x["theta0"], x["g"], x["seed"], i, x["N"], x["theta"], x["lq"], x["lp"])
-        if n_events == 1:
-            x = evs[0]
-            binding.pe_loglike_batch(x["ev"].handle, x["theta"], x["N"], prec, x["ll"], None)
+            binding.pe_loglike_batch(h_, x["theta"], x["N"], prec, x["ll"], None)
+            binding.pe_weights_ess(x["ll"], x["lp"], x["lq"], x["N"], x["w"], st_rows[0])
         else:
-            binding.pe_loglike_multi([x["ev"] for x in evs], [x["theta"] for x in evs], [x["N"] for x in evs],
-                                     prec, [x["ll"] for x in evs])
-        for e, x in enumerate(evs):
-            binding.pe_weights_ess(x["ll"], x["lp"], x["lq"], x["N"], x["w"], st_rows[e])
+            # every stage as one set of launches over the batch of events
+            items = [binding.make_item(x["ev"], n=x["N"], data=x["data"], psd=x["psd"], theta0=x["theta0"],
+                                       seed=x["seed"], stream_id=i, g=x["g"], theta=x["theta"], logq=x["lq"],
+                                       logprior=x["lp"], loglike=x["ll"], w=x["w"], stats=st_rows[e])
+                     for e, x in enumerate(evs)]
+            binding.pe_batch_run(items, binding.PE_STAGE_ALL, prec)
 
     for i in range(args.warmup):
         step(1000 + i, stats[0])

@@ -196,6 +196,52 @@ pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t *events, const d
                              void *stream);
 
 /*
+ * The whole path for a batch of events in one call: for every item, the
+ * stages selected in `stages` run in the order
+ *   PE_STAGE_PREP    re-prepare the event's tables from data/psd (as pe_event_update)
+ *   PE_STAGE_METRIC  g = metric at theta0 (as pe_metric with fd_step, metric_flags)
+ *   PE_STAGE_DRAW    n draws from N(theta0, g^-1) (as pe_draw with seed, stream_id)
+ *   PE_STAGE_LOGLIKE ln L of the n draws in theta (as pe_loglike_batch)
+ *   PE_STAGE_WEIGHTS weights and ESS of loglike, logprior, logq (as pe_weights_ess)
+ * and each stage is one set of launches over all items (events of any
+ * detector count and size mixed), so a batch costs a fixed number of launches
+ * whatever the number of events. Every item's results equal those of the
+ * corresponding single-event calls bit for bit, whatever else is in the batch.
+ * Pointers in the items are device pointers with the layouts of the
+ * single-event calls; fields of unselected stages are ignored. Each event may
+ * appear once. Work on an event must not overlap other work on it.
+ * Errors: PE_ERR_ARG (bad item, duplicate event, bad stages or precision),
+ * PE_ERR_OOM, PE_ERR_HIP.
+ */
+#define PE_STAGE_PREP 1
+#define PE_STAGE_METRIC 2
+#define PE_STAGE_DRAW 4
+#define PE_STAGE_LOGLIKE 8
+#define PE_STAGE_WEIGHTS 16
+#define PE_STAGE_ALL 31
+
+typedef struct {
+    pe_event_t ev;
+    const void *data, *psd;     /* PREP: [n_det][n_bins] in the event's storage types */
+    const double *theta0;       /* METRIC, DRAW: [D] */
+    const double *fd_step;      /* METRIC: NULL = default steps */
+    int32_t metric_flags;       /* METRIC: as pe_metric */
+    uint32_t stream_id;         /* DRAW */
+    uint64_t seed;              /* DRAW */
+    double *g;                  /* METRIC writes, DRAW reads: [D*D] */
+    int64_t n;                  /* DRAW, LOGLIKE, WEIGHTS: draws */
+    double *theta;              /* DRAW writes, LOGLIKE reads: [D][n] */
+    double *logq, *logprior;    /* DRAW writes, WEIGHTS reads: [n] */
+    double *loglike;            /* LOGLIKE writes, WEIGHTS reads: [n] */
+    double *aux;                /* LOGLIKE: NULL or [n][3] */
+    double *w;                  /* WEIGHTS: NULL or [n] */
+    double *stats;              /* WEIGHTS: [4] */
+} pe_batch_item_t;
+
+pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t *items, int32_t stages, int32_t precision,
+                         void *stream);
+
+/*
  * Importance weights (Eq. 5) and ESS (Eq. 6) of n draws, with
  * ln w_i = loglike_i + logprior_i - logq_i and max-shifted sums in FP64.
  *   w_dev: NULL or [n] normalised weights (sum 1; 0 where ln w = -inf).

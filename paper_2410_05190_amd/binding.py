@@ -29,7 +29,7 @@ PE_F32 = 1
 MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
-           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_weights_ess", "pe_waveform",
+           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_last_error"]
 
 
@@ -48,6 +48,20 @@ class EventDesc(ctypes.Structure):
 
 
 _lib = None
+
+
+PE_STAGE_PREP, PE_STAGE_METRIC, PE_STAGE_DRAW, PE_STAGE_LOGLIKE, PE_STAGE_WEIGHTS = 1, 2, 4, 8, 16
+PE_STAGE_ALL = 31
+
+
+class BatchItem(ctypes.Structure):
+    """pe_batch_item_t."""
+    _fields_ = [("ev", ctypes.c_void_p), ("data", ctypes.c_void_p), ("psd", ctypes.c_void_p),
+                ("theta0", ctypes.c_void_p), ("fd_step", ctypes.c_void_p), ("metric_flags", ctypes.c_int32),
+                ("stream_id", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("g", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("theta", ctypes.c_void_p), ("logq", ctypes.c_void_p),
+                ("logprior", ctypes.c_void_p), ("loglike", ctypes.c_void_p), ("aux", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
 
 
 def load(path=LIB_PATH):
@@ -71,6 +85,7 @@ def load(path=LIB_PATH):
         "pe_draw": (i32, [vp, dp, dp, u64, u32, i64, dp, dp, dp, vp]),
         "pe_loglike_batch": (i32, [vp, dp, i64, i32, dp, dp, vp]),
         "pe_loglike_multi": (i32, [i32, vp, vp, vp, i32, vp, vp, vp]),
+        "pe_batch_run": (i32, [i32, vp, i32, i32, vp]),
         "pe_weights_ess": (i32, [dp, dp, dp, i64, dp, dp, vp]),
         "pe_waveform": (i32, [ctypes.POINTER(EventDesc), dp, vp, dp, dp, vp]),
         "pe_rng_uniforms": (i32, [u64, u32, i64, i32, dp, vp]),
@@ -210,6 +225,29 @@ def pe_loglike_multi(events, thetas, ns, precision, loglikes, auxs=None, stream=
     if auxs is not None:
         ax_a = (ctypes.c_void_p * max(ne, 1))(*[_ptr(t, f64, "aux", allow_none=True) for t in auxs])
     _check(load().pe_loglike_multi(ne, ev_a, th_a, n_a, int(precision), ll_a, ax_a, _stream(stream)))
+
+
+def make_item(ev, n=0, data=None, psd=None, theta0=None, fd_step=None, metric_flags=0, seed=0, stream_id=0, g=None,
+              theta=None, logq=None, logprior=None, loglike=None, aux=None, w=None, stats=None):
+    """A pe_batch_item_t from device tensors (None = NULL)."""
+    def p(t):
+        return None if t is None else t.data_ptr()
+    it = BatchItem()
+    it.ev = ev.handle.value if isinstance(ev, Event) else (ev.value if isinstance(ev, ctypes.c_void_p) else ev)
+    it.data, it.psd, it.theta0, it.fd_step = p(data), p(psd), p(theta0), p(fd_step)
+    it.metric_flags = int(metric_flags)
+    it.stream_id = int(stream_id) & 0xFFFFFFFF
+    it.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    it.g, it.n = p(g), int(n)
+    it.theta, it.logq, it.logprior, it.loglike = p(theta), p(logq), p(logprior), p(loglike)
+    it.aux, it.w, it.stats = p(aux), p(w), p(stats)
+    return it
+
+
+def pe_batch_run(items, stages, precision, stream=None):
+    arr = (BatchItem * max(len(items), 1))(*items)
+    _check(load().pe_batch_run(len(items), ctypes.cast(arr, ctypes.c_void_p), int(stages), int(precision),
+                               _stream(stream)))
 
 
 def pe_weights_ess(loglike, logprior, logq, n, w, stats, stream=None):

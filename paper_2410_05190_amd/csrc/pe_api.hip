@@ -1,38 +1,39 @@
 // pe_api.hip -- host runtime of the likelihood engine: the C ABI of include/pe.h,
-// argument validation, device tables and workspace, stream ordering, profiling.
+// argument validation, event memory, batch areas, stream ordering, profiling.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <algorithm>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
 #include <utility>
 #include <vector>
 
-#include "pe_internal.h"
+#include "pe_host.h"
 
 namespace {
 
 thread_local std::string g_err;
+int g_chunks = 0;  // cap on the hot loop's groups of chunks per event; 0 = automatic (64)
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+namespace pe {
 
 pe_status_t fail(pe_status_t s, const std::string& msg) {
     g_err = msg;
     return s;
 }
-
-#define PE_HIP(call)                                                                                  \
-    do {                                                                                              \
-        hipError_t _e = (call);                                                                       \
-        if (_e != hipSuccess) return fail(PE_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
-    } while (0)
-
-int g_chunks = 0;  // cap on the hot loop's groups of chunks per event; 0 = automatic (64)
-
-hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 pe_status_t validate_desc(const pe_event_desc_t* d) {
     if (!d) return fail(PE_ERR_ARG, "desc is NULL");
@@ -55,7 +56,7 @@ pe_status_t validate_desc(const pe_event_desc_t* d) {
 
 // Detector tensor D = (x x^T - y y^T)/2 from latitude, longitude and the
 // x-arm azimuth (north toward east); y arm 90 degrees east of x.
-void build_const(const pe_event_desc_t& d, pe::EvConst& ec) {
+void build_const(const pe_event_desc_t& d, EvConst& ec) {
     std::memset(&ec, 0, sizeof(ec));
     ec.n_det = d.n_det;
     ec.params = d.params;
@@ -90,11 +91,9 @@ void build_const(const pe_event_desc_t& d, pe::EvConst& ec) {
     }
 }
 
-template <typename T>
-pe_status_t dalloc(T** p, size_t count) {
+pe_status_t dalloc_bytes(char** p, size_t bytes) {
     *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    hipError_t e = hipMalloc((void**)p, bytes ? bytes : 1);
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
@@ -103,89 +102,283 @@ pe_status_t dalloc(T** p, size_t count) {
     return PE_OK;
 }
 
-template <typename T>
-void dfree(T*& p) {
+void dfree_bytes(char*& p) {
     if (p) (void)hipFree(p);
     p = nullptr;
 }
 
-void free_batch(pe::BatchDev& b) {
-    dfree(b.evs);
-    dfree(b.doff);
-    dfree(b.ioff);
-    dfree(b.hdr);
-    b.cap = 0;
+// ------------------------------------------------------------- event memory
+// Tables: rec32/rec64 (K + kTabPad records), pw, pfx, status word, metric and
+// draw workspace. Workspace for npad draws: cuts, bucket counts, plan, order,
+// coefficient rows, responses, (h|h) and the hot loop's partials.
+int64_t npad_for(int64_t n) { return ((n + kTile - 1) / kTile) * kTile; }
+
+int64_t partial_cap_for(int64_t npad) { return std::min<int64_t>(64 * npad, (int64_t)1 << 22); }
+
+size_t layout_tables(pe_event_s* ev, char* base) {
+    Carver c(base);
+    const int64_t K = ev->desc.n_bins;
+    const int nd = ev->desc.n_det;
+    ev->rec32 = c.take<Rec32>((size_t)(K + kTabPad));
+    ev->rec64 = c.take<Rec64>((size_t)(K + kTabPad));
+    ev->pw = c.take<double>((size_t)nd * K);
+    ev->pfx = c.take<double>((size_t)nd * (K + 1));
+    ev->status = c.take<int>(1);
+    ev->mws = c.take<double>((size_t)kMwsTotal);
+    return c.size();
 }
 
-pe_status_t ensure_batch(pe::BatchDev& b, int n_events) {
-    if (n_events <= b.cap) return PE_OK;
-    if (b.cap > 0) PE_HIP(hipDeviceSynchronize());  // earlier batches may still read the old buffers
-    free_batch(b);
-    pe_status_t s;
-    if ((s = dalloc(&b.evs, (size_t)n_events)) != PE_OK) return s;
-    if ((s = dalloc(&b.doff, (size_t)n_events + 1)) != PE_OK) return s;
-    if ((s = dalloc(&b.ioff, (size_t)n_events + 1)) != PE_OK) return s;
-    if ((s = dalloc(&b.hdr, 4)) != PE_OK) return s;
-    b.cap = n_events;
-    return PE_OK;
+size_t layout_ws(pe_event_s* ev, int64_t npad, char* base) {
+    Carver c(base);
+    const int nd = ev->desc.n_det;
+    const int64_t cap = partial_cap_for(npad);
+    ev->kc_all = c.take<int>((size_t)npad);
+    ev->hist = c.take<int>((size_t)kBuckets);
+    ev->plan = c.take<EvPlan>(1);
+    ev->idx = c.take<int>((size_t)npad);
+    ev->coef = c.take<double>((size_t)kNCoef * npad);
+    ev->kcut = c.take<int>((size_t)npad);
+    ev->resp = c.take<double>((size_t)2 * nd * npad);
+    ev->hh = c.take<double>((size_t)npad);
+    ev->partial = c.take<double2>((size_t)nd * cap);
+    if (base) {
+        ev->npad = npad;
+        ev->partial_cap = cap;
+    }
+    return c.size();
 }
 
-void free_draw_ws(pe_event_s* ev) {
-    dfree(ev->kc_all);
-    dfree(ev->hist);
-    dfree(ev->plan);
-    dfree(ev->idx);
-    dfree(ev->coef);
-    dfree(ev->kcut);
-    dfree(ev->resp);
-    dfree(ev->hh);
-    dfree(ev->partial);
+size_t tables_bytes(const pe_event_desc_t& d) {
+    pe_event_s tmp;
+    tmp.desc = d;
+    return layout_tables(&tmp, nullptr);
+}
+
+size_t ws_bytes(const pe_event_desc_t& d, int64_t npad) {
+    pe_event_s tmp;
+    tmp.desc = d;
+    return layout_ws(&tmp, npad, nullptr);
+}
+
+size_t event_footprint(const pe_event_desc_t& d, int64_t max_draws) {
+    return align_up(tables_bytes(d), 256) + ws_bytes(d, npad_for(max_draws));
+}
+
+// Grow the workspace to hold batches of n draws (own memory only).
+pe_status_t ensure_ws(pe_event_s* ev, int64_t n) {
+    const int64_t npad = npad_for(n);
+    if (npad <= ev->npad && ev->partial) return PE_OK;
+    if (!ev->own_mem) return fail(PE_ERR_ARG, "the event was sized for fewer draws");
+    PE_HIP(hipDeviceSynchronize());
+    dfree_bytes(ev->ws_mem);
     ev->npad = 0;
-    ev->partial_cap = 0;
+    ev->partial = nullptr;
+    pe_status_t s = dalloc_bytes(&ev->ws_mem, ws_bytes(ev->desc, npad));
+    if (s != PE_OK) return s;
+    layout_ws(ev, npad, ev->ws_mem);
+    return PE_OK;
 }
 
 void free_event(pe_event_s* ev) {
     if (!ev) return;
-    free_draw_ws(ev);
-    free_batch(ev->self);
-    dfree(ev->rec32);
-    dfree(ev->rec64);
-    dfree(ev->pw);
-    dfree(ev->pfx);
-    dfree(ev->status);
-    dfree(ev->mws);
+    if (ev->own_mem) {
+        dfree_bytes(ev->tab_mem);
+        dfree_bytes(ev->ws_mem);
+    }
     delete ev;
 }
 
-// Per-draw workspace for batches of up to n draws. The hot loop keeps up to 64
-// groups of partials per draw and detector; min(64 npad, 2^22) slots per
-// detector bound the groups of large batches (16 at 2^18 draws), where the plan
-// asks for few groups anyway (it aims at ~16k work items per event).
-pe_status_t ensure_ws(pe_event_s* ev, int64_t n) {
-    const int64_t npad = ((n + pe::kTile - 1) / pe::kTile) * pe::kTile;
-    if (npad <= ev->npad && ev->partial) return PE_OK;
-    PE_HIP(hipDeviceSynchronize());
-    const int64_t np = npad > ev->npad ? npad : ev->npad;
-    free_draw_ws(ev);
-    const int nd = ev->desc.n_det;
-    const int64_t cap = std::min<int64_t>(64 * np, (int64_t)1 << 22);
-    pe_status_t s;
-    if ((s = dalloc(&ev->kc_all, (size_t)np)) != PE_OK) return s;
-    if ((s = dalloc(&ev->hist, (size_t)pe::kBuckets)) != PE_OK) return s;
-    if ((s = dalloc(&ev->plan, 1)) != PE_OK) return s;
-    if ((s = dalloc(&ev->idx, (size_t)np)) != PE_OK) return s;
-    if ((s = dalloc(&ev->coef, (size_t)pe::kNCoef * np)) != PE_OK) return s;
-    if ((s = dalloc(&ev->kcut, (size_t)np)) != PE_OK) return s;
-    if ((s = dalloc(&ev->resp, (size_t)2 * nd * np)) != PE_OK) return s;
-    if ((s = dalloc(&ev->hh, (size_t)np)) != PE_OK) return s;
-    if ((s = dalloc(&ev->partial, (size_t)nd * cap)) != PE_OK) return s;
-    ev->npad = np;
-    ev->partial_cap = cap;
+// Event object with its pointers laid out in `mem` (tables, then workspace for
+// max_draws), or in its own allocations when mem is NULL.
+pe_status_t new_event(const pe_event_desc_t* desc, char* mem, int64_t max_draws, pe_event_s** out) {
+    *out = nullptr;
+    pe_status_t s = validate_desc(desc);
+    if (s != PE_OK) return s;
+    pe_event_s* ev = new (std::nothrow) pe_event_s();
+    if (!ev) return fail(PE_ERR_OOM, "host allocation failed");
+    ev->desc = *desc;
+    build_const(*desc, ev->ec);
+    if (mem) {
+        ev->own_mem = false;
+        const size_t tb = align_up(tables_bytes(*desc), 256);
+        ev->tab_mem = mem;
+        ev->ws_mem = mem + tb;
+        layout_tables(ev, ev->tab_mem);
+        layout_ws(ev, npad_for(max_draws), ev->ws_mem);
+    } else {
+        if ((s = dalloc_bytes(&ev->tab_mem, tables_bytes(*desc))) != PE_OK) {
+            free_event(ev);
+            return s;
+        }
+        layout_tables(ev, ev->tab_mem);
+        if (max_draws > 0 && (s = ensure_ws(ev, max_draws)) != PE_OK) {
+            free_event(ev);
+            return s;
+        }
+    }
+    *out = ev;
     return PE_OK;
 }
 
-pe::EvDev make_evdev(const pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux) {
-    pe::EvDev d;
+// --------------------------------------------------------------- batch areas
+// One device buffer per (stream, kind): header, argument records, offsets
+// (uploaded with one copy, skipped when identical to the last upload), then
+// scratch. Batches on one stream are ordered, so the buffer is reused safely;
+// the area's lock is held from the upload until the launches are queued.
+struct Area {
+    std::mutex mu;
+    char* dev = nullptr;
+    size_t cap = 0;
+    std::vector<char> shadow;
+};
+
+std::mutex g_areas_mu;
+std::map<std::pair<void*, int>, std::unique_ptr<Area>> g_areas;
+
+Area& area_for(hipStream_t st, int kind) {
+    std::lock_guard<std::mutex> lk(g_areas_mu);
+    auto& p = g_areas[{(void*)st, kind}];
+    if (!p) p.reset(new Area());
+    return *p;
+}
+
+pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const void* args, size_t arg_bytes,
+                        const std::vector<int64_t>& off, const std::vector<int64_t>* off2, size_t scratch_bytes,
+                        hipStream_t st, BatchPtrs& out) {
+    const size_t o_args = 256;
+    const size_t o_off = align_up(o_args + arg_bytes, 256);
+    const size_t o_off2 = align_up(o_off + sizeof(int64_t) * (ne + 1), 256);
+    const size_t o_scr = align_up(o_off2 + sizeof(int64_t) * (ne + 1), 256);
+    const size_t need = o_scr + std::max<size_t>(scratch_bytes, 256);
+    if (need > A.cap) {
+        PE_HIP(hipDeviceSynchronize());  // earlier batches may still read the old buffer
+        dfree_bytes(A.dev);
+        A.cap = 0;
+        A.shadow.clear();
+        const size_t cap = std::max<size_t>(need + need / 2, 1 << 16);
+        pe_status_t s = dalloc_bytes(&A.dev, cap);
+        if (s != PE_OK) return s;
+        A.cap = cap;
+    }
+    std::vector<char> img(o_scr, 0);
+    BatchHdr h = {};
+    h.ne = ne;
+    h.total = total;
+    h.total2 = total2;
+    std::memcpy(img.data(), &h, sizeof(h));
+    if (arg_bytes) std::memcpy(img.data() + o_args, args, arg_bytes);
+    std::memcpy(img.data() + o_off, off.data(), sizeof(int64_t) * (ne + 1));
+    if (off2) std::memcpy(img.data() + o_off2, off2->data(), sizeof(int64_t) * (ne + 1));
+    if (img != A.shadow) {
+        PE_HIP(hipMemcpyAsync(A.dev, img.data(), img.size(), hipMemcpyHostToDevice, st));
+        A.shadow.swap(img);
+    }
+    out.hdr = (BatchHdr*)A.dev;
+    out.args = A.dev + o_args;
+    out.off = (int64_t*)(A.dev + o_off);
+    out.off2 = (int64_t*)(A.dev + o_off2);
+    out.scratch = (double*)(A.dev + o_scr);
+    return PE_OK;
+}
+
+// ------------------------------------------------------------ stage runners
+PrepArg prep_arg(const pe_event_s* ev, const void* data, const void* psd) {
+    PrepArg a;
+    std::memset(&a, 0, sizeof(a));
+    a.ec = ev->ec;
+    a.data = data;
+    a.psd = psd;
+    a.data_f32 = ev->desc.data_dtype == PE_C64;
+    a.psd_f32 = ev->desc.psd_dtype == PE_F32;
+    a.rec32 = ev->rec32;
+    a.rec64 = ev->rec64;
+    a.pw = ev->pw;
+    a.pfx = ev->pfx;
+    a.seg = ev->mws + kMwsScan;
+    a.status = ev->status;
+    return a;
+}
+
+pe_status_t run_prep(const std::vector<PrepArg>& all, hipStream_t st) {
+    for (int cls = 0; cls < 4; ++cls) {
+        std::vector<PrepArg> v;
+        for (const PrepArg& a : all)
+            if (a.data_f32 * 2 + a.psd_f32 == cls) v.push_back(a);
+        if (v.empty()) continue;
+        const int ne = (int)v.size();
+        std::vector<int64_t> off(ne + 1, 0);
+        for (int e = 0; e < ne; ++e) off[e + 1] = off[e] + v[e].ec.K + kTabPad;
+        Area& A = area_for(st, kAreaPrep);
+        std::lock_guard<std::mutex> lk(A.mu);
+        BatchPtrs b;
+        pe_status_t s = upload_area(A, ne, off[ne], 0, v.data(), sizeof(PrepArg) * ne, off, nullptr, 0, st, b);
+        if (s != PE_OK) return s;
+        PE_HIP(launch_prep_batch(b, ne, off[ne], cls >> 1, cls & 1, st));
+    }
+    return PE_OK;
+}
+
+MetricArg metric_arg(const pe_event_s* ev, const double* theta0, const double* steps, int flags, double* g) {
+    MetricArg a;
+    std::memset(&a, 0, sizeof(a));
+    a.ec = ev->ec;
+    a.tab = ev->rec64;
+    a.pw = ev->pw;
+    a.mws = ev->mws;
+    a.theta0 = theta0;
+    a.steps = steps;
+    a.g = g;
+    a.flags = flags;
+    return a;
+}
+
+pe_status_t run_metric(const std::vector<MetricArg>& v, hipStream_t st) {
+    const int ne = (int)v.size();
+    if (ne == 0) return PE_OK;
+    std::vector<int64_t> off(ne + 1, 0);
+    Area& A = area_for(st, kAreaMetric);
+    std::lock_guard<std::mutex> lk(A.mu);
+    BatchPtrs b;
+    pe_status_t s = upload_area(A, ne, 0, 0, v.data(), sizeof(MetricArg) * ne, off, nullptr, 0, st, b);
+    if (s != PE_OK) return s;
+    PE_HIP(launch_metric_batch(b, ne, st));
+    return PE_OK;
+}
+
+DrawArg draw_arg(const pe_event_s* ev, const double* theta0, const double* g, uint64_t seed, uint32_t stream_id,
+                 int64_t n, double* theta, double* logq, double* logprior) {
+    DrawArg a;
+    std::memset(&a, 0, sizeof(a));
+    a.ec = ev->ec;
+    a.theta0 = theta0;
+    a.g = g;
+    a.chol = ev->mws + kMwsChol;
+    a.status = ev->status;
+    a.seed = seed;
+    a.stream_id = stream_id;
+    a.n = n;
+    a.theta = theta;
+    a.logq = logq;
+    a.logprior = logprior;
+    return a;
+}
+
+pe_status_t run_draw(const std::vector<DrawArg>& v, hipStream_t st) {
+    const int ne = (int)v.size();
+    if (ne == 0) return PE_OK;
+    std::vector<int64_t> off(ne + 1, 0);
+    for (int e = 0; e < ne; ++e) off[e + 1] = off[e] + v[e].n;
+    Area& A = area_for(st, kAreaDraw);
+    std::lock_guard<std::mutex> lk(A.mu);
+    BatchPtrs b;
+    pe_status_t s = upload_area(A, ne, off[ne], 0, v.data(), sizeof(DrawArg) * ne, off, nullptr, 0, st, b);
+    if (s != PE_OK) return s;
+    PE_HIP(launch_draw_batch(b, ne, off[ne], st));
+    return PE_OK;
+}
+
+EvDev loglike_arg(const pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux) {
+    EvDev d;
     std::memset(&d, 0, sizeof(d));
     d.ec = ev->ec;
     d.rec32 = ev->rec32;
@@ -205,6 +398,9 @@ pe::EvDev make_evdev(const pe_event_s* ev, const double* theta, int64_t n, doubl
     if (mg > 64) mg = 64;
     if (g_chunks > 0 && mg > g_chunks) mg = g_chunks;
     d.max_groups = (int)(mg < 1 ? 1 : mg);
+    d.tile_lo = 0;
+    d.tile_hi = INT_MAX;
+    d.flags = kLlPrologue | kLlFinalize;
     d.theta = theta;
     d.n = n;
     d.loglike = loglike;
@@ -212,29 +408,50 @@ pe::EvDev make_evdev(const pe_event_s* ev, const double* theta, int64_t n, doubl
     return d;
 }
 
-// Upload the descriptors of ne events (same n_det) and launch the batch.
-pe_status_t run_batch(pe::BatchDev& b, const std::vector<pe::EvDev>& evs, int n_det, int precision,
-                      hipStream_t st) {
-    const int ne = (int)evs.size();
-    pe_status_t s = ensure_batch(b, ne);
+pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t st) {
+    const int ne = (int)v.size();
+    if (ne == 0) return PE_OK;
+    std::vector<int64_t> poff(ne + 1, 0), foff(ne + 1, 0);
+    for (int e = 0; e < ne; ++e) {
+        poff[e + 1] = poff[e] + ((v[e].flags & kLlPrologue) ? v[e].n : 0);
+        foff[e + 1] = foff[e] + ((v[e].flags & kLlFinalize) ? v[e].n : 0);
+    }
+    Area& A = area_for(st, kAreaLoglike);
+    std::lock_guard<std::mutex> lk(A.mu);
+    BatchPtrs b;
+    pe_status_t s = upload_area(A, ne, poff[ne], foff[ne], v.data(), sizeof(EvDev) * ne, poff, &foff,
+                                sizeof(int64_t) * (ne + 1), st, b);
     if (s != PE_OK) return s;
-    std::vector<int64_t> off(ne + 1, 0);
-    for (int e = 0; e < ne; ++e) off[e + 1] = off[e] + evs[e].n;
-    PE_HIP(hipMemcpyAsync(b.evs, evs.data(), sizeof(pe::EvDev) * ne, hipMemcpyHostToDevice, st));
-    PE_HIP(hipMemcpyAsync(b.doff, off.data(), sizeof(int64_t) * (ne + 1), hipMemcpyHostToDevice, st));
-    PE_HIP(pe::launch_batch(b, ne, n_det, off[ne], precision, st));
+    PE_HIP(launch_loglike_batch(b, ne, poff[ne], foff[ne], precision, st));
     return PE_OK;
 }
+
+pe_status_t run_weights(const std::vector<WeightArg>& v, hipStream_t st) {
+    const int ne = (int)v.size();
+    if (ne == 0) return PE_OK;
+    std::vector<int64_t> boff(ne + 1, 0), doff(ne + 1, 0);
+    for (int e = 0; e < ne; ++e) {
+        boff[e + 1] = boff[e] + (v[e].n + kWBlock - 1) / kWBlock;
+        doff[e + 1] = doff[e] + v[e].n;
+    }
+    Area& A = area_for(st, kAreaWeights);
+    std::lock_guard<std::mutex> lk(A.mu);
+    BatchPtrs b;
+    const size_t scratch = sizeof(double4) * std::max<int64_t>(boff[ne], 1) + sizeof(double2) * ne;
+    pe_status_t s =
+        upload_area(A, ne, boff[ne], doff[ne], v.data(), sizeof(WeightArg) * ne, boff, &doff, scratch, st, b);
+    if (s != PE_OK) return s;
+    PE_HIP(launch_weights_batch(b, ne, boff[ne], doff[ne], st));
+    return PE_OK;
+}
+
+int chunks_setting() { return g_chunks; }
 
 // ------------------------------------------------------------------ profiling
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> g_prof;
 std::map<std::string, hipEvent_t> g_prof_open;
-
-}  // namespace
-
-namespace pe {
 
 void prof_begin(const char* name, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -257,7 +474,19 @@ void prof_end(const char* name, hipStream_t st) {
     g_prof_open.erase(it);
 }
 
+pe_status_t check_n(int64_t n) {
+    if (n < 0 || n > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "n must be in 0..2^30");
+    return PE_OK;
+}
+
+pe_status_t check_precision(int32_t precision) {
+    if (precision != PE_PREC_FP64 && precision != PE_PREC_SPLIT) return fail(PE_ERR_ARG, "bad precision");
+    return PE_OK;
+}
+
 }  // namespace pe
+
+using namespace pe;
 
 extern "C" {
 
@@ -274,31 +503,16 @@ pe_status_t pe_event_create(const pe_event_desc_t* desc, const void* data_dev, c
     pe_status_t s = validate_desc(desc);
     if (s != PE_OK) return s;
     if (!data_dev || !psd_dev) return fail(PE_ERR_ARG, "data and psd must be device pointers");
-    pe_event_s* ev = new (std::nothrow) pe_event_s();
-    if (!ev) return fail(PE_ERR_OOM, "host allocation failed");
-    ev->desc = *desc;
-    build_const(*desc, ev->ec);
-    const int64_t K = desc->n_bins;
-    const int nd = desc->n_det;
-    if ((s = dalloc(&ev->rec32, (size_t)(K + pe::kTabPad))) != PE_OK ||
-        (s = dalloc(&ev->rec64, (size_t)(K + pe::kTabPad))) != PE_OK ||
-        (s = dalloc(&ev->pw, (size_t)nd * K)) != PE_OK || (s = dalloc(&ev->pfx, (size_t)nd * (K + 1))) != PE_OK ||
-        (s = dalloc(&ev->status, 1)) != PE_OK || (s = dalloc(&ev->mws, (size_t)pe::kMwsTotal)) != PE_OK) {
-        free_event(ev);
-        return s;
-    }
+    pe_event_s* ev = nullptr;
+    if ((s = new_event(desc, nullptr, 0, &ev)) != PE_OK) return s;
     hipStream_t st = as_stream(stream);
-    hipError_t e = hipMemsetAsync(ev->status, 0, sizeof(int), st);
-    if (e == hipSuccess) e = hipMemsetAsync(ev->rec32 + K, 0, sizeof(pe::Rec32) * pe::kTabPad, st);
-    if (e == hipSuccess) e = hipMemsetAsync(ev->rec64 + K, 0, sizeof(pe::Rec64) * pe::kTabPad, st);
-    if (e == hipSuccess) e = hipMemsetAsync(ev->mws, 0, sizeof(double) * pe::kMwsTotal, st);
-    if (e == hipSuccess) e = pe::launch_prep(ev, data_dev, psd_dev, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipError_t e = hipMemsetAsync(ev->tab_mem, 0, tables_bytes(*desc), st);
     if (e != hipSuccess) {
         free_event(ev);
         return fail(PE_ERR_HIP, std::string("event preparation: ") + hipGetErrorString(e));
     }
-    s = pe_event_status(ev, stream);
+    s = run_prep(std::vector<PrepArg>(1, prep_arg(ev, data_dev, psd_dev)), st);
+    if (s == PE_OK) s = pe_event_status(ev, stream);
     if (s != PE_OK) {
         std::string msg = g_err;
         free_event(ev);
@@ -311,8 +525,7 @@ pe_status_t pe_event_create(const pe_event_desc_t* desc, const void* data_dev, c
 pe_status_t pe_event_update(pe_event_t ev, const void* data_dev, const void* psd_dev, void* stream) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
     if (!data_dev || !psd_dev) return fail(PE_ERR_ARG, "data and psd must be device pointers");
-    PE_HIP(pe::launch_prep(ev, data_dev, psd_dev, as_stream(stream)));
-    return PE_OK;
+    return run_prep(std::vector<PrepArg>(1, prep_arg(ev, data_dev, psd_dev)), as_stream(stream));
 }
 
 pe_status_t pe_event_status(pe_event_t ev, void* stream) {
@@ -322,9 +535,9 @@ pe_status_t pe_event_status(pe_event_t ev, void* stream) {
     int flags = 0;
     PE_HIP(hipMemcpy(&flags, ev->status, sizeof(int), hipMemcpyDeviceToHost));
     if (flags) PE_HIP(hipMemset(ev->status, 0, sizeof(int)));
-    if (flags & pe::kStBadPsd) return fail(PE_ERR_ARG, "PSD values must be positive and finite");
-    if (flags & pe::kStNonfinite) return fail(PE_ERR_NONFINITE, "data contains inf or nan");
-    if (flags & pe::kStSingular) return fail(PE_ERR_SINGULAR, "metric is not positive definite");
+    if (flags & kStBadPsd) return fail(PE_ERR_ARG, "PSD values must be positive and finite");
+    if (flags & kStNonfinite) return fail(PE_ERR_NONFINITE, "data contains inf or nan");
+    if (flags & kStSingular) return fail(PE_ERR_SINGULAR, "metric is not positive definite");
     return PE_OK;
 }
 
@@ -336,6 +549,7 @@ pe_status_t pe_event_reserve(pe_event_t ev, int64_t max_draws) {
 
 pe_status_t pe_event_destroy(pe_event_t ev) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (!ev->own_mem) return fail(PE_ERR_ARG, "the event belongs to a server");
     (void)hipDeviceSynchronize();
     free_event(ev);
     return PE_OK;
@@ -346,32 +560,33 @@ pe_status_t pe_metric(pe_event_t ev, const double* theta0_dev, const double* fd_
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
     if (!theta0_dev || !g_dev) return fail(PE_ERR_ARG, "theta0 and g must be device pointers");
     if (flags & ~1) return fail(PE_ERR_ARG, "unknown metric flags");
-    PE_HIP(pe::launch_metric(ev, theta0_dev, fd_step_dev, flags, g_dev, as_stream(stream)));
-    return PE_OK;
+    return run_metric(std::vector<MetricArg>(1, metric_arg(ev, theta0_dev, fd_step_dev, flags, g_dev)),
+                      as_stream(stream));
 }
 
 pe_status_t pe_draw(pe_event_t ev, const double* theta0_dev, const double* g_dev, uint64_t seed, uint32_t stream_id,
                     int64_t n, double* theta_dev, double* logq_dev, double* logprior_dev, void* stream) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
-    if (n < 0 || n > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "n must be in 0..2^30");
+    pe_status_t s = check_n(n);
+    if (s != PE_OK) return s;
     if (!theta0_dev || !g_dev) return fail(PE_ERR_ARG, "theta0 and g must be device pointers");
     if (n > 0 && (!theta_dev || !logq_dev || !logprior_dev)) return fail(PE_ERR_ARG, "output pointers are NULL");
-    PE_HIP(pe::launch_draw(ev, theta0_dev, g_dev, seed, stream_id, n, theta_dev, logq_dev, logprior_dev,
-                           as_stream(stream)));
-    return PE_OK;
+    return run_draw(std::vector<DrawArg>(1, draw_arg(ev, theta0_dev, g_dev, seed, stream_id, n, theta_dev, logq_dev,
+                                                     logprior_dev)),
+                    as_stream(stream));
 }
 
 pe_status_t pe_loglike_batch(pe_event_t ev, const double* theta_dev, int64_t n, int32_t precision,
                              double* loglike_dev, double* aux_dev, void* stream) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
-    if (n < 0 || n > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "n must be in 0..2^30");
-    if (precision != PE_PREC_FP64 && precision != PE_PREC_SPLIT) return fail(PE_ERR_ARG, "bad precision");
+    pe_status_t s = check_n(n);
+    if (s == PE_OK) s = check_precision(precision);
+    if (s != PE_OK) return s;
     if (n == 0) return PE_OK;
     if (!theta_dev || !loglike_dev) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
-    pe_status_t s = ensure_ws(ev, n);
-    if (s != PE_OK) return s;
-    std::vector<pe::EvDev> one(1, make_evdev(ev, theta_dev, n, loglike_dev, aux_dev));
-    return run_batch(ev->self, one, ev->desc.n_det, precision, as_stream(stream));
+    if ((s = ensure_ws(ev, n)) != PE_OK) return s;
+    return run_loglike(std::vector<EvDev>(1, loglike_arg(ev, theta_dev, n, loglike_dev, aux_dev)), precision,
+                       as_stream(stream));
 }
 
 pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t* events, const double* const* theta_dev,
@@ -379,31 +594,75 @@ pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t* events, const d
                              double* const* aux_dev, void* stream) {
     if (n_events < 0 || n_events > 65535 || (n_events > 0 && (!events || !theta_dev || !n || !loglike_dev)))
         return fail(PE_ERR_ARG, "bad batch arrays (n_events must be in 0..65535)");
-    if (precision != PE_PREC_FP64 && precision != PE_PREC_SPLIT) return fail(PE_ERR_ARG, "bad precision");
-    // One batch per detector count; its descriptor buffers are those of its
-    // first event, so two calls race only where they share an event.
-    std::vector<pe::EvDev> cls[PE_MAX_DET + 1];
-    pe_event_s* owner[PE_MAX_DET + 1] = {};
+    pe_status_t s = check_precision(precision);
+    if (s != PE_OK) return s;
+    std::vector<EvDev> v;
     for (int e = 0; e < n_events; ++e) {
         pe_event_s* ev = events[e];
         if (!ev) return fail(PE_ERR_ARG, "event is NULL");
         for (int f = 0; f < e; ++f)
             if (events[f] == ev) return fail(PE_ERR_ARG, "an event appears twice in the batch");
-        if (n[e] < 0 || n[e] > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "n must be in 0..2^30");
+        if ((s = check_n(n[e])) != PE_OK) return s;
         if (n[e] == 0) continue;
         if (!theta_dev[e] || !loglike_dev[e]) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
-        pe_status_t s = ensure_ws(ev, n[e]);
-        if (s != PE_OK) return s;
-        const int nd = ev->desc.n_det;
-        if (!owner[nd]) owner[nd] = ev;
-        cls[nd].push_back(make_evdev(ev, theta_dev[e], n[e], loglike_dev[e], aux_dev ? aux_dev[e] : nullptr));
+        if ((s = ensure_ws(ev, n[e])) != PE_OK) return s;
+        v.push_back(loglike_arg(ev, theta_dev[e], n[e], loglike_dev[e], aux_dev ? aux_dev[e] : nullptr));
     }
-    for (int nd = 1; nd <= PE_MAX_DET; ++nd) {
-        if (cls[nd].empty()) continue;
-        pe_status_t s = run_batch(owner[nd]->self, cls[nd], nd, precision, as_stream(stream));
-        if (s != PE_OK) return s;
+    return run_loglike(v, precision, as_stream(stream));
+}
+
+pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t* items, int32_t stages, int32_t precision,
+                         void* stream) {
+    if (n_items < 0 || n_items > 65535 || (n_items > 0 && !items))
+        return fail(PE_ERR_ARG, "bad items (n_items must be in 0..65535)");
+    if (stages & ~PE_STAGE_ALL) return fail(PE_ERR_ARG, "unknown stages");
+    pe_status_t s = check_precision(precision);
+    if (s != PE_OK) return s;
+    std::vector<PrepArg> vp;
+    std::vector<MetricArg> vm;
+    std::vector<DrawArg> vd;
+    std::vector<EvDev> vl;
+    std::vector<WeightArg> vw;
+    for (int e = 0; e < n_items; ++e) {
+        const pe_batch_item_t& it = items[e];
+        pe_event_s* ev = it.ev;
+        if (!ev) return fail(PE_ERR_ARG, "item " + std::to_string(e) + ": event is NULL");
+        for (int f = 0; f < e; ++f)
+            if (items[f].ev == ev) return fail(PE_ERR_ARG, "an event appears twice in the batch");
+        if ((s = check_n(it.n)) != PE_OK) return s;
+        if (stages & PE_STAGE_PREP) {
+            if (!it.data || !it.psd) return fail(PE_ERR_ARG, "item " + std::to_string(e) + ": data and psd needed");
+            vp.push_back(prep_arg(ev, it.data, it.psd));
+        }
+        if (stages & PE_STAGE_METRIC) {
+            if (!it.theta0 || !it.g) return fail(PE_ERR_ARG, "item " + std::to_string(e) + ": theta0 and g needed");
+            if (it.metric_flags & ~1) return fail(PE_ERR_ARG, "unknown metric flags");
+            vm.push_back(metric_arg(ev, it.theta0, it.fd_step, it.metric_flags, it.g));
+        }
+        if (stages & PE_STAGE_DRAW) {
+            if (!it.theta0 || !it.g || (it.n > 0 && (!it.theta || !it.logq || !it.logprior)))
+                return fail(PE_ERR_ARG, "item " + std::to_string(e) + ": draw pointers needed");
+            vd.push_back(draw_arg(ev, it.theta0, it.g, it.seed, it.stream_id, it.n, it.theta, it.logq, it.logprior));
+        }
+        if ((stages & PE_STAGE_LOGLIKE) && it.n > 0) {
+            if (!it.theta || !it.loglike)
+                return fail(PE_ERR_ARG, "item " + std::to_string(e) + ": theta and loglike needed");
+            if ((s = ensure_ws(ev, it.n)) != PE_OK) return s;
+            vl.push_back(loglike_arg(ev, it.theta, it.n, it.loglike, it.aux));
+        }
+        if (stages & PE_STAGE_WEIGHTS) {
+            if (!it.stats || (it.n > 0 && (!it.loglike || !it.logprior || !it.logq)))
+                return fail(PE_ERR_ARG, "item " + std::to_string(e) + ": weight pointers needed");
+            WeightArg w = {it.loglike, it.logprior, it.logq, it.n, it.w, it.stats};
+            vw.push_back(w);
+        }
     }
-    return PE_OK;
+    hipStream_t st = as_stream(stream);
+    if ((s = run_prep(vp, st)) != PE_OK) return s;
+    if ((s = run_metric(vm, st)) != PE_OK) return s;
+    if ((s = run_draw(vd, st)) != PE_OK) return s;
+    if ((s = run_loglike(vl, precision, st)) != PE_OK) return s;
+    return run_weights(vw, st);
 }
 
 pe_status_t pe_weights_ess(const double* loglike_dev, const double* logprior_dev, const double* logq_dev, int64_t n,
@@ -411,29 +670,28 @@ pe_status_t pe_weights_ess(const double* loglike_dev, const double* logprior_dev
     if (n < 0) return fail(PE_ERR_ARG, "n must be >= 0");
     if (!stats_dev) return fail(PE_ERR_ARG, "stats must be a device pointer");
     if (n > 0 && (!loglike_dev || !logprior_dev || !logq_dev)) return fail(PE_ERR_ARG, "inputs are NULL");
-    PE_HIP(pe::launch_weights(loglike_dev, logprior_dev, logq_dev, n, w_dev, stats_dev, as_stream(stream)));
-    return PE_OK;
+    WeightArg w = {loglike_dev, logprior_dev, logq_dev, n, w_dev, stats_dev};
+    return run_weights(std::vector<WeightArg>(1, w), as_stream(stream));
 }
 
 pe_status_t pe_waveform(const pe_event_desc_t* desc, const double* theta_dev, const void* psd_dev, double* h_dev,
                         double* snr2_dev, void* stream) {
-    pe_event_desc_t d2;
     if (!desc) return fail(PE_ERR_ARG, "desc is NULL");
-    d2 = *desc;
+    pe_event_desc_t d2 = *desc;
     if (d2.params == PE_PARAMS_4D && !(d2.amp0 > 0.0)) d2.amp0 = 1.0;
     pe_status_t s = validate_desc(&d2);
     if (s != PE_OK) return s;
     if (!theta_dev || !h_dev) return fail(PE_ERR_ARG, "theta and h must be device pointers");
     if (snr2_dev && !psd_dev) return fail(PE_ERR_ARG, "snr2 needs the PSD");
-    pe::EvConst ec;
+    EvConst ec;
     build_const(*desc, ec);
     const int64_t nb = (ec.K + 255) / 256;
-    double* scratch = nullptr;
-    if ((s = dalloc(&scratch, (size_t)(32 + nb))) != PE_OK) return s;
+    char* scratch = nullptr;
+    if ((s = dalloc_bytes(&scratch, sizeof(double) * (size_t)(32 + nb))) != PE_OK) return s;
     hipStream_t st = as_stream(stream);
-    hipError_t e = pe::launch_waveform(ec, desc->psd_dtype, theta_dev, psd_dev, h_dev, snr2_dev, scratch, st);
+    hipError_t e = launch_waveform(ec, desc->psd_dtype, theta_dev, psd_dev, h_dev, snr2_dev, (double*)scratch, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    dfree(scratch);
+    dfree_bytes(scratch);
     if (e != hipSuccess) return fail(PE_ERR_HIP, std::string("waveform: ") + hipGetErrorString(e));
     return PE_OK;
 }
@@ -442,7 +700,7 @@ pe_status_t pe_rng_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int32_
                             void* stream) {
     if (n < 0 || npairs < 0 || npairs > 64) return fail(PE_ERR_ARG, "bad n or npairs");
     if (n * npairs > 0 && !u_dev) return fail(PE_ERR_ARG, "u must be a device pointer");
-    PE_HIP(pe::launch_uniforms(seed, stream_id, n, npairs, u_dev, as_stream(stream)));
+    PE_HIP(launch_uniforms(seed, stream_id, n, npairs, u_dev, as_stream(stream)));
     return PE_OK;
 }
 

@@ -47,6 +47,20 @@ __device__ __forceinline__ void pn_coeffs(double eta, double delta, double chis,
              (-25150083775.0 / 3048192.0 + 26804935.0 / 6048.0 * eta - 1985.0 / 48.0 * eta2) * delta * chia;
 }
 
+// Slot of x in a batch's prefix offsets: the last e with off[e] <= x (events
+// with nothing to do have off[e] == off[e+1] and are skipped).
+__device__ __forceinline__ int find_slot(const int64_t* __restrict__ off, int n, int64_t x) {
+    int lo = 0, hi = n;  // off[lo] <= x < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // Per-draw source quantities.
 struct Src {
     double M, eta, delta, chis, chia, tc, phic;

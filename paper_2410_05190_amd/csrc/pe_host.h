@@ -1,0 +1,69 @@
+// pe_host.h -- host-side runtime shared by the C ABI (pe_api.hip) and the
+// serving loop (pe_server.hip): errors, event memory, batch stage runners.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "pe_internal.h"
+
+namespace pe {
+
+// Records msg as the calling thread's last error and returns s.
+pe_status_t fail(pe_status_t s, const std::string& msg);
+
+#define PE_HIP(call)                                                                                      \
+    do {                                                                                                  \
+        hipError_t _e = (call);                                                                           \
+        if (_e != hipSuccess) return ::pe::fail(PE_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// Sequential carving of one device range into 256-byte aligned buffers; with a
+// NULL base it only measures.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(char* b) : base(b) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) / 256 * 256;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += (count ? count : 1) * sizeof(T);
+        return p;
+    }
+    size_t size() const { return (off + 255) / 256 * 256; }
+};
+
+pe_status_t validate_desc(const pe_event_desc_t* d);
+void build_const(const pe_event_desc_t& d, EvConst& ec);
+pe_status_t dalloc_bytes(char** p, size_t bytes);
+void dfree_bytes(char*& p);
+
+// Event memory: bytes of the tables and of the workspace for npad draws, and
+// the footprint of an event sized for max_draws (one range).
+size_t tables_bytes(const pe_event_desc_t& d);
+size_t ws_bytes(const pe_event_desc_t& d, int64_t npad);
+size_t event_footprint(const pe_event_desc_t& d, int64_t max_draws);
+int64_t npad_for(int64_t n);
+
+// New event laid out in `mem` (a range of event_footprint bytes, not owned)
+// or in its own allocations (mem NULL). Does not prepare the tables.
+pe_status_t new_event(const pe_event_desc_t* desc, char* mem, int64_t max_draws, pe_event_s** out);
+void free_event(pe_event_s* ev);
+pe_status_t ensure_ws(pe_event_s* ev, int64_t n);
+
+// Argument records of the batched stages.
+PrepArg prep_arg(const pe_event_s* ev, const void* data, const void* psd);
+MetricArg metric_arg(const pe_event_s* ev, const double* theta0, const double* steps, int flags, double* g);
+DrawArg draw_arg(const pe_event_s* ev, const double* theta0, const double* g, uint64_t seed, uint32_t stream_id,
+                 int64_t n, double* theta, double* logq, double* logprior);
+EvDev loglike_arg(const pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux);
+
+// Stage runners: upload the records to the stream's area and queue the launches.
+pe_status_t run_prep(const std::vector<PrepArg>& v, hipStream_t st);
+pe_status_t run_metric(const std::vector<MetricArg>& v, hipStream_t st);
+pe_status_t run_draw(const std::vector<DrawArg>& v, hipStream_t st);
+pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t st);
+pe_status_t run_weights(const std::vector<WeightArg>& v, hipStream_t st);
+
+}  // namespace pe

@@ -68,17 +68,59 @@ constexpr int kMetricMaxDp = PE_MAX_DIM + 1;
 constexpr int kMetricNG = kMetricMaxDp * (kMetricMaxDp + 1) / 2;  // 78 >= 66
 constexpr int kMetricBlocks = 512;
 
-// Device-side plan of one event in a batch (written by the batch kernels).
+// Device-side plan of one event in a log-likelihood batch.
 struct EvPlan {
     int n_active;  // live draws
-    int kmax;      // largest cut among them
+    int kmax;      // bound on their cuts: upper edge of the highest non-empty cut bucket
     int fine;      // bins per chunk (a multiple of kBlk)
     int n_fine;    // chunks over [0, kmax)
     int n_groups;  // groups of chunks = partials per draw and detector
     int tiles;     // tiles of kTile live draws
 };
 
-// Device-side descriptor of one event in a batch.
+// ---------------------------------------------------------------------------
+// Batched launches. Every stage of the path runs as one set of launches over a
+// list of events: a header {ne, ...} and per-event argument records in device
+// memory, plus prefix offsets of the flattened index space (draws, bins or
+// blocks). Kernels read the counts from device memory and walk the flattened
+// space with grid-stride loops, so one launch shape serves any batch (and a
+// captured graph can be replayed on new contents).
+// ---------------------------------------------------------------------------
+struct PrepArg {
+    EvConst ec;
+    const void *data, *psd;
+    int data_f32, psd_f32;
+    Rec32 *rec32;
+    Rec64 *rec64;
+    double *pw, *pfx, *seg;
+    int *status;
+};
+
+struct MetricArg {
+    EvConst ec;
+    const Rec64 *tab;
+    const double *pw;
+    double *mws;
+    const double *theta0, *steps;
+    double *g;
+    int flags, pad;
+};
+
+struct DrawArg {
+    EvConst ec;
+    const double *theta0, *g;
+    double *chol;
+    int *status;
+    uint64_t seed;
+    uint32_t stream_id, pad;
+    int64_t n;
+    double *theta, *logq, *logprior;
+};
+
+// One event of a log-likelihood batch. flags select the stages it takes part
+// in: kLlPrologue (support, cut buckets, plan, per-draw coefficients) and
+// kLlFinalize (combine the partials, ln L); the hot loop evaluates the draw
+// tiles [tile_lo, tile_hi) of its plan (the whole event: 0, INT_MAX).
 struct EvDev {
     EvConst ec;
     const Rec32 *rec32;
@@ -90,20 +132,33 @@ struct EvDev {
     EvPlan *plan;
     int64_t npad;
     int max_groups;  // partial capacity / npad
+    int tile_lo, tile_hi;
+    int flags;
     const double *theta;
     int64_t n;
     double *loglike, *aux;
 };
 
-// Device buffers of a batch: descriptors, draw offsets [ne+1], item offsets
-// [ne+1], header {item counter, item total}.
-struct BatchDev {
-    EvDev *evs = nullptr;
-    int64_t *doff = nullptr;
-    int64_t *ioff = nullptr;
-    int *hdr = nullptr;
-    int cap = 0;
+constexpr int kLlPrologue = 1;
+constexpr int kLlFinalize = 2;
+
+struct WeightArg {
+    const double *ll, *lp, *lq;
+    int64_t n;
+    double *w, *stats;
 };
+
+// Header of a batch in device memory.
+struct BatchHdr {
+    int ne;          // events
+    int items;       // hot-loop work items (written by the planning kernel)
+    int next;        // hot-loop queue counter
+    int pad;
+    int64_t total;   // flattened size (draws, bins or weight blocks)
+    int64_t total2;  // second flattened size (weights: draws)
+};
+
+constexpr int kWBlock = 4096;  // draws per block of the weights reduction (256 threads x 16)
 
 }  // namespace pe
 
@@ -116,6 +171,7 @@ struct pe_event_s {
     double *pw = nullptr;   // [n_det][K] 4 df f^(-7/3) / S
     double *pfx = nullptr;  // [n_det][K+1] exclusive prefix of pw
     int *status = nullptr;  // device status word
+    double *mws = nullptr;  // metric + draw workspace
     // per-draw workspace
     int64_t npad = 0;
     int *kc_all = nullptr;  // [npad] cut per draw, -1 out of support
@@ -123,27 +179,42 @@ struct pe_event_s {
     int *idx = nullptr;
     pe::EvPlan *plan = nullptr;
     int64_t partial_cap = 0;  // double2 entries per detector
-    pe::BatchDev self;        // one-event batch of pe_loglike_batch
-    double *coef = nullptr;  // [kNCoef][npad]
-    int *kcut = nullptr;     // [npad]
-    double *resp = nullptr;  // [2*n_det][npad] Re/Im R_d
-    double *hh = nullptr;    // [npad] (h|h)
+    double *coef = nullptr;   // [kNCoef][npad]
+    int *kcut = nullptr;      // [npad]
+    double *resp = nullptr;   // [2*n_det][npad] Re/Im R_d
+    double *hh = nullptr;     // [npad] (h|h)
     double2 *partial = nullptr;
-    // metric + draw workspace
-    double *mws = nullptr;
+    // memory: the tables and the workspace each in one range; owned by the
+    // event (hipMalloc) unless a server placed the event in its slab
+    char *tab_mem = nullptr;
+    char *ws_mem = nullptr;
+    bool own_mem = true;
 };
 
 namespace pe {
 
-// kernel launchers (pe_kernels.hip)
-hipError_t launch_prep(const pe_event_s *ev, const void *data, const void *psd, hipStream_t st);
-hipError_t launch_batch(const BatchDev &b, int ne, int n_det, int64_t max_draws, int precision, hipStream_t st);
-hipError_t launch_metric(const pe_event_s *ev, const double *theta0, const double *steps, int flags, double *g,
-                         hipStream_t st);
-hipError_t launch_draw(const pe_event_s *ev, const double *theta0, const double *g, uint64_t seed, uint32_t stream_id,
-                       int64_t n, double *theta, double *logq, double *logprior, hipStream_t st);
-hipError_t launch_weights(const double *ll, const double *lp, const double *lq, int64_t n, double *w, double *stats,
-                          hipStream_t st);
+// Kinds of batch areas.
+enum AreaKind { kAreaPrep = 0, kAreaMetric = 1, kAreaDraw = 2, kAreaLoglike = 3, kAreaWeights = 4, kAreaKinds = 5 };
+
+// Device pointers into an uploaded batch area.
+struct BatchPtrs {
+    BatchHdr *hdr;
+    void *args;       // argument records
+    int64_t *off;     // [ne + 1] prefix offsets of the flattened space
+    int64_t *off2;    // [ne + 1] second offsets (weights: draws; loglike: finalize draws)
+    double *scratch;  // kind-specific scratch
+};
+
+// kernel launchers (pe_kernels.hip, pe_loglike.hip). Each takes the batch's
+// device pointers, the number of events, the flattened size(s) known on the
+// host (for the grid) and the stream.
+hipError_t launch_prep_batch(const BatchPtrs &b, int ne, int64_t total_bins, int data_f32, int psd_f32,
+                             hipStream_t st);
+hipError_t launch_metric_batch(const BatchPtrs &b, int ne, hipStream_t st);
+hipError_t launch_draw_batch(const BatchPtrs &b, int ne, int64_t total_draws, hipStream_t st);
+hipError_t launch_loglike_batch(const BatchPtrs &b, int ne, int64_t prologue_draws, int64_t finalize_draws,
+                                int precision, hipStream_t st);
+hipError_t launch_weights_batch(const BatchPtrs &b, int ne, int64_t total_blocks, int64_t total_draws, hipStream_t st);
 hipError_t launch_waveform(const EvConst &ec, int data_psd_dtype, const double *theta, const void *psd, double *h,
                            double *snr2, double *scratch, hipStream_t st);
 hipError_t launch_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int npairs, double *u, hipStream_t st);

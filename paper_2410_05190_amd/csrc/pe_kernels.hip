@@ -1,26 +1,38 @@
 // pe_kernels.hip -- HIP kernels of the likelihood engine for gfx950 (MI355X).
 //
-// Hot path, per event and batch of draws:
-//   k_prep, k_seg_*        event tables and the (h|h) prefix sums (once per event)
-//   (pe_loglike.hip)       per-draw scalars, the hot loop and ln L for batches of
-//                          draws of one or many events
-//   k_weights              log-sum-exp weights and ESS (Eqs. 5-6)
-// plus the metric (finite-difference Fisher matrix) and the Gaussian draws.
+// Every stage runs as one set of launches over a batch of events (argument
+// records and offsets in device memory; grid-stride loops over the flattened
+// bins, draws or blocks):
+//   k_prep, k_seg_*        event tables and the (h|h) prefix sums
+//   k_metric_*             finite-difference Fisher matrix at the proposal centre
+//   k_cholesky, k_draw     the Gaussian proposal's draws, log q and log prior
+//   (pe_loglike.hip)       per-draw scalars, the hot loop and ln L
+//   k_w_*                  log-sum-exp weights and ESS (Eqs. 5-6)
+// plus the waveform of one point (injections) and the proposal's uniforms.
 #include <math.h>
 
 #include "pe_device.h"
 
 namespace pe {
 
+// Grid of a grid-stride launch over `total` items of `per` threads each.
+static unsigned stride_grid(int64_t total, int per = 256, unsigned cap = 16384) {
+    int64_t g = (total + per - 1) / per;
+    if (g < 1) g = 1;
+    return (unsigned)(g < (int64_t)cap ? g : cap);
+}
+static unsigned event_grid(int ne, unsigned cap = 4096) {
+    return (unsigned)(ne < 1 ? 1 : (ne < (int)cap ? ne : cap));
+}
+
 // ===========================================================================
 // event preparation
 // ===========================================================================
 template <typename DT, typename ST>
-__global__ __launch_bounds__(256) void k_prep(EvConst ev, const DT* __restrict__ data, const ST* __restrict__ psd,
-                                              Rec32* __restrict__ rec32, Rec64* __restrict__ rec64,
-                                              double* __restrict__ pw, int* __restrict__ status) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ev.K) return;
+__device__ __forceinline__ void prep_bin(const PrepArg& A, int64_t k) {
+    const EvConst& ev = A.ec;
+    const DT* __restrict__ data = (const DT*)A.data;
+    const ST* __restrict__ psd = (const ST*)A.psd;
     const double f = grid_f(ev, k);
     const double x = cbrt(f);
     const double x2 = x * x;
@@ -46,93 +58,126 @@ __global__ __launch_bounds__(256) void k_prep(EvConst ev, const DT* __restrict__
             double al = atan2(wi, wr) * kInvTwoPi;
             if (al < 0.0) al += 1.0;
             r32.w[d] = make_float2((float)hypot(wr, wi), (float)al);
-            pw[o] = 4.0 * ev.df / (S * f76 * f76);
+            A.pw[o] = 4.0 * ev.df / (S * f76 * f76);
         } else {
             r64.w[d] = make_double2(0.0, 0.0);
             r32.w[d] = make_float2(0.0f, 0.0f);
         }
     }
-    rec32[k] = r32;
-    rec64[k] = r64;
-    if (bad) atomicOr(status, bad);
+    A.rec32[k] = r32;
+    A.rec64[k] = r64;
+    if (bad) atomicOr(A.status, bad);
 }
 
-// Exclusive prefix C_k = sum_{j<k} pw_j (k = 0..K) per detector, in two passes
-// over kScanSeg contiguous segments: segment sums, then each segment adds the
-// sums before it (fixed order) and scans its bins in coalesced 256-wide tiles
-// (wave shuffle scan + LDS across the four waves).
-__global__ __launch_bounds__(256) void k_seg_sums(const double* __restrict__ pw, int64_t K, int64_t seg,
-                                                  double* __restrict__ tot) {
+// Bins of every event of the batch (one storage class per launch); the
+// kTabPad records past each table's end are zeroed here too.
+template <typename DT, typename ST>
+__global__ __launch_bounds__(256) void k_prep(const BatchHdr* __restrict__ hdr, const PrepArg* __restrict__ args,
+                                              const int64_t* __restrict__ koff) {
+    const int ne = hdr->ne;
+    const int64_t total = koff[ne];
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+         gid += (int64_t)gridDim.x * blockDim.x) {
+        const int e = find_slot(koff, ne, gid);
+        const PrepArg& A = args[e];
+        const int64_t k = gid - koff[e];
+        if (k < A.ec.K) {
+            prep_bin<DT, ST>(A, k);
+        } else {
+            Rec32 z32 = {};
+            Rec64 z64 = {};
+            A.rec32[k] = z32;
+            A.rec64[k] = z64;
+        }
+    }
+}
+
+// Exclusive prefix C_k = sum_{j<k} pw_j (k = 0..K) per event and detector, in
+// two passes over kScanSeg contiguous segments: segment sums, then each
+// segment adds the sums before it (fixed order) and scans its bins in
+// coalesced 256-wide tiles (wave shuffle scan + LDS across the four waves).
+// Grid: (kScanSeg, PE_MAX_DET, events).
+__global__ __launch_bounds__(256) void k_seg_sums(const BatchHdr* __restrict__ hdr,
+                                                  const PrepArg* __restrict__ args) {
     __shared__ double sh[4];
+    const int ne = hdr->ne;
     const int d = blockIdx.y, b = blockIdx.x;
-    const double* a = pw + (int64_t)d * K;
-    const int64_t k0 = (int64_t)b * seg;
-    const int64_t k1 = min(k0 + seg, K);
-    double s = 0.0;
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) s += a[k];
+    for (int e = blockIdx.z; e < ne; e += gridDim.z) {
+        const PrepArg& A = args[e];
+        if (d >= A.ec.n_det) continue;
+        const int64_t K = A.ec.K;
+        const int64_t seg = (K + kScanSeg - 1) / kScanSeg;
+        const double* a = A.pw + (int64_t)d * K;
+        const int64_t k0 = (int64_t)b * seg;
+        const int64_t k1 = min(k0 + seg, K);
+        double s = 0.0;
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) s += a[k];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) tot[d * kScanSeg + b] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) A.seg[d * kScanSeg + b] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        __syncthreads();
+    }
 }
 
-__global__ __launch_bounds__(256) void k_seg_scan(const double* __restrict__ pw, int64_t K, int64_t seg,
-                                                  const double* __restrict__ tot, double* __restrict__ pfx) {
+__global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ hdr,
+                                                  const PrepArg* __restrict__ args) {
     __shared__ double sh[4];
+    const int ne = hdr->ne;
     const int d = blockIdx.y, b = blockIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const double* a = pw + (int64_t)d * K;
-    double* o = pfx + (int64_t)d * (K + 1);
-    double carry = 0.0;
-    for (int i = 0; i < b; ++i) carry += tot[d * kScanSeg + i];
-    const int64_t k0 = (int64_t)b * seg;
-    const int64_t k1 = min(k0 + seg, K);
-    for (int64_t base = k0; base < k1; base += 256) {
-        const int64_t k = base + threadIdx.x;
-        const double v = (k < k1) ? a[k] : 0.0;
-        double inc = v;
+    for (int e = blockIdx.z; e < ne; e += gridDim.z) {
+        const PrepArg& A = args[e];
+        if (d >= A.ec.n_det) continue;
+        const int64_t K = A.ec.K;
+        const int64_t seg = (K + kScanSeg - 1) / kScanSeg;
+        const double* a = A.pw + (int64_t)d * K;
+        double* o = A.pfx + (int64_t)d * (K + 1);
+        double carry = 0.0;
+        for (int i = 0; i < b; ++i) carry += A.seg[d * kScanSeg + i];
+        const int64_t k0 = (int64_t)b * seg;
+        const int64_t k1 = min(k0 + seg, K);
+        for (int64_t base = k0; base < k1; base += 256) {
+            const int64_t k = base + threadIdx.x;
+            const double v = (k < k1) ? a[k] : 0.0;
+            double inc = v;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const double u = __shfl_up(inc, off);
-            if (lane >= off) inc += u;
+            for (int off = 1; off < 64; off <<= 1) {
+                const double u = __shfl_up(inc, off);
+                if (lane >= off) inc += u;
+            }
+            double exc = __shfl_up(inc, 1);
+            if (lane == 0) exc = 0.0;
+            if (lane == 63) sh[w] = inc;
+            __syncthreads();
+            double woff = 0.0;
+            for (int i = 0; i < w; ++i) woff += sh[i];
+            const double tile = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+            __syncthreads();
+            if (k < k1) o[k] = carry + (woff + exc);
+            carry += tile;
         }
-        double exc = __shfl_up(inc, 1);
-        if (lane == 0) exc = 0.0;
-        if (lane == 63) sh[w] = inc;
-        __syncthreads();
-        double woff = 0.0;
-        for (int i = 0; i < w; ++i) woff += sh[i];
-        const double tile = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-        __syncthreads();
-        if (k < k1) o[k] = carry + (woff + exc);
-        carry += tile;
+        if (b == kScanSeg - 1 && threadIdx.x == 0) o[K] = carry;
     }
-    if (b == gridDim.x - 1 && threadIdx.x == 0) o[K] = carry;
 }
 
-hipError_t launch_prep(const pe_event_s* ev, const void* data, const void* psd, hipStream_t st) {
-    const EvConst& ec = ev->ec;
-    const unsigned nb = (unsigned)((ec.K + 255) / 256);
-    const bool c64 = ev->desc.data_dtype == PE_C64, f32 = ev->desc.psd_dtype == PE_F32;
-    if (c64 && f32)
-        k_prep<float, float><<<nb, 256, 0, st>>>(ec, (const float*)data, (const float*)psd, ev->rec32, ev->rec64,
-                                                  ev->pw, ev->status);
-    else if (c64)
-        k_prep<float, double><<<nb, 256, 0, st>>>(ec, (const float*)data, (const double*)psd, ev->rec32, ev->rec64,
-                                                   ev->pw, ev->status);
-    else if (f32)
-        k_prep<double, float><<<nb, 256, 0, st>>>(ec, (const double*)data, (const float*)psd, ev->rec32, ev->rec64,
-                                                   ev->pw, ev->status);
+hipError_t launch_prep_batch(const BatchPtrs& b, int ne, int64_t total_bins, int data_f32, int psd_f32,
+                             hipStream_t st) {
+    if (ne <= 0) return hipSuccess;
+    const PrepArg* args = (const PrepArg*)b.args;
+    const unsigned nb = stride_grid(total_bins);
+    if (data_f32 && psd_f32)
+        k_prep<float, float><<<nb, 256, 0, st>>>(b.hdr, args, b.off);
+    else if (data_f32)
+        k_prep<float, double><<<nb, 256, 0, st>>>(b.hdr, args, b.off);
+    else if (psd_f32)
+        k_prep<double, float><<<nb, 256, 0, st>>>(b.hdr, args, b.off);
     else
-        k_prep<double, double><<<nb, 256, 0, st>>>(ec, (const double*)data, (const double*)psd, ev->rec32,
-                                                    ev->rec64, ev->pw, ev->status);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t seg = (ec.K + kScanSeg - 1) / kScanSeg;
-    double* tot = ev->mws + kMwsScan;
-    k_seg_sums<<<dim3(kScanSeg, ec.n_det), 256, 0, st>>>(ev->pw, ec.K, seg, tot);
-    k_seg_scan<<<dim3(kScanSeg, ec.n_det), 256, 0, st>>>(ev->pw, ec.K, seg, tot, ev->pfx);
+        k_prep<double, double><<<nb, 256, 0, st>>>(b.hdr, args, b.off);
+    const dim3 g(kScanSeg, PE_MAX_DET, event_grid(ne, 64));
+    k_seg_sums<<<g, 256, 0, st>>>(b.hdr, args);
+    k_seg_scan<<<g, 256, 0, st>>>(b.hdr, args);
     return hipGetLastError();
 }
 
@@ -166,51 +211,60 @@ __device__ __forceinline__ void default_steps(const EvConst& ev, const double* t
 }
 
 // Sources of the stencil: index 0 = theta0, 2a+1 / 2a+2 = theta0 +/- step_a.
-__global__ void k_metric_setup(EvConst ev, const double* __restrict__ theta0, const double* __restrict__ steps_in,
-                               double* __restrict__ mws) {
+// One workgroup per event.
+__global__ __launch_bounds__(32) void k_metric_setup(const BatchHdr* __restrict__ hdr,
+                                                     const MetricArg* __restrict__ args) {
+    const int ne = hdr->ne;
     const int t = threadIdx.x;
-    const int D = ev.dim;
     __shared__ double st[PE_MAX_DIM];
-    double th0[PE_MAX_DIM];
+    for (int e = blockIdx.x; e < ne; e += gridDim.x) {
+        const MetricArg& A = args[e];
+        const EvConst& ev = A.ec;
+        const int D = ev.dim;
+        double* mws = A.mws;
+        double th0[PE_MAX_DIM];
 #pragma unroll
-    for (int a = 0; a < PE_MAX_DIM; ++a) th0[a] = (a < D) ? theta0[a] : 0.0;
-    if (t == 0) {
-        double s[PE_MAX_DIM];
-        if (steps_in)
-            for (int a = 0; a < D; ++a) s[a] = steps_in[a];
-        else
-            default_steps(ev, th0, s);
-        for (int a = 0; a < D; ++a) {
-            st[a] = s[a];
-            mws[kMwsSteps + a] = s[a];
-            const double tp = th0[a] + s[a], tm = th0[a] - s[a];
-            mws[kMwsDen + a] = (tp - th0[a]) + (th0[a] - tm);
+        for (int a = 0; a < PE_MAX_DIM; ++a) th0[a] = (a < D) ? A.theta0[a] : 0.0;
+        if (t == 0) {
+            double s[PE_MAX_DIM];
+            if (A.steps)
+                for (int a = 0; a < D; ++a) s[a] = A.steps[a];
+            else
+                default_steps(ev, th0, s);
+            for (int a = 0; a < D; ++a) {
+                st[a] = s[a];
+                mws[kMwsSteps + a] = s[a];
+                const double tp = th0[a] + s[a], tm = th0[a] - s[a];
+                mws[kMwsDen + a] = (tp - th0[a]) + (th0[a] - tm);
+            }
+            Src s0;
+            source_from_theta(ev, th0, s0);
+            mws[kMwsKcut] = (double)kcut_of(ev, s0.fisco);
         }
-        Src s0;
-        source_from_theta(ev, th0, s0);
-        mws[kMwsKcut] = (double)kcut_of(ev, s0.fisco);
-    }
-    __syncthreads();
-    if (t >= 2 * D + 1) return;
-    double th[PE_MAX_DIM];
+        __syncthreads();
+        if (t < 2 * D + 1) {
+            double th[PE_MAX_DIM];
 #pragma unroll
-    for (int a = 0; a < PE_MAX_DIM; ++a) th[a] = th0[a];
-    if (t > 0) {
-        const int a = (t - 1) / 2;
-        th[a] = ((t - 1) % 2 == 0) ? th0[a] + st[a] : th0[a] - st[a];
-    }
-    Src s;
-    source_from_theta(ev, th, s);
-    PhaseCoef pc;
-    phase_coeffs(s, pc);
-    double* o = mws + kMwsSrc + (int64_t)t * kMetricSrcStride;
-    for (int a = 0; a < 8; ++a) o[a] = pc.A[a];
-    o[8] = pc.B5;
-    o[9] = pc.B6;
-    for (int d = 0; d < PE_MAX_DET; ++d) {
-        o[10 + d] = s.rre[d];
-        o[14 + d] = s.rim[d];
-        o[18 + d] = s.tc + s.dt[d];
+            for (int a = 0; a < PE_MAX_DIM; ++a) th[a] = th0[a];
+            if (t > 0) {
+                const int a = (t - 1) / 2;
+                th[a] = ((t - 1) % 2 == 0) ? th0[a] + st[a] : th0[a] - st[a];
+            }
+            Src s;
+            source_from_theta(ev, th, s);
+            PhaseCoef pc;
+            phase_coeffs(s, pc);
+            double* o = mws + kMwsSrc + (int64_t)t * kMetricSrcStride;
+            for (int a = 0; a < 8; ++a) o[a] = pc.A[a];
+            o[8] = pc.B5;
+            o[9] = pc.B6;
+            for (int d = 0; d < PE_MAX_DET; ++d) {
+                o[10 + d] = s.rre[d];
+                o[14 + d] = s.rim[d];
+                o[18 + d] = s.tc + s.dt[d];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -229,14 +283,16 @@ __device__ __forceinline__ void model_unit(const double* __restrict__ src, int d
 }
 
 // Columns: coordinates 0..D-1 by central differences, except the phase column
-// (index DP-1 in 4-D, 10 in 11-D), which is i h(theta0).
+// (index DP-1 in 4-D, 10 in 11-D), which is i h(theta0). Block b of kMetricBlocks
+// strides over the bins below the frozen cut.
 template <int NDET, int D, int DP>
-__global__ __launch_bounds__(256) void k_metric_partial(EvConst ev, const Rec64* __restrict__ tab,
-                                                        const double* __restrict__ pw, double* __restrict__ mws) {
+__device__ __forceinline__ void metric_partial(const MetricArg& A) {
     constexpr int NG = DP * (DP + 1) / 2;
     constexpr int PH = (DP == D) ? D - 1 : D;  // phase column
+    const double* mws = A.mws;
     const int64_t kc = (int64_t)mws[kMwsKcut];
     const double* src = mws + kMwsSrc;
+    const int64_t K = A.ec.K;
     double den[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) den[a] = mws[kMwsDen + a];
@@ -244,10 +300,10 @@ __global__ __launch_bounds__(256) void k_metric_partial(EvConst ev, const Rec64*
 #pragma unroll
     for (int q = 0; q < NG; ++q) G[q] = 0.0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < kc; k += (int64_t)gridDim.x * blockDim.x) {
-        const Rec64 r = tab[k];
+        const Rec64 r = A.tab[k];
 #pragma unroll
         for (int d = 0; d < NDET; ++d) {
-            const double p = pw[(int64_t)d * ev.K + k];
+            const double p = A.pw[(int64_t)d * K + k];
             double ur[DP], ui[DP];
 #pragma unroll
             for (int a = 0; a < DP; ++a) {
@@ -275,7 +331,7 @@ __global__ __launch_bounds__(256) void k_metric_partial(EvConst ev, const Rec64*
         }
     }
     // wave butterfly, then the four waves through LDS
-    __shared__ double sh[4][NG];
+    __shared__ double sh[4][kMetricNG];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
@@ -286,141 +342,155 @@ __global__ __launch_bounds__(256) void k_metric_partial(EvConst ev, const Rec64*
     }
     __syncthreads();
     for (int q = threadIdx.x; q < NG; q += blockDim.x)
-        mws[kMwsPart + (int64_t)blockIdx.x * kMetricNG + q] = (sh[0][q] + sh[1][q]) + (sh[2][q] + sh[3][q]);
-}
-
-__global__ __launch_bounds__(128) void k_metric_final(EvConst ev, int DP, int flags, const double* __restrict__ mws,
-                                                      double* __restrict__ g) {
-    __shared__ double Gs[kMetricNG];
-    const int NG = DP * (DP + 1) / 2;
-    const int t = threadIdx.x;
-    if (t < NG) {
-        double acc[8];
-        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-        for (int b = 0; b < kMetricBlocks; ++b) acc[b & 7] += mws[kMwsPart + (int64_t)b * kMetricNG + t];
-        for (int w = 4; w > 0; w >>= 1)
-            for (int q = 0; q < w; ++q) acc[q] += acc[q + w];
-        Gs[t] = acc[0];
-    }
+        A.mws[kMwsPart + (int64_t)blockIdx.x * kMetricNG + q] = (sh[0][q] + sh[1][q]) + (sh[2][q] + sh[3][q]);
     __syncthreads();
-    if (t != 0) return;
-    const int D = ev.dim;
-    const int PH = (DP == D) ? D - 1 : D;
-    double M[kMetricMaxDp][kMetricMaxDp];
-    int q = 0;
-    for (int a = 0; a < DP; ++a)
-        for (int b = a; b < DP; ++b) {
-            M[a][b] = M[b][a] = Gs[q];
-            ++q;
+}
+
+// Grid (kMetricBlocks, events): each event dispatches on its detector count
+// and parameter set (uniform across the workgroup).
+__global__ __launch_bounds__(256) void k_metric_partial(const BatchHdr* __restrict__ hdr,
+                                                        const MetricArg* __restrict__ args) {
+    const int ne = hdr->ne;
+    for (int e = blockIdx.y; e < ne; e += gridDim.y) {
+        const MetricArg& A = args[e];
+        const bool four = A.ec.params == PE_PARAMS_4D;
+        switch (A.ec.n_det) {
+            case 1: four ? metric_partial<1, 4, 5>(A) : metric_partial<1, 11, 11>(A); break;
+            case 2: four ? metric_partial<2, 4, 5>(A) : metric_partial<2, 11, 11>(A); break;
+            case 3: four ? metric_partial<3, 4, 5>(A) : metric_partial<3, 11, 11>(A); break;
+            default: four ? metric_partial<4, 4, 5>(A) : metric_partial<4, 11, 11>(A); break;
         }
-    if (ev.phase == PE_PHASE_MARG) {
-        const double gpp = M[PH][PH];
-        double P[kMetricMaxDp][kMetricMaxDp];
-        for (int a = 0; a < DP; ++a)
-            for (int b = 0; b < DP; ++b)
-                P[a][b] = (a == PH || b == PH) ? 0.0 : M[a][b] - M[a][PH] * M[PH][b] / gpp;
-        for (int a = 0; a < DP; ++a)
-            for (int b = 0; b < DP; ++b) M[a][b] = P[a][b];
     }
-    double reg[PE_MAX_DIM];
-    if (ev.params == PE_PARAMS_4D) {
-        reg[0] = 0.0;
-        reg[1] = 12.0 / 0.0625;
-        reg[2] = 3.0 / (ev.chi_max * ev.chi_max);
-        reg[3] = 0.0;
-    } else {
-        const double p2 = 3.0 / (kPi * kPi);  // 12 / (2 pi)^2
-        const double p1 = 12.0 / (kPi * kPi);
-        reg[0] = 0.0;
-        reg[1] = 12.0;
-        reg[2] = reg[3] = 3.0 / (ev.chi_max * ev.chi_max);
-        reg[4] = p2;
-        reg[5] = reg[6] = reg[7] = p1;
-        reg[8] = 12.0 / (ev.dl_max * ev.dl_max);
-        reg[9] = 0.0;
-        reg[10] = p2;
-    }
-    for (int a = 0; a < D; ++a)
-        for (int b = 0; b < D; ++b) g[a * D + b] = M[a][b] + ((a == b && !(flags & 1)) ? reg[a] : 0.0);
 }
 
-template <int NDET>
-static hipError_t launch_metric_nd(const pe_event_s* ev, double* mws, hipStream_t st) {
-    if (ev->ec.params == PE_PARAMS_4D)
-        k_metric_partial<NDET, 4, 5><<<kMetricBlocks, 256, 0, st>>>(ev->ec, ev->rec64, ev->pw, mws);
-    else
-        k_metric_partial<NDET, 11, 11><<<kMetricBlocks, 256, 0, st>>>(ev->ec, ev->rec64, ev->pw, mws);
-    return hipGetLastError();
+// Fixed-order sum of the block partials, phase projection (marginalised
+// likelihood) and prior regularisation; one workgroup per event.
+__global__ __launch_bounds__(128) void k_metric_final(const BatchHdr* __restrict__ hdr,
+                                                      const MetricArg* __restrict__ args) {
+    __shared__ double Gs[kMetricNG];
+    const int ne = hdr->ne;
+    const int t = threadIdx.x;
+    for (int e = blockIdx.x; e < ne; e += gridDim.x) {
+        const MetricArg& A = args[e];
+        const EvConst& ev = A.ec;
+        const int D = ev.dim;
+        const int DP = (ev.params == PE_PARAMS_4D) ? 5 : 11;
+        const int NG = DP * (DP + 1) / 2;
+        if (t < NG) {
+            double acc[8];
+            for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+            for (int b = 0; b < kMetricBlocks; ++b) acc[b & 7] += A.mws[kMwsPart + (int64_t)b * kMetricNG + t];
+            for (int w = 4; w > 0; w >>= 1)
+                for (int q = 0; q < w; ++q) acc[q] += acc[q + w];
+            Gs[t] = acc[0];
+        }
+        __syncthreads();
+        if (t == 0) {
+            const int PH = (DP == D) ? D - 1 : D;
+            double M[kMetricMaxDp][kMetricMaxDp];
+            int q = 0;
+            for (int a = 0; a < DP; ++a)
+                for (int b = a; b < DP; ++b) {
+                    M[a][b] = M[b][a] = Gs[q];
+                    ++q;
+                }
+            if (ev.phase == PE_PHASE_MARG) {
+                const double gpp = M[PH][PH];
+                double P[kMetricMaxDp][kMetricMaxDp];
+                for (int a = 0; a < DP; ++a)
+                    for (int b = 0; b < DP; ++b)
+                        P[a][b] = (a == PH || b == PH) ? 0.0 : M[a][b] - M[a][PH] * M[PH][b] / gpp;
+                for (int a = 0; a < DP; ++a)
+                    for (int b = 0; b < DP; ++b) M[a][b] = P[a][b];
+            }
+            double reg[PE_MAX_DIM];
+            if (ev.params == PE_PARAMS_4D) {
+                reg[0] = 0.0;
+                reg[1] = 12.0 / 0.0625;
+                reg[2] = 3.0 / (ev.chi_max * ev.chi_max);
+                reg[3] = 0.0;
+            } else {
+                const double p2 = 3.0 / (kPi * kPi);  // 12 / (2 pi)^2
+                const double p1 = 12.0 / (kPi * kPi);
+                reg[0] = 0.0;
+                reg[1] = 12.0;
+                reg[2] = reg[3] = 3.0 / (ev.chi_max * ev.chi_max);
+                reg[4] = p2;
+                reg[5] = reg[6] = reg[7] = p1;
+                reg[8] = 12.0 / (ev.dl_max * ev.dl_max);
+                reg[9] = 0.0;
+                reg[10] = p2;
+            }
+            for (int a = 0; a < D; ++a)
+                for (int b = 0; b < D; ++b) A.g[a * D + b] = M[a][b] + ((a == b && !(A.flags & 1)) ? reg[a] : 0.0);
+        }
+        __syncthreads();
+    }
 }
 
-hipError_t launch_metric(const pe_event_s* ev, const double* theta0, const double* steps, int flags, double* g,
-                         hipStream_t st) {
-    const EvConst& ec = ev->ec;
-    k_metric_setup<<<1, 32, 0, st>>>(ec, theta0, steps, ev->mws);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    switch (ec.n_det) {
-        case 1: e = launch_metric_nd<1>(ev, ev->mws, st); break;
-        case 2: e = launch_metric_nd<2>(ev, ev->mws, st); break;
-        case 3: e = launch_metric_nd<3>(ev, ev->mws, st); break;
-        default: e = launch_metric_nd<4>(ev, ev->mws, st); break;
-    }
-    if (e != hipSuccess) return e;
-    const int DP = (ec.params == PE_PARAMS_4D) ? 5 : 11;
-    k_metric_final<<<1, 128, 0, st>>>(ec, DP, flags, ev->mws, g);
+hipError_t launch_metric_batch(const BatchPtrs& b, int ne, hipStream_t st) {
+    if (ne <= 0) return hipSuccess;
+    const MetricArg* args = (const MetricArg*)b.args;
+    k_metric_setup<<<event_grid(ne), 32, 0, st>>>(b.hdr, args);
+    k_metric_partial<<<dim3(kMetricBlocks, event_grid(ne, 64)), 256, 0, st>>>(b.hdr, args);
+    k_metric_final<<<event_grid(ne), 128, 0, st>>>(b.hdr, args);
     return hipGetLastError();
 }
 
 // ===========================================================================
 // draws
 // ===========================================================================
-__global__ void k_cholesky(int D, const double* __restrict__ g, double* __restrict__ chol, int* __restrict__ status) {
-    if (threadIdx.x != 0) return;
-    double L[PE_MAX_DIM * PE_MAX_DIM];
-    int ok = 1;
-    for (int a = 0; a < D * D; ++a) L[a] = 0.0;
-    for (int i = 0; i < D && ok; ++i)
-        for (int j = 0; j <= i; ++j) {
-            double s = g[i * D + j];
-            for (int k = 0; k < j; ++k) s -= L[i * D + k] * L[j * D + k];
-            if (i == j) {
-                if (!(s > 0.0)) {
-                    ok = 0;
-                    break;
+// Cholesky factor of every event's metric, one thread per event.
+__global__ __launch_bounds__(64) void k_cholesky(const BatchHdr* __restrict__ hdr, const DrawArg* __restrict__ args) {
+    const int ne = hdr->ne;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+        const DrawArg& A = args[e];
+        const int D = A.ec.dim;
+        const double* g = A.g;
+        double L[PE_MAX_DIM * PE_MAX_DIM];
+        int ok = 1;
+        for (int a = 0; a < D * D; ++a) L[a] = 0.0;
+        for (int i = 0; i < D && ok; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double s = g[i * D + j];
+                for (int k = 0; k < j; ++k) s -= L[i * D + k] * L[j * D + k];
+                if (i == j) {
+                    if (!(s > 0.0)) {
+                        ok = 0;
+                        break;
+                    }
+                    L[i * D + i] = sqrt(s);
+                } else {
+                    L[i * D + j] = s / L[j * D + j];
                 }
-                L[i * D + i] = sqrt(s);
-            } else {
-                L[i * D + j] = s / L[j * D + j];
             }
-        }
-    double logdet = 0.0;
-    for (int a = 0; a < D * D; ++a) chol[a] = L[a];
-    if (ok)
-        for (int a = 0; a < D; ++a) logdet += log(L[a * D + a]);
-    chol[PE_MAX_DIM * PE_MAX_DIM] = logdet;
-    chol[PE_MAX_DIM * PE_MAX_DIM + 1] = ok ? 1.0 : 0.0;
-    if (!ok) atomicOr(status, kStSingular);
+        double logdet = 0.0;
+        for (int a = 0; a < D * D; ++a) A.chol[a] = L[a];
+        if (ok)
+            for (int a = 0; a < D; ++a) logdet += log(L[a * D + a]);
+        A.chol[PE_MAX_DIM * PE_MAX_DIM] = logdet;
+        A.chol[PE_MAX_DIM * PE_MAX_DIM + 1] = ok ? 1.0 : 0.0;
+        if (!ok) atomicOr(A.status, kStSingular);
+    }
 }
 
-__global__ __launch_bounds__(256) void k_draw(EvConst ev, const double* __restrict__ theta0,
-                                              const double* __restrict__ chol, uint64_t seed, uint32_t stream_id,
-                                              int64_t n, double* __restrict__ theta, double* __restrict__ logq,
-                                              double* __restrict__ logprior) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ void draw_one(const DrawArg& A, int64_t i) {
+    const EvConst& ev = A.ec;
+    const double* __restrict__ chol = A.chol;
+    const int64_t n = A.n;
     const int D = ev.dim;
     double th0[PE_MAX_DIM];
-    for (int a = 0; a < D; ++a) th0[a] = theta0[a];
+    for (int a = 0; a < D; ++a) th0[a] = A.theta0[a];
     if (chol[PE_MAX_DIM * PE_MAX_DIM + 1] == 0.0) {
-        for (int a = 0; a < D; ++a) theta[(int64_t)a * n + i] = th0[a];
-        logq[i] = 0.0;
-        logprior[i] = -INFINITY;
+        for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th0[a];
+        A.logq[i] = 0.0;
+        A.logprior[i] = -INFINITY;
         return;
     }
     double z[PE_MAX_DIM + 1];
     for (int j = 0; 2 * j < D; ++j) {
         double ua, ub, sn, cs;
-        block_uniforms(seed, stream_id, (uint64_t)i, (uint32_t)j, ua, ub);
+        block_uniforms(A.seed, A.stream_id, (uint64_t)i, (uint32_t)j, ua, ub);
         const double rad = sqrt(-2.0 * log(ua));
         sincos_turns(ub >= 1.0 ? 0.0 : ub, sn, cs);  // 2 pi ub
         z[2 * j] = rad * cs;
@@ -444,7 +514,7 @@ __global__ __launch_bounds__(256) void k_draw(EvConst ev, const double* __restri
         k0[p] = floor(v / per[p]);
         th[pidx[p]] = v - per[p] * k0[p];
     }
-    for (int a = 0; a < D; ++a) theta[(int64_t)a * n + i] = th[a];
+    for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th[a];
     // log-density of the wrapped Gaussian: images k in {-1,0,1}^p, whitened
     // offset L^T (x - theta0) = z + L^T s with s = (k - k0) P on the periodic rows
     const int nimg = (np == 0) ? 1 : 27;
@@ -469,27 +539,37 @@ __global__ __launch_bounds__(256) void k_draw(EvConst ev, const double* __restri
     }
     double acc = 0.0;
     for (int m = 0; m < nimg; ++m) acc += exp(lq[m] - mx);
-    logq[i] = mx + log(acc) + chol[PE_MAX_DIM * PE_MAX_DIM] - 0.5 * D * log(kTwoPi);
+    A.logq[i] = mx + log(acc) + chol[PE_MAX_DIM * PE_MAX_DIM] - 0.5 * D * log(kTwoPi);
     Src src;
     const int ok = source_from_theta(ev, th, src);
     double lp = -INFINITY;
     if (ok) lp = (ev.params == PE_PARAMS_4D) ? 0.0 : log(cos(th[5])) + log(sin(th[6])) + 2.0 * log(th[8]);
-    logprior[i] = lp;
+    A.logprior[i] = lp;
 }
 
-hipError_t launch_draw(const pe_event_s* ev, const double* theta0, const double* g, uint64_t seed, uint32_t stream_id,
-                       int64_t n, double* theta, double* logq, double* logprior, hipStream_t st) {
-    double* chol = ev->mws + kMwsChol;
-    k_cholesky<<<1, 64, 0, st>>>(ev->ec.dim, g, chol, ev->status);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n == 0) return e;
-    k_draw<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(ev->ec, theta0, chol, seed, stream_id, n, theta, logq,
-                                                        logprior);
+__global__ __launch_bounds__(256) void k_draw(const BatchHdr* __restrict__ hdr, const DrawArg* __restrict__ args,
+                                              const int64_t* __restrict__ doff) {
+    const int ne = hdr->ne;
+    const int64_t total = doff[ne];
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+         gid += (int64_t)gridDim.x * blockDim.x) {
+        const int e = find_slot(doff, ne, gid);
+        draw_one(args[e], gid - doff[e]);
+    }
+}
+
+hipError_t launch_draw_batch(const BatchPtrs& b, int ne, int64_t total_draws, hipStream_t st) {
+    if (ne <= 0) return hipSuccess;
+    const DrawArg* args = (const DrawArg*)b.args;
+    k_cholesky<<<stride_grid(ne, 64), 64, 0, st>>>(b.hdr, args);
+    k_draw<<<stride_grid(total_draws), 256, 0, st>>>(b.hdr, args, b.off);
     return hipGetLastError();
 }
 
 // ===========================================================================
-// weights and ESS (one workgroup; fixed-order reductions)
+// weights and ESS: ln w = ln L + ln prior - ln q; per block of kWBlock draws
+// its max and the sums of exp(ln w - max) and exp(2 (ln w - max)); per event
+// the blocks combined in a fixed order; then the normalised weights.
 // ===========================================================================
 __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
     const double t = s + x;
@@ -500,83 +580,140 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
     s = t;
 }
 
-__global__ __launch_bounds__(1024) void k_weights(const double* __restrict__ ll, const double* __restrict__ lp,
-                                                  const double* __restrict__ lq, int64_t n, double* __restrict__ w,
-                                                  double* __restrict__ stats) {
-    __shared__ double s1[1024], s2[1024];
-    __shared__ long long sc[1024];
-    const int t = threadIdx.x;
-    double m = -INFINITY;
-    long long cnt = 0;
-    for (int64_t i = t; i < n; i += 1024) {
-        const double l = ll[i] + lp[i] - lq[i];
-        if (isfinite(l)) {
-            ++cnt;
-            m = fmax(m, l);
-        }
-    }
-    s1[t] = m;
-    sc[t] = cnt;
+__device__ __forceinline__ double block_max256(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if (t < o) {
-            s1[t] = fmax(s1[t], s1[t + o]);
-            sc[t] += sc[t + o];
-        }
-        __syncthreads();
-    }
-    const double mx = s1[0];
-    const long long nin = sc[0];
+    const double r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
     __syncthreads();
-    if (nin == 0) {
-        if (w)
-            for (int64_t i = t; i < n; i += 1024) w[i] = 0.0;
-        if (t == 0) {
-            stats[0] = 0.0;
-            stats[1] = -INFINITY;
-            stats[2] = -INFINITY;
-            stats[3] = 0.0;
-        }
-        return;
-    }
-    double a = 0.0, ac = 0.0, b = 0.0, bc = 0.0;
-    for (int64_t i = t; i < n; i += 1024) {
-        const double l = ll[i] + lp[i] - lq[i];
-        if (isfinite(l)) {
-            const double e = exp(l - mx);
-            neumaier(a, ac, e);
-            neumaier(b, bc, e * e);
-        }
-    }
-    s1[t] = a + ac;
-    s2[t] = b + bc;
+    return r;
+}
+
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if (t < o) {
-            s1[t] += s1[t + o];
-            s2[t] += s2[t + o];
+    const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+// part[b] = {max, sum exp(l - max), sum exp(2 (l - max)), finite count}
+__global__ __launch_bounds__(256) void k_w_part(const BatchHdr* __restrict__ hdr, const WeightArg* __restrict__ args,
+                                                const int64_t* __restrict__ boff, double4* __restrict__ part) {
+    __shared__ double sh[4];
+    const int ne = hdr->ne;
+    const int64_t nblk = boff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(boff, ne, b);
+        const WeightArg& A = args[e];
+        const int64_t i0 = (b - boff[e]) * kWBlock;
+        double l[kWBlock / 256];
+        double m = -INFINITY, cnt = 0.0;
+#pragma unroll
+        for (int j = 0; j < kWBlock / 256; ++j) {
+            const int64_t i = i0 + threadIdx.x + 256 * j;
+            double v = -INFINITY;
+            if (i < A.n) v = A.ll[i] + A.lp[i] - A.lq[i];
+            if (!isfinite(v)) v = -INFINITY;
+            l[j] = v;
+            if (v > -INFINITY) {
+                m = fmax(m, v);
+                cnt += 1.0;
+            }
         }
-        __syncthreads();
-    }
-    const double S1 = s1[0], S2 = s2[0];
-    if (w) {
-        const double inv = 1.0 / S1;
-        for (int64_t i = t; i < n; i += 1024) {
-            const double l = ll[i] + lp[i] - lq[i];
-            w[i] = isfinite(l) ? exp(l - mx) * inv : 0.0;
+        const double M = block_max256(m, sh);
+        double s1 = 0.0, s2 = 0.0;
+        if (M > -INFINITY) {
+#pragma unroll
+            for (int j = 0; j < kWBlock / 256; ++j) {
+                if (l[j] > -INFINITY) {
+                    const double x = exp(l[j] - M);
+                    s1 += x;
+                    s2 += x * x;
+                }
+            }
         }
-    }
-    if (t == 0) {
-        stats[0] = S1 * S1 / S2;
-        stats[1] = mx + log(S1) - log((double)n);
-        stats[2] = mx;
-        stats[3] = (double)nin;
+        const double S1 = block_sum256(s1, sh);
+        const double S2 = block_sum256(s2, sh);
+        const double C = block_sum256(cnt, sh);
+        if (threadIdx.x == 0) part[b] = make_double4(M, S1, S2, C);
     }
 }
 
-hipError_t launch_weights(const double* ll, const double* lp, const double* lq, int64_t n, double* w, double* stats,
-                          hipStream_t st) {
-    k_weights<<<1, 1024, 0, st>>>(ll, lp, lq, n, w, stats);
+// Per event: combine its blocks in index order; stats and {max, 1/S1} for the
+// normalisation.
+__global__ __launch_bounds__(256) void k_w_final(const BatchHdr* __restrict__ hdr, const WeightArg* __restrict__ args,
+                                                 const int64_t* __restrict__ boff, const double4* __restrict__ part,
+                                                 double2* __restrict__ fin) {
+    __shared__ double sh[4];
+    const int ne = hdr->ne;
+    for (int e = blockIdx.x; e < ne; e += gridDim.x) {
+        const WeightArg& A = args[e];
+        const int64_t b0 = boff[e], b1 = boff[e + 1];
+        double m = -INFINITY;
+        for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) m = fmax(m, part[b].x);
+        const double M = block_max256(m, sh);
+        double a = 0.0, ac = 0.0, q = 0.0, qc = 0.0, cnt = 0.0;
+        if (M > -INFINITY) {
+            for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) {
+                const double4 p = part[b];
+                cnt += p.w;
+                if (p.x > -INFINITY) {
+                    const double r = exp(p.x - M);
+                    neumaier(a, ac, p.y * r);
+                    neumaier(q, qc, p.z * (r * r));
+                }
+            }
+        }
+        const double S1 = block_sum256(a + ac, sh);
+        const double S2 = block_sum256(q + qc, sh);
+        const double nin = block_sum256(cnt, sh);
+        if (threadIdx.x == 0) {
+            if (nin == 0.0) {
+                A.stats[0] = 0.0;
+                A.stats[1] = -INFINITY;
+                A.stats[2] = -INFINITY;
+                A.stats[3] = 0.0;
+                fin[e] = make_double2(0.0, 0.0);
+            } else {
+                A.stats[0] = S1 * S1 / S2;
+                A.stats[1] = M + log(S1) - log((double)A.n);
+                A.stats[2] = M;
+                A.stats[3] = nin;
+                fin[e] = make_double2(M, 1.0 / S1);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_w_norm(const BatchHdr* __restrict__ hdr, const WeightArg* __restrict__ args,
+                                                const int64_t* __restrict__ doff, const double2* __restrict__ fin) {
+    const int ne = hdr->ne;
+    const int64_t total = doff[ne];
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+         gid += (int64_t)gridDim.x * blockDim.x) {
+        const int e = find_slot(doff, ne, gid);
+        const WeightArg& A = args[e];
+        if (!A.w) continue;
+        const int64_t i = gid - doff[e];
+        const double l = A.ll[i] + A.lp[i] - A.lq[i];
+        const double2 f = fin[e];
+        A.w[i] = (isfinite(l) && f.y > 0.0) ? exp(l - f.x) * f.y : 0.0;
+    }
+}
+
+hipError_t launch_weights_batch(const BatchPtrs& b, int ne, int64_t total_blocks, int64_t total_draws,
+                                hipStream_t st) {
+    if (ne <= 0) return hipSuccess;
+    const WeightArg* args = (const WeightArg*)b.args;
+    double4* part = (double4*)b.scratch;
+    double2* fin = (double2*)(part + (total_blocks > 0 ? total_blocks : 1));
+    k_w_part<<<stride_grid(total_blocks, 1, 8192), 256, 0, st>>>(b.hdr, args, b.off, part);
+    k_w_final<<<event_grid(ne), 256, 0, st>>>(b.hdr, args, b.off, part, fin);
+    k_w_norm<<<stride_grid(total_draws), 256, 0, st>>>(b.hdr, args, b.off2, fin);
     return hipGetLastError();
 }
 

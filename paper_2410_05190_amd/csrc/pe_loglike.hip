@@ -1,10 +1,10 @@
 // pe_loglike.hip -- log-likelihoods of batches of draws of one or many events
-// (Eq. 3), eight launches per batch whatever the number of events.
+// (Eq. 3), seven launches per batch whatever the number of events.
 //
-//   k_b_reset     clear the events' cut histograms, plans and the item queue
+//   k_b_reset     clear the cut histograms and plans of the events starting here
 //   k_b_support   support mask, ISCO cut and cut bucket of every draw
 //   k_b_plan      per event: bucket offsets, live count, frequency decomposition
-//   k_b_items     per event: offset of its work items in the batch's queue
+//   k_b_items     offsets of every event's work items in the batch's queue
 //   k_b_scatter   live draws into their cut buckets
 //   k_b_coeffs    per live draw: phase polynomial, delays, responses, (h|h)
 //   k_b_split / k_b_f64   hot loop: persistent workgroups take (event, tile of
@@ -14,25 +14,15 @@
 //   k_b_finalize  fixed-order combine of the group partials, ln L
 //
 // An event's decomposition (chunk length, groups) is planned on the device from
-// its own live draws only (their largest cut and their number), so its results
-// do not depend on the other events of the batch.
+// its own live draws only (their largest cut bucket and their number), so its
+// results do not depend on the other events of the batch, nor on how its tiles
+// are spread over launches. Events of any detector count share one queue: each
+// item dispatches on its event's count (uniform across the workgroup).
 #include <math.h>
 
 #include "pe_device.h"
 
 namespace pe {
-
-__device__ __forceinline__ int find_slot(const int64_t* __restrict__ off, int n, int64_t x) {
-    int lo = 0, hi = n;  // off[lo] <= x < off[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= x)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
 
 // Loads from read-only device memory. The hot loop reaches its tables through
 // pointers held in device memory, so the compiler cannot prove on its own that
@@ -61,13 +51,16 @@ __device__ __forceinline__ int bucket_shift(int64_t K) {
     return s;
 }
 
-__global__ __launch_bounds__(256) void k_b_reset(const EvDev* __restrict__ evs, int* __restrict__ hdr) {
-    const EvDev& E = evs[blockIdx.y];
-    E.hist[blockIdx.x * 256 + threadIdx.x] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        EvPlan z = {};
-        *E.plan = z;
-        if (blockIdx.y == 0) hdr[0] = 0;  // item counter
+__global__ __launch_bounds__(256) void k_b_reset(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs) {
+    const int ne = hdr->ne;
+    for (int e = blockIdx.y; e < ne; e += gridDim.y) {
+        const EvDev& E = evs[e];
+        if (!(E.flags & kLlPrologue)) continue;
+        E.hist[blockIdx.x * 256 + threadIdx.x] = 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            EvPlan z = {};
+            *E.plan = z;
+        }
     }
 }
 
@@ -78,139 +71,161 @@ __device__ __forceinline__ void gather_theta(const EvDev& E, int64_t i, double t
 
 // Support mask, ISCO cut and cut bucket. Buckets run from the longest cut down,
 // so a wave of the hot loop holds draws whose cuts differ by less than one bucket.
-__global__ __launch_bounds__(256) void k_b_support(const EvDev* __restrict__ evs, const int64_t* __restrict__ doff,
-                                                   int ne) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= doff[ne]) return;
-    const int e = find_slot(doff, ne, gid);
-    const EvDev& E = evs[e];
-    const int64_t i = gid - doff[e];
-    double th[PE_MAX_DIM];
-    gather_theta(E, i, th);
-    Src s;
-    if (!source_from_theta(E.ec, th, s)) {
-        E.kc_all[i] = -1;
-        E.loglike[i] = -INFINITY;
-        if (E.aux) {
-            E.aux[3 * i] = 0.0;
-            E.aux[3 * i + 1] = 0.0;
-            E.aux[3 * i + 2] = 0.0;
+__global__ __launch_bounds__(256) void k_b_support(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                   const int64_t* __restrict__ poff) {
+    const int ne = hdr->ne;
+    const int64_t total = poff[ne];
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+         gid += (int64_t)gridDim.x * blockDim.x) {
+        const int e = find_slot(poff, ne, gid);
+        const EvDev& E = evs[e];
+        const int64_t i = gid - poff[e];
+        double th[PE_MAX_DIM];
+        gather_theta(E, i, th);
+        Src s;
+        if (!source_from_theta(E.ec, th, s)) {
+            E.kc_all[i] = -1;
+            E.loglike[i] = -INFINITY;
+            if (E.aux) {
+                E.aux[3 * i] = 0.0;
+                E.aux[3 * i + 1] = 0.0;
+                E.aux[3 * i + 2] = 0.0;
+            }
+            continue;
         }
-        return;
+        const int kc = (int)kcut_of(E.ec, s.fisco);
+        E.kc_all[i] = kc;
+        atomicAdd(&E.hist[(kBuckets - 1) - (kc >> bucket_shift(E.ec.K))], 1);
     }
-    const int kc = (int)kcut_of(E.ec, s.fisco);
-    E.kc_all[i] = kc;
-    atomicAdd(&E.hist[(kBuckets - 1) - (kc >> bucket_shift(E.ec.K))], 1);
-    atomicMax(&E.plan->kmax, kc);
 }
 
 // One workgroup per event: exclusive scan of the bucket counts in place (4 per
 // thread), the live count, and the frequency decomposition of the hot loop:
 // ~16k work items for the event alone (groups a power of two up to 64), at least
-// 1024 bins per group, 8 chunks per group spread over [0, largest cut), chunk
-// length a multiple of kBlk.
-__global__ __launch_bounds__(1024) void k_b_plan(const EvDev* __restrict__ evs) {
+// 1024 bins per group, 8 chunks per group spread over [0, kmax), chunk length a
+// multiple of kBlk. kmax is the upper edge of the highest non-empty cut bucket:
+// a bound on every live cut that follows from the event's own draws.
+__global__ __launch_bounds__(1024) void k_b_plan(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs) {
     __shared__ int sh[1024];
-    const EvDev& E = evs[blockIdx.x];
-    int* hist = E.hist;
+    __shared__ int first;
+    const int ne = hdr->ne;
     const int t = threadIdx.x;
-    const int a0 = hist[4 * t], a1 = hist[4 * t + 1], a2 = hist[4 * t + 2], a3 = hist[4 * t + 3];
-    const int c = a0 + a1 + a2 + a3;
-    sh[t] = c;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = (t >= off) ? sh[t - off] : 0;
+    for (int e = blockIdx.x; e < ne; e += gridDim.x) {
+        const EvDev& E = evs[e];
+        if (!(E.flags & kLlPrologue)) continue;
+        int* hist = E.hist;
+        if (t == 0) first = kBuckets;
+        const int a0 = hist[4 * t], a1 = hist[4 * t + 1], a2 = hist[4 * t + 2], a3 = hist[4 * t + 3];
+        const int c = a0 + a1 + a2 + a3;
+        sh[t] = c;
         __syncthreads();
-        sh[t] += v;
+        if (c > 0) atomicMin(&first, 4 * t + (a0 > 0 ? 0 : a1 > 0 ? 1 : a2 > 0 ? 2 : 3));
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int v = (t >= off) ? sh[t - off] : 0;
+            __syncthreads();
+            sh[t] += v;
+            __syncthreads();
+        }
+        const int ex = sh[t] - c;
+        hist[4 * t] = ex;
+        hist[4 * t + 1] = ex + a0;
+        hist[4 * t + 2] = ex + a0 + a1;
+        hist[4 * t + 3] = ex + a0 + a1 + a2;
+        if (t == 1023) {
+            EvPlan p = {};
+            p.n_active = sh[1023];
+            p.tiles = (p.n_active + kTile - 1) / kTile;
+            if (p.n_active > 0) {
+                const int sh_b = bucket_shift(E.ec.K);
+                const int64_t top = ((int64_t)(kBuckets - first) << sh_b);  // one past the top bucket's last cut
+                p.kmax = (int)(top < E.ec.K ? top : E.ec.K);
+                const int want = (16384 + p.tiles - 1) / p.tiles;
+                int G = 1;
+                while (G < want && G < 64) G <<= 1;
+                const int by_bins = max(1, p.kmax / 1024);
+                G = min(G, min(by_bins, E.max_groups));
+                const int target = 8 * G;
+                int fine = ((p.kmax + target - 1) / target + kBlk - 1) / kBlk * kBlk;
+                fine = max(fine, kBlk);
+                p.n_groups = G;
+                p.fine = fine;
+                p.n_fine = (p.kmax + fine - 1) / fine;
+            } else {
+                p.fine = kBlk;
+            }
+            *E.plan = p;
+        }
         __syncthreads();
     }
-    const int ex = sh[t] - c;
-    hist[4 * t] = ex;
-    hist[4 * t + 1] = ex + a0;
-    hist[4 * t + 2] = ex + a0 + a1;
-    hist[4 * t + 3] = ex + a0 + a1 + a2;
-    if (t != 1023) return;
-    EvPlan p = *E.plan;
-    p.n_active = sh[1023];
-    p.tiles = (p.n_active + kTile - 1) / kTile;
-    if (p.n_active == 0 || p.kmax == 0) {
-        p.n_groups = 0;
-        p.fine = kBlk;
-        p.n_fine = 0;
-    } else {
-        const int want = (16384 + p.tiles - 1) / p.tiles;
-        int G = 1;
-        while (G < want && G < 64) G <<= 1;
-        const int by_bins = max(1, p.kmax / 1024);
-        G = min(G, min(by_bins, E.max_groups));
-        const int target = 8 * G;
-        int fine = ((p.kmax + target - 1) / target + kBlk - 1) / kBlk * kBlk;
-        fine = max(fine, kBlk);
-        p.n_groups = G;
-        p.fine = fine;
-        p.n_fine = (p.kmax + fine - 1) / fine;
-    }
-    *E.plan = p;
 }
 
-// Offsets of every event's items in the batch queue (items = tiles x groups).
-__global__ void k_b_items(const EvDev* __restrict__ evs, int ne, int64_t* __restrict__ ioff,
-                          int* __restrict__ hdr) {
-    if (threadIdx.x != 0) return;
+// Offsets of every event's items in the batch queue (items = tiles of this
+// launch x groups), the item total, and the queue counter reset.
+__global__ void k_b_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs, int64_t* __restrict__ ioff) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int ne = hdr->ne;
     int64_t acc = 0;
     for (int e = 0; e < ne; ++e) {
         ioff[e] = acc;
         const EvPlan p = *evs[e].plan;
-        acc += (int64_t)p.tiles * p.n_groups;
+        const int lo = max(0, evs[e].tile_lo), hi = min(p.tiles, evs[e].tile_hi);
+        if (hi > lo) acc += (int64_t)(hi - lo) * p.n_groups;
     }
     ioff[ne] = acc;
-    hdr[1] = (int)acc;
+    hdr->items = (int)acc;
+    hdr->next = 0;
 }
 
 // Live draws into their buckets; the order inside a bucket is immaterial.
-__global__ __launch_bounds__(256) void k_b_scatter(const EvDev* __restrict__ evs, const int64_t* __restrict__ doff,
-                                                   int ne) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= doff[ne]) return;
-    const int e = find_slot(doff, ne, gid);
-    const EvDev& E = evs[e];
-    const int64_t i = gid - doff[e];
-    const int kc = E.kc_all[i];
-    if (kc < 0) return;
-    const int pos = atomicAdd(&E.hist[(kBuckets - 1) - (kc >> bucket_shift(E.ec.K))], 1);
-    E.idx[pos] = (int)i;
+__global__ __launch_bounds__(256) void k_b_scatter(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                   const int64_t* __restrict__ poff) {
+    const int ne = hdr->ne;
+    const int64_t total = poff[ne];
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+         gid += (int64_t)gridDim.x * blockDim.x) {
+        const int e = find_slot(poff, ne, gid);
+        const EvDev& E = evs[e];
+        const int64_t i = gid - poff[e];
+        const int kc = E.kc_all[i];
+        if (kc < 0) continue;
+        const int pos = atomicAdd(&E.hist[(kBuckets - 1) - (kc >> bucket_shift(E.ec.K))], 1);
+        E.idx[pos] = (int)i;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_b_coeffs(const EvDev* __restrict__ evs, const int64_t* __restrict__ doff,
-                                                  int ne) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= doff[ne]) return;
-    const int e = find_slot(doff, ne, gid);
-    const EvDev& E = evs[e];
-    const int64_t j = gid - doff[e];
-    if (j >= E.plan->n_active) return;
-    const int64_t i = E.idx[j];
-    const int64_t np = E.npad;
-    double th[PE_MAX_DIM];
-    gather_theta(E, i, th);
-    Src s;
-    source_from_theta(E.ec, th, s);
-    PhaseCoef pc;
-    phase_coeffs(s, pc);
+__global__ __launch_bounds__(256) void k_b_coeffs(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                  const int64_t* __restrict__ poff) {
+    const int ne = hdr->ne;
+    const int64_t total = poff[ne];
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+         gid += (int64_t)gridDim.x * blockDim.x) {
+        const int e = find_slot(poff, ne, gid);
+        const EvDev& E = evs[e];
+        const int64_t j = gid - poff[e];
+        if (j >= E.plan->n_active) continue;
+        const int64_t i = E.idx[j];
+        const int64_t np = E.npad;
+        double th[PE_MAX_DIM];
+        gather_theta(E, i, th);
+        Src s;
+        source_from_theta(E.ec, th, s);
+        PhaseCoef pc;
+        phase_coeffs(s, pc);
 #pragma unroll
-    for (int a = 0; a < 8; ++a) E.coef[(kCoefA + a) * np + j] = pc.A[a];
-    E.coef[kCoefB5 * np + j] = pc.B5;
-    E.coef[kCoefB6 * np + j] = pc.B6;
-    const int64_t kc = E.kc_all[i];
-    E.kcut[j] = (int)kc;
-    double h = 0.0;
-    for (int d = 0; d < E.ec.n_det; ++d) {
-        E.coef[(kCoefTau + d) * np + j] = s.tc + s.dt[d];
-        E.resp[(2 * d) * np + j] = s.rre[d];
-        E.resp[(2 * d + 1) * np + j] = s.rim[d];
-        h += (s.rre[d] * s.rre[d] + s.rim[d] * s.rim[d]) * E.pfx[(int64_t)d * (E.ec.K + 1) + kc];
+        for (int a = 0; a < 8; ++a) E.coef[(kCoefA + a) * np + j] = pc.A[a];
+        E.coef[kCoefB5 * np + j] = pc.B5;
+        E.coef[kCoefB6 * np + j] = pc.B6;
+        const int64_t kc = E.kc_all[i];
+        E.kcut[j] = (int)kc;
+        double h = 0.0;
+        for (int d = 0; d < E.ec.n_det; ++d) {
+            E.coef[(kCoefTau + d) * np + j] = s.tc + s.dt[d];
+            E.resp[(2 * d) * np + j] = s.rre[d];
+            E.resp[(2 * d + 1) * np + j] = s.rim[d];
+            h += (s.rre[d] * s.rre[d] + s.rim[d] * s.rim[d]) * E.pfx[(int64_t)d * (E.ec.K + 1) + kc];
+        }
+        E.hh[j] = h;
     }
-    E.hh[j] = h;
 }
 
 // ---------------------------------------------------------------------------
@@ -285,19 +300,20 @@ struct Item {
 
 // Next item of the batch queue; false when the queue is empty (every workgroup
 // reaches that exit).
-__device__ __forceinline__ bool next_item(int* __restrict__ hdr, const int64_t* __restrict__ ioff, int ne,
+__device__ __forceinline__ bool next_item(BatchHdr* __restrict__ hdr, const int64_t* __restrict__ ioff, int ne,
                                           const EvDev* __restrict__ evs, Item& it) {
     __shared__ int s_item;
     __syncthreads();  // every wave is done with the previous s_item
-    if (threadIdx.x == 0) s_item = atomicAdd(&hdr[0], 1);
+    if (threadIdx.x == 0) s_item = atomicAdd(&hdr->next, 1);
     __syncthreads();
     const int x = __builtin_amdgcn_readfirstlane(s_item);
-    if (x >= hdr[1]) return false;
+    if (x >= hdr->items) return false;
     it.e = find_slot(ioff, ne, x);
     const int loc = x - (int)ioff[it.e];
     const int G = load_const(evs[it.e].plan).n_groups;
-    it.tile = loc / G;
-    it.g = loc - it.tile * G;
+    const int lo = max(0, evs[it.e].tile_lo);
+    it.tile = lo + loc / G;
+    it.g = loc - (loc / G) * G;
     return true;
 }
 
@@ -420,71 +436,83 @@ __device__ __forceinline__ void f64_item(const EvDev& E, const EvPlan& p, int ti
     }
 }
 
-template <int NDET>
-__global__ __launch_bounds__(256) void k_b_split(const EvDev* __restrict__ evs, const int64_t* __restrict__ ioff,
-                                                 int ne, int* __restrict__ hdr) {
+__global__ __launch_bounds__(256) void k_b_split(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                 const int64_t* __restrict__ ioff) {
+    const int ne = hdr->ne;
     Item it;
     while (next_item(hdr, ioff, ne, evs, it)) {
         const EvDev& E = evs[it.e];
         const EvPlan p = load_const(E.plan);
-        split_item<NDET>(E, p, it.tile, it.g);
+        switch (E.ec.n_det) {
+            case 1: split_item<1>(E, p, it.tile, it.g); break;
+            case 2: split_item<2>(E, p, it.tile, it.g); break;
+            case 3: split_item<3>(E, p, it.tile, it.g); break;
+            default: split_item<4>(E, p, it.tile, it.g); break;
+        }
     }
 }
 
-template <int NDET>
-__global__ __launch_bounds__(256) void k_b_f64(const EvDev* __restrict__ evs, const int64_t* __restrict__ ioff,
-                                               int ne, int* __restrict__ hdr) {
+__global__ __launch_bounds__(256) void k_b_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                               const int64_t* __restrict__ ioff) {
+    const int ne = hdr->ne;
     Item it;
     while (next_item(hdr, ioff, ne, evs, it)) {
         const EvDev& E = evs[it.e];
         const EvPlan p = load_const(E.plan);
-        f64_item<NDET>(E, p, it.tile, it.g);
+        switch (E.ec.n_det) {
+            case 1: f64_item<1>(E, p, it.tile, it.g); break;
+            case 2: f64_item<2>(E, p, it.tile, it.g); break;
+            case 3: f64_item<3>(E, p, it.tile, it.g); break;
+            default: f64_item<4>(E, p, it.tile, it.g); break;
+        }
     }
 }
 
 // Fixed-order combine of the group partials (8 interleaved accumulators, then a
 // pairwise tree), then ln L of Eq. 3.
-template <int NDET>
-__global__ __launch_bounds__(256) void k_b_finalize(const EvDev* __restrict__ evs, const int64_t* __restrict__ doff,
-                                                    int ne) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= doff[ne]) return;
-    const int e = find_slot(doff, ne, gid);
-    const EvDev& E = evs[e];
-    const int64_t j = gid - doff[e];
-    const EvPlan p = *E.plan;
-    if (j >= p.n_active) return;
-    const int64_t np = E.npad;
-    double zr = 0.0, zi = 0.0;
+__global__ __launch_bounds__(256) void k_b_finalize(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                    const int64_t* __restrict__ foff) {
+    const int ne = hdr->ne;
+    const int64_t total = foff[ne];
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+         gid += (int64_t)gridDim.x * blockDim.x) {
+        const int e = find_slot(foff, ne, gid);
+        const EvDev& E = evs[e];
+        const int64_t j = gid - foff[e];
+        const EvPlan p = *E.plan;
+        if (j >= p.n_active) continue;
+        const int64_t np = E.npad;
+        const int nd = E.ec.n_det;
+        double zr = 0.0, zi = 0.0;
+        for (int d = 0; d < nd; ++d) {
+            double ar[8], ai[8];
 #pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-        double ar[8], ai[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0.0;
-        for (int c = 0; c < p.n_groups; ++c) {
-            const double2 v = E.partial[((int64_t)c * NDET + d) * np + j];
-            ar[c & 7] += v.x;
-            ai[c & 7] += v.y;
-        }
-#pragma unroll
-        for (int w = 4; w > 0; w >>= 1)
-#pragma unroll
-            for (int q = 0; q < w; ++q) {
-                ar[q] += ar[q + w];
-                ai[q] += ai[q + w];
+            for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0.0;
+            for (int c = 0; c < p.n_groups; ++c) {
+                const double2 v = E.partial[((int64_t)c * nd + d) * np + j];
+                ar[c & 7] += v.x;
+                ai[c & 7] += v.y;
             }
-        const double rr = E.resp[(2 * d) * np + j], ri = E.resp[(2 * d + 1) * np + j];
-        zr += rr * ar[0] - ri * ai[0];
-        zi += rr * ai[0] + ri * ar[0];
-    }
-    const double h = E.hh[j];
-    const double ll = (E.ec.phase == PE_PHASE_EXPLICIT) ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
-    const int64_t i = E.idx[j];
-    E.loglike[i] = ll;
-    if (E.aux) {
-        E.aux[3 * i] = zr;
-        E.aux[3 * i + 1] = zi;
-        E.aux[3 * i + 2] = h;
+#pragma unroll
+            for (int w = 4; w > 0; w >>= 1)
+#pragma unroll
+                for (int q = 0; q < w; ++q) {
+                    ar[q] += ar[q + w];
+                    ai[q] += ai[q + w];
+                }
+            const double rr = E.resp[(2 * d) * np + j], ri = E.resp[(2 * d + 1) * np + j];
+            zr += rr * ar[0] - ri * ai[0];
+            zi += rr * ai[0] + ri * ar[0];
+        }
+        const double h = E.hh[j];
+        const double ll = (E.ec.phase == PE_PHASE_EXPLICIT) ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
+        const int64_t i = E.idx[j];
+        E.loglike[i] = ll;
+        if (E.aux) {
+            E.aux[3 * i] = zr;
+            E.aux[3 * i + 1] = zi;
+            E.aux[3 * i + 2] = h;
+        }
     }
 }
 
@@ -499,45 +527,41 @@ static unsigned resident_grid(Kern kernel) {
     return (unsigned)(per_cu * n_cu);
 }
 
-template <int NDET>
-static hipError_t launch_hot(const BatchDev& b, int ne, int precision, hipStream_t st) {
-    if (precision == PE_PREC_SPLIT) {
-        static const unsigned grid = resident_grid(k_b_split<NDET>);
-        prof_begin("loglike_split", st);
-        k_b_split<NDET><<<grid, kTile, 0, st>>>(b.evs, b.ioff, ne, b.hdr);
-        prof_end("loglike_split", st);
-    } else {
-        static const unsigned grid = resident_grid(k_b_f64<NDET>);
-        prof_begin("loglike_fp64", st);
-        k_b_f64<NDET><<<grid, kTile, 0, st>>>(b.evs, b.ioff, ne, b.hdr);
-        prof_end("loglike_fp64", st);
+static unsigned grid_for(int64_t total, unsigned cap = 16384) {
+    int64_t g = (total + 255) / 256;
+    if (g < 1) g = 1;
+    return (unsigned)(g < (int64_t)cap ? g : cap);
+}
+
+hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_draws, int64_t finalize_draws,
+                                int precision, hipStream_t st) {
+    if (ne <= 0) return hipSuccess;
+    const EvDev* evs = (const EvDev*)b.args;
+    int64_t* ioff = (int64_t*)b.scratch;
+    const unsigned eg = (unsigned)min(ne, 1024);
+    if (prologue_draws > 0) {
+        const unsigned nb = grid_for(prologue_draws);
+        k_b_reset<<<dim3(kBuckets / 256, eg), 256, 0, st>>>(b.hdr, evs);
+        k_b_support<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
+        k_b_plan<<<eg, 1024, 0, st>>>(b.hdr, evs);
+        k_b_scatter<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
     }
-    return hipGetLastError();
-}
-
-template <int NDET>
-static void launch_finalize(const BatchDev& b, int ne, int64_t max_draws, hipStream_t st) {
-    k_b_finalize<NDET><<<(unsigned)((max_draws + 255) / 256), 256, 0, st>>>(b.evs, b.doff, ne);
-}
-
-hipError_t launch_batch(const BatchDev& b, int ne, int n_det, int64_t max_draws, int precision, hipStream_t st) {
-    if (ne <= 0 || max_draws <= 0) return hipSuccess;
-    const unsigned nb = (unsigned)((max_draws + 255) / 256);
-    k_b_reset<<<dim3(kBuckets / 256, ne), 256, 0, st>>>(b.evs, b.hdr);
-    k_b_support<<<nb, 256, 0, st>>>(b.evs, b.doff, ne);
-    k_b_plan<<<ne, 1024, 0, st>>>(b.evs);
-    k_b_items<<<1, 64, 0, st>>>(b.evs, ne, b.ioff, b.hdr);
-    k_b_scatter<<<nb, 256, 0, st>>>(b.evs, b.doff, ne);
-    k_b_coeffs<<<nb, 256, 0, st>>>(b.evs, b.doff, ne);
+    k_b_items<<<1, 64, 0, st>>>(b.hdr, evs, ioff);
+    if (prologue_draws > 0) k_b_coeffs<<<grid_for(prologue_draws), 256, 0, st>>>(b.hdr, evs, b.off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    switch (n_det) {
-        case 1: e = launch_hot<1>(b, ne, precision, st); launch_finalize<1>(b, ne, max_draws, st); break;
-        case 2: e = launch_hot<2>(b, ne, precision, st); launch_finalize<2>(b, ne, max_draws, st); break;
-        case 3: e = launch_hot<3>(b, ne, precision, st); launch_finalize<3>(b, ne, max_draws, st); break;
-        default: e = launch_hot<4>(b, ne, precision, st); launch_finalize<4>(b, ne, max_draws, st); break;
+    if (precision == PE_PREC_SPLIT) {
+        static const unsigned grid = resident_grid(k_b_split);
+        prof_begin("loglike_split", st);
+        k_b_split<<<grid, kTile, 0, st>>>(b.hdr, evs, ioff);
+        prof_end("loglike_split", st);
+    } else {
+        static const unsigned grid = resident_grid(k_b_f64);
+        prof_begin("loglike_fp64", st);
+        k_b_f64<<<grid, kTile, 0, st>>>(b.hdr, evs, ioff);
+        prof_end("loglike_fp64", st);
     }
-    if (e != hipSuccess) return e;
+    if (finalize_draws > 0) k_b_finalize<<<grid_for(finalize_draws), 256, 0, st>>>(b.hdr, evs, b.off2);
     return hipGetLastError();
 }
 

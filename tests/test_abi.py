@@ -50,6 +50,22 @@ def test_binding_loads_and_pure_host_calls():
     assert L.pe_loglike_multi(0, None, None, None, 7, None, None, None) == 1
 
 
+def test_batch_item_layout_matches_header():
+    # pe_batch_item_t: 5 pointers, int32, uint32, uint64, pointer, int64, 7 pointers
+    assert ctypes.sizeof(binding.BatchItem) == 5 * 8 + 4 + 4 + 8 + 8 + 8 + 7 * 8
+
+
+def test_batch_run_argument_errors_on_host():
+    L = binding.load()
+    assert L.pe_batch_run(0, None, binding.PE_STAGE_ALL, 1, None) == 0
+    assert L.pe_batch_run(1, None, binding.PE_STAGE_ALL, 1, None) == 1
+    assert L.pe_batch_run(0, None, 64, 1, None) == 1
+    it = binding.BatchItem()
+    arr = (binding.BatchItem * 1)(it)
+    assert L.pe_batch_run(1, ctypes.cast(arr, ctypes.c_void_p), binding.PE_STAGE_LOGLIKE, 1, None) == 1
+    assert "event is NULL" in binding.pe_last_error()
+
+
 def test_event_desc_layout_matches_header():
     # pe_event_desc_t: int32, int64, 2 double, 2 int32, double, 2 int32, 4 double, double[4][3]
     assert ctypes.sizeof(binding.EventDesc) == 8 + 8 + 16 + 8 + 8 + 8 + 32 + 96
