@@ -307,7 +307,7 @@ pe_status_t run_prep(const std::vector<PrepArg>& all, hipStream_t st) {
         if (v.empty()) continue;
         const int ne = (int)v.size();
         std::vector<int64_t> off(ne + 1, 0);
-        for (int e = 0; e < ne; ++e) off[e + 1] = off[e] + v[e].ec.K + kTabPad;
+        for (int e = 0; e < ne; ++e) off[e + 1] = off[e] + blocks256(v[e].ec.K + kTabPad);
         Area& A = area_for(st, kAreaPrep);
         std::lock_guard<std::mutex> lk(A.mu);
         BatchPtrs b;
@@ -336,12 +336,13 @@ pe_status_t run_metric(const std::vector<MetricArg>& v, hipStream_t st) {
     const int ne = (int)v.size();
     if (ne == 0) return PE_OK;
     std::vector<int64_t> off(ne + 1, 0);
+    for (int e = 0; e < ne; ++e) off[e + 1] = off[e] + metric_blocks(v[e].ec.K);
     Area& A = area_for(st, kAreaMetric);
     std::lock_guard<std::mutex> lk(A.mu);
     BatchPtrs b;
-    pe_status_t s = upload_area(A, ne, 0, 0, v.data(), sizeof(MetricArg) * ne, off, nullptr, 0, st, b);
+    pe_status_t s = upload_area(A, ne, off[ne], 0, v.data(), sizeof(MetricArg) * ne, off, nullptr, 0, st, b);
     if (s != PE_OK) return s;
-    PE_HIP(launch_metric_batch(b, ne, st));
+    PE_HIP(launch_metric_batch(b, ne, off[ne], st));
     return PE_OK;
 }
 
@@ -367,7 +368,7 @@ pe_status_t run_draw(const std::vector<DrawArg>& v, hipStream_t st) {
     const int ne = (int)v.size();
     if (ne == 0) return PE_OK;
     std::vector<int64_t> off(ne + 1, 0);
-    for (int e = 0; e < ne; ++e) off[e + 1] = off[e] + v[e].n;
+    for (int e = 0; e < ne; ++e) off[e + 1] = off[e] + blocks256(v[e].n);
     Area& A = area_for(st, kAreaDraw);
     std::lock_guard<std::mutex> lk(A.mu);
     BatchPtrs b;
@@ -413,8 +414,8 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     if (ne == 0) return PE_OK;
     std::vector<int64_t> poff(ne + 1, 0), foff(ne + 1, 0);
     for (int e = 0; e < ne; ++e) {
-        poff[e + 1] = poff[e] + ((v[e].flags & kLlPrologue) ? v[e].n : 0);
-        foff[e + 1] = foff[e] + ((v[e].flags & kLlFinalize) ? v[e].n : 0);
+        poff[e + 1] = poff[e] + ((v[e].flags & kLlPrologue) ? blocks256(v[e].n) : 0);
+        foff[e + 1] = foff[e] + ((v[e].flags & kLlFinalize) ? blocks256(v[e].n) : 0);
     }
     Area& A = area_for(st, kAreaLoglike);
     std::lock_guard<std::mutex> lk(A.mu);
@@ -432,7 +433,7 @@ pe_status_t run_weights(const std::vector<WeightArg>& v, hipStream_t st) {
     std::vector<int64_t> boff(ne + 1, 0), doff(ne + 1, 0);
     for (int e = 0; e < ne; ++e) {
         boff[e + 1] = boff[e] + (v[e].n + kWBlock - 1) / kWBlock;
-        doff[e + 1] = doff[e] + v[e].n;
+        doff[e + 1] = doff[e] + blocks256(v[e].n);
     }
     Area& A = area_for(st, kAreaWeights);
     std::lock_guard<std::mutex> lk(A.mu);

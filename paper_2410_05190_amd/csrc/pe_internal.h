@@ -68,6 +68,16 @@ constexpr int kMetricMaxDp = PE_MAX_DIM + 1;
 constexpr int kMetricNG = kMetricMaxDp * (kMetricMaxDp + 1) / 2;  // 78 >= 66
 constexpr int kMetricBlocks = 512;
 
+// Blocks of the metric reduction for an event of K bins: one per 256 bins, at
+// most kMetricBlocks (a function of the event only).
+__host__ __device__ inline int metric_blocks(int64_t K) {
+    const int64_t b = (K + 255) / 256;
+    return (int)(b < kMetricBlocks ? b : kMetricBlocks);
+}
+
+// Blocks of 256 in n items.
+__host__ __device__ inline int64_t blocks256(int64_t n) { return (n + 255) / 256; }
+
 // Device-side plan of one event in a log-likelihood batch.
 struct EvPlan {
     int n_active;  // live draws
@@ -208,13 +218,18 @@ struct BatchPtrs {
 // kernel launchers (pe_kernels.hip, pe_loglike.hip). Each takes the batch's
 // device pointers, the number of events, the flattened size(s) known on the
 // host (for the grid) and the stream.
-hipError_t launch_prep_batch(const BatchPtrs &b, int ne, int64_t total_bins, int data_f32, int psd_f32,
+// Offsets are in blocks that each belong to one event: 256 bins (prep: K +
+// kTabPad bins per event), metric_blocks(K) (metric), 256 draws (draws,
+// log-likelihood prologue and finalize, weight normalisation) or kWBlock
+// draws (weight reduction).
+hipError_t launch_prep_batch(const BatchPtrs &b, int ne, int64_t total_blocks, int data_f32, int psd_f32,
                              hipStream_t st);
-hipError_t launch_metric_batch(const BatchPtrs &b, int ne, hipStream_t st);
-hipError_t launch_draw_batch(const BatchPtrs &b, int ne, int64_t total_draws, hipStream_t st);
-hipError_t launch_loglike_batch(const BatchPtrs &b, int ne, int64_t prologue_draws, int64_t finalize_draws,
+hipError_t launch_metric_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
+hipError_t launch_draw_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
+hipError_t launch_loglike_batch(const BatchPtrs &b, int ne, int64_t prologue_blocks, int64_t finalize_blocks,
                                 int precision, hipStream_t st);
-hipError_t launch_weights_batch(const BatchPtrs &b, int ne, int64_t total_blocks, int64_t total_draws, hipStream_t st);
+hipError_t launch_weights_batch(const BatchPtrs &b, int ne, int64_t total_blocks, int64_t total_draw_blocks,
+                                hipStream_t st);
 hipError_t launch_waveform(const EvConst &ec, int data_psd_dtype, const double *theta, const void *psd, double *h,
                            double *snr2, double *scratch, hipStream_t st);
 hipError_t launch_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int npairs, double *u, hipStream_t st);

@@ -69,21 +69,21 @@ __device__ __forceinline__ void prep_bin(const PrepArg& A, int64_t k) {
     if (bad) atomicOr(A.status, bad);
 }
 
-// Bins of every event of the batch (one storage class per launch); the
+// Bins of every event of the batch (one storage class per launch), in blocks
+// of 256 bins that each belong to one event (koff: block offsets); the
 // kTabPad records past each table's end are zeroed here too.
 template <typename DT, typename ST>
 __global__ __launch_bounds__(256) void k_prep(const BatchHdr* __restrict__ hdr, const PrepArg* __restrict__ args,
                                               const int64_t* __restrict__ koff) {
     const int ne = hdr->ne;
-    const int64_t total = koff[ne];
-    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
-         gid += (int64_t)gridDim.x * blockDim.x) {
-        const int e = find_slot(koff, ne, gid);
+    const int64_t nblk = koff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(koff, ne, b);
         const PrepArg& A = args[e];
-        const int64_t k = gid - koff[e];
+        const int64_t k = (b - koff[e]) * 256 + threadIdx.x;
         if (k < A.ec.K) {
             prep_bin<DT, ST>(A, k);
-        } else {
+        } else if (k < A.ec.K + kTabPad) {
             Rec32 z32 = {};
             Rec64 z64 = {};
             A.rec32[k] = z32;
@@ -162,11 +162,11 @@ __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ h
     }
 }
 
-hipError_t launch_prep_batch(const BatchPtrs& b, int ne, int64_t total_bins, int data_f32, int psd_f32,
+hipError_t launch_prep_batch(const BatchPtrs& b, int ne, int64_t total_blocks, int data_f32, int psd_f32,
                              hipStream_t st) {
     if (ne <= 0) return hipSuccess;
     const PrepArg* args = (const PrepArg*)b.args;
-    const unsigned nb = stride_grid(total_bins);
+    const unsigned nb = stride_grid(total_blocks, 1);
     if (data_f32 && psd_f32)
         k_prep<float, float><<<nb, 256, 0, st>>>(b.hdr, args, b.off);
     else if (data_f32)
@@ -283,26 +283,28 @@ __device__ __forceinline__ void model_unit(const double* __restrict__ src, int d
 }
 
 // Columns: coordinates 0..D-1 by central differences, except the phase column
-// (index DP-1 in 4-D, 10 in 11-D), which is i h(theta0). Block b of kMetricBlocks
-// strides over the bins below the frozen cut.
-template <int NDET, int D, int DP>
-__device__ __forceinline__ void metric_partial(const MetricArg& A) {
+// (index DP-1 in 4-D, 10 in 11-D), which is i h(theta0). Block lb of the
+// event's nb blocks strides over the bins below the frozen cut; the detector
+// loop is not unrolled, so the register need does not grow with n_det.
+template <int D, int DP>
+__device__ __forceinline__ void metric_partial(const MetricArg& A, int lb, int nb) {
     constexpr int NG = DP * (DP + 1) / 2;
     constexpr int PH = (DP == D) ? D - 1 : D;  // phase column
     const double* mws = A.mws;
     const int64_t kc = (int64_t)mws[kMwsKcut];
     const double* src = mws + kMwsSrc;
     const int64_t K = A.ec.K;
+    const int nd = A.ec.n_det;
     double den[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) den[a] = mws[kMwsDen + a];
     double G[NG];
 #pragma unroll
     for (int q = 0; q < NG; ++q) G[q] = 0.0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < kc; k += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t k = (int64_t)lb * 256 + threadIdx.x; k < kc; k += (int64_t)nb * 256) {
         const Rec64 r = A.tab[k];
-#pragma unroll
-        for (int d = 0; d < NDET; ++d) {
+#pragma nounroll
+        for (int d = 0; d < nd; ++d) {
             const double p = A.pw[(int64_t)d * K + k];
             double ur[DP], ui[DP];
 #pragma unroll
@@ -342,24 +344,26 @@ __device__ __forceinline__ void metric_partial(const MetricArg& A) {
     }
     __syncthreads();
     for (int q = threadIdx.x; q < NG; q += blockDim.x)
-        A.mws[kMwsPart + (int64_t)blockIdx.x * kMetricNG + q] = (sh[0][q] + sh[1][q]) + (sh[2][q] + sh[3][q]);
+        A.mws[kMwsPart + (int64_t)lb * kMetricNG + q] = (sh[0][q] + sh[1][q]) + (sh[2][q] + sh[3][q]);
     __syncthreads();
 }
 
-// Grid (kMetricBlocks, events): each event dispatches on its detector count
-// and parameter set (uniform across the workgroup).
+// Blocks of every event (moff: block offsets); each dispatches on its
+// event's parameter set (uniform across the workgroup).
 __global__ __launch_bounds__(256) void k_metric_partial(const BatchHdr* __restrict__ hdr,
-                                                        const MetricArg* __restrict__ args) {
+                                                        const MetricArg* __restrict__ args,
+                                                        const int64_t* __restrict__ moff) {
     const int ne = hdr->ne;
-    for (int e = blockIdx.y; e < ne; e += gridDim.y) {
+    const int64_t nblk = moff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(moff, ne, b);
         const MetricArg& A = args[e];
-        const bool four = A.ec.params == PE_PARAMS_4D;
-        switch (A.ec.n_det) {
-            case 1: four ? metric_partial<1, 4, 5>(A) : metric_partial<1, 11, 11>(A); break;
-            case 2: four ? metric_partial<2, 4, 5>(A) : metric_partial<2, 11, 11>(A); break;
-            case 3: four ? metric_partial<3, 4, 5>(A) : metric_partial<3, 11, 11>(A); break;
-            default: four ? metric_partial<4, 4, 5>(A) : metric_partial<4, 11, 11>(A); break;
-        }
+        const int lb = (int)(b - moff[e]);
+        const int nb = (int)(moff[e + 1] - moff[e]);
+        if (A.ec.params == PE_PARAMS_4D)
+            metric_partial<4, 5>(A, lb, nb);
+        else
+            metric_partial<11, 11>(A, lb, nb);
     }
 }
 
@@ -379,7 +383,8 @@ __global__ __launch_bounds__(128) void k_metric_final(const BatchHdr* __restrict
         if (t < NG) {
             double acc[8];
             for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-            for (int b = 0; b < kMetricBlocks; ++b) acc[b & 7] += A.mws[kMwsPart + (int64_t)b * kMetricNG + t];
+            const int nb = metric_blocks(ev.K);
+            for (int b = 0; b < nb; ++b) acc[b & 7] += A.mws[kMwsPart + (int64_t)b * kMetricNG + t];
             for (int w = 4; w > 0; w >>= 1)
                 for (int q = 0; q < w; ++q) acc[q] += acc[q + w];
             Gs[t] = acc[0];
@@ -428,11 +433,11 @@ __global__ __launch_bounds__(128) void k_metric_final(const BatchHdr* __restrict
     }
 }
 
-hipError_t launch_metric_batch(const BatchPtrs& b, int ne, hipStream_t st) {
+hipError_t launch_metric_batch(const BatchPtrs& b, int ne, int64_t total_blocks, hipStream_t st) {
     if (ne <= 0) return hipSuccess;
     const MetricArg* args = (const MetricArg*)b.args;
     k_metric_setup<<<event_grid(ne), 32, 0, st>>>(b.hdr, args);
-    k_metric_partial<<<dim3(kMetricBlocks, event_grid(ne, 64)), 256, 0, st>>>(b.hdr, args);
+    k_metric_partial<<<stride_grid(total_blocks, 1, 8192), 256, 0, st>>>(b.hdr, args, b.off);
     k_metric_final<<<event_grid(ne), 128, 0, st>>>(b.hdr, args);
     return hipGetLastError();
 }
@@ -440,54 +445,76 @@ hipError_t launch_metric_batch(const BatchPtrs& b, int ne, hipStream_t st) {
 // ===========================================================================
 // draws
 // ===========================================================================
-// Cholesky factor of every event's metric, one thread per event.
+// Cholesky factor g = L L^T of one event's metric (row-major L), log det L and
+// a success flag, in registers (D is a template constant).
+template <int D>
+__device__ __forceinline__ void cholesky_one(const DrawArg& A) {
+    const double* g = A.g;
+    double L[D][D];
+    int ok = 1;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) L[i][j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double s = g[i * D + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            if (i == j) {
+                ok = ok && (s > 0.0);
+                L[i][i] = ok ? sqrt(s) : 1.0;
+            } else {
+                L[i][j] = s / L[j][j];
+            }
+        }
+    double logdet = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) A.chol[i * D + j] = ok ? L[i][j] : 0.0;
+    if (ok)
+#pragma unroll
+        for (int a = 0; a < D; ++a) logdet += log(L[a][a]);
+    A.chol[PE_MAX_DIM * PE_MAX_DIM] = logdet;
+    A.chol[PE_MAX_DIM * PE_MAX_DIM + 1] = ok ? 1.0 : 0.0;
+    if (!ok) atomicOr(A.status, kStSingular);
+}
+
+// One thread per event.
 __global__ __launch_bounds__(64) void k_cholesky(const BatchHdr* __restrict__ hdr, const DrawArg* __restrict__ args) {
     const int ne = hdr->ne;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
         const DrawArg& A = args[e];
-        const int D = A.ec.dim;
-        const double* g = A.g;
-        double L[PE_MAX_DIM * PE_MAX_DIM];
-        int ok = 1;
-        for (int a = 0; a < D * D; ++a) L[a] = 0.0;
-        for (int i = 0; i < D && ok; ++i)
-            for (int j = 0; j <= i; ++j) {
-                double s = g[i * D + j];
-                for (int k = 0; k < j; ++k) s -= L[i * D + k] * L[j * D + k];
-                if (i == j) {
-                    if (!(s > 0.0)) {
-                        ok = 0;
-                        break;
-                    }
-                    L[i * D + i] = sqrt(s);
-                } else {
-                    L[i * D + j] = s / L[j * D + j];
-                }
-            }
-        double logdet = 0.0;
-        for (int a = 0; a < D * D; ++a) A.chol[a] = L[a];
-        if (ok)
-            for (int a = 0; a < D; ++a) logdet += log(L[a * D + a]);
-        A.chol[PE_MAX_DIM * PE_MAX_DIM] = logdet;
-        A.chol[PE_MAX_DIM * PE_MAX_DIM + 1] = ok ? 1.0 : 0.0;
-        if (!ok) atomicOr(A.status, kStSingular);
+        if (A.ec.dim == 4)
+            cholesky_one<4>(A);
+        else
+            cholesky_one<11>(A);
     }
 }
 
-__device__ __forceinline__ void draw_one(const DrawArg& A, int64_t i) {
+// Draw i of an event: normals, theta = theta0 + L^-T z (wrapped), log q of the
+// wrapped Gaussian (images -1, 0, +1 of each periodic coordinate, summed with
+// a running maximum), log prior. L (row-major), its log det and the success
+// flag are in LDS (lc).
+template <int D>
+__device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int64_t i) {
     const EvConst& ev = A.ec;
-    const double* __restrict__ chol = A.chol;
     const int64_t n = A.n;
-    const int D = ev.dim;
-    double th0[PE_MAX_DIM];
+    double th0[D];
+#pragma unroll
     for (int a = 0; a < D; ++a) th0[a] = A.theta0[a];
-    if (chol[PE_MAX_DIM * PE_MAX_DIM + 1] == 0.0) {
+    if (lc[PE_MAX_DIM * PE_MAX_DIM + 1] == 0.0) {
+#pragma unroll
         for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th0[a];
         A.logq[i] = 0.0;
         A.logprior[i] = -INFINITY;
         return;
     }
-    double z[PE_MAX_DIM + 1];
+    double z[D + 1];
+#pragma unroll
     for (int j = 0; 2 * j < D; ++j) {
         double ua, ub, sn, cs;
         block_uniforms(A.seed, A.stream_id, (uint64_t)i, (uint32_t)j, ua, ub);
@@ -497,72 +524,94 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, int64_t i) {
         z[2 * j + 1] = rad * sn;
     }
     // theta = theta0 + L^-T z (back substitution with L^T)
-    double y[PE_MAX_DIM];
+    double y[D];
+#pragma unroll
     for (int r = D - 1; r >= 0; --r) {
         double s = z[r];
-        for (int c = r + 1; c < D; ++c) s -= chol[c * D + r] * y[c];
-        y[r] = s / chol[r * D + r];
+#pragma unroll
+        for (int c = r + 1; c < D; ++c) s -= lc[c * D + r] * y[c];
+        y[r] = s / lc[r * D + r];
     }
-    double th[PE_MAX_DIM];
+    double th[D];
+#pragma unroll
     for (int a = 0; a < D; ++a) th[a] = th0[a] + y[a];
-    const int np = (ev.params == PE_PARAMS_4D) ? 0 : 3;
-    const int pidx[3] = {4, 7, 10};
+    constexpr int NP = (D == 4) ? 0 : 3;
+    constexpr int pidx[3] = {4, 7, 10};
     const double per[3] = {kTwoPi, kPi, kTwoPi};
     double k0[3] = {0.0, 0.0, 0.0};
-    for (int p = 0; p < np; ++p) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
         const double v = th[pidx[p]];
         k0[p] = floor(v / per[p]);
         th[pidx[p]] = v - per[p] * k0[p];
     }
+#pragma unroll
     for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th[a];
-    // log-density of the wrapped Gaussian: images k in {-1,0,1}^p, whitened
-    // offset L^T (x - theta0) = z + L^T s with s = (k - k0) P on the periodic rows
-    const int nimg = (np == 0) ? 1 : 27;
-    double lq[27];
-    double mx = -INFINITY;
-    for (int m = 0; m < nimg; ++m) {
-        double s[3];
+    // whitened offset of image m: L^T (x - theta0) = z + L^T s with
+    // s = (k - k0) P on the periodic rows
+    double mx = -INFINITY, acc = 0.0;
+    constexpr int NIMG = (NP == 0) ? 1 : 27;
+#pragma unroll 1
+    for (int m = 0; m < NIMG; ++m) {
+        double s[3] = {0.0, 0.0, 0.0};
         int code = m;
-        for (int p = 0; p < np; ++p) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
             s[p] = ((double)(code % 3 - 1) - k0[p]) * per[p];
             code /= 3;
         }
         double qf = 0.0;
+#pragma unroll
         for (int r = 0; r < D; ++r) {
             double v = z[r];
-            for (int p = 0; p < np; ++p)
-                if (pidx[p] >= r) v += chol[pidx[p] * D + r] * s[p];
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                if (pidx[p] >= r) v += lc[pidx[p] * D + r] * s[p];
             qf += v * v;
         }
-        lq[m] = -0.5 * qf;
-        mx = fmax(mx, lq[m]);
+        const double l = -0.5 * qf;
+        if (l > mx) {
+            acc = acc * exp(mx - l) + 1.0;
+            mx = l;
+        } else {
+            acc += exp(l - mx);
+        }
     }
-    double acc = 0.0;
-    for (int m = 0; m < nimg; ++m) acc += exp(lq[m] - mx);
-    A.logq[i] = mx + log(acc) + chol[PE_MAX_DIM * PE_MAX_DIM] - 0.5 * D * log(kTwoPi);
+    A.logq[i] = mx + log(acc) + lc[PE_MAX_DIM * PE_MAX_DIM] - 0.5 * D * log(kTwoPi);
     Src src;
     const int ok = source_from_theta(ev, th, src);
     double lp = -INFINITY;
-    if (ok) lp = (ev.params == PE_PARAMS_4D) ? 0.0 : log(cos(th[5])) + log(sin(th[6])) + 2.0 * log(th[8]);
+    if (ok) lp = (D == 4) ? 0.0 : log(cos(th[5])) + log(sin(th[6])) + 2.0 * log(th[8]);
     A.logprior[i] = lp;
 }
 
+// Blocks of 256 draws that each belong to one event (doff: block offsets).
 __global__ __launch_bounds__(256) void k_draw(const BatchHdr* __restrict__ hdr, const DrawArg* __restrict__ args,
                                               const int64_t* __restrict__ doff) {
+    __shared__ double lc[PE_MAX_DIM * PE_MAX_DIM + 2];
     const int ne = hdr->ne;
-    const int64_t total = doff[ne];
-    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
-         gid += (int64_t)gridDim.x * blockDim.x) {
-        const int e = find_slot(doff, ne, gid);
-        draw_one(args[e], gid - doff[e]);
+    const int64_t nblk = doff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(doff, ne, b);
+        const DrawArg& A = args[e];
+        __syncthreads();  // the previous block's readers are done with lc
+        for (int q = threadIdx.x; q < PE_MAX_DIM * PE_MAX_DIM + 2; q += 256) lc[q] = A.chol[q];
+        __syncthreads();
+        const int64_t i = (b - doff[e]) * 256 + threadIdx.x;
+        if (i < A.n) {
+            if (A.ec.dim == 4)
+                draw_one<4>(A, lc, i);
+            else
+                draw_one<11>(A, lc, i);
+        }
     }
 }
 
-hipError_t launch_draw_batch(const BatchPtrs& b, int ne, int64_t total_draws, hipStream_t st) {
+hipError_t launch_draw_batch(const BatchPtrs& b, int ne, int64_t total_blocks, hipStream_t st) {
     if (ne <= 0) return hipSuccess;
     const DrawArg* args = (const DrawArg*)b.args;
     k_cholesky<<<stride_grid(ne, 64), 64, 0, st>>>(b.hdr, args);
-    k_draw<<<stride_grid(total_draws), 256, 0, st>>>(b.hdr, args, b.off);
+    k_draw<<<stride_grid(total_blocks, 1), 256, 0, st>>>(b.hdr, args, b.off);
     return hipGetLastError();
 }
 
@@ -689,23 +738,23 @@ __global__ __launch_bounds__(256) void k_w_final(const BatchHdr* __restrict__ hd
     }
 }
 
+// Blocks of 256 draws that each belong to one event (doff: block offsets).
 __global__ __launch_bounds__(256) void k_w_norm(const BatchHdr* __restrict__ hdr, const WeightArg* __restrict__ args,
                                                 const int64_t* __restrict__ doff, const double2* __restrict__ fin) {
     const int ne = hdr->ne;
-    const int64_t total = doff[ne];
-    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
-         gid += (int64_t)gridDim.x * blockDim.x) {
-        const int e = find_slot(doff, ne, gid);
+    const int64_t nblk = doff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(doff, ne, b);
         const WeightArg& A = args[e];
-        if (!A.w) continue;
-        const int64_t i = gid - doff[e];
+        const int64_t i = (b - doff[e]) * 256 + threadIdx.x;
+        if (!A.w || i >= A.n) continue;
         const double l = A.ll[i] + A.lp[i] - A.lq[i];
         const double2 f = fin[e];
         A.w[i] = (isfinite(l) && f.y > 0.0) ? exp(l - f.x) * f.y : 0.0;
     }
 }
 
-hipError_t launch_weights_batch(const BatchPtrs& b, int ne, int64_t total_blocks, int64_t total_draws,
+hipError_t launch_weights_batch(const BatchPtrs& b, int ne, int64_t total_blocks, int64_t total_draw_blocks,
                                 hipStream_t st) {
     if (ne <= 0) return hipSuccess;
     const WeightArg* args = (const WeightArg*)b.args;
@@ -713,7 +762,7 @@ hipError_t launch_weights_batch(const BatchPtrs& b, int ne, int64_t total_blocks
     double2* fin = (double2*)(part + (total_blocks > 0 ? total_blocks : 1));
     k_w_part<<<stride_grid(total_blocks, 1, 8192), 256, 0, st>>>(b.hdr, args, b.off, part);
     k_w_final<<<event_grid(ne), 256, 0, st>>>(b.hdr, args, b.off, part, fin);
-    k_w_norm<<<stride_grid(total_draws), 256, 0, st>>>(b.hdr, args, b.off2, fin);
+    k_w_norm<<<stride_grid(total_draw_blocks, 1), 256, 0, st>>>(b.hdr, args, b.off2, fin);
     return hipGetLastError();
 }
 

@@ -71,15 +71,17 @@ __device__ __forceinline__ void gather_theta(const EvDev& E, int64_t i, double t
 
 // Support mask, ISCO cut and cut bucket. Buckets run from the longest cut down,
 // so a wave of the hot loop holds draws whose cuts differ by less than one bucket.
+// Blocks of 256 draws that each belong to one event (poff: block offsets of
+// the events in their prologue).
 __global__ __launch_bounds__(256) void k_b_support(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                    const int64_t* __restrict__ poff) {
     const int ne = hdr->ne;
-    const int64_t total = poff[ne];
-    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
-         gid += (int64_t)gridDim.x * blockDim.x) {
-        const int e = find_slot(poff, ne, gid);
+    const int64_t nblk = poff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(poff, ne, b);
         const EvDev& E = evs[e];
-        const int64_t i = gid - poff[e];
+        const int64_t i = (b - poff[e]) * 256 + threadIdx.x;
+        if (i >= E.n) continue;
         double th[PE_MAX_DIM];
         gather_theta(E, i, th);
         Src s;
@@ -180,12 +182,12 @@ __global__ void k_b_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ 
 __global__ __launch_bounds__(256) void k_b_scatter(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                    const int64_t* __restrict__ poff) {
     const int ne = hdr->ne;
-    const int64_t total = poff[ne];
-    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
-         gid += (int64_t)gridDim.x * blockDim.x) {
-        const int e = find_slot(poff, ne, gid);
+    const int64_t nblk = poff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(poff, ne, b);
         const EvDev& E = evs[e];
-        const int64_t i = gid - poff[e];
+        const int64_t i = (b - poff[e]) * 256 + threadIdx.x;
+        if (i >= E.n) continue;
         const int kc = E.kc_all[i];
         if (kc < 0) continue;
         const int pos = atomicAdd(&E.hist[(kBuckets - 1) - (kc >> bucket_shift(E.ec.K))], 1);
@@ -196,12 +198,11 @@ __global__ __launch_bounds__(256) void k_b_scatter(const BatchHdr* __restrict__ 
 __global__ __launch_bounds__(256) void k_b_coeffs(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                   const int64_t* __restrict__ poff) {
     const int ne = hdr->ne;
-    const int64_t total = poff[ne];
-    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
-         gid += (int64_t)gridDim.x * blockDim.x) {
-        const int e = find_slot(poff, ne, gid);
+    const int64_t nblk = poff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(poff, ne, b);
         const EvDev& E = evs[e];
-        const int64_t j = gid - poff[e];
+        const int64_t j = (b - poff[e]) * 256 + threadIdx.x;
         if (j >= E.plan->n_active) continue;
         const int64_t i = E.idx[j];
         const int64_t np = E.npad;
@@ -473,12 +474,11 @@ __global__ __launch_bounds__(256) void k_b_f64(BatchHdr* __restrict__ hdr, const
 __global__ __launch_bounds__(256) void k_b_finalize(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                     const int64_t* __restrict__ foff) {
     const int ne = hdr->ne;
-    const int64_t total = foff[ne];
-    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
-         gid += (int64_t)gridDim.x * blockDim.x) {
-        const int e = find_slot(foff, ne, gid);
+    const int64_t nblk = foff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(foff, ne, b);
         const EvDev& E = evs[e];
-        const int64_t j = gid - foff[e];
+        const int64_t j = (b - foff[e]) * 256 + threadIdx.x;
         const EvPlan p = *E.plan;
         if (j >= p.n_active) continue;
         const int64_t np = E.npad;
@@ -527,27 +527,26 @@ static unsigned resident_grid(Kern kernel) {
     return (unsigned)(per_cu * n_cu);
 }
 
-static unsigned grid_for(int64_t total, unsigned cap = 16384) {
-    int64_t g = (total + 255) / 256;
-    if (g < 1) g = 1;
-    return (unsigned)(g < (int64_t)cap ? g : cap);
+static unsigned grid_for(int64_t blocks, unsigned cap = 16384) {
+    if (blocks < 1) blocks = 1;
+    return (unsigned)(blocks < (int64_t)cap ? blocks : cap);
 }
 
-hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_draws, int64_t finalize_draws,
+hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blocks, int64_t finalize_blocks,
                                 int precision, hipStream_t st) {
     if (ne <= 0) return hipSuccess;
     const EvDev* evs = (const EvDev*)b.args;
     int64_t* ioff = (int64_t*)b.scratch;
     const unsigned eg = (unsigned)min(ne, 1024);
-    if (prologue_draws > 0) {
-        const unsigned nb = grid_for(prologue_draws);
+    if (prologue_blocks > 0) {
+        const unsigned nb = grid_for(prologue_blocks);
         k_b_reset<<<dim3(kBuckets / 256, eg), 256, 0, st>>>(b.hdr, evs);
         k_b_support<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
         k_b_plan<<<eg, 1024, 0, st>>>(b.hdr, evs);
         k_b_scatter<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
     }
     k_b_items<<<1, 64, 0, st>>>(b.hdr, evs, ioff);
-    if (prologue_draws > 0) k_b_coeffs<<<grid_for(prologue_draws), 256, 0, st>>>(b.hdr, evs, b.off);
+    if (prologue_blocks > 0) k_b_coeffs<<<grid_for(prologue_blocks), 256, 0, st>>>(b.hdr, evs, b.off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (precision == PE_PREC_SPLIT) {
@@ -561,7 +560,7 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_dra
         k_b_f64<<<grid, kTile, 0, st>>>(b.hdr, evs, ioff);
         prof_end("loglike_fp64", st);
     }
-    if (finalize_draws > 0) k_b_finalize<<<grid_for(finalize_draws), 256, 0, st>>>(b.hdr, evs, b.off2);
+    if (finalize_blocks > 0) k_b_finalize<<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2);
     return hipGetLastError();
 }
 
