@@ -67,7 +67,8 @@ typedef enum {
     PE_ERR_HIP = 3,       /* a HIP runtime call failed */
     PE_ERR_SINGULAR = 4,  /* the metric given to pe_draw is not positive definite */
     PE_ERR_NONFINITE = 5, /* data contains inf or nan */
-    PE_ERR_BUDGET = 6     /* request exceeds a fixed capacity */
+    PE_ERR_BUDGET = 6,    /* request exceeds a fixed capacity */
+    PE_ERR_TIMEOUT = 7    /* a wait ended before the request completed */
 } pe_status_t;
 
 typedef enum { PE_PREC_FP64 = 0, PE_PREC_SPLIT = 1 } pe_precision_t;
@@ -265,6 +266,80 @@ pe_status_t pe_waveform(const pe_event_desc_t *desc, const double *theta_dev, co
  * block j < npairs, exactly the values pe_draw uses. */
 pe_status_t pe_rng_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int32_t npairs, double *u_dev,
                             void *stream);
+
+/*
+ * Serving loop. A server owns one slab of device memory (hbm_budget bytes), a
+ * stream and a native worker thread. Requests (one detection event each:
+ * data, PSD, proposal centre, number of draws) are submitted from any thread
+ * and queued; the worker admits them in arrival order while their footprint
+ * (tables, workspace and per-draw buffers, all in the slab) fits the free
+ * memory and fewer than max_active are on the device, and runs for each
+ * newly admitted group: table preparation, metric, draws and the
+ * log-likelihood prologue as batched launches. The hot loop then runs in
+ * slices of about slice_ms: each slice takes draw tiles of the active events,
+ * shortest remaining work first, into one work queue, so requests that arrive
+ * while others are on the GPU join the next slice and their work overlaps on
+ * the device (continuous batching). When an event's last tile is done the
+ * same slice combines its partials, computes ln L, the weights and the ESS,
+ * and the event's results are copied back and its memory released. With
+ * use_graph, the slice (work-queue setup, hot loop, ln L, weights) is
+ * captured once in a hipGraph and replayed on the new contents of fixed
+ * device buffers. Every result equals that of the single-event calls for the
+ * same inputs bit for bit, whatever else is in flight.
+ */
+typedef struct pe_server_s *pe_server_t;
+
+typedef struct {
+    int64_t hbm_budget;  /* bytes of the device slab for admitted requests */
+    int32_t precision;   /* PE_PREC_SPLIT or PE_PREC_FP64 */
+    int32_t max_active;  /* requests on the device at once, 1..4096 */
+    double slice_ms;     /* target duration of one hot-loop slice, > 0 */
+    int32_t use_graph;   /* 1: replay the slice as a captured hipGraph */
+    int32_t max_groups;  /* cap on an event's groups of frequency chunks (0 = automatic) */
+} pe_server_config_t;
+
+typedef struct {
+    pe_event_desc_t desc;
+    const void *data, *psd;  /* [n_det][n_bins] in desc's storage types; valid until the request completes */
+    int32_t data_on_host;    /* 1: data and psd are host memory, copied to the slab at admission */
+    int32_t metric_flags;    /* as pe_metric */
+    const double *theta0;    /* host [D]: proposal centre (copied at submission) */
+    uint64_t seed;           /* draws as pe_draw(seed, stream_id) */
+    uint32_t stream_id;
+    int32_t pad;
+    int64_t n_draws;         /* 1 .. 2^22 */
+    double *loglike_out;     /* NULL or host [n]: ln L of every draw */
+    double *w_out;           /* NULL or host [n]: normalised weights */
+    double *theta_out;       /* NULL or host [D][n]: the draws */
+} pe_request_t;
+
+typedef struct {
+    int64_t ticket;
+    int32_t status;      /* PE_OK or the request's error */
+    int32_t n_active;    /* requests on the device when this one was admitted */
+    double stats[4];     /* as pe_weights_ess: ESS, ln Z, max ln w, finite count */
+    double t_submit;     /* seconds on the server clock (pe_server_now) */
+    double t_admit;
+    double t_done;
+} pe_result_t;
+
+/* Start a server (allocates the slab; starts the worker). Errors: PE_ERR_ARG,
+ * PE_ERR_OOM, PE_ERR_HIP. */
+pe_status_t pe_server_create(const pe_server_config_t *cfg, pe_server_t *out);
+/* Queue a request; *ticket identifies it. Host-side argument checks only;
+ * a request whose footprint exceeds the whole budget completes with
+ * PE_ERR_BUDGET. */
+pe_status_t pe_server_submit(pe_server_t srv, const pe_request_t *req, int64_t *ticket);
+/* Wait up to timeout_s seconds (< 0: forever) for a request; PE_ERR_TIMEOUT
+ * if it has not completed. A result is returned once. */
+pe_status_t pe_server_wait(pe_server_t srv, int64_t ticket, double timeout_s, pe_result_t *out);
+/* Seconds on the server's monotonic clock. */
+double pe_server_now(pe_server_t srv);
+/* Counters: {requests completed, slices run, hot-loop items run, graph
+ * replays, peak slab bytes in use, admissions waiting for memory}. */
+pe_status_t pe_server_counters(pe_server_t srv, int64_t out[6]);
+/* Finish every submitted request, stop the worker, free the slab. */
+pe_status_t pe_server_destroy(pe_server_t srv);
 
 /* Kernel timing with HIP events on the launch stream. enable != 0 starts
  * recording around the hot-loop kernel launches; pe_profile_read synchronises

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libpe.so")
 
 PE_OK = 0
 STATUS_NAMES = {0: "PE_OK", 1: "PE_ERR_ARG", 2: "PE_ERR_OOM", 3: "PE_ERR_HIP", 4: "PE_ERR_SINGULAR",
-                5: "PE_ERR_NONFINITE", 6: "PE_ERR_BUDGET"}
+                5: "PE_ERR_NONFINITE", 6: "PE_ERR_BUDGET", 7: "PE_ERR_TIMEOUT"}
+PE_ERR_BUDGET = 6
 PE_PREC_FP64 = 0
 PE_PREC_SPLIT = 1
 PE_PHASE_MARG = 0
@@ -30,7 +31,9 @@ MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
            "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_waveform",
-           "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_last_error"]
+           "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_last_error",
+           "pe_server_create", "pe_server_submit", "pe_server_wait", "pe_server_now", "pe_server_counters",
+           "pe_server_destroy"]
 
 
 class PeError(RuntimeError):
@@ -64,6 +67,31 @@ class BatchItem(ctypes.Structure):
                 ("w", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
 
 
+PE_ERR_TIMEOUT = 7
+
+
+class ServerConfig(ctypes.Structure):
+    """pe_server_config_t."""
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("precision", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("slice_ms", ctypes.c_double), ("use_graph", ctypes.c_int32), ("max_groups", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    """pe_request_t."""
+    _fields_ = [("desc", EventDesc), ("data", ctypes.c_void_p), ("psd", ctypes.c_void_p),
+                ("data_on_host", ctypes.c_int32), ("metric_flags", ctypes.c_int32), ("theta0", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("pad", ctypes.c_int32),
+                ("n_draws", ctypes.c_int64), ("loglike_out", ctypes.c_void_p), ("w_out", ctypes.c_void_p),
+                ("theta_out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    """pe_result_t."""
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int32), ("n_active", ctypes.c_int32),
+                ("stats", ctypes.c_double * 4), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
 def load(path=LIB_PATH):
     """Load libpe.so and declare the signatures (no GPU call is made)."""
     global _lib
@@ -92,6 +120,12 @@ def load(path=LIB_PATH):
         "pe_profile_enable": (i32, [i32]),
         "pe_profile_read": (i32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         "pe_set_chunks": (i32, [i32]),
+        "pe_server_create": (i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
+        "pe_server_submit": (i32, [vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]),
+        "pe_server_wait": (i32, [vp, i64, ctypes.c_double, ctypes.POINTER(Result)]),
+        "pe_server_now": (ctypes.c_double, [vp]),
+        "pe_server_counters": (i32, [vp, ctypes.POINTER(i64)]),
+        "pe_server_destroy": (i32, [vp]),
         "pe_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -362,3 +396,76 @@ def loglike_multi(events, thetas, precision=PE_PREC_SPLIT, aux=False, stream=Non
     axs = [torch.empty((n, 3), dtype=torch.float64, device=t.device) for n, t in zip(ns, thetas)] if aux else None
     pe_loglike_multi(events, thetas, ns, precision, lls, axs, stream)
     return (lls, axs) if aux else lls
+
+
+class Server:
+    """Owns a pe_server_t. submit() takes numpy host arrays or device tensors for data/psd, a host
+    theta0, the draw seed and count, and optional host output arrays (kept alive until the result
+    is collected by wait())."""
+
+    def __init__(self, hbm_budget, precision=PE_PREC_SPLIT, max_active=256, slice_ms=8.0, use_graph=True,
+                 max_groups=0):
+        L = load()
+        cfg = ServerConfig(int(hbm_budget), int(precision), int(max_active), float(slice_ms), int(bool(use_graph)),
+                           int(max_groups))
+        h = ctypes.c_void_p()
+        _check(L.pe_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def now(self):
+        return load().pe_server_now(self.handle)
+
+    def submit(self, desc, data, psd, theta0, n_draws, seed, stream_id=0, metric_flags=0, loglike_out=None,
+               w_out=None, theta_out=None):
+        import numpy as np
+        r = Request()
+        r.desc = desc
+        on_host = isinstance(data, np.ndarray)
+        if on_host:
+            data = np.ascontiguousarray(data)
+            psd = np.ascontiguousarray(psd)
+            r.data, r.psd = data.ctypes.data, psd.ctypes.data
+        else:
+            r.data, r.psd = data.data_ptr(), psd.data_ptr()
+        r.data_on_host = int(on_host)
+        r.metric_flags = int(metric_flags)
+        th0 = np.ascontiguousarray(theta0, dtype=np.float64)
+        r.theta0 = th0.ctypes.data
+        r.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        r.stream_id = int(stream_id) & 0xFFFFFFFF
+        r.n_draws = int(n_draws)
+        outs = []
+        for name, arr in (("loglike_out", loglike_out), ("w_out", w_out), ("theta_out", theta_out)):
+            if arr is not None:
+                assert arr.dtype == np.float64 and arr.flags["C_CONTIGUOUS"]
+                setattr(r, name, arr.ctypes.data)
+                outs.append(arr)
+        t = ctypes.c_int64()
+        _check(load().pe_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = (data, psd, th0, outs)
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        res = Result()
+        _check(load().pe_server_wait(self.handle, int(ticket), float(timeout), ctypes.byref(res)))
+        self._keep.pop(int(ticket), None)
+        return res
+
+    def counters(self):
+        out = (ctypes.c_int64 * 6)()
+        _check(load().pe_server_counters(self.handle, out))
+        keys = ("completed", "slices", "items", "graph_replays", "peak_slab_bytes", "admission_waits")
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if self.handle is not None:
+            h, self.handle = self.handle, None
+            _check(load().pe_server_destroy(h))
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

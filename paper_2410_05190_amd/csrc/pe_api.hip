@@ -113,7 +113,21 @@ void dfree_bytes(char*& p) {
 // coefficient rows, responses, (h|h) and the hot loop's partials.
 int64_t npad_for(int64_t n) { return ((n + kTile - 1) / kTile) * kTile; }
 
-int64_t partial_cap_for(int64_t npad) { return std::min<int64_t>(64 * npad, (int64_t)1 << 22); }
+// Groups of frequency chunks a batch of np draws may use on an event of K
+// bins: at most 64, at most one per 1024 bins (the plan never asks for more),
+// and at most 2^22 / np so that the partials stay bounded.
+int64_t groups_cap(int64_t np, int64_t K) {
+    int64_t g = std::min<int64_t>(64, std::max<int64_t>(1, K / 1024));
+    g = std::min<int64_t>(g, ((int64_t)1 << 22) / std::max<int64_t>(np, 1));
+    return std::max<int64_t>(g, 1);
+}
+
+// Partial slots per detector of a workspace for up to npad draws: enough for
+// any batch of np <= npad draws (np * groups_cap(np, K) never exceeds it).
+int64_t partial_cap_for(int64_t npad, int64_t K) {
+    return std::min<int64_t>(npad * std::min<int64_t>(64, std::max<int64_t>(1, K / 1024)),
+                             std::max<int64_t>((int64_t)1 << 22, npad));
+}
 
 size_t layout_tables(pe_event_s* ev, char* base) {
     Carver c(base);
@@ -131,7 +145,7 @@ size_t layout_tables(pe_event_s* ev, char* base) {
 size_t layout_ws(pe_event_s* ev, int64_t npad, char* base) {
     Carver c(base);
     const int nd = ev->desc.n_det;
-    const int64_t cap = partial_cap_for(npad);
+    const int64_t cap = partial_cap_for(npad, ev->desc.n_bins);
     ev->kc_all = c.take<int>((size_t)npad);
     ev->hist = c.take<int>((size_t)kBuckets);
     ev->plan = c.take<EvPlan>(1);
@@ -225,13 +239,6 @@ pe_status_t new_event(const pe_event_desc_t* desc, char* mem, int64_t max_draws,
 // (uploaded with one copy, skipped when identical to the last upload), then
 // scratch. Batches on one stream are ordered, so the buffer is reused safely;
 // the area's lock is held from the upload until the launches are queued.
-struct Area {
-    std::mutex mu;
-    char* dev = nullptr;
-    size_t cap = 0;
-    std::vector<char> shadow;
-};
-
 std::mutex g_areas_mu;
 std::map<std::pair<void*, int>, std::unique_ptr<Area>> g_areas;
 
@@ -242,15 +249,48 @@ Area& area_for(hipStream_t st, int kind) {
     return *p;
 }
 
-pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const void* args, size_t arg_bytes,
-                        const std::vector<int64_t>& off, const std::vector<int64_t>* off2, size_t scratch_bytes,
-                        hipStream_t st, BatchPtrs& out) {
+size_t area_bytes(int ne, size_t arg_bytes, size_t scratch_bytes) {
     const size_t o_args = 256;
     const size_t o_off = align_up(o_args + arg_bytes, 256);
     const size_t o_off2 = align_up(o_off + sizeof(int64_t) * (ne + 1), 256);
     const size_t o_scr = align_up(o_off2 + sizeof(int64_t) * (ne + 1), 256);
+    return o_scr + std::max<size_t>(scratch_bytes, 256);
+}
+
+pe_status_t reserve_area(Area& A, size_t bytes) {
+    if (bytes <= A.cap) return PE_OK;
+    PE_HIP(hipDeviceSynchronize());  // earlier batches may still read the old buffer
+    dfree_bytes(A.dev);
+    A.cap = 0;
+    A.shadow.clear();
+    pe_status_t s = dalloc_bytes(&A.dev, bytes);
+    if (s != PE_OK) return s;
+    A.cap = bytes;
+    return PE_OK;
+}
+
+void release_area(Area& A) {
+    dfree_bytes(A.dev);
+    A.cap = 0;
+    A.shadow.clear();
+}
+
+pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const void* args, size_t arg_bytes,
+                        const std::vector<int64_t>& off, const std::vector<int64_t>* off2, size_t scratch_bytes,
+                        hipStream_t st, BatchPtrs& out) {
+    // a fixed area keeps one layout (sized for layout_ne records of
+    // layout_rec bytes) so that its pointers never move
+    const int lne = A.fixed ? A.layout_ne : ne;
+    const size_t lab = A.fixed ? A.layout_rec * (size_t)A.layout_ne : arg_bytes;
+    if (A.fixed && (ne > A.layout_ne || arg_bytes > lab))
+        return fail(PE_ERR_BUDGET, "batch exceeds the area's fixed capacity");
+    const size_t o_args = 256;
+    const size_t o_off = align_up(o_args + lab, 256);
+    const size_t o_off2 = align_up(o_off + sizeof(int64_t) * (lne + 1), 256);
+    const size_t o_scr = align_up(o_off2 + sizeof(int64_t) * (lne + 1), 256);
     const size_t need = o_scr + std::max<size_t>(scratch_bytes, 256);
     if (need > A.cap) {
+        if (A.fixed) return fail(PE_ERR_BUDGET, "batch exceeds the area's fixed capacity");
         PE_HIP(hipDeviceSynchronize());  // earlier batches may still read the old buffer
         dfree_bytes(A.dev);
         A.cap = 0;
@@ -269,7 +309,15 @@ pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const vo
     if (arg_bytes) std::memcpy(img.data() + o_args, args, arg_bytes);
     std::memcpy(img.data() + o_off, off.data(), sizeof(int64_t) * (ne + 1));
     if (off2) std::memcpy(img.data() + o_off2, off2->data(), sizeof(int64_t) * (ne + 1));
-    if (img != A.shadow) {
+    if (A.fixed) {
+        // only the used parts
+        PE_HIP(hipMemcpyAsync(A.dev, img.data(), o_args + arg_bytes, hipMemcpyHostToDevice, st));
+        PE_HIP(hipMemcpyAsync(A.dev + o_off, img.data() + o_off, sizeof(int64_t) * (ne + 1), hipMemcpyHostToDevice,
+                              st));
+        if (off2)
+            PE_HIP(hipMemcpyAsync(A.dev + o_off2, img.data() + o_off2, sizeof(int64_t) * (ne + 1),
+                                  hipMemcpyHostToDevice, st));
+    } else if (img != A.shadow) {
         PE_HIP(hipMemcpyAsync(A.dev, img.data(), img.size(), hipMemcpyHostToDevice, st));
         A.shadow.swap(img);
     }
@@ -280,6 +328,9 @@ pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const vo
     out.scratch = (double*)(A.dev + o_scr);
     return PE_OK;
 }
+
+// Bytes of a fixed area for ne records of rec bytes and the given scratch.
+size_t fixed_area_bytes(int ne, size_t rec, size_t scratch_bytes) { return area_bytes(ne, rec * (size_t)ne, scratch_bytes); }
 
 // ------------------------------------------------------------ stage runners
 PrepArg prep_arg(const pe_event_s* ev, const void* data, const void* psd) {
@@ -394,11 +445,14 @@ EvDev loglike_arg(const pe_event_s* ev, const double* theta, int64_t n, double* 
     d.hh = ev->hh;
     d.partial = ev->partial;
     d.plan = ev->plan;
-    d.npad = ev->npad;
-    int64_t mg = ev->partial_cap / (ev->npad > 0 ? ev->npad : 1);
-    if (mg > 64) mg = 64;
+    // Row stride and group cap follow from n alone (the workspace holds at
+    // least this much), so a batch's plan does not depend on how large the
+    // event's workspace happens to be.
+    const int64_t np = std::max<int64_t>(npad_for(n), kTile);
+    d.npad = np;
+    int64_t mg = groups_cap(np, ev->desc.n_bins);
     if (g_chunks > 0 && mg > g_chunks) mg = g_chunks;
-    d.max_groups = (int)(mg < 1 ? 1 : mg);
+    d.max_groups = (int)mg;
     d.tile_lo = 0;
     d.tile_hi = INT_MAX;
     d.flags = kLlPrologue | kLlFinalize;
@@ -423,7 +477,7 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     pe_status_t s = upload_area(A, ne, poff[ne], foff[ne], v.data(), sizeof(EvDev) * ne, poff, &foff,
                                 sizeof(int64_t) * (ne + 1), st, b);
     if (s != PE_OK) return s;
-    PE_HIP(launch_loglike_batch(b, ne, poff[ne], foff[ne], precision, st));
+    PE_HIP(launch_loglike_batch(b, ne, poff[ne], foff[ne], precision, true, st));
     return PE_OK;
 }
 

@@ -2,6 +2,7 @@
 // serving loop (pe_server.hip): errors, event memory, batch stage runners.
 #pragma once
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,12 +46,38 @@ size_t tables_bytes(const pe_event_desc_t& d);
 size_t ws_bytes(const pe_event_desc_t& d, int64_t npad);
 size_t event_footprint(const pe_event_desc_t& d, int64_t max_draws);
 int64_t npad_for(int64_t n);
+int64_t partial_cap_for(int64_t npad, int64_t K);
+int64_t groups_cap(int64_t np, int64_t K);
 
 // New event laid out in `mem` (a range of event_footprint bytes, not owned)
 // or in its own allocations (mem NULL). Does not prepare the tables.
 pe_status_t new_event(const pe_event_desc_t* desc, char* mem, int64_t max_draws, pe_event_s** out);
 void free_event(pe_event_s* ev);
 pe_status_t ensure_ws(pe_event_s* ev, int64_t n);
+
+// A batch area: one device buffer holding the header, the argument records,
+// the offsets (uploaded with one copy, skipped when identical to the last
+// upload) and kind-specific scratch. Batches on one stream are ordered, so the
+// buffer is reused safely; `mu` is held from the upload until the launches are
+// queued. A fixed area never reallocates (its pointers may be captured in a
+// graph); a batch that does not fit is an error.
+struct Area {
+    std::mutex mu;
+    char* dev = nullptr;
+    size_t cap = 0;
+    bool fixed = false;
+    int layout_ne = 0;      // fixed layout: records
+    size_t layout_rec = 0;  // fixed layout: bytes per record
+    std::vector<char> shadow;
+};
+
+size_t area_bytes(int ne, size_t arg_bytes, size_t scratch_bytes);
+size_t fixed_area_bytes(int ne, size_t rec, size_t scratch_bytes);
+pe_status_t reserve_area(Area& A, size_t bytes);
+void release_area(Area& A);
+pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const void* args, size_t arg_bytes,
+                        const std::vector<int64_t>& off, const std::vector<int64_t>* off2, size_t scratch_bytes,
+                        hipStream_t st, BatchPtrs& out);
 
 // Argument records of the batched stages.
 PrepArg prep_arg(const pe_event_s* ev, const void* data, const void* psd);

@@ -227,9 +227,10 @@ hipError_t launch_prep_batch(const BatchPtrs &b, int ne, int64_t total_blocks, i
 hipError_t launch_metric_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
 hipError_t launch_draw_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
 hipError_t launch_loglike_batch(const BatchPtrs &b, int ne, int64_t prologue_blocks, int64_t finalize_blocks,
-                                int precision, hipStream_t st);
+                                int precision, bool profile, hipStream_t st);
 hipError_t launch_weights_batch(const BatchPtrs &b, int ne, int64_t total_blocks, int64_t total_draw_blocks,
                                 hipStream_t st);
+void prime_hot_grids();
 hipError_t launch_waveform(const EvConst &ec, int data_psd_dtype, const double *theta, const void *psd, double *h,
                            double *snr2, double *scratch, hipStream_t st);
 hipError_t launch_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int npairs, double *u, hipStream_t st);

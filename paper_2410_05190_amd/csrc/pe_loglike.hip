@@ -532,8 +532,24 @@ static unsigned grid_for(int64_t blocks, unsigned cap = 16384) {
     return (unsigned)(blocks < (int64_t)cap ? blocks : cap);
 }
 
+static unsigned split_grid() {
+    static const unsigned grid = resident_grid(k_b_split);
+    return grid;
+}
+static unsigned f64_grid() {
+    static const unsigned grid = resident_grid(k_b_f64);
+    return grid;
+}
+
+// Evaluates the hot loop's resident grids (device queries) ahead of any graph
+// capture.
+void prime_hot_grids() {
+    (void)split_grid();
+    (void)f64_grid();
+}
+
 hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blocks, int64_t finalize_blocks,
-                                int precision, hipStream_t st) {
+                                int precision, bool profile, hipStream_t st) {
     if (ne <= 0) return hipSuccess;
     const EvDev* evs = (const EvDev*)b.args;
     int64_t* ioff = (int64_t*)b.scratch;
@@ -550,15 +566,15 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (precision == PE_PREC_SPLIT) {
-        static const unsigned grid = resident_grid(k_b_split);
-        prof_begin("loglike_split", st);
+        const unsigned grid = split_grid();
+        if (profile) prof_begin("loglike_split", st);
         k_b_split<<<grid, kTile, 0, st>>>(b.hdr, evs, ioff);
-        prof_end("loglike_split", st);
+        if (profile) prof_end("loglike_split", st);
     } else {
-        static const unsigned grid = resident_grid(k_b_f64);
-        prof_begin("loglike_fp64", st);
+        const unsigned grid = f64_grid();
+        if (profile) prof_begin("loglike_fp64", st);
         k_b_f64<<<grid, kTile, 0, st>>>(b.hdr, evs, ioff);
-        prof_end("loglike_fp64", st);
+        if (profile) prof_end("loglike_fp64", st);
     }
     if (finalize_blocks > 0) k_b_finalize<<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2);
     return hipGetLastError();

@@ -66,6 +66,24 @@ def test_batch_run_argument_errors_on_host():
     assert "event is NULL" in binding.pe_last_error()
 
 
+def test_server_structs_and_host_checks():
+    # pe_server_config_t: int64, 2 int32, double, 2 int32
+    assert ctypes.sizeof(binding.ServerConfig) == 8 + 8 + 8 + 8
+    # pe_request_t: desc, 2 pointers, 2 int32, pointer, uint64, uint32, int32, int64, 3 pointers
+    assert ctypes.sizeof(binding.Request) == ctypes.sizeof(binding.EventDesc) + 16 + 8 + 8 + 8 + 8 + 8 + 24
+    # pe_result_t: int64, 2 int32, 4 double, 3 double
+    assert ctypes.sizeof(binding.Result) == 8 + 8 + 32 + 24
+    L = binding.load()
+    h = ctypes.c_void_p()
+    bad = binding.ServerConfig(1 << 10, 1, 16, 8.0, 1, 0)  # budget below 1 MiB
+    assert L.pe_server_create(ctypes.byref(bad), ctypes.byref(h)) == 1 and h.value is None
+    bad = binding.ServerConfig(1 << 30, 1, 0, 8.0, 1, 0)  # no slots
+    assert L.pe_server_create(ctypes.byref(bad), ctypes.byref(h)) == 1
+    bad = binding.ServerConfig(1 << 30, 1, 16, 0.0, 1, 0)  # no slice time
+    assert L.pe_server_create(ctypes.byref(bad), ctypes.byref(h)) == 1
+    assert L.pe_server_destroy(None) == 1
+
+
 def test_event_desc_layout_matches_header():
     # pe_event_desc_t: int32, int64, 2 double, 2 int32, double, 2 int32, 4 double, double[4][3]
     assert ctypes.sizeof(binding.EventDesc) == 8 + 8 + 16 + 8 + 8 + 8 + 32 + 96
