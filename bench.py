@@ -50,6 +50,13 @@ def parse():
     ap.add_argument("--chunks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--serve-events", type=int, default=120,
+                    help="requests of the serving load (Poisson arrivals); 0 skips the serving leg")
+    ap.add_argument("--serve-rate", type=float, default=5.0, help="arrival rate of the serving load (1/s)")
+    ap.add_argument("--serve-slice-ms", type=float, default=8.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--serve-no-graph", action="store_true")
+    ap.add_argument("--serve-no-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (HBM counter calibration)")
     return ap.parse_args()
@@ -200,15 +207,18 @@ def main():
     for x in evs:
         x["ev"].close()
 
+    if args.serve_events > 0:
+        out["serving"] = serve_bench(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_sample, first["data"], first["psd"], first["theta_inj"],
                                            first["amp0"], first["common"])
     print(json.dumps(out), flush=True)
 
 
-def make_event(c, e, N):
-    """Event e of configuration c with its device buffers for N draws: the injection is made by the
-    library's own waveform (amplitude or distance set to the target SNR), plus seeded noise."""
+def make_data(c, e, nd=None):
+    """Synthetic event e of configuration c (nd detectors: the first nd of the configuration's network)
+    on the device: the injection is made by the library's own waveform (amplitude or distance set to the
+    target SNR), plus seeded noise. Returns the description and device data."""
     import numpy as np
     import torch
 
@@ -216,7 +226,7 @@ def make_event(c, e, N):
 
     cfg = synth.CONFIGS[c]
     f_lo, df, K = synth.grid(c)
-    nd = cfg["n_det"]
+    nd = nd or cfg["n_det"]
     four_d = cfg["params"] == "4d"
     params = binding.PE_PARAMS_4D if four_d else binding.PE_PARAMS_11D
     phase = binding.PE_PHASE_MARG if cfg["phase"] == "marg" else binding.PE_PHASE_EXPLICIT
@@ -249,43 +259,125 @@ def make_event(c, e, N):
     data = torch.view_as_complex(h) + noise
     data = data.to(torch.complex64 if f32 else torch.complex128).contiguous()
     del noise, h
-    ev = binding.Event(data, psd_t, amp0=amp0, **common)
+    return {"desc": desc, "data": data, "psd": psd_t, "theta_inj": theta_inj, "amp0": amp0, "common": common}
+
+
+def make_event(c, e, N, nd=None):
+    """make_data plus an event with its device buffers for N draws."""
+    import torch
+
+    from paper_2410_05190_amd import binding, synth
+
+    x = make_data(c, e, nd)
+    ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], **x["common"])
     ev.reserve(N)
     D = ev.dim
     f64 = dict(dtype=torch.float64, device="cuda")
-    return {"ev": ev, "data": data, "psd": psd_t, "theta_inj": theta_inj, "amp0": amp0, "common": common, "N": N,
-            "theta0": torch.from_numpy(theta_inj).cuda(), "g": torch.empty((D, D), **f64),
-            "theta": torch.empty((D, N), **f64), "lq": torch.empty(N, **f64), "lp": torch.empty(N, **f64),
-            "ll": torch.empty(N, **f64), "w": torch.empty(N, **f64), "seed": synth.draw_seed(c, e)}
+    x.update({"ev": ev, "N": N, "theta0": torch.from_numpy(x["theta_inj"]).cuda(),
+              "g": torch.empty((D, D), **f64), "theta": torch.empty((D, N), **f64), "lq": torch.empty(N, **f64),
+              "lp": torch.empty(N, **f64), "ll": torch.empty(N, **f64), "w": torch.empty(N, **f64),
+              "seed": synth.draw_seed(c, e)})
+    return x
 
 
-def cpu_baseline(c, n_sample, data, psd_t, theta_inj, amp0, common):
-    """The FP64 oracle as it stands, on the host cores: its own metric and draws for the same
-    event, then the log-likelihood of n_sample draws (timed) and the weights."""
+def percentiles(lat_ms):
     import numpy as np
+    a = np.sort(np.asarray(lat_ms))
+    return {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99)), "max": float(a[-1])}
 
-    import oracle
 
-    threads = os.cpu_count() or 1
-    d_h = data.cpu().numpy()
-    p_h = psd_t.cpu().numpy()
-    ev = oracle.Event(d_h.shape[0], d_h.shape[1], common["f_lo"], common["df"], data=d_h, psd=p_h,
-                      strain_scale=common["strain_scale"], params=common["params"], phase=common["phase"],
-                      amp0=amp0, gmst=common["gmst"], chi_max=common["chi_max"], dl_max=common["dl_max"],
-                      det_geom=common["det_geom"])
-    t0 = time.perf_counter()
-    g = ev.metric(theta_inj)
-    t1 = time.perf_counter()
-    rc, th, lq, lp = ev.draw(theta_inj, g, 12345, 0, 4 * n_sample)
-    live = np.flatnonzero(np.isfinite(lp))[:n_sample]
-    th = np.ascontiguousarray(th[:, live])
-    t2 = time.perf_counter()
-    ll = ev.loglike(th, n_threads=threads)
-    t3 = time.perf_counter()
-    oracle.weights_ess(ll, lp[live], lq[live])
-    return {"value": live.size / (t3 - t2), "unit": "likelihood evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{live.size} in-support draws of the same event (oracle's own metric and draws); "
-                      f"oracle metric {t1 - t0:.1f} s single-threaded, not in value"}
+def serve_bench(args):
+    """The serving load: requests shaped like configs 1 and 2 (70/30), 1..3 detectors, 2^14..2^18 draws,
+    Poisson arrivals at --serve-rate, through the serving loop (continuous batching, graph-replayed hot
+    slices); then the same trace served one request at a time with the plain FP64 path (single-event
+    calls, no graphs, no batching) as the baseline. Latency = completion - arrival."""
+    import numpy as np
+    import torch
+
+    from paper_2410_05190_amd import binding, synth
+
+    tr = synth.serving_trace(args.serve_events, args.serve_rate)
+    n = args.serve_events
+    keys = sorted({(int(tr["shape"][i]), int(tr["n_det"][i]), int(tr["pool"][i])) for i in range(n)})
+    pool = {k: make_data(k[0], synth.SERVE["pool_base"] + k[2], k[1]) for k in keys}
+    torch.cuda.synchronize()
+    print(f"serving: {n} requests over {tr['t'][-1]:.1f} s, pool of {len(pool)} events", file=sys.stderr, flush=True)
+
+    def request(i):
+        k = (int(tr["shape"][i]), int(tr["n_det"][i]), int(tr["pool"][i]))
+        return pool[k], int(tr["n_draws"][i]), synth.draw_seed(3, i)
+
+    srv = binding.Server(int(args.serve_budget_gib * (1 << 30)), precision=binding.PE_PREC_SPLIT, max_active=256,
+                         slice_ms=args.serve_slice_ms, use_graph=not args.serve_no_graph)
+    # warm-up (kernel loading, graph capture): two requests, not timed
+    for i in range(2):
+        x, N, seed = request(i)
+        srv.wait(srv.submit(x["desc"], x["data"], x["psd"], x["theta_inj"], N, seed=seed, stream_id=999))
+    t0 = srv.now()
+    tickets = []
+    for i in range(n):
+        while srv.now() - t0 < tr["t"][i]:
+            time.sleep(min(0.002, max(0.0, tr["t"][i] - (srv.now() - t0))))
+        x, N, seed = request(i)
+        tickets.append(srv.submit(x["desc"], x["data"], x["psd"], x["theta_inj"], N, seed=seed, stream_id=i))
+    res = [srv.wait(t) for t in tickets]
+    counters = srv.counters()
+    srv.close()
+    bad = [r.status for r in res if r.status not in (0, 4)]
+    lat = [1e3 * (r.t_done - r.t_submit) for r in res]
+    t_end = max(r.t_done for r in res) - t0
+    live = sum(r.stats[3] for r in res)
+    ess = sum(r.stats[0] for r in res)
+    out = {"requests": n, "arrival_rate_hz": args.serve_rate, "window_s": t_end,
+           "latency_ms": percentiles(lat), "evals_per_s": live / t_end, "ess_per_s": ess / t_end,
+           "draws": int(sum(int(tr["n_draws"][i]) for i in range(n))), "failed": len(bad),
+           "slice_ms": args.serve_slice_ms, "graph": not args.serve_no_graph, "counters": counters,
+           "kind": "continuous batching, split precision, admission by HBM budget"}
+    print(f"serving: p50 {out['latency_ms']['p50']:.1f} ms p99 {out['latency_ms']['p99']:.1f} ms", file=sys.stderr,
+          flush=True)
+
+    if not args.serve_no_baseline:
+        # serial plain-FP64 baseline on the same trace
+        f64 = dict(dtype=torch.float64, device="cuda")
+        evs = {}
+        for k, x in pool.items():
+            nmax = max(int(tr["n_draws"][i]) for i in range(n)
+                       if (int(tr["shape"][i]), int(tr["n_det"][i]), int(tr["pool"][i])) == k)
+            ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], **x["common"])
+            ev.reserve(nmax)
+            D = ev.dim
+            evs[k] = (ev, torch.from_numpy(x["theta_inj"]).cuda(), torch.empty((D, D), **f64),
+                      torch.empty((D, nmax), **f64), torch.empty(nmax, **f64), torch.empty(nmax, **f64),
+                      torch.empty(nmax, **f64), torch.empty(nmax, **f64), torch.empty(4, **f64))
+        torch.cuda.synchronize()
+        lat0, live0, ess0 = [], 0.0, 0.0
+        t0 = time.perf_counter()
+        for i in range(n):
+            while time.perf_counter() - t0 < tr["t"][i]:
+                time.sleep(min(0.002, max(0.0, tr["t"][i] - (time.perf_counter() - t0))))
+            k = (int(tr["shape"][i]), int(tr["n_det"][i]), int(tr["pool"][i]))
+            x = pool[k]
+            ev, th0, g, th, lq, lp, ll, w, st = evs[k]
+            N = int(tr["n_draws"][i])
+            h_ = ev.handle
+            binding.pe_event_update(h_, x["data"], x["psd"])
+            binding.pe_metric(h_, th0, None, 0, g)
+            binding.pe_draw(h_, th0, g, synth.draw_seed(3, i), i, N, th, lq, lp)
+            binding.pe_loglike_batch(h_, th, N, binding.PE_PREC_FP64, ll, None)
+            binding.pe_weights_ess(ll, lp, lq, N, w, st)
+            sv = st.cpu().numpy()
+            lat0.append(1e3 * (time.perf_counter() - t0 - tr["t"][i]))
+            live0 += sv[3]
+            ess0 += sv[0]
+        t_end0 = time.perf_counter() - t0
+        for v in evs.values():
+            v[0].close()
+        out["baseline"] = {"kind": "same trace, one request at a time, plain FP64 path, no graphs or batching",
+                           "latency_ms": percentiles(lat0), "evals_per_s": live0 / t_end0,
+                           "ess_per_s": ess0 / t_end0, "window_s": t_end0}
+        print(f"serving baseline: p50 {out['baseline']['latency_ms']['p50']:.1f} ms "
+              f"p99 {out['baseline']['latency_ms']['p99']:.1f} ms", file=sys.stderr, flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -114,6 +114,26 @@ def injection(config, event):
     return out
 
 
+# Serving load: Poisson arrivals of requests shaped like config 1 (BNS) or
+# config 2 (BBH), each with 1..3 detectors (the first n_det of that
+# configuration's network) and 2^14..2^18 draws; the event data of a request
+# is one of POOL pool events per (shape, n_det).
+SERVE = dict(name="serving-bns-bbh-mix", n_events=2000, rate_hz=5.0, bns_fraction=0.7, pool=4, pool_base=100)
+
+
+def serving_trace(n_events, rate_hz=SERVE["rate_hz"]):
+    """Arrival times (s, first at 0), shape config (1 or 2), n_det, draw count and pool index of each
+    request, seeded."""
+    g = rng(3, 0, ST_SERVE)
+    gaps = g.exponential(1.0 / rate_hz, n_events)
+    t = np.concatenate([[0.0], np.cumsum(gaps[1:])])
+    shape = np.where(g.uniform(size=n_events) < SERVE["bns_fraction"], 1, 2)
+    n_det = g.integers(1, 4, size=n_events)
+    n_draws = 2 ** g.integers(14, 19, size=n_events)
+    pool = g.integers(0, SERVE["pool"], size=n_events)
+    return dict(t=t, shape=shape, n_det=n_det, n_draws=n_draws, pool=pool)
+
+
 def draw_seed(config, event):
     """64-bit key of the proposal's counter-based generator for this event."""
     return int(rng(config, event, ST_DRAW_SEED).integers(0, 2 ** 63 - 1))
