@@ -33,10 +33,10 @@ PSI_OPS_PER_DRAW_BIN = 10
 SPLIT_OPS_PER_TERM = 6 + 2 * 2
 FP64_OPS_PER_TERM = 2 + 26 + 4
 # HBM bytes per launch of the split kernel at the benchmark shape (config 1, automatic
-# groups), from rocprofv3
-# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors read off a 1 GiB device copy
-# in the same run; None when the kernel has changed since the counters were taken.
-SPLIT_TRAFFIC_BYTES = None
+# groups), from rocprofv3 FETCH_SIZE x 1.9999 + WRITE_SIZE x 1.0 (KiB per dispatch), the
+# factors read off a 1 GiB device-to-device copy in the same runs (profiles/
+# loglike_split_config1.md); None when the kernel has changed since the counters were taken.
+SPLIT_TRAFFIC_BYTES = 736481746
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 
 
@@ -378,6 +378,36 @@ def serve_bench(args):
         print(f"serving baseline: p50 {out['baseline']['latency_ms']['p50']:.1f} ms "
               f"p99 {out['baseline']['latency_ms']['p99']:.1f} ms", file=sys.stderr, flush=True)
     return out
+
+
+def cpu_baseline(c, n_sample, data, psd_t, theta_inj, amp0, common):
+    """The FP64 oracle as it stands, on the host cores: its own metric and draws for the same
+    event, then the log-likelihood of n_sample draws (timed) and the weights."""
+    import numpy as np
+
+    import oracle
+
+    threads = os.cpu_count() or 1
+    d_h = data.cpu().numpy()
+    p_h = psd_t.cpu().numpy()
+    ev = oracle.Event(d_h.shape[0], d_h.shape[1], common["f_lo"], common["df"], data=d_h, psd=p_h,
+                      strain_scale=common["strain_scale"], params=common["params"], phase=common["phase"],
+                      amp0=amp0, gmst=common["gmst"], chi_max=common["chi_max"], dl_max=common["dl_max"],
+                      det_geom=common["det_geom"])
+    t0 = time.perf_counter()
+    g = ev.metric(theta_inj)
+    t1 = time.perf_counter()
+    rc, th, lq, lp = ev.draw(theta_inj, g, 12345, 0, 4 * n_sample)
+    live = np.flatnonzero(np.isfinite(lp))[:n_sample]
+    th = np.ascontiguousarray(th[:, live])
+    t2 = time.perf_counter()
+    ll = ev.loglike(th, n_threads=threads)
+    t3 = time.perf_counter()
+    oracle.weights_ess(ll, lp[live], lq[live])
+    return {"value": live.size / (t3 - t2), "unit": "likelihood evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{live.size} in-support draws of the same event (oracle's own metric and draws); "
+                      f"oracle metric {t1 - t0:.1f} s single-threaded, not in value"}
+
 
 
 if __name__ == "__main__":

@@ -475,7 +475,7 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     std::lock_guard<std::mutex> lk(A.mu);
     BatchPtrs b;
     pe_status_t s = upload_area(A, ne, poff[ne], foff[ne], v.data(), sizeof(EvDev) * ne, poff, &foff,
-                                sizeof(int64_t) * (ne + 1), st, b);
+                                sizeof(int64_t) * kQueues * (ne + 1), st, b);
     if (s != PE_OK) return s;
     PE_HIP(launch_loglike_batch(b, ne, poff[ne], foff[ne], precision, true, st));
     return PE_OK;

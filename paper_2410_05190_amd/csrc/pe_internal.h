@@ -158,14 +158,18 @@ struct WeightArg {
     double *w, *stats;
 };
 
+// Hot-loop work queues: one per XCD (workgroup b of a launch runs on XCD
+// b mod kQueues).
+constexpr int kQueues = 8;
+
 // Header of a batch in device memory.
 struct BatchHdr {
-    int ne;          // events
-    int items;       // hot-loop work items (written by the planning kernel)
-    int next;        // hot-loop queue counter
+    int ne;                // events
     int pad;
-    int64_t total;   // flattened size (draws, bins or weight blocks)
-    int64_t total2;  // second flattened size (weights: draws)
+    int64_t total;         // flattened size (blocks)
+    int64_t total2;        // second flattened size (blocks)
+    int qitems[kQueues];   // hot-loop items per queue (written by k_b_items)
+    int qnext[kQueues];    // queue counters
 };
 
 constexpr int kWBlock = 4096;  // draws per block of the weights reduction (256 threads x 16)

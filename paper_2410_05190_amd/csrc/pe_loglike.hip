@@ -146,6 +146,7 @@ __global__ __launch_bounds__(1024) void k_b_plan(const BatchHdr* __restrict__ hd
                 while (G < want && G < 64) G <<= 1;
                 const int by_bins = max(1, p.kmax / 1024);
                 G = min(G, min(by_bins, E.max_groups));
+                while (G & (G - 1)) G &= G - 1;  // a power of two
                 const int target = 8 * G;
                 int fine = ((p.kmax + target - 1) / target + kBlk - 1) / kBlk * kBlk;
                 fine = max(fine, kBlk);
@@ -161,21 +162,33 @@ __global__ __launch_bounds__(1024) void k_b_plan(const BatchHdr* __restrict__ hd
     }
 }
 
-// Offsets of every event's items in the batch queue (items = tiles of this
-// launch x groups), the item total, and the queue counter reset.
+// Items of an event in queue x: with G >= 8 groups (a multiple of 8), the
+// groups g = x (mod 8) of every tile, so an XCD reads only its eighth of the
+// frequency chunks through its L2; with G < 8, every eighth item of the
+// event's (tile, group) sequence.
+__device__ __forceinline__ int64_t queue_items(int64_t ntiles, int G, int x) {
+    if (G >= kQueues) return ntiles * (G / kQueues);
+    const int64_t T = ntiles * G;
+    return T > x ? (T - x + kQueues - 1) / kQueues : 0;
+}
+
+// Per queue: offsets of every event's items (ioff[x][ne + 1]), the item
+// total, and the counter reset. Thread x serves queue x.
 __global__ void k_b_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs, int64_t* __restrict__ ioff) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int x = threadIdx.x;
+    if (x >= kQueues || blockIdx.x != 0) return;
     const int ne = hdr->ne;
+    int64_t* o = ioff + (int64_t)x * (ne + 1);
     int64_t acc = 0;
     for (int e = 0; e < ne; ++e) {
-        ioff[e] = acc;
+        o[e] = acc;
         const EvPlan p = *evs[e].plan;
         const int lo = max(0, evs[e].tile_lo), hi = min(p.tiles, evs[e].tile_hi);
-        if (hi > lo) acc += (int64_t)(hi - lo) * p.n_groups;
+        if (hi > lo && p.n_groups > 0) acc += queue_items(hi - lo, p.n_groups, x);
     }
-    ioff[ne] = acc;
-    hdr->items = (int)acc;
-    hdr->next = 0;
+    o[ne] = acc;
+    hdr->qitems[x] = (int)acc;
+    hdr->qnext[x] = 0;
 }
 
 // Live draws into their buckets; the order inside a bucket is immaterial.
@@ -299,22 +312,44 @@ struct Item {
     int e, tile, g;
 };
 
-// Next item of the batch queue; false when the queue is empty (every workgroup
-// reaches that exit).
+// Next item for a workgroup on XCD x0: from queue x0, else (once it is
+// empty) from the other queues in turn; false when every queue is empty (every
+// workgroup reaches that exit).
 __device__ __forceinline__ bool next_item(BatchHdr* __restrict__ hdr, const int64_t* __restrict__ ioff, int ne,
-                                          const EvDev* __restrict__ evs, Item& it) {
-    __shared__ int s_item;
+                                          const EvDev* __restrict__ evs, int x0, Item& it) {
+    __shared__ int s_item, s_q;
     __syncthreads();  // every wave is done with the previous s_item
-    if (threadIdx.x == 0) s_item = atomicAdd(&hdr->next, 1);
+    if (threadIdx.x == 0) {
+        int q = -1, v = 0;
+        for (int k = 0; k < kQueues; ++k) {
+            const int qq = (x0 + k) & (kQueues - 1);
+            v = atomicAdd(&hdr->qnext[qq], 1);
+            if (v < hdr->qitems[qq]) {
+                q = qq;
+                break;
+            }
+        }
+        s_q = q;
+        s_item = v;
+    }
     __syncthreads();
+    const int q = __builtin_amdgcn_readfirstlane(s_q);
+    if (q < 0) return false;
     const int x = __builtin_amdgcn_readfirstlane(s_item);
-    if (x >= hdr->items) return false;
-    it.e = find_slot(ioff, ne, x);
-    const int loc = x - (int)ioff[it.e];
+    const int64_t* o = ioff + (int64_t)q * (ne + 1);
+    it.e = find_slot(o, ne, x);
+    const int l = x - (int)o[it.e];
     const int G = load_const(evs[it.e].plan).n_groups;
     const int lo = max(0, evs[it.e].tile_lo);
-    it.tile = lo + loc / G;
-    it.g = loc - (loc / G) * G;
+    if (G >= kQueues) {
+        const int gq = G / kQueues;
+        it.tile = lo + l / gq;
+        it.g = q + kQueues * (l - (l / gq) * gq);
+    } else {
+        const int f = q + kQueues * l;
+        it.tile = lo + f / G;
+        it.g = f - (f / G) * G;
+    }
     return true;
 }
 
@@ -440,8 +475,9 @@ __device__ __forceinline__ void f64_item(const EvDev& E, const EvPlan& p, int ti
 __global__ __launch_bounds__(256) void k_b_split(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                  const int64_t* __restrict__ ioff) {
     const int ne = hdr->ne;
+    const int x0 = blockIdx.x & (kQueues - 1);
     Item it;
-    while (next_item(hdr, ioff, ne, evs, it)) {
+    while (next_item(hdr, ioff, ne, evs, x0, it)) {
         const EvDev& E = evs[it.e];
         const EvPlan p = load_const(E.plan);
         switch (E.ec.n_det) {
@@ -456,8 +492,9 @@ __global__ __launch_bounds__(256) void k_b_split(BatchHdr* __restrict__ hdr, con
 __global__ __launch_bounds__(256) void k_b_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                const int64_t* __restrict__ ioff) {
     const int ne = hdr->ne;
+    const int x0 = blockIdx.x & (kQueues - 1);
     Item it;
-    while (next_item(hdr, ioff, ne, evs, it)) {
+    while (next_item(hdr, ioff, ne, evs, x0, it)) {
         const EvDev& E = evs[it.e];
         const EvPlan p = load_const(E.plan);
         switch (E.ec.n_det) {

@@ -356,7 +356,7 @@ pe_status_t pe_server_s::slice() {
     }
     BatchPtrs bll, bw;
     pe_status_t s = upload_area(a_ll, ne, poff[ne], foff[ne], vl.data(), sizeof(EvDev) * ne, poff, &foff,
-                                sizeof(int64_t) * (cap_ne + 1), st, bll);
+                                sizeof(int64_t) * kQueues * (cap_ne + 1), st, bll);
     if (s == PE_OK)
         s = upload_area(a_w, nw, boff[nw], doff[nw], vw.data(), sizeof(WeightArg) * nw, boff, &doff,
                         sizeof(double4) * cap_wblocks + sizeof(double2) * cap_ne, st, bw);
@@ -473,7 +473,7 @@ pe_status_t pe_server_create(const pe_server_config_t* cfg, pe_server_t* out) {
     s->a_ll.layout_ne = s->a_w.layout_ne = s->cap_ne;
     s->a_ll.layout_rec = sizeof(EvDev);
     s->a_w.layout_rec = sizeof(WeightArg);
-    const size_t ll_bytes = fixed_area_bytes(s->cap_ne, sizeof(EvDev), sizeof(int64_t) * (s->cap_ne + 1));
+    const size_t ll_bytes = fixed_area_bytes(s->cap_ne, sizeof(EvDev), sizeof(int64_t) * kQueues * (s->cap_ne + 1));
     const size_t w_bytes = fixed_area_bytes(s->cap_ne, sizeof(WeightArg),
                                             sizeof(double4) * s->cap_wblocks + sizeof(double2) * s->cap_ne);
     if ((st = dalloc_bytes(&s->a_ll.dev, ll_bytes)) != PE_OK) return bail(st);
