@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--precision", choices=["split", "fp64"], default="split")
     ap.add_argument("--chunks", type=int, default=0)
+    ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
+                    help="pick the hot loop's plan with the library's autotuner before timing (auto: batches only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--serve-events", type=int, default=120,
@@ -138,6 +140,18 @@ def main():
     torch.cuda.synchronize()
     for x in evs:
         x["ev"].status()
+    plan = {"tuned": False}
+    if args.autotune == "on" or (args.autotune == "auto" and n_events > 1):
+        if args.warmup == 0:
+            step(999, stats[0])
+        t_tune = time.perf_counter()
+        it, mb, best_ms = binding.pe_autotune_plan([x["ev"] for x in evs], [x["theta"] for x in evs],
+                                                   [x["N"] for x in evs], prec, reps=2)
+        binding.pe_set_plan(it, mb)
+        plan = {"tuned": True, "tune_s": time.perf_counter() - t_tune, "best_loglike_ms": best_ms}
+        step(998, stats[0])
+        torch.cuda.synchronize()
+    plan["items_target"], plan["min_group_bins"] = binding.pe_get_plan()
 
     binding.pe_profile_enable(True)
     binding.pe_profile_read(kname)
@@ -190,7 +204,7 @@ def main():
         "data": "synthetic (seeded coloured Gaussian noise + TaylorF2 injection)",
         "config": {"workload": cfg["name"], "n_det": nd, "n_bins": K, "events_per_step": n_events,
                    "draws_per_event": Ns[0] if n_events == 1 else Ns, "dim": D,
-                   "precision": args.precision, "chunks": args.chunks or "auto"},
+                   "precision": args.precision, "chunks": args.chunks or "auto", "plan": plan},
         "draws_per_s": n_draws / wall,
         "in_support_fraction": n_live / n_draws,
         "ess_per_s": ess / wall,

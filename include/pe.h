@@ -296,6 +296,8 @@ typedef struct {
     double slice_ms;     /* target duration of one hot-loop slice, > 0 */
     int32_t use_graph;   /* 1: replay the slice as a captured hipGraph */
     int32_t max_groups;  /* cap on an event's groups of frequency chunks (0 = automatic) */
+    int32_t items_target;    /* hot-loop plan (see pe_set_plan); 0 = the library's setting */
+    int32_t min_group_bins;  /* hot-loop plan (see pe_set_plan); 0 = the library's setting */
 } pe_server_config_t;
 
 typedef struct {
@@ -353,6 +355,26 @@ pe_status_t pe_profile_read(const char *kernel, double *total_ms, int64_t *launc
  * (0 = automatic, at most 64; 1 = one group walks the whole band). Results do
  * not depend on it. Global setting, read at launch time. */
 pe_status_t pe_set_chunks(int32_t n_chunks);
+
+/* Plan of the hot loop's work decomposition, read at launch time (global):
+ * each event's tiles x groups aim at about items_target work items (more
+ * items balance the persistent queues better; fewer write fewer partials),
+ * with at least min_group_bins bins per group. Defaults 16384 and 1024.
+ * Results are bitwise reproducible for a fixed setting and change only in
+ * rounding between settings. Errors: PE_ERR_ARG (out of range). */
+pe_status_t pe_set_plan(int32_t items_target, int32_t min_group_bins);
+pe_status_t pe_get_plan(int32_t *items_target, int32_t *min_group_bins);
+
+/* Autotuner of the plan for a workload: times pe_loglike_multi on the given
+ * events and draws (one untimed and `reps` timed batches per candidate, HIP
+ * events on `stream`) over items_target in {4096 .. 65536} and min_group_bins
+ * in {256 .. 4096}, and returns the fastest pair and its time per batch in
+ * milliseconds. The library's setting is left unchanged; apply the result with
+ * pe_set_plan (or a server's config). Allocates scratch for the log-likelihoods
+ * and synchronises `stream`. */
+pe_status_t pe_autotune_plan(int32_t n_events, const pe_event_t *events, const double *const *theta_dev,
+                             const int64_t *n, int32_t precision, int32_t reps, int32_t *best_items_target,
+                             int32_t *best_min_group_bins, double *best_ms, void *stream);
 
 const char *pe_last_error(void);
 

@@ -31,7 +31,8 @@ MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
            "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_waveform",
-           "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_last_error",
+           "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
+           "pe_autotune_plan", "pe_last_error",
            "pe_server_create", "pe_server_submit", "pe_server_wait", "pe_server_now", "pe_server_counters",
            "pe_server_destroy"]
 
@@ -73,7 +74,8 @@ PE_ERR_TIMEOUT = 7
 class ServerConfig(ctypes.Structure):
     """pe_server_config_t."""
     _fields_ = [("hbm_budget", ctypes.c_int64), ("precision", ctypes.c_int32), ("max_active", ctypes.c_int32),
-                ("slice_ms", ctypes.c_double), ("use_graph", ctypes.c_int32), ("max_groups", ctypes.c_int32)]
+                ("slice_ms", ctypes.c_double), ("use_graph", ctypes.c_int32), ("max_groups", ctypes.c_int32),
+                ("items_target", ctypes.c_int32), ("min_group_bins", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -120,6 +122,10 @@ def load(path=LIB_PATH):
         "pe_profile_enable": (i32, [i32]),
         "pe_profile_read": (i32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         "pe_set_chunks": (i32, [i32]),
+        "pe_set_plan": (i32, [i32, i32]),
+        "pe_get_plan": (i32, [ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "pe_autotune_plan": (i32, [i32, vp, vp, vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(ctypes.c_double), vp]),
         "pe_server_create": (i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
         "pe_server_submit": (i32, [vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]),
         "pe_server_wait": (i32, [vp, i64, ctypes.c_double, ctypes.POINTER(Result)]),
@@ -320,6 +326,29 @@ def pe_set_chunks(n_chunks):
     _check(load().pe_set_chunks(int(n_chunks)))
 
 
+def pe_set_plan(items_target, min_group_bins):
+    _check(load().pe_set_plan(int(items_target), int(min_group_bins)))
+
+
+def pe_get_plan():
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().pe_get_plan(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def pe_autotune_plan(events, thetas, ns, precision, reps=2, stream=None):
+    """Fastest (items_target, min_group_bins) for this workload and its time per batch (ms)."""
+    import torch
+    ne = len(events)
+    ev_a = (ctypes.c_void_p * max(ne, 1))(*[e.handle if isinstance(e, Event) else e for e in events])
+    th_a = (ctypes.c_void_p * max(ne, 1))(*[_ptr(t, torch.float64, "theta") for t in thetas])
+    n_a = (ctypes.c_int64 * max(ne, 1))(*[int(n) for n in ns])
+    a, b, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(load().pe_autotune_plan(ne, ev_a, th_a, n_a, int(precision), int(reps), ctypes.byref(a), ctypes.byref(b),
+                                   ctypes.byref(ms), _stream(stream)))
+    return a.value, b.value, ms.value
+
+
 def pe_last_error():
     return load().pe_last_error().decode()
 
@@ -404,10 +433,10 @@ class Server:
     is collected by wait())."""
 
     def __init__(self, hbm_budget, precision=PE_PREC_SPLIT, max_active=256, slice_ms=8.0, use_graph=True,
-                 max_groups=0):
+                 max_groups=0, items_target=0, min_group_bins=0):
         L = load()
         cfg = ServerConfig(int(hbm_budget), int(precision), int(max_active), float(slice_ms), int(bool(use_graph)),
-                           int(max_groups))
+                           int(max_groups), int(items_target), int(min_group_bins))
         h = ctypes.c_void_p()
         _check(L.pe_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

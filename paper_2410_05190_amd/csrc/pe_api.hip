@@ -20,7 +20,9 @@
 namespace {
 
 thread_local std::string g_err;
-int g_chunks = 0;  // cap on the hot loop's groups of chunks per event; 0 = automatic (64)
+int g_chunks = 0;             // cap on the hot loop's groups of chunks per event; 0 = automatic (64)
+int g_items_target = 16384;   // plan: work items per event
+int g_min_group_bins = 1024;  // plan: bins per group at least
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -453,6 +455,8 @@ EvDev loglike_arg(const pe_event_s* ev, const double* theta, int64_t n, double* 
     int64_t mg = groups_cap(np, ev->desc.n_bins);
     if (g_chunks > 0 && mg > g_chunks) mg = g_chunks;
     d.max_groups = (int)mg;
+    d.items_target = g_items_target;
+    d.min_group_bins = g_min_group_bins;
     d.tile_lo = 0;
     d.tile_hi = INT_MAX;
     d.flags = kLlPrologue | kLlFinalize;
@@ -789,6 +793,89 @@ pe_status_t pe_profile_read(const char* kernel, double* total_ms, int64_t* launc
     *total_ms = tot;
     *launches = (int64_t)v.size();
     return s;
+}
+
+pe_status_t pe_set_plan(int32_t items_target, int32_t min_group_bins) {
+    if (items_target < 256 || items_target > (1 << 20)) return fail(PE_ERR_ARG, "items_target must be in 256..2^20");
+    if (min_group_bins < 32 || min_group_bins > (1 << 20)) return fail(PE_ERR_ARG, "min_group_bins must be in 32..2^20");
+    g_items_target = items_target;
+    g_min_group_bins = min_group_bins;
+    return PE_OK;
+}
+
+pe_status_t pe_get_plan(int32_t* items_target, int32_t* min_group_bins) {
+    if (!items_target || !min_group_bins) return fail(PE_ERR_ARG, "NULL argument");
+    *items_target = g_items_target;
+    *min_group_bins = g_min_group_bins;
+    return PE_OK;
+}
+
+pe_status_t pe_autotune_plan(int32_t n_events, const pe_event_t* events, const double* const* theta_dev,
+                             const int64_t* n, int32_t precision, int32_t reps, int32_t* best_items_target,
+                             int32_t* best_min_group_bins, double* best_ms, void* stream) {
+    if (!best_items_target || !best_min_group_bins || !best_ms) return fail(PE_ERR_ARG, "NULL output");
+    if (reps < 1 || reps > 100) return fail(PE_ERR_ARG, "reps must be in 1..100");
+    std::vector<double*> ll;
+    std::vector<const double*> th;
+    std::vector<pe_event_t> evv;
+    std::vector<int64_t> nn;
+    pe_status_t s = PE_OK;
+    for (int e = 0; e < n_events && events && n; ++e) {
+        if (n[e] <= 0) continue;
+        char* p = nullptr;
+        if ((s = dalloc_bytes(&p, sizeof(double) * (size_t)n[e])) != PE_OK) break;
+        ll.push_back((double*)p);
+        th.push_back(theta_dev[e]);
+        evv.push_back(events[e]);
+        nn.push_back(n[e]);
+    }
+    const int32_t keep_items = g_items_target, keep_bins = g_min_group_bins;
+    hipStream_t st = as_stream(stream);
+    hipEvent_t a = nullptr, b = nullptr;
+    double best = 1e300;
+    int32_t bi = keep_items, bb = keep_bins;
+    if (s == PE_OK && (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess))
+        s = fail(PE_ERR_HIP, "autotune events");
+    const int32_t items[] = {4096, 8192, 16384, 32768, 65536};
+    const int32_t bins[] = {256, 512, 1024, 2048, 4096};
+    for (int32_t it : items) {
+        for (int32_t bn : bins) {
+            if (s != PE_OK) break;
+            g_items_target = it;
+            g_min_group_bins = bn;
+            // one untimed run, then reps timed ones
+            s = pe_loglike_multi((int32_t)evv.size(), evv.data(), th.data(), nn.data(), precision, ll.data(),
+                                 nullptr, stream);
+            if (s != PE_OK) break;
+            if (hipEventRecord(a, st) != hipSuccess) s = fail(PE_ERR_HIP, "autotune record");
+            for (int r = 0; r < reps && s == PE_OK; ++r)
+                s = pe_loglike_multi((int32_t)evv.size(), evv.data(), th.data(), nn.data(), precision, ll.data(),
+                                     nullptr, stream);
+            float ms = 0.0f;
+            if (s == PE_OK && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                               hipEventElapsedTime(&ms, a, b) != hipSuccess))
+                s = fail(PE_ERR_HIP, "autotune timing");
+            if (s == PE_OK && ms / reps < best) {
+                best = ms / reps;
+                bi = it;
+                bb = bn;
+            }
+        }
+    }
+    g_items_target = keep_items;
+    g_min_group_bins = keep_bins;
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipStreamSynchronize(st);
+    for (double* p : ll) {
+        char* c = (char*)p;
+        dfree_bytes(c);
+    }
+    if (s != PE_OK) return s;
+    *best_items_target = bi;
+    *best_min_group_bins = bb;
+    *best_ms = best;
+    return PE_OK;
 }
 
 pe_status_t pe_set_chunks(int32_t n_chunks) {

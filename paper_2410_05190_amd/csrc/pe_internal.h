@@ -141,9 +141,12 @@ struct EvDev {
     double2 *partial;
     EvPlan *plan;
     int64_t npad;
-    int max_groups;  // partial capacity / npad
+    int max_groups;      // cap on the groups of chunks (partial capacity / npad)
+    int items_target;    // plan: work items the event's tiles x groups aim at
+    int min_group_bins;  // plan: bins per group at least
     int tile_lo, tile_hi;
     int flags;
+    int pad2;
     const double *theta;
     int64_t n;
     double *loglike, *aux;

@@ -367,27 +367,30 @@ __global__ __launch_bounds__(256) void k_metric_partial(const BatchHdr* __restri
     }
 }
 
-// Fixed-order sum of the block partials, phase projection (marginalised
-// likelihood) and prior regularisation; one workgroup per event.
-__global__ __launch_bounds__(128) void k_metric_final(const BatchHdr* __restrict__ hdr,
-                                                      const MetricArg* __restrict__ args) {
+// Fixed-order sum of the block partials (16 lanes per entry, each summing every
+// 16th block, then a butterfly over the 16), phase projection (marginalised
+// likelihood) and prior regularisation; one workgroup of 1024 per event.
+__global__ __launch_bounds__(1024) void k_metric_final(const BatchHdr* __restrict__ hdr,
+                                                       const MetricArg* __restrict__ args) {
     __shared__ double Gs[kMetricNG];
     const int ne = hdr->ne;
     const int t = threadIdx.x;
+    const int sub = t & 15;
     for (int e = blockIdx.x; e < ne; e += gridDim.x) {
         const MetricArg& A = args[e];
         const EvConst& ev = A.ec;
         const int D = ev.dim;
         const int DP = (ev.params == PE_PARAMS_4D) ? 5 : 11;
         const int NG = DP * (DP + 1) / 2;
-        if (t < NG) {
-            double acc[8];
-            for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-            const int nb = metric_blocks(ev.K);
-            for (int b = 0; b < nb; ++b) acc[b & 7] += A.mws[kMwsPart + (int64_t)b * kMetricNG + t];
-            for (int w = 4; w > 0; w >>= 1)
-                for (int q = 0; q < w; ++q) acc[q] += acc[q + w];
-            Gs[t] = acc[0];
+        const int nb = metric_blocks(ev.K);
+        for (int q0 = 0; q0 < NG; q0 += 64) {
+            const int q = q0 + (t >> 4);
+            double acc = 0.0;
+            if (q < NG)
+                for (int b = sub; b < nb; b += 16) acc += A.mws[kMwsPart + (int64_t)b * kMetricNG + q];
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+            if (q < NG && sub == 0) Gs[q] = acc;
         }
         __syncthreads();
         if (t == 0) {
@@ -438,7 +441,7 @@ hipError_t launch_metric_batch(const BatchPtrs& b, int ne, int64_t total_blocks,
     const MetricArg* args = (const MetricArg*)b.args;
     k_metric_setup<<<event_grid(ne), 32, 0, st>>>(b.hdr, args);
     k_metric_partial<<<stride_grid(total_blocks, 1, 8192), 256, 0, st>>>(b.hdr, args, b.off);
-    k_metric_final<<<event_grid(ne), 128, 0, st>>>(b.hdr, args);
+    k_metric_final<<<event_grid(ne), 1024, 0, st>>>(b.hdr, args);
     return hipGetLastError();
 }
 

@@ -103,9 +103,9 @@ __global__ __launch_bounds__(256) void k_b_support(const BatchHdr* __restrict__ 
 
 // One workgroup per event: exclusive scan of the bucket counts in place (4 per
 // thread), the live count, and the frequency decomposition of the hot loop:
-// ~16k work items for the event alone (groups a power of two up to 64), at least
-// 1024 bins per group, 8 chunks per group spread over [0, kmax), chunk length a
-// multiple of kBlk. kmax is the upper edge of the highest non-empty cut bucket:
+// about items_target work items for the event alone (groups a power of two up
+// to 64 and up to the cap), at least min_group_bins bins per group, 8 chunks
+// per group spread over [0, kmax), chunk length a multiple of kBlk. kmax is the upper edge of the highest non-empty cut bucket:
 // a bound on every live cut that follows from the event's own draws.
 __global__ __launch_bounds__(1024) void k_b_plan(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs) {
     __shared__ int sh[1024];
@@ -141,10 +141,10 @@ __global__ __launch_bounds__(1024) void k_b_plan(const BatchHdr* __restrict__ hd
                 const int sh_b = bucket_shift(E.ec.K);
                 const int64_t top = ((int64_t)(kBuckets - first) << sh_b);  // one past the top bucket's last cut
                 p.kmax = (int)(top < E.ec.K ? top : E.ec.K);
-                const int want = (16384 + p.tiles - 1) / p.tiles;
+                const int want = (E.items_target + p.tiles - 1) / p.tiles;
                 int G = 1;
                 while (G < want && G < 64) G <<= 1;
-                const int by_bins = max(1, p.kmax / 1024);
+                const int by_bins = max(1, p.kmax / E.min_group_bins);
                 G = min(G, min(by_bins, E.max_groups));
                 while (G & (G - 1)) G &= G - 1;  // a power of two
                 const int target = 8 * G;

@@ -247,6 +247,8 @@ void pe_server_s::admit() {
         vd.push_back(draw_arg(q->ev, q->d_theta0, q->d_g, q->r.seed, q->r.stream_id, q->r.n_draws, q->d_theta,
                               q->d_logq, q->d_logprior));
         EvDev l = loglike_arg(q->ev, q->d_theta, q->r.n_draws, q->d_loglike, nullptr);
+        if (cfg.items_target > 0) l.items_target = cfg.items_target;
+        if (cfg.min_group_bins > 0) l.min_group_bins = cfg.min_group_bins;
         l.flags = kLlPrologue;
         l.tile_lo = l.tile_hi = 0;
         if (cfg.max_groups > 0 && l.max_groups > cfg.max_groups) l.max_groups = cfg.max_groups;
@@ -443,6 +445,10 @@ pe_status_t pe_server_create(const pe_server_config_t* cfg, pe_server_t* out) {
     if (cfg->max_active < 1 || cfg->max_active > 4096) return fail(PE_ERR_ARG, "max_active must be in 1..4096");
     if (!(cfg->slice_ms > 0.0)) return fail(PE_ERR_ARG, "slice_ms must be > 0");
     if (cfg->max_groups < 0 || cfg->max_groups > 64) return fail(PE_ERR_ARG, "max_groups must be in 0..64");
+    if (cfg->items_target != 0 && (cfg->items_target < 256 || cfg->items_target > (1 << 20)))
+        return fail(PE_ERR_ARG, "items_target must be 0 or in 256..2^20");
+    if (cfg->min_group_bins != 0 && (cfg->min_group_bins < 32 || cfg->min_group_bins > (1 << 20)))
+        return fail(PE_ERR_ARG, "min_group_bins must be 0 or in 32..2^20");
     pe_server_s* s = new (std::nothrow) pe_server_s();
     if (!s) return fail(PE_ERR_OOM, "host allocation failed");
     s->cfg = *cfg;

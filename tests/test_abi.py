@@ -43,6 +43,9 @@ def test_binding_loads_and_pure_host_calls():
     assert L.pe_set_chunks(65) == 1
     assert L.pe_set_chunks(-1) == 1
     assert L.pe_set_chunks(0) == 0
+    assert L.pe_set_plan(100, 1024) == 1 and L.pe_set_plan(16384, 16) == 1
+    assert binding.pe_get_plan() == (16384, 1024)
+    assert L.pe_autotune_plan(0, None, None, None, 1, 0, None, None, None, None) == 1
     assert L.pe_loglike_batch(None, None, 0, 0, None, None, None) == 1
     # an empty multi-event batch is a no-op; bad arrays are rejected on the host
     assert L.pe_loglike_multi(0, None, None, None, 1, None, None, None) == 0
@@ -67,19 +70,21 @@ def test_batch_run_argument_errors_on_host():
 
 
 def test_server_structs_and_host_checks():
-    # pe_server_config_t: int64, 2 int32, double, 2 int32
-    assert ctypes.sizeof(binding.ServerConfig) == 8 + 8 + 8 + 8
+    # pe_server_config_t: int64, 2 int32, double, 4 int32
+    assert ctypes.sizeof(binding.ServerConfig) == 8 + 8 + 8 + 16
     # pe_request_t: desc, 2 pointers, 2 int32, pointer, uint64, uint32, int32, int64, 3 pointers
     assert ctypes.sizeof(binding.Request) == ctypes.sizeof(binding.EventDesc) + 16 + 8 + 8 + 8 + 8 + 8 + 24
     # pe_result_t: int64, 2 int32, 4 double, 3 double
     assert ctypes.sizeof(binding.Result) == 8 + 8 + 32 + 24
     L = binding.load()
     h = ctypes.c_void_p()
-    bad = binding.ServerConfig(1 << 10, 1, 16, 8.0, 1, 0)  # budget below 1 MiB
+    bad = binding.ServerConfig(1 << 10, 1, 16, 8.0, 1, 0, 0, 0)  # budget below 1 MiB
     assert L.pe_server_create(ctypes.byref(bad), ctypes.byref(h)) == 1 and h.value is None
-    bad = binding.ServerConfig(1 << 30, 1, 0, 8.0, 1, 0)  # no slots
+    bad = binding.ServerConfig(1 << 30, 1, 0, 8.0, 1, 0, 0, 0)  # no slots
     assert L.pe_server_create(ctypes.byref(bad), ctypes.byref(h)) == 1
-    bad = binding.ServerConfig(1 << 30, 1, 16, 0.0, 1, 0)  # no slice time
+    bad = binding.ServerConfig(1 << 30, 1, 16, 0.0, 1, 0, 0, 0)  # no slice time
+    assert L.pe_server_create(ctypes.byref(bad), ctypes.byref(h)) == 1
+    bad = binding.ServerConfig(1 << 30, 1, 16, 8.0, 1, 0, 100, 0)  # plan out of range
     assert L.pe_server_create(ctypes.byref(bad), ctypes.byref(h)) == 1
     assert L.pe_server_destroy(None) == 1
 

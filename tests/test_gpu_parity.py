@@ -416,6 +416,39 @@ def test_batch_run_whole_path_equals_single_event_calls():
         ev.close()
 
 
+def test_autotuned_plan_is_reproducible_and_within_tolerance():
+    """The autotuner returns a plan from its grid; under that plan the results are reproducible bit
+    for bit and agree with the oracle within the split bound; the library's plan is untouched by
+    the tuning itself."""
+    torch_cuda()
+    bs = [build_event(2, e) for e in range(3)]
+    evs, ths, keep = [], [], []
+    for i, b in enumerate(bs):
+        rc, th, lq, lp = b.ev.draw(b.theta_inj, b.ev.metric(b.theta_inj), 40 + i, 0, 3000 + 1000 * i)
+        ev, data, psd = upload_event(b)
+        evs.append(ev)
+        ths.append(th)
+        keep.append((data, psd))
+    dth = [dev(t) for t in ths]
+    before = binding.pe_get_plan()
+    it, mb, ms = binding.pe_autotune_plan(evs, dth, [t.shape[1] for t in ths], binding.PE_PREC_SPLIT, reps=1)
+    assert binding.pe_get_plan() == before
+    assert it in (4096, 8192, 16384, 32768, 65536) and mb in (256, 512, 1024, 2048, 4096) and ms > 0
+    note(f"autotuned plan: items_target {it}, min_group_bins {mb}, {ms:.3f} ms per batch")
+    try:
+        binding.pe_set_plan(it, mb)
+        a = [host(x) for x in binding.loglike_multi(evs, dth)]
+        c = [host(x) for x in binding.loglike_multi(evs, dth)]
+    finally:
+        binding.pe_set_plan(*before)
+    for b, t, x, y in zip(bs, ths, a, c):
+        assert np.array_equal(x, y)
+        live = np.flatnonzero(np.isfinite(x))[:40]
+        assert np.max(np.abs(x[live] - b.ev.loglike(t[:, live]))) <= 1e-3
+    for ev in evs:
+        ev.close()
+
+
 def test_long_signal_config4_full_size_sampled():
     """Config 4 at full size (3 detectors, K = 2 086 912, 262 144 draws, SNR up to 100): the FP64
     phase over ~1e5 rad and the split path's compensated FP32 sums against the oracle on sampled
