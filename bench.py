@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--serve-no-graph", action="store_true")
     ap.add_argument("--serve-no-baseline", action="store_true")
+    ap.add_argument("--drift-sample", type=int, default=-1,
+                    help="draws of the last step compared with the oracle (FP64-phase drift); -1: 1024 for config 4, "
+                         "else 0")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (HBM counter calibration)")
     return ap.parse_args()
@@ -218,6 +221,9 @@ def main():
                      "kernel_ms_avg": k_avg_s * 1e3, "kernel_launches": k_n, "ops_per_launch": ops_last},
     }
     first = evs[0]
+    n_drift = args.drift_sample if args.drift_sample >= 0 else (1024 if c == 4 else 0)
+    if n_drift > 0:
+        out["drift"] = drift_leg(first, n_drift, prec)
     for x in evs:
         x["ev"].close()
 
@@ -392,6 +398,49 @@ def serve_bench(args):
         print(f"serving baseline: p50 {out['baseline']['latency_ms']['p50']:.1f} ms "
               f"p99 {out['baseline']['latency_ms']['p99']:.1f} ms", file=sys.stderr, flush=True)
     return out
+
+
+def drift_leg(x, n_sample, prec):
+    """FP64-phase drift at this shape: on the first n_sample in-support draws of the last step, ln L
+    of the timed path and of the plain FP64 GPU path against the FP64 oracle (host threads), with the
+    phase-rounding bound of the FP64 comparison (2 x 16 u Phi_N sum_k |t_k| at the injection)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2410_05190_amd import binding
+
+    th_all = x["theta"].cpu().numpy()
+    ll_all = x["ll"].cpu().numpy()
+    live = np.flatnonzero(np.isfinite(ll_all))[:n_sample]
+    th = np.ascontiguousarray(th_all[:, live])
+    ll_fast = ll_all[live]
+    ll64 = torch.empty(live.size, dtype=torch.float64, device="cuda")
+    binding.pe_loglike_batch(x["ev"].handle, torch.from_numpy(th).cuda(), live.size, binding.PE_PREC_FP64, ll64)
+    ll64 = ll64.cpu().numpy()
+    d_h = x["data"].cpu().numpy()
+    p_h = x["psd"].cpu().numpy()
+    cm = x["common"]
+    ev = oracle.Event(d_h.shape[0], d_h.shape[1], cm["f_lo"], cm["df"], data=d_h, psd=p_h,
+                      strain_scale=cm["strain_scale"], params=cm["params"], phase=cm["phase"], amp0=x["amp0"],
+                      gmst=cm["gmst"], chi_max=cm["chi_max"], dl_max=cm["dl_max"], det_geom=cm["det_geom"])
+    t0 = time.perf_counter()
+    ll_o = ev.loglike(th, n_threads=os.cpu_count() or 1)
+    t1 = time.perf_counter()
+    h = ev.waveform(x["theta_inj"])
+    d = d_h.astype(np.complex128)
+    S = p_h.astype(np.float64)
+    sabs = float((4 * cm["df"] * np.abs(d) * np.abs(h) / S).sum())
+    phin = 3.0 / 128.0 * (math.pi * x["theta_inj"][0] * oracle.t_sun() * cm["f_lo"]) ** (-5.0 / 3.0)
+    bound = 2 * 16 * np.finfo(np.float64).eps * phin * sabs
+    df_ = np.abs(ll_fast - ll_o)
+    d64 = np.abs(ll64 - ll_o)
+    return {"draws": int(live.size), "oracle_s": t1 - t0, "phase_newtonian_rad_at_f_lo": 2 * math.pi * phin,
+            "timed_path": {"precision": "split" if prec == binding.PE_PREC_SPLIT else "fp64",
+                           "max_abs_dlnL": float(df_.max()), "median_abs_dlnL": float(np.median(df_)),
+                           "bound": 1e-3 if prec == binding.PE_PREC_SPLIT else bound},
+            "fp64_path": {"max_abs_dlnL": float(d64.max()), "median_abs_dlnL": float(np.median(d64)), "bound": bound},
+            "max_abs_lnL": float(np.abs(ll_o).max())}
 
 
 def cpu_baseline(c, n_sample, data, psd_t, theta_inj, amp0, common):
