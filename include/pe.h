@@ -167,8 +167,9 @@ pe_status_t pe_draw(pe_event_t ev, const double *theta0_dev, const double *g_dev
  * Z = sum_d R_d Z_d, H = sum_d |R_d|^2 C_{d,kcut} and
  * ln L = Re Z - H/2 (explicit) or ln I0(|Z|) - H/2 (marginalised).
  *   precision: PE_PREC_FP64 (every step in FP64) or PE_PREC_SPLIT (phase in
- *              FP64; reduced-phase sincos, products and partial sums in FP32
- *              with compensated accumulation; final combination in FP64).
+ *              FP64; reduced-phase sincos, products and sums over blocks of
+ *              16 bins in FP32, the block sums accumulated in FP64; final
+ *              combination in FP64).
  *   loglike_dev: [n]; out-of-support draws get -inf.
  *   aux_dev: NULL or [n][3] = Re Z, Im Z, H (zeros out of support).
  */

@@ -277,9 +277,13 @@ void release_area(Area& A) {
     A.shadow.clear();
 }
 
+size_t loglike_scratch_bytes(int ne, int redo_cap) {
+    return sizeof(int64_t) * kQueues * (ne + 1) + sizeof(int2) * (size_t)redo_cap;
+}
+
 pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const void* args, size_t arg_bytes,
                         const std::vector<int64_t>& off, const std::vector<int64_t>* off2, size_t scratch_bytes,
-                        hipStream_t st, BatchPtrs& out) {
+                        hipStream_t st, BatchPtrs& out, int redo_cap) {
     // a fixed area keeps one layout (sized for layout_ne records of
     // layout_rec bytes) so that its pointers never move
     const int lne = A.fixed ? A.layout_ne : ne;
@@ -305,6 +309,7 @@ pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const vo
     std::vector<char> img(o_scr, 0);
     BatchHdr h = {};
     h.ne = ne;
+    h.redo_cap = redo_cap;
     h.total = total;
     h.total2 = total2;
     std::memcpy(img.data(), &h, sizeof(h));
@@ -447,6 +452,7 @@ EvDev loglike_arg(const pe_event_s* ev, const double* theta, int64_t n, double* 
     d.hh = ev->hh;
     d.partial = ev->partial;
     d.plan = ev->plan;
+    d.status = ev->status;
     // Row stride and group cap follow from n alone (the workspace holds at
     // least this much), so a batch's plan does not depend on how large the
     // event's workspace happens to be.
@@ -478,8 +484,9 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     Area& A = area_for(st, kAreaLoglike);
     std::lock_guard<std::mutex> lk(A.mu);
     BatchPtrs b;
+    const int redo_cap = (int)std::min<int64_t>(foff[ne] * 256, kRedoCapMax);
     pe_status_t s = upload_area(A, ne, poff[ne], foff[ne], v.data(), sizeof(EvDev) * ne, poff, &foff,
-                                sizeof(int64_t) * kQueues * (ne + 1), st, b);
+                                loglike_scratch_bytes(ne, redo_cap), st, b, redo_cap);
     if (s != PE_OK) return s;
     PE_HIP(launch_loglike_batch(b, ne, poff[ne], foff[ne], precision, true, st));
     return PE_OK;
@@ -597,6 +604,8 @@ pe_status_t pe_event_status(pe_event_t ev, void* stream) {
     if (flags & kStBadPsd) return fail(PE_ERR_ARG, "PSD values must be positive and finite");
     if (flags & kStNonfinite) return fail(PE_ERR_NONFINITE, "data contains inf or nan");
     if (flags & kStSingular) return fail(PE_ERR_SINGULAR, "metric is not positive definite");
+    if (flags & kStRedoFull)
+        return fail(PE_ERR_BUDGET, "too many draws needed the FP64 re-evaluation of the split path");
     return PE_OK;
 }
 

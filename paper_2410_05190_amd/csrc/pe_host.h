@@ -77,7 +77,11 @@ pe_status_t reserve_area(Area& A, size_t bytes);
 void release_area(Area& A);
 pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const void* args, size_t arg_bytes,
                         const std::vector<int64_t>& off, const std::vector<int64_t>* off2, size_t scratch_bytes,
-                        hipStream_t st, BatchPtrs& out);
+                        hipStream_t st, BatchPtrs& out, int redo_cap = 0);
+
+// Scratch of a log-likelihood batch: the queue offsets for ne events and a
+// re-evaluation list of redo_cap entries.
+size_t loglike_scratch_bytes(int ne, int redo_cap);
 
 // Argument records of the batched stages.
 PrepArg prep_arg(const pe_event_s* ev, const void* data, const void* psd);

@@ -53,7 +53,7 @@ constexpr int kCoefTau = 10;  // tau_d = tc + dt_d, PE_MAX_DET rows
 constexpr int kNCoef = 14;
 
 constexpr int kTile = 256;    // draws per workgroup of the hot loop
-constexpr int kBlk = 32;      // bins per FP32 partial before the compensated fold
+constexpr int kBlk = 16;      // bins per FP32 block sum before its fold into FP64
 constexpr int kBuckets = 4096;  // ISCO-cut buckets of the draw ordering
 constexpr int kTabPad = 8;      // zeroed records past the last bin
 
@@ -61,6 +61,7 @@ constexpr int kTabPad = 8;      // zeroed records past the last bin
 constexpr int kStBadPsd = 1;
 constexpr int kStNonfinite = 2;
 constexpr int kStSingular = 4;
+constexpr int kStRedoFull = 8;  // the split path's FP64 re-evaluation list overflowed
 
 // Workspace of the metric: per FD source, coefficients, response and delays.
 constexpr int kMetricSrcStride = 32;  // doubles: A[8], B5, B6, rre[4], rim[4], tau[4], pad
@@ -140,6 +141,7 @@ struct EvDev {
     double *coef, *resp, *hh;
     double2 *partial;
     EvPlan *plan;
+    int *status;
     int64_t npad;
     int max_groups;      // cap on the groups of chunks (partial capacity / npad)
     int items_target;    // plan: work items the event's tiles x groups aim at
@@ -168,12 +170,27 @@ constexpr int kQueues = 8;
 // Header of a batch in device memory.
 struct BatchHdr {
     int ne;                // events
-    int pad;
+    int redo_cap;          // log-likelihood batches: capacity of the FP64 re-evaluation list
     int64_t total;         // flattened size (blocks)
     int64_t total2;        // second flattened size (blocks)
     int qitems[kQueues];   // hot-loop items per queue (written by k_b_items)
     int qnext[kQueues];    // queue counters
+    int redo_count;        // entries appended to the re-evaluation list (reset by k_b_items)
+    int pad;
 };
+
+// Split precision and the hardware sine/cosine of gfx950 (v_sin_f32 and
+// v_cos_f32 of a turn-based argument), measured over 2^24 arguments in
+// [-2, 2): at most 1.25e-7 off, and on average too small in magnitude by
+// 3.23e-8 (phase bias below 1e-10). The mean magnitude bias adds coherently
+// over a matched sum, so the split path scales its sums by kTrigGain; the rest
+// can still add coherently when the terms' phases align, by at most ~1e-7 of
+// sum_d |R_d| |Z_d|, so a draw whose sum exceeds kRedoMagnitude is re-evaluated
+// in FP64, which keeps |d ln L| below 1e-3 for every draw.
+constexpr double kTrigGain = 1.0 + 3.23e-8;
+constexpr double kRedoMagnitude = 6000.0;
+// Entries of the re-evaluation list in a batch's scratch, at most.
+constexpr int kRedoCapMax = 1 << 20;
 
 constexpr int kWBlock = 4096;  // draws per block of the weights reduction (256 threads x 16)
 

@@ -189,6 +189,7 @@ __global__ void k_b_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ 
     o[ne] = acc;
     hdr->qitems[x] = (int)acc;
     hdr->qnext[x] = 0;
+    if (x == 0) hdr->redo_count = 0;
 }
 
 // Live draws into their buckets; the order inside a bucket is immaterial.
@@ -254,14 +255,6 @@ __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
     return __builtin_amdgcn_readfirstlane(v);
-}
-
-// Kahan step: s - c tracks the sum, c holds the lost low part.
-__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
 }
 
 struct DrawRow {
@@ -382,9 +375,11 @@ __device__ __forceinline__ void split_item(const EvDev& E, const EvPlan& p, int 
     item_setup<NDET>(E, p.n_active, tile, j, valid, row, tau, kc, wmin, wmax);
     const Rec32* tab = E.rec32;
     const int K = (int)E.ec.K;
-    float sr[NDET], cr[NDET], si[NDET], ci[NDET];
+    // FP32 sums over blocks of kBlk bins, folded into FP64 accumulators (an FP64
+    // add costs one issue slot, as an FP32 one does without packed math).
+    double sr[NDET], si[NDET];
 #pragma unroll
-    for (int d = 0; d < NDET; ++d) sr[d] = cr[d] = si[d] = ci[d] = 0.0f;
+    for (int d = 0; d < NDET; ++d) sr[d] = si[d] = 0.0;
     // Blocks of kBlk bins sit on multiples of kBlk (chunks start on one), and a
     // lane folds a block only if the block starts below its own cut: a draw's
     // operations do not depend on the draws sharing its wave.
@@ -407,8 +402,8 @@ __device__ __forceinline__ void split_item(const EvDev& E, const EvPlan& p, int 
             }
 #pragma unroll
             for (int d = 0; d < NDET; ++d) {
-                kahan_add(sr[d], cr[d], br[d]);
-                kahan_add(si[d], ci[d], bi[d]);
+                sr[d] += (double)br[d];
+                si[d] += (double)bi[d];
             }
         }
         for (; kb < kB; kb += kBlk) {
@@ -423,17 +418,15 @@ __device__ __forceinline__ void split_item(const EvDev& E, const EvPlan& p, int 
             if (kb < kc) {
 #pragma unroll
                 for (int d = 0; d < NDET; ++d) {
-                    kahan_add(sr[d], cr[d], br[d]);
-                    kahan_add(si[d], ci[d], bi[d]);
+                    sr[d] += (double)br[d];
+                    si[d] += (double)bi[d];
                 }
             }
         }
     }
     if (valid) {
 #pragma unroll
-        for (int d = 0; d < NDET; ++d)
-            E.partial[((int64_t)g * NDET + d) * E.npad + j] =
-                make_double2((double)sr[d] - (double)cr[d], (double)si[d] - (double)ci[d]);
+        for (int d = 0; d < NDET; ++d) E.partial[((int64_t)g * NDET + d) * E.npad + j] = make_double2(sr[d], si[d]);
     }
 }
 
@@ -508,8 +501,9 @@ __global__ __launch_bounds__(256) void k_b_f64(BatchHdr* __restrict__ hdr, const
 
 // Fixed-order combine of the group partials (8 interleaved accumulators, then a
 // pairwise tree), then ln L of Eq. 3.
-__global__ __launch_bounds__(256) void k_b_finalize(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
-                                                    const int64_t* __restrict__ foff) {
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void k_b_finalize(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                    const int64_t* __restrict__ foff, int2* __restrict__ redo) {
     const int ne = hdr->ne;
     const int64_t nblk = foff[ne];
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
@@ -520,7 +514,7 @@ __global__ __launch_bounds__(256) void k_b_finalize(const BatchHdr* __restrict__
         if (j >= p.n_active) continue;
         const int64_t np = E.npad;
         const int nd = E.ec.n_det;
-        double zr = 0.0, zi = 0.0;
+        double zr = 0.0, zi = 0.0, mag = 0.0;
         for (int d = 0; d < nd; ++d) {
             double ar[8], ai[8];
 #pragma unroll
@@ -537,9 +531,22 @@ __global__ __launch_bounds__(256) void k_b_finalize(const BatchHdr* __restrict__
                     ar[q] += ar[q + w];
                     ai[q] += ai[q + w];
                 }
+                if (SPLIT) {
+                ar[0] *= kTrigGain;
+                ai[0] *= kTrigGain;
+            }
             const double rr = E.resp[(2 * d) * np + j], ri = E.resp[(2 * d + 1) * np + j];
             zr += rr * ar[0] - ri * ai[0];
             zi += rr * ai[0] + ri * ar[0];
+            mag += hypot(rr, ri) * hypot(ar[0], ai[0]);
+        }
+        if (SPLIT && mag > kRedoMagnitude) {
+            // too large for the split path's error bound: the FP64 pass rewrites this draw
+            const int slot = atomicAdd(&hdr->redo_count, 1);
+            if (slot < hdr->redo_cap)
+                redo[slot] = make_int2(e, (int)j);
+            else
+                atomicOr(E.status, kStRedoFull);
         }
         const double h = E.hh[j];
         const double ll = (E.ec.phase == PE_PHASE_EXPLICIT) ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
@@ -550,6 +557,84 @@ __global__ __launch_bounds__(256) void k_b_finalize(const BatchHdr* __restrict__
             E.aux[3 * i + 1] = zi;
             E.aux[3 * i + 2] = h;
         }
+    }
+}
+
+// FP64 re-evaluation of the draws the split finalize listed: one workgroup per
+// draw, lanes over its bins below the cut (FP64 phase, FP64 sincos, complex128
+// weights), a fixed-order reduction (wave butterfly, then the four waves), and
+// ln L as in the finalize.
+__global__ __launch_bounds__(256) void k_b_redo(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                const int2* __restrict__ redo) {
+    __shared__ double sh[4][2 * PE_MAX_DET];
+    const int n = min(hdr->redo_count, hdr->redo_cap);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = blockIdx.x; q < n; q += gridDim.x) {
+        const int2 r = redo[q];
+        const EvDev& E = evs[r.x];
+        const int64_t j = r.y;
+        const int64_t np = E.npad;
+        const int nd = E.ec.n_det;
+        DrawRow row;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) row.A[a] = E.coef[(kCoefA + a) * np + j];
+        row.B5 = E.coef[kCoefB5 * np + j];
+        row.B6 = E.coef[kCoefB6 * np + j];
+        double tau[PE_MAX_DET];
+#pragma unroll
+        for (int d = 0; d < PE_MAX_DET; ++d) tau[d] = (d < nd) ? E.coef[(kCoefTau + d) * np + j] : 0.0;
+        const int kc = E.kcut[j];
+        double zr[PE_MAX_DET], zi[PE_MAX_DET];
+#pragma unroll
+        for (int d = 0; d < PE_MAX_DET; ++d) zr[d] = zi[d] = 0.0;
+        for (int k = threadIdx.x; k < kc; k += 256) {
+            const Rec64 rc = E.rec64[k];
+            const double psi = psi_turns(row.A, row.B5, row.B6, rc.x, rc.xm5, rc.lnx);
+#pragma unroll
+            for (int d = 0; d < PE_MAX_DET; ++d) {
+                if (d >= nd) break;
+                double sn, cs;
+                sincos_turns(fract64(fma(rc.f, tau[d], psi)), sn, cs);
+                const double wr = rc.w[d].x, wi = rc.w[d].y;
+                zr[d] = fma(wr, cs, zr[d]);
+                zr[d] = fma(-wi, sn, zr[d]);
+                zi[d] = fma(-wr, sn, zi[d]);
+                zi[d] = fma(-wi, cs, zi[d]);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < PE_MAX_DET; ++d) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                zr[d] += __shfl_xor(zr[d], o);
+                zi[d] += __shfl_xor(zi[d], o);
+            }
+            if (lane == 0) {
+                sh[wv][2 * d] = zr[d];
+                sh[wv][2 * d + 1] = zi[d];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double Zr = 0.0, Zi = 0.0;
+            for (int d = 0; d < nd; ++d) {
+                const double ar = (sh[0][2 * d] + sh[1][2 * d]) + (sh[2][2 * d] + sh[3][2 * d]);
+                const double ai = (sh[0][2 * d + 1] + sh[1][2 * d + 1]) + (sh[2][2 * d + 1] + sh[3][2 * d + 1]);
+                const double rr = E.resp[(2 * d) * np + j], ri = E.resp[(2 * d + 1) * np + j];
+                Zr += rr * ar - ri * ai;
+                Zi += rr * ai + ri * ar;
+            }
+            const double h = E.hh[j];
+            const double ll = (E.ec.phase == PE_PHASE_EXPLICIT) ? Zr - 0.5 * h : log_i0(hypot(Zr, Zi)) - 0.5 * h;
+            const int64_t i = E.idx[j];
+            E.loglike[i] = ll;
+            if (E.aux) {
+                E.aux[3 * i] = Zr;
+                E.aux[3 * i + 1] = Zi;
+                E.aux[3 * i + 2] = h;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -613,7 +698,15 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
         k_b_f64<<<grid, kTile, 0, st>>>(b.hdr, evs, ioff);
         if (profile) prof_end("loglike_fp64", st);
     }
-    if (finalize_blocks > 0) k_b_finalize<<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2);
+    int2* redo = (int2*)(ioff + (int64_t)kQueues * (ne + 1));
+    if (finalize_blocks > 0) {
+        if (precision == PE_PREC_SPLIT) {
+            k_b_finalize<true><<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2, redo);
+            k_b_redo<<<grid_for(finalize_blocks, 2048), 256, 0, st>>>(b.hdr, evs, redo);
+        } else {
+            k_b_finalize<false><<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2, redo);
+        }
+    }
     return hipGetLastError();
 }
 

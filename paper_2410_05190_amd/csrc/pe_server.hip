@@ -24,6 +24,7 @@ namespace pe {
 namespace {
 
 constexpr int64_t kMaxServerDraws = (int64_t)1 << 22;
+constexpr int kServerRedoCap = 1 << 18;  // split-path FP64 re-evaluations per slice
 
 // First-fit allocator over one device slab in 256-byte granules; frees
 // coalesce with their neighbours.
@@ -358,7 +359,7 @@ pe_status_t pe_server_s::slice() {
     }
     BatchPtrs bll, bw;
     pe_status_t s = upload_area(a_ll, ne, poff[ne], foff[ne], vl.data(), sizeof(EvDev) * ne, poff, &foff,
-                                sizeof(int64_t) * kQueues * (cap_ne + 1), st, bll);
+                                loglike_scratch_bytes(cap_ne, kServerRedoCap), st, bll, kServerRedoCap);
     if (s == PE_OK)
         s = upload_area(a_w, nw, boff[nw], doff[nw], vw.data(), sizeof(WeightArg) * nw, boff, &doff,
                         sizeof(double4) * cap_wblocks + sizeof(double2) * cap_ne, st, bw);
@@ -377,6 +378,7 @@ pe_status_t pe_server_s::slice() {
         Req* q = fin[i];
         const int64_t n = q->r.n_draws;
         PE_HIP(hipMemcpyAsync(h_stage + 8 * i, q->d_stats, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        PE_HIP(hipMemcpyAsync(h_stage + 8 * i + 4, q->ev->status, sizeof(int), hipMemcpyDeviceToHost, st));
         if (q->r.loglike_out)
             PE_HIP(hipMemcpyAsync(q->r.loglike_out, q->d_loglike, n * sizeof(double), hipMemcpyDeviceToHost, st));
         if (q->r.w_out) PE_HIP(hipMemcpyAsync(q->r.w_out, q->d_w, n * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -401,6 +403,9 @@ pe_status_t pe_server_s::slice() {
     for (int i = 0; i < nw; ++i) {
         Req* q = fin[i];
         std::memcpy(q->res.stats, h_stage + 8 * i, 4 * sizeof(double));
+        int flags = 0;
+        std::memcpy(&flags, h_stage + 8 * i + 4, sizeof(int));
+        if ((flags & kStRedoFull) && q->res.status == PE_OK) q->res.status = PE_ERR_BUDGET;
         active.erase(std::find(active.begin(), active.end(), q));
         finish(q, q->res.status);
     }
@@ -479,7 +484,7 @@ pe_status_t pe_server_create(const pe_server_config_t* cfg, pe_server_t* out) {
     s->a_ll.layout_ne = s->a_w.layout_ne = s->cap_ne;
     s->a_ll.layout_rec = sizeof(EvDev);
     s->a_w.layout_rec = sizeof(WeightArg);
-    const size_t ll_bytes = fixed_area_bytes(s->cap_ne, sizeof(EvDev), sizeof(int64_t) * kQueues * (s->cap_ne + 1));
+    const size_t ll_bytes = fixed_area_bytes(s->cap_ne, sizeof(EvDev), loglike_scratch_bytes(s->cap_ne, kServerRedoCap));
     const size_t w_bytes = fixed_area_bytes(s->cap_ne, sizeof(WeightArg),
                                             sizeof(double4) * s->cap_wblocks + sizeof(double2) * s->cap_ne);
     if ((st = dalloc_bytes(&s->a_ll.dev, ll_bytes)) != PE_OK) return bail(st);

@@ -416,6 +416,87 @@ def test_batch_run_whole_path_equals_single_event_calls():
         ev.close()
 
 
+def test_batch_config2_full_size_sampled():
+    """Config 2 at full size in the benchmark's launch configuration: 64 BBH events with their
+    2^14..2^18 draws each (6.5 M draws, drawn by the oracle) through one pe_batch_run (metric,
+    log-likelihoods, weights as one launch set per stage, autotuned plan); the metric of every event
+    and ln L on 3 sampled draws per event against the oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+    torch = torch_cuda()
+    f64 = dict(dtype=torch.float64, device="cuda")
+    Ns = synth.n_draws_batch(2, 64)
+    bs = [build_event(2, e) for e in range(64)]
+    gs = [b.ev.metric(b.theta_inj) for b in bs]
+    with ThreadPoolExecutor(8) as pool:  # the oracle's draws release the GIL
+        draws = list(pool.map(lambda e: bs[e].ev.draw(bs[e].theta_inj, gs[e], synth.draw_seed(2, e), 0, Ns[e]),
+                              range(64)))
+    note(f"c2 full: {sum(Ns)} oracle draws")
+    evs, items, outs = [], [], []
+    for e, b in enumerate(bs):
+        ev, data, psd = upload_event(b)
+        rc, th, lq, lp = draws[e]
+        o = dict(th0=dev(b.theta_inj), g=torch.empty((11, 11), **f64), theta=dev(th), logq=dev(lq), logprior=dev(lp),
+                 ll=torch.empty(Ns[e], **f64), w=torch.empty(Ns[e], **f64), st=torch.empty(4, **f64), keep=(data, psd))
+        evs.append(ev)
+        outs.append(o)
+        items.append(binding.make_item(ev, n=Ns[e], theta0=o["th0"], g=o["g"], theta=o["theta"], logq=o["logq"],
+                                       logprior=o["logprior"], loglike=o["ll"], w=o["w"], stats=o["st"]))
+    before = binding.pe_get_plan()
+    it, mb, ms = binding.pe_autotune_plan(evs, [o["theta"] for o in outs], Ns, binding.PE_PREC_SPLIT, reps=1)
+    try:
+        binding.pe_set_plan(it, mb)
+        binding.pe_batch_run(items, binding.PE_STAGE_METRIC | binding.PE_STAGE_LOGLIKE | binding.PE_STAGE_WEIGHTS,
+                             binding.PE_PREC_SPLIT)
+        torch.cuda.synchronize()
+    finally:
+        binding.pe_set_plan(*before)
+    rng = np.random.default_rng(22)
+    worst_g, worst_l = 0.0, 0.0
+    for e, (b, o) in enumerate(zip(bs, outs)):
+        evs[e].status()
+        g = host(o["g"])
+        s = np.sqrt(np.outer(np.diag(gs[e]), np.diag(gs[e])))
+        worst_g = max(worst_g, float(np.max(np.abs(g - gs[e]) / s)))
+        ll = host(o["ll"])
+        rc, th, lq, lp = draws[e]
+        assert np.array_equal(np.isfinite(ll), np.isfinite(lp))
+        live = np.flatnonzero(np.isfinite(ll))
+        pick = rng.choice(live, 3, replace=False)
+        worst_l = max(worst_l, float(np.max(np.abs(ll[pick] - b.ev.loglike(th[:, pick])))))
+        st = host(o["st"])
+        assert st[3] == live.size and 1.0 <= st[0] <= live.size
+    note(f"c2 full: plan ({it}, {mb}); max metric error {worst_g:.2e} of sqrt(g_ii g_jj); "
+         f"max |dlnL| {worst_l:.2e} on 192 sampled draws")
+    assert worst_g <= 1e-6
+    assert worst_l <= 1e-3
+    for ev in evs:
+        ev.close()
+
+
+@pytest.mark.parametrize("cfg,event", [(2, 7), (1, 3)])
+def test_split_large_amplitude_draws_within_bound(cfg, event):
+    """Draws far louder than the data (distance shrunk up to 40-100x, so |Z| passes 1e4): the split
+    path's hardware sine/cosine error grows with the size of the coherent sum, so such draws are
+    re-evaluated in FP64 and every draw stays within the 1e-3 bound of the oracle."""
+    torch_cuda()
+    b = build_event(cfg, event, n_bins=None if cfg == 2 else 60000)
+    g = b.ev.metric(b.theta_inj)
+    rc, th, lq, lp = b.ev.draw(b.theta_inj, g, 5, 0, 400)
+    th = th.copy()
+    th[8] = b.theta_inj[8] / np.geomspace(1.0, 40.0 if cfg == 2 else 100.0, th.shape[1])
+    ev, data, psd = upload_event(b)
+    ll, ax = ev.loglike(dev(th), precision=binding.PE_PREC_SPLIT, aux=True)
+    ll, ax = host(ll), host(ax)
+    ev.status()
+    live = np.flatnonzero(np.isfinite(ll))
+    ll_o, zh = b.ev.loglike(th[:, live], return_zh=True)
+    d = np.abs(ll[live] - ll_o)
+    zmax = float(np.max(np.hypot(zh[:, 0], zh[:, 1])))
+    note(f"large-amplitude draws cfg {cfg}: |Z| up to {zmax:.3g}, max |dlnL| {d.max():.2e} over {live.size} draws")
+    assert zmax > 1e4
+    assert d.max() <= 1e-3
+
+
 def test_autotuned_plan_is_reproducible_and_within_tolerance():
     """The autotuner returns a plan from its grid; under that plan the results are reproducible bit
     for bit and agree with the oracle within the split bound; the library's plan is untouched by

@@ -20,6 +20,7 @@ SHAPES = [  # (config, event, n_det, n_bins, draws, host data)
     (0, 0, None, None, 2500, False),
     (2, 3, 3, None, 5000, False),
     (1, 4, 2, 25000, 1, True),
+    (1, 5, 3, None, 16384, False),  # full config-1 band (519 168 bins)
 ]
 
 
