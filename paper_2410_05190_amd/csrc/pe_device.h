@@ -95,13 +95,31 @@ __device__ __forceinline__ void antenna(const EvConst& ev, int d, double ra, dou
 
 __device__ __forceinline__ double f_isco(double M) { return 1.0 / (kSix32 * kPi * M * kTsun); }
 
+// Support of the prior and the total mass of theta: the part of the source
+// that the support mask, the ISCO cut and the prior need.
+__device__ __forceinline__ int mass_and_support(const EvConst& ev, const double* th, double& M) {
+    if (ev.params == PE_PARAMS_4D) {
+        const double mc = th[0], eta = th[1], chi = th[2];
+        M = mc * pow(eta, -0.6);
+        return (mc > 0.0) && (eta > 0.0) && (eta <= 0.25) && (fabs(chi) <= ev.chi_max);
+    }
+    const double mc = th[0], q = th[1], c1 = th[2], c2 = th[3];
+    const double dec = th[5], iota = th[6], dl = th[8];
+    const double opq = 1.0 + q;
+    M = mc * pow(opq, 1.2) * pow(q, -0.6);
+    return (mc > 0.0) && (q > 0.0) && (q <= 1.0) && (fabs(c1) <= ev.chi_max) && (fabs(c2) <= ev.chi_max) &&
+           (fabs(dec) <= 0.5 * kPi) && (iota >= 0.0) && (iota <= kPi) && (dl > 0.0) && (dl <= ev.dl_max);
+}
+
 // Support of the prior and the source parameters of theta (D values).
 __device__ __forceinline__ int source_from_theta(const EvConst& ev, const double* th, Src& s) {
     int ok;
+    double M;
+    ok = mass_and_support(ev, th, M);
+    s.M = M;
     if (ev.params == PE_PARAMS_4D) {
-        const double mc = th[0], eta = th[1], chi = th[2];
+        const double eta = th[1], chi = th[2];
         s.eta = eta;
-        s.M = mc * pow(eta, -0.6);
         s.delta = sqrt(fmax(0.0, 1.0 - 4.0 * eta));
         s.chis = chi;
         s.chia = 0.0;
@@ -114,13 +132,11 @@ __device__ __forceinline__ int source_from_theta(const EvConst& ev, const double
             s.rim[d] = 0.0;
             s.dt[d] = 0.0;
         }
-        ok = (mc > 0.0) && (eta > 0.0) && (eta <= 0.25) && (fabs(chi) <= ev.chi_max);
     } else {
         const double mc = th[0], q = th[1], c1 = th[2], c2 = th[3];
         const double ra = th[4], dec = th[5], iota = th[6], psi = th[7], dl = th[8];
         const double opq = 1.0 + q;
         s.eta = q / (opq * opq);
-        s.M = mc * pow(opq, 1.2) * pow(q, -0.6);
         s.delta = (1.0 - q) / opq;
         s.chis = 0.5 * (c1 + c2);
         s.chia = 0.5 * (c1 - c2);
@@ -138,8 +154,6 @@ __device__ __forceinline__ int source_from_theta(const EvConst& ev, const double
             s.rim[d] = -amp * fc * hx;
             s.dt[d] = dt;
         }
-        ok = (mc > 0.0) && (q > 0.0) && (q <= 1.0) && (fabs(c1) <= ev.chi_max) && (fabs(c2) <= ev.chi_max) &&
-             (fabs(dec) <= 0.5 * kPi) && (iota >= 0.0) && (iota <= kPi) && (dl > 0.0) && (dl <= ev.dl_max);
     }
     s.fisco = f_isco(s.M);
     s.ok = ok;

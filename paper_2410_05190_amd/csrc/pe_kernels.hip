@@ -483,6 +483,20 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
         for (int a = 0; a < D; ++a) logdet += log(L[a][a]);
     A.chol[PE_MAX_DIM * PE_MAX_DIM] = logdet;
     A.chol[PE_MAX_DIM * PE_MAX_DIM + 1] = ok ? 1.0 : 0.0;
+    // (L L^T) at the periodic coordinates (11-D: ra, psi, phic), for the image sum of log q
+    if constexpr (D == 11) {
+        constexpr int pidx[3] = {4, 7, 10};
+        int w = 0;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = p; q < 3; ++q) {
+                double gpq = 0.0;
+#pragma unroll
+                for (int r = 0; r < D; ++r) gpq += L[pidx[p]][r] * L[pidx[q]][r];
+                A.chol[PE_MAX_DIM * PE_MAX_DIM + 2 + w++] = ok ? gpq : 0.0;
+            }
+    }
     if (!ok) atomicOr(A.status, kStSingular);
 }
 
@@ -551,26 +565,30 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
 #pragma unroll
     for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th[a];
     // whitened offset of image m: L^T (x - theta0) = z + L^T s with
-    // s = (k - k0) P on the periodic rows
+    // s = (k - k0) P on the periodic rows, so its squared norm is
+    // |z|^2 + 2 s.a + s^T G s with a_p = (L^T row pidx_p) . z and G = L L^T there
+    double zz = 0.0;
+#pragma unroll
+    for (int r = 0; r < D; ++r) zz = fma(z[r], z[r], zz);
+    double a[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int r = 0; r <= pidx[p]; ++r) a[p] = fma(lc[pidx[p] * D + r], z[r], a[p]);
+    const double* G = lc + PE_MAX_DIM * PE_MAX_DIM + 2;  // G00 G01 G02 G11 G12 G22
     double mx = -INFINITY, acc = 0.0;
     constexpr int NIMG = (NP == 0) ? 1 : 27;
 #pragma unroll 1
     for (int m = 0; m < NIMG; ++m) {
-        double s[3] = {0.0, 0.0, 0.0};
-        int code = m;
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            s[p] = ((double)(code % 3 - 1) - k0[p]) * per[p];
-            code /= 3;
-        }
-        double qf = 0.0;
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            double v = z[r];
-#pragma unroll
-            for (int p = 0; p < NP; ++p)
-                if (pidx[p] >= r) v += lc[pidx[p] * D + r] * s[p];
-            qf += v * v;
+        double qf = zz;
+        if (NP == 3) {
+            const double s0 = ((double)(m % 3 - 1) - k0[0]) * per[0];
+            const double s1 = ((double)((m / 3) % 3 - 1) - k0[1]) * per[1];
+            const double s2 = ((double)(m / 9 - 1) - k0[2]) * per[2];
+            const double lin = s0 * a[0] + s1 * a[1] + s2 * a[2];
+            const double quad = s0 * (s0 * G[0] + 2.0 * (s1 * G[1] + s2 * G[2])) +
+                                s1 * (s1 * G[3] + 2.0 * s2 * G[4]) + s2 * s2 * G[5];
+            qf = zz + 2.0 * lin + quad;
         }
         const double l = -0.5 * qf;
         if (l > mx) {
@@ -581,8 +599,8 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
         }
     }
     A.logq[i] = mx + log(acc) + lc[PE_MAX_DIM * PE_MAX_DIM] - 0.5 * D * log(kTwoPi);
-    Src src;
-    const int ok = source_from_theta(ev, th, src);
+    double M;
+    const int ok = mass_and_support(ev, th, M);
     double lp = -INFINITY;
     if (ok) lp = (D == 4) ? 0.0 : log(cos(th[5])) + log(sin(th[6])) + 2.0 * log(th[8]);
     A.logprior[i] = lp;
@@ -591,14 +609,14 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
 // Blocks of 256 draws that each belong to one event (doff: block offsets).
 __global__ __launch_bounds__(256) void k_draw(const BatchHdr* __restrict__ hdr, const DrawArg* __restrict__ args,
                                               const int64_t* __restrict__ doff) {
-    __shared__ double lc[PE_MAX_DIM * PE_MAX_DIM + 2];
+    __shared__ double lc[PE_MAX_DIM * PE_MAX_DIM + 8];
     const int ne = hdr->ne;
     const int64_t nblk = doff[ne];
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         const int e = find_slot(doff, ne, b);
         const DrawArg& A = args[e];
         __syncthreads();  // the previous block's readers are done with lc
-        for (int q = threadIdx.x; q < PE_MAX_DIM * PE_MAX_DIM + 2; q += 256) lc[q] = A.chol[q];
+        for (int q = threadIdx.x; q < PE_MAX_DIM * PE_MAX_DIM + 8; q += 256) lc[q] = A.chol[q];
         __syncthreads();
         const int64_t i = (b - doff[e]) * 256 + threadIdx.x;
         if (i < A.n) {

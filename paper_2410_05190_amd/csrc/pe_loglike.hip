@@ -84,8 +84,8 @@ __global__ __launch_bounds__(256) void k_b_support(const BatchHdr* __restrict__ 
         if (i >= E.n) continue;
         double th[PE_MAX_DIM];
         gather_theta(E, i, th);
-        Src s;
-        if (!source_from_theta(E.ec, th, s)) {
+        double M;
+        if (!mass_and_support(E.ec, th, M)) {
             E.kc_all[i] = -1;
             E.loglike[i] = -INFINITY;
             if (E.aux) {
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_b_support(const BatchHdr* __restrict__ 
             }
             continue;
         }
-        const int kc = (int)kcut_of(E.ec, s.fisco);
+        const int kc = (int)kcut_of(E.ec, f_isco(M));
         E.kc_all[i] = kc;
         atomicAdd(&E.hist[(kBuckets - 1) - (kc >> bucket_shift(E.ec.K))], 1);
     }

@@ -258,6 +258,31 @@ def test_edge_cases_and_determinism():
     ev.status()
 
 
+@pytest.mark.parametrize("cfg,n_det,K", [(1, 4, 20000), (1, 3, 17), (1, 2, 1), (0, None, 6000), (2, 1, None)])
+def test_edge_shapes_parity(cfg, n_det, K):
+    """Shapes at the edges of the kernels' assumptions: four detectors (the maximum), a band shorter
+    than one FP32 block, a single bin, the 4-D parameter set through the split path, one detector.
+    Split within 1e-3 and FP64 within its derived bound of the oracle, on every draw."""
+    torch_cuda()
+    b = build_event(cfg, 0, n_det=n_det, n_bins=K)
+    # a diagonal proposal (the metric of a one-bin band is singular): 1% of each coordinate
+    scale = 0.01 * np.maximum(np.abs(b.theta_inj), 0.05)
+    rc, th, lq, lp = b.ev.draw(b.theta_inj, np.diag(1.0 / scale ** 2), 77, 0, 600)
+    assert rc == 0
+    ev, data, psd = upload_event(b)
+    ll_o = np.full(th.shape[1], -np.inf)
+    live = np.flatnonzero(np.isfinite(lp))
+    ll_o[live] = b.ev.loglike(th[:, live])
+    tol = fp64_tol(b)
+    for prec, bound in ((binding.PE_PREC_SPLIT, 1e-3), (binding.PE_PREC_FP64, max(tol, 1e-12))):
+        ll = host(ev.loglike(dev(th), precision=prec))
+        assert np.array_equal(np.isfinite(ll), np.isfinite(ll_o))
+        d = np.abs(ll[live] - ll_o[live]) if live.size else np.zeros(1)
+        note(f"edge cfg {cfg} n_det {b.n_det} K {b.n_bins} prec {prec}: max |dlnL| {d.max():.2e} (bound {bound:.1e})")
+        assert d.max() <= bound
+    ev.status()
+
+
 def test_event_input_errors():
     torch = torch_cuda()
     b = build_event(1, 0, n_bins=2000)
