@@ -69,35 +69,73 @@ __device__ __forceinline__ void gather_theta(const EvDev& E, int64_t i, double t
     for (int j = 0; j < PE_MAX_DIM; ++j) th[j] = (j < E.ec.dim) ? E.theta[(int64_t)j * E.n + i] : 0.0;
 }
 
+// Smallest and largest bucket of a block's live draws (bk < 0: none), for
+// every thread of the block. sh: 8 ints of shared memory.
+__device__ __forceinline__ void block_bucket_range(int bk, int* sh, int& lo, int& hi) {
+    int a = bk >= 0 ? bk : kBuckets, z = bk;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a = min(a, __shfl_xor(a, o));
+        z = max(z, __shfl_xor(z, o));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = a;
+        sh[4 + w] = z;
+    }
+    __syncthreads();
+    lo = min(min(sh[0], sh[1]), min(sh[2], sh[3]));
+    hi = max(max(sh[4], sh[5]), max(sh[6], sh[7]));
+    __syncthreads();
+}
+
 // Support mask, ISCO cut and cut bucket. Buckets run from the longest cut down,
 // so a wave of the hot loop holds draws whose cuts differ by less than one bucket.
 // Blocks of 256 draws that each belong to one event (poff: block offsets of
-// the events in their prologue).
+// the events in their prologue). The draws of an event crowd into few buckets,
+// so each block counts its own in shared memory over its bucket range and adds
+// the counts to the event's histogram once per bucket.
 __global__ __launch_bounds__(256) void k_b_support(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                    const int64_t* __restrict__ poff) {
+    __shared__ int lh[kBuckets];
+    __shared__ int sh[8];
     const int ne = hdr->ne;
     const int64_t nblk = poff[ne];
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         const int e = find_slot(poff, ne, b);
         const EvDev& E = evs[e];
         const int64_t i = (b - poff[e]) * 256 + threadIdx.x;
-        if (i >= E.n) continue;
-        double th[PE_MAX_DIM];
-        gather_theta(E, i, th);
-        double M;
-        if (!mass_and_support(E.ec, th, M)) {
-            E.kc_all[i] = -1;
-            E.loglike[i] = -INFINITY;
-            if (E.aux) {
-                E.aux[3 * i] = 0.0;
-                E.aux[3 * i + 1] = 0.0;
-                E.aux[3 * i + 2] = 0.0;
+        int bk = -1;
+        if (i < E.n) {
+            double th[PE_MAX_DIM];
+            gather_theta(E, i, th);
+            double M;
+            if (!mass_and_support(E.ec, th, M)) {
+                E.kc_all[i] = -1;
+                E.loglike[i] = -INFINITY;
+                if (E.aux) {
+                    E.aux[3 * i] = 0.0;
+                    E.aux[3 * i + 1] = 0.0;
+                    E.aux[3 * i + 2] = 0.0;
+                }
+            } else {
+                const int kc = (int)kcut_of(E.ec, f_isco(M));
+                E.kc_all[i] = kc;
+                bk = (kBuckets - 1) - (kc >> bucket_shift(E.ec.K));
             }
-            continue;
         }
-        const int kc = (int)kcut_of(E.ec, f_isco(M));
-        E.kc_all[i] = kc;
-        atomicAdd(&E.hist[(kBuckets - 1) - (kc >> bucket_shift(E.ec.K))], 1);
+        int lo, hi;
+        block_bucket_range(bk, sh, lo, hi);
+        if (hi < 0) continue;  // uniform: no live draw in the block
+        for (int q = lo + (int)threadIdx.x; q <= hi; q += 256) lh[q] = 0;
+        __syncthreads();
+        if (bk >= 0) atomicAdd(&lh[bk], 1);
+        __syncthreads();
+        for (int q = lo + (int)threadIdx.x; q <= hi; q += 256) {
+            const int c = lh[q];
+            if (c) atomicAdd(&E.hist[q], c);
+        }
+        __syncthreads();
     }
 }
 
@@ -192,20 +230,38 @@ __global__ void k_b_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ 
     if (x == 0) hdr->redo_count = 0;
 }
 
-// Live draws into their buckets; the order inside a bucket is immaterial.
+// Live draws into their buckets; the order inside a bucket is immaterial. A
+// block ranks its draws per bucket in shared memory and claims one run of
+// positions per bucket, so a block's draws of one bucket sit side by side.
 __global__ __launch_bounds__(256) void k_b_scatter(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                    const int64_t* __restrict__ poff) {
+    __shared__ int lh[kBuckets];
+    __shared__ int sh[8];
     const int ne = hdr->ne;
     const int64_t nblk = poff[ne];
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         const int e = find_slot(poff, ne, b);
         const EvDev& E = evs[e];
         const int64_t i = (b - poff[e]) * 256 + threadIdx.x;
-        if (i >= E.n) continue;
-        const int kc = E.kc_all[i];
-        if (kc < 0) continue;
-        const int pos = atomicAdd(&E.hist[(kBuckets - 1) - (kc >> bucket_shift(E.ec.K))], 1);
-        E.idx[pos] = (int)i;
+        int bk = -1;
+        if (i < E.n) {
+            const int kc = E.kc_all[i];
+            if (kc >= 0) bk = (kBuckets - 1) - (kc >> bucket_shift(E.ec.K));
+        }
+        int lo, hi;
+        block_bucket_range(bk, sh, lo, hi);
+        if (hi < 0) continue;
+        for (int q = lo + (int)threadIdx.x; q <= hi; q += 256) lh[q] = 0;
+        __syncthreads();
+        const int rank = bk >= 0 ? atomicAdd(&lh[bk], 1) : 0;
+        __syncthreads();
+        for (int q = lo + (int)threadIdx.x; q <= hi; q += 256) {
+            const int c = lh[q];
+            if (c) lh[q] = atomicAdd(&E.hist[q], c);
+        }
+        __syncthreads();
+        if (bk >= 0) E.idx[lh[bk] + rank] = (int)i;
+        __syncthreads();
     }
 }
 
