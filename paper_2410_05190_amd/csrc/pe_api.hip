@@ -125,10 +125,14 @@ int64_t groups_cap(int64_t np, int64_t K) {
 }
 
 // Partial slots per detector of a workspace for up to npad draws: enough for
-// any batch of np <= npad draws (np * groups_cap(np, K) never exceeds it).
-int64_t partial_cap_for(int64_t npad, int64_t K) {
-    return std::min<int64_t>(npad * std::min<int64_t>(64, std::max<int64_t>(1, K / 1024)),
-                             std::max<int64_t>((int64_t)1 << 22, npad));
+// any batch of np <= npad draws (np * groups_cap(np, K) never exceeds it), and
+// for the prologue's parameter records (kRecStride doubles per draw), which
+// use the same memory before the hot loop runs.
+int64_t partial_cap_for(int64_t npad, int64_t K, int n_det) {
+    const int64_t groups = std::min<int64_t>(npad * std::min<int64_t>(64, std::max<int64_t>(1, K / 1024)),
+                                             std::max<int64_t>((int64_t)1 << 22, npad));
+    const int64_t recs = (kRecStride * npad + 2 * n_det - 1) / (2 * n_det);
+    return std::max(groups, recs);
 }
 
 size_t layout_tables(pe_event_s* ev, char* base) {
@@ -147,7 +151,7 @@ size_t layout_tables(pe_event_s* ev, char* base) {
 size_t layout_ws(pe_event_s* ev, int64_t npad, char* base) {
     Carver c(base);
     const int nd = ev->desc.n_det;
-    const int64_t cap = partial_cap_for(npad, ev->desc.n_bins);
+    const int64_t cap = partial_cap_for(npad, ev->desc.n_bins, nd);
     ev->kc_all = c.take<int>((size_t)npad);
     ev->hist = c.take<int>((size_t)kBuckets);
     ev->plan = c.take<EvPlan>(1);

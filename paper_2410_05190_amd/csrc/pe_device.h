@@ -69,28 +69,44 @@ struct Src {
     int ok;
 };
 
-// Long-wavelength response F+, Fx of detector d and the arrival delay dt
-// (geocentre -> detector) for a source at (ra, dec) with polarisation psi.
-// The sky basis is (east, north) at the source direction, rotated by psi.
-__device__ __forceinline__ void antenna(const EvConst& ev, int d, double ra, double dec, double psi, double& fp,
-                                        double& fc, double& dt) {
+// Source direction n and polarisation axes X, Y for (ra, dec, psi): the sky
+// basis (east, north) at the source direction, rotated by psi.
+struct SkyFrame {
+    double n0, n1, n2, X0, X1, X2, Y0, Y1, Y2;
+};
+
+__device__ __forceinline__ SkyFrame sky_frame(const EvConst& ev, double ra, double dec, double psi) {
     double sl, cl, sd, cd, sp, cp;
     sincos(ra - ev.gmst, &sl, &cl);
     sincos(dec, &sd, &cd);
     sincos(psi, &sp, &cp);
-    const double n0 = cd * cl, n1 = cd * sl, n2 = sd;
+    SkyFrame f;
+    f.n0 = cd * cl;
+    f.n1 = cd * sl;
+    f.n2 = sd;
     const double u0 = -sl, u1 = cl;  // u2 = 0
     const double w0 = -sd * cl, w1 = -sd * sl, w2 = cd;
-    const double X0 = cp * u0 + sp * w0, X1 = cp * u1 + sp * w1, X2 = sp * w2;
-    const double Y0 = -sp * u0 + cp * w0, Y1 = -sp * u1 + cp * w1, Y2 = cp * w2;
+    f.X0 = cp * u0 + sp * w0;
+    f.X1 = cp * u1 + sp * w1;
+    f.X2 = sp * w2;
+    f.Y0 = -sp * u0 + cp * w0;
+    f.Y1 = -sp * u1 + cp * w1;
+    f.Y2 = cp * w2;
+    return f;
+}
+
+// Long-wavelength response F+, Fx of detector d and the arrival delay dt
+// (geocentre -> detector).
+__device__ __forceinline__ void antenna(const EvConst& ev, int d, const SkyFrame& f, double& fp, double& fc,
+                                        double& dt) {
     const double* D = ev.dtensor[d];  // xx xy xz yy yz zz
     auto quad = [&](double a0, double a1, double a2, double b0, double b1, double b2) {
         return D[0] * a0 * b0 + D[3] * a1 * b1 + D[5] * a2 * b2 + D[1] * (a0 * b1 + a1 * b0) +
                D[2] * (a0 * b2 + a2 * b0) + D[4] * (a1 * b2 + a2 * b1);
     };
-    fp = quad(X0, X1, X2, X0, X1, X2) - quad(Y0, Y1, Y2, Y0, Y1, Y2);
-    fc = 2.0 * quad(X0, X1, X2, Y0, Y1, Y2);
-    dt = -(kREarth / kC) * (ev.up[d][0] * n0 + ev.up[d][1] * n1 + ev.up[d][2] * n2);
+    fp = quad(f.X0, f.X1, f.X2, f.X0, f.X1, f.X2) - quad(f.Y0, f.Y1, f.Y2, f.Y0, f.Y1, f.Y2);
+    fc = 2.0 * quad(f.X0, f.X1, f.X2, f.Y0, f.Y1, f.Y2);
+    dt = -(kREarth / kC) * (ev.up[d][0] * f.n0 + ev.up[d][1] * f.n1 + ev.up[d][2] * f.n2);
 }
 
 __device__ __forceinline__ double f_isco(double M) { return 1.0 / (kSix32 * kPi * M * kTsun); }
@@ -147,9 +163,13 @@ __device__ __forceinline__ int source_from_theta(const EvConst& ev, const double
             kAmpNewt * pow(mc * kTsun, 5.0 / 6.0) / (dl * (kMpc / kC)) * ev.scale;
         const double ci = cos(iota);
         const double hp = 0.5 * (1.0 + ci * ci), hx = ci;
-        for (int d = 0; d < ev.n_det; ++d) {
+        const SkyFrame fr = sky_frame(ev, ra, dec, psi);
+        // fixed-bound loop, so the per-detector arrays stay in registers
+#pragma unroll
+        for (int d = 0; d < PE_MAX_DET; ++d) {
+            if (d >= ev.n_det) break;
             double fp, fc, dt;
-            antenna(ev, d, ra, dec, psi, fp, fc, dt);
+            antenna(ev, d, fr, fp, fc, dt);
             s.rre[d] = amp * fp * hp;  // F+ h+ + Fx hx, hx = -i cos(iota) A
             s.rim[d] = -amp * fc * hx;
             s.dt[d] = dt;

@@ -46,7 +46,7 @@ size_t tables_bytes(const pe_event_desc_t& d);
 size_t ws_bytes(const pe_event_desc_t& d, int64_t npad);
 size_t event_footprint(const pe_event_desc_t& d, int64_t max_draws);
 int64_t npad_for(int64_t n);
-int64_t partial_cap_for(int64_t npad, int64_t K);
+int64_t partial_cap_for(int64_t npad, int64_t K, int n_det);
 int64_t groups_cap(int64_t np, int64_t K);
 
 // New event laid out in `mem` (a range of event_footprint bytes, not owned)

@@ -51,6 +51,10 @@ constexpr int kCoefB5 = 8;
 constexpr int kCoefB6 = 9;
 constexpr int kCoefTau = 10;  // tau_d = tc + dt_d, PE_MAX_DET rows
 constexpr int kNCoef = 14;
+// Parameter records of the live draws in position order (doubles per draw),
+// written by the scatter into the partial buffer and read by the coefficients.
+constexpr int kRecStride = 12;
+static_assert(kRecStride >= PE_MAX_DIM, "a record holds one draw's parameters");
 
 constexpr int kTile = 256;    // draws per workgroup of the hot loop
 constexpr int kBlk = 16;      // bins per FP32 block sum before its fold into FP64

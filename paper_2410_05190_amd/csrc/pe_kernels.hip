@@ -93,10 +93,27 @@ __global__ __launch_bounds__(256) void k_prep(const BatchHdr* __restrict__ hdr, 
 }
 
 // Exclusive prefix C_k = sum_{j<k} pw_j (k = 0..K) per event and detector, in
-// two passes over kScanSeg contiguous segments: segment sums, then each
-// segment adds the sums before it (fixed order) and scans its bins in
-// coalesced 256-wide tiles (wave shuffle scan + LDS across the four waves).
-// Grid: (kScanSeg, PE_MAX_DET, events).
+// two passes over contiguous segments: segment sums, then each segment adds
+// the sums before it (fixed order) and scans its bins in coalesced 256-wide
+// tiles (wave shuffle scan + LDS across the four waves).
+// Grid: (kScanSeg, PE_MAX_DET, events); blocks past the event's segment or
+// detector count return at once.
+// Segments of the scan: at least 1024 bins each, at most kScanSeg of them.
+__device__ __forceinline__ void scan_layout(int64_t K, int64_t& seg, int& nseg) {
+    seg = max((int64_t)1024, (K + kScanSeg - 1) / kScanSeg);
+    nseg = (int)((K + seg - 1) / seg);
+}
+
+__device__ __forceinline__ double block_sum4(double s, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_seg_sums(const BatchHdr* __restrict__ hdr,
                                                   const PrepArg* __restrict__ args) {
     __shared__ double sh[4];
@@ -104,23 +121,23 @@ __global__ __launch_bounds__(256) void k_seg_sums(const BatchHdr* __restrict__ h
     const int d = blockIdx.y, b = blockIdx.x;
     for (int e = blockIdx.z; e < ne; e += gridDim.z) {
         const PrepArg& A = args[e];
-        if (d >= A.ec.n_det) continue;
         const int64_t K = A.ec.K;
-        const int64_t seg = (K + kScanSeg - 1) / kScanSeg;
+        int64_t seg;
+        int nseg;
+        scan_layout(K, seg, nseg);
+        if (d >= A.ec.n_det || b >= nseg) continue;
         const double* a = A.pw + (int64_t)d * K;
         const int64_t k0 = (int64_t)b * seg;
         const int64_t k1 = min(k0 + seg, K);
         double s = 0.0;
         for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) s += a[k];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) A.seg[d * kScanSeg + b] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-        __syncthreads();
+        s = block_sum4(s, sh);
+        if (threadIdx.x == 0) A.seg[d * kScanSeg + b] = s;
     }
 }
 
+// Each segment: its carry (the sum of the segment sums before it, one block
+// reduction), then a block-wide inclusive scan per 256 bins.
 __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ hdr,
                                                   const PrepArg* __restrict__ args) {
     __shared__ double sh[4];
@@ -129,13 +146,14 @@ __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ h
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int e = blockIdx.z; e < ne; e += gridDim.z) {
         const PrepArg& A = args[e];
-        if (d >= A.ec.n_det) continue;
         const int64_t K = A.ec.K;
-        const int64_t seg = (K + kScanSeg - 1) / kScanSeg;
+        int64_t seg;
+        int nseg;
+        scan_layout(K, seg, nseg);
+        if (d >= A.ec.n_det || b >= nseg) continue;
         const double* a = A.pw + (int64_t)d * K;
         double* o = A.pfx + (int64_t)d * (K + 1);
-        double carry = 0.0;
-        for (int i = 0; i < b; ++i) carry += A.seg[d * kScanSeg + i];
+        double carry = block_sum4((int)threadIdx.x < b ? A.seg[d * kScanSeg + threadIdx.x] : 0.0, sh);
         const int64_t k0 = (int64_t)b * seg;
         const int64_t k1 = min(k0 + seg, K);
         for (int64_t base = k0; base < k1; base += 256) {
@@ -158,7 +176,7 @@ __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ h
             if (k < k1) o[k] = carry + (woff + exc);
             carry += tile;
         }
-        if (b == kScanSeg - 1 && threadIdx.x == 0) o[K] = carry;
+        if (b == nseg - 1 && threadIdx.x == 0) o[K] = carry;
     }
 }
 
@@ -393,44 +411,40 @@ __global__ __launch_bounds__(1024) void k_metric_final(const BatchHdr* __restric
             if (q < NG && sub == 0) Gs[q] = acc;
         }
         __syncthreads();
-        if (t == 0) {
-            const int PH = (DP == D) ? D - 1 : D;
-            double M[kMetricMaxDp][kMetricMaxDp];
-            int q = 0;
-            for (int a = 0; a < DP; ++a)
-                for (int b = a; b < DP; ++b) {
-                    M[a][b] = M[b][a] = Gs[q];
-                    ++q;
+        // g_ab: one entry per thread, from the packed upper triangle (row a holds
+        // b = a .. DP-1); marginalised phase: the Schur complement of the phase
+        // coordinate PH; then the prior precision on the diagonal.
+        const int PH = (DP == D) ? D - 1 : D;
+        auto at = [&](int a, int b) {
+            const int lo = min(a, b), hi = max(a, b);
+            return Gs[lo * DP - lo * (lo - 1) / 2 + (hi - lo)];
+        };
+        if (t < D * D) {
+            const int a = t / D, b = t - (t / D) * D;
+            double m = at(a, b);
+            if (ev.phase == PE_PHASE_MARG) m = (a == PH || b == PH) ? 0.0 : m - at(a, PH) * at(PH, b) / at(PH, PH);
+            double reg = 0.0;
+            if (a == b && !(A.flags & 1)) {
+                if (ev.params == PE_PARAMS_4D) {
+                    reg = (a == 1) ? 12.0 / 0.0625 : (a == 2) ? 3.0 / (ev.chi_max * ev.chi_max) : 0.0;
+                } else {
+                    const double p2 = 3.0 / (kPi * kPi);  // 12 / (2 pi)^2
+                    const double p1 = 12.0 / (kPi * kPi);
+                    switch (a) {
+                        case 1: reg = 12.0; break;
+                        case 2:
+                        case 3: reg = 3.0 / (ev.chi_max * ev.chi_max); break;
+                        case 4:
+                        case 10: reg = p2; break;
+                        case 5:
+                        case 6:
+                        case 7: reg = p1; break;
+                        case 8: reg = 12.0 / (ev.dl_max * ev.dl_max); break;
+                        default: reg = 0.0;
+                    }
                 }
-            if (ev.phase == PE_PHASE_MARG) {
-                const double gpp = M[PH][PH];
-                double P[kMetricMaxDp][kMetricMaxDp];
-                for (int a = 0; a < DP; ++a)
-                    for (int b = 0; b < DP; ++b)
-                        P[a][b] = (a == PH || b == PH) ? 0.0 : M[a][b] - M[a][PH] * M[PH][b] / gpp;
-                for (int a = 0; a < DP; ++a)
-                    for (int b = 0; b < DP; ++b) M[a][b] = P[a][b];
             }
-            double reg[PE_MAX_DIM];
-            if (ev.params == PE_PARAMS_4D) {
-                reg[0] = 0.0;
-                reg[1] = 12.0 / 0.0625;
-                reg[2] = 3.0 / (ev.chi_max * ev.chi_max);
-                reg[3] = 0.0;
-            } else {
-                const double p2 = 3.0 / (kPi * kPi);  // 12 / (2 pi)^2
-                const double p1 = 12.0 / (kPi * kPi);
-                reg[0] = 0.0;
-                reg[1] = 12.0;
-                reg[2] = reg[3] = 3.0 / (ev.chi_max * ev.chi_max);
-                reg[4] = p2;
-                reg[5] = reg[6] = reg[7] = p1;
-                reg[8] = 12.0 / (ev.dl_max * ev.dl_max);
-                reg[9] = 0.0;
-                reg[10] = p2;
-            }
-            for (int a = 0; a < D; ++a)
-                for (int b = 0; b < D; ++b) A.g[a * D + b] = M[a][b] + ((a == b && !(A.flags & 1)) ? reg[a] : 0.0);
+            A.g[a * D + b] = m + reg;
         }
         __syncthreads();
     }
@@ -590,11 +604,13 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
                                 s1 * (s1 * G[3] + 2.0 * s2 * G[4]) + s2 * s2 * G[5];
             qf = zz + 2.0 * lin + quad;
         }
+        // exp of anything below -800 is exactly zero in FP64: skip those terms
         const double l = -0.5 * qf;
         if (l > mx) {
-            acc = acc * exp(mx - l) + 1.0;
+            const double dl = mx - l;
+            acc = (dl < -800.0) ? 1.0 : acc * exp(dl) + 1.0;
             mx = l;
-        } else {
+        } else if (l - mx >= -800.0) {
             acc += exp(l - mx);
         }
     }

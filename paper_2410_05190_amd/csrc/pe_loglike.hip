@@ -233,16 +233,25 @@ __global__ void k_b_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ 
 // Live draws into their buckets; the order inside a bucket is immaterial. A
 // block ranks its draws per bucket in shared memory and claims one run of
 // positions per bucket, so a block's draws of one bucket sit side by side.
+// The block then sorts its draws by position (bitonic, 256 keys) and writes
+// each live draw's parameters as one record of kRecStride doubles at its
+// position in the record buffer (the event's partial buffer, idle until the
+// hot loop), staged in shared memory so that consecutive lanes write
+// consecutive words; k_b_coeffs reads the records in position order.
 __global__ __launch_bounds__(256) void k_b_scatter(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                    const int64_t* __restrict__ poff) {
     __shared__ int lh[kBuckets];
     __shared__ int sh[8];
+    __shared__ unsigned long long key[256];
+    __shared__ double srec[256 * kRecStride];
     const int ne = hdr->ne;
+    const int t = threadIdx.x;
     const int64_t nblk = poff[ne];
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         const int e = find_slot(poff, ne, b);
         const EvDev& E = evs[e];
-        const int64_t i = (b - poff[e]) * 256 + threadIdx.x;
+        const int64_t i0 = (b - poff[e]) * 256;
+        const int64_t i = i0 + t;
         int bk = -1;
         if (i < E.n) {
             const int kc = E.kc_all[i];
@@ -251,16 +260,45 @@ __global__ __launch_bounds__(256) void k_b_scatter(const BatchHdr* __restrict__ 
         int lo, hi;
         block_bucket_range(bk, sh, lo, hi);
         if (hi < 0) continue;
-        for (int q = lo + (int)threadIdx.x; q <= hi; q += 256) lh[q] = 0;
+        for (int q = lo + t; q <= hi; q += 256) lh[q] = 0;
         __syncthreads();
         const int rank = bk >= 0 ? atomicAdd(&lh[bk], 1) : 0;
         __syncthreads();
-        for (int q = lo + (int)threadIdx.x; q <= hi; q += 256) {
+        for (int q = lo + t; q <= hi; q += 256) {
             const int c = lh[q];
             if (c) lh[q] = atomicAdd(&E.hist[q], c);
         }
         __syncthreads();
-        if (bk >= 0) E.idx[lh[bk] + rank] = (int)i;
+        key[t] = (bk >= 0) ? ((unsigned long long)(lh[bk] + rank) << 8) | (unsigned)t : ~0ull;
+        const int L = __syncthreads_count(bk >= 0);
+        for (int k = 2; k <= 256; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int p = t ^ j;
+                if (p > t) {
+                    const unsigned long long x = key[t], y = key[p];
+                    if ((x > y) == ((t & k) == 0)) {
+                        key[t] = y;
+                        key[p] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        if (t < L) {
+            const unsigned long long k = key[t];
+            const int64_t pos = (int64_t)(k >> 8);
+            const int64_t is = i0 + (int)(k & 255u);
+            E.idx[pos] = (int)is;
+            E.kcut[pos] = E.kc_all[is];
+#pragma unroll
+            for (int a = 0; a < kRecStride; ++a)
+                srec[t * kRecStride + a] = (a < E.ec.dim) ? E.theta[(int64_t)a * E.n + is] : 0.0;
+        }
+        __syncthreads();
+        double* rec = (double*)E.partial;
+        for (int w = t; w < L * kRecStride; w += 256) {
+            const int r = w / kRecStride;
+            rec[(int64_t)(key[r] >> 8) * kRecStride + (w - r * kRecStride)] = srec[w];
+        }
         __syncthreads();
     }
 }
@@ -274,10 +312,10 @@ __global__ __launch_bounds__(256) void k_b_coeffs(const BatchHdr* __restrict__ h
         const EvDev& E = evs[e];
         const int64_t j = (b - poff[e]) * 256 + threadIdx.x;
         if (j >= E.plan->n_active) continue;
-        const int64_t i = E.idx[j];
         const int64_t np = E.npad;
         double th[PE_MAX_DIM];
-        gather_theta(E, i, th);
+#pragma unroll
+        for (int a = 0; a < PE_MAX_DIM; ++a) th[a] = (a < E.ec.dim) ? ((const double*)E.partial)[j * kRecStride + a] : 0.0;
         Src s;
         source_from_theta(E.ec, th, s);
         PhaseCoef pc;
@@ -286,10 +324,11 @@ __global__ __launch_bounds__(256) void k_b_coeffs(const BatchHdr* __restrict__ h
         for (int a = 0; a < 8; ++a) E.coef[(kCoefA + a) * np + j] = pc.A[a];
         E.coef[kCoefB5 * np + j] = pc.B5;
         E.coef[kCoefB6 * np + j] = pc.B6;
-        const int64_t kc = E.kc_all[i];
-        E.kcut[j] = (int)kc;
+        const int64_t kc = E.kcut[j];
         double h = 0.0;
-        for (int d = 0; d < E.ec.n_det; ++d) {
+#pragma unroll
+        for (int d = 0; d < PE_MAX_DET; ++d) {
+            if (d >= E.ec.n_det) break;
             E.coef[(kCoefTau + d) * np + j] = s.tc + s.dt[d];
             E.resp[(2 * d) * np + j] = s.rre[d];
             E.resp[(2 * d + 1) * np + j] = s.rim[d];
