@@ -83,6 +83,8 @@ def lib():
         L.peo_logprior.restype = ctypes.c_double
         L.peo_logprior.argtypes = [ctypes.POINTER(_Event), _dp]
         L.peo_weights_ess.argtypes = [_dp, _dp, _dp, ctypes.c_long, _dp, _dp]
+        L.peo_proposal_update.restype = ctypes.c_long
+        L.peo_proposal_update.argtypes = [ctypes.POINTER(_Event), _dp, _dp, ctypes.c_long, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -225,6 +227,19 @@ class Event:
         lq = np.zeros(n)
         rc = lib().peo_logq_theta(self.ref, _p(th0), _p(gg), _p(th), n, _p(lq))
         return rc, lq
+
+    def proposal_update(self, theta0, theta, w):
+        """Weighted centre and covariance of the draws about theta0 (peo_proposal_update):
+        returns (theta0_new [D], cov [D, D], number of positive weights)."""
+        th0 = _f64(theta0)
+        th = _f64(theta)
+        ww = _f64(w)
+        n = ww.shape[0]
+        assert th.shape == (self.dim, n)
+        out = np.zeros(self.dim)
+        cov = np.zeros((self.dim, self.dim))
+        cnt = lib().peo_proposal_update(self.ref, _p(th0), _p(th), n, _p(ww), _p(out), _p(cov))
+        return out, cov, int(cnt)
 
     def logprior(self, theta):
         th = _f64(theta)

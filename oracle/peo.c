@@ -774,3 +774,79 @@ void peo_weights_ess(const double *ll, const double *lp, const double *lq, long 
     stats[2] = m;
     stats[3] = (double)nin;
 }
+
+/*
+ * Proposal update between rounds of importance sampling (Sec. III.A, end of
+ * the efficiency discussion: the proposal can be refined iteratively from the
+ * local metric around the sampled points). The new centre is the
+ * importance-weighted mean of the draws; the proposal around it is the metric
+ * there (peo_metric_fd at the new centre, by the caller).
+ * Offsets from the current centre, each periodic coordinate taken to its
+ * image nearest theta0: d_i = theta_i - theta0, d -> d - P floor(d/P + 1/2).
+ *   m      = sum_i w_i d_i / sum_i w_i
+ *   theta0' = theta0 + m, periodic coordinates wrapped into [0, P)
+ *   C      = sum_i w_i d_i d_i^T / sum_i w_i - m m^T   (D x D, row-major)
+ * Draws with w_i = 0 are skipped (their parameters may lie outside the
+ * support). With no positive weight theta0' = theta0 and C = 0. Weights need
+ * not be normalised. Returns the number of draws with w_i > 0.
+ */
+long peo_proposal_update(const peo_event *ev, const double *th0, const double *theta, long n, const double *w,
+                         double *th0_out, double *cov)
+{
+    const int D = peo_dim(ev->params);
+    int pidx[3], np, a, b;
+    double per[PEO_MAX_DIM];
+    nsum sw = {0, 0}, s1[PEO_MAX_DIM], s2[PEO_MAX_DIM * PEO_MAX_DIM];
+    long i, cnt = 0;
+    double pp[3];
+    np = periodic_dims(ev, pidx, pp);
+    for (a = 0; a < D; a++)
+        per[a] = 0.0;
+    for (a = 0; a < np; a++)
+        per[pidx[a]] = pp[a];
+    for (a = 0; a < D; a++)
+        s1[a].s = s1[a].c = 0.0;
+    for (a = 0; a < D * D; a++)
+        s2[a].s = s2[a].c = 0.0;
+    for (i = 0; i < n; i++) {
+        double d[PEO_MAX_DIM];
+        if (!(w[i] > 0.0))
+            continue;
+        cnt++;
+        for (a = 0; a < D; a++) {
+            double v = theta[(long)a * n + i] - th0[a];
+            if (per[a] > 0.0)
+                v -= per[a] * floor(v / per[a] + 0.5);
+            d[a] = v;
+        }
+        nadd(&sw, w[i]);
+        for (a = 0; a < D; a++) {
+            nadd(&s1[a], w[i] * d[a]);
+            for (b = 0; b < D; b++)
+                nadd(&s2[a * D + b], w[i] * d[a] * d[b]);
+        }
+    }
+    if (cnt == 0) {
+        for (a = 0; a < D; a++)
+            th0_out[a] = th0[a];
+        if (cov)
+            for (a = 0; a < D * D; a++)
+                cov[a] = 0.0;
+        return 0;
+    }
+    {
+        const double W = nval(&sw);
+        double m[PEO_MAX_DIM];
+        for (a = 0; a < D; a++) {
+            m[a] = nval(&s1[a]) / W;
+            th0_out[a] = th0[a] + m[a];
+            if (per[a] > 0.0)
+                th0_out[a] -= per[a] * floor(th0_out[a] / per[a]);
+        }
+        if (cov)
+            for (a = 0; a < D; a++)
+                for (b = 0; b < D; b++)
+                    cov[a * D + b] = nval(&s2[a * D + b]) / W - m[a] * m[b];
+    }
+    return cnt;
+}

@@ -128,6 +128,11 @@ double peo_logprior(const peo_event *ev, const double *theta);
 void peo_weights_ess(const double *loglike, const double *logprior, const double *logq, long n,
                      double *w, double *stats);
 
+/* Weighted centre and covariance of draws about theta0 (proposal update between
+ * rounds). theta0_out [D]; cov [D*D] or NULL. Returns the number of w > 0. */
+long peo_proposal_update(const peo_event *ev, const double *theta0, const double *theta, long n, const double *w,
+                         double *theta0_out, double *cov);
+
 #ifdef __cplusplus
 }
 #endif
