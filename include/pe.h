@@ -263,6 +263,46 @@ pe_status_t pe_weights_ess(const double *loglike_dev, const double *logprior_dev
 pe_status_t pe_waveform(const pe_event_desc_t *desc, const double *theta_dev, const void *psd_dev, double *h_dev,
                         double *snr2_dev, void *stream);
 
+/*
+ * Proposal update between rounds of importance sampling (Sec. III.A, end of
+ * the efficiency discussion: the proposal is refined iteratively from the
+ * local metric around the sampled points). The new centre is the weighted
+ * mean of the draws, the weighted covariance about it is returned for
+ * diagnostics; the proposal at the new centre is the metric there
+ * (pe_metric). Offsets from the current centre take each periodic
+ * coordinate (ra, psi, phic) to its image nearest theta0:
+ *   d_i = theta_i - theta0,  d -> d - P floor(d/P + 1/2)
+ *   m = sum_i w_i d_i / sum_i w_i,   theta0_out = theta0 + m (periodic
+ *       coordinates wrapped into [0, P))
+ *   cov = sum_i w_i d_i d_i^T / sum_i w_i - m m^T
+ * Draws with w_i = 0 are skipped (their parameters are not read into the
+ * sums); weights need not be normalised (pe_weights_ess's w is fine). With no
+ * positive weight theta0_out = theta0 and cov = 0. Sums in FP64, reduced in a
+ * fixed order (bitwise reproducible).
+ *   theta_dev [D][n], w_dev [n] (finite, >= 0), theta0_dev [D] (device).
+ *   theta0_out_dev [D] (may equal theta0_dev); cov_dev NULL or [D*D] row-major.
+ * Errors: PE_ERR_ARG (NULL pointers, n < 0), PE_ERR_OOM, PE_ERR_HIP.
+ */
+pe_status_t pe_proposal_update(pe_event_t ev, const double *theta_dev, const double *w_dev, int64_t n,
+                               const double *theta0_dev, double *theta0_out_dev, double *cov_dev, void *stream);
+
+/*
+ * Iterative proposal refinement: `rounds` rounds of
+ *   g = pe_metric(theta0); n draws (seed, stream_id = round); ln L (precision);
+ *   weights and ESS into stats_dev[4 r .. 4 r + 3]; theta0 = pe_proposal_update(...)
+ * followed by g = pe_metric(theta0) at the final centre. Everything is
+ * enqueued on `stream` (no host synchronisation). On return theta0_dev holds
+ * the refined centre and g_dev the metric there; the buffers hold the last
+ * round's draws (from the proposal before the last update).
+ *   theta0_dev [D] (in/out), g_dev [D*D] (out), theta_dev [D][n],
+ *   logq_dev, logprior_dev, loglike_dev, w_dev [n], stats_dev [rounds][4]
+ *   (all device, caller-owned). rounds 1..64.
+ * Errors: as the calls it makes; PE_ERR_ARG for rounds out of range.
+ */
+pe_status_t pe_refine(pe_event_t ev, double *theta0_dev, double *g_dev, int32_t rounds, int64_t n, uint64_t seed,
+                      int32_t precision, double *theta_dev, double *logq_dev, double *logprior_dev,
+                      double *loglike_dev, double *w_dev, double *stats_dev, void *stream);
+
 /* The proposal's uniforms: u_dev[(i*npairs + j)*2 + {0,1}] for draw i and
  * block j < npairs, exactly the values pe_draw uses. */
 pe_status_t pe_rng_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int32_t npairs, double *u_dev,

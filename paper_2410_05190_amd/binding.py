@@ -30,7 +30,7 @@ PE_F32 = 1
 MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
-           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_waveform",
+           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_proposal_update", "pe_refine", "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
            "pe_autotune_plan", "pe_last_error",
            "pe_server_create", "pe_server_submit", "pe_server_wait", "pe_server_now", "pe_server_counters",
@@ -117,6 +117,8 @@ def load(path=LIB_PATH):
         "pe_loglike_multi": (i32, [i32, vp, vp, vp, i32, vp, vp, vp]),
         "pe_batch_run": (i32, [i32, vp, i32, i32, vp]),
         "pe_weights_ess": (i32, [dp, dp, dp, i64, dp, dp, vp]),
+        "pe_proposal_update": (i32, [vp, dp, dp, i64, dp, dp, dp, vp]),
+        "pe_refine": (i32, [vp, dp, dp, i32, i64, u64, i32, dp, dp, dp, dp, dp, dp, vp]),
         "pe_waveform": (i32, [ctypes.POINTER(EventDesc), dp, vp, dp, dp, vp]),
         "pe_rng_uniforms": (i32, [u64, u32, i64, i32, dp, vp]),
         "pe_profile_enable": (i32, [i32]),
@@ -298,6 +300,23 @@ def pe_weights_ess(loglike, logprior, logq, n, w, stats, stream=None):
                                  _ptr(stats, f64, "stats"), _stream(stream)))
 
 
+def pe_proposal_update(ev, theta, w, n, theta0, theta0_out, cov=None, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(load().pe_proposal_update(ev, _ptr(theta, f64, "theta"), _ptr(w, f64, "w"), int(n),
+                                     _ptr(theta0, f64, "theta0"), _ptr(theta0_out, f64, "theta0_out"),
+                                     _ptr(cov, f64, "cov", allow_none=True), _stream(stream)))
+
+
+def pe_refine(ev, theta0, g, rounds, n, seed, precision, theta, logq, logprior, loglike, w, stats, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(load().pe_refine(ev, _ptr(theta0, f64, "theta0"), _ptr(g, f64, "g"), int(rounds), int(n),
+                            int(seed) & 0xFFFFFFFFFFFFFFFF, int(precision), _ptr(theta, f64, "theta"),
+                            _ptr(logq, f64, "logq"), _ptr(logprior, f64, "logprior"), _ptr(loglike, f64, "loglike"),
+                            _ptr(w, f64, "w"), _ptr(stats, f64, "stats"), _stream(stream)))
+
+
 def pe_waveform(desc, theta, psd, h, snr2=None, stream=None):
     import torch
     f64 = torch.float64
@@ -398,6 +417,26 @@ class Event:
         lp = torch.empty(n, dtype=torch.float64, device=dev)
         pe_draw(self.handle, theta0, g, seed, stream_id, n, theta, lq, lp, stream)
         return theta, lq, lp
+
+    def proposal_update(self, theta, w, theta0, cov=False, stream=None):
+        """pe_proposal_update: returns the new centre (and the weighted covariance if cov)."""
+        import torch
+        out = torch.empty(self.dim, dtype=torch.float64, device=theta0.device)
+        c = torch.empty((self.dim, self.dim), dtype=torch.float64, device=theta0.device) if cov else None
+        pe_proposal_update(self.handle, theta, w, theta.shape[1], theta0, out, c, stream)
+        return (out, c) if cov else out
+
+    def refine(self, theta0, rounds, n, seed, precision=PE_PREC_SPLIT, stream=None):
+        """pe_refine: returns (refined centre, metric there, per-round stats [rounds, 4])."""
+        import torch
+        dev = theta0.device
+        t0 = theta0.clone()
+        g = torch.empty((self.dim, self.dim), dtype=torch.float64, device=dev)
+        bufs = [torch.empty((self.dim, n), dtype=torch.float64, device=dev)] + \
+               [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
+        st = torch.empty((rounds, 4), dtype=torch.float64, device=dev)
+        pe_refine(self.handle, t0, g, rounds, n, seed, precision, *bufs, st, stream)
+        return t0, g, st
 
     def loglike(self, theta, precision=PE_PREC_SPLIT, aux=False, stream=None):
         import torch

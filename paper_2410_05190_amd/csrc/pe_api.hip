@@ -515,6 +515,21 @@ pe_status_t run_weights(const std::vector<WeightArg>& v, hipStream_t st) {
     return PE_OK;
 }
 
+pe_status_t run_update(const std::vector<UpdateArg>& v, hipStream_t st) {
+    const int ne = (int)v.size();
+    if (ne == 0) return PE_OK;
+    std::vector<int64_t> boff(ne + 1, 0);
+    for (int e = 0; e < ne; ++e) boff[e + 1] = boff[e] + (v[e].n + kWBlock - 1) / kWBlock;
+    Area& A = area_for(st, kAreaUpdate);
+    std::lock_guard<std::mutex> lk(A.mu);
+    BatchPtrs b;
+    const size_t scratch = sizeof(double) * kUpdNQ * std::max<int64_t>(boff[ne], 1);
+    pe_status_t s = upload_area(A, ne, boff[ne], 0, v.data(), sizeof(UpdateArg) * ne, boff, nullptr, scratch, st, b);
+    if (s != PE_OK) return s;
+    PE_HIP(launch_update_batch(b, ne, boff[ne], st));
+    return PE_OK;
+}
+
 int chunks_setting() { return g_chunks; }
 
 // ------------------------------------------------------------------ profiling
@@ -744,6 +759,42 @@ pe_status_t pe_weights_ess(const double* loglike_dev, const double* logprior_dev
     if (n > 0 && (!loglike_dev || !logprior_dev || !logq_dev)) return fail(PE_ERR_ARG, "inputs are NULL");
     WeightArg w = {loglike_dev, logprior_dev, logq_dev, n, w_dev, stats_dev};
     return run_weights(std::vector<WeightArg>(1, w), as_stream(stream));
+}
+
+pe_status_t pe_proposal_update(pe_event_t ev, const double* theta_dev, const double* w_dev, int64_t n,
+                               const double* theta0_dev, double* theta0_out_dev, double* cov_dev, void* stream) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    pe_status_t s = check_n(n);
+    if (s != PE_OK) return s;
+    if (!theta0_dev || !theta0_out_dev) return fail(PE_ERR_ARG, "theta0 and theta0_out must be device pointers");
+    if (n > 0 && (!theta_dev || !w_dev)) return fail(PE_ERR_ARG, "theta and w must be device pointers");
+    UpdateArg a = {theta_dev, w_dev, n, theta0_dev, theta0_out_dev, cov_dev, ev->ec.dim, ev->ec.params};
+    return run_update(std::vector<UpdateArg>(1, a), as_stream(stream));
+}
+
+pe_status_t pe_refine(pe_event_t ev, double* theta0_dev, double* g_dev, int32_t rounds, int64_t n, uint64_t seed,
+                      int32_t precision, double* theta_dev, double* logq_dev, double* logprior_dev,
+                      double* loglike_dev, double* w_dev, double* stats_dev, void* stream) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (rounds < 1 || rounds > 64) return fail(PE_ERR_ARG, "rounds must be in 1..64");
+    pe_status_t s = check_n(n);
+    if (s == PE_OK) s = check_precision(precision);
+    if (s != PE_OK) return s;
+    if (n < 1) return fail(PE_ERR_ARG, "n must be >= 1");
+    if (!theta0_dev || !g_dev || !theta_dev || !logq_dev || !logprior_dev || !loglike_dev || !w_dev || !stats_dev)
+        return fail(PE_ERR_ARG, "every buffer must be a device pointer");
+    for (int r = 0; r < rounds; ++r) {
+        if ((s = pe_metric(ev, theta0_dev, nullptr, 0, g_dev, stream)) != PE_OK) return s;
+        if ((s = pe_draw(ev, theta0_dev, g_dev, seed, (uint32_t)r, n, theta_dev, logq_dev, logprior_dev, stream)) !=
+            PE_OK)
+            return s;
+        if ((s = pe_loglike_batch(ev, theta_dev, n, precision, loglike_dev, nullptr, stream)) != PE_OK) return s;
+        if ((s = pe_weights_ess(loglike_dev, logprior_dev, logq_dev, n, w_dev, stats_dev + 4 * r, stream)) != PE_OK)
+            return s;
+        if ((s = pe_proposal_update(ev, theta_dev, w_dev, n, theta0_dev, theta0_dev, nullptr, stream)) != PE_OK)
+            return s;
+    }
+    return pe_metric(ev, theta0_dev, nullptr, 0, g_dev, stream);
 }
 
 pe_status_t pe_waveform(const pe_event_desc_t* desc, const double* theta_dev, const void* psd_dev, double* h_dev,

@@ -96,5 +96,6 @@ pe_status_t run_metric(const std::vector<MetricArg>& v, hipStream_t st);
 pe_status_t run_draw(const std::vector<DrawArg>& v, hipStream_t st);
 pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t st);
 pe_status_t run_weights(const std::vector<WeightArg>& v, hipStream_t st);
+pe_status_t run_update(const std::vector<UpdateArg>& v, hipStream_t st);
 
 }  // namespace pe

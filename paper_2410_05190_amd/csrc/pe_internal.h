@@ -167,6 +167,17 @@ struct WeightArg {
     double *w, *stats;
 };
 
+// Proposal update: sums of w, w d, w d d^T (upper triangle) per block of
+// kWBlock draws, then per event in a fixed order.
+constexpr int kUpdNQ = 1 + PE_MAX_DIM + PE_MAX_DIM * (PE_MAX_DIM + 1) / 2;  // 78
+struct UpdateArg {
+    const double *theta, *w;
+    int64_t n;
+    const double *th0;
+    double *th0_out, *cov;
+    int32_t dim, params;
+};
+
 // Hot-loop work queues: one per XCD (workgroup b of a launch runs on XCD
 // b mod kQueues).
 constexpr int kQueues = 8;
@@ -232,7 +243,15 @@ struct pe_event_s {
 namespace pe {
 
 // Kinds of batch areas.
-enum AreaKind { kAreaPrep = 0, kAreaMetric = 1, kAreaDraw = 2, kAreaLoglike = 3, kAreaWeights = 4, kAreaKinds = 5 };
+enum AreaKind {
+    kAreaPrep = 0,
+    kAreaMetric = 1,
+    kAreaDraw = 2,
+    kAreaLoglike = 3,
+    kAreaWeights = 4,
+    kAreaUpdate = 5,
+    kAreaKinds = 6
+};
 
 // Device pointers into an uploaded batch area.
 struct BatchPtrs {
@@ -258,6 +277,7 @@ hipError_t launch_loglike_batch(const BatchPtrs &b, int ne, int64_t prologue_blo
                                 int precision, bool profile, hipStream_t st);
 hipError_t launch_weights_batch(const BatchPtrs &b, int ne, int64_t total_blocks, int64_t total_draw_blocks,
                                 hipStream_t st);
+hipError_t launch_update_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
 void prime_hot_grids();
 hipError_t launch_waveform(const EvConst &ec, int data_psd_dtype, const double *theta, const void *psd, double *h,
                            double *snr2, double *scratch, hipStream_t st);

@@ -804,6 +804,129 @@ hipError_t launch_weights_batch(const BatchPtrs& b, int ne, int64_t total_blocks
 }
 
 // ===========================================================================
+// proposal update: weighted centre and covariance of the draws about theta0,
+// periodic offsets taken to the nearest image. Per block of kWBlock draws of
+// one event: sums of w, w d_a, w d_a d_b (a <= b), each thread over its draws
+// in order, then a wave shuffle tree and the four waves in a fixed order; per
+// event the blocks are combined in order.
+// ===========================================================================
+__device__ __forceinline__ double update_period(int params, int a) {
+    if (params == PE_PARAMS_4D) return 0.0;
+    return (a == 4 || a == 10) ? kTwoPi : (a == 7) ? kPi : 0.0;
+}
+
+template <int D>
+__device__ __forceinline__ void update_part(const UpdateArg& A, int64_t i0, int64_t i1, double* sh,
+                                            double* __restrict__ out) {
+    constexpr int NQ = 1 + D + D * (D + 1) / 2;
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    double th0[D], per[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        th0[a] = A.th0[a];
+        per[a] = update_period(A.params, a);
+    }
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double w = A.w[i];
+        if (!(w > 0.0)) continue;
+        double d[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double v = A.theta[(int64_t)a * A.n + i] - th0[a];
+            if (per[a] > 0.0) v -= per[a] * floor(v / per[a] + 0.5);
+            d[a] = v;
+        }
+        acc[0] += w;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double wd = w * d[a];
+            acc[1 + a] += wd;
+#pragma unroll
+            for (int b = a; b < D; ++b) acc[1 + D + a * D - a * (a - 1) / 2 + (b - a)] += wd * d[b];
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) sh[wv * kUpdNQ + q] = v;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < NQ; q += 256)
+        out[q] = (sh[q] + sh[kUpdNQ + q]) + (sh[2 * kUpdNQ + q] + sh[3 * kUpdNQ + q]);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_u_part(const BatchHdr* __restrict__ hdr, const UpdateArg* __restrict__ args,
+                                                const int64_t* __restrict__ boff, double* __restrict__ part) {
+    __shared__ double sh[4 * kUpdNQ];
+    const int ne = hdr->ne;
+    const int64_t nblk = boff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(boff, ne, b);
+        const UpdateArg& A = args[e];
+        const int64_t i0 = (b - boff[e]) * kWBlock;
+        const int64_t i1 = min(i0 + kWBlock, A.n);
+        if (A.dim == 4)
+            update_part<4>(A, i0, i1, sh, part + b * kUpdNQ);
+        else
+            update_part<11>(A, i0, i1, sh, part + b * kUpdNQ);
+    }
+}
+
+// One workgroup per event: block sums in order, then centre and covariance.
+// theta0 is read into shared memory before anything is written, so the
+// output may overwrite it.
+__global__ __launch_bounds__(256) void k_u_final(const BatchHdr* __restrict__ hdr, const UpdateArg* __restrict__ args,
+                                                 const int64_t* __restrict__ boff, const double* __restrict__ part) {
+    __shared__ double S[kUpdNQ];
+    __shared__ double c0[PE_MAX_DIM], m[PE_MAX_DIM];
+    const int ne = hdr->ne;
+    const int t = threadIdx.x;
+    for (int e = blockIdx.x; e < ne; e += gridDim.x) {
+        const UpdateArg& A = args[e];
+        const int D = A.dim;
+        const int NQ = 1 + D + D * (D + 1) / 2;
+        if (t < NQ) {
+            double acc = 0.0;
+            for (int64_t b = boff[e]; b < boff[e + 1]; ++b) acc += part[b * kUpdNQ + t];
+            S[t] = acc;
+        }
+        if (t < D) c0[t] = A.th0[t];
+        __syncthreads();
+        const double W = S[0];
+        if (t < D) {
+            const double mt = (W > 0.0) ? S[1 + t] / W : 0.0;
+            m[t] = mt;
+            double c = c0[t] + mt;
+            const double P = update_period(A.params, t);
+            if (W > 0.0 && P > 0.0) c -= P * floor(c / P);
+            A.th0_out[t] = (W > 0.0) ? c : c0[t];
+        }
+        __syncthreads();
+        if (A.cov && t < D * D) {
+            const int a = t / D, b = t - (t / D) * D;
+            const int lo = min(a, b), hi = max(a, b);
+            const double s2 = S[1 + D + lo * D - lo * (lo - 1) / 2 + (hi - lo)];
+            A.cov[t] = (W > 0.0) ? s2 / W - m[a] * m[b] : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_update_batch(const BatchPtrs& b, int ne, int64_t total_blocks, hipStream_t st) {
+    if (ne <= 0) return hipSuccess;
+    const UpdateArg* args = (const UpdateArg*)b.args;
+    k_u_part<<<stride_grid(total_blocks, 1, 8192), 256, 0, st>>>(b.hdr, args, b.off, b.scratch);
+    k_u_final<<<event_grid(ne), 256, 0, st>>>(b.hdr, args, b.off, b.scratch);
+    return hipGetLastError();
+}
+
+// ===========================================================================
 // waveform of one point (injections), and the proposal's uniforms
 // ===========================================================================
 __global__ void k_wave_setup(EvConst ev, const double* __restrict__ theta, double* __restrict__ scratch) {

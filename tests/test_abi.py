@@ -53,6 +53,13 @@ def test_binding_loads_and_pure_host_calls():
     assert L.pe_loglike_multi(0, None, None, None, 7, None, None, None) == 1
 
 
+def test_proposal_update_and_refine_argument_errors_on_host():
+    L = binding.load()
+    assert L.pe_proposal_update(None, None, None, 0, None, None, None, None) == 1
+    assert "event is NULL" in binding.pe_last_error()
+    assert L.pe_refine(None, None, None, 1, 16, 0, 1, None, None, None, None, None, None, None) == 1
+
+
 def test_batch_item_layout_matches_header():
     # pe_batch_item_t: 5 pointers, int32, uint32, uint64, pointer, int64, 7 pointers
     assert ctypes.sizeof(binding.BatchItem) == 5 * 8 + 4 + 4 + 8 + 8 + 8 + 7 * 8
