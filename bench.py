@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--drift-sample", type=int, default=-1,
                     help="draws of the last step compared with the oracle (FP64-phase drift); -1: 1024 for config 4, "
                          "else 0")
+    ap.add_argument("--refine-rounds", type=int, default=3,
+                    help="rounds of proposal refinement before the refined-proposal leg (0 skips the leg)")
+    ap.add_argument("--refine-draws", type=int, default=16384, help="draws per refinement round")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (HBM counter calibration)")
     return ap.parse_args()
@@ -221,6 +224,8 @@ def main():
                      "kernel_ms_avg": k_avg_s * 1e3, "kernel_launches": k_n, "ops_per_launch": ops_last},
     }
     first = evs[0]
+    if n_events == 1 and args.refine_rounds > 0:
+        out["refined"] = refine_leg(first, args.refine_rounds, args.refine_draws, max(args.steps, 1), prec)
     n_drift = args.drift_sample if args.drift_sample >= 0 else (1024 if c == 4 else 0)
     if n_drift > 0:
         out["drift"] = drift_leg(first, n_drift, prec)
@@ -233,6 +238,53 @@ def main():
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_sample, first["data"], first["psd"], first["theta_inj"],
                                            first["amp0"], first["common"])
     print(json.dumps(out), flush=True)
+
+
+def refine_leg(x, rounds, n_round, steps, prec):
+    """Proposal refinement (pe_refine: `rounds` rounds of metric, draws, likelihood, weights and
+    weighted-centre update from the injection-centred start), then `steps` full steps (event
+    update, metric, N draws, likelihood, weights) at the refined centre. ESS per event and ESS/s
+    of the refined proposal, with and without the refinement's own cost."""
+    import torch
+
+    from paper_2410_05190_amd import binding
+    h_ = x["ev"].handle
+    N = x["N"]
+    dev = x["theta0"].device
+    t0 = x["theta0"].clone()
+    g = torch.empty_like(x["g"])
+    st_r = torch.empty((rounds, 4), dtype=torch.float64, device=dev)
+    st_f = torch.empty((steps, 4), dtype=torch.float64, device=dev)
+    bufs = [torch.empty((x["ev"].dim, n_round), dtype=torch.float64, device=dev)] + \
+           [torch.empty(n_round, dtype=torch.float64, device=dev) for _ in range(4)]
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    binding.pe_refine(h_, t0, g, rounds, n_round, x["seed"] + 7, prec, *bufs, st_r)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for i in range(steps):
+        binding.pe_event_update(h_, x["data"], x["psd"])
+        binding.pe_metric(h_, t0, None, 0, g)
+        binding.pe_draw(h_, t0, g, x["seed"] + 11, i, N, x["theta"], x["lq"], x["lp"])
+        binding.pe_loglike_batch(h_, x["theta"], N, prec, x["ll"], None)
+        binding.pe_weights_ess(x["ll"], x["lp"], x["lq"], N, x["w"], st_f[i])
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    x["ev"].status()
+    sr = st_r.cpu().numpy()
+    sf = st_f.cpu().numpy()
+    ess_f = float(sf[:, 0].mean())
+    t_ref, t_step = tb - ta, (tc - tb) / steps
+    return {
+        "kind": "proposal recentred on the weighted mean of the draws, metric at the new centre (pe_refine)",
+        "rounds": rounds, "draws_per_round": n_round, "ess_per_round": [float(v) for v in sr[:, 0]],
+        "refine_ms": 1e3 * t_ref, "steps": steps, "draws_per_step": N, "ms_per_step": 1e3 * t_step,
+        "ess_per_event_mean": ess_f, "efficiency": ess_f / N,
+        "ess_per_s": ess_f / t_step,
+        "ess_per_s_with_refine": ess_f / (t_ref + t_step),
+        "evals_per_s": float(sf[:, 3].sum()) / (tc - tb),
+        "centre": [float(v) for v in t0.cpu().numpy()],
+    }
 
 
 def make_data(c, e, nd=None):
