@@ -32,6 +32,10 @@ class _Event(ctypes.Structure):
                 ("det_geom", (ctypes.c_double * 3) * MAX_DET)]
 
 
+class _Slice(ctypes.Structure):
+    _fields_ = [("centre", ctypes.c_double * 11), ("chol", ctypes.c_double * 121), ("radius", ctypes.c_double)]
+
+
 class _Source(ctypes.Structure):
     _fields_ = [("in_support", ctypes.c_int), ("mc", ctypes.c_double), ("M", ctypes.c_double),
                 ("eta", ctypes.c_double), ("delta", ctypes.c_double), ("chi1", ctypes.c_double),
@@ -83,6 +87,23 @@ def lib():
         L.peo_logprior.restype = ctypes.c_double
         L.peo_logprior.argtypes = [ctypes.POINTER(_Event), _dp]
         L.peo_weights_ess.argtypes = [_dp, _dp, _dp, ctypes.c_long, _dp, _dp]
+        _sp = ctypes.POINTER(_Slice)
+        _ip = ctypes.POINTER(ctypes.c_int)
+        _lp = ctypes.POINTER(ctypes.c_long)
+        L.peo_slice_candidate.restype = ctypes.c_int
+        L.peo_slice_candidate.argtypes = [ctypes.POINTER(_Event), _sp, ctypes.c_uint64, ctypes.c_uint32,
+                                          ctypes.c_uint64, _dp, _dp]
+        L.peo_slice_sample.restype = ctypes.c_long
+        L.peo_slice_sample.argtypes = [ctypes.POINTER(_Event), _sp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_long,
+                                       ctypes.c_long, _dp, _dp, _dp]
+        L.peo_tile_bank.restype = ctypes.c_long
+        L.peo_tile_bank.argtypes = [ctypes.POINTER(_Event), _sp, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                    ctypes.c_long, ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp, _dp, _lp]
+        L.peo_tile_assign.argtypes = [ctypes.c_int, ctypes.c_long, _dp, ctypes.c_long, ctypes.c_long, _dp,
+                                      ctypes.c_long, _ip]
+        L.peo_tile_draw.restype = ctypes.c_int
+        L.peo_tile_draw.argtypes = [ctypes.c_long, _dp, ctypes.c_long, _ip, _dp, ctypes.c_int, _dp, ctypes.c_long,
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_long, _dp, _dp, _dp, _lp]
         L.peo_proposal_update.restype = ctypes.c_long
         L.peo_proposal_update.argtypes = [ctypes.POINTER(_Event), _dp, _dp, ctypes.c_long, _dp, _dp, _dp]
         _lib = L
@@ -241,6 +262,32 @@ class Event:
         cnt = lib().peo_proposal_update(self.ref, _p(th0), _p(th), n, _p(ww), _p(out), _p(cov))
         return out, cov, int(cnt)
 
+    # ---- tile-mixture proposal ----
+    def slice_candidate(self, sl, seed, stream, i):
+        y = np.zeros(self.dim)
+        th = np.zeros(self.dim)
+        ok = lib().peo_slice_candidate(self.ref, ctypes.byref(sl), int(seed), int(stream), int(i), _p(y), _p(th))
+        return bool(ok), y, th
+
+    def slice_sample(self, sl, seed, stream, first, n):
+        """Kept candidates first..first+n-1 of the slice: (y [D, k], theta [D, k], logprior [k])."""
+        y = np.zeros((self.dim, n))
+        th = np.zeros((self.dim, n))
+        lp = np.zeros(n)
+        k = lib().peo_slice_sample(self.ref, ctypes.byref(sl), int(seed), int(stream), int(first), int(n), _p(y),
+                                   _p(th), _p(lp))
+        return y[:, :k].copy(), th[:, :k].copy(), lp[:k].copy()
+
+    def tile_bank(self, sl, min_dist, seed, stream, batch, max_tiles, stop_fraction, max_batches):
+        """Stochastic bank: (templates y [D, m], theta [D, m], candidates consumed)."""
+        ty = np.zeros((self.dim, max_tiles))
+        tth = np.zeros((self.dim, max_tiles))
+        used = ctypes.c_long(0)
+        m = lib().peo_tile_bank(self.ref, ctypes.byref(sl), float(min_dist), int(seed), int(stream), int(batch),
+                                int(max_tiles), float(stop_fraction), int(max_batches), _p(ty), _p(tth),
+                                ctypes.byref(used))
+        return ty[:, :m].copy(), tth[:, :m].copy(), int(used.value)
+
     def logprior(self, theta):
         th = _f64(theta)
         return lib().peo_logprior(self.ref, _p(th))
@@ -282,6 +329,48 @@ def uniforms(seed, stream, n, npairs):
     u = np.zeros((n, npairs, 2))
     lib().peo_uniforms(int(seed), int(stream), int(n), int(npairs), _p(u))
     return u
+
+
+def make_slice(centre, chol, radius):
+    """Slice of the prior: ball of `radius` in y = L^T (theta - centre), chol = lower L."""
+    sl = _Slice()
+    c = np.asarray(centre, dtype=np.float64)
+    Lm = np.asarray(chol, dtype=np.float64)
+    D = c.shape[0]
+    for a in range(D):
+        sl.centre[a] = float(c[a])
+        for b in range(D):
+            sl.chol[a * D + b] = float(Lm[a, b])
+    sl.radius = float(radius)
+    return sl
+
+
+def tile_assign(tiles_y, y):
+    """Nearest template (whitened distance, lowest index among equals) of every sample."""
+    ty = _f64(tiles_y)
+    yy = _f64(y)
+    D, m = ty.shape
+    n = yy.shape[1]
+    out = np.zeros(n, dtype=np.int32)
+    lib().peo_tile_assign(D, m, _p(ty), m, n, _p(yy), n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return out
+
+
+def tile_draw(tile_ll, tile_of, logprior, samples, seed, stream, n):
+    """Tile-mixture proposal draws: (rc, theta [D, n], logq, logprior, index)."""
+    tl = _f64(tile_ll)
+    to = np.ascontiguousarray(tile_of, dtype=np.int32)
+    lp = _f64(logprior)
+    sm = _f64(samples)
+    D, P = sm.shape
+    theta = np.zeros((D, n))
+    lq = np.zeros(n)
+    lpo = np.zeros(n)
+    idx = np.zeros(n, dtype=np.int64)
+    rc = lib().peo_tile_draw(tl.shape[0], _p(tl), P, to.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(lp), D,
+                             _p(sm), P, int(seed), int(stream), int(n), _p(theta), _p(lq), _p(lpo),
+                             idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
+    return rc, theta, lq, lpo, idx
 
 
 def weights_ess(loglike, logprior, logq):

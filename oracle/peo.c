@@ -850,3 +850,208 @@ long peo_proposal_update(const peo_event *ev, const double *th0, const double *t
     }
     return cnt;
 }
+
+/*
+ * Tile-mixture proposal (Sec. II.A: tile the metric space, give each tile the
+ * prior volume closest to its template, and propose from the tiles in
+ * proportion to that volume times the posterior at the template; App. A:
+ * template bank, tiling of the prior volume, proposal), on the slice of the
+ * prior a detection points to: the ball of radius R in whitened coordinates
+ * y = L^T (theta - c) of a metric G = L L^T around a centre c.
+ */
+
+/* Squared Euclidean distance of whitened points, summed in index order. */
+static double wdist2(int D, const double *a, long sa, const double *b, long sb)
+{
+    double s = 0.0;
+    int k;
+    for (k = 0; k < D; k++) {
+        double d = a[(long)k * sa] - b[(long)k * sb];
+        s += d * d;
+    }
+    return s;
+}
+
+/* Candidate i of the slice: y_a = R (2 u_a - 1) with u_a the (a mod 2)-th
+ * uniform of Philox block (seed, stream, i, a / 2); kept if |y|^2 <= R^2 and
+ * theta = c + L^-T y lies in the prior's support. Returns 1 if kept. */
+int peo_slice_candidate(const peo_event *ev, const peo_slice *sl, uint64_t seed, uint32_t stream, uint64_t i,
+                        double *y, double *theta)
+{
+    const int D = peo_dim(ev->params);
+    double u[PEO_MAX_DIM + 1], x[PEO_MAX_DIM], r2 = 0.0;
+    peo_source src;
+    int a, r, c;
+    for (a = 0; 2 * a < D; a++)
+        block_uniforms(seed, stream, i, (uint32_t)a, &u[2 * a], &u[2 * a + 1]);
+    for (a = 0; a < D; a++) {
+        y[a] = sl->radius * (2.0 * u[a] - 1.0);
+        r2 += y[a] * y[a];
+    }
+    /* theta - c = L^-T y: back substitution with L^T */
+    for (r = D - 1; r >= 0; r--) {
+        double t = y[r];
+        for (c = r + 1; c < D; c++)
+            t -= sl->chol[c * D + r] * x[c];
+        x[r] = t / sl->chol[r * D + r];
+    }
+    for (a = 0; a < D; a++)
+        theta[a] = sl->centre[a] + x[a];
+    if (!(r2 <= sl->radius * sl->radius))
+        return 0;
+    return peo_source_from_theta(ev, theta, &src) ? 1 : 0;
+}
+
+/* The kept candidates among first .. first + n - 1, in order: y, theta
+ * [D][n] (row stride n), logprior [n]. Returns how many were kept. */
+long peo_slice_sample(const peo_event *ev, const peo_slice *sl, uint64_t seed, uint32_t stream, long first, long n,
+                      double *y, double *theta, double *logprior)
+{
+    const int D = peo_dim(ev->params);
+    long i, k = 0;
+    int a;
+    for (i = 0; i < n; i++) {
+        double yy[PEO_MAX_DIM], th[PEO_MAX_DIM];
+        if (!peo_slice_candidate(ev, sl, seed, stream, (uint64_t)(first + i), yy, th))
+            continue;
+        for (a = 0; a < D; a++) {
+            y[(long)a * n + k] = yy[a];
+            theta[(long)a * n + k] = th[a];
+        }
+        logprior[k] = peo_logprior(ev, th);
+        k++;
+    }
+    return k;
+}
+
+/* Stochastic template bank in the slice (App. A, template bank generation;
+ * the stochastic placement the paper uses, in its plain form): candidates in
+ * order (consecutive counters from 0, batches of `batch`), a kept candidate
+ * becomes a template when its whitened squared distance to every template so
+ * far is at least min_dist^2. Stops after the first batch that adds fewer
+ * than stop_fraction * (kept candidates of the batch), when max_tiles
+ * templates exist, or after max_batches batches. Templates: y, theta
+ * [D][max_tiles] (row stride max_tiles). Returns the number of templates;
+ * *consumed = candidates drawn. */
+long peo_tile_bank(const peo_event *ev, const peo_slice *sl, double min_dist, uint64_t seed, uint32_t stream,
+                   long batch, long max_tiles, double stop_fraction, long max_batches, double *ty, double *tth,
+                   long *consumed)
+{
+    const int D = peo_dim(ev->params);
+    const double r2 = min_dist * min_dist;
+    long m = 0, b, i;
+    int a;
+    *consumed = 0;
+    for (b = 0; b < max_batches && m < max_tiles; b++) {
+        long kept = 0, added = 0;
+        for (i = 0; i < batch && m < max_tiles; i++) {
+            double yy[PEO_MAX_DIM], th[PEO_MAX_DIM];
+            long j, ok = 1;
+            const uint64_t ci = (uint64_t)(b * batch + i);
+            *consumed = (long)ci + 1;
+            if (!peo_slice_candidate(ev, sl, seed, stream, ci, yy, th))
+                continue;
+            kept++;
+            for (j = 0; j < m; j++)
+                if (wdist2(D, yy, 1, ty + j, max_tiles) < r2) {
+                    ok = 0;
+                    break;
+                }
+            if (!ok)
+                continue;
+            for (a = 0; a < D; a++) {
+                ty[(long)a * max_tiles + m] = yy[a];
+                tth[(long)a * max_tiles + m] = th[a];
+            }
+            m++;
+            added++;
+        }
+        if (m >= max_tiles || (double)added < stop_fraction * (double)kept)
+            break;
+    }
+    return m;
+}
+
+/* Tile of each sample: the template nearest in whitened coordinates, the
+ * lowest index among equals. tiles [D][ld_t], samples [D][ld_s]. */
+void peo_tile_assign(int D, long n_tiles, const double *ty, long ld_t, long n, const double *y, long ld_s,
+                     int *tile_of)
+{
+    long s, j;
+    for (s = 0; s < n; s++) {
+        long best = 0;
+        double bd = wdist2(D, y + s, ld_s, ty, ld_t);
+        for (j = 1; j < n_tiles; j++) {
+            double d = wdist2(D, y + s, ld_s, ty + j, ld_t);
+            if (d < bd) {
+                bd = d;
+                best = j;
+            }
+        }
+        tile_of[s] = (int)best;
+    }
+}
+
+/* Proposal draws: sample s carries mass m_s = exp(ll_{t(s)} - max ll + lp_s -
+ * max lp) (its tile's likelihood times its prior density; 0 if either is
+ * -inf); draw i takes the first uniform u of Philox block (seed, stream, i, 0)
+ * and the smallest s with u C_P <= C_s, C_s = m_0 + ... + m_s (compensated).
+ * theta_i = sample s, logprior_i = lp_s, logq_i = ln m_s - ln(C_P / P): the
+ * proposal density relative to the flat measure the samples were drawn from
+ * (each sample 1/P there, m_s / C_P here). index_i = s. With no positive mass: logprior -inf, logq 0,
+ * index -1, theta = sample 0; returns 5. Else returns 0. */
+int peo_tile_draw(long n_tiles, const double *tile_ll, long P, const int *tile_of, const double *lp, int D,
+                  const double *samples, long ld, uint64_t seed, uint32_t stream, long n, double *theta,
+                  double *logq, double *logprior, long *index)
+{
+    double lmax = -INFINITY, pmax = -INFINITY, tot;
+    double *C;
+    nsum acc = {0, 0};
+    long s, i, j;
+    int a;
+    for (j = 0; j < n_tiles; j++)
+        if (isfinite(tile_ll[j]) && tile_ll[j] > lmax)
+            lmax = tile_ll[j];
+    for (s = 0; s < P; s++)
+        if (isfinite(lp[s]) && lp[s] > pmax)
+            pmax = lp[s];
+    C = (double *)malloc(sizeof(double) * (P > 0 ? P : 1));
+    for (s = 0; s < P; s++) {
+        const double l = tile_ll[tile_of[s]];
+        const double m = (isfinite(l) && isfinite(lp[s])) ? exp((l - lmax) + (lp[s] - pmax)) : 0.0;
+        nadd(&acc, m);
+        C[s] = nval(&acc);
+    }
+    tot = P > 0 ? C[P - 1] : 0.0;
+    for (i = 0; i < n; i++) {
+        double u, u2;
+        block_uniforms(seed, stream, (uint64_t)i, 0, &u, &u2);
+        if (!(tot > 0.0)) {
+            for (a = 0; a < D; a++)
+                theta[(long)a * n + i] = P > 0 ? samples[(long)a * ld] : 0.0;
+            logq[i] = 0.0;
+            logprior[i] = -INFINITY;
+            index[i] = -1;
+            continue;
+        }
+        {
+            const double target = u * tot;
+            long lo = 0, hi = P - 1;
+            while (lo < hi) { /* smallest s with target <= C_s */
+                long mid = lo + (hi - lo) / 2;
+                if (target <= C[mid])
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            s = lo;
+        }
+        for (a = 0; a < D; a++)
+            theta[(long)a * n + i] = samples[(long)a * ld + s];
+        logprior[i] = lp[s];
+        logq[i] = ((tile_ll[tile_of[s]] - lmax) + (lp[s] - pmax)) - log(tot / (double)P);
+        index[i] = s;
+    }
+    free(C);
+    return tot > 0.0 ? 0 : 5;
+}

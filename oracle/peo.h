@@ -128,6 +128,27 @@ double peo_logprior(const peo_event *ev, const double *theta);
 void peo_weights_ess(const double *loglike, const double *logprior, const double *logq, long n,
                      double *w, double *stats);
 
+/* Slice of the prior: the ball |y| <= radius in whitened coordinates
+ * y = L^T (theta - centre), G = L L^T (chol: row-major lower L). */
+typedef struct {
+    double centre[PEO_MAX_DIM];
+    double chol[PEO_MAX_DIM * PEO_MAX_DIM];
+    double radius;
+} peo_slice;
+
+int peo_slice_candidate(const peo_event *ev, const peo_slice *sl, uint64_t seed, uint32_t stream, uint64_t i,
+                        double *y, double *theta);
+long peo_slice_sample(const peo_event *ev, const peo_slice *sl, uint64_t seed, uint32_t stream, long first, long n,
+                      double *y, double *theta, double *logprior);
+long peo_tile_bank(const peo_event *ev, const peo_slice *sl, double min_dist, uint64_t seed, uint32_t stream,
+                   long batch, long max_tiles, double stop_fraction, long max_batches, double *ty, double *tth,
+                   long *consumed);
+void peo_tile_assign(int D, long n_tiles, const double *ty, long ld_t, long n, const double *y, long ld_s,
+                     int *tile_of);
+int peo_tile_draw(long n_tiles, const double *tile_ll, long P, const int *tile_of, const double *lp, int D,
+                  const double *samples, long ld, uint64_t seed, uint32_t stream, long n, double *theta,
+                  double *logq, double *logprior, long *index);
+
 /* Weighted centre and covariance of draws about theta0 (proposal update between
  * rounds). theta0_out [D]; cov [D*D] or NULL. Returns the number of w > 0. */
 long peo_proposal_update(const peo_event *ev, const double *theta0, const double *theta, long n, const double *w,
