@@ -303,6 +303,81 @@ pe_status_t pe_refine(pe_event_t ev, double *theta0_dev, double *g_dev, int32_t 
                       int32_t precision, double *theta_dev, double *logq_dev, double *logprior_dev,
                       double *loglike_dev, double *w_dev, double *stats_dev, void *stream);
 
+/*
+ * Tile-mixture proposal (Sec. II.A: tile the metric space, give each tile the
+ * part of the prior volume closest to its template, and propose from the
+ * tiles in proportion to that volume times the posterior at the template;
+ * App. A: template bank, tiling of the prior volume, proposal). Built on the
+ * slice of the prior that a detection points to: the ball |y| <= radius in
+ * the whitened coordinates y = L^T (theta - centre) of a metric G = L L^T.
+ * Bank and assignment work in y, where the metric distance is Euclidean.
+ */
+typedef struct {
+    double centre[PE_MAX_DIM];              /* first D entries used */
+    double chol[PE_MAX_DIM * PE_MAX_DIM];   /* L, lower triangular, D x D row-major in the first D*D entries */
+    double radius;
+} pe_slice_t;
+
+/*
+ * Samples of the slice: candidate i (first .. first + n - 1) has
+ * y_a = radius (2 u_a - 1), u_a the (a mod 2)-th uniform of Philox block
+ * (seed, stream_id, i, a / 2) (as pe_draw's generator); it is kept when
+ * |y|^2 <= radius^2 and theta = centre + L^-T y lies in the prior's support.
+ * Kept candidates are written in candidate order: y_dev, theta_dev [D][n]
+ * (row stride n), logprior_dev [n] (the event's log prior); their number goes
+ * to count_dev[0] (int64, device). The arithmetic of a candidate is done
+ * without contractions, so it is the same bit for bit on every run.
+ * Errors: PE_ERR_ARG, PE_ERR_OOM, PE_ERR_HIP.
+ */
+pe_status_t pe_slice_sample(pe_event_t ev, const pe_slice_t *slice, uint64_t seed, uint32_t stream_id, int64_t first,
+                            int64_t n, double *y_dev, double *theta_dev, double *logprior_dev, int64_t *count_dev,
+                            void *stream);
+
+/*
+ * Stochastic template bank in the slice (App. A, template bank generation):
+ * candidates of the slice (as pe_slice_sample with stream_id, counters from
+ * 0 in batches of `batch`) are taken in order, and a kept candidate becomes a
+ * template when |y - y_t|^2 >= min_dist^2 for every template t so far. Stops
+ * after the first batch that adds fewer than stop_fraction times its kept
+ * candidates, at max_tiles templates, or after max_batches batches.
+ * Templates: tiles_y_dev, tiles_theta_dev [D][max_tiles] (row stride
+ * max_tiles); *n_tiles and *consumed (candidates drawn) are host outputs.
+ * Synchronises the stream (the acceptance runs batch by batch).
+ */
+pe_status_t pe_tile_bank(pe_event_t ev, const pe_slice_t *slice, double min_dist, uint64_t seed, uint32_t stream_id,
+                         int32_t batch, int32_t max_tiles, double stop_fraction, int32_t max_batches,
+                         double *tiles_y_dev, double *tiles_theta_dev, int32_t *n_tiles, int64_t *consumed,
+                         void *stream);
+
+/*
+ * Tile of each sample (App. A, tiling the prior volume): the template nearest
+ * in whitened coordinates, |y_s - y_t|^2 summed in index order without
+ * contractions; the lowest index among equals.
+ *   tiles_y_dev [dim][ld_tiles] (n_tiles used), y_dev [dim][ld_y] (n used),
+ *   tile_of_dev [n] int32 (device). n_tiles 1 .. 2^24.
+ */
+pe_status_t pe_tile_assign(int32_t dim, int32_t n_tiles, const double *tiles_y_dev, int64_t ld_tiles, int64_t n,
+                           const double *y_dev, int64_t ld_y, int32_t *tile_of_dev, void *stream);
+
+/*
+ * Proposal draws from the tiles (Sec. II.A; App. A, the proposal): sample s
+ * (of P) carries the mass m_s = exp(ll_t(s) - max ll + lp_s - max lp) (its
+ * tile's template log-likelihood tile_loglike_dev[t(s)] and its log prior
+ * sample_logprior_dev[s]; 0 where either is -inf); draw i takes the first
+ * uniform u of Philox block (seed, stream_id, i, 0) and returns the smallest
+ * s with u C_P <= C_s, C_s = m_0 + ... + m_s (FP64 prefix sums).
+ *   theta_dev [D][n] = sample s (samples_theta_dev [D][ld]),
+ *   logprior_dev[i] = lp_s, logq_dev[i] = ln m_s - ln(C_P / P) (the proposal
+ *   density relative to the flat measure the samples come from),
+ *   index_dev[i] = s (int64; may be NULL).
+ * With no positive mass every draw gets logprior -inf, logq 0, index -1.
+ * Importance weights then follow from pe_weights_ess as for pe_draw.
+ */
+pe_status_t pe_tile_draw(int32_t n_tiles, const double *tile_loglike_dev, int64_t n_samples,
+                         const int32_t *tile_of_dev, const double *sample_logprior_dev, int32_t dim,
+                         const double *samples_theta_dev, int64_t ld, uint64_t seed, uint32_t stream_id, int64_t n,
+                         double *theta_dev, double *logq_dev, double *logprior_dev, int64_t *index_dev, void *stream);
+
 /* The proposal's uniforms: u_dev[(i*npairs + j)*2 + {0,1}] for draw i and
  * block j < npairs, exactly the values pe_draw uses. */
 pe_status_t pe_rng_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int32_t npairs, double *u_dev,

@@ -30,7 +30,8 @@ PE_F32 = 1
 MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
-           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_proposal_update", "pe_refine", "pe_waveform",
+           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_proposal_update", "pe_refine", "pe_slice_sample", "pe_tile_bank",
+           "pe_tile_assign", "pe_tile_draw", "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
            "pe_autotune_plan", "pe_last_error",
            "pe_server_create", "pe_server_submit", "pe_server_wait", "pe_server_now", "pe_server_counters",
@@ -49,6 +50,25 @@ class EventDesc(ctypes.Structure):
                 ("strain_scale", ctypes.c_double), ("params", ctypes.c_int32), ("phase", ctypes.c_int32),
                 ("amp0", ctypes.c_double), ("gmst", ctypes.c_double), ("chi_max", ctypes.c_double),
                 ("dl_max", ctypes.c_double), ("det_geom", (ctypes.c_double * 3) * MAX_DET)]
+
+
+class Slice(ctypes.Structure):
+    """pe_slice_t: ball of `radius` in y = L^T (theta - centre)."""
+    _fields_ = [("centre", ctypes.c_double * 11), ("chol", ctypes.c_double * 121), ("radius", ctypes.c_double)]
+
+
+def make_slice(centre, chol, radius):
+    import numpy as np
+    sl = Slice()
+    c = np.asarray(centre, dtype=np.float64)
+    Lm = np.asarray(chol, dtype=np.float64)
+    D = c.shape[0]
+    for a in range(D):
+        sl.centre[a] = float(c[a])
+        for b in range(D):
+            sl.chol[a * D + b] = float(Lm[a, b])
+    sl.radius = float(radius)
+    return sl
 
 
 _lib = None
@@ -118,6 +138,11 @@ def load(path=LIB_PATH):
         "pe_batch_run": (i32, [i32, vp, i32, i32, vp]),
         "pe_weights_ess": (i32, [dp, dp, dp, i64, dp, dp, vp]),
         "pe_proposal_update": (i32, [vp, dp, dp, i64, dp, dp, dp, vp]),
+        "pe_slice_sample": (i32, [vp, ctypes.POINTER(Slice), u64, u32, i64, i64, dp, dp, dp, vp, vp]),
+        "pe_tile_bank": (i32, [vp, ctypes.POINTER(Slice), ctypes.c_double, u64, u32, i32, i32, ctypes.c_double, i32,
+                               dp, dp, ctypes.POINTER(i32), ctypes.POINTER(i64), vp]),
+        "pe_tile_assign": (i32, [i32, i32, dp, i64, i64, dp, i64, vp, vp]),
+        "pe_tile_draw": (i32, [i32, dp, i64, vp, dp, i32, dp, i64, u64, u32, i64, dp, dp, dp, vp, vp]),
         "pe_refine": (i32, [vp, dp, dp, i32, i64, u64, i32, dp, dp, dp, dp, dp, dp, vp]),
         "pe_waveform": (i32, [ctypes.POINTER(EventDesc), dp, vp, dp, dp, vp]),
         "pe_rng_uniforms": (i32, [u64, u32, i64, i32, dp, vp]),
@@ -317,6 +342,47 @@ def pe_refine(ev, theta0, g, rounds, n, seed, precision, theta, logq, logprior, 
                             _ptr(w, f64, "w"), _ptr(stats, f64, "stats"), _stream(stream)))
 
 
+def pe_slice_sample(ev, slice_, seed, stream_id, first, n, y, theta, logprior, count, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(load().pe_slice_sample(ev, ctypes.byref(slice_), int(seed) & 0xFFFFFFFFFFFFFFFF, int(stream_id) & 0xFFFFFFFF,
+                                  int(first), int(n), _ptr(y, f64, "y"), _ptr(theta, f64, "theta"),
+                                  _ptr(logprior, f64, "logprior"), _ptr(count, torch.int64, "count"), _stream(stream)))
+
+
+def pe_tile_bank(ev, slice_, min_dist, seed, stream_id, batch, max_tiles, stop_fraction, max_batches, tiles_y,
+                 tiles_theta, stream=None):
+    """Returns (n_tiles, candidates consumed)."""
+    import torch
+    f64 = torch.float64
+    m = ctypes.c_int32(0)
+    used = ctypes.c_int64(0)
+    _check(load().pe_tile_bank(ev, ctypes.byref(slice_), float(min_dist), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                               int(stream_id) & 0xFFFFFFFF, int(batch), int(max_tiles), float(stop_fraction),
+                               int(max_batches), _ptr(tiles_y, f64, "tiles_y"), _ptr(tiles_theta, f64, "tiles_theta"),
+                               ctypes.byref(m), ctypes.byref(used), _stream(stream)))
+    return m.value, used.value
+
+
+def pe_tile_assign(dim, n_tiles, tiles_y, ld_tiles, n, y, ld_y, tile_of, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(load().pe_tile_assign(int(dim), int(n_tiles), _ptr(tiles_y, f64, "tiles_y"), int(ld_tiles), int(n),
+                                 _ptr(y, f64, "y"), int(ld_y), _ptr(tile_of, torch.int32, "tile_of"), _stream(stream)))
+
+
+def pe_tile_draw(n_tiles, tile_loglike, n_samples, tile_of, sample_logprior, dim, samples_theta, ld, seed, stream_id, n,
+                 theta, logq, logprior, index=None, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(load().pe_tile_draw(int(n_tiles), _ptr(tile_loglike, f64, "tile_loglike"), int(n_samples),
+                               _ptr(tile_of, torch.int32, "tile_of"), _ptr(sample_logprior, f64, "sample_logprior"),
+                               int(dim), _ptr(samples_theta, f64, "samples_theta"), int(ld),
+                               int(seed) & 0xFFFFFFFFFFFFFFFF, int(stream_id) & 0xFFFFFFFF, int(n),
+                               _ptr(theta, f64, "theta"), _ptr(logq, f64, "logq"), _ptr(logprior, f64, "logprior"),
+                               _ptr(index, torch.int64, "index", allow_none=True), _stream(stream)))
+
+
 def pe_waveform(desc, theta, psd, h, snr2=None, stream=None):
     import torch
     f64 = torch.float64
@@ -438,6 +504,28 @@ class Event:
         pe_refine(self.handle, t0, g, rounds, n, seed, precision, *bufs, st, stream)
         return t0, g, st
 
+    def slice_sample(self, slice_, seed, stream_id, first, n, stream=None):
+        """pe_slice_sample: (y [D, k], theta [D, k], logprior [k]) of the kept candidates (synchronises)."""
+        import torch
+        f64 = dict(dtype=torch.float64, device="cuda")
+        y = torch.empty((self.dim, n), **f64)
+        th = torch.empty((self.dim, n), **f64)
+        lp = torch.empty(n, **f64)
+        cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+        pe_slice_sample(self.handle, slice_, seed, stream_id, first, n, y, th, lp, cnt, stream)
+        k = int(cnt.item())
+        return y[:, :k], th[:, :k], lp[:k]
+
+    def tile_bank(self, slice_, min_dist, seed, stream_id, batch, max_tiles, stop_fraction, max_batches, stream=None):
+        """pe_tile_bank: (templates y [D, m], theta [D, m], candidates consumed)."""
+        import torch
+        f64 = dict(dtype=torch.float64, device="cuda")
+        ty = torch.empty((self.dim, max_tiles), **f64)
+        tth = torch.empty((self.dim, max_tiles), **f64)
+        m, used = pe_tile_bank(self.handle, slice_, min_dist, seed, stream_id, batch, max_tiles, stop_fraction,
+                               max_batches, ty, tth, stream)
+        return ty[:, :m], tth[:, :m], used
+
     def loglike(self, theta, precision=PE_PREC_SPLIT, aux=False, stream=None):
         import torch
         n = theta.shape[1]
@@ -454,6 +542,40 @@ def weights_ess(loglike, logprior, logq, want_w=True, stream=None):
     st = torch.empty(4, dtype=torch.float64, device=loglike.device)
     pe_weights_ess(loglike, logprior, logq, n, w, st, stream)
     return w, st
+
+
+def tile_assign(tiles_y, y, stream=None):
+    """pe_tile_assign over [D, m] and [D, n] tensors (any row stride): int32 tile of every sample."""
+    import torch
+    D, m = tiles_y.shape
+    n = y.shape[1]
+    ty = tiles_y if tiles_y.stride(1) == 1 else tiles_y.contiguous()
+    yy = y if y.stride(1) == 1 else y.contiguous()
+    out = torch.empty(n, dtype=torch.int32, device=y.device)
+    _check(load().pe_tile_assign(int(D), int(m), ctypes.c_void_p(ty.data_ptr()), int(ty.stride(0)), int(n),
+                                 ctypes.c_void_p(yy.data_ptr()), int(yy.stride(0)), ctypes.c_void_p(out.data_ptr()),
+                                 _stream(stream)))
+    return out
+
+
+def tile_draw(tile_loglike, tile_of, sample_logprior, samples_theta, seed, stream_id, n, stream=None):
+    """pe_tile_draw: (theta [D, n], logq, logprior, index)."""
+    import torch
+    D, P = samples_theta.shape
+    sm = samples_theta if samples_theta.stride(1) == 1 else samples_theta.contiguous()
+    f64 = dict(dtype=torch.float64, device=sm.device)
+    th = torch.empty((D, n), **f64)
+    lq = torch.empty(n, **f64)
+    lp = torch.empty(n, **f64)
+    idx = torch.empty(n, dtype=torch.int64, device=sm.device)
+    _check(load().pe_tile_draw(int(tile_loglike.shape[0]), _ptr(tile_loglike, torch.float64, "tile_loglike"), int(P),
+                               _ptr(tile_of, torch.int32, "tile_of"),
+                               _ptr(sample_logprior, torch.float64, "sample_logprior"), int(D),
+                               ctypes.c_void_p(sm.data_ptr()), int(sm.stride(0)), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                               int(stream_id) & 0xFFFFFFFF, int(n), _ptr(th, torch.float64, "theta"),
+                               _ptr(lq, torch.float64, "logq"), _ptr(lp, torch.float64, "logprior"),
+                               _ptr(idx, torch.int64, "index"), _stream(stream)))
+    return th, lq, lp, idx
 
 
 def loglike_multi(events, thetas, precision=PE_PREC_SPLIT, aux=False, stream=None):

@@ -128,6 +128,14 @@ __device__ __forceinline__ int mass_and_support(const EvConst& ev, const double*
 }
 
 // Support of the prior and the source parameters of theta (D values).
+// Log prior (flat in Mc, eta or q, spins, tc, ra, psi, phic; cos dec; sin
+// iota; dL^2; unnormalised), -inf outside the support.
+__device__ __forceinline__ double log_prior_of(const EvConst& ev, const double* th) {
+    double M;
+    if (!mass_and_support(ev, th, M)) return -INFINITY;
+    return (ev.params == PE_PARAMS_4D) ? 0.0 : log(cos(th[5])) + log(sin(th[6])) + 2.0 * log(th[8]);
+}
+
 __device__ __forceinline__ int source_from_theta(const EvConst& ev, const double* th, Src& s) {
     int ok;
     double M;

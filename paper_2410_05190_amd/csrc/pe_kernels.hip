@@ -615,11 +615,7 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
         }
     }
     A.logq[i] = mx + log(acc) + lc[PE_MAX_DIM * PE_MAX_DIM] - 0.5 * D * log(kTwoPi);
-    double M;
-    const int ok = mass_and_support(ev, th, M);
-    double lp = -INFINITY;
-    if (ok) lp = (D == 4) ? 0.0 : log(cos(th[5])) + log(sin(th[6])) + 2.0 * log(th[8]);
-    A.logprior[i] = lp;
+    A.logprior[i] = log_prior_of(ev, th);
 }
 
 // Blocks of 256 draws that each belong to one event (doff: block offsets).

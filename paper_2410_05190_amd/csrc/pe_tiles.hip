@@ -1,0 +1,586 @@
+// pe_tiles.hip -- the tile-mixture proposal (Sec. II.A; App. A: template bank,
+// tiling of the prior volume, proposal) on a slice of the prior: the ball
+// |y| <= R in whitened coordinates y = L^T (theta - c) of a metric G = L L^T.
+//
+//   k_slice_count / k_slice_scan / k_slice_write
+//                  slice samples: candidates from Philox, kept ones compacted
+//                  in candidate order (count, block offsets, write)
+//   k_bank_cand    one batch of bank candidates and whether each is at least
+//                  min_dist from every template so far (the host then takes
+//                  the batch in order against the batch's own new templates)
+//   k_tile_assign  nearest template of every sample, templates staged in LDS
+//   k_tile_max, k_tile_mass, k_scan_sums, k_scan_write, k_tile_pick
+//                  proposal draws: per-sample masses, FP64 prefix sums,
+//                  inverse-CDF pick by binary search
+//
+// Candidate coordinates, whitened distances and the acceptance tests are
+// evaluated without contractions, so their decisions are the same bit for bit
+// on every run (and in any other IEEE FP64 evaluation in the same order).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "pe_device.h"
+#include "pe_host.h"
+
+namespace pe {
+namespace {
+
+struct Slice {
+    double c[PE_MAX_DIM];
+    double L[PE_MAX_DIM * PE_MAX_DIM];
+    double R;
+};
+
+// |a - b|^2 summed in index order, no contractions (host and device).
+template <int D>
+__host__ __device__ __forceinline__ double wdist2(const double* a, int64_t sa, const double* b, int64_t sb) {
+#pragma clang fp contract(off)
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double d = a[k * sa] - b[k * sb];
+        s += d * d;
+    }
+    return s;
+}
+
+__host__ double wdist2_rt(int D, const double* a, int64_t sa, const double* b, int64_t sb) {
+    return D == 4 ? wdist2<4>(a, sa, b, sb) : wdist2<11>(a, sa, b, sb);
+}
+
+// Candidate i of the slice: y, theta; 1 if kept.
+template <int D>
+__device__ __forceinline__ int slice_candidate(const EvConst& ev, const Slice& sl, uint64_t seed, uint32_t st,
+                                               uint64_t i, double (&y)[D], double (&th)[D]) {
+#pragma clang fp contract(off)
+    double u[D + 1];
+#pragma unroll
+    for (int a = 0; 2 * a < D; ++a) block_uniforms(seed, st, i, (uint32_t)a, u[2 * a], u[2 * a + 1]);
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        y[a] = sl.R * (2.0 * u[a] - 1.0);
+        r2 += y[a] * y[a];
+    }
+    double x[D];
+#pragma unroll
+    for (int r = D - 1; r >= 0; --r) {
+        double t = y[r];
+#pragma unroll
+        for (int c = r + 1; c < D; ++c) t -= sl.L[c * D + r] * x[c];
+        x[r] = t / sl.L[r * D + r];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) th[a] = sl.c[a] + x[a];
+    if (!(r2 <= sl.R * sl.R)) return 0;
+    double M;
+    return mass_and_support(ev, th, M);
+}
+
+// --------------------------------------------------------------- slice samples
+template <int D>
+__global__ __launch_bounds__(256) void k_slice_count(EvConst ev, Slice sl, uint64_t seed, uint32_t st, int64_t first,
+                                                     int64_t n, int64_t* __restrict__ bcount) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int keep = 0;
+    if (k < n) {
+        double y[D], th[D];
+        keep = slice_candidate<D>(ev, sl, seed, st, (uint64_t)(first + k), y, th);
+    }
+    const int c = __syncthreads_count(keep);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = c;
+}
+
+// Exclusive scan of the nb block counts in place (one workgroup, in order);
+// the total into total[0].
+__global__ __launch_bounds__(1024) void k_slice_scan(int64_t* __restrict__ bcount, int64_t nb,
+                                                     int64_t* __restrict__ total) {
+    __shared__ int64_t sh[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = min(nb, b0 + per);
+    int64_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += bcount[b];
+    sh[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    int64_t run = sh[t] - s;
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t c = bcount[b];
+        bcount[b] = run;
+        run += c;
+    }
+    if (t == 1023) total[0] = sh[1023];
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_slice_write(EvConst ev, Slice sl, uint64_t seed, uint32_t st, int64_t first,
+                                                     int64_t n, const int64_t* __restrict__ boff,
+                                                     double* __restrict__ yo, double* __restrict__ tho,
+                                                     double* __restrict__ lpo) {
+    __shared__ int wcount[4];
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int keep = 0;
+    double y[D], th[D];
+    if (k < n) keep = slice_candidate<D>(ev, sl, seed, st, (uint64_t)(first + k), y, th);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t mask = __ballot(keep);
+    if (lane == 0) wcount[w] = __popcll(mask);
+    __syncthreads();
+    int woff = 0;
+    for (int q = 0; q < w; ++q) woff += wcount[q];
+    if (keep) {
+        const int64_t pos = boff[blockIdx.x] + woff + __popcll(mask & ((1ull << lane) - 1));
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            yo[a * n + pos] = y[a];
+            tho[a * n + pos] = th[a];
+        }
+        lpo[pos] = log_prior_of(ev, th);
+    }
+}
+
+__global__ void k_set_count(int64_t* c) { c[0] = 0; }
+
+// ----------------------------------------------------------------------- bank
+// Candidates b0 .. b0 + nb - 1: y, theta [D][nb], flag = 0 (not kept), 1 (kept,
+// within min_dist of a template), 2 (kept, at least min_dist from all m).
+template <int D>
+__global__ __launch_bounds__(256) void k_bank_cand(EvConst ev, Slice sl, uint64_t seed, uint32_t st, int64_t b0,
+                                                   int nb, const double* __restrict__ ty, int64_t ldt, int m,
+                                                   double r2, double* __restrict__ cy, double* __restrict__ cth,
+                                                   int* __restrict__ flag) {
+    __shared__ double tl[256 * D];
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    double y[D], th[D];
+    int keep = 0;
+    if (k < nb) keep = slice_candidate<D>(ev, sl, seed, st, (uint64_t)(b0 + k), y, th);
+    bool far = keep != 0;
+    for (int j0 = 0; j0 < m; j0 += 256) {
+        const int cnt = min(256, m - j0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt * D; q += 256) {
+            const int a = q / cnt, j = q - a * cnt;
+            tl[a * 256 + j] = ty[a * ldt + j0 + j];
+        }
+        __syncthreads();
+        if (far)
+            for (int j = 0; j < cnt; ++j)
+                if (wdist2<D>(y, 1, tl + j, 256) < r2) {
+                    far = false;
+                    break;
+                }
+    }
+    if (k < nb) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            cy[a * nb + k] = y[a];
+            cth[a * nb + k] = th[a];
+        }
+        flag[k] = keep ? (far ? 2 : 1) : 0;
+    }
+}
+
+// ------------------------------------------------------------------ assignment
+template <int D>
+__global__ __launch_bounds__(256) void k_tile_assign(int m, const double* __restrict__ ty, int64_t ldt, int64_t n,
+                                                     const double* __restrict__ ys, int64_t lds,
+                                                     int* __restrict__ tile_of) {
+    __shared__ double tl[256 * D];
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double y[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) y[a] = (s < n) ? ys[a * lds + s] : 0.0;
+    double bd = INFINITY;
+    int best = 0;
+    for (int j0 = 0; j0 < m; j0 += 256) {
+        const int cnt = min(256, m - j0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt * D; q += 256) {
+            const int a = q / cnt, j = q - a * cnt;
+            tl[a * 256 + j] = ty[a * ldt + j0 + j];
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const double d = wdist2<D>(y, 1, tl + j, 256);
+            if (d < bd || j0 + j == 0) {
+                bd = d;
+                best = j0 + j;
+            }
+        }
+    }
+    if (s < n) tile_of[s] = best;
+}
+
+// ---------------------------------------------------------------------- draws
+// part[2 b] = max finite tile log-likelihood seen by block b, part[2 b + 1] =
+// max finite sample log prior (order-free, so deterministic).
+__global__ __launch_bounds__(256) void k_tile_max(int m, const double* __restrict__ tll, int64_t P,
+                                                  const double* __restrict__ lp, double* __restrict__ part) {
+    __shared__ double sh[8];
+    double a = -INFINITY, b = -INFINITY;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < m; j += stride)
+        if (isfinite(tll[j])) a = fmax(a, tll[j]);
+    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < P; s += stride)
+        if (isfinite(lp[s])) b = fmax(b, lp[s]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a = fmax(a, __shfl_xor(a, o));
+        b = fmax(b, __shfl_xor(b, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6] = a;
+        sh[4 + (threadIdx.x >> 6)] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+        part[2 * blockIdx.x + 1] = fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
+    }
+}
+
+// mass[s] = exp((ll_t(s) - lmax) + (lp_s - pmax)), the maxima folded from the
+// nb block parts first (every thread folds them: nb is small).
+__global__ __launch_bounds__(256) void k_tile_mass(const double* __restrict__ part, int nb,
+                                                   const double* __restrict__ tll, const int* __restrict__ tile_of,
+                                                   const double* __restrict__ lp, int64_t P, double* __restrict__ mass,
+                                                   double* __restrict__ mx) {
+    double lmax = -INFINITY, pmax = -INFINITY;
+    for (int b = 0; b < nb; ++b) {
+        lmax = fmax(lmax, part[2 * b]);
+        pmax = fmax(pmax, part[2 * b + 1]);
+    }
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s == 0) {
+        mx[0] = lmax;
+        mx[1] = pmax;
+    }
+    if (s >= P) return;
+    const double l = tll[tile_of[s]], p = lp[s];
+    mass[s] = (isfinite(l) && isfinite(p)) ? exp((l - lmax) + (p - pmax)) : 0.0;
+}
+
+// Inclusive prefix sums of x[0..P) in place, in two passes over nseg
+// contiguous segments: segment sums, then each segment adds the sums before
+// it (one block reduction) and scans its elements 256 at a time.
+__device__ __forceinline__ double block_sum(double s, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(const double* __restrict__ x, int64_t P, int64_t seg,
+                                                   double* __restrict__ ssum) {
+    __shared__ double sh[4];
+    const int64_t k0 = (int64_t)blockIdx.x * seg, k1 = min(P, k0 + seg);
+    double s = 0.0;
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) s += x[k];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) ssum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_scan_write(double* __restrict__ x, int64_t P, int64_t seg,
+                                                    const double* __restrict__ ssum) {
+    __shared__ double sh[4];
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double carry = 0.0;
+    for (int q = threadIdx.x; q < b; q += 256) carry += ssum[q];
+    carry = block_sum(carry, sh);
+    const int64_t k0 = (int64_t)b * seg, k1 = min(P, k0 + seg);
+    for (int64_t base = k0; base < k1; base += 256) {
+        const int64_t k = base + threadIdx.x;
+        double inc = (k < k1) ? x[k] : 0.0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double u = __shfl_up(inc, off);
+            if (lane >= off) inc += u;
+        }
+        if (lane == 63) sh[w] = inc;
+        __syncthreads();
+        double woff = 0.0;
+        for (int q = 0; q < w; ++q) woff += sh[q];
+        const double tile = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        __syncthreads();
+        if (k < k1) x[k] = carry + (woff + inc);
+        carry += tile;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_tile_pick(const double* __restrict__ C, int64_t P,
+                                                   const double* __restrict__ mx, const double* __restrict__ tll,
+                                                   const int* __restrict__ tile_of, const double* __restrict__ lp,
+                                                   const double* __restrict__ smp, int64_t ld, uint64_t seed,
+                                                   uint32_t st, int64_t n, double* __restrict__ theta,
+                                                   double* __restrict__ logq, double* __restrict__ logprior,
+                                                   int64_t* __restrict__ index) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double tot = P > 0 ? C[P - 1] : 0.0;
+    if (!(tot > 0.0)) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) theta[a * n + i] = P > 0 ? smp[a * ld] : 0.0;
+        logq[i] = 0.0;
+        logprior[i] = -INFINITY;
+        if (index) index[i] = -1;
+        return;
+    }
+    double u, u2;
+    block_uniforms(seed, st, (uint64_t)i, 0u, u, u2);
+    const double target = u * tot;
+    int64_t lo = 0, hi = P - 1;
+    while (lo < hi) {  // smallest s with target <= C_s
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (target <= C[mid])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const int64_t s = lo;
+#pragma unroll
+    for (int a = 0; a < D; ++a) theta[a * n + i] = smp[a * ld + s];
+    logprior[i] = lp[s];
+    logq[i] = ((tll[tile_of[s]] - mx[0]) + (lp[s] - mx[1])) - log(tot / (double)P);
+    if (index) index[i] = s;
+}
+
+// ------------------------------------------------------------------- scratch
+// One growing device buffer per stream; work on a stream is ordered, so it is
+// reused safely, and the stream is drained before a buffer is replaced.
+std::mutex g_scr_mu;
+std::map<hipStream_t, std::pair<char*, size_t>> g_scr;
+
+pe_status_t scratch_for(hipStream_t st, size_t bytes, char** out) {
+    std::lock_guard<std::mutex> lk(g_scr_mu);
+    auto& e = g_scr[st];
+    if (e.second < bytes) {
+        PE_HIP(hipStreamSynchronize(st));
+        dfree_bytes(e.first);
+        e.second = 0;
+        pe_status_t s = dalloc_bytes(&e.first, bytes);
+        if (s != PE_OK) return s;
+        e.second = bytes;
+    }
+    *out = e.first;
+    return PE_OK;
+}
+
+Slice to_slice(const pe_slice_t& s) {
+    Slice o;
+    for (int a = 0; a < PE_MAX_DIM; ++a) o.c[a] = s.centre[a];
+    for (int a = 0; a < PE_MAX_DIM * PE_MAX_DIM; ++a) o.L[a] = s.chol[a];
+    o.R = s.radius;
+    return o;
+}
+
+pe_status_t check_slice(const pe_event_s* ev, const pe_slice_t* s) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (!s) return fail(PE_ERR_ARG, "slice is NULL");
+    const int D = ev->ec.dim;
+    if (!(s->radius > 0.0) || !std::isfinite(s->radius)) return fail(PE_ERR_ARG, "slice radius must be > 0");
+    for (int r = 0; r < D; ++r) {
+        if (!std::isfinite(s->centre[r])) return fail(PE_ERR_ARG, "slice centre must be finite");
+        if (!(s->chol[r * D + r] > 0.0)) return fail(PE_ERR_ARG, "slice factor needs a positive diagonal");
+        for (int c = 0; c <= r; ++c)
+            if (!std::isfinite(s->chol[r * D + c])) return fail(PE_ERR_ARG, "slice factor must be finite");
+    }
+    return PE_OK;
+}
+
+unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+}  // namespace pe
+
+using namespace pe;
+
+extern "C" pe_status_t pe_slice_sample(pe_event_t ev, const pe_slice_t* slice, uint64_t seed, uint32_t stream_id,
+                                       int64_t first, int64_t n, double* y_dev, double* theta_dev,
+                                       double* logprior_dev, int64_t* count_dev, void* stream) {
+    pe_status_t s = check_slice(ev, slice);
+    if (s != PE_OK) return s;
+    if (n < 0 || n > ((int64_t)1 << 30) || first < 0) return fail(PE_ERR_ARG, "n must be in 0..2^30, first >= 0");
+    if (!count_dev || (n > 0 && (!y_dev || !theta_dev || !logprior_dev)))
+        return fail(PE_ERR_ARG, "output pointers are NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t nb = std::max<int64_t>(1, (n + 255) / 256);
+    char* scr = nullptr;
+    if ((s = scratch_for(st, sizeof(int64_t) * nb, &scr)) != PE_OK) return s;
+    int64_t* bc = reinterpret_cast<int64_t*>(scr);
+    const Slice sl = to_slice(*slice);
+    const EvConst& ec = ev->ec;
+    if (n == 0) {
+        k_set_count<<<1, 1, 0, st>>>(count_dev);
+        PE_HIP(hipGetLastError());
+        return PE_OK;
+    }
+    if (ec.dim == 4) {
+        k_slice_count<4><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc);
+        k_slice_scan<<<1, 1024, 0, st>>>(bc, nb, count_dev);
+        k_slice_write<4><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc, y_dev, theta_dev,
+                                                      logprior_dev);
+    } else {
+        k_slice_count<11><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc);
+        k_slice_scan<<<1, 1024, 0, st>>>(bc, nb, count_dev);
+        k_slice_write<11><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc, y_dev, theta_dev,
+                                                       logprior_dev);
+    }
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+}
+
+extern "C" pe_status_t pe_tile_bank(pe_event_t ev, const pe_slice_t* slice, double min_dist, uint64_t seed,
+                                    uint32_t stream_id, int32_t batch, int32_t max_tiles, double stop_fraction,
+                                    int32_t max_batches, double* tiles_y_dev, double* tiles_theta_dev,
+                                    int32_t* n_tiles, int64_t* consumed, void* stream) {
+    pe_status_t s = check_slice(ev, slice);
+    if (s != PE_OK) return s;
+    if (!(min_dist > 0.0) || batch < 1 || batch > (1 << 20) || max_tiles < 1 || max_tiles > (1 << 24) ||
+        max_batches < 1 || !(stop_fraction >= 0.0))
+        return fail(PE_ERR_ARG, "bad bank parameters");
+    if (!tiles_y_dev || !tiles_theta_dev || !n_tiles || !consumed) return fail(PE_ERR_ARG, "NULL output");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int D = ev->ec.dim;
+    const Slice sl = to_slice(*slice);
+    const double r2 = min_dist * min_dist;
+    char* scr = nullptr;
+    const size_t cand_bytes = sizeof(double) * 2 * D * (size_t)batch;
+    if ((s = scratch_for(st, cand_bytes + sizeof(int) * (size_t)batch, &scr)) != PE_OK) return s;
+    double* cy = reinterpret_cast<double*>(scr);
+    double* cth = cy + (size_t)D * batch;
+    int* flag = reinterpret_cast<int*>(scr + cand_bytes);
+    std::vector<double> hy((size_t)D * batch), hth((size_t)D * batch);
+    std::vector<int> hf(batch);
+    std::vector<double> ny, nth;  // this batch's new templates, [k][D]
+    int m = 0;
+    int64_t used = 0;
+    for (int b = 0; b < max_batches && m < max_tiles; ++b) {
+        const int64_t b0 = (int64_t)b * batch;
+        if (D == 4)
+            k_bank_cand<4><<<nblocks(batch), 256, 0, st>>>(ev->ec, sl, seed, stream_id, b0, batch, tiles_y_dev,
+                                                            max_tiles, m, r2, cy, cth, flag);
+        else
+            k_bank_cand<11><<<nblocks(batch), 256, 0, st>>>(ev->ec, sl, seed, stream_id, b0, batch, tiles_y_dev,
+                                                             max_tiles, m, r2, cy, cth, flag);
+        PE_HIP(hipGetLastError());
+        PE_HIP(hipMemcpyAsync(hy.data(), cy, sizeof(double) * D * batch, hipMemcpyDeviceToHost, st));
+        PE_HIP(hipMemcpyAsync(hth.data(), cth, sizeof(double) * D * batch, hipMemcpyDeviceToHost, st));
+        PE_HIP(hipMemcpyAsync(hf.data(), flag, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+        PE_HIP(hipStreamSynchronize(st));
+        const int m0 = m;
+        int64_t kept = 0, added = 0;
+        ny.clear();
+        nth.clear();
+        for (int i = 0; i < batch && m < max_tiles; ++i) {
+            used = b0 + i + 1;
+            if (hf[i] == 0) continue;
+            ++kept;
+            if (hf[i] != 2) continue;
+            bool ok = true;
+            for (int j = 0; j < m - m0 && ok; ++j)
+                if (wdist2_rt(D, hy.data() + i, batch, ny.data() + (size_t)j * D, 1) < r2) ok = false;
+            if (!ok) continue;
+            for (int a = 0; a < D; ++a) {
+                ny.push_back(hy[(size_t)a * batch + i]);
+                nth.push_back(hth[(size_t)a * batch + i]);
+            }
+            ++m;
+            ++added;
+        }
+        // append the new templates, one row segment per coordinate
+        if (added > 0) {
+            std::vector<double> rowy(added), rowt(added);
+            for (int a = 0; a < D; ++a) {
+                for (int64_t j = 0; j < added; ++j) {
+                    rowy[j] = ny[(size_t)j * D + a];
+                    rowt[j] = nth[(size_t)j * D + a];
+                }
+                PE_HIP(hipMemcpyAsync(tiles_y_dev + (size_t)a * max_tiles + m0, rowy.data(), sizeof(double) * added,
+                                      hipMemcpyHostToDevice, st));
+                PE_HIP(hipMemcpyAsync(tiles_theta_dev + (size_t)a * max_tiles + m0, rowt.data(),
+                                      sizeof(double) * added, hipMemcpyHostToDevice, st));
+            }
+            PE_HIP(hipStreamSynchronize(st));
+        }
+        if (m >= max_tiles || (double)added < stop_fraction * (double)kept) break;
+    }
+    *n_tiles = m;
+    *consumed = used;
+    return PE_OK;
+}
+
+extern "C" pe_status_t pe_tile_assign(int32_t dim, int32_t n_tiles, const double* tiles_y_dev, int64_t ld_tiles,
+                                      int64_t n, const double* y_dev, int64_t ld_y, int32_t* tile_of_dev,
+                                      void* stream) {
+    if (dim != 4 && dim != 11) return fail(PE_ERR_ARG, "dim must be 4 or 11");
+    if (n_tiles < 1 || n_tiles > (1 << 24) || ld_tiles < n_tiles) return fail(PE_ERR_ARG, "bad n_tiles or ld_tiles");
+    if (n < 0 || n > ((int64_t)1 << 30) || ld_y < n) return fail(PE_ERR_ARG, "bad n or ld_y");
+    if (!tiles_y_dev || (n > 0 && (!y_dev || !tile_of_dev))) return fail(PE_ERR_ARG, "NULL pointer");
+    if (n == 0) return PE_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (dim == 4)
+        k_tile_assign<4><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld_y, tile_of_dev);
+    else
+        k_tile_assign<11><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld_y, tile_of_dev);
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+}
+
+extern "C" pe_status_t pe_tile_draw(int32_t n_tiles, const double* tile_loglike_dev, int64_t n_samples,
+                                    const int32_t* tile_of_dev, const double* sample_logprior_dev, int32_t dim,
+                                    const double* samples_theta_dev, int64_t ld, uint64_t seed, uint32_t stream_id,
+                                    int64_t n, double* theta_dev, double* logq_dev, double* logprior_dev,
+                                    int64_t* index_dev, void* stream) {
+    if (dim != 4 && dim != 11) return fail(PE_ERR_ARG, "dim must be 4 or 11");
+    if (n_tiles < 1 || n_tiles > (1 << 24)) return fail(PE_ERR_ARG, "bad n_tiles");
+    if (n_samples < 1 || n_samples > ((int64_t)1 << 30) || ld < n_samples) return fail(PE_ERR_ARG, "bad n_samples or ld");
+    if (n < 0 || n > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "n must be in 0..2^30");
+    if (!tile_loglike_dev || !tile_of_dev || !sample_logprior_dev || !samples_theta_dev)
+        return fail(PE_ERR_ARG, "NULL input");
+    if (n > 0 && (!theta_dev || !logq_dev || !logprior_dev)) return fail(PE_ERR_ARG, "NULL output");
+    if (n == 0) return PE_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int nbm = 64;
+    const int64_t seg = std::max<int64_t>(1024, (n_samples + 1023) / 1024);
+    const int nseg = (int)((n_samples + seg - 1) / seg);
+    const size_t bytes = sizeof(double) * ((size_t)n_samples + 2 * nbm + 2 + nseg);
+    char* scr = nullptr;
+    pe_status_t s = scratch_for(st, bytes, &scr);
+    if (s != PE_OK) return s;
+    double* C = reinterpret_cast<double*>(scr);
+    double* part = C + n_samples;
+    double* mx = part + 2 * nbm;
+    double* ssum = mx + 2;
+    k_tile_max<<<nbm, 256, 0, st>>>(n_tiles, tile_loglike_dev, n_samples, sample_logprior_dev, part);
+    k_tile_mass<<<nblocks(n_samples), 256, 0, st>>>(part, nbm, tile_loglike_dev, tile_of_dev, sample_logprior_dev,
+                                                     n_samples, C, mx);
+    k_scan_sums<<<nseg, 256, 0, st>>>(C, n_samples, seg, ssum);
+    k_scan_write<<<nseg, 256, 0, st>>>(C, n_samples, seg, ssum);
+    if (dim == 4)
+        k_tile_pick<4><<<nblocks(n), 256, 0, st>>>(C, n_samples, mx, tile_loglike_dev, tile_of_dev, sample_logprior_dev,
+                                                    samples_theta_dev, ld, seed, stream_id, n, theta_dev, logq_dev,
+                                                    logprior_dev, index_dev);
+    else
+        k_tile_pick<11><<<nblocks(n), 256, 0, st>>>(C, n_samples, mx, tile_loglike_dev, tile_of_dev,
+                                                     sample_logprior_dev, samples_theta_dev, ld, seed, stream_id, n,
+                                                     theta_dev, logq_dev, logprior_dev, index_dev);
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+}

@@ -60,6 +60,18 @@ def test_proposal_update_and_refine_argument_errors_on_host():
     assert L.pe_refine(None, None, None, 1, 16, 0, 1, None, None, None, None, None, None, None) == 1
 
 
+def test_tile_entry_points_reject_bad_arguments_on_host():
+    L = binding.load()
+    sl = binding.make_slice([1.0] * 4, [[1.0, 0, 0, 0], [0, 1.0, 0, 0], [0, 0, 1.0, 0], [0, 0, 0, 1.0]], 2.0)
+    assert ctypes.sizeof(binding.Slice) == (11 + 121 + 1) * 8
+    assert L.pe_slice_sample(None, ctypes.byref(sl), 0, 0, 0, 10, None, None, None, None, None) == 1
+    assert L.pe_tile_bank(None, ctypes.byref(sl), 1.0, 0, 0, 16, 16, 0.1, 4, None, None, None, None, None) == 1
+    assert L.pe_tile_assign(5, 1, None, 1, 0, None, 0, None, None) == 1
+    assert "dim" in binding.pe_last_error()
+    assert L.pe_tile_assign(4, 0, None, 1, 0, None, 0, None, None) == 1
+    assert L.pe_tile_draw(1, None, 1, None, None, 4, None, 1, 0, 0, 1, None, None, None, None, None) == 1
+
+
 def test_batch_item_layout_matches_header():
     # pe_batch_item_t: 5 pointers, int32, uint32, uint64, pointer, int64, 7 pointers
     assert ctypes.sizeof(binding.BatchItem) == 5 * 8 + 4 + 4 + 8 + 8 + 8 + 7 * 8
