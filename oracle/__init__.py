@@ -104,6 +104,8 @@ def lib():
         L.peo_tile_draw.restype = ctypes.c_int
         L.peo_tile_draw.argtypes = [ctypes.c_long, _dp, ctypes.c_long, _ip, _dp, ctypes.c_int, _dp, ctypes.c_long,
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_long, _dp, _dp, _dp, _lp]
+        L.peo_tile_reweight.argtypes = [ctypes.c_long, _dp, ctypes.c_long, _ip, _dp, ctypes.c_long, _lp, _dp,
+                                        ctypes.c_double, _dp]
         L.peo_proposal_update.restype = ctypes.c_long
         L.peo_proposal_update.argtypes = [ctypes.POINTER(_Event), _dp, _dp, ctypes.c_long, _dp, _dp, _dp]
         _lib = L
@@ -371,6 +373,20 @@ def tile_draw(tile_ll, tile_of, logprior, samples, seed, stream, n):
                              _p(sm), P, int(seed), int(stream), int(n), _p(theta), _p(lq), _p(lpo),
                              idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
     return rc, theta, lq, lpo, idx
+
+
+def tile_reweight(tile_ll, tile_of, logprior, index, w, alpha):
+    """Per-tile values for the next round's tile_draw (peo_tile_reweight)."""
+    tl = _f64(tile_ll)
+    to = np.ascontiguousarray(tile_of, dtype=np.int32)
+    lp = _f64(logprior)
+    ix = np.ascontiguousarray(index, dtype=np.int64)
+    ww = _f64(w)
+    out = np.zeros(tl.shape[0])
+    lib().peo_tile_reweight(tl.shape[0], _p(tl), lp.shape[0], to.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                            _p(lp), ix.shape[0], ix.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _p(ww),
+                            float(alpha), _p(out))
+    return out
 
 
 def weights_ess(loglike, logprior, logq):

@@ -1055,3 +1055,54 @@ int peo_tile_draw(long n_tiles, const double *tile_ll, long P, const int *tile_o
     free(C);
     return tot > 0.0 ? 0 : 5;
 }
+
+/*
+ * Tile weights for the next round (the iterative update of the proposal the
+ * paper suggests at the end of Sec. III.A, applied to the tile mixture): the
+ * posterior mass of tile j estimated by importance sampling from the previous
+ * round, P_j = sum of the normalised weights w_i of the draws from tile j,
+ * mixed with the previous round's tile probabilities p_j (defensive share
+ * alpha):  pi_j = (1 - alpha) P_j / sum P + alpha p_j,
+ * p_j = exp(l_j - max l) V_j / sum_k exp(l_k - max l) V_k, with V_j = sum over
+ * the tile's samples of exp(lp_s - max lp) (its prior volume). The result
+ * l'_j = ln pi_j - ln V_j (-inf where pi_j or V_j is 0) fed to peo_tile_draw
+ * gives sample s the mass pi_j exp(lp_s) / V_j. index: the previous draws'
+ * sample indices (negative ones are skipped).
+ */
+void peo_tile_reweight(long n_tiles, const double *tile_ll, long P, const int *tile_of, const double *lp, long n,
+                       const long *index, const double *w, double alpha, double *out)
+{
+    double lmax = -INFINITY, pmax = -INFINITY, ptot, wtot;
+    nsum *V = (nsum *)calloc((size_t)(n_tiles > 0 ? n_tiles : 1), sizeof(nsum));
+    nsum *Ph = (nsum *)calloc((size_t)(n_tiles > 0 ? n_tiles : 1), sizeof(nsum));
+    nsum pt = {0, 0}, wt = {0, 0};
+    long s, j, i;
+    for (j = 0; j < n_tiles; j++)
+        if (isfinite(tile_ll[j]) && tile_ll[j] > lmax)
+            lmax = tile_ll[j];
+    for (s = 0; s < P; s++)
+        if (isfinite(lp[s]) && lp[s] > pmax)
+            pmax = lp[s];
+    for (s = 0; s < P; s++)
+        if (isfinite(lp[s]))
+            nadd(&V[tile_of[s]], exp(lp[s] - pmax));
+    for (i = 0; i < n; i++)
+        if (index[i] >= 0 && w[i] > 0.0) {
+            nadd(&Ph[tile_of[index[i]]], w[i]);
+            nadd(&wt, w[i]);
+        }
+    for (j = 0; j < n_tiles; j++)
+        if (isfinite(tile_ll[j]))
+            nadd(&pt, exp(tile_ll[j] - lmax) * nval(&V[j]));
+    ptot = nval(&pt);
+    wtot = nval(&wt);
+    for (j = 0; j < n_tiles; j++) {
+        const double v = nval(&V[j]);
+        const double pj = (ptot > 0.0 && isfinite(tile_ll[j])) ? exp(tile_ll[j] - lmax) * v / ptot : 0.0;
+        const double hj = wtot > 0.0 ? nval(&Ph[j]) / wtot : 0.0;
+        const double pi = (1.0 - alpha) * hj + alpha * pj;
+        out[j] = (pi > 0.0 && v > 0.0) ? log(pi) - log(v) : -INFINITY;
+    }
+    free(V);
+    free(Ph);
+}

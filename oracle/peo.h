@@ -149,6 +149,11 @@ int peo_tile_draw(long n_tiles, const double *tile_ll, long P, const int *tile_o
                   const double *samples, long ld, uint64_t seed, uint32_t stream, long n, double *theta,
                   double *logq, double *logprior, long *index);
 
+/* Per-tile values for the next round's peo_tile_draw from the previous round's
+ * draws (index) and normalised weights (w), defensive share alpha. */
+void peo_tile_reweight(long n_tiles, const double *tile_ll, long P, const int *tile_of, const double *lp, long n,
+                       const long *index, const double *w, double alpha, double *out);
+
 /* Weighted centre and covariance of draws about theta0 (proposal update between
  * rounds). theta0_out [D]; cov [D*D] or NULL. Returns the number of w > 0. */
 long peo_proposal_update(const peo_event *ev, const double *theta0, const double *theta, long n, const double *w,

@@ -165,3 +165,70 @@ def test_tile_mixture_chain_is_efficient():
     ll = ev.loglike(thd, n_threads=8)
     w, st = oracle.weights_ess(ll, lpd, lq)
     assert st[0] / 4096 > 0.10
+
+
+def test_reweight_with_full_defensive_share_keeps_the_previous_masses():
+    rng = np.random.default_rng(13)
+    P, M, n = 4000, 50, 3000
+    to = rng.integers(0, M, P).astype(np.int32)
+    tl = rng.normal(0, 2, M)
+    lp = rng.normal(0, 0.4, P)
+    idx = rng.integers(0, P, n)
+    w = rng.random(n)
+    w /= w.sum()
+    out = oracle.tile_reweight(tl, to, lp, idx, w, 1.0)
+    # sample masses exp(out_t + lp) must be proportional to exp(tl_t + lp): out - tl is constant
+    d = out - tl
+    np.testing.assert_allclose(d, d[0], rtol=0, atol=1e-12)
+
+
+def test_reweight_puts_the_mass_where_the_weights_are():
+    P, M = 600, 6
+    to = (np.arange(P) % M).astype(np.int32)
+    lp = np.zeros(P)
+    tl = np.zeros(M)
+    idx = np.array([0, 6, 1, 2, -1])  # tiles 0, 0, 1, 2 and a draw without a sample
+    w = np.array([0.5, 0.3, 0.2, 0.0, 0.7])
+    out = oracle.tile_reweight(tl, to, lp, idx, w, 0.0)
+    # pi = (0.8, 0.2, 0, 0, 0, 0) over tiles of 100 samples each
+    np.testing.assert_allclose(out[:2], np.log([0.8, 0.2]) - math.log(100.0), rtol=0, atol=1e-14)
+    assert np.all(out[2:] == -np.inf)
+    mix = oracle.tile_reweight(tl, to, lp, idx, w, 0.25)
+    np.testing.assert_allclose(np.exp(mix) * 100, 0.75 * np.array([0.8, 0.2, 0, 0, 0, 0]) + 0.25 / 6, rtol=1e-13)
+
+
+def test_reweight_estimates_tile_posterior_masses():
+    # tiles with known target masses; draws from uniform tile probabilities, weights = target/proposal
+    rng = np.random.default_rng(14)
+    M, per = 20, 50
+    P = M * per
+    to = np.repeat(np.arange(M), per).astype(np.int32)
+    true = rng.random(M) ** 3
+    true /= true.sum()
+    n = 400000
+    idx = rng.integers(0, P, n)
+    w = true[to[idx]] * M
+    w /= w.sum()
+    out = oracle.tile_reweight(np.zeros(M), to, np.zeros(P), idx, w, 0.0)
+    est = np.exp(out) * per
+    np.testing.assert_allclose(est, true, rtol=0, atol=5 * math.sqrt(true.max() / n) + 1e-12)
+
+
+def test_reweighted_round_raises_the_efficiency():
+    """The config-0 chain of test_tile_mixture_chain_is_efficient, then one reweighted round."""
+    b = build_event(0, 0)
+    ev = b.ev
+    sl, L, c = _slice(b, 6.0)
+    ty, tth, _ = ev.tile_bank(sl, 1.0, 5, 1, 4096, 20000, 0.002, 400)
+    y, th, lp = ev.slice_sample(sl, 5, 2, 0, 4000000)
+    to = oracle.tile_assign(ty, y)
+    llt = ev.loglike(tth, n_threads=8)
+    eff = []
+    ell = llt
+    for rnd in range(2):
+        rc, thd, lq, lpd, idx = oracle.tile_draw(ell, to, lp, th, 7, rnd, 4096)
+        ll = ev.loglike(thd, n_threads=8)
+        w, st = oracle.weights_ess(ll, lpd, lq)
+        eff.append(st[0] / 4096)
+        ell = oracle.tile_reweight(ell, to, lp, idx, w, 0.1)
+    assert eff[1] > 0.2 and eff[1] > 3 * eff[0]
