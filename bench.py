@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--precision", choices=["split", "fp64"], default="split")
     ap.add_argument("--chunks", type=int, default=0)
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
-                    help="pick the hot loop's plan with the library's autotuner before timing (auto: batches only)")
+                    help="pick the hot loop's plan with the library's autotuner before timing (auto: batches and "
+                         "small events)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--serve-events", type=int, default=120,
@@ -65,6 +66,10 @@ def parse():
     ap.add_argument("--refine-rounds", type=int, default=3,
                     help="rounds of proposal refinement before the refined-proposal leg (0 skips the leg)")
     ap.add_argument("--refine-draws", type=int, default=16384, help="draws per refinement round")
+    ap.add_argument("--tile-radius", type=float, default=6.0, help="tile-mixture leg: slice radius (whitened)")
+    ap.add_argument("--tile-spacing", type=float, default=1.0, help="tile-mixture leg: template spacing (whitened)")
+    ap.add_argument("--tile-candidates", type=int, default=4000000,
+                    help="tile-mixture leg: slice candidates for the prior samples (0 skips the leg; 4-D only)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (HBM counter calibration)")
     return ap.parse_args()
@@ -147,7 +152,8 @@ def main():
     for x in evs:
         x["ev"].status()
     plan = {"tuned": False}
-    if args.autotune == "on" or (args.autotune == "auto" and n_events > 1):
+    small = sum(Ns) * K < 10 ** 9  # launch-latency-bound shapes: the default plan leaves CUs idle
+    if args.autotune == "on" or (args.autotune == "auto" and (n_events > 1 or small)):
         if args.warmup == 0:
             step(999, stats[0])
         t_tune = time.perf_counter()
@@ -226,6 +232,8 @@ def main():
     first = evs[0]
     if n_events == 1 and args.refine_rounds > 0:
         out["refined"] = refine_leg(first, args.refine_rounds, args.refine_draws, max(args.steps, 1), prec)
+    if n_events == 1 and D == 4 and args.tile_candidates > 0:
+        out["tiles"] = tile_leg(first, args, max(args.steps, 1), prec)
     n_drift = args.drift_sample if args.drift_sample >= 0 else (1024 if c == 4 else 0)
     if n_drift > 0:
         out["drift"] = drift_leg(first, n_drift, prec)
@@ -257,6 +265,9 @@ def refine_leg(x, rounds, n_round, steps, prec):
     st_f = torch.empty((steps, 4), dtype=torch.float64, device=dev)
     bufs = [torch.empty((x["ev"].dim, n_round), dtype=torch.float64, device=dev)] + \
            [torch.empty(n_round, dtype=torch.float64, device=dev) for _ in range(4)]
+    x["ev"].reserve(max(N, n_round))
+    # one untimed refinement from a different seed first (first-use costs of the round size)
+    binding.pe_refine(h_, t0.clone(), g, rounds, n_round, x["seed"] + 5, prec, *bufs, st_r)
     torch.cuda.synchronize()
     ta = time.perf_counter()
     binding.pe_refine(h_, t0, g, rounds, n_round, x["seed"] + 7, prec, *bufs, st_r)
@@ -284,6 +295,83 @@ def refine_leg(x, rounds, n_round, steps, prec):
         "ess_per_s_with_refine": ess_f / (t_ref + t_step),
         "evals_per_s": float(sf[:, 3].sum()) / (tc - tb),
         "centre": [float(v) for v in t0.cpu().numpy()],
+    }
+
+
+def tile_leg(x, args, steps, prec):
+    """Tile-mixture proposal: the precompute (stochastic bank and prior samples in the slice around
+    the trigger, nearest-template assignment), then `steps` online steps (likelihood at every
+    template, N proposal draws, their likelihoods, weights). ESS per event and ESS/s."""
+    import numpy as np
+    import torch
+
+    from paper_2410_05190_amd import binding
+    ev = x["ev"]
+    h_ = ev.handle
+    N = x["N"]
+    binding.pe_metric(h_, x["theta0"], None, 0, x["g"])
+    L = np.linalg.cholesky(x["g"].cpu().numpy())
+    sl = binding.make_slice(x["theta_inj"], L, args.tile_radius)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ty, tth, used = ev.tile_bank(sl, args.tile_spacing, x["seed"], 1, 4096, 200000, 0.002, 2000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    y, th, lp = ev.slice_sample(sl, x["seed"], 2, 0, args.tile_candidates)
+    to = binding.tile_assign(ty, y)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tth = tth.contiguous()
+    M = tth.shape[1]
+    llt = torch.empty(M, dtype=torch.float64, device="cuda")
+    st = torch.empty((steps, 4), dtype=torch.float64, device="cuda")
+    ev.reserve(max(M, N))
+    st2 = torch.empty((steps, 4), dtype=torch.float64, device="cuda")
+    for i in range(-1, steps):  # step -1: untimed warm-up (first-use costs)
+        if i == 0:
+            torch.cuda.synchronize()
+            t_on = time.perf_counter()
+        binding.pe_loglike_batch(h_, tth, M, prec, llt, None)
+        thd, lq, lpd, idx = binding.tile_draw(llt, to, lp, th, x["seed"] + 3, max(i, 0), N)
+        binding.pe_loglike_batch(h_, thd, N, prec, x["ll"], None)
+        binding.pe_weights_ess(x["ll"], lpd, lq, N, x["w"], st[max(i, 0)])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    # two rounds per step: the second draws from the tiles reweighted by the first round's weights
+    for i in range(-1, steps):
+        if i == 0:
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+        binding.pe_loglike_batch(h_, tth, M, prec, llt, None)
+        thd, lq, lpd, idx = binding.tile_draw(llt, to, lp, th, x["seed"] + 5, 2 * max(i, 0), N)
+        binding.pe_loglike_batch(h_, thd, N, prec, x["ll"], None)
+        binding.pe_weights_ess(x["ll"], lpd, lq, N, x["w"], st[max(i, 0)])
+        ell = binding.tile_reweight(llt, to, lp, idx, x["w"], 0.1)
+        thd, lq, lpd, idx = binding.tile_draw(ell, to, lp, th, x["seed"] + 5, 2 * max(i, 0) + 1, N)
+        binding.pe_loglike_batch(h_, thd, N, prec, x["ll"], None)
+        binding.pe_weights_ess(x["ll"], lpd, lq, N, x["w"], st2[max(i, 0)])
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    ev.status()
+    s = st.cpu().numpy()
+    s2 = st2.cpu().numpy()
+    ess = float(s[:, 0].mean())
+    ess2 = float(s2[:, 0].mean())
+    t_step = (t3 - t_on) / steps
+    t_step2 = (t5 - t4) / steps
+    return {
+        "kind": "tile mixture: templates in the whitened slice, prior samples weighted by their tile's likelihood",
+        "slice_radius": args.tile_radius, "spacing": args.tile_spacing, "templates": M,
+        "bank_candidates": used, "prior_samples": int(y.shape[1]), "bank_ms": 1e3 * (t1 - t0),
+        "samples_and_assign_ms": 1e3 * (t2 - t1), "steps": steps, "draws_per_step": N,
+        "ms_per_step": 1e3 * t_step, "ess_per_event_mean": ess, "efficiency": ess / N,
+        "ess_per_event_min": float(s[:, 0].min()), "ess_per_event_max": float(s[:, 0].max()),
+        "ess_per_s": ess / t_step, "evals_per_s": (M + N) / t_step,
+        "reweighted": {"kind": "second round from the tiles reweighted by the first round's weights "
+                               "(defensive share 0.1); ESS of the second round",
+                       "ms_per_step": 1e3 * t_step2, "ess_per_event_mean": ess2, "efficiency": ess2 / N,
+                       "ess_per_event_min": float(s2[:, 0].min()), "ess_per_event_max": float(s2[:, 0].max()),
+                       "ess_per_s": ess2 / t_step2},
     }
 
 

@@ -378,6 +378,32 @@ pe_status_t pe_tile_draw(int32_t n_tiles, const double *tile_loglike_dev, int64_
                          const double *samples_theta_dev, int64_t ld, uint64_t seed, uint32_t stream_id, int64_t n,
                          double *theta_dev, double *logq_dev, double *logprior_dev, int64_t *index_dev, void *stream);
 
+/*
+ * Tile values for the next round (the iterative update of the proposal that
+ * the paper suggests at the end of Sec. III.A, applied to the tile mixture):
+ * tile j's posterior mass estimated from the previous round, P_j = the sum of
+ * the normalised weights of the draws that came from it, mixed with the
+ * previous round's tile probability p_j (defensive share alpha):
+ *   pi_j = (1 - alpha) P_j / sum P + alpha p_j,
+ *   p_j = exp(l_j - max l) V_j / sum_k exp(l_k - max l) V_k,
+ *   V_j = sum over the tile's samples of exp(lp_s - max lp) (prior volume);
+ *   out_dev[j] = ln pi_j - ln V_j (-inf where pi_j or V_j is 0).
+ * Passed to pe_tile_draw in place of the template log-likelihoods, it gives
+ * sample s the mass pi_j exp(lp_s) / V_j.
+ *   tile_loglike_dev [n_tiles]: the values the previous pe_tile_draw used;
+ *   tile_of_dev, sample_logprior_dev [n_samples] (n_samples <= 2^31);
+ *   index_dev [n] (pe_tile_draw's sample indices; negative ones skipped),
+ *   w_dev [n] (normalised weights of those draws, pe_weights_ess: each in
+ *   [0, 1], sum 1); alpha in [0, 1]; out_dev [n_tiles], not aliasing the input.
+ * The per-tile sums are 64-bit fixed point (prior volume in units of 2^-32 of
+ * the largest sample's, weights in units of 2^-52), so the result does not
+ * depend on the order of the additions.
+ */
+pe_status_t pe_tile_reweight(int32_t n_tiles, const double *tile_loglike_dev, int64_t n_samples,
+                             const int32_t *tile_of_dev, const double *sample_logprior_dev, int64_t n,
+                             const int64_t *index_dev, const double *w_dev, double alpha, double *out_dev,
+                             void *stream);
+
 /* The proposal's uniforms: u_dev[(i*npairs + j)*2 + {0,1}] for draw i and
  * block j < npairs, exactly the values pe_draw uses. */
 pe_status_t pe_rng_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int32_t npairs, double *u_dev,

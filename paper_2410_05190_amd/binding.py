@@ -31,7 +31,7 @@ MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
            "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_proposal_update", "pe_refine", "pe_slice_sample", "pe_tile_bank",
-           "pe_tile_assign", "pe_tile_draw", "pe_waveform",
+           "pe_tile_assign", "pe_tile_draw", "pe_tile_reweight", "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
            "pe_autotune_plan", "pe_last_error",
            "pe_server_create", "pe_server_submit", "pe_server_wait", "pe_server_now", "pe_server_counters",
@@ -143,6 +143,7 @@ def load(path=LIB_PATH):
                                dp, dp, ctypes.POINTER(i32), ctypes.POINTER(i64), vp]),
         "pe_tile_assign": (i32, [i32, i32, dp, i64, i64, dp, i64, vp, vp]),
         "pe_tile_draw": (i32, [i32, dp, i64, vp, dp, i32, dp, i64, u64, u32, i64, dp, dp, dp, vp, vp]),
+        "pe_tile_reweight": (i32, [i32, dp, i64, vp, dp, i64, vp, dp, ctypes.c_double, dp, vp]),
         "pe_refine": (i32, [vp, dp, dp, i32, i64, u64, i32, dp, dp, dp, dp, dp, dp, vp]),
         "pe_waveform": (i32, [ctypes.POINTER(EventDesc), dp, vp, dp, dp, vp]),
         "pe_rng_uniforms": (i32, [u64, u32, i64, i32, dp, vp]),
@@ -576,6 +577,18 @@ def tile_draw(tile_loglike, tile_of, sample_logprior, samples_theta, seed, strea
                                _ptr(lq, torch.float64, "logq"), _ptr(lp, torch.float64, "logprior"),
                                _ptr(idx, torch.int64, "index"), _stream(stream)))
     return th, lq, lp, idx
+
+
+def tile_reweight(tile_loglike, tile_of, sample_logprior, index, w, alpha, stream=None):
+    """pe_tile_reweight: per-tile values for the next round's tile_draw."""
+    import torch
+    out = torch.empty_like(tile_loglike)
+    _check(load().pe_tile_reweight(int(tile_loglike.shape[0]), _ptr(tile_loglike, torch.float64, "tile_loglike"),
+                                   int(tile_of.shape[0]), _ptr(tile_of, torch.int32, "tile_of"),
+                                   _ptr(sample_logprior, torch.float64, "sample_logprior"), int(index.shape[0]),
+                                   _ptr(index, torch.int64, "index"), _ptr(w, torch.float64, "w"), float(alpha),
+                                   _ptr(out, torch.float64, "out"), _stream(stream)))
+    return out
 
 
 def loglike_multi(events, thetas, precision=PE_PREC_SPLIT, aux=False, stream=None):

@@ -361,6 +361,80 @@ __global__ __launch_bounds__(256) void k_tile_pick(const double* __restrict__ C,
     if (index) index[i] = s;
 }
 
+// --------------------------------------------------------------- reweighting
+// Per-tile sums in 64-bit fixed point (order-free, so deterministic): prior
+// volume in units of 2^-32 of the largest sample's, weights in units of 2^-52.
+constexpr double kVolScale = 4294967296.0;         // 2^32
+constexpr double kWScale = 4503599627370496.0;     // 2^52
+
+__global__ void k_rw_zero(int m, unsigned long long* __restrict__ a, unsigned long long* __restrict__ b) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < m) {
+        a[j] = 0ull;
+        b[j] = 0ull;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rw_prior(const double* __restrict__ part, int nb, int64_t P,
+                                                  const int* __restrict__ tile_of, const double* __restrict__ lp,
+                                                  unsigned long long* __restrict__ vfx) {
+    double pmax = -INFINITY;
+    for (int b = 0; b < nb; ++b) pmax = fmax(pmax, part[2 * b + 1]);
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= P || !isfinite(lp[s])) return;
+    atomicAdd(&vfx[tile_of[s]], (unsigned long long)rint(exp(lp[s] - pmax) * kVolScale));
+}
+
+__global__ __launch_bounds__(256) void k_rw_post(int64_t n, const int64_t* __restrict__ index,
+                                                 const double* __restrict__ w, const int* __restrict__ tile_of,
+                                                 unsigned long long* __restrict__ pfx) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n || index[i] < 0 || !(w[i] > 0.0)) return;
+    atomicAdd(&pfx[tile_of[index[i]]], (unsigned long long)rint(fmin(w[i], 1.0) * kWScale));
+}
+
+// One workgroup: sum_j exp(l_j - lmax) V_j (fixed order) and sum_j P_j, then
+// out_j = ln((1 - alpha) P_j / sum P + alpha p_j) - ln V_j.
+__global__ __launch_bounds__(1024) void k_rw_final(int m, const double* __restrict__ tll,
+                                                   const double* __restrict__ part, int nb,
+                                                   const unsigned long long* __restrict__ vfx,
+                                                   const unsigned long long* __restrict__ pfx, double alpha,
+                                                   double* __restrict__ out) {
+    __shared__ double shp[16];
+    __shared__ unsigned long long shw[16];
+    double lmax = -INFINITY;
+    for (int b = 0; b < nb; ++b) lmax = fmax(lmax, part[2 * b]);
+    double ps = 0.0;
+    unsigned long long ws = 0ull;
+    for (int j = threadIdx.x; j < m; j += 1024) {
+        if (isfinite(tll[j])) ps += exp(tll[j] - lmax) * ((double)vfx[j] / kVolScale);
+        ws += pfx[j];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        ps += __shfl_xor(ps, o);
+        ws += __shfl_xor(ws, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        shp[threadIdx.x >> 6] = ps;
+        shw[threadIdx.x >> 6] = ws;
+    }
+    __syncthreads();
+    double ptot = 0.0;
+    unsigned long long wtot = 0ull;
+    for (int q = 0; q < 16; ++q) {
+        ptot += shp[q];
+        wtot += shw[q];
+    }
+    for (int j = threadIdx.x; j < m; j += 1024) {
+        const double v = (double)vfx[j] / kVolScale;
+        const double pj = (ptot > 0.0 && isfinite(tll[j])) ? exp(tll[j] - lmax) * v / ptot : 0.0;
+        const double hj = wtot > 0ull ? (double)pfx[j] / (double)wtot : 0.0;
+        const double pi = (1.0 - alpha) * hj + alpha * pj;
+        out[j] = (pi > 0.0 && v > 0.0) ? log(pi) - log(v) : -INFINITY;
+    }
+}
+
 // ------------------------------------------------------------------- scratch
 // One growing device buffer per stream; work on a stream is ordered, so it is
 // reused safely, and the stream is drained before a buffer is replaced.
@@ -581,6 +655,35 @@ extern "C" pe_status_t pe_tile_draw(int32_t n_tiles, const double* tile_loglike_
         k_tile_pick<11><<<nblocks(n), 256, 0, st>>>(C, n_samples, mx, tile_loglike_dev, tile_of_dev,
                                                      sample_logprior_dev, samples_theta_dev, ld, seed, stream_id, n,
                                                      theta_dev, logq_dev, logprior_dev, index_dev);
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+}
+
+extern "C" pe_status_t pe_tile_reweight(int32_t n_tiles, const double* tile_loglike_dev, int64_t n_samples,
+                                        const int32_t* tile_of_dev, const double* sample_logprior_dev, int64_t n,
+                                        const int64_t* index_dev, const double* w_dev, double alpha, double* out_dev,
+                                        void* stream) {
+    if (n_tiles < 1 || n_tiles > (1 << 24)) return fail(PE_ERR_ARG, "bad n_tiles");
+    if (n_samples < 1 || n_samples > ((int64_t)1 << 31)) return fail(PE_ERR_ARG, "n_samples must be in 1..2^31");
+    if (n < 0 || n > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "n must be in 0..2^30");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(PE_ERR_ARG, "alpha must be in [0, 1]");
+    if (!tile_loglike_dev || !tile_of_dev || !sample_logprior_dev || !out_dev || (n > 0 && (!index_dev || !w_dev)))
+        return fail(PE_ERR_ARG, "NULL pointer");
+    if (out_dev == tile_loglike_dev) return fail(PE_ERR_ARG, "out may not alias tile_loglike");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int nbm = 64;
+    const size_t bytes = sizeof(double) * 2 * nbm + sizeof(unsigned long long) * 2 * (size_t)n_tiles;
+    char* scr = nullptr;
+    pe_status_t s = scratch_for(st, bytes, &scr);
+    if (s != PE_OK) return s;
+    double* part = reinterpret_cast<double*>(scr);
+    unsigned long long* vfx = reinterpret_cast<unsigned long long*>(part + 2 * nbm);
+    unsigned long long* pfx = vfx + n_tiles;
+    k_rw_zero<<<nblocks(n_tiles), 256, 0, st>>>(n_tiles, vfx, pfx);
+    k_tile_max<<<nbm, 256, 0, st>>>(n_tiles, tile_loglike_dev, n_samples, sample_logprior_dev, part);
+    k_rw_prior<<<nblocks(n_samples), 256, 0, st>>>(part, nbm, n_samples, tile_of_dev, sample_logprior_dev, vfx);
+    if (n > 0) k_rw_post<<<nblocks(n), 256, 0, st>>>(n, index_dev, w_dev, tile_of_dev, pfx);
+    k_rw_final<<<1, 1024, 0, st>>>(n_tiles, tile_loglike_dev, part, nbm, vfx, pfx, alpha, out_dev);
     PE_HIP(hipGetLastError());
     return PE_OK;
 }

@@ -16,6 +16,16 @@ from paper_2410_05190_amd import binding
 pytestmark = pytest.mark.gpu
 
 
+def dev_i32(x):
+    torch = torch_cuda()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).cuda()
+
+
+def dev_i64(x):
+    torch = torch_cuda()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int64)).cuda()
+
+
 def _slices(b, radius):
     g = b.ev.metric(b.theta_inj)
     L = np.linalg.cholesky(g)
@@ -87,8 +97,7 @@ def test_draw_parity_on_the_same_inputs():
         smp = rng.normal(0.0, 1.0, (4, P))
         note(f"tile draw: P {P}, M {M}, n {n}")
         rc, tho, lqo, lpo, idxo = oracle.tile_draw(tl, to, lp, smp, 61, 4, n)
-        th, lq, lpg, idx = binding.tile_draw(dev(tl), dev(to).to(dtype=__import__("torch").int32), dev(lp), dev(smp),
-                                             61, 4, n)
+        th, lq, lpg, idx = binding.tile_draw(dev(tl), dev_i32(to), dev(lp), dev(smp), 61, 4, n)
         th, lq, lpg, idx = host(th), host(lq), host(lpg), host(idx)
         same = idx == idxo
         # picks differ only where the uniform lands within rounding of a cumulative boundary
@@ -104,9 +113,30 @@ def test_draw_parity_on_the_same_inputs():
         assert np.array_equal(lpg[same], lpo[same])
         np.testing.assert_allclose(lq[same], lqo[same], rtol=0, atol=1e-12)
     # no positive mass
-    th, lq, lpg, idx = binding.tile_draw(dev(np.full(2, -np.inf)), dev(np.zeros(10)).to(dtype=__import__("torch").int32),
-                                         dev(np.zeros(10)), dev(np.ones((4, 10))), 1, 0, 5)
+    th, lq, lpg, idx = binding.tile_draw(dev(np.full(2, -np.inf)), dev_i32(np.zeros(10)), dev(np.zeros(10)),
+                                         dev(np.ones((4, 10))), 1, 0, 5)
     assert np.all(host(idx) == -1) and np.all(host(lpg) == -np.inf) and np.all(host(lq) == 0)
+
+
+def test_reweight_parity():
+    torch_cuda()
+    rng = np.random.default_rng(71)
+    for P, M, n, alpha, flat in ((300000, 1200, 40000, 0.1, True), (5000, 40, 3000, 0.0, False),
+                                 (777, 3, 100, 1.0, False)):
+        to = rng.integers(0, M, P).astype(np.int32)
+        tl = rng.normal(0.0, 2.0, M)
+        tl[rng.random(M) < 0.1] = -np.inf
+        lp = np.zeros(P) if flat else rng.normal(0.0, 0.4, P)
+        idx = rng.integers(-1, P, n)
+        w = rng.random(n) ** 4
+        w[rng.random(n) < 0.2] = 0.0
+        w /= w.sum()
+        note(f"reweight: P {P}, M {M}, n {n}, alpha {alpha}")
+        want = oracle.tile_reweight(tl, to, lp, idx, w, alpha)
+        got = host(binding.tile_reweight(dev(tl), dev_i32(to), dev(lp), dev_i64(idx), dev(w), alpha))
+        assert np.array_equal(np.isfinite(got), np.isfinite(want))
+        fin = np.isfinite(want)
+        np.testing.assert_allclose(got[fin], want[fin], rtol=0, atol=1e-9)
 
 
 def test_tile_mixture_chain_on_the_gpu():
@@ -131,4 +161,12 @@ def test_tile_mixture_chain_on_the_gpu():
     st = host(st)
     note(f"tile chain: {ty.shape[1]} tiles, {y.shape[1]} samples, ESS {st[0]:.0f} of {n} ({st[0] / n:.1%})")
     assert st[0] / n > 0.02
+    # second round with the tiles reweighted by the first round's weights
+    ell = binding.tile_reweight(llt, to, lp, idx, w, 0.1)
+    thd, lq, lpd, idx = binding.tile_draw(ell, to, lp, th, 7, 1, n)
+    ll = ev.loglike(thd)
+    w, st2 = binding.weights_ess(ll, lpd, lq)
+    st2 = host(st2)
+    note(f"reweighted round: ESS {st2[0]:.0f} of {n} ({st2[0] / n:.1%})")
+    assert st2[0] / n > 0.2 and st2[0] > 3 * st[0]
     ev.close()
