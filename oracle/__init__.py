@@ -106,6 +106,9 @@ def lib():
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_long, _dp, _dp, _dp, _lp]
         L.peo_tile_reweight.argtypes = [ctypes.c_long, _dp, ctypes.c_long, _ip, _dp, ctypes.c_long, _lp, _dp,
                                         ctypes.c_double, _dp]
+        L.peo_relbin_edges.restype = ctypes.c_long
+        L.peo_relbin_edges.argtypes = [ctypes.POINTER(_Event), ctypes.c_double, ctypes.c_long, _lp]
+        L.peo_relbin_loglike.argtypes = [ctypes.POINTER(_Event), _dp, ctypes.c_long, _lp, _dp, ctypes.c_long, _dp, _dp]
         L.peo_proposal_update.restype = ctypes.c_long
         L.peo_proposal_update.argtypes = [ctypes.POINTER(_Event), _dp, _dp, ctypes.c_long, _dp, _dp, _dp]
         _lib = L
@@ -289,6 +292,25 @@ class Event:
                                 int(max_tiles), float(stop_fraction), int(max_batches), _p(ty), _p(tth),
                                 ctypes.byref(used))
         return ty[:, :m].copy(), tth[:, :m].copy(), int(used.value)
+
+    # ---- relative binning ----
+    def relbin_edges(self, eps, max_edges=1 << 20):
+        e = np.zeros(max_edges, dtype=np.int64)
+        m = lib().peo_relbin_edges(self.ref, float(eps), int(max_edges), e.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
+        if m < 0:
+            raise ValueError("too many relative-binning edges")
+        return e[:m].copy()
+
+    def relbin_loglike(self, theta_f, edges, theta, return_zh=False):
+        tf = _f64(theta_f)
+        ed = np.ascontiguousarray(edges, dtype=np.int64)
+        th = _f64(theta)
+        n = th.shape[1]
+        ll = np.zeros(n)
+        zh = np.zeros((n, 3))
+        lib().peo_relbin_loglike(self.ref, _p(tf), ed.shape[0], ed.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                                 _p(th), n, _p(ll), _p(zh))
+        return (ll, zh) if return_zh else ll
 
     def logprior(self, theta):
         th = _f64(theta)

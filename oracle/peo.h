@@ -154,6 +154,12 @@ int peo_tile_draw(long n_tiles, const double *tile_ll, long P, const int *tile_o
 void peo_tile_reweight(long n_tiles, const double *tile_ll, long P, const int *tile_of, const double *lp, long n,
                        const long *index, const double *w, double alpha, double *out);
 
+/* Relative binning: bin edges from the phase envelope (returns the number of
+ * edges or -1), and log-likelihoods of draws about a fiducial point. */
+long peo_relbin_edges(const peo_event *ev, double eps, long max_edges, long *edges);
+void peo_relbin_loglike(const peo_event *ev, const double *theta_f, long n_edges, const long *edges,
+                        const double *theta, long n, double *loglike, double *zh);
+
 /* Weighted centre and covariance of draws about theta0 (proposal update between
  * rounds). theta0_out [D]; cov [D*D] or NULL. Returns the number of w > 0. */
 long peo_proposal_update(const peo_event *ev, const double *theta0, const double *theta, long n, const double *w,
