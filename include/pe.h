@@ -71,7 +71,9 @@ typedef enum {
     PE_ERR_TIMEOUT = 7    /* a wait ended before the request completed */
 } pe_status_t;
 
-typedef enum { PE_PREC_FP64 = 0, PE_PREC_SPLIT = 1 } pe_precision_t;
+/* PE_PREC_RELBIN: relative binning about the fiducial point of the last
+ * pe_relbin_setup on the event (pe_loglike_batch only). */
+typedef enum { PE_PREC_FP64 = 0, PE_PREC_SPLIT = 1, PE_PREC_RELBIN = 2 } pe_precision_t;
 typedef enum { PE_PHASE_MARG = 0, PE_PHASE_EXPLICIT = 1 } pe_phase_t;
 typedef enum { PE_PARAMS_4D = 0, PE_PARAMS_11D = 1 } pe_params_t;
 typedef enum { PE_C128 = 0, PE_C64 = 1 } pe_data_dtype_t;
@@ -403,6 +405,34 @@ pe_status_t pe_tile_reweight(int32_t n_tiles, const double *tile_loglike_dev, in
                              const int32_t *tile_of_dev, const double *sample_logprior_dev, int64_t n,
                              const int64_t *index_dev, const double *w_dev, double alpha, double *out_dev,
                              void *stream);
+
+/*
+ * Relative binning (Zackay, Dai & Venumadhav 2018; the paper lists such
+ * reduced representations among the ways to speed the likelihood up, Sec. I).
+ * About a fiducial point theta_f near the peak, the ratio rho_d(f) =
+ * exp(-i (Phi_d - Phi0_d)(f)) of a draw's phase factor to the fiducial's is
+ * smooth in f; it is replaced in each bin by its linear interpolation between
+ * the bin edges, so that
+ *   Z_d = R_d sum_b [rho_d(f_b) A0_{d,b} + s_{d,b} A1_{d,b}],
+ *   s_{d,b} = (rho_d(f_{b+1}) - rho_d(f_b)) / (f_{b+1} - f_b),
+ *   A0_{d,b} = sum_{k in b, k < kcut} a_k,  A1_{d,b} = sum_{k in b, k < kcut} a_k (f_k - f_b),
+ *   a_k = conj(w_k) exp(-i Phi0_d(f_k))  (w as in pe_loglike_batch),
+ * with the bin holding the draw's cut summed only below it; (h|h) stays exact.
+ * Edges: grid indices 0 = k_0 < ... < k_B = K; the next edge is the first k
+ * where E(f) = 2 pi sum_a sgn(a) (f / f_a)^a (a in {-5/3, -2/3, 1, 5/3, 7/3},
+ * f_a = f_lo for a < 0, f_lo + K df for a > 0) has grown by at least eps.
+ * pe_relbin_setup computes the edges on the host, then the fiducial phases
+ * and the per-bin and prefix sums on the device (it allocates and
+ * synchronises); afterwards pe_loglike_batch(..., PE_PREC_RELBIN, ...)
+ * evaluates draws at O(bins) cost each. A new setup replaces the previous
+ * one; pe_event_update does not refresh it (set up again after new data).
+ *   theta_f_dev: D doubles (device). eps > 0 (0 gives one bin per grid
+ *   point); at most max_edges edges (PE_ERR_BUDGET beyond).
+ * pe_relbin_edges copies the edges to a host array of capacity cap and
+ * writes their number to *n (0 before any setup).
+ */
+pe_status_t pe_relbin_setup(pe_event_t ev, const double *theta_f_dev, double eps, int32_t max_edges, void *stream);
+pe_status_t pe_relbin_edges(pe_event_t ev, int64_t *edges, int32_t cap, int32_t *n);
 
 /* The proposal's uniforms: u_dev[(i*npairs + j)*2 + {0,1}] for draw i and
  * block j < npairs, exactly the values pe_draw uses. */

@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "PE_OK", 1: "PE_ERR_ARG", 2: "PE_ERR_OOM", 3: "PE_ERR_HIP", 4
 PE_ERR_BUDGET = 6
 PE_PREC_FP64 = 0
 PE_PREC_SPLIT = 1
+PE_PREC_RELBIN = 2
 PE_PHASE_MARG = 0
 PE_PHASE_EXPLICIT = 1
 PE_PARAMS_4D = 0
@@ -31,7 +32,8 @@ MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
            "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_proposal_update", "pe_refine", "pe_slice_sample", "pe_tile_bank",
-           "pe_tile_assign", "pe_tile_draw", "pe_tile_reweight", "pe_waveform",
+           "pe_tile_assign", "pe_tile_draw", "pe_tile_reweight", "pe_relbin_setup", "pe_relbin_edges",
+           "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
            "pe_autotune_plan", "pe_last_error",
            "pe_server_create", "pe_server_submit", "pe_server_wait", "pe_server_now", "pe_server_counters",
@@ -526,6 +528,22 @@ class Event:
         m, used = pe_tile_bank(self.handle, slice_, min_dist, seed, stream_id, batch, max_tiles, stop_fraction,
                                max_batches, ty, tth, stream)
         return ty[:, :m], tth[:, :m], used
+
+    def relbin_setup(self, theta_f, eps, max_edges=1 << 20, stream=None):
+        """pe_relbin_setup: relative binning about theta_f (device tensor [D]); then
+        loglike(..., precision=PE_PREC_RELBIN)."""
+        import torch
+        _check(load().pe_relbin_setup(self.handle, _ptr(theta_f, torch.float64, "theta_f"), float(eps),
+                                      int(max_edges), _stream(stream)))
+
+    def relbin_edges(self):
+        import numpy as np
+        n = ctypes.c_int32(0)
+        _check(load().pe_relbin_edges(self.handle, None, 0, ctypes.byref(n)))
+        out = np.zeros(max(n.value, 1), dtype=np.int64)
+        if n.value:
+            _check(load().pe_relbin_edges(self.handle, out.ctypes.data_as(ctypes.c_void_p), n.value, ctypes.byref(n)))
+        return out[: n.value]
 
     def loglike(self, theta, precision=PE_PREC_SPLIT, aux=False, stream=None):
         import torch

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpe.so")
-SOURCES = ["pe_kernels.hip", "pe_loglike.hip", "pe_api.hip", "pe_server.hip", "pe_tiles.hip"]
+SOURCES = ["pe_kernels.hip", "pe_loglike.hip", "pe_api.hip", "pe_server.hip", "pe_tiles.hip", "pe_relbin.hip"]
 ARCH = os.environ.get("PE_OFFLOAD_ARCH", "gfx950")
 
 

@@ -205,6 +205,7 @@ void free_event(pe_event_s* ev) {
         dfree_bytes(ev->tab_mem);
         dfree_bytes(ev->ws_mem);
     }
+    dfree_bytes(ev->rb_mem);
     delete ev;
 }
 
@@ -666,6 +667,13 @@ pe_status_t pe_draw(pe_event_t ev, const double* theta0_dev, const double* g_dev
 pe_status_t pe_loglike_batch(pe_event_t ev, const double* theta_dev, int64_t n, int32_t precision,
                              double* loglike_dev, double* aux_dev, void* stream) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (precision == PE_PREC_RELBIN) {
+        pe_status_t s = check_n(n);
+        if (s != PE_OK) return s;
+        if (n == 0) return PE_OK;
+        if (!theta_dev || !loglike_dev) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
+        return run_relbin(ev, theta_dev, n, loglike_dev, aux_dev, as_stream(stream));
+    }
     pe_status_t s = check_n(n);
     if (s == PE_OK) s = check_precision(precision);
     if (s != PE_OK) return s;

@@ -97,5 +97,7 @@ pe_status_t run_draw(const std::vector<DrawArg>& v, hipStream_t st);
 pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t st);
 pe_status_t run_weights(const std::vector<WeightArg>& v, hipStream_t st);
 pe_status_t run_update(const std::vector<UpdateArg>& v, hipStream_t st);
+// Relative-binning log-likelihoods (pe_relbin.hip); needs pe_relbin_setup.
+pe_status_t run_relbin(pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux, hipStream_t st);
 
 }  // namespace pe

@@ -238,6 +238,15 @@ struct pe_event_s {
     char *tab_mem = nullptr;
     char *ws_mem = nullptr;
     bool own_mem = true;
+    // relative binning about a fiducial point (pe_relbin_setup); own memory
+    int32_t rb_n = 0;            // bin edges (bins = rb_n - 1)
+    char *rb_mem = nullptr;
+    int64_t *rb_k = nullptr;     // [rb_n] grid index of each edge
+    double *rb_erec = nullptr;   // [rb_n][4] f, f^(1/3), f^(-5/3), ln(f)/3 at the edges
+    double *rb_phi0 = nullptr;   // [n_det][rb_n] fiducial phase at the edges, turns
+    double2 *rb_A = nullptr;     // [n_det][rb_n - 1][2] per-bin sums A0, A1
+    double2 *rb_P = nullptr;     // [n_det][K + 1][2] prefix sums P0, P1 (partial bins)
+    double *rb_fid = nullptr;    // [PE_MAX_DIM] fiducial point
 };
 
 namespace pe {

@@ -1,0 +1,76 @@
+"""Relative binning (Zackay, Dai & Venumadhav 2018) on the GPU, through the C ABI: bin edges equal
+to the oracle's, log-likelihoods equal to the oracle's relative-binning evaluation on the same
+draws (FP64 on both sides, sums in different orders), the exact limits (the fiducial point; one
+bin per grid point equals the plain FP64 path), the error against the exact likelihood on
+proposal draws, and the error path without a setup."""
+import numpy as np
+import pytest
+
+import oracle
+from events import build_event
+from gpu_util import dev, host, note, torch_cuda, upload_event
+from paper_2410_05190_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("cfg,n_bins,n", [(0, None, 300), (1, 60000, 200), (1, None, 48)])
+def test_relbin_parity_with_the_oracle(cfg, n_bins, n):
+    torch_cuda()
+    b = build_event(cfg, 1, n_bins=n_bins)
+    ev, data, psd = upload_event(b)
+    eps = 0.03
+    ev.relbin_setup(dev(b.theta_inj), eps)
+    e = ev.relbin_edges()
+    eo = b.ev.relbin_edges(eps)
+    assert np.array_equal(e, eo)
+    g = b.ev.metric(b.theta_inj)
+    rc, th, lq, lp = b.ev.draw(b.theta_inj, g, 17, 0, n)
+    note(f"relbin parity: config {cfg}, K {b.n_bins}, {len(e)} edges, {n} draws")
+    ll, aux = ev.loglike(dev(th), precision=binding.PE_PREC_RELBIN, aux=True)
+    ll, aux = host(ll), host(aux)
+    llo, zo = b.ev.relbin_loglike(b.theta_inj, eo, th, return_zh=True)
+    f = np.isfinite(llo)
+    assert np.array_equal(np.isfinite(ll), f)
+    scale = np.abs(zo[f]).max()
+    np.testing.assert_allclose(aux[f], zo[f], rtol=0, atol=1e-11 * scale)
+    np.testing.assert_allclose(ll[f], llo[f], rtol=0, atol=1e-9 * scale)
+    ev.close()
+
+
+def test_relbin_exact_limits_and_error():
+    torch = torch_cuda()
+    b = build_event(1, 2, n_bins=30000)
+    ev, data, psd = upload_event(b)
+    g = b.ev.metric(b.theta_inj)
+    rc, th, lq, lp = b.ev.draw(b.theta_inj, g, 5, 0, 500)
+    exact = host(ev.loglike(dev(th), precision=binding.PE_PREC_FP64))
+    f = np.isfinite(exact)
+    # one bin per grid point: the linear model is exact at every grid point
+    ev.relbin_setup(dev(b.theta_inj), 0.0)
+    assert len(ev.relbin_edges()) == b.n_bins + 1
+    r0 = host(ev.loglike(dev(th), precision=binding.PE_PREC_RELBIN))
+    np.testing.assert_allclose(r0[f], exact[f], rtol=1e-10, atol=1e-8)
+    # the fiducial point itself is exact with any bins
+    ev.relbin_setup(dev(b.theta_inj), 0.1)
+    rf = host(ev.loglike(dev(b.theta_inj[:, None]), precision=binding.PE_PREC_RELBIN))
+    ef = host(ev.loglike(dev(b.theta_inj[:, None]), precision=binding.PE_PREC_FP64))
+    np.testing.assert_allclose(rf, ef, rtol=1e-10)
+    # proposal draws: the binning error at eps = 0.03
+    ev.relbin_setup(dev(b.theta_inj), 0.03)
+    r = host(ev.loglike(dev(th), precision=binding.PE_PREC_RELBIN))
+    err = np.abs(r[f] - exact[f])
+    note(f"relbin error on 500 proposal draws (eps 0.03): max {err.max():.2e} median {np.median(err):.2e}")
+    assert err.max() < 0.1
+    ev.close()
+
+
+def test_relbin_needs_a_setup():
+    torch = torch_cuda()
+    b = build_event(0, 0, n_bins=2048)
+    ev, data, psd = upload_event(b)
+    with pytest.raises(binding.PeError):
+        ev.loglike(dev(b.theta_inj[:, None]), precision=binding.PE_PREC_RELBIN)
+    with pytest.raises(binding.PeError):
+        ev.relbin_setup(dev(b.theta_inj), 0.03, max_edges=8)
+    ev.close()
