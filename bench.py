@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--refine-rounds", type=int, default=3,
                     help="rounds of proposal refinement before the refined-proposal leg (0 skips the leg)")
     ap.add_argument("--refine-draws", type=int, default=16384, help="draws per refinement round")
+    ap.add_argument("--relbin-eps", type=float, default=0.03,
+                    help="relative-binning leg: envelope step between bin edges (0 skips the leg)")
     ap.add_argument("--tile-radius", type=float, default=6.0, help="tile-mixture leg: slice radius (whitened)")
     ap.add_argument("--tile-spacing", type=float, default=1.0, help="tile-mixture leg: template spacing (whitened)")
     ap.add_argument("--tile-candidates", type=int, default=4000000,
@@ -232,6 +234,8 @@ def main():
     first = evs[0]
     if n_events == 1 and args.refine_rounds > 0:
         out["refined"] = refine_leg(first, args.refine_rounds, args.refine_draws, max(args.steps, 1), prec)
+    if n_events == 1 and args.relbin_eps > 0:
+        out["relbin"] = relbin_leg(first, args.relbin_eps, max(args.steps, 1), prec)
     if n_events == 1 and D == 4 and args.tile_candidates > 0:
         out["tiles"] = tile_leg(first, args, max(args.steps, 1), prec)
     n_drift = args.drift_sample if args.drift_sample >= 0 else (1024 if c == 4 else 0)
@@ -295,6 +299,54 @@ def refine_leg(x, rounds, n_round, steps, prec):
         "ess_per_s_with_refine": ess_f / (t_ref + t_step),
         "evals_per_s": float(sf[:, 3].sum()) / (tc - tb),
         "centre": [float(v) for v in t0.cpu().numpy()],
+    }
+
+
+def relbin_leg(x, eps, steps, prec):
+    """Relative binning about the injection (the trigger point): the same step as the main leg
+    (event update, metric, N draws, likelihoods, weights) with relative-binning likelihoods, and
+    the binning error against the main leg's precision on the last step's draws."""
+    import numpy as np
+    import torch
+
+    from paper_2410_05190_amd import binding
+    ev = x["ev"]
+    h_ = ev.handle
+    N = x["N"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev.relbin_setup(x["theta0"], eps)
+    t1 = time.perf_counter()
+    n_edges = len(ev.relbin_edges())
+    st = torch.empty((steps, 4), dtype=torch.float64, device="cuda")
+    for i in range(-1, steps):  # step -1: untimed warm-up
+        if i == 0:
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        binding.pe_event_update(h_, x["data"], x["psd"])
+        binding.pe_metric(h_, x["theta0"], None, 0, x["g"])
+        binding.pe_draw(h_, x["theta0"], x["g"], x["seed"], max(i, 0), N, x["theta"], x["lq"], x["lp"])
+        binding.pe_loglike_batch(h_, x["theta"], N, binding.PE_PREC_RELBIN, x["ll"], None)
+        binding.pe_weights_ess(x["ll"], x["lp"], x["lq"], N, x["w"], st[max(i, 0)])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ll_rb = x["ll"].clone()
+    binding.pe_loglike_batch(h_, x["theta"], N, prec, x["ll"], None)
+    torch.cuda.synchronize()
+    ev.status()
+    a, b = ll_rb.cpu().numpy(), x["ll"].cpu().numpy()
+    f = np.isfinite(b)
+    err = np.abs(a[f] - b[f])
+    s = st.cpu().numpy()
+    t_step = (t3 - t2) / steps
+    return {
+        "kind": "relative binning about the trigger point (per-bin sums of the fiducial-phased data)",
+        "eps": eps, "edges": n_edges, "setup_ms": 1e3 * (t1 - t0), "steps": steps, "draws_per_step": N,
+        "ms_per_step": 1e3 * t_step, "evals_per_s": float(s[:, 3].sum()) / (t3 - t2),
+        "ess_per_event_mean": float(s[:, 0].mean()), "ess_per_s": float(s[:, 0].mean()) / t_step,
+        "abs_dlnL_vs_main_precision": {"max": float(err.max()) if err.size else None,
+                                       "median": float(np.median(err)) if err.size else None,
+                                       "draws": int(err.size)},
     }
 
 
