@@ -203,15 +203,74 @@ __device__ __forceinline__ void rb_rho(const PhaseCoef& pc, double tau, const do
     ri = -sn;
 }
 
+// kRbSeg adjacent lanes per draw, each over one contiguous quarter of the
+// bins (more waves in flight than one lane per draw); partial sums combined
+// by shuffles, written by the first lane of the draw.
+constexpr int kRbSeg = 4;
+
 __global__ __launch_bounds__(256) void k_rb_ll(RbArg a) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.n) return;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = t / kRbSeg;
+    const int sg = (int)(t - i * kRbSeg);
     const EvConst& ev = a.ec;
-    double th[PE_MAX_DIM];
+    double zr = 0.0, zi = 0.0, h = 0.0;
+    int ok = 0;
+    if (i < a.n) {
+        double th[PE_MAX_DIM];
 #pragma unroll
-    for (int q = 0; q < PE_MAX_DIM; ++q) th[q] = (q < ev.dim) ? a.theta[(int64_t)q * a.n + i] : 0.0;
-    Src s;
-    if (!source_from_theta(ev, th, s)) {
+        for (int q = 0; q < PE_MAX_DIM; ++q) th[q] = (q < ev.dim) ? a.theta[(int64_t)q * a.n + i] : 0.0;
+        Src s;
+        ok = source_from_theta(ev, th, s);
+        if (ok) {
+            PhaseCoef pc;
+            phase_coeffs(s, pc);
+            const int64_t K = ev.K;
+            const int64_t kc = kcut_of(ev, s.fisco);
+            const int nb = a.n_edges - 1;
+            const int b0 = (int)((int64_t)sg * nb / kRbSeg), b1 = (int)((int64_t)(sg + 1) * nb / kRbSeg);
+#pragma unroll
+            for (int d = 0; d < PE_MAX_DET; ++d) {  // fixed bound: the per-detector arrays stay in registers
+                if (d >= ev.n_det) break;
+                h += (s.rre[d] * s.rre[d] + s.rim[d] * s.rim[d]) * a.pfx[(int64_t)d * (K + 1) + kc];
+                if (b0 >= b1 || a.kk[b0] >= kc) continue;
+                const double tau = s.tc + s.dt[d];
+                const double* phd = a.phi0 + (int64_t)d * a.n_edges;
+                const double2* Ad = a.A + (int64_t)d * nb * 2;
+                const double2* Pd = a.P + (int64_t)d * (K + 1) * 2;
+                double ur = 0.0, ui = 0.0, r0r, r0i;
+                rb_rho(pc, tau, a.erec + 4 * b0, phd[b0], r0r, r0i);
+                for (int b = b0; b < b1 && a.kk[b] < kc; ++b) {
+                    double r1r, r1i;
+                    rb_rho(pc, tau, a.erec + 4 * (b + 1), phd[b + 1], r1r, r1i);
+                    const double inv = 1.0 / (a.erec[4 * (b + 1)] - a.erec[4 * b]);
+                    const double sr = (r1r - r0r) * inv, si = (r1i - r0i) * inv;
+                    double2 A0, A1;
+                    if (a.kk[b + 1] <= kc) {
+                        A0 = Ad[2 * b];
+                        A1 = Ad[2 * b + 1];
+                    } else {
+                        const double2 p0 = Pd[2 * kc], q0 = Pd[2 * a.kk[b]];
+                        const double2 p1 = Pd[2 * kc + 1], q1 = Pd[2 * a.kk[b] + 1];
+                        A0 = make_double2(p0.x - q0.x, p0.y - q0.y);
+                        A1 = make_double2(p1.x - q1.x, p1.y - q1.y);
+                    }
+                    ur += r0r * A0.x - r0i * A0.y + sr * A1.x - si * A1.y;
+                    ui += r0r * A0.y + r0i * A0.x + sr * A1.y + si * A1.x;
+                    r0r = r1r;
+                    r0i = r1i;
+                }
+                zr += s.rre[d] * ur - s.rim[d] * ui;
+                zi += s.rre[d] * ui + s.rim[d] * ur;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < kRbSeg; o <<= 1) {
+        zr += __shfl_xor(zr, o);
+        zi += __shfl_xor(zi, o);
+    }
+    if (i >= a.n || sg != 0) return;
+    if (!ok) {
         a.loglike[i] = -INFINITY;
         if (a.aux) {
             a.aux[3 * i] = 0.0;
@@ -219,45 +278,6 @@ __global__ __launch_bounds__(256) void k_rb_ll(RbArg a) {
             a.aux[3 * i + 2] = 0.0;
         }
         return;
-    }
-    PhaseCoef pc;
-    phase_coeffs(s, pc);
-    const int64_t K = ev.K;
-    const int64_t kc = kcut_of(ev, s.fisco);
-    double zr = 0.0, zi = 0.0, h = 0.0;
-    const int nb = a.n_edges - 1;
-#pragma unroll
-    for (int d = 0; d < PE_MAX_DET; ++d) {  // fixed bound: the per-detector arrays stay in registers
-        if (d >= ev.n_det) break;
-        h += (s.rre[d] * s.rre[d] + s.rim[d] * s.rim[d]) * a.pfx[(int64_t)d * (K + 1) + kc];
-        const double tau = s.tc + s.dt[d];
-        const double* phd = a.phi0 + (int64_t)d * a.n_edges;
-        const double2* Ad = a.A + (int64_t)d * nb * 2;
-        const double2* Pd = a.P + (int64_t)d * (K + 1) * 2;
-        double ur = 0.0, ui = 0.0, r0r, r0i;
-        rb_rho(pc, tau, a.erec, phd[0], r0r, r0i);
-        for (int b = 0; b < nb && a.kk[b] < kc; ++b) {
-            double r1r, r1i;
-            rb_rho(pc, tau, a.erec + 4 * (b + 1), phd[b + 1], r1r, r1i);
-            const double inv = 1.0 / (a.erec[4 * (b + 1)] - a.erec[4 * b]);
-            const double sr = (r1r - r0r) * inv, si = (r1i - r0i) * inv;
-            double2 A0, A1;
-            if (a.kk[b + 1] <= kc) {
-                A0 = Ad[2 * b];
-                A1 = Ad[2 * b + 1];
-            } else {
-                const double2 p0 = Pd[2 * kc], q0 = Pd[2 * a.kk[b]];
-                const double2 p1 = Pd[2 * kc + 1], q1 = Pd[2 * a.kk[b] + 1];
-                A0 = make_double2(p0.x - q0.x, p0.y - q0.y);
-                A1 = make_double2(p1.x - q1.x, p1.y - q1.y);
-            }
-            ur += r0r * A0.x - r0i * A0.y + sr * A1.x - si * A1.y;
-            ui += r0r * A0.y + r0i * A0.x + sr * A1.y + si * A1.x;
-            r0r = r1r;
-            r0i = r1i;
-        }
-        zr += s.rre[d] * ur - s.rim[d] * ui;
-        zi += s.rre[d] * ui + s.rim[d] * ur;
     }
     const double ll = (ev.phase == PE_PHASE_EXPLICIT) ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
     a.loglike[i] = ll;
@@ -287,7 +307,7 @@ pe_status_t run_relbin(pe_event_s* ev, const double* theta, int64_t n, double* l
     a.A = ev->rb_A;
     a.P = ev->rb_P;
     a.n_edges = ev->rb_n;
-    k_rb_ll<<<nblk(n), 256, 0, st>>>(a);
+    k_rb_ll<<<nblk(n * kRbSeg), 256, 0, st>>>(a);
     PE_HIP(hipGetLastError());
     return PE_OK;
 }
