@@ -337,6 +337,8 @@ def relbin_leg(x, eps, steps, prec):
     a, b = ll_rb.cpu().numpy(), x["ll"].cpu().numpy()
     f = np.isfinite(b)
     err = np.abs(a[f] - b[f])
+    # where the weights are: ln L within 20 of the largest (the far tails carry no weight)
+    core = b[f] > b[f].max() - 20.0 if err.size else np.zeros(0, dtype=bool)
     s = st.cpu().numpy()
     t_step = (t3 - t2) / steps
     return {
@@ -346,7 +348,9 @@ def relbin_leg(x, eps, steps, prec):
         "ess_per_event_mean": float(s[:, 0].mean()), "ess_per_s": float(s[:, 0].mean()) / t_step,
         "abs_dlnL_vs_main_precision": {"max": float(err.max()) if err.size else None,
                                        "median": float(np.median(err)) if err.size else None,
-                                       "draws": int(err.size)},
+                                       "draws": int(err.size),
+                                       "max_within_20_of_peak": float(err[core].max()) if core.any() else None,
+                                       "draws_within_20_of_peak": int(core.sum())},
     }
 
 

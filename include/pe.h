@@ -429,7 +429,8 @@ pe_status_t pe_tile_reweight(int32_t n_tiles, const double *tile_loglike_dev, in
  *   theta_f_dev: D doubles (device). eps > 0 (0 gives one bin per grid
  *   point); at most max_edges edges (PE_ERR_BUDGET beyond).
  * pe_relbin_edges copies the edges to a host array of capacity cap and
- * writes their number to *n (0 before any setup).
+ * writes their number to *n (0 before any setup); with edges NULL it writes
+ * only the number.
  */
 pe_status_t pe_relbin_setup(pe_event_t ev, const double *theta_f_dev, double eps, int32_t max_edges, void *stream);
 pe_status_t pe_relbin_edges(pe_event_t ev, int64_t *edges, int32_t cap, int32_t *n);

@@ -146,6 +146,8 @@ def load(path=LIB_PATH):
         "pe_tile_assign": (i32, [i32, i32, dp, i64, i64, dp, i64, vp, vp]),
         "pe_tile_draw": (i32, [i32, dp, i64, vp, dp, i32, dp, i64, u64, u32, i64, dp, dp, dp, vp, vp]),
         "pe_tile_reweight": (i32, [i32, dp, i64, vp, dp, i64, vp, dp, ctypes.c_double, dp, vp]),
+        "pe_relbin_setup": (i32, [vp, dp, ctypes.c_double, i32, vp]),
+        "pe_relbin_edges": (i32, [vp, vp, i32, ctypes.POINTER(i32)]),
         "pe_refine": (i32, [vp, dp, dp, i32, i64, u64, i32, dp, dp, dp, dp, dp, dp, vp]),
         "pe_waveform": (i32, [ctypes.POINTER(EventDesc), dp, vp, dp, dp, vp]),
         "pe_rng_uniforms": (i32, [u64, u32, i64, i32, dp, vp]),

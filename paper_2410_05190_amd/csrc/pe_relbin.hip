@@ -385,8 +385,8 @@ extern "C" pe_status_t pe_relbin_setup(pe_event_t ev, const double* theta_f_dev,
 extern "C" pe_status_t pe_relbin_edges(pe_event_t ev, int64_t* edges, int32_t cap, int32_t* n) {
     if (!ev || !n) return fail(PE_ERR_ARG, "event and n must not be NULL");
     *n = ev->rb_n;
-    if (ev->rb_n == 0) return PE_OK;
-    if (!edges || cap < ev->rb_n) return fail(PE_ERR_ARG, "edges array too small");
+    if (ev->rb_n == 0 || !edges) return PE_OK;  // NULL edges: the count only
+    if (cap < ev->rb_n) return fail(PE_ERR_ARG, "edges array too small");
     PE_HIP(hipMemcpy(edges, ev->rb_k, sizeof(int64_t) * ev->rb_n, hipMemcpyDeviceToHost));
     return PE_OK;
 }

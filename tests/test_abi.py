@@ -29,6 +29,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_binding_declares_every_signature():
+    L = binding.load()
+    for name in binding.EXPORTS:
+        f = getattr(L, name)
+        assert f.argtypes is not None, name
+        assert f.restype is not None, name
+
+
 def test_binding_loads_and_pure_host_calls():
     L = binding.load()
     assert binding.pe_dim(binding.PE_PARAMS_4D) == 4

@@ -60,8 +60,13 @@ def test_relbin_exact_limits_and_error():
     ev.relbin_setup(dev(b.theta_inj), 0.03)
     r = host(ev.loglike(dev(th), precision=binding.PE_PREC_RELBIN))
     err = np.abs(r[f] - exact[f])
-    note(f"relbin error on 500 proposal draws (eps 0.03): max {err.max():.2e} median {np.median(err):.2e}")
-    assert err.max() < 0.1
+    # the binning error grows with the phase offset from the fiducial: what matters is the error
+    # where the weights are (within 20 of the largest ln L)
+    core = exact[f] > exact[f].max() - 20.0
+    note(f"relbin error on 500 proposal draws (eps 0.03): median {np.median(err):.2e}, max {err.max():.2e}, "
+         f"max within 20 of the peak {err[core].max():.2e} ({core.sum()} draws)")
+    assert np.median(err) < 1e-3
+    assert err[core].max() < 0.05
     ev.close()
 
 
