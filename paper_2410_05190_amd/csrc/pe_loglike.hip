@@ -400,45 +400,96 @@ struct Item {
     int e, tile, g;
 };
 
-// Next item for a workgroup on XCD x0: from queue x0, else (once it is
-// empty) from the other queues in turn; false when every queue is empty (every
-// workgroup reaches that exit).
-__device__ __forceinline__ bool next_item(BatchHdr* __restrict__ hdr, const int64_t* __restrict__ ioff, int ne,
-                                          const EvDev* __restrict__ evs, int x0, Item& it) {
-    __shared__ int s_item, s_q;
-    __syncthreads();  // every wave is done with the previous s_item
-    if (threadIdx.x == 0) {
-        int q = -1, v = 0;
-        for (int k = 0; k < kQueues; ++k) {
-            const int qq = (x0 + k) & (kQueues - 1);
-            v = atomicAdd(&hdr->qnext[qq], 1);
-            if (v < hdr->qitems[qq]) {
-                q = qq;
-                break;
-            }
-        }
-        s_q = q;
-        s_item = v;
+// Work tickets. A workgroup on XCD x0 takes items from queue x0 (for short
+// items it claims the next ticket while it works on the current one), and only
+// once queue x0 has run dry does it wait on the other queues in turn. q < 0:
+// every queue is empty (every workgroup reaches that exit).
+struct Ticket {
+    int q, v;
+};
+
+__device__ __forceinline__ Ticket steal_ticket(BatchHdr* __restrict__ hdr, int x0) {
+    for (int k = 1; k < kQueues; ++k) {
+        const int qq = (x0 + k) & (kQueues - 1);
+        const int v = atomicAdd(&hdr->qnext[qq], 1);
+        if (v < hdr->qitems[qq]) return Ticket{qq, v};
     }
-    __syncthreads();
-    const int q = __builtin_amdgcn_readfirstlane(s_q);
-    if (q < 0) return false;
-    const int x = __builtin_amdgcn_readfirstlane(s_item);
+    return Ticket{-1, 0};
+}
+
+// Checks a ticket claimed from queue x0 (thread 0 only).
+__device__ __forceinline__ Ticket own_or_steal(BatchHdr* __restrict__ hdr, int x0, int v) {
+    return (v < hdr->qitems[x0]) ? Ticket{x0, v} : steal_ticket(hdr, x0);
+}
+
+// Item of ticket (q, x).
+__device__ __forceinline__ void decode_item(const int64_t* __restrict__ ioff, int ne, const EvDev* __restrict__ evs,
+                                            int q, int x, Item& it) {
     const int64_t* o = ioff + (int64_t)q * (ne + 1);
-    it.e = find_slot(o, ne, x);
-    const int l = x - (int)o[it.e];
+    int lo = 0, hi = ne;  // o[lo] <= x < o[hi]; offsets through the scalar cache
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (load_const(o + mid) <= (int64_t)x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    it.e = lo;
+    const int l = x - (int)load_const(o + it.e);
     const int G = load_const(evs[it.e].plan).n_groups;
-    const int lo = max(0, evs[it.e].tile_lo);
+    const int tlo = max(0, evs[it.e].tile_lo);
     if (G >= kQueues) {
         const int gq = G / kQueues;
-        it.tile = lo + l / gq;
+        it.tile = tlo + l / gq;
         it.g = q + kQueues * (l - (l / gq) * gq);
     } else {
         const int f = q + kQueues * l;
-        it.tile = lo + f / G;
+        it.tile = tlo + f / G;
         it.g = f - (f / G) * G;
     }
-    return true;
+}
+
+// The persistent loop of the hot kernels: process(it) for every item this
+// workgroup draws.
+template <typename F>
+__device__ __forceinline__ void item_loop(BatchHdr* __restrict__ hdr, const int64_t* __restrict__ ioff,
+                                          const EvDev* __restrict__ evs, F process) {
+    // two ticket slots used in turn: a slot is rewritten only after the barrier
+    // that follows every wave's read of it
+    __shared__ int s_q[2], s_v[2];
+    const int ne = hdr->ne;
+    const int x0 = blockIdx.x & (kQueues - 1);
+    if (threadIdx.x == 0) {
+        const Ticket t = own_or_steal(hdr, x0, atomicAdd(&hdr->qnext[x0], 1));
+        s_q[0] = t.q;
+        s_v[0] = t.v;
+    }
+    __syncthreads();
+    int slot = 0;
+    int q = __builtin_amdgcn_readfirstlane(s_q[0]);
+    int v = __builtin_amdgcn_readfirstlane(s_v[0]);
+    while (q >= 0) {
+        Item it;
+        decode_item(ioff, ne, evs, q, v, it);
+        // Short items (under ~4k bins) claim the next ticket before they run, so
+        // the atomic's latency hides behind them; long ones claim it when done,
+        // which keeps the last items spread evenly over the workgroups.
+        const EvPlan pl = load_const(evs[it.e].plan);
+        const bool early = pl.kmax < 4096 * pl.n_groups;
+        int nv = 0;
+        if (early && threadIdx.x == 0) nv = atomicAdd(&hdr->qnext[x0], 1);
+        process(it);
+        slot ^= 1;
+        if (threadIdx.x == 0) {
+            if (!early) nv = atomicAdd(&hdr->qnext[x0], 1);
+            const Ticket t = own_or_steal(hdr, x0, nv);
+            s_q[slot] = t.q;
+            s_v[slot] = t.v;
+        }
+        __syncthreads();
+        q = __builtin_amdgcn_readfirstlane(s_q[slot]);
+        v = __builtin_amdgcn_readfirstlane(s_v[slot]);
+    }
 }
 
 // The lane's draw, its row and delays, its cut, and the wave's range of cuts.
@@ -562,10 +613,7 @@ __device__ __forceinline__ void f64_item(const EvDev& E, const EvPlan& p, int ti
 
 __global__ __launch_bounds__(256) void k_b_split(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                  const int64_t* __restrict__ ioff) {
-    const int ne = hdr->ne;
-    const int x0 = blockIdx.x & (kQueues - 1);
-    Item it;
-    while (next_item(hdr, ioff, ne, evs, x0, it)) {
+    item_loop(hdr, ioff, evs, [&](const Item& it) {
         const EvDev& E = evs[it.e];
         const EvPlan p = load_const(E.plan);
         switch (E.ec.n_det) {
@@ -574,15 +622,12 @@ __global__ __launch_bounds__(256) void k_b_split(BatchHdr* __restrict__ hdr, con
             case 3: split_item<3>(E, p, it.tile, it.g); break;
             default: split_item<4>(E, p, it.tile, it.g); break;
         }
-    }
+    });
 }
 
 __global__ __launch_bounds__(256) void k_b_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                const int64_t* __restrict__ ioff) {
-    const int ne = hdr->ne;
-    const int x0 = blockIdx.x & (kQueues - 1);
-    Item it;
-    while (next_item(hdr, ioff, ne, evs, x0, it)) {
+    item_loop(hdr, ioff, evs, [&](const Item& it) {
         const EvDev& E = evs[it.e];
         const EvPlan p = load_const(E.plan);
         switch (E.ec.n_det) {
@@ -591,7 +636,7 @@ __global__ __launch_bounds__(256) void k_b_f64(BatchHdr* __restrict__ hdr, const
             case 3: f64_item<3>(E, p, it.tile, it.g); break;
             default: f64_item<4>(E, p, it.tile, it.g); break;
         }
-    }
+    });
 }
 
 // Fixed-order combine of the group partials (8 interleaved accumulators, then a
