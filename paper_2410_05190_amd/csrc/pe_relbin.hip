@@ -194,19 +194,66 @@ struct RbArg {
     int n_edges;
 };
 
-__device__ __forceinline__ void rb_rho(const PhaseCoef& pc, double tau, const double* er, double phi0, double& rr,
-                                       double& ri) {
-    const double ph = fma(er[0], tau, psi_turns(pc.A, pc.B5, pc.B6, er[1], er[2], er[3]));
-    double sn, cs;
-    sincos_turns(fract64(ph - phi0), sn, cs);
-    rr = cs;
-    ri = -sn;
-}
-
 // kRbSeg adjacent lanes per draw, each over one contiguous quarter of the
-// bins (more waves in flight than one lane per draw); partial sums combined
-// by shuffles, written by the first lane of the draw.
+// bins (more waves in flight than one lane per draw); the draw's phase
+// polynomial at an edge is evaluated once for all detectors. Partial sums
+// are combined by shuffles and written by the first lane of the draw.
 constexpr int kRbSeg = 4;
+
+template <int ND>
+__device__ __forceinline__ void rb_segment(const RbArg& a, const Src& s, const PhaseCoef& pc, int64_t kc, int b0,
+                                           int b1, double& zr, double& zi) {
+    const int64_t K = a.ec.K;
+    const int nb = a.n_edges - 1;
+    double tau[ND], ur[ND], ui[ND], r0r[ND], r0i[ND];
+    {
+        const double* er = a.erec + 4 * b0;
+        const double psi = psi_turns(pc.A, pc.B5, pc.B6, er[1], er[2], er[3]);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            tau[d] = s.tc + s.dt[d];
+            ur[d] = ui[d] = 0.0;
+            double sn, cs;
+            sincos_turns(fract64(fma(er[0], tau[d], psi) - a.phi0[(int64_t)d * a.n_edges + b0]), sn, cs);
+            r0r[d] = cs;
+            r0i[d] = -sn;
+        }
+    }
+    for (int b = b0; b < b1 && a.kk[b] < kc; ++b) {
+        const double* er = a.erec + 4 * (b + 1);
+        const double psi = psi_turns(pc.A, pc.B5, pc.B6, er[1], er[2], er[3]);
+        const double inv = 1.0 / (er[0] - a.erec[4 * b]);
+        const bool full = a.kk[b + 1] <= kc;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            double sn, cs;
+            sincos_turns(fract64(fma(er[0], tau[d], psi) - a.phi0[(int64_t)d * a.n_edges + b + 1]), sn, cs);
+            const double r1r = cs, r1i = -sn;
+            const double sr = (r1r - r0r[d]) * inv, si = (r1i - r0i[d]) * inv;
+            double2 A0, A1;
+            if (full) {
+                const double2* Ad = a.A + ((int64_t)d * nb + b) * 2;
+                A0 = Ad[0];
+                A1 = Ad[1];
+            } else {
+                const double2* Pd = a.P + (int64_t)d * (K + 1) * 2;
+                const double2 p0 = Pd[2 * kc], q0 = Pd[2 * a.kk[b]];
+                const double2 p1 = Pd[2 * kc + 1], q1 = Pd[2 * a.kk[b] + 1];
+                A0 = make_double2(p0.x - q0.x, p0.y - q0.y);
+                A1 = make_double2(p1.x - q1.x, p1.y - q1.y);
+            }
+            ur[d] += r0r[d] * A0.x - r0i[d] * A0.y + sr * A1.x - si * A1.y;
+            ui[d] += r0r[d] * A0.y + r0i[d] * A0.x + sr * A1.y + si * A1.x;
+            r0r[d] = r1r;
+            r0i[d] = r1i;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        zr += s.rre[d] * ur[d] - s.rim[d] * ui[d];
+        zi += s.rre[d] * ui[d] + s.rim[d] * ur[d];
+    }
+}
 
 __global__ __launch_bounds__(256) void k_rb_ll(RbArg a) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -226,41 +273,20 @@ __global__ __launch_bounds__(256) void k_rb_ll(RbArg a) {
             phase_coeffs(s, pc);
             const int64_t K = ev.K;
             const int64_t kc = kcut_of(ev, s.fisco);
-            const int nb = a.n_edges - 1;
-            const int b0 = (int)((int64_t)sg * nb / kRbSeg), b1 = (int)((int64_t)(sg + 1) * nb / kRbSeg);
 #pragma unroll
             for (int d = 0; d < PE_MAX_DET; ++d) {  // fixed bound: the per-detector arrays stay in registers
                 if (d >= ev.n_det) break;
                 h += (s.rre[d] * s.rre[d] + s.rim[d] * s.rim[d]) * a.pfx[(int64_t)d * (K + 1) + kc];
-                if (b0 >= b1 || a.kk[b0] >= kc) continue;
-                const double tau = s.tc + s.dt[d];
-                const double* phd = a.phi0 + (int64_t)d * a.n_edges;
-                const double2* Ad = a.A + (int64_t)d * nb * 2;
-                const double2* Pd = a.P + (int64_t)d * (K + 1) * 2;
-                double ur = 0.0, ui = 0.0, r0r, r0i;
-                rb_rho(pc, tau, a.erec + 4 * b0, phd[b0], r0r, r0i);
-                for (int b = b0; b < b1 && a.kk[b] < kc; ++b) {
-                    double r1r, r1i;
-                    rb_rho(pc, tau, a.erec + 4 * (b + 1), phd[b + 1], r1r, r1i);
-                    const double inv = 1.0 / (a.erec[4 * (b + 1)] - a.erec[4 * b]);
-                    const double sr = (r1r - r0r) * inv, si = (r1i - r0i) * inv;
-                    double2 A0, A1;
-                    if (a.kk[b + 1] <= kc) {
-                        A0 = Ad[2 * b];
-                        A1 = Ad[2 * b + 1];
-                    } else {
-                        const double2 p0 = Pd[2 * kc], q0 = Pd[2 * a.kk[b]];
-                        const double2 p1 = Pd[2 * kc + 1], q1 = Pd[2 * a.kk[b] + 1];
-                        A0 = make_double2(p0.x - q0.x, p0.y - q0.y);
-                        A1 = make_double2(p1.x - q1.x, p1.y - q1.y);
-                    }
-                    ur += r0r * A0.x - r0i * A0.y + sr * A1.x - si * A1.y;
-                    ui += r0r * A0.y + r0i * A0.x + sr * A1.y + si * A1.x;
-                    r0r = r1r;
-                    r0i = r1i;
+            }
+            const int nb = a.n_edges - 1;
+            const int b0 = (int)((int64_t)sg * nb / kRbSeg), b1 = (int)((int64_t)(sg + 1) * nb / kRbSeg);
+            if (b0 < b1 && a.kk[b0] < kc) {
+                switch (ev.n_det) {
+                    case 1: rb_segment<1>(a, s, pc, kc, b0, b1, zr, zi); break;
+                    case 2: rb_segment<2>(a, s, pc, kc, b0, b1, zr, zi); break;
+                    case 3: rb_segment<3>(a, s, pc, kc, b0, b1, zr, zi); break;
+                    default: rb_segment<4>(a, s, pc, kc, b0, b1, zr, zi); break;
                 }
-                zr += s.rre[d] * ur - s.rim[d] * ui;
-                zi += s.rre[d] * ui + s.rim[d] * ur;
             }
         }
     }
