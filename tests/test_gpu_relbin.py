@@ -14,10 +14,11 @@ from paper_2410_05190_amd import binding
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("cfg,n_bins,n", [(0, None, 300), (1, 60000, 200), (1, None, 48)])
-def test_relbin_parity_with_the_oracle(cfg, n_bins, n):
+@pytest.mark.parametrize("cfg,n_bins,n,n_det", [(0, None, 300, None), (1, 60000, 200, None), (1, None, 48, None),
+                                                (2, None, 300, None), (1, 30000, 100, 4), (1, 30000, 100, 1)])
+def test_relbin_parity_with_the_oracle(cfg, n_bins, n, n_det):
     torch_cuda()
-    b = build_event(cfg, 1, n_bins=n_bins)
+    b = build_event(cfg, 1, n_bins=n_bins, n_det=n_det)
     ev, data, psd = upload_event(b)
     eps = 0.03
     ev.relbin_setup(dev(b.theta_inj), eps)
@@ -26,7 +27,7 @@ def test_relbin_parity_with_the_oracle(cfg, n_bins, n):
     assert np.array_equal(e, eo)
     g = b.ev.metric(b.theta_inj)
     rc, th, lq, lp = b.ev.draw(b.theta_inj, g, 17, 0, n)
-    note(f"relbin parity: config {cfg}, K {b.n_bins}, {len(e)} edges, {n} draws")
+    note(f"relbin parity: config {cfg}, {b.n_det} detectors, K {b.n_bins}, {len(e)} edges, {n} draws")
     ll, aux = ev.loglike(dev(th), precision=binding.PE_PREC_RELBIN, aux=True)
     ll, aux = host(ll), host(aux)
     llo, zo = b.ev.relbin_loglike(b.theta_inj, eo, th, return_zh=True)

@@ -112,6 +112,18 @@ def test_draw_parity_on_the_same_inputs():
         assert np.array_equal(th[:, same], tho[:, same])
         assert np.array_equal(lpg[same], lpo[same])
         np.testing.assert_allclose(lq[same], lqo[same], rtol=0, atol=1e-12)
+    # 11-D samples (the other draw kernel)
+    P, M, n = 20000, 50, 3000
+    to = rng.integers(0, M, P).astype(np.int32)
+    tl = rng.normal(0.0, 1.0, M)
+    lp = rng.normal(0.0, 0.3, P)
+    smp = rng.normal(0.0, 1.0, (11, P))
+    rc, tho, lqo, lpo, idxo = oracle.tile_draw(tl, to, lp, smp, 62, 1, n)
+    th, lq, lpg, idx = binding.tile_draw(dev(tl), dev_i32(to), dev(lp), dev(smp), 62, 1, n)
+    same = host(idx) == idxo
+    assert (~same).sum() <= 2
+    assert np.array_equal(host(th)[:, same], tho[:, same])
+    np.testing.assert_allclose(host(lq)[same], lqo[same], rtol=0, atol=1e-12)
     # no positive mass
     th, lq, lpg, idx = binding.tile_draw(dev(np.full(2, -np.inf)), dev_i32(np.zeros(10)), dev(np.zeros(10)),
                                          dev(np.ones((4, 10))), 1, 0, 5)
