@@ -36,7 +36,7 @@ FP64_OPS_PER_TERM = 2 + 26 + 4
 # groups), from rocprofv3 FETCH_SIZE x 1.9999 + WRITE_SIZE x 1.0 (KiB per dispatch), the
 # factors read off a 1 GiB device-to-device copy in the same runs (profiles/
 # loglike_split_config1.md); None when the kernel has changed since the counters were taken.
-SPLIT_TRAFFIC_BYTES = 748019367
+SPLIT_TRAFFIC_BYTES = 751939667
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 
 
