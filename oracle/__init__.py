@@ -19,6 +19,8 @@ PARAMS_4D = 0
 PARAMS_11D = 1
 PHASE_MARG = 0
 PHASE_EXPLICIT = 1
+DIST_SAMPLED = 0
+DIST_MARG = 1
 MAX_DET = 4
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -29,7 +31,7 @@ class _Event(ctypes.Structure):
                 ("df", ctypes.c_double), ("data", _dp), ("psd", _dp), ("strain_scale", ctypes.c_double),
                 ("params", ctypes.c_int), ("phase", ctypes.c_int), ("amp0", ctypes.c_double),
                 ("gmst", ctypes.c_double), ("chi_max", ctypes.c_double), ("dl_max", ctypes.c_double),
-                ("det_geom", (ctypes.c_double * 3) * MAX_DET)]
+                ("det_geom", (ctypes.c_double * 3) * MAX_DET), ("distance", ctypes.c_int)]
 
 
 class _Slice(ctypes.Structure):
@@ -72,6 +74,8 @@ def lib():
         L.peo_inner.argtypes = [ctypes.POINTER(_Event), ctypes.c_int, _dp, _dp]
         L.peo_log_i0.restype = ctypes.c_double
         L.peo_log_i0.argtypes = [ctypes.c_double]
+        L.peo_log_dist_marg.restype = ctypes.c_double
+        L.peo_log_dist_marg.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.peo_loglike.argtypes = [ctypes.POINTER(_Event), _dp, ctypes.c_long, _dp, _dp, ctypes.c_int]
         L.peo_default_steps.argtypes = [ctypes.POINTER(_Event), _dp, _dp]
         L.peo_metric_fd.restype = ctypes.c_int
@@ -144,7 +148,8 @@ class Event:
     psd: real [n_det, K]. data/psd may be None for template-only use (psd needed for inner products)."""
 
     def __init__(self, n_det, n_bins, f_lo, df, data=None, psd=None, strain_scale=1.0, params=PARAMS_11D,
-                 phase=PHASE_EXPLICIT, amp0=0.0, gmst=0.0, chi_max=0.4, dl_max=1e4, det_geom=None):
+                 phase=PHASE_EXPLICIT, amp0=0.0, gmst=0.0, chi_max=0.4, dl_max=1e4, det_geom=None,
+                 distance=DIST_SAMPLED):
         self.n_det = int(n_det)
         self.n_bins = int(n_bins)
         self.f_lo = float(f_lo)
@@ -175,6 +180,8 @@ class Event:
         s.gmst = float(gmst)
         s.chi_max = float(chi_max)
         s.dl_max = float(dl_max)
+        self.distance = int(distance)
+        s.distance = self.distance
         if det_geom is not None:
             g = np.asarray(det_geom, dtype=np.float64).reshape(-1, 3)
             for i in range(g.shape[0]):
@@ -420,3 +427,8 @@ def weights_ess(loglike, logprior, logq):
     st = np.zeros(4)
     lib().peo_weights_ess(_p(ll), _p(lp), _p(lq), n, _p(w), _p(st))
     return w, st
+
+
+def log_dist_marg(a, b, explicit_phase):
+    """ln of int_1^inf 3 x^-4 exp(phi(x) - b x^2) dx, phi = a x (explicit phase) or ln I0(a x)."""
+    return lib().peo_log_dist_marg(float(a), float(b), int(bool(explicit_phase)))

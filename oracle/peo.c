@@ -218,7 +218,7 @@ int peo_source_from_theta(const peo_event *ev, const double *th, peo_source *s)
         }
         ok = (mc > 0.0) && (q > 0.0) && (q <= 1.0) && (fabs(th[2]) <= ev->chi_max) &&
              (fabs(th[3]) <= ev->chi_max) && (fabs(dec) <= 0.5 * PI) && (iota >= 0.0) && (iota <= PI) &&
-             (dl > 0.0) && (dl <= ev->dl_max);
+             (ev->distance == PEO_DIST_MARG || ((dl > 0.0) && (dl <= ev->dl_max)));
     }
     peo_pn_coeffs(s->eta, s->delta, s->chi1, s->chi2, s->phi, s->phil);
     s->fisco = peo_f_isco(s->M);
@@ -296,16 +296,126 @@ double peo_log_i0(double x)
     return x + log(nval(&acc) * tmax / (PI * (double)m));
 }
 
+/* ln I0(x) by the same integral representation as peo_log_i0 with 128 nodes:
+ * the trapezoid rule on the periodic integrand converges geometrically, and 128
+ * nodes over the truncated range keep its error below 1e-30 for every x (the
+ * distance integral evaluates it many times per draw). */
+static double log_i0_quick(double x)
+{
+    const long m = 128;
+    long i;
+    double tmax = PI, s, acc = 0.0;
+    x = fabs(x);
+    if (x == 0.0)
+        return 0.0;
+    s = sqrt(375.0 / x);
+    if (s < 1.0)
+        tmax = 2.0 * asin(s);
+    for (i = 0; i <= m; i++) {
+        double t = tmax * (double)i / (double)m;
+        double sh = sin(0.5 * t);
+        acc += ((i == 0 || i == m) ? 0.5 : 1.0) * exp(-2.0 * x * sh * sh);
+    }
+    return x + log(acc * tmax / (PI * (double)m));
+}
+
+/* Log of the distance integrand in u = ln(dl_max / dL) = ln x, u >= 0:
+ * 3 x^-4 exp(phi(x) - b x^2) dx = 3 exp(-3u + phi(e^u) - b e^{2u}) du. */
+static double dm_logf(double u, double a, double b, int ex)
+{
+    const double x = exp(u);
+    return log(3.0) - 3.0 * u + (ex ? a * x : log_i0_quick(a * x)) - b * x * x;
+}
+
+typedef struct {
+    double a, b, G;
+    int ex;
+} dm_arg;
+
+static double dm_f(const dm_arg *q, double u) { return exp(dm_logf(u, q->a, q->b, q->ex) - q->G); }
+
+/* Adaptive Simpson on [lo, hi] (Richardson-corrected once converged); the
+ * tolerance halves with each split, down to the rounding level of the integrand. */
+static double dm_simpson(const dm_arg *q, double lo, double hi, double flo, double fm, double fhi, double whole,
+                         double tol, int depth)
+{
+    const double m = 0.5 * (lo + hi), lm = 0.5 * (lo + m), rm = 0.5 * (m + hi);
+    const double flm = dm_f(q, lm), frm = dm_f(q, rm);
+    const double left = (m - lo) / 6.0 * (flo + 4.0 * flm + fm), right = (hi - m) / 6.0 * (fm + 4.0 * frm + fhi);
+    const double d = left + right - whole;
+    /* converged, or at the level of the integrand's own rounding: its logarithm
+     * is a difference of terms up to ~1e4, so its values carry ~1e-13 relative error */
+    if (depth >= 24 || fabs(d) <= 15.0 * fmax(tol, 1e-13 * fabs(left + right)))
+        return left + right + d / 15.0;
+    return dm_simpson(q, lo, m, flo, flm, fm, left, 0.5 * tol, depth + 1) +
+           dm_simpson(q, m, hi, fm, frm, fhi, right, 0.5 * tol, depth + 1);
+}
+
+/* The integral over u in [0, 40] (x up to e^40; beyond, the integrand is below
+ * e^-120 of its prior weight alone) on 16384 panels, each refined adaptively to
+ * 1e-16 of the coarse total, in units of exp(G), G the largest coarse sample.
+ * The integrand's peak has width ~1/rho in u, rho the matched-filter SNR at the
+ * best distance; the coarse samples (every 1.2e-3) resolve it for rho up to ~800. */
+double peo_log_dist_marg(double a, double b, int explicit_phase)
+{
+    const int N = 16384;
+    const double U = 40.0, h = U / N;
+    double *f = (double *)malloc(sizeof(double) * (2 * N + 1));
+    dm_arg q;
+    double coarse = 0.0, tot = 0.0, G = -INFINITY;
+    int j;
+    q.a = a;
+    q.b = b;
+    q.ex = explicit_phase;
+    for (j = 0; j <= 2 * N; j++) {
+        f[j] = dm_logf(0.5 * h * j, a, b, explicit_phase);
+        if (f[j] > G)
+            G = f[j];
+    }
+    q.G = G;
+    for (j = 0; j <= 2 * N; j++)
+        f[j] = exp(f[j] - G);
+    for (j = 0; j < N; j++)
+        coarse += h / 6.0 * (f[2 * j] + 4.0 * f[2 * j + 1] + f[2 * j + 2]);
+    for (j = 0; j < N; j++) {
+        const double whole = h / 6.0 * (f[2 * j] + 4.0 * f[2 * j + 1] + f[2 * j + 2]);
+        tot += dm_simpson(&q, j * h, (j + 1) * h, f[2 * j], f[2 * j + 1], f[2 * j + 2], whole, 1e-16 * coarse, 0);
+    }
+    free(f);
+    return G + log(tot);
+}
+
+/* ln L from Z and H (Eq. 3): explicit phase Re Z - H/2; marginalised over a
+ * uniform coalescence phase ln I0(|Z|) - H/2; distance-marginalised events take
+ * Z and H at the reference distance dl_max and integrate over dL. */
+static double loglike_from_zh(const peo_event *ev, double Zr, double Zi, double H)
+{
+    const int ex = (ev->phase == PEO_PHASE_EXPLICIT);
+    if (ev->distance == PEO_DIST_MARG)
+        return peo_log_dist_marg(ex ? Zr : hypot(Zr, Zi), 0.5 * H, ex);
+    return ex ? Zr - 0.5 * H : peo_log_i0(hypot(Zr, Zi)) - 0.5 * H;
+}
+
+/* The parameters the likelihood's waveform is evaluated at: theta itself, or
+ * theta with dL at the reference distance dl_max for distance-marginalised events. */
+static void likelihood_theta(const peo_event *ev, const double *th, double *out)
+{
+    memcpy(out, th, sizeof(double) * peo_dim(ev->params));
+    if (ev->params == PEO_PARAMS_11D && ev->distance == PEO_DIST_MARG)
+        out[8] = ev->dl_max;
+}
+
 /* Eq. 3 with Eq. 1: Z = sum_d (d_d|h_d) as a complex overlap, H = sum_d (h_d|h_d).
  * Explicit phase: ln L = Re Z - H/2. Marginalised over a uniform coalescence
  * phase: ln L = ln I0(|Z|) - H/2. */
-static double loglike_one(const peo_event *ev, const double *th, double *zh)
+static double loglike_one(const peo_event *ev, const double *th_in, double *zh)
 {
     peo_source s;
     nsum zr = {0, 0}, zi = {0, 0}, hh = {0, 0};
     int d;
     long k;
-    double Zr, Zi, H;
+    double Zr, Zi, H, th[PEO_MAX_DIM];
+    likelihood_theta(ev, th_in, th);
     if (!peo_source_from_theta(ev, th, &s)) {
         if (zh)
             zh[0] = zh[1] = zh[2] = 0.0;
@@ -333,9 +443,7 @@ static double loglike_one(const peo_event *ev, const double *th, double *zh)
         zh[1] = Zi;
         zh[2] = H;
     }
-    if (ev->phase == PEO_PHASE_EXPLICIT)
-        return Zr - 0.5 * H;
-    return peo_log_i0(hypot(Zr, Zi)) - 0.5 * H;
+    return loglike_from_zh(ev, Zr, Zi, H);
 }
 
 #ifdef _OPENMP
@@ -500,6 +608,16 @@ int peo_metric_fd(const peo_event *ev, const double *th0, const double *steps, i
                 P[a][b] = (a == iphi || b == iphi) ? 0.0 : Gd[a][b] - Gd[a][iphi] * Gd[iphi][b] / gpp;
         memcpy(Gd, P, sizeof(P));
     }
+    /* distance-marginalised likelihood: project out dL the same way */
+    if (!is4 && ev->distance == PEO_DIST_MARG) {
+        const int il = 8;
+        double gll = Gd[il][il];
+        double P[PEO_MAX_DIM + 1][PEO_MAX_DIM + 1];
+        for (a = 0; a < Dp; a++)
+            for (b = 0; b < Dp; b++)
+                P[a][b] = (a == il || b == il) ? 0.0 : Gd[a][b] - Gd[a][il] * Gd[il][b] / gll;
+        memcpy(Gd, P, sizeof(P));
+    }
     for (a = 0; a < D; a++)
         for (b = 0; b < D; b++)
             g[a * D + b] = Gd[a][b];
@@ -619,6 +737,8 @@ double peo_logprior(const peo_event *ev, const double *th)
         return -INFINITY;
     if (ev->params == PEO_PARAMS_4D)
         return 0.0;
+    if (ev->distance == PEO_DIST_MARG) /* the dL prior is inside the marginalised likelihood */
+        return log(cos(th[5])) + log(sin(th[6]));
     return log(cos(th[5])) + log(sin(th[6])) + 2.0 * log(th[8]);
 }
 
@@ -658,16 +778,93 @@ static double logq_one(int D, const double *L, const double *th0, const double *
     return mx + log(acc) + logdet - 0.5 * D * log(2.0 * PI);
 }
 
+/* Inverse of a symmetric positive-definite matrix: L L^T X = I solved column by
+ * column. Returns 0, or 3 if the matrix is not positive definite. */
+static int spd_inverse(const double *g, int D, double *inv)
+{
+    double L[PEO_MAX_DIM * PEO_MAX_DIM], y[PEO_MAX_DIM];
+    int i, j, k, rc = cholesky(g, D, L);
+    if (rc)
+        return rc;
+    for (j = 0; j < D; j++) {
+        for (i = 0; i < D; i++) { /* L y = e_j */
+            double t = (i == j) ? 1.0 : 0.0;
+            for (k = 0; k < i; k++)
+                t -= L[i * D + k] * y[k];
+            y[i] = t / L[i * D + i];
+        }
+        for (i = D - 1; i >= 0; i--) { /* L^T x = y */
+            double t = y[i];
+            for (k = i + 1; k < D; k++)
+                t -= L[k * D + i] * inv[k * D + j];
+            inv[i * D + j] = t / L[i * D + i];
+        }
+    }
+    return 0;
+}
+
+/* Distance-marginalised events: the proposal over the coordinates other than
+ * dL (index 8). dec_g: g with the dL row and column decoupled by the Schur
+ * complement (g_dLdL kept), the metric the draws are taken with. Lm: Cholesky
+ * factor of the marginal precision of the other D-1 coordinates, the inverse of
+ * the sub-block of the covariance g^-1; pidx_m: the periodic indices among them. */
+typedef struct {
+    double dec_g[PEO_MAX_DIM * PEO_MAX_DIM];
+    double Lm[PEO_MAX_DIM * PEO_MAX_DIM];
+    int pidx_m[3];
+} dist_prop;
+
+static int dist_proposal(const double *g, int np, const int *pidx, dist_prop *dp)
+{
+    const int D = 11, il = 8, Dm = 10;
+    double C[PEO_MAX_DIM * PEO_MAX_DIM], Cm[PEO_MAX_DIM * PEO_MAX_DIM], gm[PEO_MAX_DIM * PEO_MAX_DIM];
+    int a, b, rc;
+    for (a = 0; a < D; a++)
+        for (b = 0; b < D; b++)
+            dp->dec_g[a * D + b] = (a == il || b == il) ? ((a == b) ? g[il * D + il] : 0.0)
+                                                         : g[a * D + b] - g[a * D + il] * g[il * D + b] / g[il * D + il];
+    rc = spd_inverse(g, D, C);
+    if (rc)
+        return rc;
+    for (a = 0; a < Dm; a++)
+        for (b = 0; b < Dm; b++)
+            Cm[a * Dm + b] = C[(a + (a >= il)) * D + (b + (b >= il))];
+    rc = spd_inverse(Cm, Dm, gm);
+    if (rc)
+        return rc;
+    rc = cholesky(gm, Dm, dp->Lm);
+    if (rc)
+        return rc;
+    for (a = 0; a < np; a++)
+        dp->pidx_m[a] = pidx[a] - (pidx[a] > il);
+    return 0;
+}
+
+static double logq_dist(const dist_prop *dp, const double *th0, const double *th, int np, const double *per)
+{
+    double t0[PEO_MAX_DIM], t[PEO_MAX_DIM];
+    int a;
+    for (a = 0; a < 10; a++) {
+        t0[a] = th0[a + (a >= 8)];
+        t[a] = th[a + (a >= 8)];
+    }
+    return logq_one(10, dp->Lm, t0, t, np, dp->pidx_m, per);
+}
+
 int peo_draw(const peo_event *ev, const double *th0, const double *g, uint64_t seed, uint32_t stream, long n,
              double *theta, double *logq, double *logprior)
 {
     const int D = peo_dim(ev->params);
+    const int dist = (ev->params == PEO_PARAMS_11D && ev->distance == PEO_DIST_MARG);
     double L[PEO_MAX_DIM * PEO_MAX_DIM];
+    dist_prop dp;
     int pidx[3], np, rc;
     double per[3];
     long i;
     np = periodic_dims(ev, pidx, per);
-    rc = cholesky(g, D, L);
+    rc = dist ? dist_proposal(g, np, pidx, &dp) : 0;
+    if (!rc)
+        rc = cholesky(dist ? dp.dec_g : g, D, L);
     if (rc) {
         for (i = 0; i < n; i++) {
             int a;
@@ -704,7 +901,7 @@ int peo_draw(const peo_event *ev, const double *th0, const double *g, uint64_t s
         }
         for (a = 0; a < D; a++)
             theta[(long)a * n + i] = th[a];
-        logq[i] = logq_one(D, L, th0, th, np, pidx, per);
+        logq[i] = dist ? logq_dist(&dp, th0, th, np, per) : logq_one(D, L, th0, th, np, pidx, per);
         logprior[i] = peo_logprior(ev, th);
     }
     return 0;
@@ -714,11 +911,13 @@ int peo_logq_theta(const peo_event *ev, const double *th0, const double *g, cons
                    double *logq)
 {
     const int D = peo_dim(ev->params);
+    const int dist = (ev->params == PEO_PARAMS_11D && ev->distance == PEO_DIST_MARG);
     double L[PEO_MAX_DIM * PEO_MAX_DIM], per[3];
+    dist_prop dp;
     int pidx[3], np, rc;
     long i;
     np = periodic_dims(ev, pidx, per);
-    rc = cholesky(g, D, L);
+    rc = dist ? dist_proposal(g, np, pidx, &dp) : cholesky(g, D, L);
     if (rc)
         return rc;
     for (i = 0; i < n; i++) {
@@ -726,7 +925,7 @@ int peo_logq_theta(const peo_event *ev, const double *th0, const double *g, cons
         int a;
         for (a = 0; a < D; a++)
             th[a] = theta[(long)a * n + i];
-        logq[i] = logq_one(D, L, th0, th, np, pidx, per);
+        logq[i] = dist ? logq_dist(&dp, th0, th, np, per) : logq_one(D, L, th0, th, np, pidx, per);
     }
     return 0;
 }
@@ -1195,13 +1394,14 @@ void peo_relbin_loglike(const peo_event *ev, const double *theta_f, long n_edges
         }
     }
     for (i = 0; i < n; i++) {
-        double th[PEO_MAX_DIM];
+        double th_in[PEO_MAX_DIM], th[PEO_MAX_DIM];
         peo_source s;
         nsum zr = {0, 0}, zi = {0, 0}, hh = {0, 0};
         double Zr, Zi, H;
         int a;
         for (a = 0; a < D; a++)
-            th[a] = theta[(long)a * n + i];
+            th_in[a] = theta[(long)a * n + i];
+        likelihood_theta(ev, th_in, th);
         if (!peo_source_from_theta(ev, th, &s)) {
             loglike[i] = -INFINITY;
             if (zh)
@@ -1243,7 +1443,7 @@ void peo_relbin_loglike(const peo_event *ev, const double *theta_f, long n_edges
             zh[3 * i + 1] = Zi;
             zh[3 * i + 2] = H;
         }
-        loglike[i] = (ev->phase == PEO_PHASE_EXPLICIT) ? Zr - 0.5 * H : peo_log_i0(hypot(Zr, Zi)) - 0.5 * H;
+        loglike[i] = loglike_from_zh(ev, Zr, Zi, H);
     }
     free(c);
 }

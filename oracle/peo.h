@@ -44,6 +44,9 @@ extern "C" {
 /* likelihood forms */
 #define PEO_PHASE_MARG 0     /* ln I0(|Z|) - H/2, coalescence phase marginalised */
 #define PEO_PHASE_EXPLICIT 1 /* Re Z - H/2 */
+/* distance treatment (11-D only) */
+#define PEO_DIST_SAMPLED 0 /* dL is a sampled coordinate of theta */
+#define PEO_DIST_MARG 1    /* the likelihood is marginalised over dL with the dL^2 prior on (0, dl_max] */
 
 typedef struct {
     int n_det;
@@ -59,6 +62,7 @@ typedef struct {
     double chi_max; /* |chi| bound of the prior */
     double dl_max;  /* Mpc, upper bound of the distance prior (11-D) */
     double det_geom[PEO_MAX_DET][3]; /* latitude, longitude, x-arm azimuth (from north to east) */
+    int distance;   /* PEO_DIST_SAMPLED or PEO_DIST_MARG */
 } peo_event;
 
 /* Per-draw source quantities derived from theta. */
@@ -100,14 +104,29 @@ double peo_inner(const peo_event *ev, int d, const double *a, const double *b);
 
 double peo_log_i0(double x);
 
+/*
+ * Distance marginalisation (Sec. III: the extrinsic parameters are marginalised
+ * with analytic or numerical formulas; for the distance, the integral over the
+ * dL^2 prior of Singer & Price 2016). With Z and H evaluated at the reference
+ * distance dl_max, the likelihood at distance dL is Z x and H x^2 with
+ * x = dl_max / dL, and
+ *   L_D = int_0^dl_max (3 dL^2 / dl_max^3) L(dL) ddL = int_1^inf 3 x^-4 exp(phi(x) - b x^2) dx,
+ * phi(x) = a x (explicit phase, a = Re Z) or ln I0(a x) (marginalised phase,
+ * a = |Z|), b = H / 2. Returns ln L_D.
+ */
+double peo_log_dist_marg(double a, double b, int explicit_phase);
+
 /* theta: [D][n] (row j holds parameter j of every draw). zh: [n][3] = Re Z, Im Z, H, may be NULL.
- * Out-of-support draws get -inf. n_threads <= 0: OpenMP default. */
+ * Out-of-support draws get -inf. n_threads <= 0: OpenMP default. Distance-marginalised events:
+ * Z and H at the reference distance dl_max (the draw's dL is not used), ln L = ln L_D. */
 void peo_loglike(const peo_event *ev, const double *theta, long n, double *loglike, double *zh, int n_threads);
 
 /* Default finite-difference steps at theta0 (D values). */
 void peo_default_steps(const peo_event *ev, const double *theta0, double *steps);
 /* Fisher metric. flags: bit0 = do not add the prior regularisation,
  * bit1 = raw (no coalescence-phase projection, 4-D returns 5x5 with phic last).
+ * Distance-marginalised events also project out dL (Schur complement; its row and
+ * column are zero apart from the regularisation on the diagonal).
  * g is (D or D+1)^2 row-major. Returns 0. */
 int peo_metric_fd(const peo_event *ev, const double *theta0, const double *steps, int flags, double *g);
 
@@ -116,7 +135,11 @@ void peo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 /* u[i*2*npairs + 2j + {0,1}] = the two 53-bit uniforms of block (i, j). */
 void peo_uniforms(uint64_t seed, uint32_t stream, long n, int npairs, double *u);
 /* Draws from N(theta0, g^-1), periodic coordinates wrapped. theta [D][n]. Returns 0, or 3 if
- * g is not positive definite. logq uses the image sum over the wrapped coordinates. */
+ * g is not positive definite. logq uses the image sum over the wrapped coordinates.
+ * Distance-marginalised events: dL is decoupled first (g replaced by the Schur complement of
+ * its dL row and column, g_dLdL kept), which leaves the distribution of the other coordinates
+ * unchanged; logq is then the log of the proposal's marginal density over those coordinates,
+ * and the prior has no dL factor and no dL bound: the drawn dL is never used. */
 int peo_draw(const peo_event *ev, const double *theta0, const double *g, uint64_t seed, uint32_t stream,
              long n, double *theta, double *logq, double *logprior);
 /* Proposal log-density of wrapped draws from theta alone (quadratic-form route). */

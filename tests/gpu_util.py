@@ -21,7 +21,7 @@ def note(msg):
 
 def desc_kwargs(b):
     return dict(f_lo=b.f_lo, df=b.df, strain_scale=b.strain_scale, params=b.params, phase=b.phase, amp0=b.amp0,
-                gmst=b.gmst, chi_max=b.chi_max, dl_max=b.dl_max, det_geom=b.det_geom)
+                gmst=b.gmst, chi_max=b.chi_max, dl_max=b.dl_max, det_geom=b.det_geom, distance=b.distance)
 
 
 def upload_event(b):
