@@ -76,6 +76,12 @@ typedef enum {
 typedef enum { PE_PREC_FP64 = 0, PE_PREC_SPLIT = 1, PE_PREC_RELBIN = 2 } pe_precision_t;
 typedef enum { PE_PHASE_MARG = 0, PE_PHASE_EXPLICIT = 1 } pe_phase_t;
 typedef enum { PE_PARAMS_4D = 0, PE_PARAMS_11D = 1 } pe_params_t;
+/* Treatment of the luminosity distance (11-D only). PE_DIST_MARG: the
+ * likelihood is marginalised over dL (Sec. III marginalises the extrinsic
+ * parameters with analytic or numerical formulas; for the distance this is the
+ * integral over the dL^2 prior of Singer & Price 2016), so theta's dL is
+ * carried but never used: see pe_metric, pe_draw and pe_loglike_batch. */
+typedef enum { PE_DIST_SAMPLED = 0, PE_DIST_MARG = 1 } pe_distance_t;
 typedef enum { PE_C128 = 0, PE_C64 = 1 } pe_data_dtype_t;
 typedef enum { PE_F64 = 0, PE_F32 = 1 } pe_psd_dtype_t;
 
@@ -95,6 +101,7 @@ typedef struct {
     double chi_max;       /* prior bound |chi| <= chi_max */
     double dl_max;        /* 11-D prior bound 0 < dL <= dl_max (Mpc) */
     double det_geom[PE_MAX_DET][3];
+    int32_t distance;     /* pe_distance_t (a zeroed field: PE_DIST_SAMPLED); PE_DIST_MARG needs 11-D */
 } pe_event_desc_t;
 
 /* Dimension D of theta for a parameter set (4 or 11); 0 if unknown. */
@@ -140,7 +147,8 @@ pe_status_t pe_event_destroy(pe_event_t ev);
  *   g_dev      : D*D doubles, row-major (device). For the marginalised
  *                likelihood the phase direction is projected out (Schur
  *                complement); in 11-D its row and column are then zero before
- *                the prior precision is added.
+ *                the prior precision is added. PE_DIST_MARG events project out
+ *                dL the same way (jointly with the phase if both are).
  */
 pe_status_t pe_metric(pe_event_t ev, const double *theta0_dev, const double *fd_step_dev, int32_t flags,
                       double *g_dev, void *stream);
@@ -158,6 +166,11 @@ pe_status_t pe_metric(pe_event_t ev, const double *theta0_dev, const double *fd_
  *   theta_dev: [D][n]; logq_dev, logprior_dev: [n] (device, caller-owned).
  * If g is not positive definite every draw is theta0 with logprior = -inf and
  * pe_event_status reports PE_ERR_SINGULAR.
+ * PE_DIST_MARG events: dL is first decoupled (g replaced by the Schur
+ * complement of its dL row and column, g_dLdL kept), which leaves the
+ * distribution of the other coordinates unchanged; logq is the log-density of
+ * the proposal's marginal over those coordinates, and logprior has neither the
+ * dL^2 factor nor the dL bound. The drawn dL is not used by the likelihood.
  */
 pe_status_t pe_draw(pe_event_t ev, const double *theta0_dev, const double *g_dev, uint64_t seed, uint32_t stream_id,
                     int64_t n, double *theta_dev, double *logq_dev, double *logprior_dev, void *stream);
@@ -174,6 +187,13 @@ pe_status_t pe_draw(pe_event_t ev, const double *theta0_dev, const double *g_dev
  *              combination in FP64).
  *   loglike_dev: [n]; out-of-support draws get -inf.
  *   aux_dev: NULL or [n][3] = Re Z, Im Z, H (zeros out of support).
+ * PE_DIST_MARG events: Z and H are those at the reference distance dl_max
+ * (theta's dL is ignored), and with x = dl_max / dL, b = H/2,
+ *   ln L = ln int_1^inf 3 x^-4 exp(phi(x) - b x^2) dx,
+ * the likelihood integrated over the dL^2 prior on (0, dl_max]; phi = Re(Z) x
+ * (explicit phase) or ln I0(|Z| x) (marginalised phase). Evaluated per draw in
+ * FP64 by 16-point Gauss-Legendre panels walked outward from the integrand's
+ * peak until it falls below e^-45 of its maximum.
  */
 pe_status_t pe_loglike_batch(pe_event_t ev, const double *theta_dev, int64_t n, int32_t precision, double *loglike_dev,
                              double *aux_dev, void *stream);

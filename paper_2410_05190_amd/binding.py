@@ -22,6 +22,8 @@ PE_PREC_SPLIT = 1
 PE_PREC_RELBIN = 2
 PE_PHASE_MARG = 0
 PE_PHASE_EXPLICIT = 1
+PE_DIST_SAMPLED = 0
+PE_DIST_MARG = 1
 PE_PARAMS_4D = 0
 PE_PARAMS_11D = 1
 PE_C128 = 0
@@ -51,7 +53,8 @@ class EventDesc(ctypes.Structure):
                 ("df", ctypes.c_double), ("data_dtype", ctypes.c_int32), ("psd_dtype", ctypes.c_int32),
                 ("strain_scale", ctypes.c_double), ("params", ctypes.c_int32), ("phase", ctypes.c_int32),
                 ("amp0", ctypes.c_double), ("gmst", ctypes.c_double), ("chi_max", ctypes.c_double),
-                ("dl_max", ctypes.c_double), ("det_geom", (ctypes.c_double * 3) * MAX_DET)]
+                ("dl_max", ctypes.c_double), ("det_geom", (ctypes.c_double * 3) * MAX_DET),
+                ("distance", ctypes.c_int32)]
 
 
 class Slice(ctypes.Structure):
@@ -201,7 +204,7 @@ def _ptr(t, dtype=None, name="tensor", allow_none=False):
 
 def make_desc(n_det, n_bins, f_lo, df, data_dtype=PE_C128, psd_dtype=PE_F64, strain_scale=1.0,
               params=PE_PARAMS_11D, phase=PE_PHASE_EXPLICIT, amp0=0.0, gmst=0.0, chi_max=0.4, dl_max=1e4,
-              det_geom=None):
+              det_geom=None, distance=PE_DIST_SAMPLED):
     d = EventDesc()
     d.n_det = int(n_det)
     d.n_bins = int(n_bins)
@@ -216,6 +219,7 @@ def make_desc(n_det, n_bins, f_lo, df, data_dtype=PE_C128, psd_dtype=PE_F64, str
     d.gmst = float(gmst)
     d.chi_max = float(chi_max)
     d.dl_max = float(dl_max)
+    d.distance = int(distance)
     if det_geom is not None:
         g = np.asarray(det_geom, dtype=np.float64).reshape(-1, 3)
         for i in range(g.shape[0]):

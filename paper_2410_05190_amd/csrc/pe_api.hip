@@ -53,6 +53,9 @@ pe_status_t validate_desc(const pe_event_desc_t* d) {
     if (d->params == PE_PARAMS_4D && !(d->amp0 > 0.0)) return fail(PE_ERR_ARG, "4-D needs amp0 > 0");
     if (!(d->chi_max >= 0.0)) return fail(PE_ERR_ARG, "chi_max must be >= 0");
     if (d->params == PE_PARAMS_11D && !(d->dl_max > 0.0)) return fail(PE_ERR_ARG, "11-D needs dl_max > 0");
+    if (d->distance != PE_DIST_SAMPLED && d->distance != PE_DIST_MARG) return fail(PE_ERR_ARG, "bad distance");
+    if (d->distance == PE_DIST_MARG && d->params != PE_PARAMS_11D)
+        return fail(PE_ERR_ARG, "distance marginalisation needs the 11-D parameter set");
     return PE_OK;
 }
 
@@ -72,6 +75,7 @@ void build_const(const pe_event_desc_t& d, EvConst& ec) {
     ec.gmst = d.gmst;
     ec.chi_max = d.chi_max;
     ec.dl_max = d.dl_max;
+    ec.dist = (d.distance == PE_DIST_MARG) ? 1 : 0;
     for (int i = 0; i < d.n_det; ++i) {
         const double lat = d.det_geom[i][0], lon = d.det_geom[i][1], az = d.det_geom[i][2];
         const double up[3] = {std::cos(lat) * std::cos(lon), std::cos(lat) * std::sin(lon), std::sin(lat)};

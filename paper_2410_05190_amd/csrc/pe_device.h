@@ -124,16 +124,26 @@ __device__ __forceinline__ int mass_and_support(const EvConst& ev, const double*
     const double opq = 1.0 + q;
     M = mc * pow(opq, 1.2) * pow(q, -0.6);
     return (mc > 0.0) && (q > 0.0) && (q <= 1.0) && (fabs(c1) <= ev.chi_max) && (fabs(c2) <= ev.chi_max) &&
-           (fabs(dec) <= 0.5 * kPi) && (iota >= 0.0) && (iota <= kPi) && (dl > 0.0) && (dl <= ev.dl_max);
+           (fabs(dec) <= 0.5 * kPi) && (iota >= 0.0) && (iota <= kPi) &&
+           (ev.dist || ((dl > 0.0) && (dl <= ev.dl_max)));
 }
 
 // Support of the prior and the source parameters of theta (D values).
 // Log prior (flat in Mc, eta or q, spins, tc, ra, psi, phic; cos dec; sin
-// iota; dL^2; unnormalised), -inf outside the support.
+// iota; dL^2 unless the likelihood is distance-marginalised; unnormalised),
+// -inf outside the support.
 __device__ __forceinline__ double log_prior_of(const EvConst& ev, const double* th) {
     double M;
     if (!mass_and_support(ev, th, M)) return -INFINITY;
-    return (ev.params == PE_PARAMS_4D) ? 0.0 : log(cos(th[5])) + log(sin(th[6])) + 2.0 * log(th[8]);
+    if (ev.params == PE_PARAMS_4D) return 0.0;
+    const double ang = log(cos(th[5])) + log(sin(th[6]));
+    return ev.dist ? ang : ang + 2.0 * log(th[8]);
+}
+
+// The likelihood of a distance-marginalised event is evaluated at the
+// reference distance dl_max (Z and H scale as 1/dL and 1/dL^2 from there).
+__device__ __forceinline__ void likelihood_distance(const EvConst& ev, double* th) {
+    if (ev.dist) th[8] = ev.dl_max;
 }
 
 __device__ __forceinline__ int source_from_theta(const EvConst& ev, const double* th, Src& s) {
@@ -346,6 +356,151 @@ __device__ __forceinline__ double log_i0(double x) {
         if (term < 1e-17 * sum) break;
     }
     return x - 0.5 * log(kTwoPi * x) + log(sum);
+}
+
+// I1(y)/I0(y), y >= 0: ratio of the power series (DLMF 10.25.2) below 30, of
+// the Hankel asymptotic series (DLMF 10.40.1) above.
+__device__ __forceinline__ double i1_over_i0(double y) {
+    if (y < 30.0) {
+        const double q = 0.25 * y * y;
+        double t0 = 1.0, s0 = 1.0, t1 = 1.0, s1 = 1.0;  // I0 = s0, I1 = (y/2) s1
+        for (int k = 1; k < 400; ++k) {
+            t0 *= q / ((double)k * (double)k);
+            t1 *= q / ((double)k * (double)(k + 1));
+            s0 += t0;
+            s1 += t1;
+            if (t0 < 1e-17 * s0) break;
+        }
+        return 0.5 * y * s1 / s0;
+    }
+    const double inv = 1.0 / y;
+    double t0 = 1.0, s0 = 1.0, t1 = 1.0, s1 = 1.0;
+    for (int k = 1; k < 64; ++k) {
+        const double m = (2.0 * k - 1.0) * (2.0 * k - 1.0);
+        const double n0 = t0 * m / (8.0 * k) * inv, n1 = t1 * (m - 4.0) / (8.0 * k) * inv;
+        if (fabs(n0) > fabs(t0)) break;
+        t0 = n0;
+        t1 = n1;
+        s0 += t0;
+        s1 += t1;
+        if (fabs(t0) < 1e-17 * s0 && fabs(t1) < 1e-17 * fabs(s1)) break;
+    }
+    return s1 / s0;
+}
+
+// ---------------------------------------------------------------------------
+// Distance marginalisation: ln of int_1^inf 3 x^-4 exp(phi(x) - b x^2) dx with
+// phi = a x (explicit phase) or ln I0(a x) (marginalised phase), x = dl_max/dL.
+// The log-integrand g has at most one interior maximum and one minimum on
+// (0, inf) (x g' is -4 + x phi' - 2 b x^2, with x phi' convex then linear).
+// Its maximiser x+ solves 2 b x^2 - phi'(x) x + 4 = 0; for the marginalised
+// phase phi' = a I1/I0(a x), iterated from phi' = a, which decreases
+// monotonically to x+. From x+ the integral is walked outward in panels of
+// 16-point Gauss-Legendre, each panel short enough that g changes by at most
+// kDmDelta across it and that x changes by at most half, until g has fallen
+// below kDmCut of its running maximum; a separate walk from x = 1 covers the
+// boundary when g rises again toward it. Sums are scaled by the running
+// maximum. The cost is ~10-25 panels per draw.
+// ---------------------------------------------------------------------------
+// 16-point Gauss-Legendre on [-1, 1]: positive nodes and their weights
+// (csrc/gen_gauss_legendre.py).
+constexpr double kGlX[8] = {0.9894009349916499, 0.9445750230732326, 0.8656312023878318, 0.755404408355003,
+                            0.6178762444026438, 0.45801677765722737, 0.2816035507792589, 0.09501250983763744};
+constexpr double kGlW[8] = {0.027152459411754058, 0.062253523938647776, 0.0951585116824929, 0.12462897125553395,
+                            0.14959598881657682, 0.16915651939500256, 0.1826034150449236, 0.18945061045506847};
+constexpr double kDmDelta = 8.0;   // largest change of ln(integrand) across a panel
+constexpr double kDmCut = 45.0;    // walk ends below e^-45 of the maximum
+constexpr int kDmMaxPanels = 400;  // per walk; reached only by non-finite input
+
+struct DmState {
+    double a, b;
+    bool ex;
+    double G, S;  // running maximum of ln(integrand); sum scaled by exp(-G)
+};
+
+__device__ __forceinline__ double dm_g(const DmState& q, double x) {
+    const double phi = q.ex ? q.a * x : log_i0(q.a * x);
+    return 1.0986122886681098 - 4.0 * log(x) + phi - q.b * x * x;  // ln 3 - 4 ln x + ...
+}
+
+__device__ __forceinline__ void dm_panel(DmState& q, double lo, double hi) {
+    const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+#pragma unroll 1
+    for (int k = 0; k < 16; ++k) {
+        const double t = (k < 8) ? -kGlX[k] : kGlX[k - 8];
+        const double v = dm_g(q, c + h * t);
+        if (v > q.G) {
+            q.S *= exp(q.G - v);
+            q.G = v;
+        }
+        q.S += h * kGlW[k < 8 ? k : k - 8] * exp(v - q.G);
+    }
+}
+
+// Walk from x0 (where g = g0) in direction dir until g falls below the cut
+// (while decreasing) or x reaches stop; returns the last x.
+__device__ __forceinline__ double dm_walk(DmState& q, double x0, double g0, int dir, double stop, double w) {
+#pragma unroll 1
+    for (int p = 0; p < kDmMaxPanels; ++p) {
+        double x1 = x0, g1 = g0;
+#pragma unroll 1
+        for (int h = 0; h < 64; ++h) {
+            if (dir > 0) {
+                w = fmin(w, 0.5 * x0);
+                x1 = fmin(x0 + w, stop);
+            } else {
+                w = fmin(w, x0 / 3.0);
+                x1 = fmax(x0 - w, stop);
+            }
+            g1 = dm_g(q, x1);
+            if (fabs(g1 - g0) <= kDmDelta) break;
+            w *= 0.5;
+        }
+        dm_panel(q, fmin(x0, x1), fmax(x0, x1));
+        if (x1 == stop) return x1;
+        if (g1 < q.G - kDmCut && g1 < g0) return x1;
+        x0 = x1;
+        g0 = g1;
+        w *= 2.0;
+    }
+    return x0;
+}
+
+__device__ __forceinline__ double log_dist_marg(double a, double b, bool ex) {
+    if (!(b > 0.0)) return (a == 0.0) ? 0.0 : NAN;  // H = 0 only with Z = 0 (no bins below the cut)
+    DmState q{a, b, ex, -INFINITY, 0.0};
+    double xs = 1.0, ae = a;
+#pragma unroll 1
+    for (int it = 0; it < 64; ++it) {
+        const double disc = ae * ae - 32.0 * b;
+        if (!(ae > 0.0) || disc < 0.0) {  // g' < 0 on [1, inf): the maximum is at x = 1
+            xs = 1.0;
+            break;
+        }
+        const double xn = fmax(1.0, (ae + sqrt(disc)) / (4.0 * b));
+        const bool done = ex || xn == 1.0 || fabs(xn - xs) <= 1e-14 * xn;
+        xs = xn;
+        if (done) break;
+        ae = a * i1_over_i0(a * xs);
+    }
+    const double g1 = dm_g(q, 1.0);
+    const double gs = (xs > 1.0) ? dm_g(q, xs) : g1;
+    q.G = fmax(g1, gs);
+    const double w0 = fmin(1.0 / sqrt(2.0 * b), 0.5 * xs);
+    dm_walk(q, xs, gs, +1, INFINITY, w0);
+    double xl = 1.0;
+    if (xs > 1.0) xl = dm_walk(q, xs, gs, -1, 1.0, w0);
+    if (xl > 1.0 && g1 >= q.G - kDmCut) dm_walk(q, 1.0, g1, +1, xl, w0);
+    return q.G + log(q.S);
+}
+
+// ln L from Z and H (Eq. 3): explicit phase Re Z - H/2, marginalised phase
+// ln I0(|Z|) - H/2; distance-marginalised events (Z, H at dl_max) integrate
+// over the distance prior.
+__device__ __forceinline__ double loglike_of(const EvConst& ev, double zr, double zi, double h) {
+    const bool ex = (ev.phase == PE_PHASE_EXPLICIT);
+    if (ev.dist) return log_dist_marg(ex ? zr : hypot(zr, zi), 0.5 * h, ex);
+    return ex ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
 }
 
 }  // namespace pe

@@ -26,6 +26,7 @@ constexpr double kAmpNewt = 0.21278751013966339916;   // sqrt(5/24) pi^(-2/3)
 // Per-event constants, passed to kernels by value.
 struct EvConst {
     int32_t n_det, params, phase, dim;
+    int32_t dist, pad_;  // dist: 1 for a distance-marginalised likelihood (11-D)
     int64_t K;
     double f_lo, df, scale, amp0, gmst, chi_max, dl_max;
     double dtensor[PE_MAX_DET][6];  // detector tensor (x x^T - y y^T)/2: xx xy xz yy yz zz

@@ -415,14 +415,29 @@ __global__ __launch_bounds__(1024) void k_metric_final(const BatchHdr* __restric
         // b = a .. DP-1); marginalised phase: the Schur complement of the phase
         // coordinate PH; then the prior precision on the diagonal.
         const int PH = (DP == D) ? D - 1 : D;
+        constexpr int DL = 8;  // distance coordinate (11-D)
         auto at = [&](int a, int b) {
             const int lo = min(a, b), hi = max(a, b);
             return Gs[lo * DP - lo * (lo - 1) / 2 + (hi - lo)];
         };
+        const bool sp = (ev.phase == PE_PHASE_MARG);
+        const bool sd = (ev.params == PE_PARAMS_11D) && ev.dist;
         if (t < D * D) {
             const int a = t / D, b = t - (t / D) * D;
             double m = at(a, b);
-            if (ev.phase == PE_PHASE_MARG) m = (a == PH || b == PH) ? 0.0 : m - at(a, PH) * at(PH, b) / at(PH, PH);
+            // Schur complement of the projected coordinates: the phase for the
+            // marginalised phase, dL for the marginalised distance, or both
+            if ((sp && (a == PH || b == PH)) || (sd && (a == DL || b == DL))) {
+                m = 0.0;
+            } else if (sp && sd) {
+                const double pp = at(PH, PH), pl = at(PH, DL), ll = at(DL, DL);
+                const double det = pp * ll - pl * pl;
+                m -= (at(a, DL) * (pp * at(DL, b) - pl * at(PH, b)) + at(a, PH) * (ll * at(PH, b) - pl * at(DL, b))) / det;
+            } else if (sp) {
+                m -= at(a, PH) * at(PH, b) / at(PH, PH);
+            } else if (sd) {
+                m -= at(a, DL) * at(DL, b) / at(DL, DL);
+            }
             double reg = 0.0;
             if (a == b && !(A.flags & 1)) {
                 if (ev.params == PE_PARAMS_4D) {
@@ -466,18 +481,39 @@ hipError_t launch_metric_batch(const BatchPtrs& b, int ne, int64_t total_blocks,
 // a success flag, in registers (D is a template constant).
 template <int D>
 __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
-    const double* g = A.g;
+    double g[D][D];
     double L[D][D];
     int ok = 1;
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int j = 0; j < D; ++j) L[i][j] = 0.0;
+        for (int j = 0; j < D; ++j) {
+            L[i][j] = 0.0;
+            g[i][j] = A.g[i * D + j];
+        }
+    // distance-marginalised likelihood: decouple dL (index 8) by the Schur
+    // complement of its row and column, keeping g_88; the other coordinates'
+    // distribution is unchanged and dL's drawn value is never used
+    const bool dist = (D == 11) && A.ec.dist;
+    if constexpr (D == 11) {
+        if (dist) {
+            const double g88 = g[8][8];
+            ok = g88 > 0.0;
+            double c8[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) c8[i] = g[i][8];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    g[i][j] = (i == 8 || j == 8) ? ((i == j) ? g88 : 0.0) : (ok ? g[i][j] - c8[i] * c8[j] / g88 : g[i][j]);
+        }
+    }
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
-            double s = g[i * D + j];
+            double s = g[i][j];
 #pragma unroll
             for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
             if (i == j) {
@@ -492,9 +528,12 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
     for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = 0; j < D; ++j) A.chol[i * D + j] = ok ? L[i][j] : 0.0;
+    // log det of the factor of the density log q reports: without L_88 for a
+    // distance-marginalised likelihood (the marginal over dL)
     if (ok)
 #pragma unroll
-        for (int a = 0; a < D; ++a) logdet += log(L[a][a]);
+        for (int a = 0; a < D; ++a)
+            if (!(dist && a == 8)) logdet += log(L[a][a]);
     A.chol[PE_MAX_DIM * PE_MAX_DIM] = logdet;
     A.chol[PE_MAX_DIM * PE_MAX_DIM + 1] = ok ? 1.0 : 0.0;
     // (L L^T) at the periodic coordinates (11-D: ra, psi, phic), for the image sum of log q
@@ -581,9 +620,13 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
     // whitened offset of image m: L^T (x - theta0) = z + L^T s with
     // s = (k - k0) P on the periodic rows, so its squared norm is
     // |z|^2 + 2 s.a + s^T G s with a_p = (L^T row pidx_p) . z and G = L L^T there
+    // distance-marginalised likelihood: log q of the marginal over dL, whose
+    // normal z_8 (decoupled by the Cholesky kernel) moves dL alone
+    const bool dist = (D == 11) && ev.dist;
     double zz = 0.0;
 #pragma unroll
-    for (int r = 0; r < D; ++r) zz = fma(z[r], z[r], zz);
+    for (int r = 0; r < D; ++r)
+        if (!(dist && r == 8)) zz = fma(z[r], z[r], zz);
     double a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int p = 0; p < NP; ++p)
@@ -614,7 +657,7 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
             acc += exp(l - mx);
         }
     }
-    A.logq[i] = mx + log(acc) + lc[PE_MAX_DIM * PE_MAX_DIM] - 0.5 * D * log(kTwoPi);
+    A.logq[i] = mx + log(acc) + lc[PE_MAX_DIM * PE_MAX_DIM] - 0.5 * (D - (dist ? 1 : 0)) * log(kTwoPi);
     A.logprior[i] = log_prior_of(ev, th);
 }
 

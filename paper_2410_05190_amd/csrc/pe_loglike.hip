@@ -316,6 +316,7 @@ __global__ __launch_bounds__(256) void k_b_coeffs(const BatchHdr* __restrict__ h
         double th[PE_MAX_DIM];
 #pragma unroll
         for (int a = 0; a < PE_MAX_DIM; ++a) th[a] = (a < E.ec.dim) ? ((const double*)E.partial)[j * kRecStride + a] : 0.0;
+        likelihood_distance(E.ec, th);
         Src s;
         source_from_theta(E.ec, th, s);
         PhaseCoef pc;
@@ -689,7 +690,7 @@ __global__ __launch_bounds__(256) void k_b_finalize(BatchHdr* __restrict__ hdr, 
                 atomicOr(E.status, kStRedoFull);
         }
         const double h = E.hh[j];
-        const double ll = (E.ec.phase == PE_PHASE_EXPLICIT) ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
+        const double ll = loglike_of(E.ec, zr, zi, h);
         const int64_t i = E.idx[j];
         E.loglike[i] = ll;
         if (E.aux) {
@@ -765,7 +766,7 @@ __global__ __launch_bounds__(256) void k_b_redo(const BatchHdr* __restrict__ hdr
                 Zi += rr * ai + ri * ar;
             }
             const double h = E.hh[j];
-            const double ll = (E.ec.phase == PE_PHASE_EXPLICIT) ? Zr - 0.5 * h : log_i0(hypot(Zr, Zi)) - 0.5 * h;
+            const double ll = loglike_of(E.ec, Zr, Zi, h);
             const int64_t i = E.idx[j];
             E.loglike[i] = ll;
             if (E.aux) {

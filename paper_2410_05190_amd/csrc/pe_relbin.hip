@@ -266,6 +266,7 @@ __global__ __launch_bounds__(256) void k_rb_ll(RbArg a) {
         double th[PE_MAX_DIM];
 #pragma unroll
         for (int q = 0; q < PE_MAX_DIM; ++q) th[q] = (q < ev.dim) ? a.theta[(int64_t)q * a.n + i] : 0.0;
+        likelihood_distance(ev, th);
         Src s;
         ok = source_from_theta(ev, th, s);
         if (ok) {
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(256) void k_rb_ll(RbArg a) {
         }
         return;
     }
-    const double ll = (ev.phase == PE_PHASE_EXPLICIT) ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
+    const double ll = loglike_of(ev, zr, zi, h);
     a.loglike[i] = ll;
     if (a.aux) {
         a.aux[3 * i] = zr;

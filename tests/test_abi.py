@@ -3,6 +3,7 @@ include/pe.h declares (no compute call is made here)."""
 import ctypes
 import os
 import re
+import subprocess
 
 from paper_2410_05190_amd import binding
 
@@ -116,6 +117,17 @@ def test_server_structs_and_host_checks():
     assert L.pe_server_destroy(None) == 1
 
 
-def test_event_desc_layout_matches_header():
-    # pe_event_desc_t: int32, int64, 2 double, 2 int32, double, 2 int32, 4 double, double[4][3]
-    assert ctypes.sizeof(binding.EventDesc) == 8 + 8 + 16 + 8 + 8 + 8 + 32 + 96
+def test_event_desc_layout_matches_header(tmp_path):
+    """The binding's pe_event_desc_t has the header's size and field offsets, as the C compiler
+    lays the header's struct out."""
+    fields = [f[0] for f in binding.EventDesc._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "pe.h"\nint main(void) {\n'
+                   '    printf("%zu\\n", sizeof(pe_event_desc_t));\n' +
+                   "".join(f'    printf("%zu\\n", offsetof(pe_event_desc_t, {f}));\n' for f in fields) +
+                   "    return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert vals[0] == ctypes.sizeof(binding.EventDesc)
+    assert vals[1:] == [getattr(binding.EventDesc, f).offset for f in fields]
