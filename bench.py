@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--tile-spacing", type=float, default=1.0, help="tile-mixture leg: template spacing (whitened)")
     ap.add_argument("--tile-candidates", type=int, default=4000000,
                     help="tile-mixture leg: slice candidates for the prior samples (0 skips the leg; 4-D only)")
+    ap.add_argument("--no-distance-leg", action="store_true",
+                    help="skip the distance-marginalised leg (11-D configurations)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (HBM counter calibration)")
     return ap.parse_args()
@@ -236,6 +238,11 @@ def main():
         out["refined"] = refine_leg(first, args.refine_rounds, args.refine_draws, max(args.steps, 1), prec)
     if n_events == 1 and args.relbin_eps > 0:
         out["relbin"] = relbin_leg(first, args.relbin_eps, max(args.steps, 1), prec)
+    if n_events == 1 and D == 11 and not args.no_distance_leg:
+        centres = {"injection": first["theta0"]}
+        if "refined" in out:
+            centres["refined"] = torch.tensor(out["refined"]["centre"], dtype=torch.float64, device="cuda")
+        out["distance_marginalised"] = distance_leg(first, centres, max(args.steps, 1), prec)
     if n_events == 1 and D == 4 and args.tile_candidates > 0:
         out["tiles"] = tile_leg(first, args, max(args.steps, 1), prec)
     n_drift = args.drift_sample if args.drift_sample >= 0 else (1024 if c == 4 else 0)
@@ -352,6 +359,44 @@ def relbin_leg(x, eps, steps, prec):
                                        "max_within_20_of_peak": float(err[core].max()) if core.any() else None,
                                        "draws_within_20_of_peak": int(core.sum())},
     }
+
+
+def distance_leg(x, centres, steps, prec):
+    """Distance-marginalised likelihood (PE_DIST_MARG: the likelihood integrated over the dL^2
+    prior per draw; the metric, draws and prior without dL): the same step as the main leg on a
+    second event over the same data, at each proposal centre (the injection, and the refined
+    centre of the refinement leg when it ran). ESS per event and ESS/s."""
+    import torch
+
+    from paper_2410_05190_amd import binding
+    ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], distance=binding.PE_DIST_MARG, **x["common"])
+    N = x["N"]
+    ev.reserve(N)
+    h_ = ev.handle
+    g = torch.empty_like(x["g"])
+    res = {"kind": "likelihood marginalised over the luminosity distance (dL^2 prior), per draw in FP64"}
+    for name, t0 in centres.items():
+        st = torch.empty((steps, 4), dtype=torch.float64, device="cuda")
+        for i in range(-1, steps):  # step -1: untimed warm-up
+            if i == 0:
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+            binding.pe_event_update(h_, x["data"], x["psd"])
+            binding.pe_metric(h_, t0, None, 0, g)
+            binding.pe_draw(h_, t0, g, x["seed"] + 13, max(i, 0), N, x["theta"], x["lq"], x["lp"])
+            binding.pe_loglike_batch(h_, x["theta"], N, prec, x["ll"], None)
+            binding.pe_weights_ess(x["ll"], x["lp"], x["lq"], N, x["w"], st[max(i, 0)])
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ev.status()
+        s = st.cpu().numpy()
+        ess = float(s[:, 0].mean())
+        t_step = (tb - ta) / steps
+        res[name] = {"steps": steps, "draws_per_step": N, "ms_per_step": 1e3 * t_step,
+                     "evals_per_s": float(s[:, 3].sum()) / (tb - ta), "ess_per_event_mean": ess,
+                     "efficiency": ess / N, "ess_per_s": ess / t_step}
+    ev.close()
+    return res
 
 
 def tile_leg(x, args, steps, prec):
