@@ -284,6 +284,52 @@ void release_area(Area& A) {
     dfree_bytes(A.dev);
     A.cap = 0;
     A.shadow.clear();
+    for (int k = 0; k < 2; ++k) {
+        if (A.done[k]) {
+            (void)hipEventSynchronize(A.done[k]);
+            (void)hipEventDestroy(A.done[k]);
+            A.done[k] = nullptr;
+        }
+        if (A.host[k]) (void)hipHostFree(A.host[k]);
+        A.host[k] = A.host_dev[k] = nullptr;
+        A.host_cap[k] = 0;
+    }
+}
+
+// Copies an argument image from pinned host memory into the area on the
+// stream: 16-byte words, grid-strided. A kernel keeps the upload on the
+// compute queue, ordered with the launches around it, and leaves the host free:
+// the runtime's small host-to-device copies have stalled the host for
+// milliseconds behind the stream's earlier work.
+__global__ __launch_bounds__(256) void k_upload(uint4* __restrict__ dst, const uint4* __restrict__ src, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+hipError_t upload_bytes(char* dst, const char* src, size_t bytes, hipStream_t st) {
+    const int64_t n16 = (int64_t)((bytes + 15) / 16);
+    if (n16 == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<int64_t>((n16 + 1023) / 1024, 64);
+    k_upload<<<grid, 256, 0, st>>>((uint4*)dst, (const uint4*)src, n16);
+    return hipGetLastError();
+}
+
+// The next pinned staging buffer of the area, at least `bytes` long (rounded
+// up to 16-byte words), once the upload last made from it has completed.
+pe_status_t staging_buffer(Area& A, size_t bytes, int& k) {
+    k = A.next;
+    A.next ^= 1;
+    if (A.done[k]) PE_HIP(hipEventSynchronize(A.done[k]));
+    else PE_HIP(hipEventCreateWithFlags(&A.done[k], hipEventDisableTiming));
+    if (A.host_cap[k] < bytes + 16) {
+        if (A.host[k]) PE_HIP(hipHostFree(A.host[k]));
+        A.host[k] = nullptr;
+        A.host_cap[k] = 0;
+        const size_t cap = align_up(std::max<size_t>(bytes + bytes / 2, 1 << 14), 256);
+        PE_HIP(hipHostMalloc((void**)&A.host[k], cap, hipHostMallocDefault));
+        A.host_cap[k] = cap;
+        PE_HIP(hipHostGetDevicePointer((void**)&A.host_dev[k], A.host[k], 0));
+    }
+    return PE_OK;
 }
 
 size_t loglike_scratch_bytes(int ne, int redo_cap) {
@@ -325,17 +371,24 @@ pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const vo
     if (arg_bytes) std::memcpy(img.data() + o_args, args, arg_bytes);
     std::memcpy(img.data() + o_off, off.data(), sizeof(int64_t) * (ne + 1));
     if (off2) std::memcpy(img.data() + o_off2, off2->data(), sizeof(int64_t) * (ne + 1));
-    if (A.fixed) {
-        // only the used parts
-        PE_HIP(hipMemcpyAsync(A.dev, img.data(), o_args + arg_bytes, hipMemcpyHostToDevice, st));
-        PE_HIP(hipMemcpyAsync(A.dev + o_off, img.data() + o_off, sizeof(int64_t) * (ne + 1), hipMemcpyHostToDevice,
-                              st));
-        if (off2)
-            PE_HIP(hipMemcpyAsync(A.dev + o_off2, img.data() + o_off2, sizeof(int64_t) * (ne + 1),
-                                  hipMemcpyHostToDevice, st));
-    } else if (img != A.shadow) {
-        PE_HIP(hipMemcpyAsync(A.dev, img.data(), img.size(), hipMemcpyHostToDevice, st));
-        A.shadow.swap(img);
+    if (A.fixed || img != A.shadow) {
+        int k;
+        pe_status_t s = staging_buffer(A, img.size(), k);
+        if (s != PE_OK) return s;
+        std::memcpy(A.host[k], img.data(), img.size());
+        const char* src = A.host_dev[k];
+        // the image's parts start on 256-byte offsets; whole 16-byte words are
+        // copied (the staging buffer and the area extend past each part)
+        if (A.fixed) {
+            // only the used parts
+            PE_HIP(upload_bytes(A.dev, src, o_args + arg_bytes, st));
+            PE_HIP(upload_bytes(A.dev + o_off, src + o_off, sizeof(int64_t) * (ne + 1), st));
+            if (off2) PE_HIP(upload_bytes(A.dev + o_off2, src + o_off2, sizeof(int64_t) * (ne + 1), st));
+        } else {
+            PE_HIP(upload_bytes(A.dev, src, img.size(), st));
+            A.shadow.swap(img);
+        }
+        PE_HIP(hipEventRecord(A.done[k], st));
     }
     out.hdr = (BatchHdr*)A.dev;
     out.args = A.dev + o_args;
@@ -486,9 +539,11 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     const int ne = (int)v.size();
     if (ne == 0) return PE_OK;
     std::vector<int64_t> poff(ne + 1, 0), foff(ne + 1, 0);
+    bool any_dist = false;
     for (int e = 0; e < ne; ++e) {
         poff[e + 1] = poff[e] + ((v[e].flags & kLlPrologue) ? blocks256(v[e].n) : 0);
         foff[e + 1] = foff[e] + ((v[e].flags & kLlFinalize) ? blocks256(v[e].n) : 0);
+        any_dist = any_dist || v[e].ec.dist;
     }
     Area& A = area_for(st, kAreaLoglike);
     std::lock_guard<std::mutex> lk(A.mu);
@@ -497,7 +552,7 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     pe_status_t s = upload_area(A, ne, poff[ne], foff[ne], v.data(), sizeof(EvDev) * ne, poff, &foff,
                                 loglike_scratch_bytes(ne, redo_cap), st, b, redo_cap);
     if (s != PE_OK) return s;
-    PE_HIP(launch_loglike_batch(b, ne, poff[ne], foff[ne], precision, true, st));
+    PE_HIP(launch_loglike_batch(b, ne, poff[ne], foff[ne], precision, true, any_dist, st));
     return PE_OK;
 }
 

@@ -495,12 +495,17 @@ __device__ __forceinline__ double log_dist_marg(double a, double b, bool ex) {
 }
 
 // ln L from Z and H (Eq. 3): explicit phase Re Z - H/2, marginalised phase
-// ln I0(|Z|) - H/2; distance-marginalised events (Z, H at dl_max) integrate
+// ln I0(|Z|) - H/2.
+__device__ __forceinline__ double loglike_phase(const EvConst& ev, double zr, double zi, double h) {
+    return (ev.phase == PE_PHASE_EXPLICIT) ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
+}
+
+// The same, or for distance-marginalised events (Z, H at dl_max) the integral
 // over the distance prior.
 __device__ __forceinline__ double loglike_of(const EvConst& ev, double zr, double zi, double h) {
     const bool ex = (ev.phase == PE_PHASE_EXPLICIT);
     if (ev.dist) return log_dist_marg(ex ? zr : hypot(zr, zi), 0.5 * h, ex);
-    return ex ? zr - 0.5 * h : log_i0(hypot(zr, zi)) - 0.5 * h;
+    return loglike_phase(ev, zr, zi, h);
 }
 
 }  // namespace pe

@@ -69,6 +69,14 @@ struct Area {
     int layout_ne = 0;      // fixed layout: records
     size_t layout_rec = 0;  // fixed layout: bytes per record
     std::vector<char> shadow;
+    // pinned staging of the uploads, two buffers used in turn; done[k] is
+    // recorded after the copy from buffer k, so the host refills a buffer only
+    // once its previous copy has left it
+    char* host[2] = {nullptr, nullptr};
+    char* host_dev[2] = {nullptr, nullptr};  // the same buffers' device-side addresses
+    size_t host_cap[2] = {0, 0};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    int next = 0;
 };
 
 size_t area_bytes(int ne, size_t arg_bytes, size_t scratch_bytes);

@@ -56,6 +56,7 @@ constexpr int kNCoef = 14;
 // written by the scatter into the partial buffer and read by the coefficients.
 constexpr int kRecStride = 12;
 static_assert(kRecStride >= PE_MAX_DIM, "a record holds one draw's parameters");
+static_assert(kRecStride % 2 == 0, "records are written as 16-byte pairs");
 
 constexpr int kTile = 256;    // draws per workgroup of the hot loop
 constexpr int kBlk = 16;      // bins per FP32 block sum before its fold into FP64
@@ -283,8 +284,9 @@ hipError_t launch_prep_batch(const BatchPtrs &b, int ne, int64_t total_blocks, i
                              hipStream_t st);
 hipError_t launch_metric_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
 hipError_t launch_draw_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
+// any_dist: some event of the batch is distance-marginalised (adds k_b_dist).
 hipError_t launch_loglike_batch(const BatchPtrs &b, int ne, int64_t prologue_blocks, int64_t finalize_blocks,
-                                int precision, bool profile, hipStream_t st);
+                                int precision, bool profile, bool any_dist, hipStream_t st);
 hipError_t launch_weights_batch(const BatchPtrs &b, int ne, int64_t total_blocks, int64_t total_draw_blocks,
                                 hipStream_t st);
 hipError_t launch_update_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);

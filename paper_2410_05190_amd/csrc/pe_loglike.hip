@@ -1,5 +1,5 @@
 // pe_loglike.hip -- log-likelihoods of batches of draws of one or many events
-// (Eq. 3), seven launches per batch whatever the number of events.
+// (Eq. 3), one set of launches per batch whatever the number of events.
 //
 //   k_b_reset     clear the cut histograms and plans of the events starting here
 //   k_b_support   support mask, ISCO cut and cut bucket of every draw
@@ -12,6 +12,7 @@
 //                 lanes = draws; the bin record is wave-uniform (scalar loads)
 //                 and reused by the 64 draws of a wave and the 256 of a workgroup
 //   k_b_finalize  fixed-order combine of the group partials, ln L
+//   k_b_dist      distance-marginalised events: ln L integrated over dL
 //
 // An event's decomposition (chunk length, groups) is planned on the device from
 // its own live draws only (their largest cut bucket and their number), so its
@@ -233,33 +234,30 @@ __global__ void k_b_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ 
 // Live draws into their buckets; the order inside a bucket is immaterial. A
 // block ranks its draws per bucket in shared memory and claims one run of
 // positions per bucket, so a block's draws of one bucket sit side by side.
-// The block then sorts its draws by position (bitonic, 256 keys) and writes
-// each live draw's parameters as one record of kRecStride doubles at its
-// position in the record buffer (the event's partial buffer, idle until the
-// hot loop), staged in shared memory so that consecutive lanes write
-// consecutive words; k_b_coeffs reads the records in position order.
+// Each live draw then writes its index, its cut and its parameters (one record
+// of kRecStride doubles, as 16-byte stores) at its position in the record
+// buffer (the event's partial buffer, idle until the hot loop); the lanes of a
+// bucket's run write one contiguous span, which the L2 merges before HBM.
+// k_b_coeffs reads the records in position order.
 __global__ __launch_bounds__(256) void k_b_scatter(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                    const int64_t* __restrict__ poff) {
     __shared__ int lh[kBuckets];
     __shared__ int sh[8];
-    __shared__ unsigned long long key[256];
-    __shared__ double srec[256 * kRecStride];
     const int ne = hdr->ne;
     const int t = threadIdx.x;
     const int64_t nblk = poff[ne];
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         const int e = find_slot(poff, ne, b);
         const EvDev& E = evs[e];
-        const int64_t i0 = (b - poff[e]) * 256;
-        const int64_t i = i0 + t;
-        int bk = -1;
+        const int64_t i = (b - poff[e]) * 256 + t;
+        int bk = -1, kc = -1;
         if (i < E.n) {
-            const int kc = E.kc_all[i];
+            kc = E.kc_all[i];
             if (kc >= 0) bk = (kBuckets - 1) - (kc >> bucket_shift(E.ec.K));
         }
         int lo, hi;
         block_bucket_range(bk, sh, lo, hi);
-        if (hi < 0) continue;
+        if (hi < 0) continue;  // uniform: no live draw in the block
         for (int q = lo + t; q <= hi; q += 256) lh[q] = 0;
         __syncthreads();
         const int rank = bk >= 0 ? atomicAdd(&lh[bk], 1) : 0;
@@ -269,37 +267,18 @@ __global__ __launch_bounds__(256) void k_b_scatter(const BatchHdr* __restrict__ 
             if (c) lh[q] = atomicAdd(&E.hist[q], c);
         }
         __syncthreads();
-        key[t] = (bk >= 0) ? ((unsigned long long)(lh[bk] + rank) << 8) | (unsigned)t : ~0ull;
-        const int L = __syncthreads_count(bk >= 0);
-        for (int k = 2; k <= 256; k <<= 1)
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                const int p = t ^ j;
-                if (p > t) {
-                    const unsigned long long x = key[t], y = key[p];
-                    if ((x > y) == ((t & k) == 0)) {
-                        key[t] = y;
-                        key[p] = x;
-                    }
-                }
-                __syncthreads();
-            }
-        if (t < L) {
-            const unsigned long long k = key[t];
-            const int64_t pos = (int64_t)(k >> 8);
-            const int64_t is = i0 + (int)(k & 255u);
-            E.idx[pos] = (int)is;
-            E.kcut[pos] = E.kc_all[is];
+        if (bk >= 0) {
+            const int64_t pos = (int64_t)lh[bk] + rank;
+            E.idx[pos] = (int)i;
+            E.kcut[pos] = kc;
+            double th[kRecStride];
 #pragma unroll
-            for (int a = 0; a < kRecStride; ++a)
-                srec[t * kRecStride + a] = (a < E.ec.dim) ? E.theta[(int64_t)a * E.n + is] : 0.0;
+            for (int a = 0; a < kRecStride; ++a) th[a] = (a < E.ec.dim) ? E.theta[(int64_t)a * E.n + i] : 0.0;
+            double2* rec = (double2*)((double*)E.partial + pos * kRecStride);
+#pragma unroll
+            for (int a = 0; a < kRecStride / 2; ++a) rec[a] = make_double2(th[2 * a], th[2 * a + 1]);
         }
-        __syncthreads();
-        double* rec = (double*)E.partial;
-        for (int w = t; w < L * kRecStride; w += 256) {
-            const int r = w / kRecStride;
-            rec[(int64_t)(key[r] >> 8) * kRecStride + (w - r * kRecStride)] = srec[w];
-        }
-        __syncthreads();
+        __syncthreads();  // lh is reused by the block's next iteration
     }
 }
 
@@ -690,14 +669,36 @@ __global__ __launch_bounds__(256) void k_b_finalize(BatchHdr* __restrict__ hdr, 
                 atomicOr(E.status, kStRedoFull);
         }
         const double h = E.hh[j];
-        const double ll = loglike_of(E.ec, zr, zi, h);
         const int64_t i = E.idx[j];
-        E.loglike[i] = ll;
+        if (E.ec.dist)  // k_b_dist integrates over the distance (this draw's partials are consumed)
+            E.partial[j] = make_double2(zr, zi);
+        else
+            E.loglike[i] = loglike_phase(E.ec, zr, zi, h);
         if (E.aux) {
             E.aux[3 * i] = zr;
             E.aux[3 * i + 1] = zi;
             E.aux[3 * i + 2] = h;
         }
+    }
+}
+
+// Distance-marginalised events: ln L of each live draw from the Z that the
+// finalize (or the FP64 re-evaluation) left in the first partial slot of its
+// position and H, integrated over the distance prior. Kept out of the finalize
+// so that the finalize's register budget (and occupancy) stays that of the
+// plain likelihood; blocks of other events return at once.
+__global__ __launch_bounds__(256) void k_b_dist(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                const int64_t* __restrict__ foff) {
+    const int ne = hdr->ne;
+    const int64_t nblk = foff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(foff, ne, b);
+        const EvDev& E = evs[e];
+        if (!E.ec.dist) continue;
+        const int64_t j = (b - foff[e]) * 256 + threadIdx.x;
+        if (j >= E.plan->n_active) continue;
+        const double2 z = E.partial[j];
+        E.loglike[E.idx[j]] = loglike_of(E.ec, z.x, z.y, E.hh[j]);
     }
 }
 
@@ -766,9 +767,11 @@ __global__ __launch_bounds__(256) void k_b_redo(const BatchHdr* __restrict__ hdr
                 Zi += rr * ai + ri * ar;
             }
             const double h = E.hh[j];
-            const double ll = loglike_of(E.ec, Zr, Zi, h);
             const int64_t i = E.idx[j];
-            E.loglike[i] = ll;
+            if (E.ec.dist)
+                E.partial[j] = make_double2(Zr, Zi);
+            else
+                E.loglike[i] = loglike_phase(E.ec, Zr, Zi, h);
             if (E.aux) {
                 E.aux[3 * i] = Zr;
                 E.aux[3 * i + 1] = Zi;
@@ -812,7 +815,7 @@ void prime_hot_grids() {
 }
 
 hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blocks, int64_t finalize_blocks,
-                                int precision, bool profile, hipStream_t st) {
+                                int precision, bool profile, bool any_dist, hipStream_t st) {
     if (ne <= 0) return hipSuccess;
     const EvDev* evs = (const EvDev*)b.args;
     int64_t* ioff = (int64_t*)b.scratch;
@@ -847,6 +850,7 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
         } else {
             k_b_finalize<false><<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2, redo);
         }
+        if (any_dist) k_b_dist<<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2);
     }
     return hipGetLastError();
 }

@@ -297,7 +297,8 @@ void pe_server_s::admit() {
 pe_status_t pe_server_s::capture(const BatchPtrs& bll, const BatchPtrs& bw) {
     hipGraph_t g = nullptr;
     PE_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_loglike_batch(bll, cap_ne, 0, cap_fblocks, cfg.precision, false, st);
+    // the captured slice serves every later mix of requests: it keeps the distance pass
+    hipError_t e = launch_loglike_batch(bll, cap_ne, 0, cap_fblocks, cfg.precision, false, true, st);
     if (e == hipSuccess) e = launch_weights_batch(bw, cap_ne, cap_wblocks, cap_dblocks, st);
     hipError_t e2 = hipStreamEndCapture(st, &g);
     if (e != hipSuccess) return fail(PE_ERR_HIP, std::string("slice capture: ") + hipGetErrorString(e));
@@ -370,7 +371,7 @@ pe_status_t pe_server_s::slice() {
         PE_HIP(hipGraphLaunch(graph, st));
         ++n_replays;
     } else {
-        PE_HIP(launch_loglike_batch(bll, ne, 0, foff[ne], cfg.precision, false, st));
+        PE_HIP(launch_loglike_batch(bll, ne, 0, foff[ne], cfg.precision, false, true, st));
         PE_HIP(launch_weights_batch(bw, nw, boff[nw], doff[nw], st));
     }
     PE_HIP(hipEventRecord(ev_b, st));

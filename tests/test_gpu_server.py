@@ -13,14 +13,16 @@ from paper_2410_05190_amd import binding
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [  # (config, event, n_det, n_bins, draws, host data)
-    (1, 0, 3, 40000, 3000, False),
-    (2, 1, 2, None, 20000, True),
-    (1, 2, 1, 30000, 700, True),
-    (0, 0, None, None, 2500, False),
-    (2, 3, 3, None, 5000, False),
-    (1, 4, 2, 25000, 1, True),
-    (1, 5, 3, None, 16384, False),  # full config-1 band (519 168 bins)
+SHAPES = [  # (config, event, n_det, n_bins, draws, host data, distance-marginalised)
+    (1, 0, 3, 40000, 3000, False, 0),
+    (2, 1, 2, None, 20000, True, 0),
+    (1, 2, 1, 30000, 700, True, 0),
+    (0, 0, None, None, 2500, False, 0),
+    (2, 3, 3, None, 5000, False, 0),
+    (1, 4, 2, 25000, 1, True, 0),
+    (1, 5, 3, None, 16384, False, 0),  # full config-1 band (519 168 bins)
+    (1, 6, 3, 30000, 2000, False, 1),
+    (2, 7, 2, None, 3000, True, 1),
 ]
 
 
@@ -36,8 +38,8 @@ def _single(b, ev, theta0, n, seed, stream_id, prec):
 def _run(prec, use_graph, slice_ms, budget=1 << 32, max_active=64):
     torch = torch_cuda()
     built = []
-    for cfg, e, nd, K, n, on_host in SHAPES:
-        b = build_event(cfg, e, n_det=nd, n_bins=K)
+    for cfg, e, nd, K, n, on_host, dist in SHAPES:
+        b = build_event(cfg, e, n_det=nd, n_bins=K, distance=dist)
         built.append((b, n, on_host))
     srv = binding.Server(budget, precision=prec, max_active=max_active, slice_ms=slice_ms, use_graph=use_graph)
     tickets, outs, keep = [], [], []
