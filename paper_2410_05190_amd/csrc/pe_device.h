@@ -121,8 +121,9 @@ __device__ __forceinline__ int mass_and_support(const EvConst& ev, const double*
     }
     const double mc = th[0], q = th[1], c1 = th[2], c2 = th[3];
     const double dec = th[5], iota = th[6], dl = th[8];
+    // M = Mc (1+q)^(6/5) q^(-3/5) = Mc eta^(-3/5), eta = q/(1+q)^2: one pow
     const double opq = 1.0 + q;
-    M = mc * pow(opq, 1.2) * pow(q, -0.6);
+    M = mc * pow(q / (opq * opq), -0.6);
     return (mc > 0.0) && (q > 0.0) && (q <= 1.0) && (fabs(c1) <= ev.chi_max) && (fabs(c2) <= ev.chi_max) &&
            (fabs(dec) <= 0.5 * kPi) && (iota >= 0.0) && (iota <= kPi) &&
            (ev.dist || ((dl > 0.0) && (dl <= ev.dl_max)));

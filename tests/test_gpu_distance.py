@@ -161,3 +161,28 @@ def test_descriptor_checks():
     kw["distance"] = 7
     with pytest.raises(binding.PeError):
         binding.Event(data, psd, **kw)
+
+
+@pytest.mark.parametrize("snr,zero_noise", [(60.0, True), (8.0, False)])
+def test_loud_and_quiet_events_and_a_draw_without_bins(snr, zero_noise):
+    """The integral's regimes: a loud noise-free event (narrow peak in distance) and a quiet one
+    (prior-dominated, heavy tail), FP64 path against the oracle; a draw whose ISCO cut lies below the
+    band has Z = H = 0, so its likelihood is 1 at every distance and ln L_D = 0."""
+    torch_cuda()
+    b = build_event(1, 6, n_bins=40000, zero_noise=zero_noise, snr=snr, distance=oracle.DIST_MARG)
+    ev, data, psd = upload_event(b)
+    g = b.ev.metric(b.theta_inj)
+    rc, th, lq, lp = b.ev.draw(b.theta_inj, g, 3, 1, 120)
+    th[:, 0] = b.theta_inj
+    th[:, 1] = b.theta_inj
+    th[0, 1] = 400.0  # ISCO below the band's 20 Hz: no bin below the cut
+    ll_o = b.ev.loglike(th, n_threads=8)
+    ll = host(ev.loglike(dev(th), precision=binding.PE_PREC_FP64))
+    f = np.isfinite(ll_o)
+    assert np.array_equal(np.isfinite(ll), f)
+    assert ll[1] == 0.0 and abs(ll_o[1]) < 1e-13
+    tol = fp64_tol(b) + 1e-9 * np.maximum(1.0, np.abs(ll_o[f]))
+    d = np.abs(ll[f] - ll_o[f])
+    note(f"distance-marginalised SNR {snr}: ln L_D at the injection {ll_o[0]:.3f}, max |dlnL| {d.max():.2e}")
+    assert np.all(d <= tol)
+    ev.close()
