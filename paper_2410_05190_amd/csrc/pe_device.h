@@ -137,8 +137,9 @@ __device__ __forceinline__ double log_prior_of(const EvConst& ev, const double* 
     double M;
     if (!mass_and_support(ev, th, M)) return -INFINITY;
     if (ev.params == PE_PARAMS_4D) return 0.0;
-    const double ang = log(cos(th[5])) + log(sin(th[6]));
-    return ev.dist ? ang : ang + 2.0 * log(th[8]);
+    // one logarithm of the product (every factor is positive inside the support)
+    const double ang = cos(th[5]) * sin(th[6]);
+    return log(ev.dist ? ang : ang * (th[8] * th[8]));
 }
 
 // The likelihood of a distance-marginalised event is evaluated at the

@@ -302,7 +302,14 @@ constexpr int64_t kMwsSrc = 32;                                      // (2D+1) s
 constexpr int64_t kMwsPart = kMwsSrc + (2 * PE_MAX_DIM + 1) * kMetricSrcStride;
 constexpr int64_t kMwsChol = kMwsPart + (int64_t)kMetricBlocks * kMetricNG;  // L (D*D) + logdet + flag
 constexpr int kScanSeg = 256;                                        // segments of the prefix scan
-constexpr int64_t kMwsScan = kMwsChol + PE_MAX_DIM * PE_MAX_DIM + 8;  // segment sums [n_det][kScanSeg]
+// the Cholesky record: L (row-major D*D), log det, success flag, the periodic
+// block of L L^T (G00 G01 G02 G11 G12 G22), the reciprocals 1/L_rr
+constexpr int kCholLogdet = PE_MAX_DIM * PE_MAX_DIM;
+constexpr int kCholOk = kCholLogdet + 1;
+constexpr int kCholG = kCholLogdet + 2;
+constexpr int kCholRdiag = kCholLogdet + 8;
+constexpr int kCholLen = kCholRdiag + PE_MAX_DIM;
+constexpr int64_t kMwsScan = kMwsChol + kCholLen;  // segment sums [n_det][kScanSeg]
 constexpr int64_t kMwsTotal = kMwsScan + (int64_t)PE_MAX_DET * kScanSeg;
 constexpr int64_t kMwsKcut = kMwsSrc - 4;  // frozen cut of the metric (stored as double)
 

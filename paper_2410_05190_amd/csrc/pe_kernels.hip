@@ -534,8 +534,10 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
 #pragma unroll
         for (int a = 0; a < D; ++a)
             if (!(dist && a == 8)) logdet += log(L[a][a]);
-    A.chol[PE_MAX_DIM * PE_MAX_DIM] = logdet;
-    A.chol[PE_MAX_DIM * PE_MAX_DIM + 1] = ok ? 1.0 : 0.0;
+    A.chol[kCholLogdet] = logdet;
+    A.chol[kCholOk] = ok ? 1.0 : 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) A.chol[kCholRdiag + a] = ok ? 1.0 / L[a][a] : 0.0;
     // (L L^T) at the periodic coordinates (11-D: ra, psi, phic), for the image sum of log q
     if constexpr (D == 11) {
         constexpr int pidx[3] = {4, 7, 10};
@@ -547,7 +549,7 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
                 double gpq = 0.0;
 #pragma unroll
                 for (int r = 0; r < D; ++r) gpq += L[pidx[p]][r] * L[pidx[q]][r];
-                A.chol[PE_MAX_DIM * PE_MAX_DIM + 2 + w++] = ok ? gpq : 0.0;
+                A.chol[kCholG + w++] = ok ? gpq : 0.0;
             }
     }
     if (!ok) atomicOr(A.status, kStSingular);
@@ -576,7 +578,7 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
     double th0[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) th0[a] = A.theta0[a];
-    if (lc[PE_MAX_DIM * PE_MAX_DIM + 1] == 0.0) {
+    if (lc[kCholOk] == 0.0) {
 #pragma unroll
         for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th0[a];
         A.logq[i] = 0.0;
@@ -600,7 +602,7 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
         double s = z[r];
 #pragma unroll
         for (int c = r + 1; c < D; ++c) s -= lc[c * D + r] * y[c];
-        y[r] = s / lc[r * D + r];
+        y[r] = s * lc[kCholRdiag + r];
     }
     double th[D];
 #pragma unroll
@@ -632,11 +634,57 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int r = 0; r <= pidx[p]; ++r) a[p] = fma(lc[pidx[p] * D + r], z[r], a[p]);
-    const double* G = lc + PE_MAX_DIM * PE_MAX_DIM + 2;  // G00 G01 G02 G11 G12 G22
+    const double* G = lc + kCholG;  // G00 G01 G02 G11 G12 G22
     double mx = -INFINITY, acc = 0.0;
     constexpr int NIMG = (NP == 0) ? 1 : 27;
+    if constexpr (NP == 3) {
+        // Factorised image sum. With image k = (t_0, t_1, t_2), t in {-1, 0, 1}
+        // and o_p = -k0_p P_p, the shift is s_p = P_p t_p + o_p and
+        //   -qf/2 = -C/2 + sum_p v_p(t_p) - sum_{p<q} gam_pq t_p t_q,
+        //   C = |z|^2 + 2 o.a + o^T G o,  v_p(t) = -P_p t b_p - G_pp P_p^2 t^2 / 2,
+        //   b = a + G o,  gam_pq = G_pq P_p P_q,
+        // so each of the 27 terms is a product of three per-coordinate factors
+        // exp(v_p - V_p) <= 1 (V_p their largest exponent) and three pair
+        // factors exp(-+gam): 11 exponentials instead of 27. Taken when every
+        // |gam| <= 100, so that the pair factors stay within e^+-300 (a
+        // condition on the event's metric, uniform over the workgroup).
+        const double g00 = G[0], g01 = G[1], g02 = G[2], g11 = G[3], g12 = G[4], g22 = G[5];
+        const double gam01 = g01 * per[0] * per[1], gam02 = g02 * per[0] * per[2], gam12 = g12 * per[1] * per[2];
+        if (fabs(gam01) <= 100.0 && fabs(gam02) <= 100.0 && fabs(gam12) <= 100.0) {
+            const double o0 = -k0[0] * per[0], o1 = -k0[1] * per[1], o2 = -k0[2] * per[2];
+            const double go0 = g00 * o0 + g01 * o1 + g02 * o2;
+            const double go1 = g01 * o0 + g11 * o1 + g12 * o2;
+            const double go2 = g02 * o0 + g12 * o1 + g22 * o2;
+            const double C = zz + 2.0 * (o0 * a[0] + o1 * a[1] + o2 * a[2]) + (o0 * go0 + o1 * go1 + o2 * go2);
+            const double b[3] = {a[0] + go0, a[1] + go1, a[2] + go2};
+            const double gpp[3] = {g00, g11, g22};
+            double f[3][3], V = 0.0;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const double h = -0.5 * gpp[p] * per[p] * per[p];
+                const double vm = per[p] * b[p] + h, vp = -per[p] * b[p] + h;  // t = -1, +1
+                const double Vp = fmax(0.0, fmax(vm, vp));
+                f[p][0] = exp(vm - Vp);
+                f[p][1] = exp(-Vp);
+                f[p][2] = exp(vp - Vp);
+                V += Vp;
+            }
+            const double e01 = exp(-gam01), e02 = exp(-gam02), e12 = exp(-gam12);
+            const double x01[3] = {1.0 / e01, 1.0, e01}, x02[3] = {1.0 / e02, 1.0, e02}, x12[3] = {1.0 / e12, 1.0, e12};
+#pragma unroll
+            for (int t0 = 0; t0 < 3; ++t0)
+#pragma unroll
+                for (int t1 = 0; t1 < 3; ++t1) {
+                    const double f01 = f[0][t0] * f[1][t1] * x01[1 + (t0 - 1) * (t1 - 1)];
+#pragma unroll
+                    for (int t2 = 0; t2 < 3; ++t2)
+                        acc += f01 * f[2][t2] * x02[1 + (t0 - 1) * (t2 - 1)] * x12[1 + (t1 - 1) * (t2 - 1)];
+                }
+            mx = -0.5 * C + V;
+        }
+    }
 #pragma unroll 1
-    for (int m = 0; m < NIMG; ++m) {
+    for (int m = (acc > 0.0) ? NIMG : 0; m < NIMG; ++m) {
         double qf = zz;
         if (NP == 3) {
             const double s0 = ((double)(m % 3 - 1) - k0[0]) * per[0];
@@ -657,21 +705,23 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
             acc += exp(l - mx);
         }
     }
-    A.logq[i] = mx + log(acc) + lc[PE_MAX_DIM * PE_MAX_DIM] - 0.5 * (D - (dist ? 1 : 0)) * log(kTwoPi);
+    A.logq[i] = mx + log(acc) + lc[kCholLogdet] - 0.5 * (D - (dist ? 1 : 0)) * log(kTwoPi);
     A.logprior[i] = log_prior_of(ev, th);
 }
 
 // Blocks of 256 draws that each belong to one event (doff: block offsets).
-__global__ __launch_bounds__(256) void k_draw(const BatchHdr* __restrict__ hdr, const DrawArg* __restrict__ args,
+// At least 3 workgroups per CU: the register budget of 3 waves per SIMD (a few
+// registers spill; without the bound the compiler takes 211 and runs 2 waves).
+__global__ __launch_bounds__(256, 3) void k_draw(const BatchHdr* __restrict__ hdr, const DrawArg* __restrict__ args,
                                               const int64_t* __restrict__ doff) {
-    __shared__ double lc[PE_MAX_DIM * PE_MAX_DIM + 8];
+    __shared__ double lc[kCholLen];
     const int ne = hdr->ne;
     const int64_t nblk = doff[ne];
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         const int e = find_slot(doff, ne, b);
         const DrawArg& A = args[e];
         __syncthreads();  // the previous block's readers are done with lc
-        for (int q = threadIdx.x; q < PE_MAX_DIM * PE_MAX_DIM + 8; q += 256) lc[q] = A.chol[q];
+        for (int q = threadIdx.x; q < kCholLen; q += 256) lc[q] = A.chol[q];
         __syncthreads();
         const int64_t i = (b - doff[e]) * 256 + threadIdx.x;
         if (i < A.n) {
