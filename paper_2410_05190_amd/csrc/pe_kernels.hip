@@ -302,67 +302,101 @@ __device__ __forceinline__ void model_unit(const double* __restrict__ src, int d
 
 // Columns: coordinates 0..D-1 by central differences, except the phase column
 // (index DP-1 in 4-D, 10 in 11-D), which is i h(theta0). Block lb of the
-// event's nb blocks strides over the bins below the frozen cut; the detector
-// loop is not unrolled, so the register need does not grow with n_det.
+// event's nb blocks takes the tiles of kMetricTile bins lb, lb + nb, ... below
+// the frozen cut, in two steps with the whole workgroup on each:
+//   1. the derivative columns at every (bin, detector) of the tile, into LDS:
+//      task (column, bin, detector) with the bins fastest, so that a wave reads
+//      consecutive bin records and one source record;
+//   2. the products: thread (q, part) owns matrix entry q of the packed upper
+//      triangle and sums its weighted products over the bins part, part + NR, ...
+// The NR partial sums of each entry are added in a fixed order at the end, so
+// the block's partial does not depend on scheduling.
+constexpr int kMetricTile = 32;
+
+// Shared memory of the metric partial (one set for both parameter sets).
+struct MetricLds {
+    double ssrc[(2 * PE_MAX_DIM + 1) * kMetricSrcStride];  // the sources' records
+    double2 us[kMetricTile * PE_MAX_DET * kMetricMaxDp];  // derivative columns
+    double ps[kMetricTile * PE_MAX_DET];                  // 4 df / S
+    double red[256];
+};
+
 template <int D, int DP>
-__device__ __forceinline__ void metric_partial(const MetricArg& A, int lb, int nb) {
+__device__ __forceinline__ void metric_partial(const MetricArg& A, int lb, int nb, MetricLds& L) {
     constexpr int NG = DP * (DP + 1) / 2;
     constexpr int PH = (DP == D) ? D - 1 : D;  // phase column
+    constexpr int NS = 2 * (DP - 1) + 1;       // sources 0 .. NS-1 (the phase column uses source 0)
+    constexpr int NR = 256 / NG;               // threads per matrix entry
+    const int t = threadIdx.x;
     const double* mws = A.mws;
     const int64_t kc = (int64_t)mws[kMwsKcut];
-    const double* src = mws + kMwsSrc;
     const int64_t K = A.ec.K;
     const int nd = A.ec.n_det;
-    double den[D];
+    for (int w = t; w < NS * kMetricSrcStride; w += 256) L.ssrc[w] = mws[kMwsSrc + w];
+    // this thread's matrix entry (a, b), b >= a, and its share of the bins
+    const int q = t % NG, part = t / NG;
+    int qa = 0, qb = 0;
+    {
+        int r = q;
 #pragma unroll
-    for (int a = 0; a < D; ++a) den[a] = mws[kMwsDen + a];
-    double G[NG];
-#pragma unroll
-    for (int q = 0; q < NG; ++q) G[q] = 0.0;
-    for (int64_t k = (int64_t)lb * 256 + threadIdx.x; k < kc; k += (int64_t)nb * 256) {
-        const Rec64 r = A.tab[k];
-#pragma nounroll
-        for (int d = 0; d < nd; ++d) {
-            const double p = A.pw[(int64_t)d * K + k];
-            double ur[DP], ui[DP];
-#pragma unroll
-            for (int a = 0; a < DP; ++a) {
-                if (a == PH) {
-                    double hr, hi;
-                    model_unit(src, d, r, hr, hi);
-                    ur[a] = -hi;  // i h
-                    ui[a] = hr;
-                } else {
-                    double pr, pi_, mr, mi;
-                    model_unit(src + (2 * a + 1) * kMetricSrcStride, d, r, pr, pi_);
-                    model_unit(src + (2 * a + 2) * kMetricSrcStride, d, r, mr, mi);
-                    ur[a] = (pr - mr) / den[a];
-                    ui[a] = (pi_ - mi) / den[a];
-                }
+        for (int a = 0; a < DP; ++a) {
+            const int len = DP - a;
+            if (r >= 0 && r < len) {
+                qa = a;
+                qb = a + r;
             }
-            int q = 0;
-#pragma unroll
-            for (int a = 0; a < DP; ++a)
-#pragma unroll
-                for (int b = a; b < DP; ++b) {
-                    G[q] = fma(p, ur[a] * ur[b] + ui[a] * ui[b], G[q]);
-                    ++q;
-                }
+            r -= len;
         }
     }
-    // wave butterfly, then the four waves through LDS
-    __shared__ double sh[4][kMetricNG];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-        double v = G[q];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) sh[wv][q] = v;
-    }
+    double acc = 0.0;
     __syncthreads();
-    for (int q = threadIdx.x; q < NG; q += blockDim.x)
-        A.mws[kMwsPart + (int64_t)lb * kMetricNG + q] = (sh[0][q] + sh[1][q]) + (sh[2][q] + sh[3][q]);
+    const int nbd = nd * kMetricTile;  // (bin, detector) pairs of a tile, detector-major
+    for (int64_t k0 = (int64_t)lb * kMetricTile; k0 < kc; k0 += (int64_t)nb * kMetricTile) {
+        // 1. derivative columns
+#pragma unroll 1
+        for (int w = t; w < nbd * DP; w += 256) {
+            const int c = w / nbd, jd = w - c * nbd;
+            const int j = jd % kMetricTile, d = jd / kMetricTile;
+            const int64_t k = k0 + j;
+            double2 u = make_double2(0.0, 0.0);
+            if (k < kc) {
+                const Rec64 r = A.tab[k];
+                if (c == PH) {
+                    double hr, hi;
+                    model_unit(L.ssrc, d, r, hr, hi);
+                    u = make_double2(-hi, hr);  // i h(theta0)
+                } else {
+                    double pr, pi_, mr, mi;
+                    model_unit(L.ssrc + (2 * c + 1) * kMetricSrcStride, d, r, pr, pi_);
+                    model_unit(L.ssrc + (2 * c + 2) * kMetricSrcStride, d, r, mr, mi);
+                    const double den = mws[kMwsDen + c];
+                    u = make_double2((pr - mr) / den, (pi_ - mi) / den);
+                }
+            }
+            L.us[jd * DP + c] = u;
+        }
+        for (int w = t; w < nbd; w += 256) {
+            const int j = w % kMetricTile, d = w / kMetricTile;
+            const int64_t k = k0 + j;
+            L.ps[w] = (k < kc) ? A.pw[(int64_t)d * K + k] : 0.0;
+        }
+        __syncthreads();
+        // 2. products of this thread's entry over its bins
+        if (part < NR) {
+            for (int jd = part; jd < nbd; jd += NR) {
+                const double2 ua = L.us[jd * DP + qa], ub = L.us[jd * DP + qb];
+                acc = fma(L.ps[jd], ua.x * ub.x + ua.y * ub.y, acc);
+            }
+        }
+        __syncthreads();
+    }
+    L.red[t] = acc;
+    __syncthreads();
+    if (t < NG) {
+        double v = 0.0;
+        for (int r = 0; r < NR; ++r) v += L.red[t + r * NG];
+        A.mws[kMwsPart + (int64_t)lb * kMetricNG + t] = v;
+    }
     __syncthreads();
 }
 
@@ -371,6 +405,7 @@ __device__ __forceinline__ void metric_partial(const MetricArg& A, int lb, int n
 __global__ __launch_bounds__(256) void k_metric_partial(const BatchHdr* __restrict__ hdr,
                                                         const MetricArg* __restrict__ args,
                                                         const int64_t* __restrict__ moff) {
+    __shared__ MetricLds lds;
     const int ne = hdr->ne;
     const int64_t nblk = moff[ne];
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
@@ -379,9 +414,9 @@ __global__ __launch_bounds__(256) void k_metric_partial(const BatchHdr* __restri
         const int lb = (int)(b - moff[e]);
         const int nb = (int)(moff[e + 1] - moff[e]);
         if (A.ec.params == PE_PARAMS_4D)
-            metric_partial<4, 5>(A, lb, nb);
+            metric_partial<4, 5>(A, lb, nb, lds);
         else
-            metric_partial<11, 11>(A, lb, nb);
+            metric_partial<11, 11>(A, lb, nb, lds);
     }
 }
 
