@@ -414,10 +414,16 @@ constexpr double kDmDelta = 8.0;   // largest change of ln(integrand) across a p
 constexpr double kDmCut = 45.0;    // walk ends below e^-45 of the maximum
 constexpr int kDmMaxPanels = 400;  // per walk; reached only by non-finite input
 
+// NL lanes (consecutive, NL a power of two) may share one draw: lane `sub`
+// evaluates the nodes sub, sub + NL, ... of every panel, while all of them walk
+// the same panels, decided from values that every lane computes alike (the
+// panel end points and the starting points); at the end their scaled sums are
+// combined by a butterfly of NL shuffles in a fixed order.
 struct DmState {
     double a, b;
     bool ex;
-    double G, S;  // running maximum of ln(integrand); sum scaled by exp(-G)
+    double G, S;  // this lane's running maximum of ln(integrand); its sum scaled by exp(-G)
+    double W;     // the walk's reference maximum (end points only; equal on every lane)
 };
 
 __device__ __forceinline__ double dm_g(const DmState& q, double x) {
@@ -425,10 +431,11 @@ __device__ __forceinline__ double dm_g(const DmState& q, double x) {
     return 1.0986122886681098 - 4.0 * log(x) + phi - q.b * x * x;  // ln 3 - 4 ln x + ...
 }
 
-__device__ __forceinline__ void dm_panel(DmState& q, double lo, double hi) {
+template <int NL>
+__device__ __forceinline__ void dm_panel(DmState& q, double lo, double hi, int sub) {
     const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
 #pragma unroll 1
-    for (int k = 0; k < 16; ++k) {
+    for (int k = sub; k < 16; k += NL) {
         const double t = (k < 8) ? -kGlX[k] : kGlX[k - 8];
         const double v = dm_g(q, c + h * t);
         if (v > q.G) {
@@ -441,7 +448,9 @@ __device__ __forceinline__ void dm_panel(DmState& q, double lo, double hi) {
 
 // Walk from x0 (where g = g0) in direction dir until g falls below the cut
 // (while decreasing) or x reaches stop; returns the last x.
-__device__ __forceinline__ double dm_walk(DmState& q, double x0, double g0, int dir, double stop, double w) {
+template <int NL>
+__device__ __forceinline__ double dm_walk(DmState& q, double x0, double g0, int dir, double stop, double w,
+                                          int sub) {
 #pragma unroll 1
     for (int p = 0; p < kDmMaxPanels; ++p) {
         double x1 = x0, g1 = g0;
@@ -458,9 +467,10 @@ __device__ __forceinline__ double dm_walk(DmState& q, double x0, double g0, int 
             if (fabs(g1 - g0) <= kDmDelta) break;
             w *= 0.5;
         }
-        dm_panel(q, fmin(x0, x1), fmax(x0, x1));
+        dm_panel<NL>(q, fmin(x0, x1), fmax(x0, x1), sub);
+        q.W = fmax(q.W, g1);
         if (x1 == stop) return x1;
-        if (g1 < q.G - kDmCut && g1 < g0) return x1;
+        if (g1 < q.W - kDmCut && g1 < g0) return x1;
         x0 = x1;
         g0 = g1;
         w *= 2.0;
@@ -468,9 +478,10 @@ __device__ __forceinline__ double dm_walk(DmState& q, double x0, double g0, int 
     return x0;
 }
 
-__device__ __forceinline__ double log_dist_marg(double a, double b, bool ex) {
+template <int NL>
+__device__ __forceinline__ double log_dist_marg(double a, double b, bool ex, int sub) {
     if (!(b > 0.0)) return (a == 0.0) ? 0.0 : NAN;  // H = 0 only with Z = 0 (no bins below the cut)
-    DmState q{a, b, ex, -INFINITY, 0.0};
+    DmState q{a, b, ex, -INFINITY, 0.0, -INFINITY};
     double xs = 1.0, ae = a;
 #pragma unroll 1
     for (int it = 0; it < 64; ++it) {
@@ -487,13 +498,22 @@ __device__ __forceinline__ double log_dist_marg(double a, double b, bool ex) {
     }
     const double g1 = dm_g(q, 1.0);
     const double gs = (xs > 1.0) ? dm_g(q, xs) : g1;
-    q.G = fmax(g1, gs);
+    q.W = fmax(g1, gs);
+    q.G = q.W;
     const double w0 = fmin(1.0 / sqrt(2.0 * b), 0.5 * xs);
-    dm_walk(q, xs, gs, +1, INFINITY, w0);
+    dm_walk<NL>(q, xs, gs, +1, INFINITY, w0, sub);
     double xl = 1.0;
-    if (xs > 1.0) xl = dm_walk(q, xs, gs, -1, 1.0, w0);
-    if (xl > 1.0 && g1 >= q.G - kDmCut) dm_walk(q, 1.0, g1, +1, xl, w0);
-    return q.G + log(q.S);
+    if (xs > 1.0) xl = dm_walk<NL>(q, xs, gs, -1, 1.0, w0, sub);
+    if (xl > 1.0 && g1 >= q.W - kDmCut) dm_walk<NL>(q, 1.0, g1, +1, xl, w0, sub);
+    double G = q.G, S = q.S;
+#pragma unroll
+    for (int o = 1; o < NL; o <<= 1) {
+        const double Go = __shfl_xor(G, o), So = __shfl_xor(S, o);
+        const double Gm = fmax(G, Go);
+        S = S * exp(G - Gm) + So * exp(Go - Gm);
+        G = Gm;
+    }
+    return G + log(S);
 }
 
 // ln L from Z and H (Eq. 3): explicit phase Re Z - H/2, marginalised phase
@@ -504,9 +524,11 @@ __device__ __forceinline__ double loglike_phase(const EvConst& ev, double zr, do
 
 // The same, or for distance-marginalised events (Z, H at dl_max) the integral
 // over the distance prior.
-__device__ __forceinline__ double loglike_of(const EvConst& ev, double zr, double zi, double h) {
+// NL lanes share the draw (see log_dist_marg); every one of them returns ln L.
+template <int NL>
+__device__ __forceinline__ double loglike_of(const EvConst& ev, double zr, double zi, double h, int sub) {
     const bool ex = (ev.phase == PE_PHASE_EXPLICIT);
-    if (ev.dist) return log_dist_marg(ex ? zr : hypot(zr, zi), 0.5 * h, ex);
+    if (ev.dist) return log_dist_marg<NL>(ex ? zr : hypot(zr, zi), 0.5 * h, ex, sub);
     return loglike_phase(ev, zr, zi, h);
 }
 

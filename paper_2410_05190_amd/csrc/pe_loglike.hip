@@ -684,21 +684,27 @@ __global__ __launch_bounds__(256) void k_b_finalize(BatchHdr* __restrict__ hdr, 
 
 // Distance-marginalised events: ln L of each live draw from the Z that the
 // finalize (or the FP64 re-evaluation) left in the first partial slot of its
-// position and H, integrated over the distance prior. Kept out of the finalize
-// so that the finalize's register budget (and occupancy) stays that of the
-// plain likelihood; blocks of other events return at once.
+// position and H, integrated over the distance prior by kDistLanes lanes per
+// draw (a block covers a quarter of a finalize block's 256 positions). Kept out
+// of the finalize so that the finalize's register budget (and occupancy) stays
+// that of the plain likelihood; blocks of other events return at once.
+constexpr int kDistLanes = 4;
+
 __global__ __launch_bounds__(256) void k_b_dist(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                 const int64_t* __restrict__ foff) {
     const int ne = hdr->ne;
-    const int64_t nblk = foff[ne];
+    const int64_t nblk = foff[ne] * kDistLanes;
+    const int sub = threadIdx.x % kDistLanes;
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
-        const int e = find_slot(foff, ne, b);
+        const int64_t fb = b / kDistLanes;
+        const int e = find_slot(foff, ne, fb);
         const EvDev& E = evs[e];
         if (!E.ec.dist) continue;
-        const int64_t j = (b - foff[e]) * 256 + threadIdx.x;
-        if (j >= E.plan->n_active) continue;
+        const int64_t j = (fb - foff[e]) * 256 + (b - fb * kDistLanes) * (256 / kDistLanes) + threadIdx.x / kDistLanes;
+        if (j >= E.plan->n_active) continue;  // the same for the draw's lanes
         const double2 z = E.partial[j];
-        E.loglike[E.idx[j]] = loglike_of(E.ec, z.x, z.y, E.hh[j]);
+        const double ll = loglike_of<kDistLanes>(E.ec, z.x, z.y, E.hh[j], sub);
+        if (sub == 0) E.loglike[E.idx[j]] = ll;
     }
 }
 
@@ -850,7 +856,7 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
         } else {
             k_b_finalize<false><<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2, redo);
         }
-        if (any_dist) k_b_dist<<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2);
+        if (any_dist) k_b_dist<<<grid_for(finalize_blocks * kDistLanes), 256, 0, st>>>(b.hdr, evs, b.off2);
     }
     return hipGetLastError();
 }

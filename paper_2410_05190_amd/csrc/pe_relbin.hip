@@ -296,8 +296,9 @@ __global__ __launch_bounds__(256) void k_rb_ll(RbArg a) {
         zr += __shfl_xor(zr, o);
         zi += __shfl_xor(zi, o);
     }
-    if (i >= a.n || sg != 0) return;
+    if (i >= a.n) return;  // the same for the draw's lanes, as is ok
     if (!ok) {
+        if (sg != 0) return;
         a.loglike[i] = -INFINITY;
         if (a.aux) {
             a.aux[3 * i] = 0.0;
@@ -306,7 +307,10 @@ __global__ __launch_bounds__(256) void k_rb_ll(RbArg a) {
         }
         return;
     }
-    const double ll = loglike_of(ev, zr, zi, h);
+    // the butterfly left the same sums on every lane of the draw, which share
+    // the distance integral when there is one
+    const double ll = loglike_of<kRbSeg>(ev, zr, zi, h, sg);
+    if (sg != 0) return;
     a.loglike[i] = ll;
     if (a.aux) {
         a.aux[3 * i] = zr;
