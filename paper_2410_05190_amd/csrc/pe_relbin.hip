@@ -194,15 +194,17 @@ struct RbArg {
     int n_edges;
 };
 
-// kRbSeg adjacent lanes per draw, each over one contiguous quarter of the
-// bins (more waves in flight than one lane per draw); the draw's phase
-// polynomial at an edge is evaluated once for all detectors. Partial sums
-// are combined by shuffles and written by the first lane of the draw.
+// A workgroup holds 64 draws (one per lane) in each of its kRbSeg waves; wave
+// sg sums its draws over the sg-th contiguous share of the bins, so the bin
+// index is uniform across the wave and every per-bin table entry (edge record,
+// fiducial phase, bin coefficients) arrives through scalar loads. The draw's
+// phase polynomial at an edge is evaluated once for all detectors. The waves'
+// partial sums are combined through shared memory in a fixed order.
 constexpr int kRbSeg = 4;
 
 template <int ND>
-__device__ __forceinline__ void rb_segment(const RbArg& a, const Src& s, const PhaseCoef& pc, int64_t kc, int b0,
-                                           int b1, double& zr, double& zi) {
+__device__ __forceinline__ void rb_segment(const RbArg& a, const Src& s, const PhaseCoef& pc, int64_t kc, int kcmax,
+                                           int b0, int b1, double& zr, double& zi) {
     const int64_t K = a.ec.K;
     const int nb = a.n_edges - 1;
     double tau[ND], ur[ND], ui[ND], r0r[ND], r0i[ND];
@@ -219,7 +221,10 @@ __device__ __forceinline__ void rb_segment(const RbArg& a, const Src& s, const P
             r0i[d] = -sn;
         }
     }
-    for (int b = b0; b < b1 && a.kk[b] < kc; ++b) {
+    // the wave walks its bins up to the largest cut among its draws; a lane
+    // adds bin b only while b starts below its own cut
+    for (int b = b0; b < b1 && a.kk[b] < kcmax; ++b) {
+        const bool live = a.kk[b] < kc;
         const double* er = a.erec + 4 * (b + 1);
         const double psi = psi_turns(pc.A, pc.B5, pc.B6, er[1], er[2], er[3]);
         const double inv = 1.0 / (er[0] - a.erec[4 * b]);
@@ -230,20 +235,19 @@ __device__ __forceinline__ void rb_segment(const RbArg& a, const Src& s, const P
             sincos_turns(fract64(fma(er[0], tau[d], psi) - a.phi0[(int64_t)d * a.n_edges + b + 1]), sn, cs);
             const double r1r = cs, r1i = -sn;
             const double sr = (r1r - r0r[d]) * inv, si = (r1i - r0i[d]) * inv;
-            double2 A0, A1;
-            if (full) {
-                const double2* Ad = a.A + ((int64_t)d * nb + b) * 2;
-                A0 = Ad[0];
-                A1 = Ad[1];
-            } else {
+            const double2* Ad = a.A + ((int64_t)d * nb + b) * 2;
+            double2 A0 = Ad[0], A1 = Ad[1];
+            if (!full && live) {
                 const double2* Pd = a.P + (int64_t)d * (K + 1) * 2;
                 const double2 p0 = Pd[2 * kc], q0 = Pd[2 * a.kk[b]];
                 const double2 p1 = Pd[2 * kc + 1], q1 = Pd[2 * a.kk[b] + 1];
                 A0 = make_double2(p0.x - q0.x, p0.y - q0.y);
                 A1 = make_double2(p1.x - q1.x, p1.y - q1.y);
             }
-            ur[d] += r0r[d] * A0.x - r0i[d] * A0.y + sr * A1.x - si * A1.y;
-            ui[d] += r0r[d] * A0.y + r0i[d] * A0.x + sr * A1.y + si * A1.x;
+            if (live) {
+                ur[d] += r0r[d] * A0.x - r0i[d] * A0.y + sr * A1.x - si * A1.y;
+                ui[d] += r0r[d] * A0.y + r0i[d] * A0.x + sr * A1.y + si * A1.x;
+            }
             r0r[d] = r1r;
             r0i[d] = r1i;
         }
@@ -255,50 +259,53 @@ __device__ __forceinline__ void rb_segment(const RbArg& a, const Src& s, const P
     }
 }
 
-__global__ __launch_bounds__(256) void k_rb_ll(RbArg a) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t i = t / kRbSeg;
-    const int sg = (int)(t - i * kRbSeg);
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Four workgroups per CU: the register budget of four waves per SIMD (a few
+// values spill; the kernel waits on FP64 chains and gains more from the waves).
+__global__ __launch_bounds__(256, 4) void k_rb_ll(RbArg a) {
+    __shared__ double sz[kRbSeg][64][2];
+    const int lane = threadIdx.x & 63;
+    const int sg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wave's share of the bins
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     const EvConst& ev = a.ec;
     double zr = 0.0, zi = 0.0, h = 0.0;
     int ok = 0;
+    int64_t kc = 0;
+    Src s = {};
+    PhaseCoef pc = {};
     if (i < a.n) {
         double th[PE_MAX_DIM];
 #pragma unroll
         for (int q = 0; q < PE_MAX_DIM; ++q) th[q] = (q < ev.dim) ? a.theta[(int64_t)q * a.n + i] : 0.0;
         likelihood_distance(ev, th);
-        Src s;
         ok = source_from_theta(ev, th, s);
         if (ok) {
-            PhaseCoef pc;
             phase_coeffs(s, pc);
-            const int64_t K = ev.K;
-            const int64_t kc = kcut_of(ev, s.fisco);
-#pragma unroll
-            for (int d = 0; d < PE_MAX_DET; ++d) {  // fixed bound: the per-detector arrays stay in registers
-                if (d >= ev.n_det) break;
-                h += (s.rre[d] * s.rre[d] + s.rim[d] * s.rim[d]) * a.pfx[(int64_t)d * (K + 1) + kc];
-            }
-            const int nb = a.n_edges - 1;
-            const int b0 = (int)((int64_t)sg * nb / kRbSeg), b1 = (int)((int64_t)(sg + 1) * nb / kRbSeg);
-            if (b0 < b1 && a.kk[b0] < kc) {
-                switch (ev.n_det) {
-                    case 1: rb_segment<1>(a, s, pc, kc, b0, b1, zr, zi); break;
-                    case 2: rb_segment<2>(a, s, pc, kc, b0, b1, zr, zi); break;
-                    case 3: rb_segment<3>(a, s, pc, kc, b0, b1, zr, zi); break;
-                    default: rb_segment<4>(a, s, pc, kc, b0, b1, zr, zi); break;
-                }
-            }
+            kc = kcut_of(ev, s.fisco);
         }
     }
-#pragma unroll
-    for (int o = 1; o < kRbSeg; o <<= 1) {
-        zr += __shfl_xor(zr, o);
-        zi += __shfl_xor(zi, o);
+    const int kcmax = wave_max_i(ok ? (int)kc : 0);
+    const int nb = a.n_edges - 1;
+    const int b0 = (int)((int64_t)sg * nb / kRbSeg), b1 = (int)((int64_t)(sg + 1) * nb / kRbSeg);
+    if (kcmax > 0 && b0 < b1 && a.kk[b0] < kcmax) {
+        // lanes without a draw (or out of support) follow with kc = 0: they add nothing
+        switch (ev.n_det) {
+            case 1: rb_segment<1>(a, s, pc, kc, kcmax, b0, b1, zr, zi); break;
+            case 2: rb_segment<2>(a, s, pc, kc, kcmax, b0, b1, zr, zi); break;
+            case 3: rb_segment<3>(a, s, pc, kc, kcmax, b0, b1, zr, zi); break;
+            default: rb_segment<4>(a, s, pc, kc, kcmax, b0, b1, zr, zi); break;
+        }
     }
-    if (i >= a.n) return;  // the same for the draw's lanes, as is ok
+    sz[sg][lane][0] = zr;
+    sz[sg][lane][1] = zi;
+    __syncthreads();
+    if (sg != 0 || i >= a.n) return;
     if (!ok) {
-        if (sg != 0) return;
         a.loglike[i] = -INFINITY;
         if (a.aux) {
             a.aux[3 * i] = 0.0;
@@ -307,10 +314,15 @@ __global__ __launch_bounds__(256) void k_rb_ll(RbArg a) {
         }
         return;
     }
-    // the butterfly left the same sums on every lane of the draw, which share
-    // the distance integral when there is one
-    const double ll = loglike_of<kRbSeg>(ev, zr, zi, h, sg);
-    if (sg != 0) return;
+    zr = (sz[0][lane][0] + sz[1][lane][0]) + (sz[2][lane][0] + sz[3][lane][0]);
+    zi = (sz[0][lane][1] + sz[1][lane][1]) + (sz[2][lane][1] + sz[3][lane][1]);
+    const int64_t K = ev.K;
+#pragma unroll
+    for (int d = 0; d < PE_MAX_DET; ++d) {  // fixed bound: the per-detector arrays stay in registers
+        if (d >= ev.n_det) break;
+        h += (s.rre[d] * s.rre[d] + s.rim[d] * s.rim[d]) * a.pfx[(int64_t)d * (K + 1) + kc];
+    }
+    const double ll = loglike_of<1>(ev, zr, zi, h, 0);
     a.loglike[i] = ll;
     if (a.aux) {
         a.aux[3 * i] = zr;
@@ -338,7 +350,7 @@ pe_status_t run_relbin(pe_event_s* ev, const double* theta, int64_t n, double* l
     a.A = ev->rb_A;
     a.P = ev->rb_P;
     a.n_edges = ev->rb_n;
-    k_rb_ll<<<nblk(n * kRbSeg), 256, 0, st>>>(a);
+    k_rb_ll<<<(unsigned)((n + 63) / 64), 64 * kRbSeg, 0, st>>>(a);
     PE_HIP(hipGetLastError());
     return PE_OK;
 }
