@@ -96,7 +96,8 @@ __device__ __forceinline__ void block_bucket_range(int bk, int* sh, int& lo, int
 // the events in their prologue). The draws of an event crowd into few buckets,
 // so each block counts its own in shared memory over its bucket range and adds
 // the counts to the event's histogram once per bucket.
-__global__ __launch_bounds__(256) void k_b_support(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+// (at least five workgroups per CU: five waves per SIMD)
+__global__ __launch_bounds__(256, 5) void k_b_support(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                    const int64_t* __restrict__ poff) {
     __shared__ int lh[kBuckets];
     __shared__ int sh[8];
