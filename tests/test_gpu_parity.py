@@ -187,6 +187,41 @@ def test_draw_parity():
         np.testing.assert_allclose(lp[fin], lp_o[fin], rtol=0, atol=1e-9)
 
 
+@pytest.mark.parametrize("couple", [False, True])
+def test_draw_parity_factorised_image_sum(couple):
+    """Broad periodic coordinates (ra, psi, phic with unit precision, so that neighbouring images
+    carry weight), with and without couplings between them: every pair term |g_pq P_p P_q| stays
+    below 100, which is where the draw kernel sums the 27 images as products of per-coordinate and
+    pair factors instead of one exponential per image. log q and theta against the oracle."""
+    torch_cuda()
+    b = build_event(1, 2, n_bins=20000)
+    g = np.diag(np.diag(b.ev.metric(b.theta_inj)))
+    pidx = [4, 7, 10]
+    block = np.array([[1.0, 0.3, 0.0], [0.3, 1.0, 0.5], [0.0, 0.5, 1.0]]) if couple else np.eye(3)
+    g[np.ix_(pidx, pidx)] = block
+    per = np.array([2 * math.pi, math.pi, 2 * math.pi])
+    gam = block * np.outer(per, per)
+    assert np.abs(gam - np.diag(np.diag(gam))).max() <= 100.0
+    n = 4001
+    rc, th_o, lq_o, lp_o = b.ev.draw(b.theta_inj, g, 31337, 2, n)
+    assert rc == 0
+    ev, data, psd = upload_event(b)
+    th, lq, lp = ev.draw(dev(b.theta_inj), dev(g), 31337, 2, n)
+    ev.status()
+    th, lq, lp = host(th), host(lq), host(lp)
+    dth = th - th_o
+    for i, P in zip(pidx, per):
+        dth[i] = (dth[i] + P / 2) % P - P / 2
+    sd = np.sqrt(np.diag(np.linalg.inv(g)))
+    err = np.max(np.abs(dth) / sd[:, None])
+    note(f"factorised image sum (couplings {couple}): max |dtheta|/sd {err:.2e}, logq {np.abs(lq - lq_o).max():.2e}")
+    assert err < 1e-9
+    np.testing.assert_allclose(lq, lq_o, rtol=0, atol=1e-8)
+    fin = np.isfinite(lp_o)
+    assert np.array_equal(fin, np.isfinite(lp))
+    np.testing.assert_allclose(lp[fin], lp_o[fin], rtol=0, atol=1e-9)
+
+
 def test_weights_parity_and_identities():
     torch = torch_cuda()
     rng = np.random.default_rng(9)
