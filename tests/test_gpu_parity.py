@@ -1,7 +1,7 @@
 """GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on the same
 seeded inputs (element by element), plus edge cases and error paths.
 
-Tolerances (derivations in the design doc):
+Tolerances:
   - FP64 path: |d ln L| <= 32 u Phi_N(f_lo) sum_k |t_k| (gpu_util.fp64_tol: both sides round the
     phase differently by ~u |Phi| per bin, summed coherently over the band), relative 1e-10 on
     Z and H;
