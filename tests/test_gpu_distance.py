@@ -186,3 +186,30 @@ def test_loud_and_quiet_events_and_a_draw_without_bins(snr, zero_noise):
     note(f"distance-marginalised SNR {snr}: ln L_D at the injection {ll_o[0]:.3f}, max |dlnL| {d.max():.2e}")
     assert np.all(d <= tol)
     ev.close()
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 257])
+def test_ragged_batches(n):
+    """Batches that end inside a workgroup of the distance kernel (64 draws per block, four lanes
+    each) and of the relative-binning kernel (64 draws per block): every path against the oracle."""
+    torch_cuda()
+    b, _ = _events(1, 7, 20000)
+    ev, data, psd = upload_event(b)
+    g = b.ev.metric(b.theta_inj)
+    rc, th, lq, lp = b.ev.draw(b.theta_inj, g, 77, 3, n)
+    ll_o = b.ev.loglike(th, n_threads=8)
+    f = np.isfinite(ll_o)
+    ll64 = host(ev.loglike(dev(th), precision=binding.PE_PREC_FP64))
+    ls = host(ev.loglike(dev(th), precision=binding.PE_PREC_SPLIT))
+    assert np.array_equal(np.isfinite(ll64), f) and np.array_equal(np.isfinite(ls), f)
+    tol = fp64_tol(b) + 1e-9 * np.maximum(1.0, np.abs(ll_o[f]))
+    assert np.all(np.abs(ll64[f] - ll_o[f]) <= tol)
+    assert np.all(np.abs(ls[f] - ll_o[f]) <= 1e-3)
+    ev.relbin_setup(dev(b.theta_inj), 0.03)
+    e = ev.relbin_edges()
+    lr = host(ev.loglike(dev(th), precision=binding.PE_PREC_RELBIN))
+    lr_o, zr_o = b.ev.relbin_loglike(b.theta_inj, e, th, return_zh=True)
+    assert np.array_equal(np.isfinite(lr), f)
+    if f.any():
+        np.testing.assert_allclose(lr[f], lr_o[f], rtol=0, atol=1e-8 * np.abs(zr_o[f]).max())
+    ev.close()
