@@ -22,21 +22,23 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU issue model of the hot-loop kernels, in lane-cycles of the minimal
-# instruction sequence: the phase polynomial (10 FP64 ops) is shared by the
-# detectors of a bin; each term (draw, detector, bin) of the split kernel costs
-# FP64 FMA + fract, FP64->FP32 convert, FP32 add and two FP32 FMAs at full rate
-# plus v_sin_f32 and v_cos_f32, which issue at half rate on gfx950 (the counters
-# give SQ_ACTIVE_INST_VALU - SQ_INSTS_VALU = SQ_INSTS_VALU_TRANS_F32). The FP64
-# kernel's term: FMA + fract, the 26-op FP64 sincos, four FMAs.
+# VALU issue model of the hot-loop kernels, in issue slots (lane-cycles) of the
+# minimal instruction sequence: the phase polynomial (10 FP64 ops) is shared by
+# the detectors of a bin; each term (draw, detector, bin) of the split kernel
+# costs FP64 FMA + fract, FP64->FP32 convert, FP32 add, two FP32 FMAs and
+# v_sin_f32 + v_cos_f32, one slot each. The transcendentals hold their unit one
+# cycle longer (SQ_ACTIVE_INST_VALU - SQ_INSTS_VALU = SQ_INSTS_VALU_TRANS_F32),
+# but that cycle overlaps the instructions that follow: the kernel issues more
+# than one slot per cycle per CU if it is charged two. The FP64 kernel's term:
+# FMA + fract, the 26-op FP64 sincos, four FMAs.
 PSI_OPS_PER_DRAW_BIN = 10
-SPLIT_OPS_PER_TERM = 6 + 2 * 2
+SPLIT_OPS_PER_TERM = 6 + 2
 FP64_OPS_PER_TERM = 2 + 26 + 4
 # HBM bytes per launch of the split kernel at the benchmark shape (config 1, automatic
 # groups), from rocprofv3 FETCH_SIZE x 1.9999 + WRITE_SIZE x 1.0 (KiB per dispatch), the
 # factors read off a 1 GiB device-to-device copy in the same runs (profiles/
 # loglike_split_config1.md); None when the kernel has changed since the counters were taken.
-SPLIT_TRAFFIC_BYTES = 751939667
+SPLIT_TRAFFIC_BYTES = 528995276
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 
 

@@ -9,8 +9,9 @@
 //   k_b_coeffs    per live draw: phase polynomial, delays, responses, (h|h)
 //   k_b_split / k_b_f64   hot loop: persistent workgroups take (event, tile of
 //                 256 draws, group of frequency chunks) items off one queue;
-//                 lanes = draws; the bin record is wave-uniform (scalar loads)
-//                 and reused by the 64 draws of a wave and the 256 of a workgroup
+//                 lanes = draws; the bin records are staged in LDS (split) or
+//                 read through scalar loads (FP64), and each is reused by the
+//                 64 draws of a wave and the 256 of a workgroup
 //   k_b_finalize  fixed-order combine of the group partials, ln L
 //   k_b_dist      distance-marginalised events: ln L integrated over dL
 //
@@ -493,8 +494,21 @@ __device__ __forceinline__ void item_setup(const EvDev& E, int nact, int tile, i
     wmax = wave_max(valid ? kc : 0);
 }
 
+// One item of the split hot loop. The workgroup stages the bin records of its
+// chunks in LDS (pieces of kStage bins, 16-byte coalesced loads by all 256
+// threads), and each wave reads them back with broadcast LDS loads: every lane
+// of a wave needs the same record at the same time. Sums: FP32 over blocks of
+// kBlk bins, folded into FP64 accumulators (an FP64 add costs one issue slot,
+// as an FP32 one does without packed math). Blocks sit on multiples of kBlk
+// (chunks start on one), and a lane folds a block only if the block starts
+// below its own cut, so a draw's operations do not depend on the draws sharing
+// its wave. The workgroup walks each chunk up to the largest cut among its
+// four waves; a wave computes only below its own largest cut.
+constexpr int kStage = 256;
+
 template <int NDET>
-__device__ __forceinline__ void split_item(const EvDev& E, const EvPlan& p, int tile, int g) {
+__device__ __forceinline__ void split_item(const EvDev& E, const EvPlan& p, int tile, int g, Rec32* srec,
+                                           int* sred) {
     int j, kc, wmin, wmax;
     bool valid;
     DrawRow row;
@@ -502,55 +516,63 @@ __device__ __forceinline__ void split_item(const EvDev& E, const EvPlan& p, int 
     item_setup<NDET>(E, p.n_active, tile, j, valid, row, tau, kc, wmin, wmax);
     const Rec32* tab = E.rec32;
     const int K = (int)E.ec.K;
-    // FP32 sums over blocks of kBlk bins, folded into FP64 accumulators (an FP64
-    // add costs one issue slot, as an FP32 one does without packed math).
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sred[wv] = wmax;
+    __syncthreads();
+    const int gmax = max(max(sred[0], sred[1]), max(sred[2], sred[3]));
     double sr[NDET], si[NDET];
 #pragma unroll
     for (int d = 0; d < NDET; ++d) sr[d] = si[d] = 0.0;
-    // Blocks of kBlk bins sit on multiples of kBlk (chunks start on one), and a
-    // lane folds a block only if the block starts below its own cut: a draw's
-    // operations do not depend on the draws sharing its wave.
     for (int c = g; c < p.n_fine; c += p.n_groups) {
         const int k0 = c * p.fine;
-        if (k0 >= wmax) break;  // this and the later chunks lie above every cut of the wave
+        if (k0 >= gmax) break;  // uniform over the workgroup
         const int k1 = min(k0 + p.fine, K);
-        // [k0, kA): whole blocks below every lane's cut; [kA, kB): masked blocks
-        const int kA = k0 + (max(0, min(wmin, k1) - k0) / kBlk) * kBlk;
-        const int kB = max(kA, min(k1, wmax));
-        int kb = k0;
-        for (; kb < kA; kb += kBlk) {
-            float br[NDET], bi[NDET];
+        const bool on = k0 < wmax;  // this wave has cuts above the chunk's start
+        const int kA = on ? k0 + (max(0, min(wmin, k1) - k0) / kBlk) * kBlk : k0;
+        const int kB = on ? max(kA, min(k1, wmax)) : k0;
+        const int kl = min(k1, gmax);
+        for (int ks = k0; ks < kl; ks += kStage) {
+            const int ke = min(ks + kStage, kl);
+            __syncthreads();  // the previous piece has been read
+            const uint4* src = (const uint4*)(tab + ks);
+            uint4* dst = (uint4*)srec;
+            for (int q = threadIdx.x; q < (ke - ks) * (int)(sizeof(Rec32) / 16); q += 256) dst[q] = src[q];
+            __syncthreads();
+            for (int kb = ks; kb < min(ke, kA); kb += kBlk) {
+                float br[NDET], bi[NDET];
 #pragma unroll
-            for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
+                for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
 #pragma unroll 4
-            for (int q = 0; q < kBlk; ++q) {
-                const Rec32 r = load_const(tab + kb + q);
-                bin_split<NDET, false>(r, row, tau, true, br, bi);
-            }
-#pragma unroll
-            for (int d = 0; d < NDET; ++d) {
-                sr[d] += (double)br[d];
-                si[d] += (double)bi[d];
-            }
-        }
-        for (; kb < kB; kb += kBlk) {
-            const int ke = min(kb + kBlk, kB);
-            float br[NDET], bi[NDET];
-#pragma unroll
-            for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
-            for (int k = kb; k < ke; ++k) {
-                const Rec32 r = load_const(tab + k);
-                bin_split<NDET, true>(r, row, tau, k < kc, br, bi);
-            }
-            if (kb < kc) {
+                for (int q = 0; q < kBlk; ++q) {
+                    const Rec32 r = srec[kb - ks + q];
+                    bin_split<NDET, false>(r, row, tau, true, br, bi);
+                }
 #pragma unroll
                 for (int d = 0; d < NDET; ++d) {
                     sr[d] += (double)br[d];
                     si[d] += (double)bi[d];
                 }
             }
+            for (int kb = max(ks, kA); kb < min(ke, kB); kb += kBlk) {
+                const int kq = min(kb + kBlk, kB);
+                float br[NDET], bi[NDET];
+#pragma unroll
+                for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
+                for (int k = kb; k < kq; ++k) {
+                    const Rec32 r = srec[k - ks];
+                    bin_split<NDET, true>(r, row, tau, k < kc, br, bi);
+                }
+                if (kb < kc) {
+#pragma unroll
+                    for (int d = 0; d < NDET; ++d) {
+                        sr[d] += (double)br[d];
+                        si[d] += (double)bi[d];
+                    }
+                }
+            }
         }
     }
+    __syncthreads();  // sred and srec are reused by the next item
     if (valid) {
 #pragma unroll
         for (int d = 0; d < NDET; ++d) E.partial[((int64_t)g * NDET + d) * E.npad + j] = make_double2(sr[d], si[d]);
@@ -594,14 +616,16 @@ __device__ __forceinline__ void f64_item(const EvDev& E, const EvPlan& p, int ti
 
 __global__ __launch_bounds__(256) void k_b_split(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                  const int64_t* __restrict__ ioff) {
+    __shared__ Rec32 srec[kStage];
+    __shared__ int sred[4];
     item_loop(hdr, ioff, evs, [&](const Item& it) {
         const EvDev& E = evs[it.e];
         const EvPlan p = load_const(E.plan);
         switch (E.ec.n_det) {
-            case 1: split_item<1>(E, p, it.tile, it.g); break;
-            case 2: split_item<2>(E, p, it.tile, it.g); break;
-            case 3: split_item<3>(E, p, it.tile, it.g); break;
-            default: split_item<4>(E, p, it.tile, it.g); break;
+            case 1: split_item<1>(E, p, it.tile, it.g, srec, sred); break;
+            case 2: split_item<2>(E, p, it.tile, it.g, srec, sred); break;
+            case 3: split_item<3>(E, p, it.tile, it.g, srec, sred); break;
+            default: split_item<4>(E, p, it.tile, it.g, srec, sred); break;
         }
     });
 }
