@@ -236,6 +236,11 @@ def main():
                      "kernel_ms_avg": k_avg_s * 1e3, "kernel_launches": k_n, "ops_per_launch": ops_last},
     }
     first = evs[0]
+    # the drift check reads the last timed step's draws and log-likelihoods: before the other legs
+    # reuse those buffers
+    n_drift = args.drift_sample if args.drift_sample >= 0 else (1024 if c == 4 else 0)
+    if n_drift > 0:
+        out["drift"] = drift_leg(first, n_drift, prec)
     if n_events == 1 and args.refine_rounds > 0:
         out["refined"] = refine_leg(first, args.refine_rounds, args.refine_draws, max(args.steps, 1), prec)
     if n_events == 1 and args.relbin_eps > 0:
@@ -247,9 +252,6 @@ def main():
         out["distance_marginalised"] = distance_leg(first, centres, max(args.steps, 1), prec)
     if n_events == 1 and D == 4 and args.tile_candidates > 0:
         out["tiles"] = tile_leg(first, args, max(args.steps, 1), prec)
-    n_drift = args.drift_sample if args.drift_sample >= 0 else (1024 if c == 4 else 0)
-    if n_drift > 0:
-        out["drift"] = drift_leg(first, n_drift, prec)
     for x in evs:
         x["ev"].close()
 
