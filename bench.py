@@ -101,8 +101,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU only: run bench.py with --gpus 1 "
-                                   "(multi-GPU sharding is a design note, not built)"}), flush=True)
+        print(json.dumps({"error": "bench.py measures one GPU only: run it with --gpus 1 "
+                                   "(the library runs on one GPU; how it would shard is described, not implemented)"}), flush=True)
         sys.exit(2)
 
     import numpy as np
