@@ -15,7 +15,7 @@ import pytest
 import oracle
 from events import build_event
 from gpu_util import dev, fp64_tol, host, note, torch_cuda, upload_event
-from paper_2410_05190_amd import binding
+from paper_2410_05190_amd import binding, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -123,6 +123,33 @@ def test_batch_mixes_marginalised_and_sampled_distance():
         assert not np.array_equal(host(lls[0]), host(lls[1]))
     evd.close()
     evs.close()
+
+
+def test_loglike_split_parity_c1_full_size_sampled():
+    """Config 1 at full size in the benchmark's launch shape (65 536 draws, 519 168 bins, split
+    precision) with the distance marginalised: every draw through the GPU, sampled draws (the
+    lowest and highest cuts and 40 at random) through the oracle."""
+    torch_cuda()
+    b = build_event(1, 0, distance=oracle.DIST_MARG)
+    N = 65536
+    g = b.ev.metric(b.theta_inj)
+    rc, th, lq, lp = b.ev.draw(b.theta_inj, g, synth.draw_seed(1, 0), 0, N)
+    assert rc == 0
+    ev, data, psd = upload_event(b)
+    ev.reserve(N)
+    note("gpu split distance-marginalised loglike c1 full size")
+    ll_s = host(ev.loglike(dev(th), precision=binding.PE_PREC_SPLIT))
+    ev.status()
+    rng = np.random.default_rng(5)
+    live = np.flatnonzero(np.isfinite(ll_s))
+    pick = np.sort(np.concatenate([rng.choice(live, 40, replace=False), live[:4], live[-4:]]))
+    note(f"oracle loglike on {pick.size} sampled draws")
+    ll_o = b.ev.loglike(th[:, pick], n_threads=8)
+    d = np.abs(ll_s[pick] - ll_o)
+    note(f"  c1 full distance-marginalised split max |dlnL| = {d.max():.3e}")
+    assert d.max() <= 1e-3
+    assert np.array_equal(np.isfinite(lp), np.isfinite(ll_s))
+    ev.close()
 
 
 def test_chain_to_ess_within_tolerance():
