@@ -9,8 +9,16 @@ normalisation as Kidder 1995), through the stationary-phase integral
     Psi(v) = 2 v^3 t_c / M - phi_c - pi/4 + (2/M) int_v (v^3 - u^3) E'(u) / F(u) du,
 
 re-expanded in v. A dropped term, a wrong sign or a transposed mass ratio in the oracle's
-coefficients fails here. The 2PN spin-spin coefficient is not covered by this derivation
-(parity unpinned: checked only for exchange symmetry and quadratic scaling).
+coefficients fails here.
+
+The 2PN spin-spin pieces of E and F are not taken from a table: they are derived below
+from the leading-order physics of a circular orbit with spins along the orbital angular
+momentum (Kidder, Phys. Rev. D 52, 821 (1995): the spin-spin interaction energy
+(3 (S1.n)(S2.n) - S1.S2)/r^3 and the spin part 3/2 x^<i S^j> of the current quadrupole;
+Poisson, Phys. Rev. D 57, 5287 (1998): the quadrupole-monopole interaction of a spinning
+body whose quadrupole is that of a Kerr black hole, Q = -chi^2 m^3): Kepler's law and the
+energy of the orbit in that potential, and the flux of the mass and current quadrupoles,
+(1/5) |d^3 I/dt^3|^2 + (16/45) |d^3 J/dt^3|^2.
 """
 import math
 from functools import lru_cache
@@ -24,14 +32,65 @@ sp = pytest.importorskip("sympy")
 
 
 @lru_cache(maxsize=1)
+def _spin_spin_energy_flux():
+    """2PN spin-spin coefficients e4, f4 of E = -(eta v^2/2)(1 + ... + e4 v^4) and
+    F = (32/5) eta^2 v^10 (1 + ... + f4 v^4), in units M = 1, as sympy expressions in the mass
+    fractions x1, x2 and the aligned spins chi1, chi2. lam marks the spin-spin order; only
+    its first power is kept (the square is 4PN)."""
+    r, t, w, v, lam, a = sp.symbols("r t omega v lam a", positive=True)
+    x1, x2, c1, c2 = sp.symbols("x1 x2 chi1 chi2", real=True)
+    eta = x1 * x2
+    S1, S2 = x1 ** 2 * c1, x2 ** 2 * c2
+    # potential energy of the relative orbit (reduced mass eta), separation n in the plane
+    # orthogonal to the spins: Newtonian, spin-spin (S.n = 0), and each body's Kerr
+    # quadrupole acting on the companion at its equator (P2(0) = -1/2; m_j m_i^3 = eta x_i^2)
+    U = -eta / r + lam * (-S1 * S2 / r ** 3 - eta * x1 ** 2 * c1 ** 2 / (2 * r ** 3)
+                          - eta * x2 ** 2 * c2 ** 2 / (2 * r ** 3))
+    w2 = sp.diff(U, r) / (eta * r)            # circular orbit: eta omega^2 r = dU/dr
+    E = eta * w2 * r ** 2 / 2 + U
+    # r as a function of v = omega^(1/3): r = v^-2 / (1 + lam a v^4), a fixed by Kepler's law
+    rv = 1 / (v ** 2 * (1 + lam * a * v ** 4))
+    kepler = sp.series(sp.simplify(w2.subs(r, rv)) - v ** 6, lam, 0, 2).removeO()
+    a_sol = sp.solve(sp.expand(kepler.coeff(lam, 1)), a)[0]
+    Ev = sp.series(E.subs(r, rv).subs(a, a_sol), lam, 0, 2).removeO()
+    e_norm = sp.expand(Ev / (-eta * v ** 2 / 2))
+    assert sp.simplify(e_norm.coeff(lam, 0)) == 1
+    e4 = sp.simplify(e_norm.coeff(lam, 1) / v ** 4)
+    # flux: mass quadrupole eta x^<i x^j> of the relative orbit, and the spin part of the
+    # current quadrupole sum_A 3/2 x_A^<i S_A^j> with x_1 = x2 X, x_2 = -x1 X (centre of mass)
+    X = sp.Matrix([r * sp.cos(w * t), r * sp.sin(w * t), 0])
+    zhat = sp.Matrix([0, 0, 1])
+
+    def stf(m):
+        m = (m + m.T) / 2
+        return m - sp.eye(3) * m.trace() / 3
+
+    I = eta * stf(X * X.T)
+    J = sp.Rational(3, 2) * stf((x2 * X) * (S1 * zhat).T + (-x1 * X) * (S2 * zhat).T)
+    I3, J3 = I.diff(t, 3), J.diff(t, 3)
+    F_I = sp.simplify(sum(I3[i, j] ** 2 for i in range(3) for j in range(3)) / 5)
+    F_J = sp.simplify(sp.Rational(16, 45) * sum(J3[i, j] ** 2 for i in range(3) for j in range(3)))
+    F = (F_I + lam * F_J).subs(w, sp.sqrt(w2))
+    Fv = sp.series(sp.simplify(F.subs(r, rv).subs(a, a_sol)), lam, 0, 2).removeO()
+    f_norm = sp.expand(sp.simplify(Fv / (sp.Rational(32, 5) * eta ** 2 * v ** 10)))
+    assert sp.simplify(f_norm.coeff(lam, 0)) == 1
+    f4 = sp.simplify(f_norm.coeff(lam, 1) / v ** 4)
+    return (x1, x2, c1, c2), e4, f4
+
+
+@lru_cache(maxsize=1)
 def _derived():
     v, eta, delta, s, sg, L = sp.symbols("v eta delta s sg L")
+    c1, c2 = sp.symbols("c1 c2")
     R = sp.Rational
     pi = sp.pi
+    (x1, x2, chi1, chi2), e4ss, f4ss = _spin_spin_energy_flux()
+    xs = {x1: (1 + delta) / 2, x2: (1 - delta) / 2, chi1: c1, chi2: c2}
+    e4ss, f4ss = e4ss.subs(xs), f4ss.subs(xs)
     # E = -(M eta v^2 / 2) (1 + sum_k E_k v^k); s = S_l/M^2, sg = Sigma_l/M^2
     E = {2: -R(3, 4) - eta / 12,
          3: R(14, 3) * s + 2 * delta * sg,
-         4: -R(27, 8) + R(19, 8) * eta - eta ** 2 / 24,
+         4: -R(27, 8) + R(19, 8) * eta - eta ** 2 / 24 + e4ss,
          5: (11 - R(61, 9) * eta) * s + delta * (3 - R(10, 3) * eta) * sg,
          6: -R(675, 64) + (R(34445, 576) - R(205, 96) * pi ** 2) * eta - R(155, 96) * eta ** 2
             - R(35, 5184) * eta ** 3,
@@ -40,7 +99,7 @@ def _derived():
     # F = (32/5) eta^2 v^10 (1 + sum_k F_k v^k + F6l v^6 ln v)
     F = {2: -R(1247, 336) - R(35, 12) * eta,
          3: 4 * pi - 4 * s - R(5, 4) * delta * sg,
-         4: -R(44711, 9072) + R(9271, 504) * eta + R(65, 18) * eta ** 2,
+         4: -R(44711, 9072) + R(9271, 504) * eta + R(65, 18) * eta ** 2 + f4ss,
          5: -(R(8191, 672) + R(583, 24) * eta) * pi + (-R(9, 2) + R(272, 9) * eta) * s
             + (-R(13, 16) + R(43, 4) * eta) * delta * sg,
          6: R(6643739519, 69854400) + R(16, 3) * pi ** 2 - R(1712, 105) * sp.EulerGamma
@@ -64,16 +123,19 @@ def _derived():
     phi[5] = sp.expand(-R(40, 9) * c[5])          # (1/3 + ln v) -> (1 + 3 ln v)/3
     phi[6] = sp.expand(-20 * c6 + 10 * c6l)        # v ln v and v terms of the log integral
     phi6l = sp.expand(-20 * c6l)
-    funcs = {k: sp.lambdify((eta, delta, s, sg), phi[k], "mpmath") for k in phi}
+    funcs = {k: sp.lambdify((eta, delta, s, sg, c1, c2), phi[k], "mpmath") for k in phi}
     return funcs, float(phi6l)
 
 
-def _derived_vals(eta, delta, chi1, chi2):
+def _derived_vals(eta, delta, chi1, chi2, spin_spin=True):
+    """Derived coefficients; spin_spin=False leaves the spin-spin pieces of E and F out (their
+    products with the spin-orbit terms are cubic in the spins at 3.5PN, which the model omits)."""
     funcs, phi6l = _derived()
     x1, x2 = 0.5 * (1 + delta), 0.5 * (1 - delta)
     s = x1 * x1 * chi1 + x2 * x2 * chi2
     sg = x2 * chi2 - x1 * chi1
-    return np.array([float(funcs[k](eta, delta, s, sg)) for k in range(8)]), phi6l
+    c1, c2 = (chi1, chi2) if spin_spin else (0.0, 0.0)
+    return np.array([float(funcs[k](eta, delta, s, sg, c1, c2)) for k in range(8)]), phi6l
 
 
 ETAS = [0.25, 0.2475, 0.22, 0.2, 0.16, 0.1, 0.05]
@@ -98,9 +160,9 @@ def test_spin_orbit_terms_match_energy_flux_derivation(eta, chi1, chi2):
     p_plus, _ = oracle.pn_coeffs(eta, delta, chi1, chi2)
     p_minus, _ = oracle.pn_coeffs(eta, delta, -chi1, -chi2)
     odd = 0.5 * (p_plus - p_minus)
-    w_plus, _ = _derived_vals(eta, delta, chi1, chi2)
+    w_plus, _ = _derived_vals(eta, delta, chi1, chi2, spin_spin=False)
     # the derivation is linear in the spins except through products of 1.5PN terms (v^6 and up)
-    w_minus, _ = _derived_vals(eta, delta, -chi1, -chi2)
+    w_minus, _ = _derived_vals(eta, delta, -chi1, -chi2, spin_spin=False)
     want = 0.5 * (w_plus - w_minus)
     np.testing.assert_allclose(odd, want, rtol=1e-12, atol=1e-10)
     assert abs(odd[3]) > 0 and abs(odd[5]) > 0
@@ -108,7 +170,7 @@ def test_spin_orbit_terms_match_energy_flux_derivation(eta, chi1, chi2):
 
 def test_spin_spin_term_structure():
     """2PN spin-spin: even in the spins, only in the 2PN coefficient, exchange symmetric,
-    quadratic. Its numerical coefficients are parity unpinned (see module doc)."""
+    quadratic."""
     eta, delta = 0.2, math.sqrt(1 - 0.8)
     base, _ = oracle.pn_coeffs(eta, delta, 0.0, 0.0)
     a, _ = oracle.pn_coeffs(eta, delta, 0.3, -0.1)
@@ -119,6 +181,38 @@ def test_spin_spin_term_structure():
     assert np.all(np.abs(np.delete(even_a, 4)) < 1e-12 * np.maximum(1, np.abs(np.delete(base, 4))))
     assert even_a[4] != 0
     assert even_c[4] == pytest.approx(4 * even_a[4], rel=1e-12)
+
+
+@pytest.mark.parametrize("eta,chi1,chi2", [(0.25, 0.3, -0.2), (0.2, 0.5, 0.7), (0.1, -0.8, 0.4),
+                                           (0.16, 0.05, -0.05), (0.2475, 0.0, 0.85), (0.1875, 0.8, 0.0),
+                                           (0.09, -0.6, -0.7)])
+def test_spin_spin_terms_match_energy_flux_derivation(eta, chi1, chi2):
+    """Even part in the spins of the 2PN coefficient = the spin-spin term, against the one
+    the derived spin-spin energy and flux give (S1 S2 coupling, each body's quadrupole-monopole
+    term, and the square of the spin part of the current quadrupole). Cases with one spin zero
+    isolate the self terms; spins of both signs weigh the S1 S2 coupling."""
+    delta = math.sqrt(1 - 4 * eta)
+    p0, _ = oracle.pn_coeffs(eta, delta, 0.0, 0.0)
+    p_plus, _ = oracle.pn_coeffs(eta, delta, chi1, chi2)
+    p_minus, _ = oracle.pn_coeffs(eta, delta, -chi1, -chi2)
+    even = 0.5 * (p_plus + p_minus) - p0
+    w0, _ = _derived_vals(eta, delta, 0.0, 0.0)
+    w_plus, _ = _derived_vals(eta, delta, chi1, chi2)
+    w_minus, _ = _derived_vals(eta, delta, -chi1, -chi2)
+    want = 0.5 * (w_plus + w_minus) - w0
+    assert abs(want[4]) > 1e-3
+    assert even[4] == pytest.approx(want[4], rel=1e-12, abs=1e-12)
+
+
+def test_spin_spin_derivation_limits():
+    """The derived spin-spin pieces of E and F: for a single spinning body with a test mass
+    (x2 -> 0) the energy term is -chi1^2 (the Kerr quadrupole alone), and both pieces are
+    symmetric under the exchange of the bodies."""
+    (x1, x2, c1, c2), e4, f4 = _spin_spin_energy_flux()
+    assert sp.simplify(e4.subs({x1: 1, x2: 0}) + c1 ** 2) == 0
+    swap = {x1: x2, x2: x1, c1: c2, c2: c1}
+    assert sp.simplify(e4 - e4.subs(swap, simultaneous=True)) == 0
+    assert sp.simplify(f4 - f4.subs(swap, simultaneous=True)) == 0
 
 
 @pytest.mark.parametrize("eta,chi1,chi2", [(0.2, 0.3, -0.6), (0.1, 0.8, 0.1), (0.24, -0.05, 0.02)])
