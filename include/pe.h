@@ -184,7 +184,12 @@ pe_status_t pe_draw(pe_event_t ev, const double *theta0_dev, const double *g_dev
  *   precision: PE_PREC_FP64 (every step in FP64) or PE_PREC_SPLIT (phase in
  *              FP64; reduced-phase sincos, products and sums over blocks of
  *              16 bins in FP32, the block sums accumulated in FP64; final
- *              combination in FP64).
+ *              combination in FP64). The split path bounds each draw's error
+ *              from the hardware sine/cosine's measured error spectrum and
+ *              the data's noise statistics (taken when the event's tables are
+ *              prepared), and re-evaluates in FP64 (same plan, same value as
+ *              PE_PREC_FP64) every draw whose bound exceeds the budget of
+ *              pe_set_split_guard; pe_loglike_counts reports how many.
  *   loglike_dev: [n]; out-of-support draws get -inf.
  *   aux_dev: NULL or [n][3] = Re Z, Im Z, H (zeros out of support).
  * PE_DIST_MARG events: Z and H are those at the reference distance dl_max
@@ -542,6 +547,20 @@ pe_status_t pe_server_destroy(pe_server_t srv);
  * the named kernel ("loglike_split", "loglike_fp64"), then clears it. */
 pe_status_t pe_profile_enable(int32_t enable);
 pe_status_t pe_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
+/* Budget of the split path's per-draw error bound, |d ln L| (default 5e-4,
+ * half the split path's stated 1e-3): draws whose bound exceeds it are
+ * re-evaluated in FP64 within the same call. 0 re-evaluates every live draw
+ * (the result then equals PE_PREC_FP64 bit for bit); +inf never does. Global
+ * setting, read at launch time. Errors: PE_ERR_ARG (negative or NaN). */
+pe_status_t pe_set_split_guard(double budget);
+pe_status_t pe_get_split_guard(double *budget);
+
+/* Counts of the event's last log-likelihood batch (pe_loglike_batch,
+ * pe_loglike_multi, pe_batch_run): out[0] = in-support draws, out[1] = draws
+ * the split path re-evaluated in FP64 (0 for PE_PREC_FP64). Synchronises
+ * `stream`. Errors: PE_ERR_ARG (NULL), PE_ERR_HIP. */
+pe_status_t pe_loglike_counts(pe_event_t ev, int64_t out[2], void *stream);
 
 /* Work split of the hot loop: draws per tile are fixed (256); n_chunks caps
  * the number of groups of frequency chunks one event's tile is spread over

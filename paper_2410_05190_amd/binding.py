@@ -37,7 +37,7 @@ EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "p
            "pe_tile_assign", "pe_tile_draw", "pe_tile_reweight", "pe_relbin_setup", "pe_relbin_edges",
            "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
-           "pe_autotune_plan", "pe_last_error",
+           "pe_autotune_plan", "pe_set_split_guard", "pe_get_split_guard", "pe_loglike_counts", "pe_last_error",
            "pe_server_create", "pe_server_submit", "pe_server_wait", "pe_server_now", "pe_server_counters",
            "pe_server_destroy"]
 
@@ -157,6 +157,9 @@ def load(path=LIB_PATH):
         "pe_profile_enable": (i32, [i32]),
         "pe_profile_read": (i32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         "pe_set_chunks": (i32, [i32]),
+        "pe_set_split_guard": (i32, [ctypes.c_double]),
+        "pe_get_split_guard": (i32, [ctypes.POINTER(ctypes.c_double)]),
+        "pe_loglike_counts": (i32, [vp, ctypes.POINTER(i64), vp]),
         "pe_set_plan": (i32, [i32, i32]),
         "pe_get_plan": (i32, [ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "pe_autotune_plan": (i32, [i32, vp, vp, vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -418,6 +421,23 @@ def pe_profile_read(kernel):
 
 def pe_set_chunks(n_chunks):
     _check(load().pe_set_chunks(int(n_chunks)))
+
+
+def pe_set_split_guard(budget):
+    _check(load().pe_set_split_guard(float(budget)))
+
+
+def pe_get_split_guard():
+    b = ctypes.c_double()
+    _check(load().pe_get_split_guard(ctypes.byref(b)))
+    return b.value
+
+
+def pe_loglike_counts(ev, stream=None):
+    """(in-support draws, draws re-evaluated in FP64) of the event's last log-likelihood batch."""
+    out = (ctypes.c_int64 * 2)()
+    _check(load().pe_loglike_counts(ev.handle if isinstance(ev, Event) else ev, out, _stream(stream)))
+    return int(out[0]), int(out[1])
 
 
 def pe_set_plan(items_target, min_group_bins):

@@ -23,6 +23,7 @@ thread_local std::string g_err;
 int g_chunks = 0;             // cap on the hot loop's groups of chunks per event; 0 = automatic (64)
 int g_items_target = 16384;   // plan: work items per event
 int g_min_group_bins = 1024;  // plan: bins per group at least
+double g_redo_budget = pe::kRedoBudget;  // split path: FP64 re-evaluation above this |d ln L| estimate
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -147,6 +148,7 @@ size_t layout_tables(pe_event_s* ev, char* base) {
     ev->rec64 = c.take<Rec64>((size_t)(K + kTabPad));
     ev->pw = c.take<double>((size_t)nd * K);
     ev->pfx = c.take<double>((size_t)nd * (K + 1));
+    ev->guard = c.take<double>((size_t)kGuardLen);
     ev->status = c.take<int>(1);
     ev->mws = c.take<double>((size_t)kMwsTotal);
     return c.size();
@@ -158,8 +160,12 @@ size_t layout_ws(pe_event_s* ev, int64_t npad, char* base) {
     const int64_t cap = partial_cap_for(npad, ev->desc.n_bins, nd);
     ev->kc_all = c.take<int>((size_t)npad);
     ev->hist = c.take<int>((size_t)kBuckets);
-    ev->plan = c.take<EvPlan>(1);
+    ev->plan = c.take<EvPlan>(2);
     ev->idx = c.take<int>((size_t)npad);
+    ev->rflag = c.take<int>((size_t)npad);
+    ev->rcnt = c.take<int>((size_t)(npad / kTile + 1));
+    ev->rpos = c.take<int>((size_t)npad);
+    ev->zd = c.take<double2>((size_t)npad);
     ev->coef = c.take<double>((size_t)kNCoef * npad);
     ev->kcut = c.take<int>((size_t)npad);
     ev->resp = c.take<double>((size_t)2 * nd * npad);
@@ -332,13 +338,13 @@ pe_status_t staging_buffer(Area& A, size_t bytes, int& k) {
     return PE_OK;
 }
 
-size_t loglike_scratch_bytes(int ne, int redo_cap) {
-    return sizeof(int64_t) * kQueues * (ne + 1) + sizeof(int2) * (size_t)redo_cap;
-}
+size_t loglike_scratch_bytes(int ne) { return sizeof(int64_t) * kQueues * (ne + 1); }
+
+double redo_budget_setting() { return g_redo_budget; }
 
 pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const void* args, size_t arg_bytes,
                         const std::vector<int64_t>& off, const std::vector<int64_t>* off2, size_t scratch_bytes,
-                        hipStream_t st, BatchPtrs& out, int redo_cap) {
+                        hipStream_t st, BatchPtrs& out) {
     // a fixed area keeps one layout (sized for layout_ne records of
     // layout_rec bytes) so that its pointers never move
     const int lne = A.fixed ? A.layout_ne : ne;
@@ -364,8 +370,8 @@ pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const vo
     std::vector<char> img(o_scr, 0);
     BatchHdr h = {};
     h.ne = ne;
-    h.redo_cap = redo_cap;
     h.total = total;
+    h.redo_budget = g_redo_budget;
     h.total2 = total2;
     std::memcpy(img.data(), &h, sizeof(h));
     if (arg_bytes) std::memcpy(img.data() + o_args, args, arg_bytes);
@@ -415,6 +421,7 @@ PrepArg prep_arg(const pe_event_s* ev, const void* data, const void* psd) {
     a.pw = ev->pw;
     a.pfx = ev->pfx;
     a.seg = ev->mws + kMwsScan;
+    a.guard = ev->guard;
     a.status = ev->status;
     return a;
 }
@@ -505,6 +512,7 @@ EvDev loglike_arg(const pe_event_s* ev, const double* theta, int64_t n, double* 
     d.rec32 = ev->rec32;
     d.rec64 = ev->rec64;
     d.pfx = ev->pfx;
+    d.guard = ev->guard;
     d.kc_all = ev->kc_all;
     d.hist = ev->hist;
     d.idx = ev->idx;
@@ -514,6 +522,10 @@ EvDev loglike_arg(const pe_event_s* ev, const double* theta, int64_t n, double* 
     d.hh = ev->hh;
     d.partial = ev->partial;
     d.plan = ev->plan;
+    d.rflag = ev->rflag;
+    d.rcnt = ev->rcnt;
+    d.rpos = ev->rpos;
+    d.zd = ev->zd;
     d.status = ev->status;
     // Row stride and group cap follow from n alone (the workspace holds at
     // least this much), so a batch's plan does not depend on how large the
@@ -548,9 +560,8 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     Area& A = area_for(st, kAreaLoglike);
     std::lock_guard<std::mutex> lk(A.mu);
     BatchPtrs b;
-    const int redo_cap = (int)std::min<int64_t>(foff[ne] * 256, kRedoCapMax);
     pe_status_t s = upload_area(A, ne, poff[ne], foff[ne], v.data(), sizeof(EvDev) * ne, poff, &foff,
-                                loglike_scratch_bytes(ne, redo_cap), st, b, redo_cap);
+                                loglike_scratch_bytes(ne), st, b);
     if (s != PE_OK) return s;
     PE_HIP(launch_loglike_batch(b, ne, poff[ne], foff[ne], precision, true, any_dist, st));
     return PE_OK;
@@ -683,8 +694,6 @@ pe_status_t pe_event_status(pe_event_t ev, void* stream) {
     if (flags & kStBadPsd) return fail(PE_ERR_ARG, "PSD values must be positive and finite");
     if (flags & kStNonfinite) return fail(PE_ERR_NONFINITE, "data contains inf or nan");
     if (flags & kStSingular) return fail(PE_ERR_SINGULAR, "metric is not positive definite");
-    if (flags & kStRedoFull)
-        return fail(PE_ERR_BUDGET, "too many draws needed the FP64 re-evaluation of the split path");
     return PE_OK;
 }
 
@@ -1006,6 +1015,32 @@ pe_status_t pe_autotune_plan(int32_t n_events, const pe_event_t* events, const d
     *best_items_target = bi;
     *best_min_group_bins = bb;
     *best_ms = best;
+    return PE_OK;
+}
+
+pe_status_t pe_set_split_guard(double budget) {
+    if (!(budget >= 0.0)) return fail(PE_ERR_ARG, "budget must be >= 0 (inf: never re-evaluate)");
+    g_redo_budget = budget;
+    return PE_OK;
+}
+
+pe_status_t pe_get_split_guard(double* budget) {
+    if (!budget) return fail(PE_ERR_ARG, "NULL argument");
+    *budget = g_redo_budget;
+    return PE_OK;
+}
+
+pe_status_t pe_loglike_counts(pe_event_t ev, int64_t out[2], void* stream) {
+    if (!ev || !out) return fail(PE_ERR_ARG, "NULL argument");
+    if (!ev->plan) {
+        out[0] = out[1] = 0;
+        return PE_OK;
+    }
+    EvPlan p[2];
+    PE_HIP(hipStreamSynchronize(as_stream(stream)));
+    PE_HIP(hipMemcpy(p, ev->plan, sizeof(p), hipMemcpyDeviceToHost));
+    out[0] = p[0].n_active;
+    out[1] = p[1].n_active;
     return PE_OK;
 }
 

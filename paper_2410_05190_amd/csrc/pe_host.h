@@ -85,11 +85,14 @@ pe_status_t reserve_area(Area& A, size_t bytes);
 void release_area(Area& A);
 pe_status_t upload_area(Area& A, int ne, int64_t total, int64_t total2, const void* args, size_t arg_bytes,
                         const std::vector<int64_t>& off, const std::vector<int64_t>* off2, size_t scratch_bytes,
-                        hipStream_t st, BatchPtrs& out, int redo_cap = 0);
+                        hipStream_t st, BatchPtrs& out);
 
-// Scratch of a log-likelihood batch: the queue offsets for ne events and a
-// re-evaluation list of redo_cap entries.
-size_t loglike_scratch_bytes(int ne, int redo_cap);
+// Scratch of a log-likelihood batch: the queue offsets for ne events.
+size_t loglike_scratch_bytes(int ne);
+
+// Budget of the split path's error estimate above which a draw is
+// re-evaluated in FP64 (global setting, written into each batch header).
+double redo_budget_setting();
 
 // Argument records of the batched stages.
 PrepArg prep_arg(const pe_event_s* ev, const void* data, const void* psd);

@@ -67,7 +67,6 @@ constexpr int kTabPad = 8;      // zeroed records past the last bin
 constexpr int kStBadPsd = 1;
 constexpr int kStNonfinite = 2;
 constexpr int kStSingular = 4;
-constexpr int kStRedoFull = 8;  // the split path's FP64 re-evaluation list overflowed
 
 // Workspace of the metric: per FD source, coefficients, response and delays.
 constexpr int kMetricSrcStride = 32;  // doubles: A[8], B5, B6, rre[4], rim[4], tau[4], pad
@@ -110,6 +109,7 @@ struct PrepArg {
     Rec32 *rec32;
     Rec64 *rec64;
     double *pw, *pfx, *seg;
+    double *guard;  // [PE_MAX_DET][kGuardStride] noise statistics of the data (split-path error estimate)
     int *status;
 };
 
@@ -143,10 +143,15 @@ struct EvDev {
     const Rec32 *rec32;
     const Rec64 *rec64;
     const double *pfx;
+    const double *guard;  // noise statistics of the event's data (see kGuardStride)
     int *kc_all, *hist, *idx, *kcut;
     double *coef, *resp, *hh;
     double2 *partial;
-    EvPlan *plan;
+    EvPlan *plan;    // [2]: the batch's plan, then the plan of the FP64 re-evaluation
+    int *rflag;      // [npad] split finalize: rank of a re-evaluated draw in its block of 256, else -1
+    int *rcnt;       // [npad / 256] re-evaluated draws per block, then their offsets
+    int *rpos;       // [npad] positions of the re-evaluated draws, ascending
+    double2 *zd;     // [npad] Z of distance-marginalised events (read by k_b_dist)
     int *status;
     int64_t npad;
     int max_groups;      // cap on the groups of chunks (partial capacity / npad)
@@ -187,27 +192,59 @@ constexpr int kQueues = 8;
 // Header of a batch in device memory.
 struct BatchHdr {
     int ne;                // events
-    int redo_cap;          // log-likelihood batches: capacity of the FP64 re-evaluation list
+    int pad0;
     int64_t total;         // flattened size (blocks)
     int64_t total2;        // second flattened size (blocks)
-    int qitems[kQueues];   // hot-loop items per queue (written by k_b_items)
+    int qitems[kQueues];   // hot-loop items per queue (written by k_b_items, then k_r_items)
     int qnext[kQueues];    // queue counters
-    int redo_count;        // entries appended to the re-evaluation list (reset by k_b_items)
-    int pad;
+    double redo_budget;    // split path: |d ln L| estimate above which a draw is re-evaluated in FP64
 };
 
-// Split precision and the hardware sine/cosine of gfx950 (v_sin_f32 and
-// v_cos_f32 of a turn-based argument), measured over 2^24 arguments in
-// [-2, 2): at most 1.25e-7 off, and on average too small in magnitude by
-// 3.23e-8 (phase bias below 1e-10). The mean magnitude bias adds coherently
-// over a matched sum, so the split path scales its sums by kTrigGain; the rest
-// can still add coherently when the terms' phases align, by at most ~1e-7 of
-// sum_d |R_d| |Z_d|, so a draw whose sum exceeds kRedoMagnitude is re-evaluated
-// in FP64, which keeps |d ln L| below 1e-3 for every draw.
+// ---------------------------------------------------------------------------
+// Error of the split path and when a draw is re-evaluated in FP64.
+//
+// The hardware sine/cosine of gfx950 (v_sin_f32, v_cos_f32 of a turn-based
+// argument t) returns exp(-2 pi i t) (1 + eps(t)) with, measured over every
+// FP32 argument in [2^-30, 2): |eps| at most 1.277e-7 once the mean magnitude
+// bias (-3.23e-8) is removed by kTrigGain, RMS 3.67e-8, and Fourier
+// coefficients c_m of eps(t) (t in [0, 1)) of at most 1e-8 for |m| <= 8 (the
+// low ones 5e-10 .. 1.1e-9). The error of a detector's sum
+// Z_d = sum_k |w_k| exp(-2 pi i t_k) is then
+//   sum_m c_m Z_d^(1-m),  Z_d^(j) = sum_k |w_k| exp(-2 pi i j t_k):
+// j = 0 is L1 = sum |w_k| (term c_1 L1), j = 1 is Z_d itself, and |j| >= 2
+// add coherently only as far as the data's phases follow the template's. For
+// data with Gaussian noise at the PSD's level, the phase of bin k scatters
+// about the signal's with a Rice distribution; its harmonic j keeps the factor
+// e_j(a) <= (0.7 a)^(j-1) of the signal's coherent sum (a = signal / noise
+// amplitude in the bin; e_j from the Bessel-function form of the Rice moments),
+// so only the lowest c_m matter when a is small (configs 0, 1, 4: a < 0.4).
+// Around these expectations the sum scatters with RMS (per-term error) x
+// sqrt(sum |w_k|^2); the per-term RMS adds to the trigonometric one the FP32
+// rounding of the turn-based argument (two roundings, <= 3.9e-8 turns RMS).
+// Per draw the finalize bounds |d ln L| by
+//   sum_d |R_d| [ eps_coh(a) C_d + kEpsL1 L1_d ] + kEpsInc sqrt(sum_d |R_d|^2 W2_d)
+// (C_d the larger of |Z_d| and the matched magnitude sqrt(C_d,kcut rho2_d)/|R_d|,
+// rho2_d a bound on the detector's signal power from the data's whitened
+// power in excess of the noise's; the scatter adds in quadrature over the
+// detectors), and where the data carry less than the PSD's noise (e.g.
+// noise-free injections) by the worst case kEpsMax sum_d |R_d| L1_d. Draws
+// whose bound exceeds the batch's redo budget are re-evaluated in FP64 on the
+// hot loop's own layout.
 constexpr double kTrigGain = 1.0 + 3.23e-8;
-constexpr double kRedoMagnitude = 6000.0;
-// Entries of the re-evaluation list in a batch's scratch, at most.
-constexpr int kRedoCapMax = 1 << 20;
+constexpr double kEpsMax = 1.4e-7;       // max |eps| (1.277e-7 measured)
+constexpr double kEpsL1 = 7.0e-10;       // |c_1| (5.6e-10 measured)
+constexpr double kEpsRms = 4.4e-8;       // RMS of eps (3.67e-8 measured), tail of the harmonic sum
+constexpr double kEpsInc = 1.5e-6;       // 6 x per-term RMS 2.5e-7 (argument roundings ~2e-7 rad, trig
+                                         // 3.7e-8, FP32 weights and block sums)
+// |c_{1-j}| + |c_{1+j}| for j = 1..7 (measured, x1.5)
+constexpr double kEpsHarm[7] = {1.5e-9, 2.2e-9, 6.3e-9, 3.0e-9, 8.0e-9, 7.6e-10, 1.5e-8};
+constexpr double kRedoBudget = 5e-4;     // default: half of the split path's stated 1e-3
+// Noise statistics per detector (event tables): the bound rho2 on the signal
+// power (< 0: the data carry less than the noise the PSD implies), the largest
+// 4 df f^-7/3 / S of the band, L1 = sum |w_k| and sqrt(sum |w_k|^2).
+constexpr int kGuardStride = 4;
+constexpr int kGuardRho2 = 0, kGuardPwMax = 1, kGuardL1 = 2, kGuardW2 = 3;
+constexpr int kGuardLen = kGuardStride * PE_MAX_DET;
 
 constexpr int kWBlock = 4096;  // draws per block of the weights reduction (256 threads x 16)
 
@@ -221,6 +258,7 @@ struct pe_event_s {
     pe::Rec64 *rec64 = nullptr;
     double *pw = nullptr;   // [n_det][K] 4 df f^(-7/3) / S
     double *pfx = nullptr;  // [n_det][K+1] exclusive prefix of pw
+    double *guard = nullptr;  // [kGuardLen] noise statistics of the data
     int *status = nullptr;  // device status word
     double *mws = nullptr;  // metric + draw workspace
     // per-draw workspace
@@ -228,7 +266,11 @@ struct pe_event_s {
     int *kc_all = nullptr;  // [npad] cut per draw, -1 out of support
     int *hist = nullptr;    // [kBuckets] bucket counts, then offsets
     int *idx = nullptr;
-    pe::EvPlan *plan = nullptr;
+    pe::EvPlan *plan = nullptr;  // [2]: batch plan, FP64 re-evaluation plan
+    int *rflag = nullptr;        // [npad]
+    int *rcnt = nullptr;         // [npad / 256]
+    int *rpos = nullptr;         // [npad]
+    double2 *zd = nullptr;       // [npad]
     int64_t partial_cap = 0;  // double2 entries per detector
     double *coef = nullptr;   // [kNCoef][npad]
     int *kcut = nullptr;      // [npad]
@@ -309,8 +351,10 @@ constexpr int kCholOk = kCholLogdet + 1;
 constexpr int kCholG = kCholLogdet + 2;
 constexpr int kCholRdiag = kCholLogdet + 8;
 constexpr int kCholLen = kCholRdiag + PE_MAX_DIM;
-constexpr int64_t kMwsScan = kMwsChol + kCholLen;  // segment sums [n_det][kScanSeg]
-constexpr int64_t kMwsTotal = kMwsScan + (int64_t)PE_MAX_DET * kScanSeg;
+constexpr int64_t kMwsScan = kMwsChol + kCholLen;  // segment sums [kSegSums][n_det][kScanSeg]
+// per segment: pw (prefix scan), whitened data power, L1 and L2 of w, max pw
+constexpr int kSegSums = 5;
+constexpr int64_t kMwsTotal = kMwsScan + (int64_t)kSegSums * PE_MAX_DET * kScanSeg;
 constexpr int64_t kMwsKcut = kMwsSrc - 4;  // frozen cut of the metric (stored as double)
 
 // profiling hooks (pe_api.hip)

@@ -114,6 +114,20 @@ __device__ __forceinline__ double block_sum4(double s, double* sh) {
     return r;
 }
 
+__device__ __forceinline__ double block_max4(double s, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s = fmax(s, __shfl_xor(s, o));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    const double r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    __syncthreads();
+    return r;
+}
+
+// Per segment and detector: the sum of pw (for the prefix scan) and the noise
+// statistics of the data behind the split path's error estimate: whitened
+// power 4 df |d|^2 / S = |w|^2 / pw, L1 and L2 of the folded weights w, the
+// largest pw. Slices of A.seg: [kSegSums][PE_MAX_DET][kScanSeg].
 __global__ __launch_bounds__(256) void k_seg_sums(const BatchHdr* __restrict__ hdr,
                                                   const PrepArg* __restrict__ args) {
     __shared__ double sh[4];
@@ -129,10 +143,30 @@ __global__ __launch_bounds__(256) void k_seg_sums(const BatchHdr* __restrict__ h
         const double* a = A.pw + (int64_t)d * K;
         const int64_t k0 = (int64_t)b * seg;
         const int64_t k1 = min(k0 + seg, K);
-        double s = 0.0;
-        for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) s += a[k];
+        double s = 0.0, pwr = 0.0, l1 = 0.0, l2 = 0.0, mx = 0.0;
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+            const double pw = a[k];
+            const double2 w = A.rec64[k].w[d];
+            const double w2 = w.x * w.x + w.y * w.y;
+            s += pw;
+            if (pw > 0.0) pwr += w2 / pw;
+            l1 += sqrt(w2);
+            l2 += w2;
+            mx = fmax(mx, pw);
+        }
         s = block_sum4(s, sh);
-        if (threadIdx.x == 0) A.seg[d * kScanSeg + b] = s;
+        pwr = block_sum4(pwr, sh);
+        l1 = block_sum4(l1, sh);
+        l2 = block_sum4(l2, sh);
+        mx = block_max4(mx, sh);
+        if (threadIdx.x == 0) {
+            const int64_t o = (int64_t)d * kScanSeg + b, slice = (int64_t)PE_MAX_DET * kScanSeg;
+            A.seg[o] = s;
+            A.seg[slice + o] = pwr;
+            A.seg[2 * slice + o] = l1;
+            A.seg[3 * slice + o] = l2;
+            A.seg[4 * slice + o] = mx;
+        }
     }
 }
 
@@ -177,6 +211,29 @@ __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ h
             carry += tile;
         }
         if (b == nseg - 1 && threadIdx.x == 0) o[K] = carry;
+        if (b == 0) {
+            // the detector's noise statistics: segments combined in a fixed order
+            const int64_t slice = (int64_t)PE_MAX_DET * kScanSeg;
+            const int t = threadIdx.x;
+            const double* sg = A.seg + (int64_t)d * kScanSeg + t;
+            const bool in = t < nseg;
+            const double pwr = block_sum4(in ? sg[slice] : 0.0, sh);
+            const double l1 = block_sum4(in ? sg[2 * slice] : 0.0, sh);
+            const double l2 = block_sum4(in ? sg[3 * slice] : 0.0, sh);
+            const double mx = block_max4(in ? sg[4 * slice] : 0.0, sh);
+            if (t == 0) {
+                // Gaussian noise at the PSD's level gives each bin whitened power 2 on
+                // average (sd 2 sqrt(K) over the band); the excess bounds the signal's
+                // power rho^2 (6 sd of margin). Data with less than the noise's power
+                // less 6 sd get -1: the noise-based error estimate does not apply.
+                const double Kd = (double)K, slack = 12.0 * sqrt(Kd), excess = pwr - 2.0 * Kd;
+                double* G = A.guard + d * kGuardStride;
+                G[kGuardRho2] = excess < -slack ? -1.0 : excess + slack;
+                G[kGuardPwMax] = mx;
+                G[kGuardL1] = l1;
+                G[kGuardW2] = sqrt(l2);
+            }
+        }
     }
 }
 

@@ -12,7 +12,11 @@
 //                 lanes = draws; the bin records are staged in LDS (split) or
 //                 read through scalar loads (FP64), and each is reused by the
 //                 64 draws of a wave and the 256 of a workgroup
-//   k_b_finalize  fixed-order combine of the group partials, ln L
+//   k_b_finalize  fixed-order combine of the group partials, ln L; split path:
+//                 the draw's error estimate, and the draws to re-evaluate
+//   k_r_plan, k_r_scatter, k_r_items, k_r_f64, k_r_finalize
+//                 split path: FP64 re-evaluation of the listed draws on the hot
+//                 loop's own layout (tiles of 256 listed draws x groups of chunks)
 //   k_b_dist      distance-marginalised events: ln L integrated over dL
 //
 // An event's decomposition (chunk length, groups) is planned on the device from
@@ -61,7 +65,8 @@ __global__ __launch_bounds__(256) void k_b_reset(const BatchHdr* __restrict__ hd
         E.hist[blockIdx.x * 256 + threadIdx.x] = 0;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             EvPlan z = {};
-            *E.plan = z;
+            E.plan[0] = z;
+            E.plan[1] = z;
         }
     }
 }
@@ -230,7 +235,6 @@ __global__ void k_b_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ 
     o[ne] = acc;
     hdr->qitems[x] = (int)acc;
     hdr->qnext[x] = 0;
-    if (x == 0) hdr->redo_count = 0;
 }
 
 // Live draws into their buckets; the order inside a bucket is immaterial. A
@@ -404,7 +408,8 @@ __device__ __forceinline__ Ticket own_or_steal(BatchHdr* __restrict__ hdr, int x
     return (v < hdr->qitems[x0]) ? Ticket{x0, v} : steal_ticket(hdr, x0);
 }
 
-// Item of ticket (q, x).
+// Item of ticket (q, x); REDO: items of the FP64 re-evaluation (plan[1], tiles from 0).
+template <bool REDO>
 __device__ __forceinline__ void decode_item(const int64_t* __restrict__ ioff, int ne, const EvDev* __restrict__ evs,
                                             int q, int x, Item& it) {
     const int64_t* o = ioff + (int64_t)q * (ne + 1);
@@ -418,8 +423,8 @@ __device__ __forceinline__ void decode_item(const int64_t* __restrict__ ioff, in
     }
     it.e = lo;
     const int l = x - (int)load_const(o + it.e);
-    const int G = load_const(evs[it.e].plan).n_groups;
-    const int tlo = max(0, evs[it.e].tile_lo);
+    const int G = load_const(evs[it.e].plan + (REDO ? 1 : 0)).n_groups;
+    const int tlo = REDO ? 0 : max(0, evs[it.e].tile_lo);
     if (G >= kQueues) {
         const int gq = G / kQueues;
         it.tile = tlo + l / gq;
@@ -433,7 +438,7 @@ __device__ __forceinline__ void decode_item(const int64_t* __restrict__ ioff, in
 
 // The persistent loop of the hot kernels: process(it) for every item this
 // workgroup draws.
-template <typename F>
+template <bool REDO, typename F>
 __device__ __forceinline__ void item_loop(BatchHdr* __restrict__ hdr, const int64_t* __restrict__ ioff,
                                           const EvDev* __restrict__ evs, F process) {
     // two ticket slots used in turn: a slot is rewritten only after the barrier
@@ -452,7 +457,7 @@ __device__ __forceinline__ void item_loop(BatchHdr* __restrict__ hdr, const int6
     int v = __builtin_amdgcn_readfirstlane(s_v[0]);
     while (q >= 0) {
         Item it;
-        decode_item(ioff, ne, evs, q, v, it);
+        decode_item<REDO>(ioff, ne, evs, q, v, it);
         // Short items (under ~4k bins) claim the next ticket before they run, so
         // the atomic's latency hides behind them; long ones claim it when done,
         // which keeps the last items spread evenly over the workgroups.
@@ -474,13 +479,11 @@ __device__ __forceinline__ void item_loop(BatchHdr* __restrict__ hdr, const int6
     }
 }
 
-// The lane's draw, its row and delays, its cut, and the wave's range of cuts.
+// The row and delays of the draw at position jl, its cut, and the wave's range
+// of cuts over its valid lanes.
 template <int NDET>
-__device__ __forceinline__ void item_setup(const EvDev& E, int nact, int tile, int& j, bool& valid, DrawRow& row,
-                                           double (&tau)[NDET], int& kc, int& wmin, int& wmax) {
-    j = tile * kTile + (int)threadIdx.x;
-    valid = j < nact;
-    const int64_t jl = valid ? j : nact - 1;
+__device__ __forceinline__ void load_row(const EvDev& E, int64_t jl, bool valid, DrawRow& row, double (&tau)[NDET],
+                                         int& kc, int& wmin, int& wmax) {
     const int64_t np = E.npad;
     const gdoubles coef = (gdoubles)E.coef;
 #pragma unroll
@@ -492,6 +495,16 @@ __device__ __forceinline__ void item_setup(const EvDev& E, int nact, int tile, i
     kc = ((gints)E.kcut)[jl];
     wmin = wave_min(valid ? kc : 0x7fffffff);
     wmax = wave_max(valid ? kc : 0);
+}
+
+// The lane's draw (position tile * 256 + lane), its row and delays, its cut,
+// and the wave's range of cuts.
+template <int NDET>
+__device__ __forceinline__ void item_setup(const EvDev& E, int nact, int tile, int& j, bool& valid, DrawRow& row,
+                                           double (&tau)[NDET], int& kc, int& wmin, int& wmax) {
+    j = tile * kTile + (int)threadIdx.x;
+    valid = j < nact;
+    load_row<NDET>(E, valid ? j : nact - 1, valid, row, tau, kc, wmin, wmax);
 }
 
 // One item of the split hot loop. The workgroup stages the bin records of its
@@ -579,16 +592,13 @@ __device__ __forceinline__ void split_item(const EvDev& E, const EvPlan& p, int 
     }
 }
 
+// FP64 walk of one item's chunks (group g of the plan) for the lane's draw.
 template <int NDET>
-__device__ __forceinline__ void f64_item(const EvDev& E, const EvPlan& p, int tile, int g) {
-    int j, kc, wmin, wmax;
-    bool valid;
-    DrawRow row;
-    double tau[NDET];
-    item_setup<NDET>(E, p.n_active, tile, j, valid, row, tau, kc, wmin, wmax);
+__device__ __forceinline__ void f64_walk(const EvDev& E, const EvPlan& p, int g, const DrawRow& row,
+                                         const double (&tau)[NDET], int kc, int wmin, int wmax, double (&zr)[NDET],
+                                         double (&zi)[NDET]) {
     const Rec64* tab = E.rec64;
     const int K = (int)E.ec.K;
-    double zr[NDET], zi[NDET];
 #pragma unroll
     for (int d = 0; d < NDET; ++d) zr[d] = zi[d] = 0.0;
     for (int c = g; c < p.n_fine; c += p.n_groups) {
@@ -608,9 +618,40 @@ __device__ __forceinline__ void f64_item(const EvDev& E, const EvPlan& p, int ti
             bin_f64<NDET, true>(r, row, tau, k < kc, zr, zi);
         }
     }
+}
+
+template <int NDET>
+__device__ __forceinline__ void f64_item(const EvDev& E, const EvPlan& p, int tile, int g) {
+    int j, kc, wmin, wmax;
+    bool valid;
+    DrawRow row;
+    double tau[NDET];
+    item_setup<NDET>(E, p.n_active, tile, j, valid, row, tau, kc, wmin, wmax);
+    double zr[NDET], zi[NDET];
+    f64_walk<NDET>(E, p, g, row, tau, kc, wmin, wmax, zr, zi);
     if (valid) {
 #pragma unroll
         for (int d = 0; d < NDET; ++d) E.partial[((int64_t)g * NDET + d) * E.npad + j] = make_double2(zr[d], zi[d]);
+    }
+}
+
+// One item of the FP64 re-evaluation: lane r of the tile takes the r-th listed
+// draw (position rpos[r]); its partials go to column r. The walk is the FP64
+// kernel's, under the same plan, so each listed draw gets the FP64 path's value.
+template <int NDET>
+__device__ __forceinline__ void redo_item(const EvDev& E, const EvPlan& rp, int tile, int g) {
+    const int r = tile * kTile + (int)threadIdx.x;
+    const bool valid = r < rp.n_active;
+    const int jl = ((gints)E.rpos)[valid ? r : rp.n_active - 1];
+    int kc, wmin, wmax;
+    DrawRow row;
+    double tau[NDET];
+    load_row<NDET>(E, jl, valid, row, tau, kc, wmin, wmax);
+    double zr[NDET], zi[NDET];
+    f64_walk<NDET>(E, rp, g, row, tau, kc, wmin, wmax, zr, zi);
+    if (valid) {
+#pragma unroll
+        for (int d = 0; d < NDET; ++d) E.partial[((int64_t)g * NDET + d) * E.npad + r] = make_double2(zr[d], zi[d]);
     }
 }
 
@@ -618,7 +659,7 @@ __global__ __launch_bounds__(256) void k_b_split(BatchHdr* __restrict__ hdr, con
                                                  const int64_t* __restrict__ ioff) {
     __shared__ Rec32 srec[kStage];
     __shared__ int sred[4];
-    item_loop(hdr, ioff, evs, [&](const Item& it) {
+    item_loop<false>(hdr, ioff, evs, [&](const Item& it) {
         const EvDev& E = evs[it.e];
         const EvPlan p = load_const(E.plan);
         switch (E.ec.n_det) {
@@ -632,7 +673,7 @@ __global__ __launch_bounds__(256) void k_b_split(BatchHdr* __restrict__ hdr, con
 
 __global__ __launch_bounds__(256) void k_b_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                const int64_t* __restrict__ ioff) {
-    item_loop(hdr, ioff, evs, [&](const Item& it) {
+    item_loop<false>(hdr, ioff, evs, [&](const Item& it) {
         const EvDev& E = evs[it.e];
         const EvPlan p = load_const(E.plan);
         switch (E.ec.n_det) {
@@ -644,59 +685,258 @@ __global__ __launch_bounds__(256) void k_b_f64(BatchHdr* __restrict__ hdr, const
     });
 }
 
-// Fixed-order combine of the group partials (8 interleaved accumulators, then a
-// pairwise tree), then ln L of Eq. 3.
+// Fixed-order combine of a draw's group partials for one detector (8
+// interleaved accumulators, then a pairwise tree); col: the draw's column.
+__device__ __forceinline__ void combine_groups(const EvDev& E, int d, int nd, int G, int64_t col, double& ar,
+                                               double& ai) {
+    const int64_t np = E.npad;
+    double xr[8], xi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xr[q] = xi[q] = 0.0;
+    for (int c = 0; c < G; ++c) {
+        const double2 v = E.partial[((int64_t)c * nd + d) * np + col];
+        xr[c & 7] += v.x;
+        xi[c & 7] += v.y;
+    }
+#pragma unroll
+    for (int w = 4; w > 0; w >>= 1)
+#pragma unroll
+        for (int q = 0; q < w; ++q) {
+            xr[q] += xr[q + w];
+            xi[q] += xi[q + w];
+        }
+    ar = xr[0];
+    ai = xi[0];
+}
+
+// Coherent part of the split path's error per unit of coherent magnitude, for
+// data whose per-bin signal-to-noise amplitude is at most sqrt(a2): harmonic j
+// of the hardware error keeps the factor (0.7 a)^(j-1) of the coherent sum;
+// harmonics 8 and up are bounded together (Cauchy-Schwarz over their RMS).
+__device__ __forceinline__ double eps_coherent(double a2) {
+    const double g = 0.7 * sqrt(a2);
+    if (!(g < 0.9)) return kEpsMax;
+    double s = 0.0, gp = 1.0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        s += kEpsHarm[j] * gp;
+        gp *= g;
+    }
+    s += kEpsRms * 1.4142135623730951 * gp / sqrt(1.0 - g * g);
+    return fmin(s, kEpsMax);
+}
+
+// Bound on |d ln L| of the split path for one detector of a draw (see
+// kEpsHarm): |R_d|, the detector's FP32-path sum (ar, ai), C_{d,kcut}. lin
+// gains the parts that add linearly over detectors, var the variance of the
+// scatter (in units of kEpsInc^2).
+__device__ __forceinline__ void split_error(const double* __restrict__ G, double rm, double ar, double ai, double c,
+                                            double& lin, double& var) {
+    if (rm == 0.0 || c == 0.0) return;
+    const double rho2 = G[kGuardRho2];
+    const double sw = rm * G[kGuardW2];
+    var += sw * sw;
+    if (rho2 < 0.0) {  // no noise to scatter the phases: worst case
+        lin += kEpsMax * rm * G[kGuardL1];
+        return;
+    }
+    const double coh = fmax(rm * hypot(ar, ai), sqrt(rm * rm * c * rho2));
+    lin += eps_coherent(rho2 * G[kGuardPwMax] / c) * coh + kEpsL1 * rm * G[kGuardL1];
+}
+
+// Fixed-order combine of the group partials, then ln L of Eq. 3. The split
+// path also bounds each draw's error and marks the draws above the batch's
+// redo budget: rflag[j] = the draw's rank among the marked draws of its block
+// of 256 positions (-1: not marked), rcnt[block] = their count.
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_b_finalize(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
-                                                    const int64_t* __restrict__ foff, int2* __restrict__ redo) {
+                                                    const int64_t* __restrict__ foff) {
+    __shared__ int swc[4];
+    const int ne = hdr->ne;
+    const double budget = hdr->redo_budget;
+    const int64_t nblk = foff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(foff, ne, b);
+        const EvDev& E = evs[e];
+        const int64_t blk = b - foff[e];
+        const int64_t j = blk * 256 + threadIdx.x;
+        const EvPlan p = *E.plan;
+        bool redo = false;
+        if (j < p.n_active) {
+            const int64_t np = E.npad;
+            const int nd = E.ec.n_det;
+            const int kc = E.kcut[j];
+            double zr = 0.0, zi = 0.0, lin = 0.0, var = 0.0;
+            for (int d = 0; d < nd; ++d) {
+                double ar, ai;
+                combine_groups(E, d, nd, p.n_groups, j, ar, ai);
+                if (SPLIT) {
+                    ar *= kTrigGain;
+                    ai *= kTrigGain;
+                }
+                const double rr = E.resp[(2 * d) * np + j], ri = E.resp[(2 * d + 1) * np + j];
+                zr += rr * ar - ri * ai;
+                zi += rr * ai + ri * ar;
+                if (SPLIT)
+                    split_error(E.guard + d * kGuardStride, hypot(rr, ri), ar, ai,
+                                E.pfx[(int64_t)d * (E.ec.K + 1) + kc], lin, var);
+            }
+            if (SPLIT) {
+                const double err = lin + kEpsInc * sqrt(var);
+                redo = !(err <= budget) || budget <= 0.0;
+            }
+            const double h = E.hh[j];
+            const int64_t i = E.idx[j];
+            if (E.ec.dist)  // k_b_dist integrates over the distance
+                E.zd[j] = make_double2(zr, zi);
+            else
+                E.loglike[i] = loglike_phase(E.ec, zr, zi, h);
+            if (E.aux) {
+                E.aux[3 * i] = zr;
+                E.aux[3 * i + 1] = zi;
+                E.aux[3 * i + 2] = h;
+            }
+        }
+        if (SPLIT) {
+            const uint64_t bal = __ballot(redo);
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+            if (lane == 0) swc[wv] = __popcll(bal);
+            __syncthreads();
+            int before = 0;
+            for (int w = 0; w < wv; ++w) before += swc[w];
+            E.rflag[j] = redo ? before + __popcll(bal & ((1ull << lane) - 1ull)) : -1;
+            if (threadIdx.x == 0) E.rcnt[blk] = (swc[0] + swc[1]) + (swc[2] + swc[3]);
+            __syncthreads();  // swc is reused by the next block
+        }
+    }
+}
+
+// Per event that finalises: exclusive scan of the marked counts of its blocks
+// (in place: rcnt becomes each block's offset) and the plan of the FP64
+// re-evaluation: the event's plan with n_active = marked draws.
+__global__ __launch_bounds__(1024) void k_r_plan(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs) {
+    __shared__ int sh[1024];
+    const int ne = hdr->ne;
+    const int t = threadIdx.x;
+    for (int e = blockIdx.x; e < ne; e += gridDim.x) {
+        const EvDev& E = evs[e];
+        if (!(E.flags & kLlFinalize)) continue;
+        const EvPlan p = E.plan[0];
+        const int nb = (p.n_active + 255) / 256;
+        int carry = 0;
+        for (int base = 0; base < nb; base += 4096) {
+            int v[4], c = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = base + 4 * t + q;
+                v[q] = i < nb ? E.rcnt[i] : 0;
+                c += v[q];
+            }
+            sh[t] = c;
+            __syncthreads();
+            for (int off = 1; off < 1024; off <<= 1) {
+                const int u = t >= off ? sh[t - off] : 0;
+                __syncthreads();
+                sh[t] += u;
+                __syncthreads();
+            }
+            int run = carry + sh[t] - c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = base + 4 * t + q;
+                if (i < nb) E.rcnt[i] = run;
+                run += v[q];
+            }
+            carry += sh[1023];
+            __syncthreads();
+        }
+        if (t == 0) {
+            EvPlan r = p;
+            r.n_active = carry;
+            r.tiles = (carry + kTile - 1) / kTile;
+            E.plan[1] = r;
+        }
+        __syncthreads();
+    }
+}
+
+// Marked draws into the re-evaluation list, in position order.
+__global__ __launch_bounds__(256) void k_r_scatter(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                   const int64_t* __restrict__ foff) {
     const int ne = hdr->ne;
     const int64_t nblk = foff[ne];
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         const int e = find_slot(foff, ne, b);
         const EvDev& E = evs[e];
-        const int64_t j = (b - foff[e]) * 256 + threadIdx.x;
-        const EvPlan p = *E.plan;
-        if (j >= p.n_active) continue;
+        if (E.plan[1].n_active == 0) continue;  // uniform over the block
+        const int64_t blk = b - foff[e];
+        const int64_t j = blk * 256 + threadIdx.x;
+        if (j >= E.plan[0].n_active) continue;
+        const int r = E.rflag[j];
+        if (r >= 0) E.rpos[E.rcnt[blk] + r] = (int)j;
+    }
+}
+
+// Per queue: offsets of every event's re-evaluation items, the item total and
+// the counter reset (the main hot loop has finished with the queues).
+__global__ void k_r_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs, int64_t* __restrict__ ioff) {
+    const int x = threadIdx.x;
+    if (x >= kQueues || blockIdx.x != 0) return;
+    const int ne = hdr->ne;
+    int64_t* o = ioff + (int64_t)x * (ne + 1);
+    int64_t acc = 0;
+    for (int e = 0; e < ne; ++e) {
+        o[e] = acc;
+        if (!(evs[e].flags & kLlFinalize)) continue;
+        const EvPlan r = evs[e].plan[1];
+        if (r.tiles > 0 && r.n_groups > 0) acc += queue_items(r.tiles, r.n_groups, x);
+    }
+    o[ne] = acc;
+    hdr->qitems[x] = (int)acc;
+    hdr->qnext[x] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_r_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                               const int64_t* __restrict__ ioff) {
+    item_loop<true>(hdr, ioff, evs, [&](const Item& it) {
+        const EvDev& E = evs[it.e];
+        const EvPlan rp = load_const(E.plan + 1);
+        switch (E.ec.n_det) {
+            case 1: redo_item<1>(E, rp, it.tile, it.g); break;
+            case 2: redo_item<2>(E, rp, it.tile, it.g); break;
+            case 3: redo_item<3>(E, rp, it.tile, it.g); break;
+            default: redo_item<4>(E, rp, it.tile, it.g); break;
+        }
+    });
+}
+
+// ln L of the re-evaluated draws from their FP64 partials, combined exactly as
+// the FP64 path's finalize combines them.
+__global__ __launch_bounds__(256) void k_r_finalize(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                    const int64_t* __restrict__ foff) {
+    const int ne = hdr->ne;
+    const int64_t nblk = foff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(foff, ne, b);
+        const EvDev& E = evs[e];
+        const EvPlan rp = E.plan[1];
+        const int64_t r = (b - foff[e]) * 256 + threadIdx.x;
+        if (r >= rp.n_active) continue;
+        const int64_t j = E.rpos[r];
         const int64_t np = E.npad;
         const int nd = E.ec.n_det;
-        double zr = 0.0, zi = 0.0, mag = 0.0;
+        double zr = 0.0, zi = 0.0;
         for (int d = 0; d < nd; ++d) {
-            double ar[8], ai[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0.0;
-            for (int c = 0; c < p.n_groups; ++c) {
-                const double2 v = E.partial[((int64_t)c * nd + d) * np + j];
-                ar[c & 7] += v.x;
-                ai[c & 7] += v.y;
-            }
-#pragma unroll
-            for (int w = 4; w > 0; w >>= 1)
-#pragma unroll
-                for (int q = 0; q < w; ++q) {
-                    ar[q] += ar[q + w];
-                    ai[q] += ai[q + w];
-                }
-                if (SPLIT) {
-                ar[0] *= kTrigGain;
-                ai[0] *= kTrigGain;
-            }
+            double ar, ai;
+            combine_groups(E, d, nd, rp.n_groups, r, ar, ai);
             const double rr = E.resp[(2 * d) * np + j], ri = E.resp[(2 * d + 1) * np + j];
-            zr += rr * ar[0] - ri * ai[0];
-            zi += rr * ai[0] + ri * ar[0];
-            mag += hypot(rr, ri) * hypot(ar[0], ai[0]);
-        }
-        if (SPLIT && mag > kRedoMagnitude) {
-            // too large for the split path's error bound: the FP64 pass rewrites this draw
-            const int slot = atomicAdd(&hdr->redo_count, 1);
-            if (slot < hdr->redo_cap)
-                redo[slot] = make_int2(e, (int)j);
-            else
-                atomicOr(E.status, kStRedoFull);
+            zr += rr * ar - ri * ai;
+            zi += rr * ai + ri * ar;
         }
         const double h = E.hh[j];
         const int64_t i = E.idx[j];
-        if (E.ec.dist)  // k_b_dist integrates over the distance (this draw's partials are consumed)
-            E.partial[j] = make_double2(zr, zi);
+        if (E.ec.dist)
+            E.zd[j] = make_double2(zr, zi);
         else
             E.loglike[i] = loglike_phase(E.ec, zr, zi, h);
         if (E.aux) {
@@ -708,8 +948,7 @@ __global__ __launch_bounds__(256) void k_b_finalize(BatchHdr* __restrict__ hdr, 
 }
 
 // Distance-marginalised events: ln L of each live draw from the Z that the
-// finalize (or the FP64 re-evaluation) left in the first partial slot of its
-// position and H, integrated over the distance prior by kDistLanes lanes per
+// finalize (or the FP64 re-evaluation) left in zd at its position and H, integrated over the distance prior by kDistLanes lanes per
 // draw (a block covers a quarter of a finalize block's 256 positions). Kept out
 // of the finalize so that the finalize's register budget (and occupancy) stays
 // that of the plain likelihood; blocks of other events return at once.
@@ -727,89 +966,9 @@ __global__ __launch_bounds__(256) void k_b_dist(const BatchHdr* __restrict__ hdr
         if (!E.ec.dist) continue;
         const int64_t j = (fb - foff[e]) * 256 + (b - fb * kDistLanes) * (256 / kDistLanes) + threadIdx.x / kDistLanes;
         if (j >= E.plan->n_active) continue;  // the same for the draw's lanes
-        const double2 z = E.partial[j];
+        const double2 z = E.zd[j];
         const double ll = loglike_of<kDistLanes>(E.ec, z.x, z.y, E.hh[j], sub);
         if (sub == 0) E.loglike[E.idx[j]] = ll;
-    }
-}
-
-// FP64 re-evaluation of the draws the split finalize listed: one workgroup per
-// draw, lanes over its bins below the cut (FP64 phase, FP64 sincos, complex128
-// weights), a fixed-order reduction (wave butterfly, then the four waves), and
-// ln L as in the finalize.
-__global__ __launch_bounds__(256) void k_b_redo(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
-                                                const int2* __restrict__ redo) {
-    __shared__ double sh[4][2 * PE_MAX_DET];
-    const int n = min(hdr->redo_count, hdr->redo_cap);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int q = blockIdx.x; q < n; q += gridDim.x) {
-        const int2 r = redo[q];
-        const EvDev& E = evs[r.x];
-        const int64_t j = r.y;
-        const int64_t np = E.npad;
-        const int nd = E.ec.n_det;
-        DrawRow row;
-#pragma unroll
-        for (int a = 0; a < 8; ++a) row.A[a] = E.coef[(kCoefA + a) * np + j];
-        row.B5 = E.coef[kCoefB5 * np + j];
-        row.B6 = E.coef[kCoefB6 * np + j];
-        double tau[PE_MAX_DET];
-#pragma unroll
-        for (int d = 0; d < PE_MAX_DET; ++d) tau[d] = (d < nd) ? E.coef[(kCoefTau + d) * np + j] : 0.0;
-        const int kc = E.kcut[j];
-        double zr[PE_MAX_DET], zi[PE_MAX_DET];
-#pragma unroll
-        for (int d = 0; d < PE_MAX_DET; ++d) zr[d] = zi[d] = 0.0;
-        for (int k = threadIdx.x; k < kc; k += 256) {
-            const Rec64 rc = E.rec64[k];
-            const double psi = psi_turns(row.A, row.B5, row.B6, rc.x, rc.xm5, rc.lnx);
-#pragma unroll
-            for (int d = 0; d < PE_MAX_DET; ++d) {
-                if (d >= nd) break;
-                double sn, cs;
-                sincos_turns(fract64(fma(rc.f, tau[d], psi)), sn, cs);
-                const double wr = rc.w[d].x, wi = rc.w[d].y;
-                zr[d] = fma(wr, cs, zr[d]);
-                zr[d] = fma(-wi, sn, zr[d]);
-                zi[d] = fma(-wr, sn, zi[d]);
-                zi[d] = fma(-wi, cs, zi[d]);
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < PE_MAX_DET; ++d) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                zr[d] += __shfl_xor(zr[d], o);
-                zi[d] += __shfl_xor(zi[d], o);
-            }
-            if (lane == 0) {
-                sh[wv][2 * d] = zr[d];
-                sh[wv][2 * d + 1] = zi[d];
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double Zr = 0.0, Zi = 0.0;
-            for (int d = 0; d < nd; ++d) {
-                const double ar = (sh[0][2 * d] + sh[1][2 * d]) + (sh[2][2 * d] + sh[3][2 * d]);
-                const double ai = (sh[0][2 * d + 1] + sh[1][2 * d + 1]) + (sh[2][2 * d + 1] + sh[3][2 * d + 1]);
-                const double rr = E.resp[(2 * d) * np + j], ri = E.resp[(2 * d + 1) * np + j];
-                Zr += rr * ar - ri * ai;
-                Zi += rr * ai + ri * ar;
-            }
-            const double h = E.hh[j];
-            const int64_t i = E.idx[j];
-            if (E.ec.dist)
-                E.partial[j] = make_double2(Zr, Zi);
-            else
-                E.loglike[i] = loglike_phase(E.ec, Zr, Zi, h);
-            if (E.aux) {
-                E.aux[3 * i] = Zr;
-                E.aux[3 * i + 1] = Zi;
-                E.aux[3 * i + 2] = h;
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -837,12 +996,17 @@ static unsigned f64_grid() {
     static const unsigned grid = resident_grid(k_b_f64);
     return grid;
 }
+static unsigned redo_grid() {
+    static const unsigned grid = resident_grid(k_r_f64);
+    return grid;
+}
 
 // Evaluates the hot loop's resident grids (device queries) ahead of any graph
 // capture.
 void prime_hot_grids() {
     (void)split_grid();
     (void)f64_grid();
+    (void)redo_grid();
 }
 
 hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blocks, int64_t finalize_blocks,
@@ -873,13 +1037,20 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
         k_b_f64<<<grid, kTile, 0, st>>>(b.hdr, evs, ioff);
         if (profile) prof_end("loglike_fp64", st);
     }
-    int2* redo = (int2*)(ioff + (int64_t)kQueues * (ne + 1));
     if (finalize_blocks > 0) {
+        const unsigned fg = grid_for(finalize_blocks);
         if (precision == PE_PREC_SPLIT) {
-            k_b_finalize<true><<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2, redo);
-            k_b_redo<<<grid_for(finalize_blocks, 2048), 256, 0, st>>>(b.hdr, evs, redo);
+            k_b_finalize<true><<<fg, 256, 0, st>>>(b.hdr, evs, b.off2);
+            // FP64 re-evaluation of the draws whose error estimate exceeds the budget
+            k_r_plan<<<eg, 1024, 0, st>>>(b.hdr, evs);
+            k_r_scatter<<<fg, 256, 0, st>>>(b.hdr, evs, b.off2);
+            k_r_items<<<1, 64, 0, st>>>(b.hdr, evs, ioff);
+            if (profile) prof_begin("loglike_redo", st);
+            k_r_f64<<<redo_grid(), kTile, 0, st>>>(b.hdr, evs, ioff);
+            if (profile) prof_end("loglike_redo", st);
+            k_r_finalize<<<fg, 256, 0, st>>>(b.hdr, evs, b.off2);
         } else {
-            k_b_finalize<false><<<grid_for(finalize_blocks), 256, 0, st>>>(b.hdr, evs, b.off2, redo);
+            k_b_finalize<false><<<fg, 256, 0, st>>>(b.hdr, evs, b.off2);
         }
         if (any_dist) k_b_dist<<<grid_for(finalize_blocks * kDistLanes), 256, 0, st>>>(b.hdr, evs, b.off2);
     }

@@ -24,7 +24,6 @@ namespace pe {
 namespace {
 
 constexpr int64_t kMaxServerDraws = (int64_t)1 << 22;
-constexpr int kServerRedoCap = 1 << 18;  // split-path FP64 re-evaluations per slice
 
 // First-fit allocator over one device slab in 256-byte granules; frees
 // coalesce with their neighbours.
@@ -360,7 +359,7 @@ pe_status_t pe_server_s::slice() {
     }
     BatchPtrs bll, bw;
     pe_status_t s = upload_area(a_ll, ne, poff[ne], foff[ne], vl.data(), sizeof(EvDev) * ne, poff, &foff,
-                                loglike_scratch_bytes(cap_ne, kServerRedoCap), st, bll, kServerRedoCap);
+                                loglike_scratch_bytes(cap_ne), st, bll);
     if (s == PE_OK)
         s = upload_area(a_w, nw, boff[nw], doff[nw], vw.data(), sizeof(WeightArg) * nw, boff, &doff,
                         sizeof(double4) * cap_wblocks + sizeof(double2) * cap_ne, st, bw);
@@ -406,7 +405,6 @@ pe_status_t pe_server_s::slice() {
         std::memcpy(q->res.stats, h_stage + 8 * i, 4 * sizeof(double));
         int flags = 0;
         std::memcpy(&flags, h_stage + 8 * i + 4, sizeof(int));
-        if ((flags & kStRedoFull) && q->res.status == PE_OK) q->res.status = PE_ERR_BUDGET;
         active.erase(std::find(active.begin(), active.end(), q));
         finish(q, q->res.status);
     }
@@ -485,7 +483,7 @@ pe_status_t pe_server_create(const pe_server_config_t* cfg, pe_server_t* out) {
     s->a_ll.layout_ne = s->a_w.layout_ne = s->cap_ne;
     s->a_ll.layout_rec = sizeof(EvDev);
     s->a_w.layout_rec = sizeof(WeightArg);
-    const size_t ll_bytes = fixed_area_bytes(s->cap_ne, sizeof(EvDev), loglike_scratch_bytes(s->cap_ne, kServerRedoCap));
+    const size_t ll_bytes = fixed_area_bytes(s->cap_ne, sizeof(EvDev), loglike_scratch_bytes(s->cap_ne));
     const size_t w_bytes = fixed_area_bytes(s->cap_ne, sizeof(WeightArg),
                                             sizeof(double4) * s->cap_wblocks + sizeof(double2) * s->cap_ne);
     if ((st = dalloc_bytes(&s->a_ll.dev, ll_bytes)) != PE_OK) return bail(st);
