@@ -276,7 +276,10 @@ pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t *items, int32_t 
  *   w_dev: NULL or [n] normalised weights (sum 1; 0 where ln w = -inf).
  *   stats_dev: 4 doubles = {ESS, ln Z = ln mean(w), max ln w, number of
  *              finite ln w}. With no finite ln w: {0, -inf, -inf, 0}.
- * Needs no event; launches one workgroup.
+ * A NaN or +inf ln w (no weight is defined for it) makes ESS, ln Z, max ln w
+ * and every w NaN; stats_dev[3] still counts the finite ones.
+ * Needs no event; three launches (per-block sums, per-event combine,
+ * normalisation).
  */
 pe_status_t pe_weights_ess(const double *loglike_dev, const double *logprior_dev, const double *logq_dev, int64_t n,
                            double *w_dev, double *stats_dev, void *stream);

@@ -937,13 +937,28 @@ void peo_weights_ess(const double *ll, const double *lp, const double *lq, long 
     long i, nin = 0;
     double m = -INFINITY;
     nsum s1 = {0, 0}, s2 = {0, 0};
+    long bad = 0;
     for (i = 0; i < n; i++) {
         double l = ll[i] + lp[i] - lq[i];
         if (isfinite(l)) {
             nin++;
             if (l > m)
                 m = l;
+        } else if (!(l == -INFINITY)) {
+            bad++; /* NaN or +inf: no weight is defined */
         }
+    }
+    if (bad > 0) {
+        /* an undefined log-weight leaves the normalisation undefined: every
+           estimate is NaN (only -inf, a draw outside the support, has weight 0) */
+        if (w)
+            for (i = 0; i < n; i++)
+                w[i] = NAN;
+        stats[0] = NAN;
+        stats[1] = NAN;
+        stats[2] = NAN;
+        stats[3] = (double)nin;
+        return;
     }
     if (nin == 0) {
         if (w)

@@ -867,7 +867,8 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
     return r;
 }
 
-// part[b] = {max, sum exp(l - max), sum exp(2 (l - max)), finite count}
+// part[b] = {max, sum exp(l - max), sum exp(2 (l - max)), finite count}; a
+// block holding a NaN or +inf log-weight (no weight defined) gets max = NaN.
 __global__ __launch_bounds__(256) void k_w_part(const BatchHdr* __restrict__ hdr, const WeightArg* __restrict__ args,
                                                 const int64_t* __restrict__ boff, double4* __restrict__ part) {
     __shared__ double sh[4];
@@ -878,22 +879,25 @@ __global__ __launch_bounds__(256) void k_w_part(const BatchHdr* __restrict__ hdr
         const WeightArg& A = args[e];
         const int64_t i0 = (b - boff[e]) * kWBlock;
         double l[kWBlock / 256];
-        double m = -INFINITY, cnt = 0.0;
+        double m = -INFINITY, cnt = 0.0, bad = 0.0;
 #pragma unroll
         for (int j = 0; j < kWBlock / 256; ++j) {
             const int64_t i = i0 + threadIdx.x + 256 * j;
             double v = -INFINITY;
             if (i < A.n) v = A.ll[i] + A.lp[i] - A.lq[i];
-            if (!isfinite(v)) v = -INFINITY;
+            if (!isfinite(v)) {
+                if (!(v == -INFINITY)) bad += 1.0;
+                v = -INFINITY;
+            }
             l[j] = v;
             if (v > -INFINITY) {
                 m = fmax(m, v);
                 cnt += 1.0;
             }
         }
-        const double M = block_max256(m, sh);
+        const double M = block_sum256(bad, sh) > 0.0 ? NAN : block_max256(m, sh);
         double s1 = 0.0, s2 = 0.0;
-        if (M > -INFINITY) {
+        if (M > -INFINITY) {  // false for NaN
 #pragma unroll
             for (int j = 0; j < kWBlock / 256; ++j) {
                 if (l[j] > -INFINITY) {
@@ -920,14 +924,19 @@ __global__ __launch_bounds__(256) void k_w_final(const BatchHdr* __restrict__ hd
     for (int e = blockIdx.x; e < ne; e += gridDim.x) {
         const WeightArg& A = args[e];
         const int64_t b0 = boff[e], b1 = boff[e + 1];
-        double m = -INFINITY;
-        for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) m = fmax(m, part[b].x);
-        const double M = block_max256(m, sh);
-        double a = 0.0, ac = 0.0, q = 0.0, qc = 0.0, cnt = 0.0;
+        double m = -INFINITY, bad = 0.0, cnt = 0.0;
+        for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) {
+            const double4 p = part[b];
+            cnt += p.w;
+            if (isnan(p.x)) bad += 1.0;
+            else m = fmax(m, p.x);
+        }
+        const double nbad = block_sum256(bad, sh);
+        const double M = nbad > 0.0 ? -INFINITY : block_max256(m, sh);
+        double a = 0.0, ac = 0.0, q = 0.0, qc = 0.0;
         if (M > -INFINITY) {
             for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) {
                 const double4 p = part[b];
-                cnt += p.w;
                 if (p.x > -INFINITY) {
                     const double r = exp(p.x - M);
                     neumaier(a, ac, p.y * r);
@@ -939,7 +948,13 @@ __global__ __launch_bounds__(256) void k_w_final(const BatchHdr* __restrict__ hd
         const double S2 = block_sum256(q + qc, sh);
         const double nin = block_sum256(cnt, sh);
         if (threadIdx.x == 0) {
-            if (nin == 0.0) {
+            if (nbad > 0.0) {  // an undefined log-weight: every estimate is NaN
+                A.stats[0] = NAN;
+                A.stats[1] = NAN;
+                A.stats[2] = NAN;
+                A.stats[3] = nin;
+                fin[e] = make_double2(NAN, NAN);
+            } else if (nin == 0.0) {
                 A.stats[0] = 0.0;
                 A.stats[1] = -INFINITY;
                 A.stats[2] = -INFINITY;
@@ -968,7 +983,7 @@ __global__ __launch_bounds__(256) void k_w_norm(const BatchHdr* __restrict__ hdr
         if (!A.w || i >= A.n) continue;
         const double l = A.ll[i] + A.lp[i] - A.lq[i];
         const double2 f = fin[e];
-        A.w[i] = (isfinite(l) && f.y > 0.0) ? exp(l - f.x) * f.y : 0.0;
+        A.w[i] = isnan(f.x) ? NAN : (isfinite(l) && f.y > 0.0) ? exp(l - f.x) * f.y : 0.0;
     }
 }
 

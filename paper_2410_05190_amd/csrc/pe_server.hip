@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <climits>
 #include <condition_variable>
 #include <cstring>
@@ -405,6 +406,9 @@ pe_status_t pe_server_s::slice() {
         std::memcpy(q->res.stats, h_stage + 8 * i, 4 * sizeof(double));
         int flags = 0;
         std::memcpy(&flags, h_stage + 8 * i + 4, sizeof(int));
+        // a NaN ESS: some log-weight was NaN or +inf (no weight defined)
+        if (((flags & kStNonfinite) || std::isnan(q->res.stats[0])) && q->res.status == PE_OK)
+            q->res.status = PE_ERR_NONFINITE;
         active.erase(std::find(active.begin(), active.end(), q));
         finish(q, q->res.status);
     }

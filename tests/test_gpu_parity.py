@@ -240,6 +240,16 @@ def test_weights_parity_and_identities():
     w, st = binding.weights_ess(dev(np.full(10, -np.inf)), dev(np.zeros(10)), dev(np.zeros(10)))
     s = host(st)
     assert s[0] == 0 and s[3] == 0 and s[1] == -np.inf and np.all(host(w) == 0)
+    # a NaN or +inf log-weight: every estimate NaN, the finite count kept (as the oracle); the bad
+    # entry sits in the second of three weight blocks
+    rng = np.random.default_rng(12)
+    for bad in (np.nan, np.inf):
+        ll = rng.normal(size=9000)
+        ll[[5, 6000]] = [-np.inf, bad]
+        w, st = binding.weights_ess(dev(ll), dev(np.zeros(9000)), dev(np.zeros(9000)))
+        w_o, st_o = oracle.weights_ess(ll, np.zeros(9000), np.zeros(9000))
+        s = host(st)
+        assert np.all(np.isnan(host(w))) and np.all(np.isnan(s[:3])) and s[3] == st_o[3] == 8998
 
 
 def test_split_weights_and_ess_within_tolerance():

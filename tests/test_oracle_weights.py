@@ -158,3 +158,19 @@ def test_whole_chain_evidence_and_means_against_grid_quadrature():
     # IS estimate of ln Z has relative error ~ 1/sqrt(ESS)
     assert abs(lnz_is - lnz_grid) < 5.0 / math.sqrt(ess)
     assert np.all(np.abs(mean_is - mean_grid) < 5 * post_sd / math.sqrt(ess))
+
+
+def test_undefined_log_weight_makes_every_estimate_nan():
+    """A NaN or +inf log-weight has no weight (Eq. 5 needs a finite likelihood ratio or an
+    excluded draw): ESS, ln Z, max ln w and every weight are NaN, the finite count stays;
+    -inf alone is a draw outside the support, weight 0."""
+    rng = np.random.default_rng(5)
+    for bad in (np.nan, np.inf):
+        ll = rng.normal(size=500)
+        ll[[3, 77]] = [-np.inf, bad]
+        w, st = _ws(ll)
+        assert np.all(np.isnan(w)) and np.all(np.isnan(st[:3])) and st[3] == 498
+    ll = rng.normal(size=500)
+    ll[3] = -np.inf
+    w, st = _ws(ll)
+    assert np.isfinite(st).all() and w[3] == 0 and st[3] == 499
