@@ -285,6 +285,22 @@ pe_status_t pe_weights_ess(const double *loglike_dev, const double *logprior_dev
                            double *w_dev, double *stats_dev, void *stream);
 
 /*
+ * pe_weights_ess for callers that cannot allocate device or pinned memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same kernels and results bit for bit, but the
+ * stage's batch record and per-block partial sums live in a fixed scratch
+ * array in the library's device memory (about 130 KB per GPU, held until the
+ * process ends) instead of buffers the library allocates on first use. The
+ * call only enqueues kernels on `stream`; it calls no allocator. Every call on
+ * a GPU shares that GPU's scratch, so calls that overlap on one GPU (other
+ * streams, other threads) race; calls ordered on one stream do not.
+ * Errors: PE_ERR_ARG (n < 0, n > 2^24 (the scratch's limit), NULL pointers),
+ * PE_ERR_HIP.
+ */
+pe_status_t pe_weights_ess_noalloc(const double *loglike_dev, const double *logprior_dev, const double *logq_dev,
+                                   int64_t n, double *w_dev, double *stats_dev, void *stream);
+
+/*
  * Model waveform of one parameter point on the event grid, FP64:
  * h_dev[d][k] = s R_d f_k^(-7/6) exp(-i Phi_d(f_k)) for f_k < f_isco, else 0,
  * interleaved complex128. If psd_dev is not NULL (layout as desc), also writes

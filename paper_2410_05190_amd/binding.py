@@ -33,7 +33,7 @@ PE_F32 = 1
 MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
-           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_proposal_update", "pe_refine", "pe_slice_sample", "pe_tile_bank",
+           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_weights_ess_noalloc", "pe_proposal_update", "pe_refine", "pe_slice_sample", "pe_tile_bank",
            "pe_tile_assign", "pe_tile_draw", "pe_tile_reweight", "pe_relbin_setup", "pe_relbin_edges",
            "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
@@ -142,6 +142,7 @@ def load(path=LIB_PATH):
         "pe_loglike_multi": (i32, [i32, vp, vp, vp, i32, vp, vp, vp]),
         "pe_batch_run": (i32, [i32, vp, i32, i32, vp]),
         "pe_weights_ess": (i32, [dp, dp, dp, i64, dp, dp, vp]),
+        "pe_weights_ess_noalloc": (i32, [dp, dp, dp, i64, dp, dp, vp]),
         "pe_proposal_update": (i32, [vp, dp, dp, i64, dp, dp, dp, vp]),
         "pe_slice_sample": (i32, [vp, ctypes.POINTER(Slice), u64, u32, i64, i64, dp, dp, dp, vp, vp]),
         "pe_tile_bank": (i32, [vp, ctypes.POINTER(Slice), ctypes.c_double, u64, u32, i32, i32, ctypes.c_double, i32,
@@ -333,6 +334,14 @@ def pe_weights_ess(loglike, logprior, logq, n, w, stats, stream=None):
     import torch
     f64 = torch.float64
     _check(load().pe_weights_ess(_ptr(loglike, f64, "loglike"), _ptr(logprior, f64, "logprior"),
+                                 _ptr(logq, f64, "logq"), int(n), _ptr(w, f64, "w", allow_none=True),
+                                 _ptr(stats, f64, "stats"), _stream(stream)))
+
+
+def pe_weights_ess_noalloc(loglike, logprior, logq, n, w, stats, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(load().pe_weights_ess_noalloc(_ptr(loglike, f64, "loglike"), _ptr(logprior, f64, "logprior"),
                                  _ptr(logq, f64, "logq"), int(n), _ptr(w, f64, "w", allow_none=True),
                                  _ptr(stats, f64, "stats"), _stream(stream)))
 

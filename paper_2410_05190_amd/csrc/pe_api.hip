@@ -630,6 +630,61 @@ void prof_end(const char* name, hipStream_t st) {
     g_prof_open.erase(it);
 }
 
+// ------------------------------------------------ allocation-free weights
+// pe_weights_ess_noalloc keeps its batch header, argument record, offsets and
+// per-block partial sums in the file-scope device array `scratch` (one copy
+// per GPU, held until the process ends). Host code never hands the array's
+// name to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returns, taken once per device (with that device
+// current) on the entry point's first call there.
+constexpr int64_t kNoAllocMaxDraws = (int64_t)1 << 24;
+constexpr size_t kNoAllocArgs = 256, kNoAllocOff = 512, kNoAllocOff2 = 768, kNoAllocPart = 1024;
+constexpr size_t kNoAllocBytes =
+    kNoAllocPart + sizeof(double4) * (size_t)(kNoAllocMaxDraws / kWBlock) + sizeof(double2) + 256;
+static_assert(sizeof(BatchHdr) <= kNoAllocArgs, "batch header fits its slot");
+static_assert(kNoAllocArgs + sizeof(WeightArg) <= kNoAllocOff, "argument record fits its slot");
+
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kNoAllocDevices] = {};
+
+// The current device's address of `scratch`.
+pe_status_t noalloc_scratch(char** out) {
+    int dev = 0;
+    PE_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocDevices) return fail(PE_ERR_ARG, "device index beyond the supported 64");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PE_ERR_HIP, std::string("address of the allocation-free scratch: ") + hipGetErrorString(e));
+        g_noalloc_ptr[dev] = (char*)p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return PE_OK;
+}
+
+// Writes the one-event batch of the weights stage into the scratch: header,
+// argument record (passed by value) and the two offset arrays.
+__global__ void k_noalloc_weights_area(char* __restrict__ base, WeightArg a, int64_t nb, int64_t nd) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    BatchHdr h = {};
+    h.ne = 1;
+    h.total = nb;
+    h.total2 = nd;
+    *(BatchHdr*)base = h;
+    *(WeightArg*)(base + kNoAllocArgs) = a;
+    int64_t* o = (int64_t*)(base + kNoAllocOff);
+    o[0] = 0;
+    o[1] = nb;
+    int64_t* o2 = (int64_t*)(base + kNoAllocOff2);
+    o2[0] = 0;
+    o2[1] = nd;
+}
+
 pe_status_t check_n(int64_t n) {
     if (n < 0 || n > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "n must be in 0..2^30");
     return PE_OK;
@@ -835,6 +890,30 @@ pe_status_t pe_weights_ess(const double* loglike_dev, const double* logprior_dev
     if (n > 0 && (!loglike_dev || !logprior_dev || !logq_dev)) return fail(PE_ERR_ARG, "inputs are NULL");
     WeightArg w = {loglike_dev, logprior_dev, logq_dev, n, w_dev, stats_dev};
     return run_weights(std::vector<WeightArg>(1, w), as_stream(stream));
+}
+
+pe_status_t pe_weights_ess_noalloc(const double* loglike_dev, const double* logprior_dev, const double* logq_dev,
+                                   int64_t n, double* w_dev, double* stats_dev, void* stream) {
+    if (n < 0) return fail(PE_ERR_ARG, "n must be >= 0");
+    if (n > kNoAllocMaxDraws) return fail(PE_ERR_ARG, "n exceeds 2^24, the limit of the allocation-free scratch");
+    if (!stats_dev) return fail(PE_ERR_ARG, "stats must be a device pointer");
+    if (n > 0 && (!loglike_dev || !logprior_dev || !logq_dev)) return fail(PE_ERR_ARG, "inputs are NULL");
+    char* base = nullptr;
+    pe_status_t s = noalloc_scratch(&base);
+    if (s != PE_OK) return s;
+    const WeightArg a = {loglike_dev, logprior_dev, logq_dev, n, w_dev, stats_dev};
+    const int64_t nb = (n + kWBlock - 1) / kWBlock, nd = blocks256(n);
+    hipStream_t st = as_stream(stream);
+    k_noalloc_weights_area<<<1, 64, 0, st>>>(base, a, nb, nd);
+    PE_HIP(hipGetLastError());
+    BatchPtrs b;
+    b.hdr = (BatchHdr*)base;
+    b.args = base + kNoAllocArgs;
+    b.off = (int64_t*)(base + kNoAllocOff);
+    b.off2 = (int64_t*)(base + kNoAllocOff2);
+    b.scratch = (double*)(base + kNoAllocPart);
+    PE_HIP(launch_weights_batch(b, 1, nb, nd, st));
+    return PE_OK;
 }
 
 pe_status_t pe_proposal_update(pe_event_t ev, const double* theta_dev, const double* w_dev, int64_t n,
