@@ -40,6 +40,16 @@ FP64_OPS_PER_TERM = 2 + 26 + 4
 # loglike_split_config1.md); None when the kernel has changed since the counters were taken.
 SPLIT_TRAFFIC_BYTES = 528995276
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# Algorithmic floating-point work per term (draw, detector, bin) of the split path: the FP64
+# phase polynomial (about 24 flops with its log term and scaling) shared by the detectors plus
+# the FP64 time-shift FMA and fract (3); the FP32 complex multiply-accumulate (8; the sine/cosine
+# pair is not counted as flops). Vector peaks: FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s.
+PSI_FLOP64_PER_DRAW_BIN = 24.0
+FLOP64_PER_TERM = 3.0
+FLOP32_PER_TERM = 8.0
+FP64_PEAK = 78.6e12
+FP32_PEAK = 157.3e12
+SPLIT_TRAFFIC_SOURCE = "rocprofv3 FETCH_SIZE x 1.9999 + WRITE_SIZE x 1.0 per launch (profiles/loglike_split_config1.md)"
 
 
 def parse():
@@ -54,7 +64,8 @@ def parse():
                     help="pick the hot loop's plan with the library's autotuner before timing (auto: batches and "
                          "small events)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--cpu-sample", type=int, default=1024,
+                    help="cpu_baseline: in-support draws of the benchmark event timed on the oracle")
     ap.add_argument("--serve-events", type=int, default=120,
                     help="requests of the serving load (Poisson arrivals); 0 skips the serving leg")
     ap.add_argument("--serve-rate", type=float, default=5.0, help="arrival rate of the serving load (1/s)")
@@ -76,6 +87,11 @@ def parse():
                     help="tile-mixture leg: slice candidates for the prior samples (0 skips the leg; 4-D only)")
     ap.add_argument("--no-distance-leg", action="store_true",
                     help="skip the distance-marginalised leg (11-D configurations)")
+    ap.add_argument("--no-batch-leg", action="store_true",
+                    help="skip the config-2 leg (64 BBH events per step through pe_batch_run) of the default run")
+    ap.add_argument("--long-steps", type=int, default=3,
+                    help="config-4 leg: timed steps per event (SNR 43 and SNR 95); 0 skips the leg")
+    ap.add_argument("--long-loud-snr", type=float, default=95.0, help="config-4 leg: SNR of the loud event")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (HBM counter calibration)")
     return ap.parse_args()
@@ -206,6 +222,8 @@ def main():
     ops_last = db_last * PSI_OPS_PER_DRAW_BIN + terms_last * ops_per_term
     achieved = ops_last / k_avg_s if k_avg_s > 0 else float("nan")
     traffic = SPLIT_TRAFFIC_BYTES if (prec == binding.PE_PREC_SPLIT and c == 1 and not args.chunks) else None
+    fvec = vector_fraction(db_last, terms_last, nd, k_avg_s) if prec == binding.PE_PREC_SPLIT else None
+    redo_last = [binding.pe_loglike_counts(x["ev"]) for x in evs]
 
     out = {
         "metric": "likelihood evals/s and ESS/s per event; p50/p99 event latency under load",
@@ -233,7 +251,11 @@ def main():
                              f"one batch of {n_events} events, one batch at a time"},
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": traffic,
-                     "kernel_ms_avg": k_avg_s * 1e3, "kernel_launches": k_n, "ops_per_launch": ops_last},
+                     "traffic_source": SPLIT_TRAFFIC_SOURCE if traffic else None,
+                     "kernel_ms_avg": k_avg_s * 1e3, "kernel_launches": k_n, "ops_per_launch": ops_last,
+                     "frac_vector": fvec},
+        "split_reevaluated_fp64": {"draws_last_step": int(sum(r[1] for r in redo_last)),
+                                   "live_last_step": int(sum(r[0] for r in redo_last))},
     }
     first = evs[0]
     # the drift check reads the last timed step's draws and log-likelihoods: before the other legs
@@ -255,12 +277,140 @@ def main():
     for x in evs:
         x["ev"].close()
 
+    if c == 1 and not args.no_batch_leg:
+        out["config2"] = batch_leg(2, max(args.steps, 1), prec)
+    if c == 1 and args.long_steps > 0:
+        out["config4"] = long_leg(args.long_steps, args.long_loud_snr, prec)
     if args.serve_events > 0:
         out["serving"] = serve_bench(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_sample, first["data"], first["psd"], first["theta_inj"],
                                            first["amp0"], first["common"])
+        if c == 1:
+            out["cpu_baseline"]["config0_full"] = cpu_config0()
+            if "config4" in out:
+                out["cpu_baseline"]["config4_sample"] = out["config4"]["snr_43"]["drift"]["oracle_rate"]
     print(json.dumps(out), flush=True)
+
+
+def vector_fraction(draw_bins, terms, n_det, t_s):
+    """Vector-ALU fraction of the split hot kernel by algorithmic FLOPs: FP64 (phase polynomial per
+    (draw, bin), time shift and fract per term) against 78.6 TFLOP/s plus FP32 (complex MAC per term)
+    against 157.3 TFLOP/s, over the kernel's average launch time."""
+    if not t_s > 0:
+        return None
+    f64 = draw_bins * PSI_FLOP64_PER_DRAW_BIN + terms * FLOP64_PER_TERM
+    f32 = terms * FLOP32_PER_TERM
+    return {"frac": f64 / (FP64_PEAK * t_s) + f32 / (FP32_PEAK * t_s), "flop64_per_launch": f64,
+            "flop32_per_launch": f32, "fp64_tflops": f64 / t_s / 1e12, "fp32_tflops": f32 / t_s / 1e12,
+            "counts": "per term: FP64 24/n_det + 3, FP32 8 (sine/cosine not counted)"}
+
+
+def batch_leg(c, steps, prec):
+    """Config 2: 64 BBH-mass events of 2^14..2^18 draws, every stage one set of launches over the batch
+    (pe_batch_run), the hot loop's plan from the autotuner. Evals/s, ESS/s, the batch's latency and the
+    hot kernel's share."""
+    import numpy as np
+    import torch
+
+    from paper_2410_05190_amd import binding, synth
+
+    cfg = synth.CONFIGS[c]
+    n_ev = cfg.get("batch", 64)
+    Ns = synth.n_draws_batch(c, n_ev)
+    evs = [make_event(c, e, N) for e, N in enumerate(Ns)]
+    st = torch.zeros((steps, n_ev, 4), dtype=torch.float64, device="cuda")
+    kname = "loglike_split" if prec == binding.PE_PREC_SPLIT else "loglike_fp64"
+
+    def step(i, rows):
+        items = [binding.make_item(x["ev"], n=x["N"], data=x["data"], psd=x["psd"], theta0=x["theta0"],
+                                   seed=x["seed"], stream_id=i, g=x["g"], theta=x["theta"], logq=x["lq"],
+                                   logprior=x["lp"], loglike=x["ll"], w=x["w"], stats=rows[e])
+                 for e, x in enumerate(evs)]
+        binding.pe_batch_run(items, binding.PE_STAGE_ALL, prec)
+
+    keep = binding.pe_get_plan()
+    for i in range(3):
+        step(900 + i, st[0])
+    torch.cuda.synchronize()
+    it, mb, best = binding.pe_autotune_plan([x["ev"] for x in evs], [x["theta"] for x in evs],
+                                            [x["N"] for x in evs], prec, reps=2)
+    binding.pe_set_plan(it, mb)
+    for i in range(10):  # warm-up at the tuned plan (first-use costs of the plan's shapes)
+        step(950 + i, st[0])
+    binding.pe_profile_enable(True)
+    binding.pe_profile_read(kname)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i, st[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    binding.pe_profile_enable(False)
+    k_ms, k_n = binding.pe_profile_read(kname)
+    binding.pe_set_plan(*keep)
+    for x in evs:
+        x["ev"].status()
+    s = st.cpu().numpy()
+    wall = t1 - t0
+    redo = [binding.pe_loglike_counts(x["ev"]) for x in evs]
+    for x in evs:
+        x["ev"].close()
+    return {"workload": cfg["name"], "events_per_step": n_ev, "draws_per_step": int(sum(Ns)),
+            "n_bins": synth.grid(c)[2], "n_det": cfg["n_det"], "steps": steps, "ms_per_step": 1e3 * wall / steps,
+            "evals_per_s": float(s[:, :, 3].sum()) / wall, "ess_per_s": float(s[:, :, 0].sum()) / wall,
+            "ess_per_event_mean": float(s[:, :, 0].mean()), "hot_kernel_ms_avg": k_ms / max(k_n, 1),
+            "plan": {"items_target": it, "min_group_bins": mb, "autotune_best_loglike_ms": best},
+            "split_reevaluated_fp64": int(sum(r[1] for r in redo)),
+            "kind": "every stage one set of launches over the 64 events (pe_batch_run)"}
+
+
+def long_leg(steps, loud_snr, prec):
+    """Config 4 (3 detectors, K = 2 086 912, 262 144 draws): the benchmark step on event 0 (SNR 43) and
+    on event 1 at SNR `loud_snr` (the top of the configuration's range), each after one untimed step.
+    Step time, hot-kernel time, the draws the split path re-evaluated in FP64, and the FP64-phase drift
+    against the oracle (1024 draws of SNR 43, 256 of the loud event)."""
+    import torch
+
+    from paper_2410_05190_amd import binding, synth
+
+    kname = "loglike_split" if prec == binding.PE_PREC_SPLIT else "loglike_fp64"
+    N = synth.CONFIGS[4]["n_draws"]
+    res = {"workload": synth.CONFIGS[4]["name"], "n_bins": synth.grid(4)[2], "draws_per_event": N}
+    for key, e, snr, n_drift in (("snr_43", 0, None, 1024), ("snr_loud", 1, loud_snr, 256)):
+        x = make_event(4, e, N, snr=snr)
+        h_ = x["ev"].handle
+        st = torch.zeros((steps, 4), dtype=torch.float64, device="cuda")
+        binding.pe_profile_enable(True)
+        for i in range(-1, steps):
+            if i == 0:
+                torch.cuda.synchronize()
+                binding.pe_profile_read(kname)
+                binding.pe_profile_read("loglike_redo")
+                t0 = time.perf_counter()
+            binding.pe_event_update(h_, x["data"], x["psd"])
+            binding.pe_metric(h_, x["theta0"], None, 0, x["g"])
+            binding.pe_draw(h_, x["theta0"], x["g"], x["seed"], max(i, 0), N, x["theta"], x["lq"], x["lp"])
+            binding.pe_loglike_batch(h_, x["theta"], N, prec, x["ll"], None)
+            binding.pe_weights_ess(x["ll"], x["lp"], x["lq"], N, x["w"], st[max(i, 0)])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        binding.pe_profile_enable(False)
+        k_ms, k_n = binding.pe_profile_read(kname)
+        r_ms, r_n = binding.pe_profile_read("loglike_redo")
+        live, redo = binding.pe_loglike_counts(x["ev"])
+        x["ev"].status()
+        s = st.cpu().numpy()
+        res[key] = {"snr": float(snr) if snr else float(synth.injection(4, e)["snr"]), "steps": steps,
+                    "ms_per_step": 1e3 * (t1 - t0) / steps, "evals_per_s": float(s[:, 3].sum()) / (t1 - t0),
+                    "ess_per_event_mean": float(s[:, 0].mean()), "hot_kernel_ms_avg": k_ms / max(k_n, 1),
+                    "reevaluation_ms_avg": r_ms / max(r_n, 1), "live_last_step": live,
+                    "reevaluated_fp64_last_step": redo,
+                    "drift": drift_leg(x, n_drift, prec)}
+        x["ev"].close()
+        del x
+    res["loud_over_quiet_step_time"] = res["snr_loud"]["ms_per_step"] / res["snr_43"]["ms_per_step"]
+    return res
 
 
 def refine_leg(x, rounds, n_round, steps, prec):
@@ -480,10 +630,11 @@ def tile_leg(x, args, steps, prec):
     }
 
 
-def make_data(c, e, nd=None):
+def make_data(c, e, nd=None, snr=None):
     """Synthetic event e of configuration c (nd detectors: the first nd of the configuration's network)
     on the device: the injection is made by the library's own waveform (amplitude or distance set to the
-    target SNR), plus seeded noise. Returns the description and device data."""
+    target SNR; `snr` overrides the configuration's draw), plus seeded noise. Returns the description and
+    device data."""
     import numpy as np
     import torch
 
@@ -514,10 +665,11 @@ def make_data(c, e, nd=None):
     binding.pe_waveform(desc1, torch.from_numpy(theta_inj).cuda(), psd_t, h, snr2)
     rho1 = math.sqrt(float(snr2.item()))
     amp0 = 0.0
+    target = float(snr) if snr else inj["snr"]
     if four_d:
-        amp0 = inj["snr"] / rho1
+        amp0 = target / rho1
     else:
-        theta_inj[8] = rho1 / inj["snr"]
+        theta_inj[8] = rho1 / target
     desc = binding.make_desc(nd, K, data_dtype=ddt, psd_dtype=pdt, amp0=amp0, **common)
     binding.pe_waveform(desc, torch.from_numpy(theta_inj).cuda(), psd_t, h, snr2)
     noise = torch.from_numpy(synth.noise(c, e, S, df) * s).cuda()
@@ -527,13 +679,13 @@ def make_data(c, e, nd=None):
     return {"desc": desc, "data": data, "psd": psd_t, "theta_inj": theta_inj, "amp0": amp0, "common": common}
 
 
-def make_event(c, e, N, nd=None):
+def make_event(c, e, N, nd=None, snr=None):
     """make_data plus an event with its device buffers for N draws."""
     import torch
 
     from paper_2410_05190_amd import binding, synth
 
-    x = make_data(c, e, nd)
+    x = make_data(c, e, nd, snr)
     ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], **x["common"])
     ev.reserve(N)
     D = ev.dim
@@ -680,7 +832,13 @@ def drift_leg(x, n_sample, prec):
     bound = 2 * 16 * np.finfo(np.float64).eps * phin * sabs
     df_ = np.abs(ll_fast - ll_o)
     d64 = np.abs(ll64 - ll_o)
-    return {"draws": int(live.size), "oracle_s": t1 - t0, "phase_newtonian_rad_at_f_lo": 2 * math.pi * phin,
+    threads = os.cpu_count() or 1
+    terms = float(d_h.shape[0] * host_cut(th, cm, d_h.shape[1]).sum())
+    rate = {"value": live.size / (t1 - t0), "unit": "likelihood evals/s", "cores": threads,
+            "per_core": live.size / (t1 - t0) / threads, "terms_per_s": terms / (t1 - t0), "kind": "oracle",
+            "sample": f"{live.size} in-support draws of the timed step, K = {d_h.shape[1]}"}
+    return {"draws": int(live.size), "oracle_s": t1 - t0, "oracle_rate": rate,
+            "phase_newtonian_rad_at_f_lo": 2 * math.pi * phin,
             "timed_path": {"precision": "split" if prec == binding.PE_PREC_SPLIT else "fp64",
                            "max_abs_dlnL": float(df_.max()), "median_abs_dlnL": float(np.median(df_)),
                            "bound": 1e-3 if prec == binding.PE_PREC_SPLIT else bound},
@@ -712,9 +870,66 @@ def cpu_baseline(c, n_sample, data, psd_t, theta_inj, amp0, common):
     ll = ev.loglike(th, n_threads=threads)
     t3 = time.perf_counter()
     oracle.weights_ess(ll, lp[live], lq[live])
+    terms = float(d_h.shape[0] * host_cut(th, common, d_h.shape[1]).sum())
     return {"value": live.size / (t3 - t2), "unit": "likelihood evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{live.size} in-support draws of the same event (oracle's own metric and draws); "
+            "per_core": live.size / (t3 - t2) / threads, "terms_per_s": terms / (t3 - t2),
+            "terms_per_s_per_core": terms / (t3 - t2) / threads,
+            "sample": f"{live.size} in-support draws of the benchmark event (oracle's own metric and draws); "
                       f"oracle metric {t1 - t0:.1f} s single-threaded, not in value"}
+
+
+def cpu_config0():
+    """The oracle on config 0 at full size: the 4096 draws of the event (its own metric and draws),
+    all host threads."""
+    import numpy as np
+
+    import oracle
+    from paper_2410_05190_amd import synth
+
+    c = 0
+    cfg = synth.CONFIGS[c]
+    f_lo, df, K = synth.grid(c)
+    f = synth.frequencies(f_lo, df, K)
+    S = synth.psd_analytic(f)[None, :]
+    geom = synth.detectors(c, 1)
+    inj = synth.injection(c, 0)
+    th0 = inj["theta"].copy()
+    common = dict(params=oracle.PARAMS_4D, phase=oracle.PHASE_MARG, gmst=0.0, chi_max=cfg["chi_max"],
+                  dl_max=cfg["dl_max"] or 1e4, det_geom=geom)
+    ref = oracle.Event(1, K, f_lo, df, data=None, psd=S, strain_scale=1.0, amp0=1.0, **common)
+    h1 = ref.waveform(th0)
+    amp0 = inj["snr"] / math.sqrt(ref.inner(0, h1, h1))
+    inj_ev = oracle.Event(1, K, f_lo, df, data=None, psd=S, strain_scale=1.0, amp0=amp0, **common)
+    data = np.ascontiguousarray(inj_ev.waveform(th0) + synth.noise(c, 0, S, df), dtype=np.complex128)
+    ev = oracle.Event(1, K, f_lo, df, data=data, psd=np.ascontiguousarray(S), strain_scale=1.0, amp0=amp0, **common)
+    threads = os.cpu_count() or 1
+    g = ev.metric(th0)
+    rc, th, lq, lp = ev.draw(th0, g, 12345, 0, cfg["n_draws"])
+    t0 = time.perf_counter()
+    ll = ev.loglike(th, n_threads=threads)
+    t1 = time.perf_counter()
+    live = int(np.isfinite(ll).sum())
+    terms = float(host_cut(th[:, np.isfinite(ll)], dict(f_lo=f_lo, df=df, params=oracle.PARAMS_4D), K).sum())
+    return {"value": th.shape[1] / (t1 - t0), "unit": "draws/s (all 4096, in and out of support)",
+            "live_evals_per_s": live / (t1 - t0), "cores": threads, "per_core": th.shape[1] / (t1 - t0) / threads,
+            "terms_per_s": terms / (t1 - t0), "sample": f"config 0 at full size: {th.shape[1]} draws, K = {K}"}
+
+
+def host_cut(theta, common, K):
+    """ISCO cut (bins below f_isco) of each draw on the host, from the masses alone."""
+    import numpy as np
+
+    from paper_2410_05190_amd import binding
+    tsun = 1.32712440018e20 / 299792458.0 ** 3
+    with np.errstate(all="ignore"):
+        if common["params"] == binding.PE_PARAMS_4D:
+            M = theta[0] * theta[1] ** -0.6
+        else:
+            q = theta[1]
+            M = theta[0] * (1 + q) ** 1.2 * q ** -0.6
+        fisco = 1.0 / (6.0 ** 1.5 * math.pi * M * tsun)
+        kc = np.clip(np.ceil((fisco - common["f_lo"]) / common["df"]), 0, K)
+    return np.nan_to_num(kc)
 
 
 

@@ -148,6 +148,8 @@ size_t layout_tables(pe_event_s* ev, char* base) {
     ev->rec64 = c.take<Rec64>((size_t)(K + kTabPad));
     ev->pw = c.take<double>((size_t)nd * K);
     ev->pfx = c.take<double>((size_t)nd * (K + 1));
+    ev->pl1 = c.take<double>((size_t)nd * (K + 1));
+    ev->pw2 = c.take<double>((size_t)nd * (K + 1));
     ev->guard = c.take<double>((size_t)kGuardLen);
     ev->status = c.take<int>(1);
     ev->mws = c.take<double>((size_t)kMwsTotal);
@@ -420,6 +422,8 @@ PrepArg prep_arg(const pe_event_s* ev, const void* data, const void* psd) {
     a.rec64 = ev->rec64;
     a.pw = ev->pw;
     a.pfx = ev->pfx;
+    a.pl1 = ev->pl1;
+    a.pw2 = ev->pw2;
     a.seg = ev->mws + kMwsScan;
     a.guard = ev->guard;
     a.status = ev->status;
@@ -512,6 +516,8 @@ EvDev loglike_arg(const pe_event_s* ev, const double* theta, int64_t n, double* 
     d.rec32 = ev->rec32;
     d.rec64 = ev->rec64;
     d.pfx = ev->pfx;
+    d.pl1 = ev->pl1;
+    d.pw2 = ev->pw2;
     d.guard = ev->guard;
     d.kc_all = ev->kc_all;
     d.hist = ev->hist;

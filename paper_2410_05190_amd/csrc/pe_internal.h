@@ -109,6 +109,7 @@ struct PrepArg {
     Rec32 *rec32;
     Rec64 *rec64;
     double *pw, *pfx, *seg;
+    double *pl1, *pw2;  // [n_det][K+1] exclusive prefixes of |w| and |w|^2 (split-path error estimate)
     double *guard;  // [PE_MAX_DET][kGuardStride] noise statistics of the data (split-path error estimate)
     int *status;
 };
@@ -143,6 +144,7 @@ struct EvDev {
     const Rec32 *rec32;
     const Rec64 *rec64;
     const double *pfx;
+    const double *pl1, *pw2;  // [n_det][K+1] exclusive prefixes of |w| and |w|^2
     const double *guard;  // noise statistics of the event's data (see kGuardStride)
     int *kc_all, *hist, *idx, *kcut;
     double *coef, *resp, *hh;
@@ -221,15 +223,16 @@ struct BatchHdr {
 // Around these expectations the sum scatters with RMS (per-term error) x
 // sqrt(sum |w_k|^2); the per-term RMS adds to the trigonometric one the FP32
 // rounding of the turn-based argument (two roundings, <= 3.9e-8 turns RMS).
-// Per draw the finalize bounds |d ln L| by
-//   sum_d |R_d| [ eps_coh(a) C_d + kEpsL1 L1_d ] + kEpsInc sqrt(sum_d |R_d|^2 W2_d)
-// (C_d the larger of |Z_d| and the matched magnitude sqrt(C_d,kcut rho2_d)/|R_d|,
-// rho2_d a bound on the detector's signal power from the data's whitened
-// power in excess of the noise's; the scatter adds in quadrature over the
-// detectors), and where the data carry less than the PSD's noise (e.g.
-// noise-free injections) by the worst case kEpsMax sum_d |R_d| L1_d. Draws
-// whose bound exceeds the batch's redo budget are re-evaluated in FP64 on the
-// hot loop's own layout.
+// Per draw the finalize bounds |d ln L| per detector by the smaller of
+//   eps_coh(a) C_d + kEpsL1 |R_d| L1_d   and the worst case   kEpsMax |R_d| L1_d
+// (L1_d = sum |w_k| and W2_d = sum |w_k|^2 below the draw's cut; C_d the
+// larger of |R_d Z_d| and the matched magnitude sqrt(H_d rho2_d), rho2_d a
+// bound on the detector's signal power from the data's whitened power in
+// excess of the noise's) plus the scatter kEpsInc sqrt(sum_d |R_d|^2 W2_d),
+// which adds in quadrature over the detectors. Where the data carry less than
+// the PSD's noise (e.g. noise-free injections) only the worst case applies.
+// Draws whose bound exceeds the batch's redo budget are re-evaluated in FP64
+// on the hot loop's own layout.
 constexpr double kTrigGain = 1.0 + 3.23e-8;
 constexpr double kEpsMax = 1.4e-7;       // max |eps| (1.277e-7 measured)
 constexpr double kEpsL1 = 7.0e-10;       // |c_1| (5.6e-10 measured)
@@ -241,7 +244,8 @@ constexpr double kEpsHarm[7] = {1.5e-9, 2.2e-9, 6.3e-9, 3.0e-9, 8.0e-9, 7.6e-10,
 constexpr double kRedoBudget = 5e-4;     // default: half of the split path's stated 1e-3
 // Noise statistics per detector (event tables): the bound rho2 on the signal
 // power (< 0: the data carry less than the noise the PSD implies), the largest
-// 4 df f^-7/3 / S of the band, L1 = sum |w_k| and sqrt(sum |w_k|^2).
+// 4 df f^-7/3 / S of the band, and over the whole band L1 = sum |w_k| and
+// sqrt(sum |w_k|^2) (diagnostics; the finalize uses the prefixes pl1, pw2).
 constexpr int kGuardStride = 4;
 constexpr int kGuardRho2 = 0, kGuardPwMax = 1, kGuardL1 = 2, kGuardW2 = 3;
 constexpr int kGuardLen = kGuardStride * PE_MAX_DET;
@@ -258,6 +262,8 @@ struct pe_event_s {
     pe::Rec64 *rec64 = nullptr;
     double *pw = nullptr;   // [n_det][K] 4 df f^(-7/3) / S
     double *pfx = nullptr;  // [n_det][K+1] exclusive prefix of pw
+    double *pl1 = nullptr;  // [n_det][K+1] exclusive prefix of |w|
+    double *pw2 = nullptr;  // [n_det][K+1] exclusive prefix of |w|^2
     double *guard = nullptr;  // [kGuardLen] noise statistics of the data
     int *status = nullptr;  // device status word
     double *mws = nullptr;  // metric + draw workspace

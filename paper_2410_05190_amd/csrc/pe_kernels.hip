@@ -170,14 +170,33 @@ __global__ __launch_bounds__(256) void k_seg_sums(const BatchHdr* __restrict__ h
     }
 }
 
-// Each segment: its carry (the sum of the segment sums before it, one block
-// reduction), then a block-wide inclusive scan per 256 bins.
+// Each segment: its carries (the sums of the segment sums before it, one block
+// reduction each), then block-wide inclusive scans per 256 bins of pw (into
+// pfx), |w| (into pl1) and |w|^2 (into pw2).
+__device__ __forceinline__ double block_scan_excl(double v, double* sh, double& tile) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double u = __shfl_up(inc, off);
+        if (lane >= off) inc += u;
+    }
+    double exc = __shfl_up(inc, 1);
+    if (lane == 0) exc = 0.0;
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    double woff = 0.0;
+    for (int i = 0; i < w; ++i) woff += sh[i];
+    tile = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return woff + exc;
+}
+
 __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ hdr,
                                                   const PrepArg* __restrict__ args) {
     __shared__ double sh[4];
     const int ne = hdr->ne;
     const int d = blockIdx.y, b = blockIdx.x;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int e = blockIdx.z; e < ne; e += gridDim.z) {
         const PrepArg& A = args[e];
         const int64_t K = A.ec.K;
@@ -186,36 +205,48 @@ __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ h
         scan_layout(K, seg, nseg);
         if (d >= A.ec.n_det || b >= nseg) continue;
         const double* a = A.pw + (int64_t)d * K;
-        double* o = A.pfx + (int64_t)d * (K + 1);
-        double carry = block_sum4((int)threadIdx.x < b ? A.seg[d * kScanSeg + threadIdx.x] : 0.0, sh);
+        const int64_t po = (int64_t)d * (K + 1);
+        double* o = A.pfx + po;
+        double* o1 = A.pl1 + po;
+        double* o2 = A.pw2 + po;
+        const int64_t slice = (int64_t)PE_MAX_DET * kScanSeg;
+        const double* sg = A.seg + (int64_t)d * kScanSeg + threadIdx.x;
+        const bool before = (int)threadIdx.x < b;
+        double carry = block_sum4(before ? sg[0] : 0.0, sh);
+        double carry1 = block_sum4(before ? sg[2 * slice] : 0.0, sh);
+        double carry2 = block_sum4(before ? sg[3 * slice] : 0.0, sh);
         const int64_t k0 = (int64_t)b * seg;
         const int64_t k1 = min(k0 + seg, K);
         for (int64_t base = k0; base < k1; base += 256) {
             const int64_t k = base + threadIdx.x;
-            const double v = (k < k1) ? a[k] : 0.0;
-            double inc = v;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const double u = __shfl_up(inc, off);
-                if (lane >= off) inc += u;
+            double v = 0.0, v1 = 0.0, v2 = 0.0;
+            if (k < k1) {
+                v = a[k];
+                const double2 w = A.rec64[k].w[d];
+                v2 = w.x * w.x + w.y * w.y;
+                v1 = sqrt(v2);
             }
-            double exc = __shfl_up(inc, 1);
-            if (lane == 0) exc = 0.0;
-            if (lane == 63) sh[w] = inc;
-            __syncthreads();
-            double woff = 0.0;
-            for (int i = 0; i < w; ++i) woff += sh[i];
-            const double tile = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-            __syncthreads();
-            if (k < k1) o[k] = carry + (woff + exc);
-            carry += tile;
+            double t, t1, t2;
+            const double x = block_scan_excl(v, sh, t);
+            const double x1 = block_scan_excl(v1, sh, t1);
+            const double x2 = block_scan_excl(v2, sh, t2);
+            if (k < k1) {
+                o[k] = carry + x;
+                o1[k] = carry1 + x1;
+                o2[k] = carry2 + x2;
+            }
+            carry += t;
+            carry1 += t1;
+            carry2 += t2;
         }
-        if (b == nseg - 1 && threadIdx.x == 0) o[K] = carry;
+        if (b == nseg - 1 && threadIdx.x == 0) {
+            o[K] = carry;
+            o1[K] = carry1;
+            o2[K] = carry2;
+        }
         if (b == 0) {
             // the detector's noise statistics: segments combined in a fixed order
-            const int64_t slice = (int64_t)PE_MAX_DET * kScanSeg;
             const int t = threadIdx.x;
-            const double* sg = A.seg + (int64_t)d * kScanSeg + t;
             const bool in = t < nseg;
             const double pwr = block_sum4(in ? sg[slice] : 0.0, sh);
             const double l1 = block_sum4(in ? sg[2 * slice] : 0.0, sh);

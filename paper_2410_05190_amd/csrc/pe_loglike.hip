@@ -394,9 +394,16 @@ struct Ticket {
     int q, v;
 };
 
+// A queue whose counter has passed its item count stays empty (counters only
+// grow), so a plain load settles it without an atomic.
+__device__ __forceinline__ bool queue_open(BatchHdr* __restrict__ hdr, int q) {
+    return __hip_atomic_load(&hdr->qnext[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < hdr->qitems[q];
+}
+
 __device__ __forceinline__ Ticket steal_ticket(BatchHdr* __restrict__ hdr, int x0) {
     for (int k = 1; k < kQueues; ++k) {
         const int qq = (x0 + k) & (kQueues - 1);
+        if (!queue_open(hdr, qq)) continue;
         const int v = atomicAdd(&hdr->qnext[qq], 1);
         if (v < hdr->qitems[qq]) return Ticket{qq, v};
     }
@@ -406,6 +413,11 @@ __device__ __forceinline__ Ticket steal_ticket(BatchHdr* __restrict__ hdr, int x
 // Checks a ticket claimed from queue x0 (thread 0 only).
 __device__ __forceinline__ Ticket own_or_steal(BatchHdr* __restrict__ hdr, int x0, int v) {
     return (v < hdr->qitems[x0]) ? Ticket{x0, v} : steal_ticket(hdr, x0);
+}
+
+// The next ticket of queue x0, or another queue's (thread 0 only).
+__device__ __forceinline__ Ticket next_ticket(BatchHdr* __restrict__ hdr, int x0) {
+    return queue_open(hdr, x0) ? own_or_steal(hdr, x0, atomicAdd(&hdr->qnext[x0], 1)) : steal_ticket(hdr, x0);
 }
 
 // Item of ticket (q, x); REDO: items of the FP64 re-evaluation (plan[1], tiles from 0).
@@ -447,7 +459,7 @@ __device__ __forceinline__ void item_loop(BatchHdr* __restrict__ hdr, const int6
     const int ne = hdr->ne;
     const int x0 = blockIdx.x & (kQueues - 1);
     if (threadIdx.x == 0) {
-        const Ticket t = own_or_steal(hdr, x0, atomicAdd(&hdr->qnext[x0], 1));
+        const Ticket t = next_ticket(hdr, x0);
         s_q[0] = t.q;
         s_v[0] = t.v;
     }
@@ -464,12 +476,11 @@ __device__ __forceinline__ void item_loop(BatchHdr* __restrict__ hdr, const int6
         const EvPlan pl = load_const(evs[it.e].plan);
         const bool early = pl.kmax < 4096 * pl.n_groups;
         int nv = 0;
-        if (early && threadIdx.x == 0) nv = atomicAdd(&hdr->qnext[x0], 1);
+        if (early && threadIdx.x == 0) nv = queue_open(hdr, x0) ? atomicAdd(&hdr->qnext[x0], 1) : INT_MAX;
         process(it);
         slot ^= 1;
         if (threadIdx.x == 0) {
-            if (!early) nv = atomicAdd(&hdr->qnext[x0], 1);
-            const Ticket t = own_or_steal(hdr, x0, nv);
+            const Ticket t = early ? own_or_steal(hdr, x0, nv) : next_ticket(hdr, x0);
             s_q[slot] = t.q;
             s_v[slot] = t.v;
         }
@@ -727,21 +738,22 @@ __device__ __forceinline__ double eps_coherent(double a2) {
 }
 
 // Bound on |d ln L| of the split path for one detector of a draw (see
-// kEpsHarm): |R_d|, the detector's FP32-path sum (ar, ai), C_{d,kcut}. lin
-// gains the parts that add linearly over detectors, var the variance of the
-// scatter (in units of kEpsInc^2).
+// kEpsHarm): guard G, |R_d|, the detector's FP32-path sum (ar, ai), and below
+// the draw's cut C = sum pw, l1 = sum |w|, w2 = sum |w|^2. lin gains the part
+// that adds linearly over detectors, var the variance of the scatter (in units
+// of kEpsInc^2).
 __device__ __forceinline__ void split_error(const double* __restrict__ G, double rm, double ar, double ai, double c,
-                                            double& lin, double& var) {
+                                            double l1, double w2, double& lin, double& var) {
     if (rm == 0.0 || c == 0.0) return;
+    var += rm * rm * w2;
+    const double worst = kEpsMax * rm * l1;  // every term's error at its largest
     const double rho2 = G[kGuardRho2];
-    const double sw = rm * G[kGuardW2];
-    var += sw * sw;
-    if (rho2 < 0.0) {  // no noise to scatter the phases: worst case
-        lin += kEpsMax * rm * G[kGuardL1];
+    if (rho2 < 0.0) {  // no noise to scatter the phases: the worst case only
+        lin += worst;
         return;
     }
     const double coh = fmax(rm * hypot(ar, ai), sqrt(rm * rm * c * rho2));
-    lin += eps_coherent(rho2 * G[kGuardPwMax] / c) * coh + kEpsL1 * rm * G[kGuardL1];
+    lin += fmin(worst, eps_coherent(rho2 * G[kGuardPwMax] / c) * coh + kEpsL1 * rm * l1);
 }
 
 // Fixed-order combine of the group partials, then ln L of Eq. 3. The split
@@ -777,9 +789,11 @@ __global__ __launch_bounds__(256) void k_b_finalize(BatchHdr* __restrict__ hdr, 
                 const double rr = E.resp[(2 * d) * np + j], ri = E.resp[(2 * d + 1) * np + j];
                 zr += rr * ar - ri * ai;
                 zi += rr * ai + ri * ar;
-                if (SPLIT)
-                    split_error(E.guard + d * kGuardStride, hypot(rr, ri), ar, ai,
-                                E.pfx[(int64_t)d * (E.ec.K + 1) + kc], lin, var);
+                if (SPLIT) {
+                    const int64_t o = (int64_t)d * (E.ec.K + 1) + kc;
+                    split_error(E.guard + d * kGuardStride, hypot(rr, ri), ar, ai, E.pfx[o], E.pl1[o], E.pw2[o],
+                                lin, var);
+                }
             }
             if (SPLIT) {
                 const double err = lin + kEpsInc * sqrt(var);
@@ -898,6 +912,10 @@ __global__ void k_r_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_r_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                const int64_t* __restrict__ ioff) {
+    int items = 0;
+#pragma unroll
+    for (int q = 0; q < kQueues; ++q) items += hdr->qitems[q];
+    if (items == 0) return;  // nothing listed (uniform over the grid)
     item_loop<true>(hdr, ioff, evs, [&](const Item& it) {
         const EvDev& E = evs[it.e];
         const EvPlan rp = load_const(E.plan + 1);
