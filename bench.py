@@ -272,6 +272,11 @@ def main():
         if "refined" in out:
             centres["refined"] = torch.tensor(out["refined"]["centre"], dtype=torch.float64, device="cuda")
         out["distance_marginalised"] = distance_leg(first, centres, max(args.steps, 1), prec)
+        out["phase_and_distance_marginalised"] = distance_leg(first, centres, max(args.steps, 1), prec,
+                                                              phase=binding.PE_PHASE_MARG)
+        out["phase_and_distance_marginalised"]["kind"] = (
+            "likelihood marginalised over the coalescence phase (ln I0 form) and the luminosity distance "
+            "(dL^2 prior); both left out of the proposal density")
     if n_events == 1 and D == 4 and args.tile_candidates > 0:
         out["tiles"] = tile_leg(first, args, max(args.steps, 1), prec)
     for x in evs:
@@ -515,15 +520,19 @@ def relbin_leg(x, eps, steps, prec):
     }
 
 
-def distance_leg(x, centres, steps, prec):
+def distance_leg(x, centres, steps, prec, phase=None):
     """Distance-marginalised likelihood (PE_DIST_MARG: the likelihood integrated over the dL^2
     prior per draw; the metric, draws and prior without dL): the same step as the main leg on a
     second event over the same data, at each proposal centre (the injection, and the refined
-    centre of the refinement leg when it ran). ESS per event and ESS/s."""
+    centre of the refinement leg when it ran). ESS per event and ESS/s. phase=PE_PHASE_MARG also
+    marginalises the coalescence phase (ln I0 form; phic left out of the proposal density)."""
     import torch
 
     from paper_2410_05190_amd import binding
-    ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], distance=binding.PE_DIST_MARG, **x["common"])
+    common = dict(x["common"])
+    if phase is not None:
+        common["phase"] = phase
+    ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], distance=binding.PE_DIST_MARG, **common)
     N = x["N"]
     ev.reserve(N)
     h_ = ev.handle

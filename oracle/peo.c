@@ -742,23 +742,27 @@ double peo_logprior(const peo_event *ev, const double *th)
     return log(cos(th[5])) + log(sin(th[6])) + 2.0 * log(th[8]);
 }
 
-/* Density of the wrapped Gaussian at theta: log sum over images k in {-1,0,1}^p of
- * N(theta + k P; theta0, g^-1), with the quadratic form evaluated as |L^T x|^2. */
+/* Density of the wrapped Gaussian at theta: log sum over images k in {-2,...,2}^p of
+ * N(theta + k P; theta0, g^-1), with the quadratic form evaluated as |L^T x|^2.
+ * theta and theta0 both lie in [0, P) on the periodic coordinates, so every
+ * omitted image is at least 2P from theta0: its term is below e^-24 of the
+ * largest while the proposal's width stays within P / sqrt(12) (the prior
+ * precision 12/P^2 of the metric bounds it there). */
 static double logq_one(int D, const double *L, const double *th0, const double *th, int np, const int *pidx,
                        const double *per)
 {
     int nimg = 1, m, a, r, c;
-    double lq[27], mx = -INFINITY, acc = 0.0, logdet = 0.0;
+    double lq[125], mx = -INFINITY, acc = 0.0, logdet = 0.0;
     for (a = 0; a < np; a++)
-        nimg *= 3;
+        nimg *= 5;
     for (m = 0; m < nimg; m++) {
         double x[PEO_MAX_DIM], q = 0.0;
         int code = m;
         for (a = 0; a < D; a++)
             x[a] = th[a] - th0[a];
         for (a = 0; a < np; a++) {
-            int kk = code % 3 - 1;
-            code /= 3;
+            int kk = code % 5 - 2;
+            code /= 5;
             x[pidx[a]] += kk * per[a];
         }
         for (r = 0; r < D; r++) {
@@ -803,68 +807,116 @@ static int spd_inverse(const double *g, int D, double *inv)
     return 0;
 }
 
-/* Distance-marginalised events: the proposal over the coordinates other than
- * dL (index 8). dec_g: g with the dL row and column decoupled by the Schur
- * complement (g_dLdL kept), the metric the draws are taken with. Lm: Cholesky
- * factor of the marginal precision of the other D-1 coordinates, the inverse of
- * the sub-block of the covariance g^-1; pidx_m: the periodic indices among them. */
+/* Marginalised coordinates: dL (index 8) of distance-marginalised events and
+ * phic (index 10) of 11-D phase-marginalised events are never used by the
+ * likelihood, so the proposal density the weights need is that of the other
+ * coordinates. dec_g: g with each marginalised row and column decoupled by the
+ * Schur complement (its diagonal entry kept), the metric the draws are taken
+ * with. Lm: Cholesky factor of the marginal precision of the Dm kept
+ * coordinates, the inverse of the sub-block of the covariance g^-1; keep: their
+ * indices; pidx_m: the periodic ones among them (np_m of them). */
 typedef struct {
     double dec_g[PEO_MAX_DIM * PEO_MAX_DIM];
     double Lm[PEO_MAX_DIM * PEO_MAX_DIM];
+    int keep[PEO_MAX_DIM];
+    int Dm, np_m;
     int pidx_m[3];
-} dist_prop;
+    double per_m[3];
+} marg_prop;
 
-static int dist_proposal(const double *g, int np, const int *pidx, dist_prop *dp)
+static int marg_dims(const peo_event *ev, int *marg)
 {
-    const int D = 11, il = 8, Dm = 10;
+    int n = 0;
+    if (ev->params != PEO_PARAMS_11D)
+        return 0;
+    if (ev->distance == PEO_DIST_MARG)
+        marg[n++] = 8;
+    if (ev->phase == PEO_PHASE_MARG)
+        marg[n++] = 10;
+    return n;
+}
+
+static int marg_proposal(const double *g, int D, int nm, const int *marg, int np, const int *pidx,
+                         const double *per, marg_prop *mp)
+{
     double C[PEO_MAX_DIM * PEO_MAX_DIM], Cm[PEO_MAX_DIM * PEO_MAX_DIM], gm[PEO_MAX_DIM * PEO_MAX_DIM];
-    int a, b, rc;
-    for (a = 0; a < D; a++)
-        for (b = 0; b < D; b++)
-            dp->dec_g[a * D + b] = (a == il || b == il) ? ((a == b) ? g[il * D + il] : 0.0)
-                                                         : g[a * D + b] - g[a * D + il] * g[il * D + b] / g[il * D + il];
+    double t[PEO_MAX_DIM * PEO_MAX_DIM];
+    int a, b, i, rc, is_m[PEO_MAX_DIM] = {0};
+    memcpy(mp->dec_g, g, sizeof(double) * D * D);
+    for (i = 0; i < nm; i++) {
+        const int il = marg[i];
+        is_m[il] = 1;
+        memcpy(t, mp->dec_g, sizeof(double) * D * D);
+        for (a = 0; a < D; a++)
+            for (b = 0; b < D; b++)
+                mp->dec_g[a * D + b] = (a == il || b == il) ? ((a == b) ? t[il * D + il] : 0.0)
+                                                             : t[a * D + b] - t[a * D + il] * t[il * D + b] / t[il * D + il];
+    }
     rc = spd_inverse(g, D, C);
     if (rc)
         return rc;
-    for (a = 0; a < Dm; a++)
-        for (b = 0; b < Dm; b++)
-            Cm[a * Dm + b] = C[(a + (a >= il)) * D + (b + (b >= il))];
-    rc = spd_inverse(Cm, Dm, gm);
+    mp->Dm = 0;
+    for (a = 0; a < D; a++)
+        if (!is_m[a])
+            mp->keep[mp->Dm++] = a;
+    for (a = 0; a < mp->Dm; a++)
+        for (b = 0; b < mp->Dm; b++)
+            Cm[a * mp->Dm + b] = C[mp->keep[a] * D + mp->keep[b]];
+    rc = spd_inverse(Cm, mp->Dm, gm);
     if (rc)
         return rc;
-    rc = cholesky(gm, Dm, dp->Lm);
+    rc = cholesky(gm, mp->Dm, mp->Lm);
     if (rc)
         return rc;
-    for (a = 0; a < np; a++)
-        dp->pidx_m[a] = pidx[a] - (pidx[a] > il);
+    mp->np_m = 0;
+    for (i = 0; i < np; i++)
+        for (a = 0; a < mp->Dm; a++)
+            if (mp->keep[a] == pidx[i]) {
+                mp->pidx_m[mp->np_m] = a;
+                mp->per_m[mp->np_m++] = per[i];
+            }
     return 0;
 }
 
-static double logq_dist(const dist_prop *dp, const double *th0, const double *th, int np, const double *per)
+static double logq_marg(const marg_prop *mp, const double *th0, const double *th)
 {
     double t0[PEO_MAX_DIM], t[PEO_MAX_DIM];
     int a;
-    for (a = 0; a < 10; a++) {
-        t0[a] = th0[a + (a >= 8)];
-        t[a] = th[a + (a >= 8)];
+    for (a = 0; a < mp->Dm; a++) {
+        t0[a] = th0[mp->keep[a]];
+        t[a] = th[mp->keep[a]];
     }
-    return logq_one(10, dp->Lm, t0, t, np, dp->pidx_m, per);
+    return logq_one(mp->Dm, mp->Lm, t0, t, mp->np_m, mp->pidx_m, mp->per_m);
+}
+
+/* theta0 with its periodic coordinates wrapped into [0, P) (the centre of the
+ * images of log q; the draws themselves do not depend on it). */
+static void wrap_centre(const peo_event *ev, const double *th0, double *out)
+{
+    int pidx[3], np, a, D = peo_dim(ev->params);
+    double per[3];
+    np = periodic_dims(ev, pidx, per);
+    for (a = 0; a < D; a++)
+        out[a] = th0[a];
+    for (a = 0; a < np; a++)
+        out[pidx[a]] = th0[pidx[a]] - per[a] * floor(th0[pidx[a]] / per[a]);
 }
 
 int peo_draw(const peo_event *ev, const double *th0, const double *g, uint64_t seed, uint32_t stream, long n,
              double *theta, double *logq, double *logprior)
 {
     const int D = peo_dim(ev->params);
-    const int dist = (ev->params == PEO_PARAMS_11D && ev->distance == PEO_DIST_MARG);
-    double L[PEO_MAX_DIM * PEO_MAX_DIM];
-    dist_prop dp;
-    int pidx[3], np, rc;
+    double L[PEO_MAX_DIM * PEO_MAX_DIM], c0[PEO_MAX_DIM];
+    marg_prop mp;
+    int pidx[3], marg[2], np, nm, rc;
     double per[3];
     long i;
     np = periodic_dims(ev, pidx, per);
-    rc = dist ? dist_proposal(g, np, pidx, &dp) : 0;
+    nm = marg_dims(ev, marg);
+    wrap_centre(ev, th0, c0);
+    rc = nm ? marg_proposal(g, D, nm, marg, np, pidx, per, &mp) : 0;
     if (!rc)
-        rc = cholesky(dist ? dp.dec_g : g, D, L);
+        rc = cholesky(nm ? mp.dec_g : g, D, L);
     if (rc) {
         for (i = 0; i < n; i++) {
             int a;
@@ -901,7 +953,7 @@ int peo_draw(const peo_event *ev, const double *th0, const double *g, uint64_t s
         }
         for (a = 0; a < D; a++)
             theta[(long)a * n + i] = th[a];
-        logq[i] = dist ? logq_dist(&dp, th0, th, np, per) : logq_one(D, L, th0, th, np, pidx, per);
+        logq[i] = nm ? logq_marg(&mp, c0, th) : logq_one(D, L, c0, th, np, pidx, per);
         logprior[i] = peo_logprior(ev, th);
     }
     return 0;
@@ -911,13 +963,14 @@ int peo_logq_theta(const peo_event *ev, const double *th0, const double *g, cons
                    double *logq)
 {
     const int D = peo_dim(ev->params);
-    const int dist = (ev->params == PEO_PARAMS_11D && ev->distance == PEO_DIST_MARG);
-    double L[PEO_MAX_DIM * PEO_MAX_DIM], per[3];
-    dist_prop dp;
-    int pidx[3], np, rc;
+    double L[PEO_MAX_DIM * PEO_MAX_DIM], per[3], c0[PEO_MAX_DIM];
+    marg_prop mp;
+    int pidx[3], marg[2], np, nm, rc;
     long i;
     np = periodic_dims(ev, pidx, per);
-    rc = dist ? dist_proposal(g, np, pidx, &dp) : cholesky(g, D, L);
+    nm = marg_dims(ev, marg);
+    wrap_centre(ev, th0, c0);
+    rc = nm ? marg_proposal(g, D, nm, marg, np, pidx, per, &mp) : cholesky(g, D, L);
     if (rc)
         return rc;
     for (i = 0; i < n; i++) {
@@ -925,7 +978,7 @@ int peo_logq_theta(const peo_event *ev, const double *th0, const double *g, cons
         int a;
         for (a = 0; a < D; a++)
             th[a] = theta[(long)a * n + i];
-        logq[i] = dist ? logq_dist(&dp, th0, th, np, per) : logq_one(D, L, th0, th, np, pidx, per);
+        logq[i] = nm ? logq_marg(&mp, c0, th) : logq_one(D, L, c0, th, np, pidx, per);
     }
     return 0;
 }

@@ -614,22 +614,28 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
             L[i][j] = 0.0;
             g[i][j] = A.g[i * D + j];
         }
-    // distance-marginalised likelihood: decouple dL (index 8) by the Schur
-    // complement of its row and column, keeping g_88; the other coordinates'
-    // distribution is unchanged and dL's drawn value is never used
+    // coordinates the likelihood does not use: dL (index 8) of a
+    // distance-marginalised likelihood, phic (index 10) of an 11-D
+    // phase-marginalised one. Each is decoupled by the Schur complement of its
+    // row and column (its diagonal kept); the other coordinates' distribution
+    // is unchanged and the drawn value is never used
     const bool dist = (D == 11) && A.ec.dist;
+    const bool pmarg = (D == 11) && A.ec.phase == PE_PHASE_MARG;
     if constexpr (D == 11) {
-        if (dist) {
-            const double g88 = g[8][8];
-            ok = g88 > 0.0;
-            double c8[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) c8[i] = g[i][8];
+        for (int m = 0; m < 2; ++m) {
+            const int il = m == 0 ? 8 : 10;
+            if (!(m == 0 ? dist : pmarg)) continue;
+            const double gll = g[il][il];
+            ok = ok && gll > 0.0;
+            double cl[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) cl[i] = g[i][il];
 #pragma unroll
             for (int i = 0; i < D; ++i)
 #pragma unroll
                 for (int j = 0; j < D; ++j)
-                    g[i][j] = (i == 8 || j == 8) ? ((i == j) ? g88 : 0.0) : (ok ? g[i][j] - c8[i] * c8[j] / g88 : g[i][j]);
+                    g[i][j] = (i == il || j == il) ? ((i == j) ? gll : 0.0) : (ok ? g[i][j] - cl[i] * cl[j] / gll : g[i][j]);
         }
     }
 #pragma unroll
@@ -651,12 +657,12 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
     for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = 0; j < D; ++j) A.chol[i * D + j] = ok ? L[i][j] : 0.0;
-    // log det of the factor of the density log q reports: without L_88 for a
-    // distance-marginalised likelihood (the marginal over dL)
+    // log det of the factor of the density log q reports: without the decoupled
+    // coordinates' L_ii (the marginal over them)
     if (ok)
 #pragma unroll
         for (int a = 0; a < D; ++a)
-            if (!(dist && a == 8)) logdet += log(L[a][a]);
+            if (!(dist && a == 8) && !(pmarg && a == 10)) logdet += log(L[a][a]);
     A.chol[kCholLogdet] = logdet;
     A.chol[kCholOk] = ok ? 1.0 : 0.0;
 #pragma unroll
@@ -691,9 +697,9 @@ __global__ __launch_bounds__(64) void k_cholesky(const BatchHdr* __restrict__ hd
 }
 
 // Draw i of an event: normals, theta = theta0 + L^-T z (wrapped), log q of the
-// wrapped Gaussian (images -1, 0, +1 of each periodic coordinate, summed with
-// a running maximum), log prior. L (row-major), its log det and the success
-// flag are in LDS (lc).
+// wrapped Gaussian (images -2..2 of each periodic coordinate about theta0
+// wrapped into [0, P), summed with a running maximum), log prior. L
+// (row-major), its log det and the success flag are in LDS (lc).
 template <int D>
 __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int64_t i) {
     const EvConst& ev = A.ec;
@@ -733,47 +739,54 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
     constexpr int NP = (D == 4) ? 0 : 3;
     constexpr int pidx[3] = {4, 7, 10};
     const double per[3] = {kTwoPi, kPi, kTwoPi};
+    // k0_p: periods between the wrapped draw and the wrapped centre
     double k0[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const double v = th[pidx[p]];
-        k0[p] = floor(v / per[p]);
-        th[pidx[p]] = v - per[p] * k0[p];
+        const double kw = floor(v / per[p]);
+        th[pidx[p]] = v - per[p] * kw;
+        k0[p] = kw - floor(th0[pidx[p]] / per[p]);
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th[a];
-    // whitened offset of image m: L^T (x - theta0) = z + L^T s with
-    // s = (k - k0) P on the periodic rows, so its squared norm is
-    // |z|^2 + 2 s.a + s^T G s with a_p = (L^T row pidx_p) . z and G = L L^T there
-    // distance-marginalised likelihood: log q of the marginal over dL, whose
-    // normal z_8 (decoupled by the Cholesky kernel) moves dL alone
+    // whitened offset of image m: L^T (x - c) = z + L^T s with c the wrapped
+    // centre and s = (k - k0) P on the periodic rows, so its squared norm is
+    // |z|^2 + 2 s.a + s^T G s with a_p = (L^T row pidx_p) . z and G = L L^T there.
+    // Decoupled coordinates (dL of a distance-marginalised likelihood, phic of an
+    // 11-D phase-marginalised one): their normals move them alone and log q is
+    // the marginal over them (their z and, for phic, its images left out).
     const bool dist = (D == 11) && ev.dist;
+    const bool pmarg = (D == 11) && ev.phase == PE_PHASE_MARG;
     double zz = 0.0;
 #pragma unroll
     for (int r = 0; r < D; ++r)
-        if (!(dist && r == 8)) zz = fma(z[r], z[r], zz);
+        if (!(dist && r == 8) && !(pmarg && r == 10)) zz = fma(z[r], z[r], zz);
     double a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int r = 0; r <= pidx[p]; ++r) a[p] = fma(lc[pidx[p] * D + r], z[r], a[p]);
     const double* G = lc + kCholG;  // G00 G01 G02 G11 G12 G22
+    // images of phic: all five, or only k = k0 (no shift) when it is marginalised
+    const int t2lo = pmarg ? 2 : 0, t2hi = pmarg ? 2 : 4;
+    if (pmarg) k0[2] = 0.0;
     double mx = -INFINITY, acc = 0.0;
-    constexpr int NIMG = (NP == 0) ? 1 : 27;
     if constexpr (NP == 3) {
-        // Factorised image sum. With image k = (t_0, t_1, t_2), t in {-1, 0, 1}
+        // Factorised image sum. With image k = (t_0, t_1, t_2), t in {-2..2}
         // and o_p = -k0_p P_p, the shift is s_p = P_p t_p + o_p and
         //   -qf/2 = -C/2 + sum_p v_p(t_p) - sum_{p<q} gam_pq t_p t_q,
         //   C = |z|^2 + 2 o.a + o^T G o,  v_p(t) = -P_p t b_p - G_pp P_p^2 t^2 / 2,
         //   b = a + G o,  gam_pq = G_pq P_p P_q,
-        // so each of the 27 terms is a product of three per-coordinate factors
+        // so each of the 125 terms is a product of three per-coordinate factors
         // exp(v_p - V_p) <= 1 (V_p their largest exponent) and three pair
-        // factors exp(-+gam): 11 exponentials instead of 27. Taken when every
-        // |gam| <= 100, so that the pair factors stay within e^+-300 (a
-        // condition on the event's metric, uniform over the workgroup).
+        // factors exp(-gam t_p t_q), t_p t_q in -4..4: 15 + 6 exponentials instead
+        // of 125. Taken when every |gam| <= 50, so that the pair factors stay
+        // within e^+-200 (a condition on the event's metric, uniform over the
+        // workgroup).
         const double g00 = G[0], g01 = G[1], g02 = G[2], g11 = G[3], g12 = G[4], g22 = G[5];
         const double gam01 = g01 * per[0] * per[1], gam02 = g02 * per[0] * per[2], gam12 = g12 * per[1] * per[2];
-        if (fabs(gam01) <= 100.0 && fabs(gam02) <= 100.0 && fabs(gam12) <= 100.0) {
+        if (fabs(gam01) <= 50.0 && fabs(gam02) <= 50.0 && fabs(gam12) <= 50.0) {
             const double o0 = -k0[0] * per[0], o1 = -k0[1] * per[1], o2 = -k0[2] * per[2];
             const double go0 = g00 * o0 + g01 * o1 + g02 * o2;
             const double go1 = g01 * o0 + g11 * o1 + g12 * o2;
@@ -781,38 +794,59 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
             const double C = zz + 2.0 * (o0 * a[0] + o1 * a[1] + o2 * a[2]) + (o0 * go0 + o1 * go1 + o2 * go2);
             const double b[3] = {a[0] + go0, a[1] + go1, a[2] + go2};
             const double gpp[3] = {g00, g11, g22};
-            double f[3][3], V = 0.0;
+            double f[3][5], V = 0.0;
 #pragma unroll
             for (int p = 0; p < 3; ++p) {
                 const double h = -0.5 * gpp[p] * per[p] * per[p];
-                const double vm = per[p] * b[p] + h, vp = -per[p] * b[p] + h;  // t = -1, +1
-                const double Vp = fmax(0.0, fmax(vm, vp));
-                f[p][0] = exp(vm - Vp);
-                f[p][1] = exp(-Vp);
-                f[p][2] = exp(vp - Vp);
+                double v[5], Vp = -INFINITY;
+#pragma unroll
+                for (int t = 0; t < 5; ++t) {
+                    const double tt = (double)(t - 2);
+                    v[t] = -per[p] * tt * b[p] + h * tt * tt;
+                    if (!(p == 2 && pmarg && t != 2)) Vp = fmax(Vp, v[t]);
+                }
+#pragma unroll
+                for (int t = 0; t < 5; ++t) f[p][t] = (p == 2 && pmarg && t != 2) ? 0.0 : exp(v[t] - Vp);
                 V += Vp;
             }
+            // x_pq[j] = exp(-gam_pq (j - 4)), j - 4 = t_p t_q in -4..4
+            double x01[9], x02[9], x12[9];
             const double e01 = exp(-gam01), e02 = exp(-gam02), e12 = exp(-gam12);
-            const double x01[3] = {1.0 / e01, 1.0, e01}, x02[3] = {1.0 / e02, 1.0, e02}, x12[3] = {1.0 / e12, 1.0, e12};
+            x01[4] = x02[4] = x12[4] = 1.0;
 #pragma unroll
-            for (int t0 = 0; t0 < 3; ++t0)
+            for (int j = 1; j <= 4; ++j) {
+                x01[4 + j] = x01[3 + j] * e01;
+                x02[4 + j] = x02[3 + j] * e02;
+                x12[4 + j] = x12[3 + j] * e12;
+            }
+            const double i01 = 1.0 / e01, i02 = 1.0 / e02, i12 = 1.0 / e12;
 #pragma unroll
-                for (int t1 = 0; t1 < 3; ++t1) {
-                    const double f01 = f[0][t0] * f[1][t1] * x01[1 + (t0 - 1) * (t1 - 1)];
+            for (int j = 1; j <= 4; ++j) {
+                x01[4 - j] = x01[5 - j] * i01;
+                x02[4 - j] = x02[5 - j] * i02;
+                x12[4 - j] = x12[5 - j] * i12;
+            }
 #pragma unroll
-                    for (int t2 = 0; t2 < 3; ++t2)
-                        acc += f01 * f[2][t2] * x02[1 + (t0 - 1) * (t2 - 1)] * x12[1 + (t1 - 1) * (t2 - 1)];
+            for (int t0 = 0; t0 < 5; ++t0)
+#pragma unroll
+                for (int t1 = 0; t1 < 5; ++t1) {
+                    const double f01 = f[0][t0] * f[1][t1] * x01[4 + (t0 - 2) * (t1 - 2)];
+#pragma unroll
+                    for (int t2 = 0; t2 < 5; ++t2)
+                        acc += f01 * f[2][t2] * x02[4 + (t0 - 2) * (t2 - 2)] * x12[4 + (t1 - 2) * (t2 - 2)];
                 }
             mx = -0.5 * C + V;
         }
     }
+    const int nimg = (NP == 0) ? 1 : 25 * (t2hi - t2lo + 1);
 #pragma unroll 1
-    for (int m = (acc > 0.0) ? NIMG : 0; m < NIMG; ++m) {
+    for (int m = (acc > 0.0) ? nimg : 0; m < nimg; ++m) {
         double qf = zz;
         if (NP == 3) {
-            const double s0 = ((double)(m % 3 - 1) - k0[0]) * per[0];
-            const double s1 = ((double)((m / 3) % 3 - 1) - k0[1]) * per[1];
-            const double s2 = ((double)(m / 9 - 1) - k0[2]) * per[2];
+            const int t0 = m % 5, t1 = (m / 5) % 5, t2 = t2lo + m / 25;
+            const double s0 = ((double)(t0 - 2) - k0[0]) * per[0];
+            const double s1 = ((double)(t1 - 2) - k0[1]) * per[1];
+            const double s2 = ((double)(t2 - 2) - k0[2]) * per[2];
             const double lin = s0 * a[0] + s1 * a[1] + s2 * a[2];
             const double quad = s0 * (s0 * G[0] + 2.0 * (s1 * G[1] + s2 * G[2])) +
                                 s1 * (s1 * G[3] + 2.0 * s2 * G[4]) + s2 * s2 * G[5];
@@ -828,7 +862,8 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
             acc += exp(l - mx);
         }
     }
-    A.logq[i] = mx + log(acc) + lc[kCholLogdet] - 0.5 * (D - (dist ? 1 : 0)) * log(kTwoPi);
+    const int dkeep = D - (dist ? 1 : 0) - (pmarg ? 1 : 0);
+    A.logq[i] = mx + log(acc) + lc[kCholLogdet] - 0.5 * dkeep * log(kTwoPi);
     A.logprior[i] = log_prior_of(ev, th);
 }
 

@@ -187,26 +187,37 @@ def test_draw_parity():
         np.testing.assert_allclose(lp[fin], lp_o[fin], rtol=0, atol=1e-9)
 
 
-@pytest.mark.parametrize("couple", [False, True])
-def test_draw_parity_factorised_image_sum(couple):
+@pytest.mark.parametrize("cfg,couple,shift", [(1, "none", False), (1, "weak", False), (1, "weak", True),
+                                              (2, "weak", True), (1, "strong", True)])
+def test_draw_parity_image_sum(cfg, couple, shift):
     """Broad periodic coordinates (ra, psi, phic with unit precision, so that neighbouring images
-    carry weight), with and without couplings between them: every pair term |g_pq P_p P_q| stays
-    below 100, which is where the draw kernel sums the 27 images as products of per-coordinate and
-    pair factors instead of one exponential per image. log q and theta against the oracle."""
+    carry weight), with and without couplings between them, and with the centre several periods
+    outside [0, P) (the images are taken about the wrapped centre). Weak couplings keep every pair
+    term |g_pq P_p P_q| within 50, where the draw kernel sums the 125 images as products of
+    per-coordinate and pair factors; strong ones take the image-by-image sum. Config 2's events are
+    phase-marginalised: phic is left out of log q. log q and theta against the oracle."""
     torch_cuda()
-    b = build_event(1, 2, n_bins=20000)
+    b = build_event(cfg, 2, n_bins=20000 if cfg == 1 else None)
     g = np.diag(np.diag(b.ev.metric(b.theta_inj)))
     pidx = [4, 7, 10]
-    block = np.array([[1.0, 0.3, 0.0], [0.3, 1.0, 0.5], [0.0, 0.5, 1.0]]) if couple else np.eye(3)
+    c = {"none": (0.0, 0.0), "weak": (0.3, 0.5), "strong": (0.9, 0.0)}[couple]
+    block = np.array([[1.0, c[0], 0.0], [c[0], 1.0, c[1]], [0.0, c[1], 1.0]])
+    if couple == "strong":
+        block = block * 10.0
     g[np.ix_(pidx, pidx)] = block
     per = np.array([2 * math.pi, math.pi, 2 * math.pi])
-    gam = block * np.outer(per, per)
-    assert np.abs(gam - np.diag(np.diag(gam))).max() <= 100.0
+    gam = np.abs(block * np.outer(per, per) - np.diag(np.diag(block * np.outer(per, per))))
+    assert (gam.max() <= 50.0) == (couple != "strong")
+    th0 = b.theta_inj.copy()
+    if shift:
+        th0[4] += 3 * per[0]
+        th0[7] -= 2 * per[1]
+        th0[10] += per[2]
     n = 4001
-    rc, th_o, lq_o, lp_o = b.ev.draw(b.theta_inj, g, 31337, 2, n)
+    rc, th_o, lq_o, lp_o = b.ev.draw(th0, g, 31337, 2, n)
     assert rc == 0
     ev, data, psd = upload_event(b)
-    th, lq, lp = ev.draw(dev(b.theta_inj), dev(g), 31337, 2, n)
+    th, lq, lp = ev.draw(dev(th0), dev(g), 31337, 2, n)
     ev.status()
     th, lq, lp = host(th), host(lq), host(lp)
     dth = th - th_o
@@ -214,7 +225,8 @@ def test_draw_parity_factorised_image_sum(couple):
         dth[i] = (dth[i] + P / 2) % P - P / 2
     sd = np.sqrt(np.diag(np.linalg.inv(g)))
     err = np.max(np.abs(dth) / sd[:, None])
-    note(f"factorised image sum (couplings {couple}): max |dtheta|/sd {err:.2e}, logq {np.abs(lq - lq_o).max():.2e}")
+    note(f"image sum cfg {cfg} couplings {couple} shifted {shift}: max |dtheta|/sd {err:.2e}, "
+         f"logq {np.abs(lq - lq_o).max():.2e}")
     assert err < 1e-9
     np.testing.assert_allclose(lq, lq_o, rtol=0, atol=1e-8)
     fin = np.isfinite(lp_o)

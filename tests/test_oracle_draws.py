@@ -125,7 +125,7 @@ def test_logq_two_routes():
     import itertools
     for m in range(n):
         terms = []
-        for ks in itertools.product((-1, 0, 1), repeat=3):
+        for ks in itertools.product((-2, -1, 0, 1, 2), repeat=3):
             shift = np.zeros(11)
             for (i, P), kk in zip(per.items(), ks):
                 shift[i] = (kk - k0[i, m]) * P
@@ -138,6 +138,86 @@ def test_logq_two_routes():
     rc2, lq2 = b.ev.logq_theta(th0, g, th)
     assert rc2 == 0
     np.testing.assert_array_equal(lq, lq2)
+
+
+def _broad_periodic_metric(rng):
+    """11-D precision whose periodic coordinates (ra, psi, phic) sit at the prior-limited width
+    P / sqrt(12), coupled to each other and to the rest."""
+    scale = [1e-3, 0.1, 0.1, 0.1, 1.0, 0.3, 0.3, 1.0, 20.0, 1e-3, 1.0]
+    g = _spd(11, rng, scale) * 0.05
+    per = {4: 2 * math.pi, 7: math.pi, 10: 2 * math.pi}
+    C = np.linalg.inv(g)
+    for i, P in per.items():  # covariance of each periodic coordinate = (P / sqrt(12))^2
+        f = (P / math.sqrt(12.0)) / math.sqrt(C[i, i])
+        C[i, :] *= f
+        C[:, i] *= f
+    return np.linalg.inv(C), per
+
+
+def _wrapped_logpdf(th, th0, C, per, kmax):
+    """log sum over images k in [-kmax, kmax]^3 of N(theta + k P; theta0, C) (scipy)."""
+    import itertools
+    mvn = stats.multivariate_normal(th0, C)
+    terms = []
+    for ks in itertools.product(range(-kmax, kmax + 1), repeat=3):
+        shift = np.zeros(11)
+        for (i, P), kk in zip(per.items(), ks):
+            shift[i] = kk * P
+        terms.append(mvn.logpdf((th + shift[:, None]).T))
+    terms = np.array(terms)
+    mx = terms.max(axis=0)
+    return mx + np.log(np.exp(terms - mx).sum(axis=0))
+
+
+def test_logq_broad_periodic_coordinates_against_many_images():
+    """Periodic coordinates as broad as the prior precision allows (sd P / sqrt(12)) and a centre
+    outside [0, P): the oracle's images -2..2 about the wrapped centre against scipy's Gaussian summed
+    over images -6..6 about the raw centre (exact to e^-(6P)^2/(2 sd^2)), within 1e-9."""
+    b = build_event(1, 1, n_bins=4000)
+    rng = np.random.default_rng(21)
+    g, per = _broad_periodic_metric(rng)
+    th0 = b.theta_inj.copy()
+    th0[4] += 2 * math.pi * 3 + 0.3   # ra: three periods up
+    th0[7] -= math.pi * 2 + 0.2       # psi: two periods down
+    th0[10] += 2 * math.pi            # phic: one period up
+    rc, th, lq, lp = b.ev.draw(th0, g, 31, 0, 300)
+    assert rc == 0
+    for i, P in per.items():
+        assert np.all((th[i] >= 0) & (th[i] < P))
+    want = _wrapped_logpdf(th, th0, np.linalg.inv(g), per, 6)
+    np.testing.assert_allclose(lq, want, rtol=0, atol=1e-9)
+
+
+def test_phase_marginal_logq_is_the_integral_over_phic():
+    """11-D phase-marginalised events leave phic out of the proposal density: log q equals the log of
+    the full 11-D wrapped density integrated over phic (periodic trapezoid rule, 128 nodes), for a
+    metric that couples phic to the other coordinates."""
+    b = build_event(2, 0, n_bins=2000)
+    assert b.phase == oracle.PHASE_MARG
+    full = oracle.Event(b.n_det, b.n_bins, b.f_lo, b.df, data=b.data, psd=b.psd, strain_scale=b.strain_scale,
+                        params=b.params, phase=oracle.PHASE_EXPLICIT, amp0=b.amp0, gmst=b.gmst,
+                        chi_max=b.chi_max, dl_max=b.dl_max, det_geom=b.det_geom)
+    rng = np.random.default_rng(22)
+    g, per = _broad_periodic_metric(rng)
+    th0 = b.theta_inj.copy()
+    rc, th, lq, lp = b.ev.draw(th0, g, 41, 0, 60)
+    assert rc == 0
+    nodes = 2 * math.pi * np.arange(128) / 128
+    vals = []
+    for phi in nodes:
+        t = th.copy()
+        t[10] = phi
+        rc, lf = full.logq_theta(th0, g, t)
+        vals.append(lf)
+    vals = np.array(vals)
+    mx = vals.max(axis=0)
+    want = mx + np.log(np.exp(vals - mx).mean(axis=0) * 2 * math.pi)
+    np.testing.assert_allclose(lq, want, rtol=0, atol=1e-9)
+    # the drawn phic is not used: moving it leaves log q unchanged
+    t = th.copy()
+    t[10] = (t[10] + 1.234) % (2 * math.pi)
+    rc, lq2 = b.ev.logq_theta(th0, g, t)
+    np.testing.assert_allclose(lq2, lq, rtol=0, atol=1e-12)
 
 
 def test_logq_unwrapped_is_gaussian_density():
