@@ -31,7 +31,8 @@ class _Event(ctypes.Structure):
                 ("df", ctypes.c_double), ("data", _dp), ("psd", _dp), ("strain_scale", ctypes.c_double),
                 ("params", ctypes.c_int), ("phase", ctypes.c_int), ("amp0", ctypes.c_double),
                 ("gmst", ctypes.c_double), ("chi_max", ctypes.c_double), ("dl_max", ctypes.c_double),
-                ("det_geom", (ctypes.c_double * 3) * MAX_DET), ("distance", ctypes.c_int)]
+                ("det_geom", (ctypes.c_double * 3) * MAX_DET), ("distance", ctypes.c_int),
+                ("time_marg", ctypes.c_int), ("tc_lo", ctypes.c_double), ("tc_hi", ctypes.c_double)]
 
 
 class _Slice(ctypes.Structure):
@@ -149,7 +150,7 @@ class Event:
 
     def __init__(self, n_det, n_bins, f_lo, df, data=None, psd=None, strain_scale=1.0, params=PARAMS_11D,
                  phase=PHASE_EXPLICIT, amp0=0.0, gmst=0.0, chi_max=0.4, dl_max=1e4, det_geom=None,
-                 distance=DIST_SAMPLED):
+                 distance=DIST_SAMPLED, time_marg=0, tc_lo=0.0, tc_hi=0.0):
         self.n_det = int(n_det)
         self.n_bins = int(n_bins)
         self.f_lo = float(f_lo)
@@ -182,6 +183,10 @@ class Event:
         s.dl_max = float(dl_max)
         self.distance = int(distance)
         s.distance = self.distance
+        self.time_marg = int(time_marg)
+        s.time_marg = self.time_marg
+        s.tc_lo = float(tc_lo)
+        s.tc_hi = float(tc_hi)
         if det_geom is not None:
             g = np.asarray(det_geom, dtype=np.float64).reshape(-1, 3)
             for i in range(g.shape[0]):

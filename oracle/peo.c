@@ -405,9 +405,13 @@ static void likelihood_theta(const peo_event *ev, const double *th, double *out)
         out[8] = ev->dl_max;
 }
 
+static double loglike_time_marg(const peo_event *ev, const peo_source *s, const double *X, double H);
+static double fmax_d(double a, double b) { return a > b ? a : b; }
+
 /* Eq. 3 with Eq. 1: Z = sum_d (d_d|h_d) as a complex overlap, H = sum_d (h_d|h_d).
  * Explicit phase: ln L = Re Z - H/2. Marginalised over a uniform coalescence
- * phase: ln L = ln I0(|Z|) - H/2. */
+ * phase: ln L = ln I0(|Z|) - H/2. Time-marginalised events integrate the
+ * likelihood over tc (see loglike_time_marg). */
 static double loglike_one(const peo_event *ev, const double *th_in, double *zh)
 {
     peo_source s;
@@ -422,6 +426,9 @@ static double loglike_one(const peo_event *ev, const double *th_in, double *zh)
         return -INFINITY;
     }
     s.kcut = peo_kcut(ev, s.fisco);
+    double *X = NULL; /* time-marginalised events: the detector-summed integrand per bin */
+    if (ev->time_marg && s.kcut > 0)
+        X = (double *)calloc(2 * (size_t)s.kcut, sizeof(double));
     for (d = 0; d < ev->n_det; d++) {
         const double *S = ev->psd + (long)d * ev->n_bins;
         const double *dd = ev->data + 2 * (long)d * ev->n_bins;
@@ -433,7 +440,21 @@ static double loglike_one(const peo_event *ev, const double *th_in, double *zh)
             nadd(&zr, w * (dd[2 * k] * hr + dd[2 * k + 1] * hi));
             nadd(&zi, w * (dd[2 * k] * hi - dd[2 * k + 1] * hr));
             nadd(&hh, w * (hr * hr + hi * hi));
+            if (X) {
+                X[2 * k] += w * (dd[2 * k] * hr + dd[2 * k + 1] * hi);
+                X[2 * k + 1] += w * (dd[2 * k] * hi - dd[2 * k + 1] * hr);
+            }
         }
+    }
+    if (ev->time_marg) {
+        const double lt = loglike_time_marg(ev, &s, X, nval(&hh));
+        free(X);
+        if (zh) {
+            zh[0] = nval(&zr);
+            zh[1] = nval(&zi);
+            zh[2] = nval(&hh);
+        }
+        return lt;
     }
     Zr = nval(&zr);
     Zi = nval(&zi);
@@ -444,6 +465,74 @@ static double loglike_one(const peo_event *ev, const double *th_in, double *zh)
         zh[2] = H;
     }
     return loglike_from_zh(ev, Zr, Zi, H);
+}
+
+/* Time-marginalised likelihood (the paper marginalises extrinsic parameters,
+ * Sec. III): with a flat prior on tc over [tc_lo, tc_hi] of width T,
+ *   L_t = (1/T) int_{tc_lo}^{tc_hi} L(theta with tc = t) dt.
+ * Shifting tc by u multiplies the model at f_k by exp(-2 pi i f_k u), so with
+ * X_k the detector-summed conj(d) h / S integrand at the draw's own tc (s->tc),
+ * Z(t) = sum_k X_k exp(-2 pi i f_k (t - s->tc)) and H does not change; each
+ * node's ln L follows from Z(t), H as in loglike_from_zh. The integral is
+ * Simpson's rule over the whole window: a scan at spacing 1/(8 f_max) finds
+ * the largest |Z(t)|; the likelihood's peak in t is no narrower than
+ * 1/(2 pi f_max sqrt(|Z|max)) (the curvature of Re Z(t) is at most
+ * (2 pi f_max)^2 |Z|), and the nodes are spaced at a quarter of that and at
+ * most T/4000, so that both the peak and a window edge that cuts it are
+ * resolved. */
+static void z_at(const peo_event *ev, const peo_source *s, const double *X, double t, double *zr, double *zi)
+{
+    nsum a = {0, 0}, b = {0, 0};
+    long k;
+    const double u = t - s->tc;
+    for (k = 0; k < s->kcut; k++) {
+        const double f = ev->f_lo + (double)k * ev->df;
+        const double ph = -2.0 * PI * f * u, c = cos(ph), sn = sin(ph);
+        nadd(&a, X[2 * k] * c - X[2 * k + 1] * sn);
+        nadd(&b, X[2 * k] * sn + X[2 * k + 1] * c);
+    }
+    *zr = nval(&a);
+    *zi = nval(&b);
+}
+
+static double loglike_time_marg(const peo_event *ev, const peo_source *s, const double *X, double H)
+{
+    const double T = ev->tc_hi - ev->tc_lo;
+    double zmax = 0.0, zr, zi, h, lmax = -INFINITY, acc = 0.0;
+    long j, nc, nf;
+    double *lv;
+    if (s->kcut <= 0)
+        return loglike_from_zh(ev, 0.0, 0.0, H);
+    {
+        const double fmax = ev->f_lo + (double)s->kcut * ev->df;
+        nc = (long)ceil(T * 8.0 * fmax) + 1;
+        for (j = 0; j < nc; j++) {
+            z_at(ev, s, X, ev->tc_lo + T * (double)j / (double)(nc - 1), &zr, &zi);
+            if (hypot(zr, zi) > zmax)
+                zmax = hypot(zr, zi);
+        }
+        h = 0.25 / (2.0 * PI * fmax * sqrt(fmax_d(zmax, 1.0)));
+    }
+    nf = (long)ceil(T / h);
+    if (nf < 4000)
+        nf = 4000;
+    nf += (nf & 1) + 1; /* an even number of intervals */
+    lv = (double *)malloc(sizeof(double) * (size_t)nf);
+    for (j = 0; j < nf; j++) {
+        z_at(ev, s, X, ev->tc_lo + T * (double)j / (double)(nf - 1), &zr, &zi);
+        lv[j] = loglike_from_zh(ev, zr, zi, H);
+        if (lv[j] > lmax)
+            lmax = lv[j];
+    }
+    if (lmax == -INFINITY) {
+        free(lv);
+        return -INFINITY;
+    }
+    for (j = 0; j < nf; j++)
+        acc += ((j == 0 || j == nf - 1) ? 1.0 : (j & 1) ? 4.0 : 2.0) * exp(lv[j] - lmax);
+    free(lv);
+    /* (1/T) * (T/(nf-1))/3 * sum */
+    return lmax + log(acc / 3.0) - log((double)(nf - 1));
 }
 
 #ifdef _OPENMP
@@ -831,6 +920,8 @@ static int marg_dims(const peo_event *ev, int *marg)
         return 0;
     if (ev->distance == PEO_DIST_MARG)
         marg[n++] = 8;
+    if (ev->time_marg)
+        marg[n++] = 9;
     if (ev->phase == PEO_PHASE_MARG)
         marg[n++] = 10;
     return n;
@@ -908,7 +999,7 @@ int peo_draw(const peo_event *ev, const double *th0, const double *g, uint64_t s
     const int D = peo_dim(ev->params);
     double L[PEO_MAX_DIM * PEO_MAX_DIM], c0[PEO_MAX_DIM];
     marg_prop mp;
-    int pidx[3], marg[2], np, nm, rc;
+    int pidx[3], marg[3], np, nm, rc;
     double per[3];
     long i;
     np = periodic_dims(ev, pidx, per);
@@ -951,6 +1042,22 @@ int peo_draw(const peo_event *ev, const double *th0, const double *g, uint64_t s
             double P = per[a], v = th[pidx[a]];
             th[pidx[a]] = v - P * floor(v / P);
         }
+        if (D == 11 && ev->time_marg) {
+            /* tc: its mean under the proposal given the other coordinates (the
+               centre the likelihood's integral over tc is taken about), from
+               their offsets to the centre, periodic ones to the nearest image */
+            double m = c0[9], dlt[PEO_MAX_DIM];
+            for (a = 0; a < D; a++)
+                dlt[a] = th[a] - c0[a];
+            for (a = 0; a < np; a++) {
+                const double P = per[a];
+                dlt[pidx[a]] -= P * floor(dlt[pidx[a]] / P + 0.5);
+            }
+            for (a = 0; a < D; a++)
+                if (a != 9)
+                    m -= g[9 * D + a] / g[9 * D + 9] * dlt[a];
+            th[9] = m;
+        }
         for (a = 0; a < D; a++)
             theta[(long)a * n + i] = th[a];
         logq[i] = nm ? logq_marg(&mp, c0, th) : logq_one(D, L, c0, th, np, pidx, per);
@@ -965,7 +1072,7 @@ int peo_logq_theta(const peo_event *ev, const double *th0, const double *g, cons
     const int D = peo_dim(ev->params);
     double L[PEO_MAX_DIM * PEO_MAX_DIM], per[3], c0[PEO_MAX_DIM];
     marg_prop mp;
-    int pidx[3], marg[2], np, nm, rc;
+    int pidx[3], marg[3], np, nm, rc;
     long i;
     np = periodic_dims(ev, pidx, per);
     nm = marg_dims(ev, marg);

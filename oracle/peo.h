@@ -63,6 +63,8 @@ typedef struct {
     double dl_max;  /* Mpc, upper bound of the distance prior (11-D) */
     double det_geom[PEO_MAX_DET][3]; /* latitude, longitude, x-arm azimuth (from north to east) */
     int distance;   /* PEO_DIST_SAMPLED or PEO_DIST_MARG */
+    int time_marg;  /* 11-D: 1 = the likelihood is marginalised over tc with a flat prior on [tc_lo, tc_hi] */
+    double tc_lo, tc_hi;
 } peo_event;
 
 /* Per-draw source quantities derived from theta. */
