@@ -87,6 +87,10 @@ def parse():
                     help="tile-mixture leg: slice candidates for the prior samples (0 skips the leg; 4-D only)")
     ap.add_argument("--no-distance-leg", action="store_true",
                     help="skip the distance-marginalised leg (11-D configurations)")
+    ap.add_argument("--time-leg", type=int, default=1,
+                    help="1: the leg with time, phase and distance marginalised (11-D configurations); 0 skips it")
+    ap.add_argument("--time-leg-draws", type=int, default=8192,
+                    help="time-marginalised leg: proposal draws per step (each evaluated at every tc node)")
     ap.add_argument("--no-batch-leg", action="store_true",
                     help="skip the config-2 leg (64 BBH events per step through pe_batch_run) of the default run")
     ap.add_argument("--long-steps", type=int, default=3,
@@ -277,6 +281,20 @@ def main():
         out["phase_and_distance_marginalised"]["kind"] = (
             "likelihood marginalised over the coalescence phase (ln I0 form) and the luminosity distance "
             "(dL^2 prior); both left out of the proposal density")
+        if args.time_leg:
+            # nodes half the explicit-phase peak width 1/sqrt(g_tc,tc) apart over the window (the
+            # phase-marginalised peak is wider)
+            gh = first["g"].cpu().numpy()
+            lo, hi = first["theta_inj"][9] - 0.01, first["theta_inj"][9] + 0.01
+            pts = int(math.ceil((hi - lo) / (0.5 / math.sqrt(gh[9, 9])))) + 1
+            tm = {"tc_lo": float(lo), "tc_hi": float(hi), "tm_points": pts}
+            leg = distance_leg(first, centres, max(args.steps // 4, 2), prec, phase=binding.PE_PHASE_MARG,
+                               time_marg=tm, n_draws=args.time_leg_draws)
+            leg["kind"] = (f"likelihood marginalised over the coalescence time (flat over 20 ms about the injected "
+                           f"tc; end-corrected trapezoid rule on {pts} nodes over the window, each a likelihood "
+                           f"evaluation), the phase and the distance; all three left out of the proposal density")
+            leg["time_nodes"] = tm
+            out["time_phase_and_distance_marginalised"] = leg
     if n_events == 1 and D == 4 and args.tile_candidates > 0:
         out["tiles"] = tile_leg(first, args, max(args.steps, 1), prec)
     for x in evs:
@@ -520,20 +538,24 @@ def relbin_leg(x, eps, steps, prec):
     }
 
 
-def distance_leg(x, centres, steps, prec, phase=None):
+def distance_leg(x, centres, steps, prec, phase=None, time_marg=None, n_draws=None):
     """Distance-marginalised likelihood (PE_DIST_MARG: the likelihood integrated over the dL^2
     prior per draw; the metric, draws and prior without dL): the same step as the main leg on a
     second event over the same data, at each proposal centre (the injection, and the refined
     centre of the refinement leg when it ran). ESS per event and ESS/s. phase=PE_PHASE_MARG also
-    marginalises the coalescence phase (ln I0 form; phic left out of the proposal density)."""
+    marginalises the coalescence phase (ln I0 form; phic left out of the proposal density);
+    time_marg = {tc_lo, tc_hi, tm_points} also the coalescence time (each draw evaluated at tm_points
+    nodes over the window, tc left out of the proposal density)."""
     import torch
 
     from paper_2410_05190_amd import binding
     common = dict(x["common"])
     if phase is not None:
         common["phase"] = phase
+    if time_marg:
+        common.update(time_marg=1, **time_marg)
     ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], distance=binding.PE_DIST_MARG, **common)
-    N = x["N"]
+    N = n_draws or x["N"]
     ev.reserve(N)
     h_ = ev.handle
     g = torch.empty_like(x["g"])

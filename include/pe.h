@@ -57,6 +57,7 @@ extern "C" {
 
 #define PE_MAX_DET 4
 #define PE_MAX_DIM 11
+#define PE_MAX_TM_POINTS 16384 /* tc nodes of a time-marginalised event */
 
 typedef struct pe_event_s *pe_event_t;
 
@@ -102,6 +103,24 @@ typedef struct {
     double dl_max;        /* 11-D prior bound 0 < dL <= dl_max (Mpc) */
     double det_geom[PE_MAX_DET][3];
     int32_t distance;     /* pe_distance_t (a zeroed field: PE_DIST_SAMPLED); PE_DIST_MARG needs 11-D */
+    /* Time marginalisation (11-D; zeroed fields: off). time_marg = 1: the
+     * likelihood is integrated over tc with a flat prior on [tc_lo, tc_hi]
+     * (the paper marginalises the extrinsic parameters, Sec. III):
+     *   L_t = (1/T) int_{tc_lo}^{tc_hi} L(theta with tc = t) dt,  T = tc_hi - tc_lo.
+     * Every draw is evaluated at tm_points nodes spread evenly over the whole
+     * window (theta's own tc is not used), and the integral is the extended
+     * trapezoid rule with fourth-order end corrections (weights 17/48, 59/48,
+     * 43/48, 49/48 at each end). The spacing h = T / (tm_points - 1) must
+     * resolve the likelihood's peak in tc: h at most half its narrowest width
+     * 1/sqrt(g_tc,tc) keeps the rule's error far below the split path's for a
+     * peak inside the window; a peak that a window edge cuts is integrated to
+     * O(h^4). Each call costs tm_points likelihood evaluations per draw.
+     * pe_draw sets each draw's tc to its conditional mean under the proposal
+     * given the other coordinates and reports the proposal's marginal over tc
+     * in logq. */
+    int32_t time_marg;
+    int32_t tm_points;    /* 8 .. PE_MAX_TM_POINTS */
+    double tc_lo, tc_hi;  /* s, tc_lo < tc_hi */
 } pe_event_desc_t;
 
 /* Dimension D of theta for a parameter set (4 or 11); 0 if unknown. */

@@ -54,7 +54,8 @@ class EventDesc(ctypes.Structure):
                 ("strain_scale", ctypes.c_double), ("params", ctypes.c_int32), ("phase", ctypes.c_int32),
                 ("amp0", ctypes.c_double), ("gmst", ctypes.c_double), ("chi_max", ctypes.c_double),
                 ("dl_max", ctypes.c_double), ("det_geom", (ctypes.c_double * 3) * MAX_DET),
-                ("distance", ctypes.c_int32)]
+                ("distance", ctypes.c_int32), ("time_marg", ctypes.c_int32), ("tm_points", ctypes.c_int32),
+                ("tc_lo", ctypes.c_double), ("tc_hi", ctypes.c_double)]
 
 
 class Slice(ctypes.Structure):
@@ -208,7 +209,7 @@ def _ptr(t, dtype=None, name="tensor", allow_none=False):
 
 def make_desc(n_det, n_bins, f_lo, df, data_dtype=PE_C128, psd_dtype=PE_F64, strain_scale=1.0,
               params=PE_PARAMS_11D, phase=PE_PHASE_EXPLICIT, amp0=0.0, gmst=0.0, chi_max=0.4, dl_max=1e4,
-              det_geom=None, distance=PE_DIST_SAMPLED):
+              det_geom=None, distance=PE_DIST_SAMPLED, time_marg=0, tm_points=0, tc_lo=0.0, tc_hi=0.0):
     d = EventDesc()
     d.n_det = int(n_det)
     d.n_bins = int(n_bins)
@@ -224,6 +225,10 @@ def make_desc(n_det, n_bins, f_lo, df, data_dtype=PE_C128, psd_dtype=PE_F64, str
     d.chi_max = float(chi_max)
     d.dl_max = float(dl_max)
     d.distance = int(distance)
+    d.time_marg = int(time_marg)
+    d.tm_points = int(tm_points)
+    d.tc_lo = float(tc_lo)
+    d.tc_hi = float(tc_hi)
     if det_geom is not None:
         g = np.asarray(det_geom, dtype=np.float64).reshape(-1, 3)
         for i in range(g.shape[0]):

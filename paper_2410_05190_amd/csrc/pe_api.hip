@@ -57,8 +57,20 @@ pe_status_t validate_desc(const pe_event_desc_t* d) {
     if (d->distance != PE_DIST_SAMPLED && d->distance != PE_DIST_MARG) return fail(PE_ERR_ARG, "bad distance");
     if (d->distance == PE_DIST_MARG && d->params != PE_PARAMS_11D)
         return fail(PE_ERR_ARG, "distance marginalisation needs the 11-D parameter set");
+    if (d->time_marg != 0 && d->time_marg != 1) return fail(PE_ERR_ARG, "time_marg must be 0 or 1");
+    if (d->time_marg) {
+        if (d->params != PE_PARAMS_11D) return fail(PE_ERR_ARG, "time marginalisation needs the 11-D parameter set");
+        if (d->tm_points < 8 || d->tm_points > PE_MAX_TM_POINTS)
+            return fail(PE_ERR_ARG, "tm_points must be in 8..PE_MAX_TM_POINTS");
+        if (!(d->tc_lo < d->tc_hi) || !std::isfinite(d->tc_lo) || !std::isfinite(d->tc_hi))
+            return fail(PE_ERR_ARG, "the tc window needs tc_lo < tc_hi");
+    }
     return PE_OK;
 }
+
+// Draws the workspace must hold for a batch of n: a time-marginalised event
+// evaluates every draw at each of its tc nodes.
+int64_t ws_draws(const pe_event_s* ev, int64_t n) { return ev->desc.time_marg ? n * ev->desc.tm_points : n; }
 
 // Detector tensor D = (x x^T - y y^T)/2 from latitude, longitude and the
 // x-arm azimuth (north toward east); y arm 90 degrees east of x.
@@ -77,6 +89,10 @@ void build_const(const pe_event_desc_t& d, EvConst& ec) {
     ec.chi_max = d.chi_max;
     ec.dl_max = d.dl_max;
     ec.dist = (d.distance == PE_DIST_MARG) ? 1 : 0;
+    ec.tm = d.time_marg ? 1 : 0;
+    ec.tm_points = d.time_marg ? d.tm_points : 0;
+    ec.tc_lo = d.tc_lo;
+    ec.tc_hi = d.tc_hi;
     for (int i = 0; i < d.n_det; ++i) {
         const double lat = d.det_geom[i][0], lon = d.det_geom[i][1], az = d.det_geom[i][2];
         const double up[3] = {std::cos(lat) * std::cos(lon), std::cos(lat) * std::sin(lon), std::sin(lat)};
@@ -168,6 +184,10 @@ size_t layout_ws(pe_event_s* ev, int64_t npad, char* base) {
     ev->rcnt = c.take<int>((size_t)(npad / kTile + 1));
     ev->rpos = c.take<int>((size_t)npad);
     ev->zd = c.take<double2>((size_t)npad);
+    if (ev->desc.time_marg) {
+        ev->tm_theta = c.take<double>((size_t)PE_MAX_DIM * npad);
+        ev->tm_ll = c.take<double>((size_t)npad);
+    }
     ev->coef = c.take<double>((size_t)kNCoef * npad);
     ev->kcut = c.take<int>((size_t)npad);
     ev->resp = c.take<double>((size_t)2 * nd * npad);
@@ -573,6 +593,26 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     return PE_OK;
 }
 
+// The log-likelihood batch entry of an event's n draws; a time-marginalised
+// event evaluates its node draws (expanded into the workspace by tm_expand)
+// into the workspace and tm_reduce sums them into loglike.
+EvDev loglike_entry(pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux,
+                    std::vector<TmJob>& tm) {
+    if (!ev->desc.time_marg) return loglike_arg(ev, theta, n, loglike, aux);
+    tm.push_back(TmJob{ev, theta, n, loglike});
+    return loglike_arg(ev, ev->tm_theta, n * ev->desc.tm_points, ev->tm_ll, nullptr);
+}
+
+pe_status_t tm_expand(const std::vector<TmJob>& tm, hipStream_t st) {
+    for (const TmJob& j : tm) PE_HIP(launch_tm_expand(j.theta, j.n, j.ev->ec, j.ev->tm_theta, st));
+    return PE_OK;
+}
+
+pe_status_t tm_reduce(const std::vector<TmJob>& tm, hipStream_t st) {
+    for (const TmJob& j : tm) PE_HIP(launch_tm_reduce(j.ev->tm_ll, j.n, j.ev->ec, j.loglike, st));
+    return PE_OK;
+}
+
 pe_status_t run_weights(const std::vector<WeightArg>& v, hipStream_t st) {
     const int ne = (int)v.size();
     if (ne == 0) return PE_OK;
@@ -761,7 +801,7 @@ pe_status_t pe_event_status(pe_event_t ev, void* stream) {
 pe_status_t pe_event_reserve(pe_event_t ev, int64_t max_draws) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
     if (max_draws < 0 || max_draws > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "max_draws must be in 0..2^30");
-    return ensure_ws(ev, max_draws);
+    return ensure_ws(ev, ws_draws(ev, max_draws));
 }
 
 pe_status_t pe_event_destroy(pe_event_t ev) {
@@ -801,6 +841,7 @@ pe_status_t pe_loglike_batch(pe_event_t ev, const double* theta_dev, int64_t n, 
         if (s != PE_OK) return s;
         if (n == 0) return PE_OK;
         if (!theta_dev || !loglike_dev) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
+        if (ev->desc.time_marg) return fail(PE_ERR_ARG, "relative binning does not take a time-marginalised event");
         return run_relbin(ev, theta_dev, n, loglike_dev, aux_dev, as_stream(stream));
     }
     pe_status_t s = check_n(n);
@@ -808,9 +849,14 @@ pe_status_t pe_loglike_batch(pe_event_t ev, const double* theta_dev, int64_t n, 
     if (s != PE_OK) return s;
     if (n == 0) return PE_OK;
     if (!theta_dev || !loglike_dev) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
-    if ((s = ensure_ws(ev, n)) != PE_OK) return s;
-    return run_loglike(std::vector<EvDev>(1, loglike_arg(ev, theta_dev, n, loglike_dev, aux_dev)), precision,
-                       as_stream(stream));
+    if (ev->desc.time_marg && aux_dev) return fail(PE_ERR_ARG, "aux is not available for a time-marginalised event");
+    if ((s = ensure_ws(ev, ws_draws(ev, n))) != PE_OK) return s;
+    hipStream_t st = as_stream(stream);
+    std::vector<TmJob> tm;
+    std::vector<EvDev> v(1, loglike_entry(ev, theta_dev, n, loglike_dev, aux_dev, tm));
+    if ((s = tm_expand(tm, st)) != PE_OK) return s;
+    if ((s = run_loglike(v, precision, st)) != PE_OK) return s;
+    return tm_reduce(tm, st);
 }
 
 pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t* events, const double* const* theta_dev,
@@ -821,6 +867,7 @@ pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t* events, const d
     pe_status_t s = check_precision(precision);
     if (s != PE_OK) return s;
     std::vector<EvDev> v;
+    std::vector<TmJob> tm;
     for (int e = 0; e < n_events; ++e) {
         pe_event_s* ev = events[e];
         if (!ev) return fail(PE_ERR_ARG, "event is NULL");
@@ -829,10 +876,15 @@ pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t* events, const d
         if ((s = check_n(n[e])) != PE_OK) return s;
         if (n[e] == 0) continue;
         if (!theta_dev[e] || !loglike_dev[e]) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
-        if ((s = ensure_ws(ev, n[e])) != PE_OK) return s;
-        v.push_back(loglike_arg(ev, theta_dev[e], n[e], loglike_dev[e], aux_dev ? aux_dev[e] : nullptr));
+        if (ev->desc.time_marg && aux_dev && aux_dev[e])
+            return fail(PE_ERR_ARG, "aux is not available for a time-marginalised event");
+        if ((s = ensure_ws(ev, ws_draws(ev, n[e]))) != PE_OK) return s;
+        v.push_back(loglike_entry(ev, theta_dev[e], n[e], loglike_dev[e], aux_dev ? aux_dev[e] : nullptr, tm));
     }
-    return run_loglike(v, precision, as_stream(stream));
+    hipStream_t st = as_stream(stream);
+    if ((s = tm_expand(tm, st)) != PE_OK) return s;
+    if ((s = run_loglike(v, precision, st)) != PE_OK) return s;
+    return tm_reduce(tm, st);
 }
 
 pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t* items, int32_t stages, int32_t precision,
@@ -847,6 +899,7 @@ pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t* items, int32_t 
     std::vector<DrawArg> vd;
     std::vector<EvDev> vl;
     std::vector<WeightArg> vw;
+    std::vector<TmJob> tm;
     for (int e = 0; e < n_items; ++e) {
         const pe_batch_item_t& it = items[e];
         pe_event_s* ev = it.ev;
@@ -871,8 +924,10 @@ pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t* items, int32_t 
         if ((stages & PE_STAGE_LOGLIKE) && it.n > 0) {
             if (!it.theta || !it.loglike)
                 return fail(PE_ERR_ARG, "item " + std::to_string(e) + ": theta and loglike needed");
-            if ((s = ensure_ws(ev, it.n)) != PE_OK) return s;
-            vl.push_back(loglike_arg(ev, it.theta, it.n, it.loglike, it.aux));
+            if (ev->desc.time_marg && it.aux)
+                return fail(PE_ERR_ARG, "item " + std::to_string(e) + ": no aux for a time-marginalised event");
+            if ((s = ensure_ws(ev, ws_draws(ev, it.n))) != PE_OK) return s;
+            vl.push_back(loglike_entry(ev, it.theta, it.n, it.loglike, it.aux, tm));
         }
         if (stages & PE_STAGE_WEIGHTS) {
             if (!it.stats || (it.n > 0 && (!it.loglike || !it.logprior || !it.logq)))
@@ -885,7 +940,9 @@ pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t* items, int32_t 
     if ((s = run_prep(vp, st)) != PE_OK) return s;
     if ((s = run_metric(vm, st)) != PE_OK) return s;
     if ((s = run_draw(vd, st)) != PE_OK) return s;
+    if ((s = tm_expand(tm, st)) != PE_OK) return s;
     if ((s = run_loglike(vl, precision, st)) != PE_OK) return s;
+    if ((s = tm_reduce(tm, st)) != PE_OK) return s;
     return run_weights(vw, st);
 }
 

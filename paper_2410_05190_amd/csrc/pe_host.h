@@ -101,6 +101,19 @@ DrawArg draw_arg(const pe_event_s* ev, const double* theta0, const double* g, ui
                  int64_t n, double* theta, double* logq, double* logprior);
 EvDev loglike_arg(const pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux);
 
+// Time-marginalised events in a log-likelihood batch (see loglike_entry).
+struct TmJob {
+    pe_event_s* ev;
+    const double* theta;
+    int64_t n;
+    double* loglike;
+};
+EvDev loglike_entry(pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux,
+                    std::vector<TmJob>& tm);
+pe_status_t tm_expand(const std::vector<TmJob>& tm, hipStream_t st);
+pe_status_t tm_reduce(const std::vector<TmJob>& tm, hipStream_t st);
+int64_t ws_draws(const pe_event_s* ev, int64_t n);
+
 // Stage runners: upload the records to the stream's area and queue the launches.
 pe_status_t run_prep(const std::vector<PrepArg>& v, hipStream_t st);
 pe_status_t run_metric(const std::vector<MetricArg>& v, hipStream_t st);

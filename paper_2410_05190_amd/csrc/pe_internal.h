@@ -27,6 +27,8 @@ constexpr double kAmpNewt = 0.21278751013966339916;   // sqrt(5/24) pi^(-2/3)
 struct EvConst {
     int32_t n_det, params, phase, dim;
     int32_t dist, pad_;  // dist: 1 for a distance-marginalised likelihood (11-D)
+    int32_t tm, tm_points;  // tm: 1 for a time-marginalised likelihood (11-D), its tc nodes
+    double tc_lo, tc_hi;
     int64_t K;
     double f_lo, df, scale, amp0, gmst, chi_max, dl_max;
     double dtensor[PE_MAX_DET][6];  // detector tensor (x x^T - y y^T)/2: xx xy xz yy yz zz
@@ -277,6 +279,10 @@ struct pe_event_s {
     int *rcnt = nullptr;         // [npad / 256]
     int *rpos = nullptr;         // [npad]
     double2 *zd = nullptr;       // [npad]
+    // time-marginalised events: the draws at every trapezoid node and their ln L
+    // (the workspace's npad counts these node draws)
+    double *tm_theta = nullptr;  // [PE_MAX_DIM][npad]
+    double *tm_ll = nullptr;     // [npad]
     int64_t partial_cap = 0;  // double2 entries per detector
     double *coef = nullptr;   // [kNCoef][npad]
     int *kcut = nullptr;      // [npad]
@@ -339,6 +345,10 @@ hipError_t launch_weights_batch(const BatchPtrs &b, int ne, int64_t total_blocks
                                 hipStream_t st);
 hipError_t launch_update_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
 void prime_hot_grids();
+// Time-marginalised events: node draws [D][n M] from theta [D][n]; ln L of each
+// draw from the node log-likelihoods (theta: the draws, for their tc).
+hipError_t launch_tm_expand(const double* theta, int64_t n, const EvConst& ec, double* out, hipStream_t st);
+hipError_t launch_tm_reduce(const double* ll, int64_t n, const EvConst& ec, double* out, hipStream_t st);
 hipError_t launch_waveform(const EvConst &ec, int data_psd_dtype, const double *theta, const void *psd, double *h,
                            double *snr2, double *scratch, hipStream_t st);
 hipError_t launch_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int npairs, double *u, hipStream_t st);
@@ -356,7 +366,10 @@ constexpr int kCholLogdet = PE_MAX_DIM * PE_MAX_DIM;
 constexpr int kCholOk = kCholLogdet + 1;
 constexpr int kCholG = kCholLogdet + 2;
 constexpr int kCholRdiag = kCholLogdet + 8;
-constexpr int kCholLen = kCholRdiag + PE_MAX_DIM;
+// time-marginalised events: g_{tc,j} / g_{tc,tc} of the metric as given (the
+// conditional mean of tc given the other coordinates)
+constexpr int kCholTm = kCholRdiag + PE_MAX_DIM;
+constexpr int kCholLen = kCholTm + PE_MAX_DIM;
 constexpr int64_t kMwsScan = kMwsChol + kCholLen;  // segment sums [kSegSums][n_det][kScanSeg]
 // per segment: pw (prefix scan), whitened data power, L1 and L2 of w, max pw
 constexpr int kSegSums = 5;

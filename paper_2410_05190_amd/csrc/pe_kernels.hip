@@ -621,11 +621,16 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
     // is unchanged and the drawn value is never used
     const bool dist = (D == 11) && A.ec.dist;
     const bool pmarg = (D == 11) && A.ec.phase == PE_PHASE_MARG;
+    const bool tmarg = (D == 11) && A.ec.tm;
     if constexpr (D == 11) {
+        // time-marginalised likelihood: tc is not drawn but set to its mean
+        // given the other coordinates, from g_{tc,j} / g_{tc,tc} of g as given
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const int il = m == 0 ? 8 : 10;
-            if (!(m == 0 ? dist : pmarg)) continue;
+        for (int j = 0; j < D; ++j) A.chol[kCholTm + j] = (tmarg && j != 9 && g[9][9] > 0.0) ? g[9][j] / g[9][9] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int il = m == 0 ? 8 : (m == 1 ? 9 : 10);
+            if (!(m == 0 ? dist : (m == 1 ? tmarg : pmarg))) continue;
             const double gll = g[il][il];
             ok = ok && gll > 0.0;
             double cl[D];
@@ -662,7 +667,7 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
     if (ok)
 #pragma unroll
         for (int a = 0; a < D; ++a)
-            if (!(dist && a == 8) && !(pmarg && a == 10)) logdet += log(L[a][a]);
+            if (!(dist && a == 8) && !(tmarg && a == 9) && !(pmarg && a == 10)) logdet += log(L[a][a]);
     A.chol[kCholLogdet] = logdet;
     A.chol[kCholOk] = ok ? 1.0 : 0.0;
 #pragma unroll
@@ -748,6 +753,25 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
         th[pidx[p]] = v - per[p] * kw;
         k0[p] = kw - floor(th0[pidx[p]] / per[p]);
     }
+    const bool tmarg = (D == 11) && ev.tm;
+    if (tmarg) {
+        // tc: its mean under the proposal given the other coordinates, from
+        // their offsets to the wrapped centre (periodic ones to the nearest image)
+        double dlt[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) dlt[a] = th[a] - th0[a];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const double c0 = th0[pidx[p]] - per[p] * floor(th0[pidx[p]] / per[p]);
+            const double d = th[pidx[p]] - c0;
+            dlt[pidx[p]] = d - per[p] * floor(d / per[p] + 0.5);
+        }
+        double m = th0[9 % D];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            if (a != 9) m -= lc[kCholTm + a] * dlt[a];
+        th[9 % D] = m;
+    }
 #pragma unroll
     for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th[a];
     // whitened offset of image m: L^T (x - c) = z + L^T s with c the wrapped
@@ -761,7 +785,7 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
     double zz = 0.0;
 #pragma unroll
     for (int r = 0; r < D; ++r)
-        if (!(dist && r == 8) && !(pmarg && r == 10)) zz = fma(z[r], z[r], zz);
+        if (!(dist && r == 8) && !(tmarg && r == 9) && !(pmarg && r == 10)) zz = fma(z[r], z[r], zz);
     double a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int p = 0; p < NP; ++p)
@@ -862,7 +886,7 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
             acc += exp(l - mx);
         }
     }
-    const int dkeep = D - (dist ? 1 : 0) - (pmarg ? 1 : 0);
+    const int dkeep = D - (dist ? 1 : 0) - (tmarg ? 1 : 0) - (pmarg ? 1 : 0);
     A.logq[i] = mx + log(acc) + lc[kCholLogdet] - 0.5 * dkeep * log(kTwoPi);
     A.logprior[i] = log_prior_of(ev, th);
 }

@@ -990,6 +990,76 @@ __global__ __launch_bounds__(256) void k_b_dist(const BatchHdr* __restrict__ hdr
     }
 }
 
+// Time-marginalised events. Every draw is evaluated at M nodes spread evenly
+// over the whole tc window, t_m = tc_lo + m h with h = T / (M - 1), whatever
+// the draw's own tc: the draws at the nodes (draw i, node m at position
+// i M + m; layout [D][n M]) go through the likelihood like any other draws.
+// The integral over the window is the extended trapezoid rule with fourth-order
+// end corrections (Gregory's form: weights 17/48, 59/48, 43/48, 49/48 on the
+// four nodes at each end and 1 inside, exact for cubics; M >= 8), so
+//   ln L_t = ln sum_m c_m L_m - ln (M - 1).
+// Inside the window the rule converges like the plain trapezoid rule on a
+// smooth peak (error ~ exp(-2 pi^2 s^2 / h^2) for a peak of width s); a peak
+// that the window cuts leaves an O(h^4) error from the end corrections.
+__device__ __forceinline__ double tm_node(const EvConst& ec, int m) {
+    const int M = ec.tm_points;
+    return (m == M - 1) ? ec.tc_hi : ec.tc_lo + (ec.tc_hi - ec.tc_lo) * ((double)m / (double)(M - 1));
+}
+
+__device__ __forceinline__ double tm_weight(int m, int M) {
+    const int e = (m < M - 1 - m) ? m : M - 1 - m;  // distance from the nearer end
+    return e == 0 ? 17.0 / 48.0 : e == 1 ? 59.0 / 48.0 : e == 2 ? 43.0 / 48.0 : e == 3 ? 49.0 / 48.0 : 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_tm_expand(const double* __restrict__ theta, int64_t n, EvConst ec,
+                                                   double* __restrict__ out) {
+    const int M = ec.tm_points;
+    const int64_t nout = n * M;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nout; q += (int64_t)gridDim.x * 256) {
+        const int64_t i = q / M;
+        const int m = (int)(q - i * M);
+        for (int a = 0; a < ec.dim; ++a)
+            out[(int64_t)a * nout + q] = (a == 9) ? tm_node(ec, m) : theta[(int64_t)a * n + i];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tm_reduce(const double* __restrict__ ll, int64_t n, EvConst ec,
+                                                   double* __restrict__ out) {
+    const int M = ec.tm_points;
+    const double lnorm = -log((double)(M - 1));
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double mx = -INFINITY, acc = 0.0;
+        bool bad = false;
+        for (int m = 0; m < M; ++m) {
+            const double v = ll[i * M + m];
+            if (isnan(v) || v == INFINITY) bad = true;
+            if (!(v > -INFINITY)) continue;
+            const double c = tm_weight(m, M);
+            if (v > mx) {
+                acc = acc * exp(mx - v) + c;
+                mx = v;
+            } else {
+                acc += c * exp(v - mx);
+            }
+        }
+        out[i] = bad ? NAN : (mx > -INFINITY ? mx + log(acc) + lnorm : -INFINITY);
+    }
+}
+
+static unsigned tm_grid(int64_t blocks) { return (unsigned)(blocks < 1 ? 1 : (blocks < 16384 ? blocks : 16384)); }
+
+hipError_t launch_tm_expand(const double* theta, int64_t n, const EvConst& ec, double* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_tm_expand<<<tm_grid(blocks256(n * ec.tm_points)), 256, 0, st>>>(theta, n, ec, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tm_reduce(const double* ll, int64_t n, const EvConst& ec, double* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_tm_reduce<<<tm_grid(blocks256(n)), 256, 0, st>>>(ll, n, ec, out);
+    return hipGetLastError();
+}
+
 // Workgroups that fit on the GPU at once for a hot-loop kernel.
 template <typename Kern>
 static unsigned resident_grid(Kern kernel) {

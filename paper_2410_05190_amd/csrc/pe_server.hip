@@ -508,6 +508,7 @@ pe_status_t pe_server_submit(pe_server_t srv, const pe_request_t* req, int64_t* 
     if (req->n_draws < 1 || req->n_draws > kMaxServerDraws) return fail(PE_ERR_ARG, "n_draws must be in 1..2^22");
     if (!req->data || !req->psd || !req->theta0) return fail(PE_ERR_ARG, "data, psd and theta0 are required");
     if (req->metric_flags & ~1) return fail(PE_ERR_ARG, "unknown metric flags");
+    if (req->desc.time_marg) return fail(PE_ERR_ARG, "the server does not take time-marginalised events");
     Req* q = new (std::nothrow) Req();
     if (!q) return fail(PE_ERR_OOM, "host allocation failed");
     q->r = *req;

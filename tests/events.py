@@ -31,17 +31,21 @@ class Built:
     snr: float
     ev: object = field(repr=False, default=None)
     distance: int = 0
+    time_marg: int = 0
+    tm_points: int = 0
+    tc_lo: float = 0.0
+    tc_hi: float = 0.0
 
     def desc(self):
         """Keyword arguments shared by the oracle Event and the GPU binding's event description."""
         return dict(n_det=self.n_det, n_bins=self.n_bins, f_lo=self.f_lo, df=self.df,
                     strain_scale=self.strain_scale, params=self.params, phase=self.phase, amp0=self.amp0,
                     gmst=self.gmst, chi_max=self.chi_max, dl_max=self.dl_max, det_geom=self.det_geom,
-                    distance=self.distance)
+                    distance=self.distance, time_marg=self.time_marg, tc_lo=self.tc_lo, tc_hi=self.tc_hi)
 
 
 def build_event(config, event=0, n_bins=None, n_det=None, zero_noise=False, storage=None, phase=None,
-                snr=None, dl_max=None, distance=0):
+                snr=None, dl_max=None, distance=0, time_marg=None):
     c = synth.CONFIGS[config]
     f_lo, df, K = synth.grid(config)
     if n_bins is not None:
@@ -78,8 +82,11 @@ def build_event(config, event=0, n_bins=None, n_det=None, zero_noise=False, stor
         data_s = np.ascontiguousarray((h + n) * sc, dtype=np.complex64)
         psd_s = np.ascontiguousarray(S * sc * sc, dtype=np.float32)
         s = sc
+    tm = dict(time_marg or {})  # {"tc_lo", "tc_hi", "tm_points"}: time-marginalised events
     ev = oracle.Event(nd, K, f_lo, df, data=data_s, psd=psd_s, strain_scale=s, amp0=amp0, distance=distance,
-                      **common)
+                      time_marg=1 if tm else 0, tc_lo=tm.get("tc_lo", 0.0), tc_hi=tm.get("tc_hi", 0.0), **common)
     return Built(config=config, n_det=nd, n_bins=K, f_lo=f_lo, df=df, data=data_s, psd=psd_s, strain_scale=s,
                  params=params, phase=phase, amp0=amp0, gmst=0.0, chi_max=c["chi_max"], dl_max=dlm,
-                 det_geom=geom, theta_inj=theta, snr=target, ev=ev, distance=int(distance))
+                 det_geom=geom, theta_inj=theta, snr=target, ev=ev, distance=int(distance),
+                 time_marg=1 if tm else 0, tm_points=int(tm.get("tm_points", 0)),
+                 tc_lo=float(tm.get("tc_lo", 0.0)), tc_hi=float(tm.get("tc_hi", 0.0)))

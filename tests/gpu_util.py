@@ -21,7 +21,8 @@ def note(msg):
 
 def desc_kwargs(b):
     return dict(f_lo=b.f_lo, df=b.df, strain_scale=b.strain_scale, params=b.params, phase=b.phase, amp0=b.amp0,
-                gmst=b.gmst, chi_max=b.chi_max, dl_max=b.dl_max, det_geom=b.det_geom, distance=b.distance)
+                gmst=b.gmst, chi_max=b.chi_max, dl_max=b.dl_max, det_geom=b.det_geom, distance=b.distance,
+                time_marg=b.time_marg, tm_points=b.tm_points, tc_lo=b.tc_lo, tc_hi=b.tc_hi)
 
 
 def upload_event(b):

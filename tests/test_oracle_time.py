@@ -2,7 +2,7 @@
 
 The paper marginalises the extrinsic parameters (Sec. III). For the coalescence time with a flat prior
 on [tc_lo, tc_hi], L_t = (1/T) int L(theta with tc = t) dt. The oracle evaluates Z(t) by shifting the
-draw's integrand in time and integrates with the trapezoid rule over the whole window. It is pinned by:
+draw's integrand in time and integrates with Simpson's rule over the whole window. It is pinned by:
   - re-evaluating the sampled-tc likelihood with the waveform recomputed at every tc (a different code
     path) and integrating that with scipy's Simpson rule on a fine grid;
   - the narrow-window limit, which equals the sampled-tc likelihood at the window's centre;
@@ -24,8 +24,8 @@ def _tm_event(b, tc_lo, tc_hi, phase=None, data=True):
     kw = b.desc()
     if phase is not None:
         kw["phase"] = phase
-    kw.pop("n_det")
-    kw.pop("n_bins")
+    for k in ("n_det", "n_bins", "time_marg", "tc_lo", "tc_hi"):
+        kw.pop(k)
     return oracle.Event(b.n_det, b.n_bins, data=b.data if data else np.zeros_like(b.data), psd=b.psd,
                         time_marg=1, tc_lo=tc_lo, tc_hi=tc_hi, **kw)
 
@@ -34,8 +34,8 @@ def _sampled_event(b, phase=None):
     kw = b.desc()
     if phase is not None:
         kw["phase"] = phase
-    kw.pop("n_det")
-    kw.pop("n_bins")
+    for k in ("n_det", "n_bins", "time_marg", "tc_lo", "tc_hi"):
+        kw.pop(k)
     return oracle.Event(b.n_det, b.n_bins, data=b.data, psd=b.psd, **kw)
 
 
