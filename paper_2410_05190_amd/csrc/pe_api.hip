@@ -166,6 +166,7 @@ size_t layout_tables(pe_event_s* ev, char* base) {
     ev->pfx = c.take<double>((size_t)nd * (K + 1));
     ev->pl1 = c.take<double>((size_t)nd * (K + 1));
     ev->pw2 = c.take<double>((size_t)nd * (K + 1));
+    ev->ppw = c.take<double>((size_t)nd * (K + 1));
     ev->guard = c.take<double>((size_t)kGuardLen);
     ev->status = c.take<int>(1);
     ev->mws = c.take<double>((size_t)kMwsTotal);
@@ -444,6 +445,7 @@ PrepArg prep_arg(const pe_event_s* ev, const void* data, const void* psd) {
     a.pfx = ev->pfx;
     a.pl1 = ev->pl1;
     a.pw2 = ev->pw2;
+    a.ppw = ev->ppw;
     a.seg = ev->mws + kMwsScan;
     a.guard = ev->guard;
     a.status = ev->status;
@@ -538,6 +540,7 @@ EvDev loglike_arg(const pe_event_s* ev, const double* theta, int64_t n, double* 
     d.pfx = ev->pfx;
     d.pl1 = ev->pl1;
     d.pw2 = ev->pw2;
+    d.ppw = ev->ppw;
     d.guard = ev->guard;
     d.kc_all = ev->kc_all;
     d.hist = ev->hist;

@@ -61,6 +61,7 @@ static_assert(kRecStride >= PE_MAX_DIM, "a record holds one draw's parameters");
 static_assert(kRecStride % 2 == 0, "records are written as 16-byte pairs");
 
 constexpr int kTile = 256;    // draws per workgroup of the hot loop
+constexpr int kRedoTile = 64; // draws per workgroup (one wave) of the FP64 re-evaluation
 constexpr int kBlk = 16;      // bins per FP32 block sum before its fold into FP64
 constexpr int kBuckets = 4096;  // ISCO-cut buckets of the draw ordering
 constexpr int kTabPad = 8;      // zeroed records past the last bin
@@ -93,7 +94,8 @@ struct EvPlan {
     int fine;      // bins per chunk (a multiple of kBlk)
     int n_fine;    // chunks over [0, kmax)
     int n_groups;  // groups of chunks = partials per draw and detector
-    int tiles;     // tiles of kTile live draws
+    int tiles;     // tiles of kTile live draws (plan of the re-evaluation: of kRedoTile listed draws)
+    int stride;    // column stride of the partials (the re-evaluation's; the main plan uses npad)
 };
 
 // ---------------------------------------------------------------------------
@@ -111,7 +113,8 @@ struct PrepArg {
     Rec32 *rec32;
     Rec64 *rec64;
     double *pw, *pfx, *seg;
-    double *pl1, *pw2;  // [n_det][K+1] exclusive prefixes of |w| and |w|^2 (split-path error estimate)
+    double *pl1, *pw2, *ppw;  // [n_det][K+1] exclusive prefixes of |w|, |w|^2 and the whitened power |w|^2/pw
+                              // (split-path error estimate)
     double *guard;  // [PE_MAX_DET][kGuardStride] noise statistics of the data (split-path error estimate)
     int *status;
 };
@@ -146,7 +149,7 @@ struct EvDev {
     const Rec32 *rec32;
     const Rec64 *rec64;
     const double *pfx;
-    const double *pl1, *pw2;  // [n_det][K+1] exclusive prefixes of |w| and |w|^2
+    const double *pl1, *pw2, *ppw;  // [n_det][K+1] exclusive prefixes of |w|, |w|^2, |w|^2/pw
     const double *guard;  // noise statistics of the event's data (see kGuardStride)
     int *kc_all, *hist, *idx, *kcut;
     double *coef, *resp, *hh;
@@ -229,8 +232,8 @@ struct BatchHdr {
 //   eps_coh(a) C_d + kEpsL1 |R_d| L1_d   and the worst case   kEpsMax |R_d| L1_d
 // (L1_d = sum |w_k| and W2_d = sum |w_k|^2 below the draw's cut; C_d the
 // larger of |R_d Z_d| and the matched magnitude sqrt(H_d rho2_d), rho2_d a
-// bound on the detector's signal power from the data's whitened power in
-// excess of the noise's) plus the scatter kEpsInc sqrt(sum_d |R_d|^2 W2_d),
+// bound on the detector's signal power below the cut from the data's whitened
+// power there in excess of the noise's) plus the scatter kEpsInc sqrt(sum_d |R_d|^2 W2_d),
 // which adds in quadrature over the detectors. Where the data carry less than
 // the PSD's noise (e.g. noise-free injections) only the worst case applies.
 // Draws whose bound exceeds the batch's redo budget are re-evaluated in FP64
@@ -266,6 +269,7 @@ struct pe_event_s {
     double *pfx = nullptr;  // [n_det][K+1] exclusive prefix of pw
     double *pl1 = nullptr;  // [n_det][K+1] exclusive prefix of |w|
     double *pw2 = nullptr;  // [n_det][K+1] exclusive prefix of |w|^2
+    double *ppw = nullptr;  // [n_det][K+1] exclusive prefix of the whitened data power |w|^2 / pw
     double *guard = nullptr;  // [kGuardLen] noise statistics of the data
     int *status = nullptr;  // device status word
     double *mws = nullptr;  // metric + draw workspace

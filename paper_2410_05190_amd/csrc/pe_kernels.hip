@@ -172,7 +172,8 @@ __global__ __launch_bounds__(256) void k_seg_sums(const BatchHdr* __restrict__ h
 
 // Each segment: its carries (the sums of the segment sums before it, one block
 // reduction each), then block-wide inclusive scans per 256 bins of pw (into
-// pfx), |w| (into pl1) and |w|^2 (into pw2).
+// pfx), |w| (into pl1), |w|^2 (into pw2) and the whitened power |w|^2 / pw (into
+// ppw).
 __device__ __forceinline__ double block_scan_excl(double v, double* sh, double& tile) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double inc = v;
@@ -209,40 +210,47 @@ __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ h
         double* o = A.pfx + po;
         double* o1 = A.pl1 + po;
         double* o2 = A.pw2 + po;
+        double* o3 = A.ppw + po;
         const int64_t slice = (int64_t)PE_MAX_DET * kScanSeg;
         const double* sg = A.seg + (int64_t)d * kScanSeg + threadIdx.x;
         const bool before = (int)threadIdx.x < b;
         double carry = block_sum4(before ? sg[0] : 0.0, sh);
         double carry1 = block_sum4(before ? sg[2 * slice] : 0.0, sh);
         double carry2 = block_sum4(before ? sg[3 * slice] : 0.0, sh);
+        double carry3 = block_sum4(before ? sg[slice] : 0.0, sh);
         const int64_t k0 = (int64_t)b * seg;
         const int64_t k1 = min(k0 + seg, K);
         for (int64_t base = k0; base < k1; base += 256) {
             const int64_t k = base + threadIdx.x;
-            double v = 0.0, v1 = 0.0, v2 = 0.0;
+            double v = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
             if (k < k1) {
                 v = a[k];
                 const double2 w = A.rec64[k].w[d];
                 v2 = w.x * w.x + w.y * w.y;
                 v1 = sqrt(v2);
+                if (v > 0.0) v3 = v2 / v;
             }
-            double t, t1, t2;
+            double t, t1, t2, t3;
             const double x = block_scan_excl(v, sh, t);
             const double x1 = block_scan_excl(v1, sh, t1);
             const double x2 = block_scan_excl(v2, sh, t2);
+            const double x3 = block_scan_excl(v3, sh, t3);
             if (k < k1) {
                 o[k] = carry + x;
                 o1[k] = carry1 + x1;
                 o2[k] = carry2 + x2;
+                o3[k] = carry3 + x3;
             }
             carry += t;
             carry1 += t1;
             carry2 += t2;
+            carry3 += t3;
         }
         if (b == nseg - 1 && threadIdx.x == 0) {
             o[K] = carry;
             o1[K] = carry1;
             o2[K] = carry2;
+            o3[K] = carry3;
         }
         if (b == 0) {
             // the detector's noise statistics: segments combined in a fixed order

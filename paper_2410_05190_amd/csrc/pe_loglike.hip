@@ -649,9 +649,49 @@ __device__ __forceinline__ void f64_item(const EvDev& E, const EvPlan& p, int ti
 // One item of the FP64 re-evaluation: lane r of the tile takes the r-th listed
 // draw (position rpos[r]); its partials go to column r. The walk is the FP64
 // kernel's, under the same plan, so each listed draw gets the FP64 path's value.
+// Tiles of the re-evaluation are one wave (kRedoTile draws): the listed draws
+// are few, and one-wave workgroups give the persistent grid enough waves per
+// SIMD to hide the latency of the FP64 sine/cosine chains (a draw's arithmetic
+// does not depend on the tile size).
+// The walk stages the records of each piece of kRedoTile bins in LDS (one
+// record per lane, 16-byte vector loads) and every lane reads them back by
+// broadcast: the few tiles of listed draws reuse a record too little for the
+// scalar loads of the FP64 kernel to find it in L2, and a lone wave would wait
+// on each of them. The bins and their order are f64_walk's.
 template <int NDET>
-__device__ __forceinline__ void redo_item(const EvDev& E, const EvPlan& rp, int tile, int g) {
-    const int r = tile * kTile + (int)threadIdx.x;
+__device__ __forceinline__ void redo_walk(const EvDev& E, const EvPlan& p, int g, const DrawRow& row,
+                                          const double (&tau)[NDET], int kc, int wmin, int wmax,
+                                          double (&zr)[NDET], double (&zi)[NDET], Rec64* srec) {
+    const Rec64* tab = E.rec64;
+    const int K = (int)E.ec.K;
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) zr[d] = zi[d] = 0.0;
+    for (int c = g; c < p.n_fine; c += p.n_groups) {
+        const int k0 = c * p.fine;
+        if (k0 >= wmax) break;
+        const int k1 = min(k0 + p.fine, K);
+        const int kA = max(k0, min(k1, wmin));
+        const int kB = max(kA, min(k1, wmax));
+        for (int ks = k0; ks < kB; ks += kRedoTile) {
+            const int ke = min(ks + kRedoTile, kB);
+            __syncthreads();  // the previous piece has been read
+            if (ks + (int)threadIdx.x < ke) {
+                const uint4* src = (const uint4*)(tab + ks + threadIdx.x);
+                uint4* dst = (uint4*)(srec + threadIdx.x);
+#pragma unroll
+                for (int q = 0; q < (int)(sizeof(Rec64) / 16); ++q) dst[q] = src[q];
+            }
+            __syncthreads();
+            const int ka = min(ke, kA);
+            for (int k = ks; k < ka; ++k) bin_f64<NDET, false>(srec[k - ks], row, tau, true, zr, zi);
+            for (int k = max(ks, kA); k < ke; ++k) bin_f64<NDET, true>(srec[k - ks], row, tau, k < kc, zr, zi);
+        }
+    }
+}
+
+template <int NDET>
+__device__ __forceinline__ void redo_item(const EvDev& E, const EvPlan& rp, int tile, int g, Rec64* srec) {
+    const int r = tile * kRedoTile + (int)threadIdx.x;
     const bool valid = r < rp.n_active;
     const int jl = ((gints)E.rpos)[valid ? r : rp.n_active - 1];
     int kc, wmin, wmax;
@@ -659,10 +699,10 @@ __device__ __forceinline__ void redo_item(const EvDev& E, const EvPlan& rp, int 
     double tau[NDET];
     load_row<NDET>(E, jl, valid, row, tau, kc, wmin, wmax);
     double zr[NDET], zi[NDET];
-    f64_walk<NDET>(E, rp, g, row, tau, kc, wmin, wmax, zr, zi);
+    redo_walk<NDET>(E, rp, g, row, tau, kc, wmin, wmax, zr, zi, srec);
     if (valid) {
 #pragma unroll
-        for (int d = 0; d < NDET; ++d) E.partial[((int64_t)g * NDET + d) * E.npad + r] = make_double2(zr[d], zi[d]);
+        for (int d = 0; d < NDET; ++d) E.partial[((int64_t)g * NDET + d) * rp.stride + r] = make_double2(zr[d], zi[d]);
     }
 }
 
@@ -698,9 +738,8 @@ __global__ __launch_bounds__(256) void k_b_f64(BatchHdr* __restrict__ hdr, const
 
 // Fixed-order combine of a draw's group partials for one detector (8
 // interleaved accumulators, then a pairwise tree); col: the draw's column.
-__device__ __forceinline__ void combine_groups(const EvDev& E, int d, int nd, int G, int64_t col, double& ar,
-                                               double& ai) {
-    const int64_t np = E.npad;
+__device__ __forceinline__ void combine_groups(const EvDev& E, int d, int nd, int G, int64_t col, int64_t np,
+                                               double& ar, double& ai) {
     double xr[8], xi[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) xr[q] = xi[q] = 0.0;
@@ -739,19 +778,24 @@ __device__ __forceinline__ double eps_coherent(double a2) {
 
 // Bound on |d ln L| of the split path for one detector of a draw (see
 // kEpsHarm): guard G, |R_d|, the detector's FP32-path sum (ar, ai), and below
-// the draw's cut C = sum pw, l1 = sum |w|, w2 = sum |w|^2. lin gains the part
-// that adds linearly over detectors, var the variance of the scatter (in units
-// of kEpsInc^2).
+// the draw's cut kc: C = sum pw, l1 = sum |w|, w2 = sum |w|^2 and pp = sum of the
+// whitened data power. lin gains the part that adds linearly over detectors,
+// var the variance of the scatter (in units of kEpsInc^2).
+// The signal power below the cut is bounded like the band's (see kGuardRho2):
+// noise gives each bin whitened power 2 on average, sd 2 sqrt(kc) over the kc
+// bins, so rho2 = pp - 2 kc + 12 sqrt(kc) bounds it with 6 sd of margin; data
+// with less power than the noise less 6 sd there take the worst case only.
 __device__ __forceinline__ void split_error(const double* __restrict__ G, double rm, double ar, double ai, double c,
-                                            double l1, double w2, double& lin, double& var) {
+                                            double l1, double w2, double pp, int kc, double& lin, double& var) {
     if (rm == 0.0 || c == 0.0) return;
     var += rm * rm * w2;
     const double worst = kEpsMax * rm * l1;  // every term's error at its largest
-    const double rho2 = G[kGuardRho2];
-    if (rho2 < 0.0) {  // no noise to scatter the phases: the worst case only
+    const double slack = 12.0 * sqrt((double)kc), excess = pp - 2.0 * (double)kc;
+    if (G[kGuardRho2] < 0.0 || excess < -slack) {  // no noise to scatter the phases: the worst case only
         lin += worst;
         return;
     }
+    const double rho2 = excess + slack;
     const double coh = fmax(rm * hypot(ar, ai), sqrt(rm * rm * c * rho2));
     lin += fmin(worst, eps_coherent(rho2 * G[kGuardPwMax] / c) * coh + kEpsL1 * rm * l1);
 }
@@ -781,7 +825,7 @@ __global__ __launch_bounds__(256) void k_b_finalize(BatchHdr* __restrict__ hdr, 
             double zr = 0.0, zi = 0.0, lin = 0.0, var = 0.0;
             for (int d = 0; d < nd; ++d) {
                 double ar, ai;
-                combine_groups(E, d, nd, p.n_groups, j, ar, ai);
+                combine_groups(E, d, nd, p.n_groups, j, E.npad, ar, ai);
                 if (SPLIT) {
                     ar *= kTrigGain;
                     ai *= kTrigGain;
@@ -792,7 +836,7 @@ __global__ __launch_bounds__(256) void k_b_finalize(BatchHdr* __restrict__ hdr, 
                 if (SPLIT) {
                     const int64_t o = (int64_t)d * (E.ec.K + 1) + kc;
                     split_error(E.guard + d * kGuardStride, hypot(rr, ri), ar, ai, E.pfx[o], E.pl1[o], E.pw2[o],
-                                lin, var);
+                                E.ppw[o], kc, lin, var);
                 }
             }
             if (SPLIT) {
@@ -827,7 +871,11 @@ __global__ __launch_bounds__(256) void k_b_finalize(BatchHdr* __restrict__ hdr, 
 
 // Per event that finalises: exclusive scan of the marked counts of its blocks
 // (in place: rcnt becomes each block's offset) and the plan of the FP64
-// re-evaluation: the event's plan with n_active = marked draws.
+// re-evaluation: the event's chunks for the marked draws, in as many groups as
+// their partials allow, up to every chunk its own group (8G groups, those past
+// n_fine empty): the marked draws are usually few, and short items keep any
+// single wave's walk from setting the kernel's length. The grouping differs from
+// the FP64 path's, so a re-evaluated draw equals that path's value to rounding.
 __global__ __launch_bounds__(1024) void k_r_plan(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs) {
     __shared__ int sh[1024];
     const int ne = hdr->ne;
@@ -867,7 +915,12 @@ __global__ __launch_bounds__(1024) void k_r_plan(const BatchHdr* __restrict__ hd
         if (t == 0) {
             EvPlan r = p;
             r.n_active = carry;
-            r.tiles = (carry + kTile - 1) / kTile;
+            r.tiles = (carry + kRedoTile - 1) / kRedoTile;
+            const int64_t cols = (int64_t)r.tiles * kRedoTile;
+            const int64_t cap = (int64_t)E.max_groups * E.npad;  // partial columns the workspace holds
+            r.stride = (int)cols;
+            while (carry > 0 && r.n_groups < 8 * p.n_groups && 2 * (int64_t)r.n_groups * cols <= cap)
+                r.n_groups *= 2;
             E.plan[1] = r;
         }
         __syncthreads();
@@ -910,20 +963,21 @@ __global__ void k_r_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ 
     hdr->qnext[x] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_r_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+__global__ __launch_bounds__(kRedoTile) void k_r_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                const int64_t* __restrict__ ioff) {
     int items = 0;
 #pragma unroll
     for (int q = 0; q < kQueues; ++q) items += hdr->qitems[q];
     if (items == 0) return;  // nothing listed (uniform over the grid)
+    __shared__ Rec64 srec[kRedoTile];
     item_loop<true>(hdr, ioff, evs, [&](const Item& it) {
         const EvDev& E = evs[it.e];
         const EvPlan rp = load_const(E.plan + 1);
         switch (E.ec.n_det) {
-            case 1: redo_item<1>(E, rp, it.tile, it.g); break;
-            case 2: redo_item<2>(E, rp, it.tile, it.g); break;
-            case 3: redo_item<3>(E, rp, it.tile, it.g); break;
-            default: redo_item<4>(E, rp, it.tile, it.g); break;
+            case 1: redo_item<1>(E, rp, it.tile, it.g, srec); break;
+            case 2: redo_item<2>(E, rp, it.tile, it.g, srec); break;
+            case 3: redo_item<3>(E, rp, it.tile, it.g, srec); break;
+            default: redo_item<4>(E, rp, it.tile, it.g, srec); break;
         }
     });
 }
@@ -946,7 +1000,7 @@ __global__ __launch_bounds__(256) void k_r_finalize(const BatchHdr* __restrict__
         double zr = 0.0, zi = 0.0;
         for (int d = 0; d < nd; ++d) {
             double ar, ai;
-            combine_groups(E, d, nd, rp.n_groups, r, ar, ai);
+            combine_groups(E, d, nd, rp.n_groups, r, rp.stride, ar, ai);
             const double rr = E.resp[(2 * d) * np + j], ri = E.resp[(2 * d + 1) * np + j];
             zr += rr * ar - ri * ai;
             zi += rr * ai + ri * ar;
@@ -1062,11 +1116,11 @@ hipError_t launch_tm_reduce(const double* ll, int64_t n, const EvConst& ec, doub
 
 // Workgroups that fit on the GPU at once for a hot-loop kernel.
 template <typename Kern>
-static unsigned resident_grid(Kern kernel) {
+static unsigned resident_grid(Kern kernel, int block = kTile) {
     int per_cu = 0, dev = 0, n_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 2048;
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 2048;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTile, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     return (unsigned)(per_cu * n_cu);
 }
@@ -1085,7 +1139,7 @@ static unsigned f64_grid() {
     return grid;
 }
 static unsigned redo_grid() {
-    static const unsigned grid = resident_grid(k_r_f64);
+    static const unsigned grid = resident_grid(k_r_f64, kRedoTile);
     return grid;
 }
 
@@ -1134,7 +1188,7 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
             k_r_scatter<<<fg, 256, 0, st>>>(b.hdr, evs, b.off2);
             k_r_items<<<1, 64, 0, st>>>(b.hdr, evs, ioff);
             if (profile) prof_begin("loglike_redo", st);
-            k_r_f64<<<redo_grid(), kTile, 0, st>>>(b.hdr, evs, ioff);
+            k_r_f64<<<redo_grid(), kRedoTile, 0, st>>>(b.hdr, evs, ioff);
             if (profile) prof_end("loglike_redo", st);
             k_r_finalize<<<fg, 256, 0, st>>>(b.hdr, evs, b.off2);
         } else {

@@ -3,8 +3,9 @@
 Each split-path draw gets a bound on its |d ln L|. The bound comes from the measured error spectrum of
 the hardware sine/cosine and the data's noise statistics. Draws above the budget of pe_set_split_guard
 are re-evaluated in FP64, on the hot loop's own layout, within the same call. The tests check:
-  - budget 0: every live draw is re-evaluated, and the split call then equals the FP64 path bit for bit
-    (single events and a multi-event batch);
+  - budget 0: every live draw is re-evaluated, and the split call then equals the FP64 path to FP64
+    rounding (the re-evaluation may split the band into more groups than the FP64 path; 1e-12 relative,
+    1e-9 absolute), for single events and a multi-event batch;
   - noise-free data: the worst-case regime lists the loud draws, and every draw stays within 1e-3 of the
     oracle;
   - a config-4-shaped event at SNR 95 (the top of that configuration's range), full size: sampled draws
@@ -43,7 +44,7 @@ def _draws(b, n, seed, metric_event=None):
 
 @pytest.mark.parametrize("cfg,K,n", [(1, 40000, 1500), (0, 31488, 700), (2, 8032, 3000)])
 def test_zero_budget_equals_fp64_path(cfg, K, n):
-    """Budget 0 sends every live draw through the FP64 re-evaluation, so split == FP64 bit for bit."""
+    """Budget 0 sends every live draw through the FP64 re-evaluation, so split == FP64 to rounding."""
     torch_cuda()
     b = build_event(cfg, 1, n_bins=K)
     th = dev(_draws(b, n, 21))
@@ -58,9 +59,11 @@ def test_zero_budget_equals_fp64_path(cfg, K, n):
     ev.status()
     note(f"cfg {cfg}: live {live}, re-evaluated {redo}")
     assert live == live_d and redo == live and live > 0
-    assert np.array_equal(ll_s, ll_d)
+    fin = np.isfinite(ll_d)
+    assert np.array_equal(fin, np.isfinite(ll_s))
+    np.testing.assert_allclose(ll_s[fin], ll_d[fin], rtol=1e-12, atol=1e-9)
     ll_d2, ax_d = ev.loglike(th, precision=binding.PE_PREC_FP64, aux=True)
-    assert np.array_equal(host(ax_d), ax_s)
+    np.testing.assert_allclose(ax_s, host(ax_d), rtol=1e-12, atol=1e-9)
     ev.close()
 
 
@@ -81,7 +84,9 @@ def test_zero_budget_multi_event_batch_equals_fp64():
         counts = [binding.pe_loglike_counts(ev) for ev in evs]
     for w, g, (live, redo) in zip(want, got, counts):
         assert redo == live and live > 0
-        assert np.array_equal(w, g)
+        fin = np.isfinite(w)
+        assert np.array_equal(fin, np.isfinite(g))
+        np.testing.assert_allclose(g[fin], w[fin], rtol=1e-12, atol=1e-9)
     for ev in evs:
         ev.close()
 
