@@ -282,11 +282,13 @@ def main():
             "likelihood marginalised over the coalescence phase (ln I0 form) and the luminosity distance "
             "(dL^2 prior); both left out of the proposal density")
         if args.time_leg:
-            # nodes half the explicit-phase peak width 1/sqrt(g_tc,tc) apart over the window (the
-            # phase-marginalised peak is wider)
+            # nodes half the phase-marginalised integrand's width in tc apart over the window: that
+            # integrand follows the envelope |Z(t)|, whose curvature is g_tc,tc with the phase
+            # projected out (the Schur complement of the explicit-phase metric's phic row)
             gh = first["g"].cpu().numpy()
+            g_tt = gh[9, 9] - gh[9, 10] ** 2 / gh[10, 10]
             lo, hi = first["theta_inj"][9] - 0.01, first["theta_inj"][9] + 0.01
-            pts = int(math.ceil((hi - lo) / (0.5 / math.sqrt(gh[9, 9])))) + 1
+            pts = int(math.ceil((hi - lo) / (0.5 / math.sqrt(g_tt)))) + 1
             tm = {"tc_lo": float(lo), "tc_hi": float(hi), "tm_points": pts}
             leg = distance_leg(first, centres, max(args.steps // 4, 2), prec, phase=binding.PE_PHASE_MARG,
                                time_marg=tm, n_draws=args.time_leg_draws)

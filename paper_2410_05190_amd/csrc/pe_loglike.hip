@@ -1077,16 +1077,23 @@ __global__ __launch_bounds__(256) void k_tm_expand(const double* __restrict__ th
     }
 }
 
+// One wave per draw: lane l takes the nodes l, l + 64, ... (coalesced reads),
+// keeping its largest ln L_m and the weighted sum of exp(ln L_m - max) with a
+// running maximum; a butterfly then merges the lanes' (max, sum) pairs. Both
+// partners of an exchange form the same commutative sum, so every lane ends
+// with the same value, and the order of the merge is fixed.
 __global__ __launch_bounds__(256) void k_tm_reduce(const double* __restrict__ ll, int64_t n, EvConst ec,
                                                    double* __restrict__ out) {
     const int M = ec.tm_points;
     const double lnorm = -log((double)(M - 1));
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = ((int64_t)gridDim.x * 256) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6; i < n; i += waves) {
         double mx = -INFINITY, acc = 0.0;
-        bool bad = false;
-        for (int m = 0; m < M; ++m) {
+        int bad = 0;
+        for (int m = lane; m < M; m += 64) {
             const double v = ll[i * M + m];
-            if (isnan(v) || v == INFINITY) bad = true;
+            if (isnan(v) || v == INFINITY) bad = 1;
             if (!(v > -INFINITY)) continue;
             const double c = tm_weight(m, M);
             if (v > mx) {
@@ -1096,7 +1103,16 @@ __global__ __launch_bounds__(256) void k_tm_reduce(const double* __restrict__ ll
                 acc += c * exp(v - mx);
             }
         }
-        out[i] = bad ? NAN : (mx > -INFINITY ? mx + log(acc) + lnorm : -INFINITY);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double mo = __shfl_xor(mx, o), ao = __shfl_xor(acc, o);
+            bad |= __shfl_xor(bad, o);
+            const double mm = fmax(mx, mo);
+            if (mm > -INFINITY)
+                acc = (mx > -INFINITY ? acc * exp(mx - mm) : 0.0) + (mo > -INFINITY ? ao * exp(mo - mm) : 0.0);
+            mx = mm;
+        }
+        if (lane == 0) out[i] = bad ? NAN : (mx > -INFINITY ? mx + log(acc) + lnorm : -INFINITY);
     }
 }
 
@@ -1110,7 +1126,7 @@ hipError_t launch_tm_expand(const double* theta, int64_t n, const EvConst& ec, d
 
 hipError_t launch_tm_reduce(const double* ll, int64_t n, const EvConst& ec, double* out, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    k_tm_reduce<<<tm_grid(blocks256(n)), 256, 0, st>>>(ll, n, ec, out);
+    k_tm_reduce<<<tm_grid(blocks256(n * 64)), 256, 0, st>>>(ll, n, ec, out);
     return hipGetLastError();
 }
 

@@ -47,15 +47,19 @@ def test_time_marg_draw_parity():
     ev.close()
 
 
-@pytest.mark.parametrize("cfg,n_bins,phase,distance,n,half_window",
-                         [(1, 12000, None, 0, 24, 0.05), (2, None, None, 0, 24, 0.2), (1, 12000, 0, 0, 24, 0.05),
-                          (2, None, None, 0, 12, 0.004)])
-def test_time_marg_loglike_parity(cfg, n_bins, phase, distance, n, half_window):
+@pytest.mark.parametrize("cfg,n_bins,phase,distance,n,half_window,own",
+                         [(1, 12000, None, 0, 24, 0.05, False), (2, None, None, 0, 24, 0.2, False),
+                          (1, 12000, 0, 0, 24, 0.05, False), (1, 12000, 0, 0, 24, 0.05, True),
+                          (2, None, None, 0, 24, 0.2, True), (2, None, None, 0, 12, 0.004, False)])
+def test_time_marg_loglike_parity(cfg, n_bins, phase, distance, n, half_window, own):
     """ln L_t of proposal draws (split and FP64) against the oracle's whole-window integral. Config 1
     shape with explicit and marginalised phase; config 2 (phase marginalised, two detectors), also
-    with a window of +-4 ms that cuts most draws' peaks."""
+    with a window of +-4 ms that cuts most draws' peaks. own: phase-marginalised events with the nodes
+    half the envelope's width apart (the phase-projected metric's 1/sqrt(g_tc,tc), about four times
+    the explicit-phase width), the narrowest scale of ln I0(|Z(t)|)."""
     torch_cuda()
-    b, b0, g, sig_t = tm_event(cfg, 1, n_bins, phase=phase, distance=distance, half_window=half_window)
+    b, b0, g, sig_t = tm_event(cfg, 1, n_bins, phase=phase, distance=distance, half_window=half_window,
+                               own_width=own)
     rc, th, lq, lp = b.ev.draw(b.theta_inj, g, 777, 0, 400)
     live = np.flatnonzero(np.isfinite(lp))[:n]
     th = np.ascontiguousarray(th[:, live])

@@ -9,13 +9,17 @@ import oracle
 from events import build_event
 
 
-def tm_event(cfg, event, n_bins, phase=None, distance=0, half_window=0.05):
+def tm_event(cfg, event, n_bins, phase=None, distance=0, half_window=0.05, own_width=False):
     """(time-marginalised event, the same event with tc sampled, sampled-tc metric at the injection,
-    the narrowest tc width)."""
+    the narrowest tc width). own_width: the width from the event's own metric (for a phase-marginalised
+    event the envelope's width, the phase projected out) instead of the explicit-phase one."""
     b0 = build_event(cfg, event, n_bins=n_bins, phase=phase, distance=distance)
     g = b0.ev.metric(b0.theta_inj)
-    b1 = build_event(cfg, event, n_bins=n_bins, phase=oracle.PHASE_EXPLICIT)
-    sig_t = 1.0 / math.sqrt(b1.ev.metric(b1.theta_inj)[9, 9])
+    if own_width:
+        sig_t = 1.0 / math.sqrt(g[9, 9])
+    else:
+        b1 = build_event(cfg, event, n_bins=n_bins, phase=oracle.PHASE_EXPLICIT)
+        sig_t = 1.0 / math.sqrt(b1.ev.metric(b1.theta_inj)[9, 9])
     tinj = b0.theta_inj[9]
     pts = int(math.ceil(2 * half_window / (0.5 * sig_t))) + 1
     tm = {"tc_lo": tinj - half_window, "tc_hi": tinj + half_window, "tm_points": pts}
