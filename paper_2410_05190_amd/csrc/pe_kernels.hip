@@ -174,28 +174,61 @@ __global__ __launch_bounds__(256) void k_seg_sums(const BatchHdr* __restrict__ h
 // reduction each), then block-wide inclusive scans per 256 bins of pw (into
 // pfx), |w| (into pl1), |w|^2 (into pw2) and the whitened power |w|^2 / pw (into
 // ppw).
-__device__ __forceinline__ double block_scan_excl(double v, double* sh, double& tile) {
+// Exclusive scans of NV values per thread over the block at once (one pair of
+// barriers for all of them); tile[i]: the block's total of value i. Each value
+// sees exactly the arithmetic of a scan of its own.
+template <int NV>
+__device__ __forceinline__ void block_scan_excl(const double (&v)[NV], double (*sh)[NV], double (&x)[NV],
+                                                double (&tile)[NV]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double inc = v;
+    double inc[NV];
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double u = __shfl_up(inc, off);
-        if (lane >= off) inc += u;
+    for (int i = 0; i < NV; ++i) inc[i] = v[i];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double u = __shfl_up(inc[i], off);
+            if (lane >= off) inc[i] += u;
+        }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double exc = __shfl_up(inc[i], 1);
+        if (lane == 0) exc = 0.0;
+        x[i] = exc;
+        if (lane == 63) sh[w][i] = inc[i];
     }
-    double exc = __shfl_up(inc, 1);
-    if (lane == 0) exc = 0.0;
-    if (lane == 63) sh[w] = inc;
     __syncthreads();
-    double woff = 0.0;
-    for (int i = 0; i < w; ++i) woff += sh[i];
-    tile = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double woff = 0.0;
+        for (int q = 0; q < w; ++q) woff += sh[q][i];
+        tile[i] = (sh[0][i] + sh[1][i]) + (sh[2][i] + sh[3][i]);
+        x[i] += woff;
+    }
     __syncthreads();
-    return woff + exc;
+}
+
+// Sums of NV values over the block at once (the arithmetic of block_sum4 per value).
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&s)[NV], double (*sh)[NV]) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) s[i] += __shfl_xor(s[i], o);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[threadIdx.x >> 6][i] = s[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s[i] = (sh[0][i] + sh[1][i]) + (sh[2][i] + sh[3][i]);
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ hdr,
                                                   const PrepArg* __restrict__ args) {
     __shared__ double sh[4];
+    __shared__ double sh4[4][4];
     const int ne = hdr->ne;
     const int d = blockIdx.y, b = blockIdx.x;
     for (int e = blockIdx.z; e < ne; e += gridDim.z) {
@@ -214,10 +247,10 @@ __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ h
         const int64_t slice = (int64_t)PE_MAX_DET * kScanSeg;
         const double* sg = A.seg + (int64_t)d * kScanSeg + threadIdx.x;
         const bool before = (int)threadIdx.x < b;
-        double carry = block_sum4(before ? sg[0] : 0.0, sh);
-        double carry1 = block_sum4(before ? sg[2 * slice] : 0.0, sh);
-        double carry2 = block_sum4(before ? sg[3 * slice] : 0.0, sh);
-        double carry3 = block_sum4(before ? sg[slice] : 0.0, sh);
+        double cr[4] = {before ? sg[0] : 0.0, before ? sg[2 * slice] : 0.0, before ? sg[3 * slice] : 0.0,
+                        before ? sg[slice] : 0.0};
+        block_sums<4>(cr, sh4);
+        double carry = cr[0], carry1 = cr[1], carry2 = cr[2], carry3 = cr[3];
         const int64_t k0 = (int64_t)b * seg;
         const int64_t k1 = min(k0 + seg, K);
         for (int64_t base = k0; base < k1; base += 256) {
@@ -230,21 +263,19 @@ __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ h
                 v1 = sqrt(v2);
                 if (v > 0.0) v3 = v2 / v;
             }
-            double t, t1, t2, t3;
-            const double x = block_scan_excl(v, sh, t);
-            const double x1 = block_scan_excl(v1, sh, t1);
-            const double x2 = block_scan_excl(v2, sh, t2);
-            const double x3 = block_scan_excl(v3, sh, t3);
+            const double vv[4] = {v, v1, v2, v3};
+            double xx[4], tt[4];
+            block_scan_excl<4>(vv, sh4, xx, tt);
             if (k < k1) {
-                o[k] = carry + x;
-                o1[k] = carry1 + x1;
-                o2[k] = carry2 + x2;
-                o3[k] = carry3 + x3;
+                o[k] = carry + xx[0];
+                o1[k] = carry1 + xx[1];
+                o2[k] = carry2 + xx[2];
+                o3[k] = carry3 + xx[3];
             }
-            carry += t;
-            carry1 += t1;
-            carry2 += t2;
-            carry3 += t3;
+            carry += tt[0];
+            carry1 += tt[1];
+            carry2 += tt[2];
+            carry3 += tt[3];
         }
         if (b == nseg - 1 && threadIdx.x == 0) {
             o[K] = carry;
