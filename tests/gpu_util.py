@@ -57,3 +57,55 @@ def fp64_tol(b):
     sabs = float((4 * b.df * np.abs(d) * np.abs(h) / S).sum())
     phin = 3.0 / 128.0 * (math.pi * b.theta_inj[0] * oracle.t_sun() * b.f_lo) ** (-5.0 / 3.0)
     return 2 * 16 * np.finfo(np.float64).eps * phin * sabs
+
+
+def fp64_draw_bounds(b, th):
+    """Per-draw bounds on |d Z| (and so on |d ln L|) between the FP64 path and the oracle, for the
+    draws th [D, n]: (worst, model). Each side rounds bin k's phase by at most ~16 u M_k, with M_k
+    the sum of the magnitudes of the phase's terms at f_k (the PN series term by term,
+    2 pi f_k (|tc| + |delay_d|), |phic| + pi/4); a phase error d_k moves the term
+    t_k = 4 df conj(d_k) h_k / S_k by -i t_k d_k.
+      worst = 32 u sum_k |t_k| M_k: every bin's error at its largest and aligned.
+      model = 16 u (|sum_k t_k M_k| + 6 sqrt(sum_k |t_k|^2 M_k^2)): the rounding model of the two
+        routes, a part proportional to M_k across the band (the rounding of the per-draw
+        coefficients, which follows the terms' phases) plus per-bin roundings that are
+        independent from bin to bin, whose sum is a random walk (6 standard deviations of the
+        largest per-bin error); a statistical bound, within ~10x of the measured errors.
+    The band-edge form of fp64_tol bounds every M_k by the Newtonian phase at f_lo and takes the
+    sums at the injection. Out-of-support draws get NaN."""
+    import math
+
+    import oracle
+    K = b.n_bins
+    f = b.f_lo + b.df * np.arange(K)
+    d = b.data.astype(np.complex128)
+    S = b.psd.astype(np.float64)
+    tsun = oracle.t_sun()
+    u = np.finfo(np.float64).eps
+    out = np.full(th.shape[1], np.nan)
+    mod = np.full(th.shape[1], np.nan)
+    for i in range(th.shape[1]):
+        ok, src = b.ev.source(th[:, i])
+        if not ok:
+            continue
+        h = b.ev.waveform(th[:, i])
+        v = np.cbrt(math.pi * src.M * tsun * f)
+        lnv = np.log(v)
+        acc = np.zeros(K)
+        vk = np.ones(K)
+        for j in range(8):
+            acc += np.abs(src.phi[j] + src.phil[j] * lnv) * vk
+            vk *= v
+        mpn = 3.0 / (128.0 * src.eta * v ** 5) * acc + abs(src.phic) + math.pi / 4.0
+        s1 = s2 = 0.0
+        s3 = 0j
+        for q in range(b.n_det):
+            mk = mpn + 2.0 * math.pi * f * (abs(src.tc) + abs(src.dt[q]))
+            tm = 4.0 * b.df * np.conj(d[q]) * h[q] / S[q] * mk
+            a = np.abs(tm)
+            s1 += float(a.sum())
+            s2 += float((a * a).sum())
+            s3 += complex(tm.sum())
+        out[i] = 32.0 * u * s1
+        mod[i] = 16.0 * u * (abs(s3) + 6.0 * math.sqrt(s2))
+    return out, mod
