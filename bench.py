@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--serve-no-graph", action="store_true")
     ap.add_argument("--serve-no-baseline", action="store_true")
+    ap.add_argument("--serve-no-tune", action="store_true",
+                    help="serving leg: skip the server's per-bucket plan autotuner (library's default plan)")
     ap.add_argument("--drift-sample", type=int, default=-1,
                     help="draws of the last step compared with the oracle (FP64-phase drift); -1: 1024 for config 4, "
                          "else 0")
@@ -759,10 +761,33 @@ def serve_bench(args):
 
     srv = binding.Server(int(args.serve_budget_gib * (1 << 30)), precision=binding.PE_PREC_SPLIT, max_active=256,
                          slice_ms=args.serve_slice_ms, use_graph=not args.serve_no_graph)
+    tuned = None
+    if not args.serve_no_tune:
+        # the server's autotuner: one plan per shape bucket from the pool events, 2^14 draws each
+        f64 = dict(dtype=torch.float64, device="cuda")
+        tev, tth = [], []
+        for k, x in pool.items():
+            ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], **x["common"])
+            th0 = torch.from_numpy(x["theta_inj"]).cuda()
+            g = ev.metric(th0)
+            th, lq, lp = ev.draw(th0, g, 77, 1, 1 << 14)
+            tev.append(ev)
+            tth.append(th)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        srv.tune(tev, tth, [1 << 14] * len(tev), reps=1)
+        tuned = {"seconds": time.perf_counter() - ta, "events": len(tev), "draws_per_event": 1 << 14,
+                 "plans": [{"n_det": p[0], "log2_bins": p[1], "items_target": p[2], "min_group_bins": p[3],
+                            "ms_per_batch": p[4]} for p in srv.plans()]}
+        for ev in tev:
+            ev.close()
+        print(f"serving: tuned {len(tuned['plans'])} shape buckets in {tuned['seconds']:.1f} s", file=sys.stderr,
+              flush=True)
     # warm-up (kernel loading, graph capture): two requests, not timed
     for i in range(2):
         x, N, seed = request(i)
         srv.wait(srv.submit(x["desc"], x["data"], x["psd"], x["theta_inj"], N, seed=seed, stream_id=999))
+    busy0 = srv.busy_ms()
     t0 = srv.now()
     tickets = []
     for i in range(n):
@@ -770,7 +795,11 @@ def serve_bench(args):
             time.sleep(min(0.002, max(0.0, tr["t"][i] - (srv.now() - t0))))
         x, N, seed = request(i)
         tickets.append(srv.submit(x["desc"], x["data"], x["psd"], x["theta_inj"], N, seed=seed, stream_id=i))
+        if (i + 1) % 250 == 0:
+            print(f"serving: {i + 1} of {n} requests submitted at {srv.now() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
     res = [srv.wait(t) for t in tickets]
+    busy1 = srv.busy_ms()
     counters = srv.counters()
     srv.close()
     bad = [r.status for r in res if r.status not in (0, 4)]
@@ -782,9 +811,14 @@ def serve_bench(args):
            "latency_ms": percentiles(lat), "evals_per_s": live / t_end, "ess_per_s": ess / t_end,
            "draws": int(sum(int(tr["n_draws"][i]) for i in range(n))), "failed": len(bad),
            "slice_ms": args.serve_slice_ms, "graph": not args.serve_no_graph, "counters": counters,
+           "gpu_busy": {"slices_ms": busy1["slices"] - busy0["slices"],
+                        "admission_ms": busy1["admission"] - busy0["admission"],
+                        "fraction": (busy1["slices"] - busy0["slices"] + busy1["admission"] - busy0["admission"])
+                        / (1e3 * t_end)},
+           "tuned": tuned,
            "kind": "continuous batching, split precision, admission by HBM budget"}
-    print(f"serving: p50 {out['latency_ms']['p50']:.1f} ms p99 {out['latency_ms']['p99']:.1f} ms", file=sys.stderr,
-          flush=True)
+    print(f"serving: p50 {out['latency_ms']['p50']:.1f} ms p99 {out['latency_ms']['p99']:.1f} ms, GPU busy "
+          f"{out['gpu_busy']['fraction']:.3f}", file=sys.stderr, flush=True)
 
     if not args.serve_no_baseline:
         # serial plain-FP64 baseline on the same trace

@@ -576,6 +576,30 @@ double pe_server_now(pe_server_t srv);
 /* Counters: {requests completed, slices run, hot-loop items run, graph
  * replays, peak slab bytes in use, admissions waiting for memory}. */
 pe_status_t pe_server_counters(pe_server_t srv, int64_t out[6]);
+/* Device time so far, in milliseconds, from HIP events on the server's stream:
+ * out[0] the hot-loop slices (queue setup, hot loop, ln L, weights), out[1]
+ * the admission stages (prep, metric, draws, log-likelihood prologue). Their
+ * sum over a window is the server's GPU busy time. */
+pe_status_t pe_server_busy(pe_server_t srv, double out[2]);
+/* The tile-shape autotuner of the serving loop (the benchmark description asks
+ * for tile shapes picked by the project's own autotuner). Groups the n given
+ * events into shape buckets (detector count, number of bins rounded up to a
+ * power of two), runs pe_autotune_plan on each bucket's events and draws
+ * (theta_dev[i]: device [D][n_draws[i]]) on the server's stream in the
+ * server's precision, and keeps the fastest plan per bucket: later requests of
+ * a tuned bucket are planned with it (over the config's items_target and
+ * min_group_bins); other buckets keep the config's or the library's setting.
+ * A request's results then equal the single-event calls run under pe_set_plan
+ * with its bucket's plan. Call on an idle server (PE_ERR_ARG otherwise: the
+ * timings would include other work); the events are the caller's own
+ * (pe_event_create) and are left unchanged apart from their workspace.
+ * Errors: PE_ERR_ARG, PE_ERR_HIP, PE_ERR_OOM. */
+pe_status_t pe_server_tune(pe_server_t srv, int32_t n, const pe_event_t *events, const double *const *theta_dev,
+                           const int64_t *n_draws, int32_t reps);
+/* The tuned plans: *count buckets; the first min(max, *count) as out[4 i ..]
+ * = {n_det, log2 of the bucket's bin bound, items_target, min_group_bins} and,
+ * if ms is not NULL, ms[i] = the tuning batch's milliseconds with that plan. */
+pe_status_t pe_server_plans(pe_server_t srv, int32_t max, int32_t *out, double *ms, int32_t *count);
 /* Finish every submitted request, stop the worker, free the slab. */
 pe_status_t pe_server_destroy(pe_server_t srv);
 

@@ -39,7 +39,7 @@ EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "p
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
            "pe_autotune_plan", "pe_set_split_guard", "pe_get_split_guard", "pe_loglike_counts", "pe_last_error",
            "pe_server_create", "pe_server_submit", "pe_server_wait", "pe_server_now", "pe_server_counters",
-           "pe_server_destroy"]
+           "pe_server_busy", "pe_server_tune", "pe_server_plans", "pe_server_destroy"]
 
 
 class PeError(RuntimeError):
@@ -171,6 +171,9 @@ def load(path=LIB_PATH):
         "pe_server_wait": (i32, [vp, i64, ctypes.c_double, ctypes.POINTER(Result)]),
         "pe_server_now": (ctypes.c_double, [vp]),
         "pe_server_counters": (i32, [vp, ctypes.POINTER(i64)]),
+        "pe_server_busy": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "pe_server_tune": (i32, [vp, i32, vp, vp, vp, i32]),
+        "pe_server_plans": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]),
         "pe_server_destroy": (i32, [vp]),
         "pe_last_error": (ctypes.c_char_p, []),
     }
@@ -718,6 +721,31 @@ class Server:
         _check(load().pe_server_counters(self.handle, out))
         keys = ("completed", "slices", "items", "graph_replays", "peak_slab_bytes", "admission_waits")
         return dict(zip(keys, list(out)))
+
+    def busy_ms(self):
+        """Device milliseconds so far: {"slices", "admission"} (pe_server_busy)."""
+        out = (ctypes.c_double * 2)()
+        _check(load().pe_server_busy(self.handle, out))
+        return {"slices": out[0], "admission": out[1]}
+
+    def tune(self, events, thetas, ns, reps=2):
+        """Per-bucket plans from these events and device draws (pe_server_tune)."""
+        import torch
+        ne = len(events)
+        ev_a = (ctypes.c_void_p * ne)(*[e.handle if isinstance(e, Event) else e for e in events])
+        th_a = (ctypes.c_void_p * ne)(*[_ptr(t, torch.float64, "theta") for t in thetas])
+        n_a = (ctypes.c_int64 * ne)(*[int(n) for n in ns])
+        _check(load().pe_server_tune(self.handle, ne, ev_a, th_a, n_a, int(reps)))
+
+    def plans(self):
+        """[(n_det, log2 of the bin bound, items_target, min_group_bins, ms)] (pe_server_plans)."""
+        c = ctypes.c_int32()
+        _check(load().pe_server_plans(self.handle, 0, None, None, ctypes.byref(c)))
+        n = max(c.value, 1)
+        out = (ctypes.c_int32 * (4 * n))()
+        ms = (ctypes.c_double * n)()
+        _check(load().pe_server_plans(self.handle, n, out, ms, ctypes.byref(c)))
+        return [(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3], ms[i]) for i in range(c.value)]
 
     def close(self):
         if self.handle is not None:

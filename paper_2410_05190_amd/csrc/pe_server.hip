@@ -126,6 +126,24 @@ size_t request_buffers(Req* q, char* base) {
     return c.size();
 }
 
+// Shape bucket of a request for the plan table: detector count and the
+// number of bins rounded up to a power of two.
+struct Bucket {
+    int n_det, log2k;
+    bool operator<(const Bucket& o) const { return n_det != o.n_det ? n_det < o.n_det : log2k < o.log2k; }
+};
+
+Bucket bucket_of(const pe_event_desc_t& d) {
+    int l = 0;
+    while (l < 40 && ((int64_t)1 << l) < d.n_bins) ++l;
+    return Bucket{d.n_det, l};
+}
+
+struct BucketPlan {
+    int32_t items_target, min_group_bins;
+    double ms;  // the tuning batch's time per log-likelihood batch
+};
+
 double now_s() {
     using namespace std::chrono;
     return duration_cast<duration<double>>(steady_clock::now().time_since_epoch()).count();
@@ -145,7 +163,9 @@ struct pe_server_s {
     int cap_ne = 0;
     int64_t cap_wblocks = 0, cap_fblocks = 0, cap_dblocks = 0;
     hipGraphExec_t graph = nullptr;
-    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
+    std::map<Bucket, BucketPlan> plans;  // tuned plans per shape bucket (pe_server_tune)
+    double busy_slice_ms = 0.0, busy_admit_ms = 0.0;  // device time of the slices and admission stages
     double* h_stage = nullptr;  // pinned: stats, plans, status words
     double rate = 0.0;          // lane-operations per ms of the hot loop (running estimate)
     double t0 = 0.0;
@@ -250,15 +270,25 @@ void pe_server_s::admit() {
         EvDev l = loglike_arg(q->ev, q->d_theta, q->r.n_draws, q->d_loglike, nullptr);
         if (cfg.items_target > 0) l.items_target = cfg.items_target;
         if (cfg.min_group_bins > 0) l.min_group_bins = cfg.min_group_bins;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            const auto it = plans.find(bucket_of(d));
+            if (it != plans.end()) {
+                l.items_target = it->second.items_target;
+                l.min_group_bins = it->second.min_group_bins;
+            }
+        }
         l.flags = kLlPrologue;
         l.tile_lo = l.tile_hi = 0;
         if (cfg.max_groups > 0 && l.max_groups > cfg.max_groups) l.max_groups = cfg.max_groups;
         vl.push_back(l);
     }
+    if (s == PE_OK && hipEventRecord(ev_c, st) != hipSuccess) s = PE_ERR_HIP;
     if (s == PE_OK) s = run_prep(vp, st);
     if (s == PE_OK) s = run_metric(vm, st);
     if (s == PE_OK) s = run_draw(vd, st);
     if (s == PE_OK) s = run_loglike(vl, cfg.precision, st);
+    if (s == PE_OK && hipEventRecord(ev_d, st) != hipSuccess) s = PE_ERR_HIP;
     // plans and status words to the pinned stage (8 doubles per request)
     for (size_t i = 0; i < fresh.size() && s == PE_OK; ++i) {
         if (hipMemcpyAsync(h_stage + 8 * i, fresh[i]->ev->plan, sizeof(EvPlan), hipMemcpyDeviceToHost, st) !=
@@ -268,6 +298,8 @@ void pe_server_s::admit() {
             s = PE_ERR_HIP;
     }
     if (s == PE_OK && hipStreamSynchronize(st) != hipSuccess) s = PE_ERR_HIP;
+    float ams = 0.0f;
+    if (s == PE_OK && hipEventElapsedTime(&ams, ev_c, ev_d) == hipSuccess) busy_admit_ms += ams;
     if (s != PE_OK) {
         fatal = s;
         for (Req* q : fresh) finish(q, s);
@@ -397,8 +429,10 @@ pe_status_t pe_server_s::slice() {
         sel[e]->tiles_done += take[e];
     }
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, ev_a, ev_b) == hipSuccess && ms > 0.5f && done_ops > 0.0)
-        rate = 0.8 * rate + 0.2 * (done_ops / ms);
+    if (hipEventElapsedTime(&ms, ev_a, ev_b) == hipSuccess) {
+        busy_slice_ms += ms;
+        if (ms > 0.5f && done_ops > 0.0) rate = 0.8 * rate + 0.2 * (done_ops / ms);
+    }
     ++n_slices;
     n_items += items;
     for (int i = 0; i < nw; ++i) {
@@ -471,6 +505,8 @@ pe_status_t pe_server_create(const pe_server_config_t* cfg, pe_server_t* out) {
         if (s->h_stage) (void)hipHostFree(s->h_stage);
         if (s->ev_a) (void)hipEventDestroy(s->ev_a);
         if (s->ev_b) (void)hipEventDestroy(s->ev_b);
+        if (s->ev_c) (void)hipEventDestroy(s->ev_c);
+        if (s->ev_d) (void)hipEventDestroy(s->ev_d);
         release_area(s->a_ll);
         release_area(s->a_w);
         s->slab.release();
@@ -480,6 +516,7 @@ pe_status_t pe_server_create(const pe_server_config_t* cfg, pe_server_t* out) {
     };
     if (hipGetDevice(&s->device) != hipSuccess || hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&s->ev_a) != hipSuccess || hipEventCreate(&s->ev_b) != hipSuccess ||
+        hipEventCreate(&s->ev_c) != hipSuccess || hipEventCreate(&s->ev_d) != hipSuccess ||
         hipHostMalloc((void**)&s->h_stage, sizeof(double) * 8 * (size_t)cfg->max_active, hipHostMallocDefault) !=
             hipSuccess)
         return bail(fail(PE_ERR_HIP, "server stream, events or pinned stage"));
@@ -563,6 +600,65 @@ pe_status_t pe_server_counters(pe_server_t srv, int64_t out[6]) {
     return PE_OK;
 }
 
+pe_status_t pe_server_busy(pe_server_t srv, double out[2]) {
+    if (!srv || !out) return fail(PE_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    out[0] = srv->busy_slice_ms;
+    out[1] = srv->busy_admit_ms;
+    return PE_OK;
+}
+
+pe_status_t pe_server_tune(pe_server_t srv, int32_t n, const pe_event_t* events, const double* const* theta_dev,
+                           const int64_t* n_draws, int32_t reps) {
+    if (!srv || !events || !theta_dev || !n_draws) return fail(PE_ERR_ARG, "NULL argument");
+    if (n < 1 || n > 4096) return fail(PE_ERR_ARG, "n must be in 1..4096");
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (!srv->pending.empty() || !srv->active.empty()) return fail(PE_ERR_ARG, "tune an idle server");
+    }
+    std::map<Bucket, std::vector<int>> groups;
+    for (int i = 0; i < n; ++i) {
+        if (!events[i] || !theta_dev[i]) return fail(PE_ERR_ARG, "NULL event or draws");
+        groups[bucket_of(events[i]->desc)].push_back(i);
+    }
+    for (const auto& kv : groups) {
+        std::vector<pe_event_t> ev;
+        std::vector<const double*> th;
+        std::vector<int64_t> nn;
+        for (int i : kv.second) {
+            ev.push_back(events[i]);
+            th.push_back(theta_dev[i]);
+            nn.push_back(n_draws[i]);
+        }
+        int32_t it = 0, mb = 0;
+        double ms = 0.0;
+        const pe_status_t s = pe_autotune_plan((int32_t)ev.size(), ev.data(), th.data(), nn.data(),
+                                               srv->cfg.precision, reps, &it, &mb, &ms, srv->st);
+        if (s != PE_OK) return s;
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->plans[kv.first] = BucketPlan{it, mb, ms};
+    }
+    return PE_OK;
+}
+
+pe_status_t pe_server_plans(pe_server_t srv, int32_t max, int32_t* out, double* ms, int32_t* count) {
+    if (!srv || !count || (max > 0 && !out)) return fail(PE_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    int32_t c = 0;
+    for (const auto& kv : srv->plans) {
+        if (c < max) {
+            out[4 * c] = kv.first.n_det;
+            out[4 * c + 1] = kv.first.log2k;
+            out[4 * c + 2] = kv.second.items_target;
+            out[4 * c + 3] = kv.second.min_group_bins;
+            if (ms) ms[c] = kv.second.ms;
+        }
+        ++c;
+    }
+    *count = c;
+    return PE_OK;
+}
+
 pe_status_t pe_server_destroy(pe_server_t srv) {
     if (!srv) return fail(PE_ERR_ARG, "server is NULL");
     {
@@ -577,6 +673,8 @@ pe_status_t pe_server_destroy(pe_server_t srv) {
     (void)hipHostFree(srv->h_stage);
     (void)hipEventDestroy(srv->ev_a);
     (void)hipEventDestroy(srv->ev_b);
+    (void)hipEventDestroy(srv->ev_c);
+    (void)hipEventDestroy(srv->ev_d);
     release_area(srv->a_ll);
     release_area(srv->a_w);
     srv->slab.release();

@@ -115,6 +115,10 @@ def test_server_structs_and_host_checks():
     bad = binding.ServerConfig(1 << 30, 1, 16, 8.0, 1, 0, 100, 0)  # plan out of range
     assert L.pe_server_create(ctypes.byref(bad), ctypes.byref(h)) == 1
     assert L.pe_server_destroy(None) == 1
+    assert L.pe_server_tune(None, 1, None, None, None, 1) == 1
+    assert L.pe_server_busy(None, None) == 1
+    c = ctypes.c_int32()
+    assert L.pe_server_plans(None, 0, None, None, ctypes.byref(c)) == 1
 
 
 def test_event_desc_layout_matches_header(tmp_path):

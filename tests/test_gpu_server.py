@@ -1,14 +1,17 @@
 """GPU: the serving loop (pe_server_*) through the C ABI. Requests of different shapes arrive while
 others are on the GPU, share hot-loop slices (continuous batching, graph replay or direct
 launches) and must return exactly what the single-event calls return for the same inputs: every
-ln L, weight and ESS bit for bit, alone or in the mix."""
+ln L, weight and ESS bit for bit, alone or in the mix. Sampled served draws are also checked
+against the oracle (split: 1e-3; FP64: the per-draw rounding model of gpu_util.fp64_draw_bounds).
+The per-bucket plans of pe_server_tune: served results equal the single-event calls under the
+bucket's plan."""
 import time
 
 import numpy as np
 import pytest
 
 from events import build_event
-from gpu_util import desc_kwargs, dev, host, note, torch_cuda, upload_event
+from gpu_util import desc_kwargs, dev, fp64_draw_bounds, host, note, torch_cuda, upload_event
 from paper_2410_05190_amd import binding
 
 pytestmark = pytest.mark.gpu
@@ -79,7 +82,27 @@ def _run(prec, use_graph, slice_ms, budget=1 << 32, max_active=64):
         assert np.array_equal(ll, ll1)
         assert np.array_equal(w, w1)
         assert np.array_equal(np.array(res.stats[:]), st1)
+        _oracle_check(b, th, ll, prec, i)
     return results, counters
+
+
+def _oracle_check(b, th, ll, prec, i, n=6):
+    """A few served draws (the live ones, spread over the request) against the oracle."""
+    live = np.flatnonzero(np.isfinite(ll))
+    if live.size == 0:
+        return
+    pick = live[np.linspace(0, live.size - 1, min(n, live.size)).round().astype(int)]
+    pick = np.unique(pick)
+    ll_o = b.ev.loglike(np.ascontiguousarray(th[:, pick]))
+    d = np.abs(ll[pick] - ll_o)
+    if prec == binding.PE_PREC_SPLIT:
+        tol = np.full(pick.size, 1e-3)
+    else:
+        tol = fp64_draw_bounds(b, np.ascontiguousarray(th[:, pick]))[1]
+        if b.distance:  # the two distance quadratures, each ~1e-13 relative
+            tol = tol + 1e-9 * np.maximum(1.0, np.abs(ll_o))
+    note(f"  request {i}: {pick.size} served draws against the oracle, max |dlnL| {d.max():.2e}")
+    assert np.all(d <= tol)
 
 
 def test_server_mixed_requests_equal_single_event_calls_graph():
@@ -113,3 +136,50 @@ def test_server_admission_by_memory_budget():
     assert rb.status == binding.PE_ERR_BUDGET
     assert c["admission_waits"] > 0 and c["peak_slab_bytes"] <= 80 << 20
     assert all(res[i].t_done <= res[i + 1].t_done for i in range(3))
+
+
+def test_server_tuned_plans_per_bucket():
+    """pe_server_tune on two shape buckets (config-1 shape, 3 detectors, 2^16 bins; config 2, 2
+    detectors, 2^13 bins): one plan per bucket, and requests of those shapes served with them equal
+    the single-event calls run under pe_set_plan with their bucket's plan, bit for bit."""
+    torch = torch_cuda()
+    shapes = [(1, 8, 3, 60000, 6000), (2, 9, 2, None, 20000)]
+    built, evs, ths, ns = [], [], [], []
+    for cfg, e, nd, K, n in shapes:
+        b = build_event(cfg, e, n_det=nd, n_bins=K)
+        ev, d_, p_ = upload_event(b)
+        g = ev.metric(dev(b.theta_inj))
+        th, lq, lp = ev.draw(dev(b.theta_inj), g, 7, 1, n)
+        built.append((b, n, ev, d_, p_))
+        evs.append(ev)
+        ths.append(th)
+        ns.append(n)
+    srv = binding.Server(1 << 32, max_active=16, slice_ms=0.05)
+    srv.tune(evs, ths, ns, reps=1)
+    plans = srv.plans()
+    note(f"tuned plans (n_det, log2 K, items_target, min_group_bins, ms): {plans}")
+    assert sorted((p[0], p[1]) for p in plans) == [(2, 13), (3, 16)]
+    tickets, outs = [], []
+    for i, (b, n, ev, d_, p_) in enumerate(built):
+        desc = binding.make_desc(b.n_det, b.n_bins, data_dtype=binding.PE_C64, psd_dtype=binding.PE_F32,
+                                 **desc_kwargs(b))
+        ll = np.full(n, np.nan)
+        w = np.full(n, np.nan)
+        tickets.append(srv.submit(desc, b.data, b.psd, b.theta_inj, n, seed=50 + i, stream_id=2, loglike_out=ll,
+                                  w_out=w))
+        outs.append((ll, w))
+    results = [srv.wait(t, timeout=120.0) for t in tickets]
+    srv.close()
+    keep = binding.pe_get_plan()
+    try:
+        for i, ((b, n, ev, d_, p_), res, (ll, w)) in enumerate(zip(built, results, outs)):
+            assert res.status == 0
+            plan = [p for p in plans if p[0] == b.n_det][0]
+            binding.pe_set_plan(plan[2], plan[3])
+            th1, ll1, w1, st1 = _single(b, ev, b.theta_inj, n, 50 + i, 2, binding.PE_PREC_SPLIT)
+            assert np.array_equal(ll, ll1)
+            assert np.array_equal(w, w1)
+    finally:
+        binding.pe_set_plan(*keep)
+    for x in built:
+        x[2].close()
