@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--refine-rounds", type=int, default=3,
                     help="rounds of proposal refinement before the refined-proposal leg (0 skips the leg)")
     ap.add_argument("--refine-draws", type=int, default=16384, help="draws per refinement round")
-    ap.add_argument("--relbin-eps", type=float, default=0.03,
+    ap.add_argument("--relbin-eps", type=float, default=0.02,
                     help="relative-binning leg: envelope step between bin edges (0 skips the leg)")
     ap.add_argument("--tile-radius", type=float, default=6.0, help="tile-mixture leg: slice radius (whitened)")
     ap.add_argument("--tile-spacing", type=float, default=1.0, help="tile-mixture leg: template spacing (whitened)")

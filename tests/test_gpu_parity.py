@@ -635,7 +635,8 @@ def test_autotuned_plan_is_reproducible_and_within_tolerance():
 
 
 def test_long_signal_config4_full_size_sampled():
-    """Config 4 at full size (3 detectors, K = 2 086 912, 262 144 draws, SNR up to 100): the FP64
+    """Config 4 at full size (3 detectors, K = 2 086 912, 262 144 draws; event 0, SNR 43; the SNR-95
+    event of the configuration's upper range is in test_gpu_guard.py): the FP64
     phase over ~1e5 rad and the split path's compensated FP32 sums against the oracle on sampled
     draws; the FP64 path within its derived bound."""
     torch_cuda()
