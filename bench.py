@@ -91,7 +91,7 @@ def parse():
                     help="skip the distance-marginalised leg (11-D configurations)")
     ap.add_argument("--time-leg", type=int, default=1,
                     help="1: the leg with time, phase and distance marginalised (11-D configurations); 0 skips it")
-    ap.add_argument("--time-leg-draws", type=int, default=1024,
+    ap.add_argument("--time-leg-draws", type=int, default=65536,
                     help="time-marginalised leg: proposal draws per step (each evaluated at every tc node)")
     ap.add_argument("--no-batch-leg", action="store_true",
                     help="skip the config-2 leg (64 BBH events per step through pe_batch_run) of the default run")

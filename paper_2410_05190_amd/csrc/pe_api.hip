@@ -68,9 +68,32 @@ pe_status_t validate_desc(const pe_event_desc_t* d) {
     return PE_OK;
 }
 
+// Whether a time-marginalised event's batch takes the block-moment path: split
+// precision and a window that the moments cover (ec.tm_P > 0).
+bool tm_moments(const pe_event_s* ev, int precision) {
+    return ev->desc.time_marg && precision == PE_PREC_SPLIT && ev->ec.tm_P > 0;
+}
+
 // Draws the workspace must hold for a batch of n: a time-marginalised event
-// evaluates every draw at each of its tc nodes.
-int64_t ws_draws(const pe_event_s* ev, int64_t n) { return ev->desc.time_marg ? n * ev->desc.tm_points : n; }
+// off the moment path evaluates every draw at each of its tc nodes.
+int64_t ws_draws(const pe_event_s* ev, int64_t n, int precision) {
+    return (ev->desc.time_marg && !tm_moments(ev, precision)) ? n * ev->desc.tm_points : n;
+}
+
+// The block moments of a batch of n draws (own allocation, grown on demand).
+pe_status_t ensure_moments(pe_event_s* ev, int64_t n) {
+    const int64_t cols = std::max<int64_t>(npad_for(n), kTile);
+    if (cols <= ev->tm_mom_cols && ev->tm_mem) return PE_OK;
+    const int64_t blocks = ev->desc.n_bins / ev->ec.tm_fine + 2;
+    PE_HIP(hipDeviceSynchronize());
+    dfree_bytes(ev->tm_mem);
+    ev->tm_mem = nullptr;
+    ev->tm_mom_cols = 0;
+    pe_status_t s = dalloc_bytes(&ev->tm_mem, sizeof(double2) * (size_t)blocks * ev->ec.tm_P * (size_t)cols);
+    if (s != PE_OK) return s;
+    ev->tm_mom_cols = cols;
+    return PE_OK;
+}
 
 // Detector tensor D = (x x^T - y y^T)/2 from latitude, longitude and the
 // x-arm azimuth (north toward east); y arm 90 degrees east of x.
@@ -91,6 +114,23 @@ void build_const(const pe_event_desc_t& d, EvConst& ec) {
     ec.dist = (d.distance == PE_DIST_MARG) ? 1 : 0;
     ec.tm = d.time_marg ? 1 : 0;
     ec.tm_points = d.time_marg ? d.tm_points : 0;
+    if (d.time_marg) {
+        // block width of the moment path: the widest multiple of kBlk bins with
+        // pi (width) |u| <= kTmAlpha over the window, with 8 moments, else 16
+        const double U = 0.5 * (d.tc_hi - d.tc_lo);
+        const double alpha[2] = {kTmAlpha8, kTmAlpha16};
+        const int P[2] = {8, 16};
+        for (int i = 0; i < 2 && ec.tm_P == 0; ++i) {
+            const double bins = alpha[i] / (kPi * d.df * U);
+            const int64_t f = bins >= (double)(1 << 24) ? (1 << 24) : ((int64_t)bins / kBlk) * kBlk;
+            if (f >= kBlk) {
+                ec.tm_P = P[i];
+                ec.tm_fine = (int32_t)f;
+            }
+        }
+        ec.tm_tmid = 0.5 * (d.tc_lo + d.tc_hi);
+        ec.tm_a = kPi * ec.tm_fine * d.df;
+    }
     ec.tc_lo = d.tc_lo;
     ec.tc_hi = d.tc_hi;
     for (int i = 0; i < d.n_det; ++i) {
@@ -239,6 +279,7 @@ void free_event(pe_event_s* ev) {
         dfree_bytes(ev->ws_mem);
     }
     dfree_bytes(ev->rb_mem);
+    dfree_bytes(ev->tm_mem);
     delete ev;
 }
 
@@ -596,23 +637,70 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     return PE_OK;
 }
 
-// The log-likelihood batch entry of an event's n draws; a time-marginalised
-// event evaluates its node draws (expanded into the workspace by tm_expand)
-// into the workspace and tm_reduce sums them into loglike.
-EvDev loglike_entry(pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux,
-                    std::vector<TmJob>& tm) {
-    if (!ev->desc.time_marg) return loglike_arg(ev, theta, n, loglike, aux);
-    tm.push_back(TmJob{ev, theta, n, loglike});
-    return loglike_arg(ev, ev->tm_theta, n * ev->desc.tm_points, ev->tm_ll, nullptr);
-}
-
-pe_status_t tm_expand(const std::vector<TmJob>& tm, hipStream_t st) {
-    for (const TmJob& j : tm) PE_HIP(launch_tm_expand(j.theta, j.n, j.ev->ec, j.ev->tm_theta, st));
+// A moment-path batch (events of one moment count P): prologue, the hot loop
+// writing block moments, and the tc nodes from the moments.
+pe_status_t run_loglike_moments(const std::vector<EvDev>& v, int P, hipStream_t st) {
+    const int ne = (int)v.size();
+    if (ne == 0) return PE_OK;
+    std::vector<int64_t> poff(ne + 1, 0), foff(ne + 1, 0);
+    for (int e = 0; e < ne; ++e) {
+        poff[e + 1] = poff[e] + blocks256(v[e].n);
+        foff[e + 1] = foff[e] + blocks256(v[e].n);
+    }
+    Area& A = area_for(st, kAreaLoglike);
+    std::lock_guard<std::mutex> lk(A.mu);
+    BatchPtrs b;
+    pe_status_t s = upload_area(A, ne, poff[ne], foff[ne], v.data(), sizeof(EvDev) * ne, poff, &foff,
+                                loglike_scratch_bytes(ne), st, b);
+    if (s != PE_OK) return s;
+    PE_HIP(launch_loglike_moments(b, ne, poff[ne], foff[ne], P, st));
     return PE_OK;
 }
 
-pe_status_t tm_reduce(const std::vector<TmJob>& tm, hipStream_t st) {
-    for (const TmJob& j : tm) PE_HIP(launch_tm_reduce(j.ev->tm_ll, j.n, j.ev->ec, j.loglike, st));
+// The log-likelihood batch entry of an event's n draws (its workspace grown
+// as needed). A time-marginalised event on the block-moment path evaluates its
+// draws once, at the window's centre, in the moment batch; off it, every tc
+// node is a draw (expanded into the workspace by run_jobs), evaluated in the
+// main batch and summed by the node reduction.
+pe_status_t loglike_entry(pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux,
+                          int precision, LlJobs& jobs) {
+    pe_status_t s = ensure_ws(ev, ws_draws(ev, n, precision));
+    if (s != PE_OK) return s;
+    if (!ev->desc.time_marg) {
+        jobs.main.push_back(loglike_arg(ev, theta, n, loglike, aux));
+        return PE_OK;
+    }
+    if (tm_moments(ev, precision)) {
+        if ((s = ensure_moments(ev, n)) != PE_OK) return s;
+        jobs.tm.push_back(TmJob{ev, theta, n, loglike, true});
+        EvDev d = loglike_arg(ev, ev->tm_theta, n, loglike, nullptr);
+        d.flags |= kLlMoments;
+        d.tm_mom = (double2*)ev->tm_mem;
+        jobs.mom.push_back(d);
+        return PE_OK;
+    }
+    jobs.tm.push_back(TmJob{ev, theta, n, loglike, false});
+    jobs.main.push_back(loglike_arg(ev, ev->tm_theta, n * ev->desc.tm_points, ev->tm_ll, nullptr));
+    return PE_OK;
+}
+
+pe_status_t run_jobs(const LlJobs& jobs, int precision, hipStream_t st) {
+    for (const TmJob& j : jobs.tm) {
+        if (j.moments)
+            PE_HIP(launch_tm_centre(j.theta, j.n, j.ev->ec, j.ev->tm_theta, st));
+        else
+            PE_HIP(launch_tm_expand(j.theta, j.n, j.ev->ec, j.ev->tm_theta, st));
+    }
+    pe_status_t s = run_loglike(jobs.main, precision, st);
+    for (int P : {8, 16}) {
+        std::vector<EvDev> vp;
+        for (const EvDev& d : jobs.mom)
+            if (d.ec.tm_P == P) vp.push_back(d);
+        if (s == PE_OK) s = run_loglike_moments(vp, P, st);
+    }
+    if (s != PE_OK) return s;
+    for (const TmJob& j : jobs.tm)
+        if (!j.moments) PE_HIP(launch_tm_reduce(j.ev->tm_ll, j.n, j.ev->ec, j.loglike, st));
     return PE_OK;
 }
 
@@ -804,7 +892,9 @@ pe_status_t pe_event_status(pe_event_t ev, void* stream) {
 pe_status_t pe_event_reserve(pe_event_t ev, int64_t max_draws) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
     if (max_draws < 0 || max_draws > ((int64_t)1 << 30)) return fail(PE_ERR_ARG, "max_draws must be in 0..2^30");
-    return ensure_ws(ev, ws_draws(ev, max_draws));
+    pe_status_t s = ensure_ws(ev, ws_draws(ev, max_draws, PE_PREC_SPLIT));
+    if (s == PE_OK && tm_moments(ev, PE_PREC_SPLIT) && max_draws > 0) s = ensure_moments(ev, max_draws);
+    return s;
 }
 
 pe_status_t pe_event_destroy(pe_event_t ev) {
@@ -853,13 +943,9 @@ pe_status_t pe_loglike_batch(pe_event_t ev, const double* theta_dev, int64_t n, 
     if (n == 0) return PE_OK;
     if (!theta_dev || !loglike_dev) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
     if (ev->desc.time_marg && aux_dev) return fail(PE_ERR_ARG, "aux is not available for a time-marginalised event");
-    if ((s = ensure_ws(ev, ws_draws(ev, n))) != PE_OK) return s;
-    hipStream_t st = as_stream(stream);
-    std::vector<TmJob> tm;
-    std::vector<EvDev> v(1, loglike_entry(ev, theta_dev, n, loglike_dev, aux_dev, tm));
-    if ((s = tm_expand(tm, st)) != PE_OK) return s;
-    if ((s = run_loglike(v, precision, st)) != PE_OK) return s;
-    return tm_reduce(tm, st);
+    LlJobs jobs;
+    if ((s = loglike_entry(ev, theta_dev, n, loglike_dev, aux_dev, precision, jobs)) != PE_OK) return s;
+    return run_jobs(jobs, precision, as_stream(stream));
 }
 
 pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t* events, const double* const* theta_dev,
@@ -869,8 +955,7 @@ pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t* events, const d
         return fail(PE_ERR_ARG, "bad batch arrays (n_events must be in 0..65535)");
     pe_status_t s = check_precision(precision);
     if (s != PE_OK) return s;
-    std::vector<EvDev> v;
-    std::vector<TmJob> tm;
+    LlJobs jobs;
     for (int e = 0; e < n_events; ++e) {
         pe_event_s* ev = events[e];
         if (!ev) return fail(PE_ERR_ARG, "event is NULL");
@@ -881,13 +966,11 @@ pe_status_t pe_loglike_multi(int32_t n_events, const pe_event_t* events, const d
         if (!theta_dev[e] || !loglike_dev[e]) return fail(PE_ERR_ARG, "theta and loglike must be device pointers");
         if (ev->desc.time_marg && aux_dev && aux_dev[e])
             return fail(PE_ERR_ARG, "aux is not available for a time-marginalised event");
-        if ((s = ensure_ws(ev, ws_draws(ev, n[e]))) != PE_OK) return s;
-        v.push_back(loglike_entry(ev, theta_dev[e], n[e], loglike_dev[e], aux_dev ? aux_dev[e] : nullptr, tm));
+        if ((s = loglike_entry(ev, theta_dev[e], n[e], loglike_dev[e], aux_dev ? aux_dev[e] : nullptr, precision,
+                               jobs)) != PE_OK)
+            return s;
     }
-    hipStream_t st = as_stream(stream);
-    if ((s = tm_expand(tm, st)) != PE_OK) return s;
-    if ((s = run_loglike(v, precision, st)) != PE_OK) return s;
-    return tm_reduce(tm, st);
+    return run_jobs(jobs, precision, as_stream(stream));
 }
 
 pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t* items, int32_t stages, int32_t precision,
@@ -900,9 +983,8 @@ pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t* items, int32_t 
     std::vector<PrepArg> vp;
     std::vector<MetricArg> vm;
     std::vector<DrawArg> vd;
-    std::vector<EvDev> vl;
+    LlJobs jobs;
     std::vector<WeightArg> vw;
-    std::vector<TmJob> tm;
     for (int e = 0; e < n_items; ++e) {
         const pe_batch_item_t& it = items[e];
         pe_event_s* ev = it.ev;
@@ -929,8 +1011,7 @@ pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t* items, int32_t 
                 return fail(PE_ERR_ARG, "item " + std::to_string(e) + ": theta and loglike needed");
             if (ev->desc.time_marg && it.aux)
                 return fail(PE_ERR_ARG, "item " + std::to_string(e) + ": no aux for a time-marginalised event");
-            if ((s = ensure_ws(ev, ws_draws(ev, it.n))) != PE_OK) return s;
-            vl.push_back(loglike_entry(ev, it.theta, it.n, it.loglike, it.aux, tm));
+            if ((s = loglike_entry(ev, it.theta, it.n, it.loglike, it.aux, precision, jobs)) != PE_OK) return s;
         }
         if (stages & PE_STAGE_WEIGHTS) {
             if (!it.stats || (it.n > 0 && (!it.loglike || !it.logprior || !it.logq)))
@@ -943,9 +1024,7 @@ pe_status_t pe_batch_run(int32_t n_items, const pe_batch_item_t* items, int32_t 
     if ((s = run_prep(vp, st)) != PE_OK) return s;
     if ((s = run_metric(vm, st)) != PE_OK) return s;
     if ((s = run_draw(vd, st)) != PE_OK) return s;
-    if ((s = tm_expand(tm, st)) != PE_OK) return s;
-    if ((s = run_loglike(vl, precision, st)) != PE_OK) return s;
-    if ((s = tm_reduce(tm, st)) != PE_OK) return s;
+    if ((s = run_jobs(jobs, precision, st)) != PE_OK) return s;
     return run_weights(vw, st);
 }
 

@@ -107,12 +107,21 @@ struct TmJob {
     const double* theta;
     int64_t n;
     double* loglike;
+    bool moments;  // block-moment path (else every tc node evaluated as a draw)
 };
-EvDev loglike_entry(pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux,
-                    std::vector<TmJob>& tm);
-pe_status_t tm_expand(const std::vector<TmJob>& tm, hipStream_t st);
-pe_status_t tm_reduce(const std::vector<TmJob>& tm, hipStream_t st);
-int64_t ws_draws(const pe_event_s* ev, int64_t n);
+// The log-likelihood batches of one call: the plain events (and time-marginalised
+// events on the node path, as their node draws) in one batch, the events on
+// the block-moment path in another.
+struct LlJobs {
+    std::vector<EvDev> main, mom;
+    std::vector<TmJob> tm;
+};
+pe_status_t loglike_entry(pe_event_s* ev, const double* theta, int64_t n, double* loglike, double* aux,
+                          int precision, LlJobs& jobs);
+pe_status_t run_jobs(const LlJobs& jobs, int precision, hipStream_t st);
+bool tm_moments(const pe_event_s* ev, int precision);
+int64_t ws_draws(const pe_event_s* ev, int64_t n, int precision);
+pe_status_t ensure_moments(pe_event_s* ev, int64_t n);
 
 // Stage runners: upload the records to the stream's area and queue the launches.
 pe_status_t run_prep(const std::vector<PrepArg>& v, hipStream_t st);

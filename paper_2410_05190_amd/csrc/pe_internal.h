@@ -29,6 +29,11 @@ struct EvConst {
     int32_t dist, pad_;  // dist: 1 for a distance-marginalised likelihood (11-D)
     int32_t tm, tm_points;  // tm: 1 for a time-marginalised likelihood (11-D), its tc nodes
     double tc_lo, tc_hi;
+    // time marginal from block moments (split precision): tm_P moments per
+    // block of tm_fine bins (0: not available for this window, see kTmAlpha),
+    // evaluated about tm_tmid; tm_a = pi tm_fine df
+    int32_t tm_P, tm_fine;
+    double tm_tmid, tm_a;
     int64_t K;
     double f_lo, df, scale, amp0, gmst, chi_max, dl_max;
     double dtensor[PE_MAX_DET][6];  // detector tensor (x x^T - y y^T)/2: xx xy xz yy yz zz
@@ -159,6 +164,7 @@ struct EvDev {
     int *rcnt;       // [npad / 256] re-evaluated draws per block, then their offsets
     int *rpos;       // [npad] positions of the re-evaluated draws, ascending
     double2 *zd;     // [npad] Z of distance-marginalised events (read by k_b_dist)
+    double2 *tm_mom; // time marginal from block moments: [n_fine][tm_P][npad] moments of each draw's integrand
     int *status;
     int64_t npad;
     int max_groups;      // cap on the groups of chunks (partial capacity / npad)
@@ -174,6 +180,17 @@ struct EvDev {
 
 constexpr int kLlPrologue = 1;
 constexpr int kLlFinalize = 2;
+constexpr int kLlMoments = 4;  // time-marginalised event on the block-moment path (plan chunks of ec.tm_fine bins)
+
+// Block moments of the time marginal. Within a block of bins with centre f_c
+// and half-width D/2, exp(-2 pi i f u) = exp(-2 pi i f_c u) sum_p (-i a u)^p x^p / p!
+// with x = (f - f_c) / (D/2) in [-1, 1] and a = pi D; the series is cut after
+// P terms, which leaves at most |a u|^P / P! / (1 - |a u| / (P + 1)) of the
+// block's sum of |terms|. The block width is chosen so that |a u| <= kTmAlpha[P]
+// over the window (u = t - tm_tmid, |u| <= T / 2): 3.9e-10 and 3.5e-11 of the
+// sum of |terms| for P = 8 and 16.
+constexpr int kTmMoments = 16;  // the most moments a block carries
+constexpr double kTmAlpha8 = 0.25, kTmAlpha16 = 1.5;
 
 struct WeightArg {
     const double *ll, *lp, *lq;
@@ -287,6 +304,8 @@ struct pe_event_s {
     // (the workspace's npad counts these node draws)
     double *tm_theta = nullptr;  // [PE_MAX_DIM][npad]
     double *tm_ll = nullptr;     // [npad]
+    char *tm_mem = nullptr;      // block moments of the time marginal (own allocation, grown on demand)
+    int64_t tm_mom_cols = 0;     // draw columns tm_mem holds
     int64_t partial_cap = 0;  // double2 entries per detector
     double *coef = nullptr;   // [kNCoef][npad]
     int *kcut = nullptr;      // [npad]
@@ -353,6 +372,9 @@ void prime_hot_grids();
 // draw from the node log-likelihoods (theta: the draws, for their tc).
 hipError_t launch_tm_expand(const double* theta, int64_t n, const EvConst& ec, double* out, hipStream_t st);
 hipError_t launch_tm_reduce(const double* ll, int64_t n, const EvConst& ec, double* out, hipStream_t st);
+hipError_t launch_tm_centre(const double* theta, int64_t n, const EvConst& ec, double* out, hipStream_t st);
+hipError_t launch_loglike_moments(const BatchPtrs& b, int ne, int64_t prologue_blocks, int64_t node_blocks, int P,
+                                  hipStream_t st);
 hipError_t launch_waveform(const EvConst &ec, int data_psd_dtype, const double *theta, const void *psd, double *h,
                            double *snr2, double *scratch, hipStream_t st);
 hipError_t launch_uniforms(uint64_t seed, uint32_t stream_id, int64_t n, int npairs, double *u, hipStream_t st);

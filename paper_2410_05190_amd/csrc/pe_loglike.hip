@@ -196,6 +196,7 @@ __global__ __launch_bounds__(1024) void k_b_plan(const BatchHdr* __restrict__ hd
                 const int target = 8 * G;
                 int fine = ((p.kmax + target - 1) / target + kBlk - 1) / kBlk * kBlk;
                 fine = max(fine, kBlk);
+                if (E.flags & kLlMoments) fine = E.ec.tm_fine;  // the moment blocks
                 p.n_groups = G;
                 p.fine = fine;
                 p.n_fine = (p.kmax + fine - 1) / fine;
@@ -1130,6 +1131,19 @@ hipError_t launch_tm_reduce(const double* ll, int64_t n, const EvConst& ec, doub
     return hipGetLastError();
 }
 
+// The draws of a moment-path batch: theta with tc at the window's centre.
+__global__ __launch_bounds__(256) void k_tm_centre(const double* __restrict__ theta, int64_t n, EvConst ec,
+                                                   double* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        for (int a = 0; a < ec.dim; ++a) out[(int64_t)a * n + i] = (a == 9) ? ec.tm_tmid : theta[(int64_t)a * n + i];
+}
+
+hipError_t launch_tm_centre(const double* theta, int64_t n, const EvConst& ec, double* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_tm_centre<<<tm_grid(blocks256(n)), 256, 0, st>>>(theta, n, ec, out);
+    return hipGetLastError();
+}
+
 // Workgroups that fit on the GPU at once for a hot-loop kernel.
 template <typename Kern>
 static unsigned resident_grid(Kern kernel, int block = kTile) {
@@ -1212,6 +1226,416 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
         }
         if (any_dist) k_b_dist<<<grid_for(finalize_blocks * kDistLanes), 256, 0, st>>>(b.hdr, evs, b.off2);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Time marginal on the block-moment path (split precision). The draws are
+// evaluated once, with tc at the window's centre t_mid. Shifting tc by u
+// multiplies a detector term at f by exp(-2 pi i f u), so with y_k the
+// detector-summed term sum_d R_d z_dk of bin k,
+//   Z(u) = sum_k y_k exp(-2 pi i f_k u)
+//        = sum_c exp(-2 pi i f_c u) sum_p mu_cp (-i a u)^p / p!,
+//   mu_cp = sum_{k in block c} y_k x_k^p,  x_k = (f_k - f_c) / (D / 2),
+// over blocks c of D = ec.tm_fine bins' width with centres f_c and a = pi D
+// (the plan's chunks are these blocks). The hot loop writes the moments; the
+// node kernel forms Z at every tc node from them.
+// ---------------------------------------------------------------------------
+
+// One item of the moment hot loop: split_item's walk (records staged in LDS,
+// FP32 sums over kBlk bins folded into FP64, the same masking of bins past a
+// lane's cut), with the detector terms combined with the draw's responses and
+// summed into the P moments of each chunk, written to tm_mom[(c P + p) npad + j].
+template <int NDET, int P>
+__device__ __forceinline__ void split_tm_item(const EvDev& E, const EvPlan& p, int tile, int g, Rec32* srec,
+                                              int* sred) {
+    int j, kc, wmin, wmax;
+    bool valid;
+    DrawRow row;
+    double tau[NDET];
+    item_setup<NDET>(E, p.n_active, tile, j, valid, row, tau, kc, wmin, wmax);
+    const Rec32* tab = E.rec32;
+    const int K = (int)E.ec.K;
+    const int64_t np = E.npad;
+    const int jl = valid ? j : p.n_active - 1;
+    float rr[NDET], ri[NDET];
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+        rr[d] = (float)((const double*)E.resp)[(2 * d) * np + jl];
+        ri[d] = (float)((const double*)E.resp)[(2 * d + 1) * np + jl];
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sred[wv] = wmax;
+    __syncthreads();
+    const int gmax = max(max(sred[0], sred[1]), max(sred[2], sred[3]));
+    const float inv_half = 2.0f / (float)p.fine;
+    for (int c = g; c < p.n_fine; c += p.n_groups) {
+        const int k0 = c * p.fine;
+        if (k0 >= gmax) break;  // uniform over the workgroup
+        const int k1 = min(k0 + p.fine, K);
+        const bool on = k0 < wmax;
+        const int kA = on ? k0 + (max(0, min(wmin, k1) - k0) / kBlk) * kBlk : k0;
+        const int kB = on ? max(kA, min(k1, wmax)) : k0;
+        const int kl = min(k1, gmax);
+        const float kmid = (float)k0 + 0.5f * (float)(p.fine - 1);
+        double mr[P], mi[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) mr[q] = mi[q] = 0.0;
+        for (int ks = k0; ks < kl; ks += kStage) {
+            const int ke = min(ks + kStage, kl);
+            __syncthreads();  // the previous piece has been read
+            const uint4* src = (const uint4*)(tab + ks);
+            uint4* dst = (uint4*)srec;
+            for (int q = threadIdx.x; q < (ke - ks) * (int)(sizeof(Rec32) / 16); q += 256) dst[q] = src[q];
+            __syncthreads();
+            for (int kb = ks; kb < min(ke, kB); kb += kBlk) {
+                const int kq = min(kb + kBlk, kB);
+                float br[P], bi[P];
+#pragma unroll
+                for (int q = 0; q < P; ++q) br[q] = bi[q] = 0.0f;
+                for (int k = kb; k < kq; ++k) {
+                    const Rec32 r = srec[k - ks];
+                    const double psi = psi_turns(row.A, row.B5, row.B6, r.x, r.xm5, r.lnx);
+                    const bool live = (k < kA) || (k < kc);
+                    float yr = 0.0f, yi = 0.0f;
+#pragma unroll
+                    for (int d = 0; d < NDET; ++d) {
+                        const double ph = fma(r.f, tau[d], psi);
+                        const float t = (float)fract64(ph) + r.w[d].y;
+                        const float sn = __builtin_amdgcn_sinf(t);
+                        const float cs = __builtin_amdgcn_cosf(t);
+                        const float m = live ? r.w[d].x : 0.0f;
+                        const float tr = m * cs, ti = -m * sn;
+                        yr = fmaf(rr[d], tr, fmaf(-ri[d], ti, yr));
+                        yi = fmaf(rr[d], ti, fmaf(ri[d], tr, yi));
+                    }
+                    const float x = ((float)k - kmid) * inv_half;
+                    float xp = 1.0f;
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        br[q] = fmaf(yr, xp, br[q]);
+                        bi[q] = fmaf(yi, xp, bi[q]);
+                        xp *= x;
+                    }
+                }
+                if (kb < kA || kb < kc) {
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        mr[q] += (double)br[q];
+                        mi[q] += (double)bi[q];
+                    }
+                }
+            }
+        }
+        if (valid && on) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) E.tm_mom[((int64_t)c * P + q) * np + j] = make_double2(mr[q], mi[q]);
+        }
+    }
+    __syncthreads();  // sred and srec are reused by the next item
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_b_split_tm(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                    const int64_t* __restrict__ ioff) {
+    __shared__ Rec32 srec[kStage];
+    __shared__ int sred[4];
+    item_loop<false>(hdr, ioff, evs, [&](const Item& it) {
+        const EvDev& E = evs[it.e];
+        const EvPlan p = load_const(E.plan);
+        switch (E.ec.n_det) {
+            case 1: split_tm_item<1, P>(E, p, it.tile, it.g, srec, sred); break;
+            case 2: split_tm_item<2, P>(E, p, it.tile, it.g, srec, sred); break;
+            case 3: split_tm_item<3, P>(E, p, it.tile, it.g, srec, sred); break;
+            default: split_tm_item<4, P>(E, p, it.tile, it.g, srec, sred); break;
+        }
+    });
+}
+
+// One workgroup per live draw position. In passes of 256 tc nodes (one per
+// thread), the draw's moments are staged in LDS in pieces of kTmPiece chunks;
+// each thread carries its node's Z(u) and the chunk phasor exp(-2 pi i f_c u)
+// (advanced chunk to chunk by exp(-2 pi i D u)) over the chunks below the
+// draw's cut, then takes the node's ln L from Z and H (the phase and distance
+// marginals as the event has them) into a running weighted log-sum-exp with
+// the end-corrected trapezoid weights of k_tm_reduce. The threads' (max, sum)
+// pairs merge by a wave butterfly and then over the four waves in order.
+// Distance-marginalised events take two passes: the distance integral at a
+// node, ln L_D = ln int 3 x^-4 exp(phi(x) - b x^2) dx over x >= 1, is at most
+// max_x (a x - b x^2) (phi <= a x for both phase forms, and 3 x^-4 integrates
+// to 1): a^2 / (4 b) when a >= 2 b, else a - b. The first pass finds the node
+// with the largest such bound and integrates there (L*); the second integrates
+// only the nodes whose bound reaches L* - kTmSkip, the others adding less than
+// e^-kTmSkip of the largest term each.
+constexpr int kTmPiece = 128;
+constexpr double kTmSkip = 46.0;
+constexpr int kTmCached = 4;  // nodes per thread whose Z stays in registers (M <= 1024)
+
+__device__ __forceinline__ double dist_bound(const EvConst& ec, double zr, double zi, double h) {
+    const double a = (ec.phase == PE_PHASE_EXPLICIT) ? zr : hypot(zr, zi), b = 0.5 * h;
+    if (!(b > 0.0)) return (a == 0.0) ? 0.0 : INFINITY;
+    return (a >= 2.0 * b) ? a * a / (4.0 * b) : a - b;
+}
+
+// Z(u) of node m of draw j (act: m < M; threads past M follow the staging
+// barriers and return 0).
+template <int P>
+__device__ __forceinline__ void tm_node_z(const EvDev& E, const EvPlan& p, int64_t j, int nch, int m, bool act,
+                                          double2* smom, double& zr, double& zi) {
+    const EvConst& ec = E.ec;
+    const int M = ec.tm_points;
+    const double T = ec.tc_hi - ec.tc_lo;
+    const double Df = (double)p.fine * ec.df;  // block width (Hz)
+    const double fc0 = ec.f_lo + 0.5 * (double)(p.fine - 1) * ec.df;
+    const int64_t np = E.npad;
+    const double t = (m == M - 1) ? ec.tc_hi : ec.tc_lo + T * ((double)m / (double)(M - 1));
+    const double u = act ? t - ec.tm_tmid : 0.0;
+    // (-i a u)^k / k!
+    double bre[P], bim[P];
+    bre[0] = 1.0;
+    bim[0] = 0.0;
+#pragma unroll
+    for (int k = 1; k < P; ++k) {
+        const double s = ec.tm_a * u / (double)k;  // multiply by -i s
+        bre[k] = bim[k - 1] * s;
+        bim[k] = -bre[k - 1] * s;
+    }
+    double pr, pi_, sr, si;
+    sincos_turns(-fract64(fc0 * u), pi_, pr);  // exp(-2 pi i f_c0 u)
+    sincos_turns(-fract64(Df * u), si, sr);    // step to the next chunk
+    // S_k = sum_c mu_ck exp(-2 pi i f_c u): P independent sums over the chunks,
+    // then Z = sum_k S_k (-i a u)^k / k!
+    double ar[P], ai[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) ar[k] = ai[k] = 0.0;
+    zr = zi = 0.0;
+    for (int c0 = 0; c0 < nch; c0 += kTmPiece) {
+        const int nc = min(kTmPiece, nch - c0);
+        __syncthreads();  // the previous piece has been read
+        for (int w = threadIdx.x; w < nc * P; w += 256)
+            smom[w] = E.tm_mom[((int64_t)(c0 + w / P) * P + (w % P)) * np + j];
+        __syncthreads();
+        for (int c = 0; c < nc; ++c) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const double2 v = smom[c * P + k];
+                ar[k] = fma(v.x, pr, fma(-v.y, pi_, ar[k]));
+                ai[k] = fma(v.x, pi_, fma(v.y, pr, ai[k]));
+            }
+            const double nr = pr * sr - pi_ * si;
+            pi_ = pr * si + pi_ * sr;
+            pr = nr;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        zr = fma(ar[k], bre[k], fma(-ai[k], bim[k], zr));
+        zi = fma(ar[k], bim[k], fma(ai[k], bre[k], zi));
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_tm_nodes(const BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                  const int64_t* __restrict__ foff) {
+    __shared__ double2 smom[kTmPiece * P];
+    __shared__ double sg[4], ss[4];
+    __shared__ int sb[4], sm[4];
+    __shared__ double sL;
+    const int ne = hdr->ne;
+    const int64_t npos = foff[ne] * 256;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t q = blockIdx.x; q < npos; q += gridDim.x) {
+        const int e = find_slot(foff, ne, q >> 8);
+        const EvDev& E = evs[e];
+        const EvConst& ec = E.ec;
+        const EvPlan p = *E.plan;
+        const int64_t j = q - foff[e] * 256;
+        if (j >= p.n_active) continue;  // uniform over the workgroup
+        const int kc = E.kcut[j];
+        const int nch = (kc + p.fine - 1) / p.fine;
+        const double h = E.hh[j];
+        const int M = ec.tm_points;
+        double mx = -INFINITY, acc = 0.0;
+        int bad = 0;
+        // the node's ln L into the running weighted log-sum-exp
+        auto take = [&](int m, double zr, double zi, double lstar) {
+            double v;
+            if (ec.dist && dist_bound(ec, zr, zi, h) < lstar - kTmSkip)
+                v = -INFINITY;  // below e^-kTmSkip of the largest node
+            else
+                v = loglike_of<1>(ec, zr, zi, h, 0);
+            if (isnan(v) || v == INFINITY) bad = 1;
+            if (v > -INFINITY) {
+                const double cw = tm_weight(m, M);
+                if (v > mx) {
+                    acc = acc * exp(mx - v) + cw;
+                    mx = v;
+                } else {
+                    acc += cw * exp(v - mx);
+                }
+            }
+        };
+        // distance-marginalised events: the node of the largest bound (the
+        // smallest such m on ties) over the workgroup, from each thread's (ub, um)
+        auto best_node = [&](double ub, int um, int& bm) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double uo = __shfl_xor(ub, o);
+                const int mo = __shfl_xor(um, o);
+                if (uo > ub || (uo == ub && mo < um)) {
+                    ub = uo;
+                    um = mo;
+                }
+            }
+            if (lane == 0) {
+                sg[wv] = ub;
+                sm[wv] = um;
+            }
+            __syncthreads();
+            double bu = sg[0];
+            bm = sm[0];
+            for (int w = 1; w < 4; ++w)
+                if (sg[w] > bu || (sg[w] == bu && sm[w] < bm)) {
+                    bu = sg[w];
+                    bm = sm[w];
+                }
+        };
+        if (M <= kTmCached * 256) {
+            // each thread's nodes' Z kept in registers: one pass over the moments
+            double cr[kTmCached], ci[kTmCached];
+#pragma unroll
+            for (int i = 0; i < kTmCached; ++i) {
+                cr[i] = ci[i] = 0.0;
+                if (i * 256 < M) {  // uniform
+                    const int m = i * 256 + (int)threadIdx.x;
+                    tm_node_z<P>(E, p, j, nch, m, m < M, smom, cr[i], ci[i]);
+                }
+            }
+            double lstar = -INFINITY;
+            if (ec.dist) {
+                double ub = -INFINITY;
+                int um = 0;
+#pragma unroll
+                for (int i = 0; i < kTmCached; ++i) {
+                    const int m = i * 256 + (int)threadIdx.x;
+                    const double bnd = dist_bound(ec, cr[i], ci[i], h);
+                    if (m < M && bnd > ub) {
+                        ub = bnd;
+                        um = m;
+                    }
+                }
+                int bm;
+                best_node(ub, um, bm);
+                // the owner of that node integrates there
+#pragma unroll
+                for (int i = 0; i < kTmCached; ++i)
+                    if (i * 256 + (int)threadIdx.x == bm) sL = loglike_of<1>(ec, cr[i], ci[i], h, 0);
+                __syncthreads();
+                lstar = sL;
+            }
+#pragma unroll
+            for (int i = 0; i < kTmCached; ++i) {
+                const int m = i * 256 + (int)threadIdx.x;
+                if (m < M) take(m, cr[i], ci[i], lstar);
+            }
+        } else {
+            // more nodes: Z recomputed per pass
+            double lstar = -INFINITY;
+            if (ec.dist) {
+                double ub = -INFINITY;
+                int um = 0;
+                for (int m0 = 0; m0 < M; m0 += 256) {
+                    const int m = m0 + (int)threadIdx.x;
+                    double zr, zi;
+                    tm_node_z<P>(E, p, j, nch, m, m < M, smom, zr, zi);
+                    const double bnd = dist_bound(ec, zr, zi, h);
+                    if (m < M && bnd > ub) {
+                        ub = bnd;
+                        um = m;
+                    }
+                }
+                int bm;
+                best_node(ub, um, bm);
+                double zr, zi;
+                tm_node_z<P>(E, p, j, nch, bm, true, smom, zr, zi);  // collective staging
+                if (threadIdx.x == 0) sL = loglike_of<1>(ec, zr, zi, h, 0);
+                __syncthreads();
+                lstar = sL;
+            }
+            for (int m0 = 0; m0 < M; m0 += 256) {
+                const int m = m0 + (int)threadIdx.x;
+                double zr, zi;
+                tm_node_z<P>(E, p, j, nch, m, m < M, smom, zr, zi);
+                if (m < M) take(m, zr, zi, lstar);
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double mo = __shfl_xor(mx, o), ao = __shfl_xor(acc, o);
+            bad |= __shfl_xor(bad, o);
+            const double mm = fmax(mx, mo);
+            if (mm > -INFINITY)
+                acc = (mx > -INFINITY ? acc * exp(mx - mm) : 0.0) + (mo > -INFINITY ? ao * exp(mo - mm) : 0.0);
+            mx = mm;
+        }
+        __syncthreads();  // sg is free again
+        if (lane == 0) {
+            sg[wv] = mx;
+            ss[wv] = acc;
+            sb[wv] = bad;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double G = -INFINITY, S = 0.0;
+            int b = 0;
+            for (int w = 0; w < 4; ++w) {
+                b |= sb[w];
+                if (!(sg[w] > -INFINITY)) continue;
+                if (sg[w] > G) {
+                    S = S * exp(G - sg[w]) + ss[w];
+                    G = sg[w];
+                } else {
+                    S += ss[w] * exp(sg[w] - G);
+                }
+            }
+            E.loglike[E.idx[j]] = b ? NAN : (G > -INFINITY ? G + log(S) - log((double)(M - 1)) : -INFINITY);
+        }
+        __syncthreads();  // sg, ss, sb, sL are reused by the next draw
+    }
+}
+
+template <int P>
+static void launch_moments_p(const BatchPtrs& b, const EvDev* evs, int64_t* ioff, unsigned grid, unsigned ng,
+                             hipStream_t st) {
+    k_b_split_tm<P><<<grid, kTile, 0, st>>>(b.hdr, evs, ioff);
+    k_tm_nodes<P><<<ng, 256, 0, st>>>(b.hdr, evs, b.off2);
+}
+
+static unsigned split_tm_grid(int P) {
+    static const unsigned g8 = resident_grid(k_b_split_tm<8>);
+    static const unsigned g16 = resident_grid(k_b_split_tm<16>);
+    return P == 8 ? g8 : g16;
+}
+
+hipError_t launch_loglike_moments(const BatchPtrs& b, int ne, int64_t prologue_blocks, int64_t node_blocks, int P,
+                                  hipStream_t st) {
+    if (ne <= 0) return hipSuccess;
+    if (P != 8 && P != 16) return hipErrorInvalidValue;
+    const EvDev* evs = (const EvDev*)b.args;
+    int64_t* ioff = (int64_t*)b.scratch;
+    const unsigned eg = (unsigned)min(ne, 1024);
+    const unsigned nb = grid_for(prologue_blocks);
+    k_b_reset<<<dim3(kBuckets / 256, eg), 256, 0, st>>>(b.hdr, evs);
+    k_b_support<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
+    k_b_plan<<<eg, 1024, 0, st>>>(b.hdr, evs);
+    k_b_scatter<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
+    k_b_items<<<1, 64, 0, st>>>(b.hdr, evs, ioff);
+    k_b_coeffs<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
+    const unsigned ng = grid_for(node_blocks * 256);
+    if (P == 8)
+        launch_moments_p<8>(b, evs, ioff, split_tm_grid(8), ng, st);
+    else
+        launch_moments_p<16>(b, evs, ioff, split_tm_grid(16), ng, st);
     return hipGetLastError();
 }
 
