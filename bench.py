@@ -292,13 +292,20 @@ def main():
             lo, hi = first["theta_inj"][9] - 0.01, first["theta_inj"][9] + 0.01
             pts = int(math.ceil((hi - lo) / (0.5 / math.sqrt(g_tt)))) + 1
             tm = {"tc_lo": float(lo), "tc_hi": float(hi), "tm_points": pts}
+            how = ("block moments of each draw's integrand (one likelihood-like pass, then every node from the "
+                   "moments)" if prec == binding.PE_PREC_SPLIT else "every node a likelihood evaluation")
             leg = distance_leg(first, centres, max(args.steps // 4, 2), prec, phase=binding.PE_PHASE_MARG,
                                time_marg=tm, n_draws=args.time_leg_draws)
             leg["kind"] = (f"likelihood marginalised over the coalescence time (flat over 20 ms about the injected "
-                           f"tc; end-corrected trapezoid rule on {pts} nodes over the window, each a likelihood "
-                           f"evaluation), the phase and the distance; all three left out of the proposal density")
+                           f"tc; end-corrected trapezoid rule on {pts} nodes over the window, from {how}), the "
+                           f"phase and the distance; all three left out of the proposal density")
             leg["time_nodes"] = tm
             out["time_phase_and_distance_marginalised"] = leg
+            leg = distance_leg(first, centres, max(args.steps // 4, 2), prec, phase=binding.PE_PHASE_MARG,
+                               time_marg=tm, n_draws=args.time_leg_draws, distance=False)
+            leg["kind"] = (f"likelihood marginalised over the coalescence time (as the leg above) and the phase; "
+                           f"the distance sampled")
+            out["time_and_phase_marginalised"] = leg
     if n_events == 1 and D == 4 and args.tile_candidates > 0:
         out["tiles"] = tile_leg(first, args, max(args.steps, 1), prec)
     for x in evs:
@@ -542,14 +549,15 @@ def relbin_leg(x, eps, steps, prec):
     }
 
 
-def distance_leg(x, centres, steps, prec, phase=None, time_marg=None, n_draws=None):
+def distance_leg(x, centres, steps, prec, phase=None, time_marg=None, n_draws=None, distance=True):
     """Distance-marginalised likelihood (PE_DIST_MARG: the likelihood integrated over the dL^2
     prior per draw; the metric, draws and prior without dL): the same step as the main leg on a
     second event over the same data, at each proposal centre (the injection, and the refined
     centre of the refinement leg when it ran). ESS per event and ESS/s. phase=PE_PHASE_MARG also
     marginalises the coalescence phase (ln I0 form; phic left out of the proposal density);
-    time_marg = {tc_lo, tc_hi, tm_points} also the coalescence time (each draw evaluated at tm_points
-    nodes over the window, tc left out of the proposal density)."""
+    time_marg = {tc_lo, tc_hi, tm_points} also the coalescence time (the likelihood integrated over
+    tm_points nodes spanning the window, tc left out of the proposal density); distance=False keeps
+    the distance sampled."""
     import torch
 
     from paper_2410_05190_amd import binding
@@ -558,7 +566,8 @@ def distance_leg(x, centres, steps, prec, phase=None, time_marg=None, n_draws=No
         common["phase"] = phase
     if time_marg:
         common.update(time_marg=1, **time_marg)
-    ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], distance=binding.PE_DIST_MARG, **common)
+    ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"],
+                       distance=binding.PE_DIST_MARG if distance else binding.PE_DIST_SAMPLED, **common)
     N = n_draws or x["N"]
     ev.reserve(N)
     h_ = ev.handle
