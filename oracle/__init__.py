@@ -106,6 +106,10 @@ def lib():
                                     ctypes.c_long, ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp, _dp, _lp]
         L.peo_tile_assign.argtypes = [ctypes.c_int, ctypes.c_long, _dp, ctypes.c_long, ctypes.c_long, _dp,
                                       ctypes.c_long, _ip]
+        L.peo_match.restype = ctypes.c_double
+        L.peo_match.argtypes = [ctypes.POINTER(_Event), _dp, _dp]
+        L.peo_tile_assign_match.argtypes = [ctypes.POINTER(_Event), ctypes.c_long, _dp, ctypes.c_long,
+                                            ctypes.c_long, _dp, ctypes.c_long, _ip, _dp]
         L.peo_tile_draw.restype = ctypes.c_int
         L.peo_tile_draw.argtypes = [ctypes.c_long, _dp, ctypes.c_long, _ip, _dp, ctypes.c_int, _dp, ctypes.c_long,
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_long, _dp, _dp, _dp, _lp]
@@ -327,6 +331,22 @@ class Event:
     def logprior(self, theta):
         th = _f64(theta)
         return lib().peo_logprior(self.ref, _p(th))
+
+    def match(self, theta_a, theta_b):
+        """Waveform match of two points (overlap maximised over a constant phase, normalised)."""
+        return lib().peo_match(self.ref, _p(_f64(theta_a)), _p(_f64(theta_b)))
+
+    def tile_assign_match(self, tiles_theta, theta):
+        """Template of largest match of every sample (brute force): (tile_of, match)."""
+        tt = _f64(tiles_theta)
+        th = _f64(theta)
+        m = tt.shape[1]
+        n = th.shape[1]
+        out = np.zeros(n, dtype=np.int32)
+        mv = np.zeros(n)
+        lib().peo_tile_assign_match(self.ref, m, _p(tt), m, n, _p(th), n,
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(mv))
+        return out, mv
 
 
 def pn_coeffs(eta, delta, chi1, chi2):

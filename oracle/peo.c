@@ -1622,3 +1622,93 @@ void peo_relbin_loglike(const peo_event *ev, const double *theta_f, long n_edges
     }
     free(c);
 }
+
+/* Waveform similarity (App. A maps the prior volume to tiles by it; Sec. III
+ * uses the plain overlap for aligned spins): the match of a and b is their
+ * complex overlap <h_a, h_b> = 4 df sum_d sum_k conj(h_a) h_b / S, maximised
+ * over a constant phase (its modulus), divided by the norms,
+ *   m(a, b) = |<h_a, h_b>| / sqrt((h_a|h_a)(h_b|h_b)),
+ * each waveform zero above its own ISCO bin. 0 when either norm is 0. The
+ * waveforms of a pair are made bin by bin (the same as in loglike_one). */
+static double match_pair(const peo_event *ev, const peo_source *sa, const peo_source *sb)
+{
+    nsum re = {0, 0}, im = {0, 0}, na = {0, 0}, nb = {0, 0};
+    int d;
+    long k;
+    for (d = 0; d < ev->n_det; d++) {
+        const double *S = ev->psd + (long)d * ev->n_bins;
+        for (k = 0; k < ev->n_bins && (k < sa->kcut || k < sb->kcut); k++) {
+            double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+            const double w = 4.0 * ev->df / S[k];
+            if (k < sa->kcut)
+                wf_bin(ev, sa, d, k, &ar, &ai);
+            if (k < sb->kcut)
+                wf_bin(ev, sb, d, k, &br, &bi);
+            nadd(&re, w * (ar * br + ai * bi));
+            nadd(&im, w * (ar * bi - ai * br));
+            nadd(&na, w * (ar * ar + ai * ai));
+            nadd(&nb, w * (br * br + bi * bi));
+        }
+    }
+    if (!(nval(&na) > 0.0) || !(nval(&nb) > 0.0))
+        return 0.0;
+    return hypot(nval(&re), nval(&im)) / sqrt(nval(&na) * nval(&nb));
+}
+
+/* Match of two parameter points (see match_pair); -1 if either is outside the
+ * support. */
+double peo_match(const peo_event *ev, const double *theta_a, const double *theta_b)
+{
+    peo_source sa, sb;
+    double ta[PEO_MAX_DIM], tb[PEO_MAX_DIM];
+    likelihood_theta(ev, theta_a, ta);
+    likelihood_theta(ev, theta_b, tb);
+    if (!peo_source_from_theta(ev, ta, &sa) || !peo_source_from_theta(ev, tb, &sb))
+        return -1.0;
+    sa.kcut = peo_kcut(ev, sa.fisco);
+    sb.kcut = peo_kcut(ev, sb.fisco);
+    return match_pair(ev, &sa, &sb);
+}
+
+/* Tile of each sample by waveform similarity (App. A): the template of
+ * largest match with the sample, the lowest index among equals, by brute force
+ * over every template. tth [D][ld_t] (n_tiles used), th [D][ld_s] (n used);
+ * tile_of [n], match [n] (the largest match). */
+void peo_tile_assign_match(const peo_event *ev, long n_tiles, const double *tth, long ld_t, long n,
+                           const double *th, long ld_s, int *tile_of, double *match)
+{
+    const int D = ev->params == PEO_PARAMS_4D ? 4 : 11;
+    peo_source *st = (peo_source *)malloc(sizeof(peo_source) * (size_t)(n_tiles > 0 ? n_tiles : 1));
+    long j, s;
+    for (j = 0; j < n_tiles; j++) {
+        double t[PEO_MAX_DIM], tl[PEO_MAX_DIM];
+        int a;
+        for (a = 0; a < D; a++)
+            t[a] = tth[(long)a * ld_t + j];
+        likelihood_theta(ev, t, tl);
+        peo_source_from_theta(ev, tl, &st[j]);
+        st[j].kcut = peo_kcut(ev, st[j].fisco);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (s = 0; s < n; s++) {
+        double t[PEO_MAX_DIM], tl[PEO_MAX_DIM], bm = -1.0;
+        peo_source ss;
+        long best = 0, jj;
+        int a;
+        for (a = 0; a < D; a++)
+            t[a] = th[(long)a * ld_s + s];
+        likelihood_theta(ev, t, tl);
+        peo_source_from_theta(ev, tl, &ss);
+        ss.kcut = peo_kcut(ev, ss.fisco);
+        for (jj = 0; jj < n_tiles; jj++) {
+            const double m = match_pair(ev, &ss, &st[jj]);
+            if (m > bm) {
+                bm = m;
+                best = jj;
+            }
+        }
+        tile_of[s] = (int)best;
+        match[s] = bm;
+    }
+    free(st);
+}

@@ -170,6 +170,12 @@ long peo_tile_bank(const peo_event *ev, const peo_slice *sl, double min_dist, ui
                    long *consumed);
 void peo_tile_assign(int D, long n_tiles, const double *ty, long ld_t, long n, const double *y, long ld_s,
                      int *tile_of);
+/* Waveform match of two points (the overlap maximised over a constant phase,
+ * normalised); -1 outside the support. */
+double peo_match(const peo_event *ev, const double *theta_a, const double *theta_b);
+/* Tile of each sample by largest match (brute force over the templates). */
+void peo_tile_assign_match(const peo_event *ev, long n_tiles, const double *tth, long ld_t, long n,
+                           const double *th, long ld_s, int *tile_of, double *match);
 int peo_tile_draw(long n_tiles, const double *tile_ll, long P, const int *tile_of, const double *lp, int D,
                   const double *samples, long ld, uint64_t seed, uint32_t stream, long n, double *theta,
                   double *logq, double *logprior, long *index);

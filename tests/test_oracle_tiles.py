@@ -232,3 +232,75 @@ def test_reweighted_round_raises_the_efficiency():
         eff.append(st[0] / 4096)
         ell = oracle.tile_reweight(ell, to, lp, idx, w, 0.1)
     assert eff[1] > 0.2 and eff[1] > 3 * eff[0]
+
+
+def _overlap(b, ta, tb):
+    """Complex overlap 4 df sum conj(h_a) h_b / S and the two norms, in numpy from the oracle's
+    waveforms (each zero above its own cut)."""
+    ha = b.ev.waveform(ta)
+    hb = b.ev.waveform(tb)
+    w = 4.0 * b.df / b.psd.astype(np.float64)
+    o = (w * np.conj(ha) * hb).sum()
+    return o, float((w * np.abs(ha) ** 2).sum()), float((w * np.abs(hb) ** 2).sum())
+
+
+def test_match_is_the_phase_maximised_overlap():
+    """The oracle's match (App. A's waveform similarity) against numpy: |<h_a, h_b>| over the norms,
+    and the largest normalised real overlap over a grid of constant phase shifts (to the grid's
+    resolution); 1 for a point with itself, symmetric, at most 1."""
+    b = build_event(0, 0, n_bins=4000)
+    rng = np.random.default_rng(3)
+    g = b.ev.metric(b.theta_inj)
+    cov = np.linalg.inv(g)
+    assert b.ev.match(b.theta_inj, b.theta_inj) == pytest.approx(1.0, abs=1e-13)
+    pts = []
+    while len(pts) < 8:  # points inside the support
+        t = b.theta_inj + rng.multivariate_normal(np.zeros(4), cov * 4.0)
+        if np.isfinite(b.ev.logprior(t)):
+            pts.append(t)
+    for ta, tb in zip(pts[::2], pts[1::2]):
+        m = b.ev.match(ta, tb)
+        o, na, nb = _overlap(b, ta, tb)
+        assert m == pytest.approx(abs(o) / math.sqrt(na * nb), rel=1e-12)
+        phis = np.linspace(0.0, 2 * math.pi, 20001)
+        best = np.max(np.real(np.exp(1j * phis) * o)) / math.sqrt(na * nb)
+        assert m == pytest.approx(best, abs=1e-7)
+        assert b.ev.match(tb, ta) == pytest.approx(m, rel=1e-13)
+        assert 0.0 <= m <= 1.0
+
+
+def test_mismatch_follows_the_metric():
+    """1 - m(theta, theta + d) = d^T g d / (2 (h|h)) + O(|d|^3) with g the phase-projected metric of
+    the 4-D set (the metric is the second-order expansion of the mismatch, Sec. II.A): at metric
+    lengths 1e-3 .. 1e-4 in random directions the two agree to 1e-3 relative."""
+    b = build_event(0, 0, n_bins=4000)
+    th = b.theta_inj
+    g = b.ev.metric(th)
+    h = b.ev.waveform(th)
+    hh = b.ev.inner(0, h, h)
+    rng = np.random.default_rng(11)
+    for eps in (1e-3, 3e-4, 1e-4):
+        for _ in range(3):
+            d = rng.standard_normal(4)
+            d /= math.sqrt(d @ g @ d)
+            mm = 1.0 - b.ev.match(th, th + eps * d)
+            assert mm == pytest.approx(0.5 * eps * eps / hh, rel=1e-3)
+
+
+def test_match_assignment_is_the_largest_match():
+    """Tile by match against brute force in numpy over every template (from the oracle's waveforms):
+    the template of largest match, and that match."""
+    b = build_event(0, 1, n_bins=3000)
+    sl, L, c = _slice(b, 4.0)
+    ty, tth, used = b.ev.tile_bank(sl, 1.0, 7, 1, 512, 40, 0.0, 20)
+    y, th, lp = b.ev.slice_sample(sl, 7, 2, 0, 400)
+    th = th[:, :30]
+    to, mv = b.ev.tile_assign_match(tth, th)
+    for s in range(th.shape[1]):
+        ms = []
+        for j in range(tth.shape[1]):
+            o, na, nb = _overlap(b, th[:, s], tth[:, j])
+            ms.append(abs(o) / math.sqrt(na * nb))
+        ms = np.array(ms)
+        assert mv[s] == pytest.approx(ms.max(), rel=1e-12)
+        assert ms[to[s]] == pytest.approx(ms.max(), rel=1e-12)
