@@ -425,6 +425,28 @@ pe_status_t pe_tile_assign(int32_t dim, int32_t n_tiles, const double *tiles_y_d
                            const double *y_dev, int64_t ld_y, int32_t *tile_of_dev, void *stream);
 
 /*
+ * Tile of each sample by waveform similarity (App. A maps the prior volume to
+ * the template nearest in match; Sec. III takes the plain overlap for aligned
+ * spins), for the 4-D parameter set with one detector: among the sample's
+ * n_cand (1, 2, 4 or 8) nearest templates in whitened coordinates, the one of
+ * largest match
+ *   m(s, t) = |sum_k pw_k exp(2 pi i (Psi_s(f_k) - Psi_t(f_k)))| / sqrt(P_s P_t),
+ * the overlap maximised over a constant phase and normalised: pw = 4 df
+ * f^(-7/3) / S from the event's tables, the sum over the bins below both
+ * points' cuts, P a point's sum of pw below its cut, Psi the phase in turns
+ * with its 2 pi f tc term (FP64 phases and sine/cosine). The lowest template
+ * index among equal matches. tiles_y_dev, tiles_theta_dev [4][ld_tiles]
+ * (n_tiles used); y_dev, theta_dev [4][ld] (n used); outputs tile_of_dev [n]
+ * int32 and, if not NULL, match_dev [n] (the chosen template's match).
+ * Allocates its scratch and synchronises the stream. Errors: PE_ERR_ARG (not a
+ * one-detector 4-D event, bad sizes, NULL), PE_ERR_OOM, PE_ERR_HIP.
+ */
+pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, const double *tiles_y_dev,
+                                 const double *tiles_theta_dev, int64_t ld_tiles, int64_t n, const double *y_dev,
+                                 const double *theta_dev, int64_t ld, int32_t n_cand, int32_t *tile_of_dev,
+                                 double *match_dev, void *stream);
+
+/*
  * Proposal draws from the tiles (Sec. II.A; App. A, the proposal): sample s
  * (of P) carries the mass m_s = exp(ll_t(s) - max ll + lp_s - max lp) (its
  * tile's template log-likelihood tile_loglike_dev[t(s)] and its log prior

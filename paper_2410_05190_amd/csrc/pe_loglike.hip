@@ -30,26 +30,6 @@
 
 namespace pe {
 
-// Loads from read-only device memory. The hot loop reaches its tables through
-// pointers held in device memory, so the compiler cannot prove on its own that
-// the kernel's stores leave them unchanged; the constant address space says so
-// and lets wave-uniform loads go through the scalar unit (s_load). Records are
-// copied as 32-bit words, which the compiler merges into wide scalar loads.
-typedef const __attribute__((address_space(4))) uint32_t* cwords;
-typedef const __attribute__((address_space(1))) double* gdoubles;
-typedef const __attribute__((address_space(1))) int* gints;
-
-template <typename T>
-__device__ __forceinline__ T load_const(const T* p) {
-    static_assert(sizeof(T) % 4 == 0, "record size must be a multiple of 4 bytes");
-    const cwords w = (cwords)p;
-    uint32_t buf[sizeof(T) / 4];
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) buf[i] = w[i];
-    T r;
-    __builtin_memcpy(&r, buf, sizeof(T));
-    return r;
-}
 
 __device__ __forceinline__ int bucket_shift(int64_t K) {
     int s = 0;

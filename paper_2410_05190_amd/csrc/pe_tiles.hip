@@ -9,6 +9,9 @@
 //                  min_dist from every template so far (the host then takes
 //                  the batch in order against the batch's own new templates)
 //   k_tile_assign  nearest template of every sample, templates staged in LDS
+//   k_match_rows, k_tile_topc, k_tile_match
+//                  tiles by waveform match: phase coefficients of templates and
+//                  samples, each sample's nearest templates, their matches
 //   k_tile_max, k_tile_mass, k_scan_sums, k_scan_write, k_tile_pick
 //                  proposal draws: per-sample masses, FP64 prefix sums,
 //                  inverse-CDF pick by binary search
@@ -221,6 +224,155 @@ __global__ __launch_bounds__(256) void k_tile_assign(int m, const double* __rest
         }
     }
     if (s < n) tile_of[s] = best;
+}
+
+// ------------------------------------------------------ assignment by match
+// Tiles by waveform similarity (App. A), for the 4-D set (one detector, a
+// common amplitude f^-7/6): the match of a sample s and a template t is
+//   |sum_k pw_k exp(2 pi i (Psi_s(f_k) - Psi_t(f_k)))| / sqrt(P_s P_t),
+// over the bins below both cuts, pw = 4 df f^-7/3 / S, P the prefix of pw at a
+// point's cut (its norm), Psi in turns with the 2 pi f tc term. Each sample's
+// candidates are its n_cand nearest templates in whitened coordinates; the
+// match picks among them (the lowest template index among equal matches).
+
+// Coefficient rows of points: A0..A7, B5, B6, tc ([kMatchRow][n]), cut, norm.
+constexpr int kMatchRow = 11;
+
+__global__ __launch_bounds__(256) void k_match_rows(EvConst ec, const double* __restrict__ th, int64_t ld, int64_t n,
+                                                    const double* __restrict__ pfx, double* __restrict__ rows,
+                                                    int* __restrict__ kc, double* __restrict__ nrm) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double t[PE_MAX_DIM];
+#pragma unroll
+        for (int a = 0; a < PE_MAX_DIM; ++a) t[a] = a < 4 ? th[a * ld + i] : 0.0;
+        Src s;
+        const int ok = source_from_theta(ec, t, s);
+        PhaseCoef pc;
+        phase_coeffs(s, pc);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) rows[a * n + i] = pc.A[a];
+        rows[8 * n + i] = pc.B5;
+        rows[9 * n + i] = pc.B6;
+        rows[10 * n + i] = s.tc + s.dt[0];
+        const int k = ok ? (int)kcut_of(ec, s.fisco) : 0;
+        kc[i] = k;
+        nrm[i] = pfx[k];
+    }
+}
+
+// The n_cand nearest templates of each sample, nearest first (ties: lower index).
+template <int C>
+__global__ __launch_bounds__(256) void k_tile_topc(int m, const double* __restrict__ ty, int64_t ldt, int64_t n,
+                                                   const double* __restrict__ ys, int64_t lds,
+                                                   int* __restrict__ cand) {
+    __shared__ double tl[256 * 4];
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double y[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) y[a] = (s < n) ? ys[a * lds + s] : 0.0;
+    double bd[C];
+    int bi[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        bd[c] = INFINITY;
+        bi[c] = 0;
+    }
+    for (int j0 = 0; j0 < m; j0 += 256) {
+        const int cnt = min(256, m - j0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt * 4; q += 256) {
+            const int a = q / cnt, j = q - a * cnt;
+            tl[a * 256 + j] = ty[a * ldt + j0 + j];
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            double d = wdist2<4>(y, 1, tl + j, 256);
+            int id = j0 + j;
+            // insertion into the sorted list (strictly smaller distance moves ahead)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (d < bd[c]) {
+                    const double td = bd[c];
+                    const int ti = bi[c];
+                    bd[c] = d;
+                    bi[c] = id;
+                    d = td;
+                    id = ti;
+                }
+            }
+        }
+    }
+    if (s < n)
+#pragma unroll
+        for (int c = 0; c < C; ++c) cand[(int64_t)c * n + s] = (c < m) ? bi[c] : bi[0];
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_tile_match(const Rec64* __restrict__ tab, const double* __restrict__ pw,
+                                                    int64_t n, const double* __restrict__ srow,
+                                                    const int* __restrict__ skc, const double* __restrict__ snrm,
+                                                    int64_t m, const double* __restrict__ trow,
+                                                    const int* __restrict__ tkc, const double* __restrict__ tnrm,
+                                                    const int* __restrict__ cand, int* __restrict__ tile_of,
+                                                    double* __restrict__ match) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = s < n;
+    const int64_t sl = valid ? s : n - 1;
+    double As[8], Ts[C][8], B5s, B6s, tcs, B5t[C], B6t[C], tct[C];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) As[a] = srow[a * n + sl];
+    B5s = srow[8 * n + sl];
+    B6s = srow[9 * n + sl];
+    tcs = srow[10 * n + sl];
+    const int kcs = skc[sl];
+    int ti[C], kl[C], kmax = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        ti[c] = cand[(int64_t)c * n + sl];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) Ts[c][a] = trow[a * m + ti[c]];
+        B5t[c] = trow[8 * m + ti[c]];
+        B6t[c] = trow[9 * m + ti[c]];
+        tct[c] = trow[10 * m + ti[c]];
+        kl[c] = min(kcs, tkc[ti[c]]);
+        kmax = max(kmax, kl[c]);
+    }
+    // the wave walks to its largest cut; lanes mask the bins past theirs
+    int wk = kmax;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wk = max(wk, __shfl_xor(wk, o));
+    wk = __builtin_amdgcn_readfirstlane(wk);
+    double ar[C], ai[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ar[c] = ai[c] = 0.0;
+    for (int k = 0; k < wk; ++k) {
+        const Rec64 r = load_const(tab + k);
+        const double w = load_const(pw + k);
+        const double ps = fma(r.f, tcs, psi_turns(As, B5s, B6s, r.x, r.xm5, r.lnx));
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const double pt = fma(r.f, tct[c], psi_turns(Ts[c], B5t[c], B6t[c], r.x, r.xm5, r.lnx));
+            double sn, cs;
+            sincos_turns(fract64(ps - pt), sn, cs);
+            const double wm = (k < kl[c]) ? w : 0.0;
+            ar[c] = fma(wm, cs, ar[c]);
+            ai[c] = fma(wm, sn, ai[c]);
+        }
+    }
+    if (!valid) return;
+    double bm = -1.0;
+    int best = ti[0];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const double den = snrm[s] * tnrm[ti[c]];
+        const double mc = den > 0.0 ? hypot(ar[c], ai[c]) / sqrt(den) : 0.0;
+        if (mc > bm || (mc == bm && ti[c] < best)) {
+            bm = mc;
+            best = ti[c];
+        }
+    }
+    tile_of[s] = best;
+    if (match) match[s] = bm;
 }
 
 // ---------------------------------------------------------------------- draws
@@ -614,6 +766,66 @@ extern "C" pe_status_t pe_tile_assign(int32_t dim, int32_t n_tiles, const double
     else
         k_tile_assign<11><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld_y, tile_of_dev);
     PE_HIP(hipGetLastError());
+    return PE_OK;
+}
+
+extern "C" pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, const double* tiles_y_dev,
+                                            const double* tiles_theta_dev, int64_t ld_tiles, int64_t n,
+                                            const double* y_dev, const double* theta_dev, int64_t ld, int32_t n_cand,
+                                            int32_t* tile_of_dev, double* match_dev, void* stream) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (ev->desc.params != PE_PARAMS_4D || ev->desc.n_det != 1)
+        return fail(PE_ERR_ARG, "match-based tiles take the 4-D parameter set with one detector");
+    if (n_cand != 1 && n_cand != 2 && n_cand != 4 && n_cand != 8) return fail(PE_ERR_ARG, "n_cand must be 1, 2, 4 or 8");
+    if (n_tiles < 1 || n_tiles > (1 << 24) || ld_tiles < n_tiles) return fail(PE_ERR_ARG, "bad n_tiles or ld_tiles");
+    if (n < 0 || n > ((int64_t)1 << 30) || ld < n) return fail(PE_ERR_ARG, "bad n or ld");
+    if (!tiles_y_dev || !tiles_theta_dev || (n > 0 && (!y_dev || !theta_dev || !tile_of_dev)))
+        return fail(PE_ERR_ARG, "NULL pointer");
+    if (n == 0) return PE_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // scratch: rows, cuts and norms of the templates and samples, the candidates
+    const int64_t m = n_tiles;
+    const size_t bytes = sizeof(double) * (size_t)(kMatchRow + 1) * (size_t)(m + n) +
+                         sizeof(int) * (size_t)(m + n + (int64_t)n_cand * n) + 1024;
+    char* mem = nullptr;
+    pe_status_t s = dalloc_bytes(&mem, bytes);
+    if (s != PE_OK) return s;
+    Carver c(mem);
+    double* trow = c.take<double>((size_t)kMatchRow * m);
+    double* tnrm = c.take<double>((size_t)m);
+    double* srow = c.take<double>((size_t)kMatchRow * n);
+    double* snrm = c.take<double>((size_t)n);
+    int* tkc = c.take<int>((size_t)m);
+    int* skc = c.take<int>((size_t)n);
+    int* cand = c.take<int>((size_t)n_cand * n);
+    k_match_rows<<<nblocks(m), 256, 0, st>>>(ev->ec, tiles_theta_dev, ld_tiles, m, ev->pfx, trow, tkc, tnrm);
+    k_match_rows<<<nblocks(n), 256, 0, st>>>(ev->ec, theta_dev, ld, n, ev->pfx, srow, skc, snrm);
+    switch (n_cand) {
+        case 1:
+            k_tile_topc<1><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand);
+            k_tile_match<1><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, n, srow, skc, snrm, m, trow, tkc, tnrm,
+                                                        cand, tile_of_dev, match_dev);
+            break;
+        case 2:
+            k_tile_topc<2><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand);
+            k_tile_match<2><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, n, srow, skc, snrm, m, trow, tkc, tnrm,
+                                                        cand, tile_of_dev, match_dev);
+            break;
+        case 4:
+            k_tile_topc<4><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand);
+            k_tile_match<4><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, n, srow, skc, snrm, m, trow, tkc, tnrm,
+                                                        cand, tile_of_dev, match_dev);
+            break;
+        default:
+            k_tile_topc<8><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand);
+            k_tile_match<8><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, n, srow, skc, snrm, m, trow, tkc, tnrm,
+                                                        cand, tile_of_dev, match_dev);
+            break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree_bytes(mem);
+    if (e != hipSuccess) return fail(PE_ERR_HIP, hipGetErrorString(e));
     return PE_OK;
 }
 

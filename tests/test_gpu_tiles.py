@@ -183,3 +183,36 @@ def test_tile_mixture_chain_on_the_gpu():
     # deterministic chain: 4.2% -> 11.3% here (the oracle's chain with 4096 draws per round: 2.1% -> 31.6%)
     assert st2[0] / n > 0.08 and st2[0] > 2 * st[0]
     ev.close()
+
+
+@pytest.mark.parametrize("n_cand", [8, 1])
+def test_match_assignment_against_the_oracle(n_cand):
+    """Tiles by waveform match (App. A) on the oracle's bank and samples: each sample's chosen template
+    has the match the oracle computes for that pair (1e-9), and where the oracle's best template is
+    among the sample's n_cand nearest in whitened coordinates, the GPU picks it (unless another of
+    them matches within 1e-9); with one candidate the choice is the nearest template."""
+    torch_cuda()
+    b = build_event(0, 0, n_bins=8000)
+    so, _ = _slices(b, 5.0)
+    tyo, ttho, _ = b.ev.tile_bank(so, 1.0, 5, 1, 1024, 80, 0.0, 40)
+    yo, tho, lpo = b.ev.slice_sample(so, 5, 2, 0, 3000)
+    yo, tho = yo[:, :400], tho[:, :400]
+    ev, data, psd = upload_event(b)
+    note(f"match tiles: {ttho.shape[1]} templates, {tho.shape[1]} samples, {n_cand} candidates")
+    to, mv = binding.tile_assign_match(ev, dev(tyo), dev(ttho), dev(yo), dev(tho), n_cand=n_cand)
+    to, mv = host(to), host(mv)
+    bo, mo = b.ev.tile_assign_match(ttho, tho)
+    # candidates: the n_cand nearest in whitened coordinates
+    d2 = ((yo[:, :, None] - tyo[:, None, :]) ** 2).sum(axis=0)
+    near = np.argsort(d2, axis=1, kind="stable")[:, :n_cand]
+    if n_cand == 1:
+        assert np.array_equal(to, oracle.tile_assign(tyo, yo))
+    pair = np.array([b.ev.match(tho[:, s], ttho[:, to[s]]) for s in range(tho.shape[1])])
+    np.testing.assert_allclose(mv, pair, rtol=0, atol=1e-9)
+    inside = np.array([bo[s] in near[s] for s in range(tho.shape[1])])
+    same = to == bo
+    close = np.abs(mv - mo) <= 1e-9
+    note(f"  oracle's best among the candidates for {inside.sum()} of {inside.size}; same tile for "
+         f"{same.sum()}; Fisher tile differs from the match tile for {(near[:, 0] != bo).sum()} samples")
+    assert np.all(same[inside] | close[inside])
+    ev.close()
