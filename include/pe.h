@@ -178,7 +178,8 @@ pe_status_t pe_metric(pe_event_t ev, const double *theta0_dev, const double *fd_
  * al., SC'11) with key (seed lo, seed hi) and counter (i lo, i hi, pair j,
  * stream_id), two 53-bit uniforms per block, Box-Muller. Periodic coordinates
  * are wrapped; logq is the log-density of the wrapped Gaussian (sum over the
- * images -1, 0, +1 of each periodic coordinate). logprior is the log prior
+ * images -2 .. +2 of each periodic coordinate about theta0 wrapped into
+ * [0, P)). logprior is the log prior
  * (flat in Mc, eta or q, spins, tc, ra, psi, phic; cos dec; sin iota; dL^2;
  * unnormalised) or -inf outside the support.
  *   theta0_dev: D doubles; g_dev: D*D doubles (device).

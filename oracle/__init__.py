@@ -36,7 +36,8 @@ class _Event(ctypes.Structure):
 
 
 class _Slice(ctypes.Structure):
-    _fields_ = [("centre", ctypes.c_double * 11), ("chol", ctypes.c_double * 121), ("radius", ctypes.c_double)]
+    _fields_ = [("centre", ctypes.c_double * 11), ("chol", ctypes.c_double * 121), ("radius", ctypes.c_double),
+                ("sub_mask", ctypes.c_uint)]
 
 
 class _Source(ctypes.Structure):
@@ -101,6 +102,11 @@ def lib():
         L.peo_slice_sample.restype = ctypes.c_long
         L.peo_slice_sample.argtypes = [ctypes.POINTER(_Event), _sp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_long,
                                        ctypes.c_long, _dp, _dp, _dp]
+        L.peo_slice_dims.restype = ctypes.c_int
+        L.peo_slice_dims.argtypes = [ctypes.POINTER(_Event), _sp, _ip]
+        L.peo_tile_extrinsic.restype = ctypes.c_int
+        L.peo_tile_extrinsic.argtypes = [ctypes.POINTER(_Event), _dp, _dp, ctypes.c_uint, ctypes.c_uint64,
+                                         ctypes.c_uint32, ctypes.c_long, _dp, _dp, _dp]
         L.peo_tile_bank.restype = ctypes.c_long
         L.peo_tile_bank.argtypes = [ctypes.POINTER(_Event), _sp, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                     ctypes.c_long, ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp, _dp, _lp]
@@ -284,15 +290,20 @@ class Event:
         return out, cov, int(cnt)
 
     # ---- tile-mixture proposal ----
+    def slice_dims(self, sl):
+        """Number of sliced coordinates (all of them when the slice's sub_mask is 0)."""
+        idx = (ctypes.c_int * 11)()
+        return int(lib().peo_slice_dims(self.ref, ctypes.byref(sl), idx))
+
     def slice_candidate(self, sl, seed, stream, i):
-        y = np.zeros(self.dim)
+        y = np.zeros(self.slice_dims(sl))
         th = np.zeros(self.dim)
         ok = lib().peo_slice_candidate(self.ref, ctypes.byref(sl), int(seed), int(stream), int(i), _p(y), _p(th))
         return bool(ok), y, th
 
     def slice_sample(self, sl, seed, stream, first, n):
-        """Kept candidates first..first+n-1 of the slice: (y [D, k], theta [D, k], logprior [k])."""
-        y = np.zeros((self.dim, n))
+        """Kept candidates first..first+n-1 of the slice: (y [S, k], theta [D, k], logprior [k])."""
+        y = np.zeros((self.slice_dims(sl), n))
         th = np.zeros((self.dim, n))
         lp = np.zeros(n)
         k = lib().peo_slice_sample(self.ref, ctypes.byref(sl), int(seed), int(stream), int(first), int(n), _p(y),
@@ -300,14 +311,28 @@ class Event:
         return y[:, :k].copy(), th[:, :k].copy(), lp[:k].copy()
 
     def tile_bank(self, sl, min_dist, seed, stream, batch, max_tiles, stop_fraction, max_batches):
-        """Stochastic bank: (templates y [D, m], theta [D, m], candidates consumed)."""
-        ty = np.zeros((self.dim, max_tiles))
+        """Stochastic bank: (templates y [S, m], theta [D, m], candidates consumed)."""
+        ty = np.zeros((self.slice_dims(sl), max_tiles))
         tth = np.zeros((self.dim, max_tiles))
         used = ctypes.c_long(0)
         m = lib().peo_tile_bank(self.ref, ctypes.byref(sl), float(min_dist), int(seed), int(stream), int(batch),
                                 int(max_tiles), float(stop_fraction), int(max_batches), _p(ty), _p(tth),
                                 ctypes.byref(used))
         return ty[:, :m].copy(), tth[:, :m].copy(), int(used.value)
+
+    def tile_extrinsic(self, theta0, g, sub_mask, seed, stream, theta, logq, logprior):
+        """Tile draws completed by the proposal's marginal over the coordinates outside sub_mask
+        (peo_tile_extrinsic): (rc, theta [D, n], logq [n], logprior [n]), new arrays."""
+        th0 = _f64(theta0)
+        gg = _f64(g)
+        th = np.array(theta, dtype=np.float64, order="C", copy=True)
+        lq = np.array(logq, dtype=np.float64, copy=True)
+        lp = np.array(logprior, dtype=np.float64, copy=True)
+        n = th.shape[1]
+        assert th.shape == (self.dim, n) and lq.shape == (n,) and lp.shape == (n,)
+        rc = lib().peo_tile_extrinsic(self.ref, _p(th0), _p(gg), ctypes.c_uint(int(sub_mask)), int(seed),
+                                      int(stream), int(n), _p(th), _p(lq), _p(lp))
+        return rc, th, lq, lp
 
     # ---- relative binning ----
     def relbin_edges(self, eps, max_edges=1 << 20):
@@ -387,17 +412,20 @@ def uniforms(seed, stream, n, npairs):
     return u
 
 
-def make_slice(centre, chol, radius):
-    """Slice of the prior: ball of `radius` in y = L^T (theta - centre), chol = lower L."""
+def make_slice(centre, chol, radius, sub_mask=0):
+    """Slice of the prior: ball of `radius` in y = L^T (theta_S - centre_S), chol = lower L (S x S)
+    over the coordinates in sub_mask (all when 0; the others stay at the centre)."""
     sl = _Slice()
     c = np.asarray(centre, dtype=np.float64)
     Lm = np.asarray(chol, dtype=np.float64)
-    D = c.shape[0]
-    for a in range(D):
+    S = Lm.shape[0]
+    for a in range(c.shape[0]):
         sl.centre[a] = float(c[a])
-        for b in range(D):
-            sl.chol[a * D + b] = float(Lm[a, b])
+    for a in range(S):
+        for b in range(S):
+            sl.chol[a * S + b] = float(Lm[a, b])
     sl.radius = float(radius)
+    sl.sub_mask = int(sub_mask)
     return sl
 
 

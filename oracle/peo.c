@@ -1066,6 +1066,84 @@ int peo_draw(const peo_event *ev, const double *th0, const double *g, uint64_t s
     return 0;
 }
 
+/* Extrinsic coordinates of tile draws: the coordinates outside sub_mask drawn
+ * from the proposal's marginal over them (declaration in peo.h). */
+int peo_tile_extrinsic(const peo_event *ev, const double *th0, const double *g, unsigned sub_mask, uint64_t seed,
+                       uint32_t stream, long n, double *theta, double *logq, double *logprior)
+{
+    const int D = peo_dim(ev->params);
+    double L[PEO_MAX_DIM * PEO_MAX_DIM], c0[PEO_MAX_DIM], per[3];
+    marg_prop mp;
+    int pidx[3], mm[3], marg[PEO_MAX_DIM], is_m[PEO_MAX_DIM] = {0}, np, nm = 0, k, a, rc;
+    long i;
+    np = periodic_dims(ev, pidx, per);
+    if (sub_mask == 0 || (sub_mask >> D) != 0)
+        return 1;
+    for (a = 0; a < np; a++)
+        if (sub_mask >> pidx[a] & 1u)
+            return 1;
+    /* decoupled: the tiled coordinates and the likelihood's marginalised ones */
+    k = marg_dims(ev, mm);
+    for (a = 0; a < k; a++)
+        is_m[mm[a]] = 1;
+    for (a = 0; a < D; a++)
+        if (sub_mask >> a & 1u)
+            is_m[a] = 1;
+    for (a = 0; a < D; a++)
+        if (is_m[a])
+            marg[nm++] = a;
+    wrap_centre(ev, th0, c0);
+    rc = marg_proposal(g, D, nm, marg, np, pidx, per, &mp);
+    if (!rc)
+        rc = cholesky(mp.dec_g, D, L);
+    if (rc)
+        return rc;
+    for (i = 0; i < n; i++) {
+        double z[PEO_MAX_DIM + 1], y[PEO_MAX_DIM], th[PEO_MAX_DIM];
+        int j, r, c;
+        for (j = 0; 2 * j < D; j++) {
+            double ua, ub, rad;
+            block_uniforms(seed, stream, (uint64_t)i, (uint32_t)j, &ua, &ub);
+            rad = sqrt(-2.0 * log(ua));
+            z[2 * j] = rad * cos(2.0 * PI * ub);
+            z[2 * j + 1] = rad * sin(2.0 * PI * ub);
+        }
+        for (r = D - 1; r >= 0; r--) {
+            double s = z[r];
+            for (c = r + 1; c < D; c++)
+                s -= L[c * D + r] * y[c];
+            y[r] = s / L[r * D + r];
+        }
+        for (a = 0; a < D; a++)
+            th[a] = (sub_mask >> a & 1u) ? theta[(long)a * n + i] : th0[a] + y[a];
+        for (a = 0; a < np; a++) {
+            double P = per[a], v = th[pidx[a]];
+            th[pidx[a]] = v - P * floor(v / P);
+        }
+        if (D == 11 && ev->time_marg) {
+            /* tc: its mean under the proposal given the other coordinates of the
+               composed draw, as peo_draw sets it */
+            double m = c0[9], dlt[PEO_MAX_DIM];
+            for (a = 0; a < D; a++)
+                dlt[a] = th[a] - c0[a];
+            for (a = 0; a < np; a++) {
+                const double P = per[a];
+                dlt[pidx[a]] -= P * floor(dlt[pidx[a]] / P + 0.5);
+            }
+            for (a = 0; a < D; a++)
+                if (a != 9)
+                    m -= g[9 * D + a] / g[9 * D + 9] * dlt[a];
+            th[9] = m;
+        }
+        for (a = 0; a < D; a++)
+            theta[(long)a * n + i] = th[a];
+        logq[i] += logq_marg(&mp, c0, th);
+        if (logprior[i] != -INFINITY)
+            logprior[i] = peo_logprior(ev, th);
+    }
+    return 0;
+}
+
 int peo_logq_theta(const peo_event *ev, const double *th0, const double *g, const double *theta, long n,
                    double *logq)
 {
@@ -1246,52 +1324,67 @@ static double wdist2(int D, const double *a, long sa, const double *b, long sb)
     return s;
 }
 
-/* Candidate i of the slice: y_a = R (2 u_a - 1) with u_a the (a mod 2)-th
- * uniform of Philox block (seed, stream, i, a / 2); kept if |y|^2 <= R^2 and
- * theta = c + L^-T y lies in the prior's support. Returns 1 if kept. */
+int peo_slice_dims(const peo_event *ev, const peo_slice *sl, int *idx)
+{
+    const int D = peo_dim(ev->params);
+    int a, S = 0;
+    for (a = 0; a < D; a++)
+        if (sl->sub_mask == 0 || (sl->sub_mask >> a & 1u))
+            idx[S++] = a;
+    return S;
+}
+
+/* Candidate i of the slice: y_a = R (2 u_a - 1) (a < S) with u_a the
+ * (a mod 2)-th uniform of Philox block (seed, stream, i, a / 2); kept if
+ * |y|^2 <= R^2 and theta (the centre, plus L^-T y on the sliced coordinates)
+ * lies in the prior's support. Returns 1 if kept. */
 int peo_slice_candidate(const peo_event *ev, const peo_slice *sl, uint64_t seed, uint32_t stream, uint64_t i,
                         double *y, double *theta)
 {
     const int D = peo_dim(ev->params);
     double u[PEO_MAX_DIM + 1], x[PEO_MAX_DIM], r2 = 0.0;
     peo_source src;
-    int a, r, c;
-    for (a = 0; 2 * a < D; a++)
+    int a, r, c, idx[PEO_MAX_DIM];
+    const int S = peo_slice_dims(ev, sl, idx);
+    for (a = 0; 2 * a < S; a++)
         block_uniforms(seed, stream, i, (uint32_t)a, &u[2 * a], &u[2 * a + 1]);
-    for (a = 0; a < D; a++) {
+    for (a = 0; a < S; a++) {
         y[a] = sl->radius * (2.0 * u[a] - 1.0);
         r2 += y[a] * y[a];
     }
-    /* theta - c = L^-T y: back substitution with L^T */
-    for (r = D - 1; r >= 0; r--) {
+    /* theta_S - c_S = L^-T y: back substitution with L^T */
+    for (r = S - 1; r >= 0; r--) {
         double t = y[r];
-        for (c = r + 1; c < D; c++)
-            t -= sl->chol[c * D + r] * x[c];
-        x[r] = t / sl->chol[r * D + r];
+        for (c = r + 1; c < S; c++)
+            t -= sl->chol[c * S + r] * x[c];
+        x[r] = t / sl->chol[r * S + r];
     }
     for (a = 0; a < D; a++)
-        theta[a] = sl->centre[a] + x[a];
+        theta[a] = sl->centre[a];
+    for (a = 0; a < S; a++)
+        theta[idx[a]] = sl->centre[idx[a]] + x[a];
     if (!(r2 <= sl->radius * sl->radius))
         return 0;
     return peo_source_from_theta(ev, theta, &src) ? 1 : 0;
 }
 
-/* The kept candidates among first .. first + n - 1, in order: y, theta
- * [D][n] (row stride n), logprior [n]. Returns how many were kept. */
+/* The kept candidates among first .. first + n - 1, in order: y [S][n],
+ * theta [D][n] (row stride n), logprior [n]. Returns how many were kept. */
 long peo_slice_sample(const peo_event *ev, const peo_slice *sl, uint64_t seed, uint32_t stream, long first, long n,
                       double *y, double *theta, double *logprior)
 {
     const int D = peo_dim(ev->params);
     long i, k = 0;
-    int a;
+    int a, idx[PEO_MAX_DIM];
+    const int S = peo_slice_dims(ev, sl, idx);
     for (i = 0; i < n; i++) {
         double yy[PEO_MAX_DIM], th[PEO_MAX_DIM];
         if (!peo_slice_candidate(ev, sl, seed, stream, (uint64_t)(first + i), yy, th))
             continue;
-        for (a = 0; a < D; a++) {
+        for (a = 0; a < S; a++)
             y[(long)a * n + k] = yy[a];
+        for (a = 0; a < D; a++)
             theta[(long)a * n + k] = th[a];
-        }
         logprior[k] = peo_logprior(ev, th);
         k++;
     }
@@ -1304,8 +1397,8 @@ long peo_slice_sample(const peo_event *ev, const peo_slice *sl, uint64_t seed, u
  * becomes a template when its whitened squared distance to every template so
  * far is at least min_dist^2. Stops after the first batch that adds fewer
  * than stop_fraction * (kept candidates of the batch), when max_tiles
- * templates exist, or after max_batches batches. Templates: y, theta
- * [D][max_tiles] (row stride max_tiles). Returns the number of templates;
+ * templates exist, or after max_batches batches. Templates: y [S][max_tiles],
+ * theta [D][max_tiles] (row stride max_tiles). Returns the number of templates;
  * *consumed = candidates drawn. */
 long peo_tile_bank(const peo_event *ev, const peo_slice *sl, double min_dist, uint64_t seed, uint32_t stream,
                    long batch, long max_tiles, double stop_fraction, long max_batches, double *ty, double *tth,
@@ -1314,7 +1407,8 @@ long peo_tile_bank(const peo_event *ev, const peo_slice *sl, double min_dist, ui
     const int D = peo_dim(ev->params);
     const double r2 = min_dist * min_dist;
     long m = 0, b, i;
-    int a;
+    int a, idx[PEO_MAX_DIM];
+    const int S = peo_slice_dims(ev, sl, idx);
     *consumed = 0;
     for (b = 0; b < max_batches && m < max_tiles; b++) {
         long kept = 0, added = 0;
@@ -1327,16 +1421,16 @@ long peo_tile_bank(const peo_event *ev, const peo_slice *sl, double min_dist, ui
                 continue;
             kept++;
             for (j = 0; j < m; j++)
-                if (wdist2(D, yy, 1, ty + j, max_tiles) < r2) {
+                if (wdist2(S, yy, 1, ty + j, max_tiles) < r2) {
                     ok = 0;
                     break;
                 }
             if (!ok)
                 continue;
-            for (a = 0; a < D; a++) {
+            for (a = 0; a < S; a++)
                 ty[(long)a * max_tiles + m] = yy[a];
+            for (a = 0; a < D; a++)
                 tth[(long)a * max_tiles + m] = th[a];
-            }
             m++;
             added++;
         }

@@ -154,12 +154,33 @@ void peo_weights_ess(const double *loglike, const double *logprior, const double
                      double *w, double *stats);
 
 /* Slice of the prior: the ball |y| <= radius in whitened coordinates
- * y = L^T (theta - centre), G = L L^T (chol: row-major lower L). */
+ * y = L^T (theta_S - centre_S), G = L L^T (chol: row-major lower L, S x S) over
+ * the sliced coordinates S: all D when sub_mask is 0, else those whose bit is
+ * set in sub_mask (in index order); the other coordinates stay at the centre
+ * (Sec. III tiles the intrinsic coordinates alone). */
 typedef struct {
     double centre[PEO_MAX_DIM];
     double chol[PEO_MAX_DIM * PEO_MAX_DIM];
     double radius;
+    unsigned sub_mask;
 } peo_slice;
+
+/* Number of sliced coordinates and their indices. */
+int peo_slice_dims(const peo_event *ev, const peo_slice *sl, int *idx);
+
+/* Extrinsic coordinates of tile draws (Sec. III: intrinsic and extrinsic
+ * parameters partially decouple, so the prior volume is tiled over the former
+ * and the latter are proposed apart): theta [D][n] holds draws whose
+ * coordinates in sub_mask come from the tile mixture; every other coordinate is
+ * drawn from the marginal of N(theta0, g^-1) over the coordinates outside
+ * sub_mask (and outside the likelihood's marginalised ones), with the normals
+ * of peo_draw (Philox blocks (seed, stream, i, pair)) and the metric decoupled
+ * at the sub_mask coordinates as at the marginalised ones; logq[i] gains that
+ * marginal's log density (wrapped on periodic coordinates); logprior[i]
+ * becomes the log prior of the composed draw, or stays -inf. Returns 0, or
+ * nonzero when g is not positive definite (nothing written then). */
+int peo_tile_extrinsic(const peo_event *ev, const double *theta0, const double *g, unsigned sub_mask, uint64_t seed,
+                       uint32_t stream, long n, double *theta, double *logq, double *logprior);
 
 int peo_slice_candidate(const peo_event *ev, const peo_slice *sl, uint64_t seed, uint32_t stream, uint64_t i,
                         double *y, double *theta);

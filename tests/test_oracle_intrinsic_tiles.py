@@ -1,0 +1,182 @@
+"""Pins of the oracle's tile mixture over the intrinsic coordinates of the 11-D set (Sec. III: the
+prior volume is tiled over the intrinsic parameters, which partially decouple from the extrinsic
+ones; App. A: bank, tiling of the prior volume, proposal): the sub-slice sampler against its own
+geometry, and the extrinsic completion of the tile draws against the Gaussian marginal written from
+its definition (covariance block, explicit image sum), its moments, and its independence from the
+tiled coordinates."""
+import math
+
+import numpy as np
+from scipy import optimize, stats
+from scipy.special import logsumexp
+
+import oracle
+from events import build_event
+
+INTRINSIC = 0xF  # Mc, q, chi1z, chi2z
+PERIODS = {4: 2 * math.pi, 7: math.pi, 10: 2 * math.pi}
+
+
+def _intrinsic_slice(b, radius, g=None):
+    g = b.ev.metric(b.theta_inj) if g is None else g
+    C = np.linalg.inv(g)
+    GI = np.linalg.inv(C[:4, :4])  # the proposal's marginal precision over the intrinsic coordinates
+    L = np.linalg.cholesky(GI)
+    return oracle.make_slice(b.theta_inj, L, radius, INTRINSIC), L, g
+
+
+def _wrapped_centre(th0):
+    c0 = np.array(th0, dtype=np.float64)
+    for k, P in PERIODS.items():
+        c0[k] = th0[k] - P * math.floor(th0[k] / P)
+    return c0
+
+
+def _marginal_logpdf(x, th0, g, keep):
+    """Log density of the marginal of N(th0, g^-1) over `keep`, wrapped: the covariance block and an
+    explicit sum over the images -2..2 of every periodic coordinate kept."""
+    C = np.linalg.inv(g)
+    Ck = C[np.ix_(keep, keep)]
+    c0 = _wrapped_centre(th0)[keep]
+    pk = [(j, PERIODS[k]) for j, k in enumerate(keep) if k in PERIODS]
+    terms = []
+    for img in np.ndindex(*([5] * len(pk))):
+        s = np.array(x, dtype=np.float64)[keep]
+        for (j, P), t in zip(pk, img):
+            s[j] += (t - 2) * P
+        terms.append(stats.multivariate_normal.logpdf(s, c0, Ck))
+    return logsumexp(terms)
+
+
+def test_sub_slice_candidates_follow_their_definition():
+    b = build_event(1, 0, n_bins=4000)
+    sl, L, g = _intrinsic_slice(b, 3.0)
+    assert b.ev.slice_dims(sl) == 4
+    u = oracle.uniforms(9, 3, 100, 2).reshape(100, 4)  # two Philox blocks per candidate (S = 4)
+    kept = 0
+    for i in range(100):
+        ok, y, th = b.ev.slice_candidate(sl, 9, 3, i)
+        assert np.array_equal(y, 3.0 * (2.0 * u[i] - 1.0))
+        assert np.array_equal(th[4:], b.theta_inj[4:])  # extrinsic coordinates stay at the centre
+        np.testing.assert_allclose(L.T @ (th[:4] - b.theta_inj[:4]), y, rtol=0, atol=1e-9 * 3.0)
+        src_ok = th[0] > 0 and 0 < th[1] <= 1 and abs(th[2]) <= b.chi_max and abs(th[3]) <= b.chi_max
+        assert ok == bool(y @ y <= 9.0 and src_ok)
+        kept += ok
+    assert kept > 20
+    # samples: the kept candidates in order, y with S rows, theta with all D
+    y, th, lp = b.ev.slice_sample(sl, 9, 3, 0, 100)
+    assert y.shape == (4, kept) and th.shape == (11, kept)
+    assert np.all(lp == b.ev.logprior(th[:, 0]))  # flat in the intrinsic coordinates
+
+
+def test_sub_slice_bank_packs_in_the_intrinsic_coordinates():
+    b = build_event(1, 0, n_bins=4000)
+    sl, L, g = _intrinsic_slice(b, 3.0)
+    ty, tth, used = b.ev.tile_bank(sl, 1.0, 5, 1, 2048, 5000, 0.002, 50)
+    m = ty.shape[1]
+    assert ty.shape[0] == 4 and tth.shape == (11, m) and 20 < m < 5000
+    d2 = ((ty[:, :, None] - ty[:, None, :]) ** 2).sum(0)
+    np.fill_diagonal(d2, np.inf)
+    assert d2.min() >= 1.0 - 1e-12
+    np.testing.assert_allclose(L.T @ (tth[:4] - b.theta_inj[:4, None]), ty, rtol=0, atol=1e-9 * 3.0)
+    assert np.all(tth[4:] == b.theta_inj[4:, None])
+
+
+def _intrinsic_inputs(th0, n, seed=1):
+    rng = np.random.default_rng(seed)
+    th = np.tile(np.asarray(th0, dtype=np.float64)[:, None], (1, n))
+    th[:4] += rng.normal(size=(4, n)) * np.array([1e-4, 0.05, 0.03, 0.03])[:, None]
+    return th
+
+
+def test_extrinsic_density_is_the_wrapped_marginal():
+    b = build_event(1, 0, n_bins=4000)  # explicit phase, distance and tc sampled: all 7 extrinsic drawn
+    th0 = b.theta_inj
+    g = b.ev.metric(th0)
+    n = 400
+    th = _intrinsic_inputs(th0, n)
+    lq_in = np.linspace(-3.0, 2.0, n)
+    lp_in = np.zeros(n)
+    lp_in[5] = -np.inf  # a draw without a sample keeps its -inf
+    rc, t2, lq, lp = b.ev.tile_extrinsic(th0, g, INTRINSIC, 7, 3, th, lq_in, lp_in)
+    assert rc == 0
+    assert np.array_equal(t2[:4], th[:4])
+    keep = list(range(4, 11))
+    ref = np.array([_marginal_logpdf(t2[:, i], th0, g, keep) for i in range(40)])
+    np.testing.assert_allclose(lq[:40] - lq_in[:40], ref, rtol=0, atol=1e-9)
+    assert lp[5] == -np.inf
+    lp_ref = np.array([b.ev.logprior(t2[:, i]) for i in range(n)])
+    ok = np.arange(n) != 5
+    np.testing.assert_array_equal(lp[ok], lp_ref[ok])
+    for k, P in PERIODS.items():
+        assert np.all((t2[k] >= 0) & (t2[k] < P))
+
+
+def test_extrinsic_draws_follow_the_marginal_and_ignore_the_tiled_coordinates():
+    # a narrow proposal (100 g): wrapping leaves the offsets Gaussian, so their whitened
+    # covariance under the marginal's precision is the identity
+    b = build_event(1, 0, n_bins=4000)
+    th0 = b.theta_inj
+    g = 100.0 * b.ev.metric(th0)
+    n = 20000
+    th = _intrinsic_inputs(th0, n)
+    rc, t2, lq, lp = b.ev.tile_extrinsic(th0, g, INTRINSIC, 11, 0, th, np.zeros(n), np.zeros(n))
+    assert rc == 0
+    keep = list(range(4, 11))
+    c0 = _wrapped_centre(th0)
+    off = t2[keep] - c0[keep, None]
+    for j, k in enumerate(keep):
+        if k in PERIODS:
+            P = PERIODS[k]
+            off[j] -= P * np.floor(off[j] / P + 0.5)
+    Ck = np.linalg.inv(g)[np.ix_(keep, keep)]
+    W = np.linalg.cholesky(np.linalg.inv(Ck))
+    w = W.T @ off
+    assert np.all(np.abs(w.mean(1)) < 5.0 / math.sqrt(n))
+    assert np.abs(np.cov(w) - np.eye(len(keep))).max() < 6.0 * math.sqrt(2.0 / n)
+    # the conditional covariance (the tiled coordinates held fixed) is narrower: a draw that used it
+    # would fail the check above; the extrinsic values do not depend on the tiled ones
+    th_b = th.copy()
+    th_b[:4] += 0.01
+    _, t3, lq3, _ = b.ev.tile_extrinsic(th0, g, INTRINSIC, 11, 0, th_b, np.zeros(n), np.zeros(n))
+    assert np.array_equal(t3[4:], t2[4:]) and np.array_equal(lq3, lq)
+
+
+def test_extrinsic_with_the_likelihood_marginals():
+    # time-, phase- and distance-marginalised event: only ra, dec, iota, psi enter log q; tc is the
+    # proposal's conditional mean given the composed draw
+    b = build_event(1, 0, n_bins=4000, phase=oracle.PHASE_MARG, distance=1,
+                    time_marg={"tc_lo": -0.02, "tc_hi": 0.02, "tm_points": 64})
+    th0 = b.theta_inj
+    g = b.ev.metric(th0)
+    n = 60
+    th = _intrinsic_inputs(th0, n)
+    rc, t2, lq, lp = b.ev.tile_extrinsic(th0, g, INTRINSIC, 3, 1, th, np.zeros(n), np.zeros(n))
+    assert rc == 0
+    keep = [4, 5, 6, 7]
+    ref = np.array([_marginal_logpdf(t2[:, i], th0, g, keep) for i in range(n)])
+    np.testing.assert_allclose(lq, ref, rtol=0, atol=1e-9)
+    c0 = _wrapped_centre(th0)
+    for i in range(0, n, 12):
+        x = t2[:, i].copy()
+        d = x - c0
+        for k, P in PERIODS.items():
+            d[k] -= P * math.floor(d[k] / P + 0.5)
+
+        def quad(t):
+            e = d.copy()
+            e[9] = t - c0[9]
+            return e @ g @ e
+
+        r = optimize.minimize_scalar(quad, bracket=(c0[9] - 1e-3, c0[9] + 1e-3), tol=1e-14)
+        assert abs(x[9] - r.x) < 1e-9
+
+
+def test_extrinsic_rejects_periodic_or_empty_masks():
+    b = build_event(1, 0, n_bins=2000)
+    th0 = b.theta_inj
+    g = b.ev.metric(th0)
+    th = _intrinsic_inputs(th0, 4)
+    for mask in (0, 0xF | (1 << 4), 1 << 7, 1 << 11):
+        rc, *_ = b.ev.tile_extrinsic(th0, g, mask, 1, 0, th, np.zeros(4), np.zeros(4))
+        assert rc != 0
