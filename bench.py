@@ -87,6 +87,17 @@ def parse():
     ap.add_argument("--tile-spacing", type=float, default=1.0, help="tile-mixture leg: template spacing (whitened)")
     ap.add_argument("--tile-candidates", type=int, default=4000000,
                     help="tile-mixture leg: slice candidates for the prior samples (0 skips the leg; 4-D only)")
+    ap.add_argument("--itile-radius", type=float, default=4.0,
+                    help="intrinsic tile leg (11-D): slice radius in the intrinsic marginal metric (whitened)")
+    ap.add_argument("--itile-spacing", type=float, default=1.0, help="intrinsic tile leg: template spacing")
+    ap.add_argument("--itile-round2", choices=["tiles", "refined", "moments"], default="moments",
+                    help="intrinsic tile leg, second round: the other coordinates from the metric proposal at the "
+                         "injection (tiles), at the first round's weighted centre (refined), or from the weighted "
+                         "moments of the first round (moments)")
+    ap.add_argument("--itile-time", type=int, default=1,
+                    help="intrinsic tile leg: 1 marginalises tc as well (as the time legs), 0 samples it")
+    ap.add_argument("--itile-candidates", type=int, default=4000000,
+                    help="intrinsic tile leg: slice candidates for the prior samples (0 skips the leg)")
     ap.add_argument("--no-distance-leg", action="store_true",
                     help="skip the distance-marginalised leg (11-D configurations)")
     ap.add_argument("--time-leg", type=int, default=1,
@@ -308,6 +319,15 @@ def main():
             out["time_and_phase_marginalised"] = leg
     if n_events == 1 and D == 4 and args.tile_candidates > 0:
         out["tiles"] = tile_leg(first, args, max(args.steps, 1), prec)
+    if n_events == 1 and D == 11 and args.itile_candidates > 0:
+        # tc marginalised as in the time legs (nodes half the envelope's width apart over 20 ms), or sampled
+        gh = first["g"].cpu().numpy()
+        g_tt = gh[9, 9] - gh[9, 10] ** 2 / gh[10, 10]
+        lo, hi = first["theta_inj"][9] - 0.01, first["theta_inj"][9] + 0.01
+        tm = {"tc_lo": float(lo), "tc_hi": float(hi),
+              "tm_points": int(math.ceil((hi - lo) / (0.5 / math.sqrt(g_tt)))) + 1}
+        out["intrinsic_tiles"] = intrinsic_tile_leg(first, args, max(args.steps // 4, 2), prec,
+                                                    time_marg=tm if args.itile_time else None)
     for x in evs:
         x["ev"].close()
 
@@ -692,6 +712,118 @@ def tile_leg(x, args, steps, prec):
                         "assign_ms": 1e3 * (t7 - t6), "share_reassigned": moved,
                         "mean_match": float(mv.mean()), "ess_per_event_mean": float(s3[:, 0].mean()),
                         "ess_per_event_min": float(s3[:, 0].min()), "ess_per_event_max": float(s3[:, 0].max())},
+    }
+
+
+def intrinsic_tile_leg(x, args, steps, prec, time_marg=None):
+    """Tile mixture over the intrinsic coordinates of the 11-D set (Sec. III: the intrinsic parameters
+    are tiled, the extrinsic ones partially decouple): the likelihood marginalised over the phase and
+    the distance (and the coalescence time with time_marg), a bank and prior samples in the ball of
+    the proposal's marginal metric over (Mc, q, chi1z, chi2z) about the injection, nearest-template
+    tiles; each step evaluates the templates (extrinsic coordinates at the injection), draws N
+    intrinsic points from the tiles and their remaining coordinates from the metric proposal's
+    marginal over them, evaluates and weights them; then a second round from the reweighted tiles.
+    The injection-centred Gaussian on the same event is timed beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2410_05190_amd import binding
+    common = dict(x["common"])
+    common["phase"] = binding.PE_PHASE_MARG
+    if time_marg:
+        common.update(time_marg=1, **time_marg)
+    ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], distance=binding.PE_DIST_MARG, **common)
+    N = x["N"]
+    h_ = ev.handle
+    th0 = x["theta0"]
+    g = ev.metric(th0)
+    gh = g.cpu().numpy()
+    GI = np.linalg.inv(np.linalg.inv(gh)[:4, :4])
+    sl = binding.make_slice(x["theta_inj"], np.linalg.cholesky(GI), args.itile_radius, 0xF)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ty, tth, used = ev.tile_bank(sl, args.itile_spacing, x["seed"], 1, 4096, 200000, 0.002, 2000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    y, th, lp = ev.slice_sample(sl, x["seed"], 2, 0, args.itile_candidates)
+    to = binding.tile_assign(ty, y)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tth = tth.contiguous()
+    M = tth.shape[1]
+    ev.reserve(max(M, N))
+    llt = torch.empty(M, dtype=torch.float64, device="cuda")
+    ll = torch.empty(N, dtype=torch.float64, device="cuda")
+    w = torch.empty(N, dtype=torch.float64, device="cuda")
+    st = torch.empty((steps, 4), dtype=torch.float64, device="cuda")
+    st2 = torch.empty((steps, 4), dtype=torch.float64, device="cuda")
+    c2b = torch.empty(11, dtype=torch.float64, device="cuda")
+    cov = torch.empty((11, 11), dtype=torch.float64, device="cuda")
+    g2b = torch.empty((11, 11), dtype=torch.float64, device="cuda")
+    ext = [4, 5, 6, 7] + ([] if time_marg else [9])  # the coordinates drawn besides the tiles
+    print(f"intrinsic tiles: {M} templates, {y.shape[1]} samples", file=sys.stderr, flush=True)
+    for i in range(-1, steps):  # step -1: untimed warm-up
+        if i == 0:
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+        binding.pe_loglike_batch(h_, tth, M, prec, llt, None)
+        thd, lq, lpd, idx = binding.tile_draw(llt, to, lp, th, x["seed"] + 7, 2 * max(i, 0), N)
+        binding.pe_tile_extrinsic(h_, th0, g, 0xF, x["seed"] + 8, 2 * max(i, 0), N, thd, lq, lpd)
+        binding.pe_loglike_batch(h_, thd, N, prec, ll, None)
+        binding.pe_weights_ess(ll, lpd, lq, N, w, st[max(i, 0)])
+        # second round from the tiles reweighted by the first round's weights; the other coordinates
+        # from the metric proposal as before, or about the first round's weighted centre: with the metric
+        # there (refined) or with the weighted covariance of those coordinates (moments)
+        ell = binding.tile_reweight(llt, to, lp, idx, w, 0.1)
+        c2, g2 = th0, g
+        if args.itile_round2 != "tiles":
+            binding.pe_proposal_update(h_, thd, w, N, th0, c2b, cov)
+            c2 = c2b
+            if args.itile_round2 == "refined":
+                binding.pe_metric(h_, c2b, None, 0, g2b)
+            else:
+                ch = cov.cpu().numpy()
+                gm = np.eye(11)
+                gm[np.ix_(ext, ext)] = np.linalg.inv(ch[np.ix_(ext, ext)])
+                g2b.copy_(torch.from_numpy(gm))
+            g2 = g2b
+        thd, lq, lpd, idx = binding.tile_draw(ell, to, lp, th, x["seed"] + 7, 2 * max(i, 0) + 1, N)
+        binding.pe_tile_extrinsic(h_, c2, g2, 0xF, x["seed"] + 8, 2 * max(i, 0) + 1, N, thd, lq, lpd)
+        binding.pe_loglike_batch(h_, thd, N, prec, ll, None)
+        binding.pe_weights_ess(ll, lpd, lq, N, w, st2[max(i, 0)])
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    # the injection-centred Gaussian on the same event
+    stg = torch.empty((steps, 4), dtype=torch.float64, device="cuda")
+    for i in range(-1, steps):
+        if i == 0:
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+        binding.pe_draw(h_, th0, g, x["seed"] + 9, max(i, 0), N, x["theta"], x["lq"], x["lp"])
+        binding.pe_loglike_batch(h_, x["theta"], N, prec, ll, None)
+        binding.pe_weights_ess(ll, x["lp"], x["lq"], N, w, stg[max(i, 0)])
+    torch.cuda.synchronize()
+    td = time.perf_counter()
+    ev.status()
+    ev.close()
+    s, s2, sg = st.cpu().numpy(), st2.cpu().numpy(), stg.cpu().numpy()
+    t_step = (tb - ta) / steps
+    t_g = (td - tc) / steps
+    e1, e2, eg = float(s[:, 0].mean()), float(s2[:, 0].mean()), float(sg[:, 0].mean())
+    return {
+        "kind": ("tile mixture over (Mc, q, chi1z, chi2z), the other coordinates from the metric proposal's "
+                 "marginal; likelihood marginalised over phase and distance" + (" and tc" if time_marg else "")),
+        "slice_radius": args.itile_radius, "spacing": args.itile_spacing, "templates": M, "bank_candidates": used,
+        "prior_samples": int(y.shape[1]), "bank_ms": 1e3 * (t1 - t0), "samples_and_assign_ms": 1e3 * (t2 - t1),
+        "steps": steps, "draws_per_round": N, "ms_per_step_two_rounds": 1e3 * t_step,
+        "round1": {"ess_per_event_mean": e1, "efficiency": e1 / N, "ess_per_event_min": float(s[:, 0].min()),
+                   "ess_per_event_max": float(s[:, 0].max())},
+        "round2_reweighted": {"extrinsic": args.itile_round2, "ess_per_event_mean": e2, "efficiency": e2 / N,
+                              "ess_per_event_min": float(s2[:, 0].min()),
+                              "ess_per_event_max": float(s2[:, 0].max())},
+        "ess_per_s": (e1 + e2) / t_step,
+        "gaussian_same_event": {"ms_per_step": 1e3 * t_g, "ess_per_event_mean": eg, "efficiency": eg / N,
+                                "ess_per_s": eg / t_g},
     }
 
 

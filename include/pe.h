@@ -375,24 +375,30 @@ pe_status_t pe_refine(pe_event_t ev, double *theta0_dev, double *g_dev, int32_t 
  * tiles in proportion to that volume times the posterior at the template;
  * App. A: template bank, tiling of the prior volume, proposal). Built on the
  * slice of the prior that a detection points to: the ball |y| <= radius in
- * the whitened coordinates y = L^T (theta - centre) of a metric G = L L^T.
- * Bank and assignment work in y, where the metric distance is Euclidean.
+ * the whitened coordinates y = L^T (theta_S - centre_S) of a metric G = L L^T
+ * over the sliced coordinates S. Bank and assignment work in y, where the
+ * metric distance is Euclidean. S is every coordinate (sub_mask 0) or, for
+ * 11-D events, the four coordinates whose bits are set in sub_mask, in index
+ * order (Sec. III tiles the intrinsic parameters, e.g. 0xF = Mc, q, chi1z,
+ * chi2z; the others stay at the centre and pe_tile_extrinsic draws them).
  */
 typedef struct {
     double centre[PE_MAX_DIM];              /* first D entries used */
-    double chol[PE_MAX_DIM * PE_MAX_DIM];   /* L, lower triangular, D x D row-major in the first D*D entries */
+    double chol[PE_MAX_DIM * PE_MAX_DIM];   /* L, lower triangular, S x S row-major in the first S*S entries */
     double radius;
+    uint32_t sub_mask;                      /* 0: all D coordinates; else 4 bits below bit 11 (11-D only) */
 } pe_slice_t;
 
 /*
  * Samples of the slice: candidate i (first .. first + n - 1) has
- * y_a = radius (2 u_a - 1), u_a the (a mod 2)-th uniform of Philox block
- * (seed, stream_id, i, a / 2) (as pe_draw's generator); it is kept when
- * |y|^2 <= radius^2 and theta = centre + L^-T y lies in the prior's support.
- * Kept candidates are written in candidate order: y_dev, theta_dev [D][n]
- * (row stride n), logprior_dev [n] (the event's log prior); their number goes
- * to count_dev[0] (int64, device). The arithmetic of a candidate is done
- * without contractions, so it is the same bit for bit on every run.
+ * y_a = radius (2 u_a - 1) (a < S), u_a the (a mod 2)-th uniform of Philox
+ * block (seed, stream_id, i, a / 2) (as pe_draw's generator); it is kept when
+ * |y|^2 <= radius^2 and theta (the centre, plus L^-T y on the sliced
+ * coordinates) lies in the prior's support. Kept candidates are written in
+ * candidate order: y_dev [S][n], theta_dev [D][n] (row stride n),
+ * logprior_dev [n] (the event's log prior); their number goes to count_dev[0]
+ * (int64, device). The arithmetic of a candidate is done without
+ * contractions, so it is the same bit for bit on every run.
  * Errors: PE_ERR_ARG, PE_ERR_OOM, PE_ERR_HIP.
  */
 pe_status_t pe_slice_sample(pe_event_t ev, const pe_slice_t *slice, uint64_t seed, uint32_t stream_id, int64_t first,
@@ -406,8 +412,9 @@ pe_status_t pe_slice_sample(pe_event_t ev, const pe_slice_t *slice, uint64_t see
  * template when |y - y_t|^2 >= min_dist^2 for every template t so far. Stops
  * after the first batch that adds fewer than stop_fraction times its kept
  * candidates, at max_tiles templates, or after max_batches batches.
- * Templates: tiles_y_dev, tiles_theta_dev [D][max_tiles] (row stride
- * max_tiles); *n_tiles and *consumed (candidates drawn) are host outputs.
+ * Templates: tiles_y_dev [S][max_tiles], tiles_theta_dev [D][max_tiles] (row
+ * stride max_tiles); *n_tiles and *consumed (candidates drawn) are host
+ * outputs.
  * Synchronises the stream (the acceptance runs batch by batch).
  */
 pe_status_t pe_tile_bank(pe_event_t ev, const pe_slice_t *slice, double min_dist, uint64_t seed, uint32_t stream_id,
@@ -465,6 +472,35 @@ pe_status_t pe_tile_draw(int32_t n_tiles, const double *tile_loglike_dev, int64_
                          const int32_t *tile_of_dev, const double *sample_logprior_dev, int32_t dim,
                          const double *samples_theta_dev, int64_t ld, uint64_t seed, uint32_t stream_id, int64_t n,
                          double *theta_dev, double *logq_dev, double *logprior_dev, int64_t *index_dev, void *stream);
+
+/*
+ * Extrinsic coordinates of tile draws (Sec. III: intrinsic and extrinsic
+ * parameters partially decouple, so the prior volume is tiled over the
+ * intrinsic ones and the others are proposed apart). theta_dev [D][n] holds
+ * draws whose coordinates in sub_mask come from pe_tile_draw on a slice with
+ * that sub_mask; every other coordinate is replaced by a draw from the
+ * marginal of N(theta0, g^-1) over the coordinates outside sub_mask: the
+ * normals of pe_draw (Philox blocks (seed, stream_id, i, pair)), g decoupled
+ * at the sub_mask coordinates by the Schur complement as pe_draw decouples the
+ * likelihood's marginalised ones (which it treats as pe_draw does: dL of
+ * PE_DIST_MARG events and phic of 11-D phase-marginalised events left out of
+ * log q, tc of time-marginalised events set to its conditional mean given the
+ * composed draw). Then
+ *   logq_dev[i] += the log density of that marginal (wrapped Gaussian, images
+ *                  -2 .. +2 of each periodic coordinate), so that it holds the
+ *                  composed proposal's log density;
+ *   logprior_dev[i] = the log prior of the composed draw, or stays -inf where
+ *                  it was (draws without a sample).
+ *   theta0_dev [D], g_dev [D*D] (device): the metric proposal whose marginal
+ *   is taken. sub_mask: nonzero, bits below 11, none of the periodic
+ *   coordinates ra, psi, phic (bits 4, 7, 10). 11-D events only.
+ * If g is not positive definite every draw gets logprior -inf (theta and logq
+ * as they were) and pe_event_status reports PE_ERR_SINGULAR.
+ * Errors: PE_ERR_ARG, PE_ERR_HIP.
+ */
+pe_status_t pe_tile_extrinsic(pe_event_t ev, const double *theta0_dev, const double *g_dev, uint32_t sub_mask,
+                              uint64_t seed, uint32_t stream_id, int64_t n, double *theta_dev, double *logq_dev,
+                              double *logprior_dev, void *stream);
 
 /*
  * Tile values for the next round (the iterative update of the proposal that

@@ -34,7 +34,7 @@ MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
            "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_weights_ess_noalloc", "pe_proposal_update", "pe_refine", "pe_slice_sample", "pe_tile_bank",
-           "pe_tile_assign", "pe_tile_assign_match", "pe_tile_draw", "pe_tile_reweight", "pe_relbin_setup", "pe_relbin_edges",
+           "pe_tile_assign", "pe_tile_assign_match", "pe_tile_draw", "pe_tile_extrinsic", "pe_tile_reweight", "pe_relbin_setup", "pe_relbin_edges",
            "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
            "pe_autotune_plan", "pe_set_split_guard", "pe_get_split_guard", "pe_loglike_counts", "pe_last_error",
@@ -59,22 +59,32 @@ class EventDesc(ctypes.Structure):
 
 
 class Slice(ctypes.Structure):
-    """pe_slice_t: ball of `radius` in y = L^T (theta - centre)."""
-    _fields_ = [("centre", ctypes.c_double * 11), ("chol", ctypes.c_double * 121), ("radius", ctypes.c_double)]
+    """pe_slice_t: ball of `radius` in y = L^T (theta_S - centre_S) over the coordinates of sub_mask
+    (all of them when 0)."""
+    _fields_ = [("centre", ctypes.c_double * 11), ("chol", ctypes.c_double * 121), ("radius", ctypes.c_double),
+                ("sub_mask", ctypes.c_uint32)]
 
 
-def make_slice(centre, chol, radius):
+def make_slice(centre, chol, radius, sub_mask=0):
+    """chol: lower factor L (S x S) of the metric over the sliced coordinates."""
     import numpy as np
     sl = Slice()
     c = np.asarray(centre, dtype=np.float64)
     Lm = np.asarray(chol, dtype=np.float64)
-    D = c.shape[0]
-    for a in range(D):
+    S = Lm.shape[0]
+    for a in range(c.shape[0]):
         sl.centre[a] = float(c[a])
-        for b in range(D):
-            sl.chol[a * D + b] = float(Lm[a, b])
+    for a in range(S):
+        for b in range(S):
+            sl.chol[a * S + b] = float(Lm[a, b])
     sl.radius = float(radius)
+    sl.sub_mask = int(sub_mask)
     return sl
+
+
+def slice_dims(dim, slice_):
+    """Number of sliced coordinates of a slice on an event of `dim` coordinates."""
+    return dim if slice_.sub_mask == 0 else bin(int(slice_.sub_mask)).count("1")
 
 
 _lib = None
@@ -139,6 +149,7 @@ def load(path=LIB_PATH):
         "pe_event_destroy": (i32, [vp]),
         "pe_metric": (i32, [vp, dp, dp, i32, dp, vp]),
         "pe_draw": (i32, [vp, dp, dp, u64, u32, i64, dp, dp, dp, vp]),
+        "pe_tile_extrinsic": (i32, [vp, dp, dp, u32, u64, u32, i64, dp, dp, dp, vp]),
         "pe_loglike_batch": (i32, [vp, dp, i64, i32, dp, dp, vp]),
         "pe_loglike_multi": (i32, [i32, vp, vp, vp, i32, vp, vp, vp]),
         "pe_batch_run": (i32, [i32, vp, i32, i32, vp]),
@@ -290,6 +301,15 @@ def pe_draw(ev, theta0, g, seed, stream_id, n, theta, logq, logprior, stream=Non
     _check(_lib.pe_draw(ev, _ptr(theta0, f64, "theta0"), _ptr(g, f64, "g"), int(seed) & 0xFFFFFFFFFFFFFFFF,
                         int(stream_id) & 0xFFFFFFFF, int(n), _ptr(theta, f64, "theta"), _ptr(logq, f64, "logq"),
                         _ptr(logprior, f64, "logprior"), _stream(stream)))
+
+
+def pe_tile_extrinsic(ev, theta0, g, sub_mask, seed, stream_id, n, theta, logq, logprior, stream=None):
+    import torch
+    f64 = torch.float64
+    _check(load().pe_tile_extrinsic(ev, _ptr(theta0, f64, "theta0"), _ptr(g, f64, "g"), int(sub_mask) & 0xFFFFFFFF,
+                                    int(seed) & 0xFFFFFFFFFFFFFFFF, int(stream_id) & 0xFFFFFFFF, int(n),
+                                    _ptr(theta, f64, "theta"), _ptr(logq, f64, "logq"),
+                                    _ptr(logprior, f64, "logprior"), _stream(stream)))
 
 
 def pe_loglike_batch(ev, theta, n, precision, loglike, aux=None, stream=None):
@@ -552,10 +572,10 @@ class Event:
         return t0, g, st
 
     def slice_sample(self, slice_, seed, stream_id, first, n, stream=None):
-        """pe_slice_sample: (y [D, k], theta [D, k], logprior [k]) of the kept candidates (synchronises)."""
+        """pe_slice_sample: (y [S, k], theta [D, k], logprior [k]) of the kept candidates (synchronises)."""
         import torch
         f64 = dict(dtype=torch.float64, device="cuda")
-        y = torch.empty((self.dim, n), **f64)
+        y = torch.empty((slice_dims(self.dim, slice_), n), **f64)
         th = torch.empty((self.dim, n), **f64)
         lp = torch.empty(n, **f64)
         cnt = torch.empty(1, dtype=torch.int64, device="cuda")
@@ -564,10 +584,10 @@ class Event:
         return y[:, :k], th[:, :k], lp[:k]
 
     def tile_bank(self, slice_, min_dist, seed, stream_id, batch, max_tiles, stop_fraction, max_batches, stream=None):
-        """pe_tile_bank: (templates y [D, m], theta [D, m], candidates consumed)."""
+        """pe_tile_bank: (templates y [S, m], theta [D, m], candidates consumed)."""
         import torch
         f64 = dict(dtype=torch.float64, device="cuda")
-        ty = torch.empty((self.dim, max_tiles), **f64)
+        ty = torch.empty((slice_dims(self.dim, slice_), max_tiles), **f64)
         tth = torch.empty((self.dim, max_tiles), **f64)
         m, used = pe_tile_bank(self.handle, slice_, min_dist, seed, stream_id, batch, max_tiles, stop_fraction,
                                max_batches, ty, tth, stream)
@@ -660,6 +680,17 @@ def tile_draw(tile_loglike, tile_of, sample_logprior, samples_theta, seed, strea
                                _ptr(lq, torch.float64, "logq"), _ptr(lp, torch.float64, "logprior"),
                                _ptr(idx, torch.int64, "index"), _stream(stream)))
     return th, lq, lp, idx
+
+
+def tile_extrinsic(ev, theta0, g, sub_mask, theta, logq, logprior, seed, stream_id, stream=None):
+    """pe_tile_extrinsic on copies: (theta [D, n], logq, logprior) of the composed draws (the
+    coordinates outside sub_mask drawn from the proposal's marginal over them)."""
+    th = theta.contiguous().clone()
+    lq = logq.clone()
+    lp = logprior.clone()
+    n = th.shape[1]
+    pe_tile_extrinsic(ev.handle, theta0, g, sub_mask, seed, stream_id, n, th, lq, lp, stream)
+    return th, lq, lp
 
 
 def tile_reweight(tile_loglike, tile_of, sample_logprior, index, w, alpha, stream=None):

@@ -558,7 +558,7 @@ DrawArg draw_arg(const pe_event_s* ev, const double* theta0, const double* g, ui
     return a;
 }
 
-pe_status_t run_draw(const std::vector<DrawArg>& v, hipStream_t st) {
+pe_status_t run_draw(const std::vector<DrawArg>& v, hipStream_t st, bool ext) {
     const int ne = (int)v.size();
     if (ne == 0) return PE_OK;
     std::vector<int64_t> off(ne + 1, 0);
@@ -568,7 +568,7 @@ pe_status_t run_draw(const std::vector<DrawArg>& v, hipStream_t st) {
     BatchPtrs b;
     pe_status_t s = upload_area(A, ne, off[ne], 0, v.data(), sizeof(DrawArg) * ne, off, nullptr, 0, st, b);
     if (s != PE_OK) return s;
-    PE_HIP(launch_draw_batch(b, ne, off[ne], st));
+    PE_HIP(launch_draw_batch(b, ne, off[ne], st, ext));
     return PE_OK;
 }
 
@@ -924,6 +924,24 @@ pe_status_t pe_draw(pe_event_t ev, const double* theta0_dev, const double* g_dev
     return run_draw(std::vector<DrawArg>(1, draw_arg(ev, theta0_dev, g_dev, seed, stream_id, n, theta_dev, logq_dev,
                                                      logprior_dev)),
                     as_stream(stream));
+}
+
+pe_status_t pe_tile_extrinsic(pe_event_t ev, const double* theta0_dev, const double* g_dev, uint32_t sub_mask,
+                              uint64_t seed, uint32_t stream_id, int64_t n, double* theta_dev, double* logq_dev,
+                              double* logprior_dev, void* stream) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (ev->ec.dim != 11) return fail(PE_ERR_ARG, "the extrinsic completion takes an 11-D event");
+    constexpr uint32_t periodic = (1u << 4) | (1u << 7) | (1u << 10);
+    if (sub_mask == 0 || (sub_mask >> 11) != 0 || (sub_mask & periodic) != 0)
+        return fail(PE_ERR_ARG, "sub_mask must be nonzero, below bit 11 and without ra, psi, phic");
+    pe_status_t s = check_n(n);
+    if (s != PE_OK) return s;
+    if (!theta0_dev || !g_dev) return fail(PE_ERR_ARG, "theta0 and g must be device pointers");
+    if (n > 0 && (!theta_dev || !logq_dev || !logprior_dev)) return fail(PE_ERR_ARG, "draw arrays are NULL");
+    if (n == 0) return PE_OK;
+    DrawArg a = draw_arg(ev, theta0_dev, g_dev, seed, stream_id, n, theta_dev, logq_dev, logprior_dev);
+    a.dmask = sub_mask;
+    return run_draw(std::vector<DrawArg>(1, a), as_stream(stream), true);
 }
 
 pe_status_t pe_loglike_batch(pe_event_t ev, const double* theta_dev, int64_t n, int32_t precision,

@@ -126,7 +126,7 @@ pe_status_t ensure_moments(pe_event_s* ev, int64_t n);
 // Stage runners: upload the records to the stream's area and queue the launches.
 pe_status_t run_prep(const std::vector<PrepArg>& v, hipStream_t st);
 pe_status_t run_metric(const std::vector<MetricArg>& v, hipStream_t st);
-pe_status_t run_draw(const std::vector<DrawArg>& v, hipStream_t st);
+pe_status_t run_draw(const std::vector<DrawArg>& v, hipStream_t st, bool ext = false);
 pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t st);
 pe_status_t run_weights(const std::vector<WeightArg>& v, hipStream_t st);
 pe_status_t run_update(const std::vector<UpdateArg>& v, hipStream_t st);

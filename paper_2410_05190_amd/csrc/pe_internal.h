@@ -134,13 +134,15 @@ struct MetricArg {
     int flags, pad;
 };
 
+// dmask: coordinates decoupled besides the likelihood's marginalised ones
+// (the tiled coordinates of an extrinsic completion; 0 for plain draws).
 struct DrawArg {
     EvConst ec;
     const double *theta0, *g;
     double *chol;
     int *status;
     uint64_t seed;
-    uint32_t stream_id, pad;
+    uint32_t stream_id, dmask;
     int64_t n;
     double *theta, *logq, *logprior;
 };
@@ -360,7 +362,7 @@ struct BatchPtrs {
 hipError_t launch_prep_batch(const BatchPtrs &b, int ne, int64_t total_blocks, int data_f32, int psd_f32,
                              hipStream_t st);
 hipError_t launch_metric_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
-hipError_t launch_draw_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
+hipError_t launch_draw_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st, bool ext = false);
 // any_dist: some event of the batch is distance-marginalised (adds k_b_dist).
 hipError_t launch_loglike_batch(const BatchPtrs &b, int ne, int64_t prologue_blocks, int64_t finalize_blocks,
                                 int precision, bool profile, bool any_dist, hipStream_t st);

@@ -655,21 +655,23 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
         }
     // coordinates the likelihood does not use: dL (index 8) of a
     // distance-marginalised likelihood, phic (index 10) of an 11-D
-    // phase-marginalised one. Each is decoupled by the Schur complement of its
-    // row and column (its diagonal kept); the other coordinates' distribution
-    // is unchanged and the drawn value is never used
+    // phase-marginalised one; and those of dmask (tiled coordinates whose
+    // values come from elsewhere). Each is decoupled by the Schur complement of
+    // its row and column (its diagonal kept), in index order; the other
+    // coordinates' distribution is unchanged and the drawn value is never used
     const bool dist = (D == 11) && A.ec.dist;
     const bool pmarg = (D == 11) && A.ec.phase == PE_PHASE_MARG;
     const bool tmarg = (D == 11) && A.ec.tm;
+    const uint32_t dmask = (D == 11) ? A.dmask : 0u;
     if constexpr (D == 11) {
         // time-marginalised likelihood: tc is not drawn but set to its mean
         // given the other coordinates, from g_{tc,j} / g_{tc,tc} of g as given
 #pragma unroll
         for (int j = 0; j < D; ++j) A.chol[kCholTm + j] = (tmarg && j != 9 && g[9][9] > 0.0) ? g[9][j] / g[9][9] : 0.0;
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const int il = m == 0 ? 8 : (m == 1 ? 9 : 10);
-            if (!(m == 0 ? dist : (m == 1 ? tmarg : pmarg))) continue;
+        for (int il = 0; il < D; ++il) {
+            const bool dec = ((dmask >> il) & 1u) || (il == 8 && dist) || (il == 9 && tmarg) || (il == 10 && pmarg);
+            if (!dec) continue;
             const double gll = g[il][il];
             ok = ok && gll > 0.0;
             double cl[D];
@@ -706,7 +708,8 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
     if (ok)
 #pragma unroll
         for (int a = 0; a < D; ++a)
-            if (!(dist && a == 8) && !(tmarg && a == 9) && !(pmarg && a == 10)) logdet += log(L[a][a]);
+            if (!(dist && a == 8) && !(tmarg && a == 9) && !(pmarg && a == 10) && !((dmask >> a) & 1u))
+                logdet += log(L[a][a]);
     A.chol[kCholLogdet] = logdet;
     A.chol[kCholOk] = ok ? 1.0 : 0.0;
 #pragma unroll
@@ -744,17 +747,24 @@ __global__ __launch_bounds__(64) void k_cholesky(const BatchHdr* __restrict__ hd
 // wrapped Gaussian (images -2..2 of each periodic coordinate about theta0
 // wrapped into [0, P), summed with a running maximum), log prior. L
 // (row-major), its log det and the success flag are in LDS (lc).
-template <int D>
+//
+// Ext (extrinsic completion of tile draws): the coordinates of A.dmask keep the
+// values theta holds on entry, log q is added to the entry's value, and the log
+// prior stays -inf where it was.
+template <int D, bool Ext = false>
 __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int64_t i) {
     const EvConst& ev = A.ec;
     const int64_t n = A.n;
+    const uint32_t dmask = Ext ? A.dmask : 0u;
     double th0[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) th0[a] = A.theta0[a];
     if (lc[kCholOk] == 0.0) {
+        if (!Ext) {
 #pragma unroll
-        for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th0[a];
-        A.logq[i] = 0.0;
+            for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th0[a];
+            A.logq[i] = 0.0;
+        }
         A.logprior[i] = -INFINITY;
         return;
     }
@@ -779,7 +789,7 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
     }
     double th[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) th[a] = th0[a] + y[a];
+    for (int a = 0; a < D; ++a) th[a] = ((dmask >> a) & 1u) ? A.theta[(int64_t)a * n + i] : th0[a] + y[a];
     constexpr int NP = (D == 4) ? 0 : 3;
     constexpr int pidx[3] = {4, 7, 10};
     const double per[3] = {kTwoPi, kPi, kTwoPi};
@@ -824,7 +834,8 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
     double zz = 0.0;
 #pragma unroll
     for (int r = 0; r < D; ++r)
-        if (!(dist && r == 8) && !(tmarg && r == 9) && !(pmarg && r == 10)) zz = fma(z[r], z[r], zz);
+        if (!(dist && r == 8) && !(tmarg && r == 9) && !(pmarg && r == 10) && !((dmask >> r) & 1u))
+            zz = fma(z[r], z[r], zz);
     double a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int p = 0; p < NP; ++p)
@@ -925,9 +936,16 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
             acc += exp(l - mx);
         }
     }
-    const int dkeep = D - (dist ? 1 : 0) - (tmarg ? 1 : 0) - (pmarg ? 1 : 0);
-    A.logq[i] = mx + log(acc) + lc[kCholLogdet] - 0.5 * dkeep * log(kTwoPi);
-    A.logprior[i] = log_prior_of(ev, th);
+    const uint32_t margm = (dist ? 1u << 8 : 0u) | (tmarg ? 1u << 9 : 0u) | (pmarg ? 1u << 10 : 0u);
+    const int dkeep = D - __builtin_popcount(margm | dmask);
+    const double lq = mx + log(acc) + lc[kCholLogdet] - 0.5 * dkeep * log(kTwoPi);
+    if (Ext) {
+        A.logq[i] += lq;
+        if (A.logprior[i] != -INFINITY) A.logprior[i] = log_prior_of(ev, th);
+    } else {
+        A.logq[i] = lq;
+        A.logprior[i] = log_prior_of(ev, th);
+    }
 }
 
 // Blocks of 256 draws that each belong to one event (doff: block offsets).
@@ -954,11 +972,31 @@ __global__ __launch_bounds__(256, 3) void k_draw(const BatchHdr* __restrict__ hd
     }
 }
 
-hipError_t launch_draw_batch(const BatchPtrs& b, int ne, int64_t total_blocks, hipStream_t st) {
+// The extrinsic completion of tile draws (11-D events, draw_one<11, true>).
+__global__ __launch_bounds__(256, 3) void k_draw_ext(const BatchHdr* __restrict__ hdr,
+                                                  const DrawArg* __restrict__ args, const int64_t* __restrict__ doff) {
+    __shared__ double lc[kCholLen];
+    const int ne = hdr->ne;
+    const int64_t nblk = doff[ne];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int e = find_slot(doff, ne, b);
+        const DrawArg& A = args[e];
+        __syncthreads();
+        for (int q = threadIdx.x; q < kCholLen; q += 256) lc[q] = A.chol[q];
+        __syncthreads();
+        const int64_t i = (b - doff[e]) * 256 + threadIdx.x;
+        if (i < A.n && A.ec.dim == 11) draw_one<11, true>(A, lc, i);
+    }
+}
+
+hipError_t launch_draw_batch(const BatchPtrs& b, int ne, int64_t total_blocks, hipStream_t st, bool ext) {
     if (ne <= 0) return hipSuccess;
     const DrawArg* args = (const DrawArg*)b.args;
     k_cholesky<<<stride_grid(ne, 64), 64, 0, st>>>(b.hdr, args);
-    k_draw<<<stride_grid(total_blocks, 1), 256, 0, st>>>(b.hdr, args, b.off);
+    if (ext)
+        k_draw_ext<<<stride_grid(total_blocks, 1), 256, 0, st>>>(b.hdr, args, b.off);
+    else
+        k_draw<<<stride_grid(total_blocks, 1), 256, 0, st>>>(b.hdr, args, b.off);
     return hipGetLastError();
 }
 

@@ -34,10 +34,13 @@
 namespace pe {
 namespace {
 
+// idx: the S sliced coordinates in index order (all D without a sub_mask);
+// L is S x S.
 struct Slice {
     double c[PE_MAX_DIM];
     double L[PE_MAX_DIM * PE_MAX_DIM];
     double R;
+    int idx[PE_MAX_DIM];
 };
 
 // |a - b|^2 summed in index order, no contractions (host and device).
@@ -57,44 +60,55 @@ __host__ double wdist2_rt(int D, const double* a, int64_t sa, const double* b, i
     return D == 4 ? wdist2<4>(a, sa, b, sb) : wdist2<11>(a, sa, b, sb);
 }
 
-// Candidate i of the slice: y, theta; 1 if kept.
-template <int D>
+// Candidate i of the slice: y (S sliced coordinates), theta (all D); 1 if kept.
+template <int S, int D>
 __device__ __forceinline__ int slice_candidate(const EvConst& ev, const Slice& sl, uint64_t seed, uint32_t st,
-                                               uint64_t i, double (&y)[D], double (&th)[D]) {
+                                               uint64_t i, double (&y)[S], double (&th)[D]) {
 #pragma clang fp contract(off)
-    double u[D + 1];
+    double u[S + 1];
 #pragma unroll
-    for (int a = 0; 2 * a < D; ++a) block_uniforms(seed, st, i, (uint32_t)a, u[2 * a], u[2 * a + 1]);
+    for (int a = 0; 2 * a < S; ++a) block_uniforms(seed, st, i, (uint32_t)a, u[2 * a], u[2 * a + 1]);
     double r2 = 0.0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
+    for (int a = 0; a < S; ++a) {
         y[a] = sl.R * (2.0 * u[a] - 1.0);
         r2 += y[a] * y[a];
     }
-    double x[D];
+    double x[S];
 #pragma unroll
-    for (int r = D - 1; r >= 0; --r) {
+    for (int r = S - 1; r >= 0; --r) {
         double t = y[r];
 #pragma unroll
-        for (int c = r + 1; c < D; ++c) t -= sl.L[c * D + r] * x[c];
-        x[r] = t / sl.L[r * D + r];
+        for (int c = r + 1; c < S; ++c) t -= sl.L[c * S + r] * x[c];
+        x[r] = t / sl.L[r * S + r];
     }
 #pragma unroll
-    for (int a = 0; a < D; ++a) th[a] = sl.c[a] + x[a];
+    for (int a = 0; a < D; ++a) th[a] = sl.c[a];
+    if constexpr (S == D) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) th[a] = sl.c[a] + x[a];
+    } else {
+        // sliced coordinates by index (a short unrolled search keeps th in registers)
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b)
+                if (sl.idx[a] == b) th[b] = sl.c[b] + x[a];
+    }
     if (!(r2 <= sl.R * sl.R)) return 0;
     double M;
     return mass_and_support(ev, th, M);
 }
 
 // --------------------------------------------------------------- slice samples
-template <int D>
+template <int S, int D>
 __global__ __launch_bounds__(256) void k_slice_count(EvConst ev, Slice sl, uint64_t seed, uint32_t st, int64_t first,
                                                      int64_t n, int64_t* __restrict__ bcount) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     int keep = 0;
     if (k < n) {
-        double y[D], th[D];
-        keep = slice_candidate<D>(ev, sl, seed, st, (uint64_t)(first + k), y, th);
+        double y[S], th[D];
+        keep = slice_candidate<S, D>(ev, sl, seed, st, (uint64_t)(first + k), y, th);
     }
     const int c = __syncthreads_count(keep);
     if (threadIdx.x == 0) bcount[blockIdx.x] = c;
@@ -127,7 +141,7 @@ __global__ __launch_bounds__(1024) void k_slice_scan(int64_t* __restrict__ bcoun
     if (t == 1023) total[0] = sh[1023];
 }
 
-template <int D>
+template <int S, int D>
 __global__ __launch_bounds__(256) void k_slice_write(EvConst ev, Slice sl, uint64_t seed, uint32_t st, int64_t first,
                                                      int64_t n, const int64_t* __restrict__ boff,
                                                      double* __restrict__ yo, double* __restrict__ tho,
@@ -135,8 +149,8 @@ __global__ __launch_bounds__(256) void k_slice_write(EvConst ev, Slice sl, uint6
     __shared__ int wcount[4];
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     int keep = 0;
-    double y[D], th[D];
-    if (k < n) keep = slice_candidate<D>(ev, sl, seed, st, (uint64_t)(first + k), y, th);
+    double y[S], th[D];
+    if (k < n) keep = slice_candidate<S, D>(ev, sl, seed, st, (uint64_t)(first + k), y, th);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t mask = __ballot(keep);
     if (lane == 0) wcount[w] = __popcll(mask);
@@ -146,10 +160,9 @@ __global__ __launch_bounds__(256) void k_slice_write(EvConst ev, Slice sl, uint6
     if (keep) {
         const int64_t pos = boff[blockIdx.x] + woff + __popcll(mask & ((1ull << lane) - 1));
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            yo[a * n + pos] = y[a];
-            tho[a * n + pos] = th[a];
-        }
+        for (int a = 0; a < S; ++a) yo[a * n + pos] = y[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a) tho[a * n + pos] = th[a];
         lpo[pos] = log_prior_of(ev, th);
     }
 }
@@ -157,40 +170,39 @@ __global__ __launch_bounds__(256) void k_slice_write(EvConst ev, Slice sl, uint6
 __global__ void k_set_count(int64_t* c) { c[0] = 0; }
 
 // ----------------------------------------------------------------------- bank
-// Candidates b0 .. b0 + nb - 1: y, theta [D][nb], flag = 0 (not kept), 1 (kept,
-// within min_dist of a template), 2 (kept, at least min_dist from all m).
-template <int D>
+// Candidates b0 .. b0 + nb - 1: y [S][nb], theta [D][nb], flag = 0 (not kept),
+// 1 (kept, within min_dist of a template), 2 (kept, at least min_dist from all m).
+template <int S, int D>
 __global__ __launch_bounds__(256) void k_bank_cand(EvConst ev, Slice sl, uint64_t seed, uint32_t st, int64_t b0,
                                                    int nb, const double* __restrict__ ty, int64_t ldt, int m,
                                                    double r2, double* __restrict__ cy, double* __restrict__ cth,
                                                    int* __restrict__ flag) {
-    __shared__ double tl[256 * D];
+    __shared__ double tl[256 * S];
     const int k = blockIdx.x * 256 + threadIdx.x;
-    double y[D], th[D];
+    double y[S], th[D];
     int keep = 0;
-    if (k < nb) keep = slice_candidate<D>(ev, sl, seed, st, (uint64_t)(b0 + k), y, th);
+    if (k < nb) keep = slice_candidate<S, D>(ev, sl, seed, st, (uint64_t)(b0 + k), y, th);
     bool far = keep != 0;
     for (int j0 = 0; j0 < m; j0 += 256) {
         const int cnt = min(256, m - j0);
         __syncthreads();
-        for (int q = threadIdx.x; q < cnt * D; q += 256) {
+        for (int q = threadIdx.x; q < cnt * S; q += 256) {
             const int a = q / cnt, j = q - a * cnt;
             tl[a * 256 + j] = ty[a * ldt + j0 + j];
         }
         __syncthreads();
         if (far)
             for (int j = 0; j < cnt; ++j)
-                if (wdist2<D>(y, 1, tl + j, 256) < r2) {
+                if (wdist2<S>(y, 1, tl + j, 256) < r2) {
                     far = false;
                     break;
                 }
     }
     if (k < nb) {
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            cy[a * nb + k] = y[a];
-            cth[a * nb + k] = th[a];
-        }
+        for (int a = 0; a < S; ++a) cy[a * nb + k] = y[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a) cth[a * nb + k] = th[a];
         flag[k] = keep ? (far ? 2 : 1) : 0;
     }
 }
@@ -608,11 +620,20 @@ pe_status_t scratch_for(hipStream_t st, size_t bytes, char** out) {
     return PE_OK;
 }
 
-Slice to_slice(const pe_slice_t& s) {
+// Number of sliced coordinates (the event's D without a sub_mask).
+int slice_dims(const pe_event_s* ev, const pe_slice_t& s) {
+    return s.sub_mask == 0 ? ev->ec.dim : __builtin_popcount(s.sub_mask);
+}
+
+Slice to_slice(const pe_event_s* ev, const pe_slice_t& s) {
     Slice o;
     for (int a = 0; a < PE_MAX_DIM; ++a) o.c[a] = s.centre[a];
     for (int a = 0; a < PE_MAX_DIM * PE_MAX_DIM; ++a) o.L[a] = s.chol[a];
     o.R = s.radius;
+    int S = 0;
+    for (int a = 0; a < PE_MAX_DIM; ++a) o.idx[a] = 0;
+    for (int a = 0; a < ev->ec.dim; ++a)
+        if (s.sub_mask == 0 || (s.sub_mask >> a & 1u)) o.idx[S++] = a;
     return o;
 }
 
@@ -620,12 +641,16 @@ pe_status_t check_slice(const pe_event_s* ev, const pe_slice_t* s) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
     if (!s) return fail(PE_ERR_ARG, "slice is NULL");
     const int D = ev->ec.dim;
+    if (s->sub_mask != 0 && (D != 11 || (s->sub_mask >> 11) != 0 || __builtin_popcount(s->sub_mask) != 4))
+        return fail(PE_ERR_ARG, "sub_mask must be 0 or name 4 of the 11 coordinates of an 11-D event");
+    const int S = slice_dims(ev, *s);
     if (!(s->radius > 0.0) || !std::isfinite(s->radius)) return fail(PE_ERR_ARG, "slice radius must be > 0");
-    for (int r = 0; r < D; ++r) {
+    for (int r = 0; r < D; ++r)
         if (!std::isfinite(s->centre[r])) return fail(PE_ERR_ARG, "slice centre must be finite");
-        if (!(s->chol[r * D + r] > 0.0)) return fail(PE_ERR_ARG, "slice factor needs a positive diagonal");
+    for (int r = 0; r < S; ++r) {
+        if (!(s->chol[r * S + r] > 0.0)) return fail(PE_ERR_ARG, "slice factor needs a positive diagonal");
         for (int c = 0; c <= r; ++c)
-            if (!std::isfinite(s->chol[r * D + c])) return fail(PE_ERR_ARG, "slice factor must be finite");
+            if (!std::isfinite(s->chol[r * S + c])) return fail(PE_ERR_ARG, "slice factor must be finite");
     }
     return PE_OK;
 }
@@ -650,23 +675,29 @@ extern "C" pe_status_t pe_slice_sample(pe_event_t ev, const pe_slice_t* slice, u
     char* scr = nullptr;
     if ((s = scratch_for(st, sizeof(int64_t) * nb, &scr)) != PE_OK) return s;
     int64_t* bc = reinterpret_cast<int64_t*>(scr);
-    const Slice sl = to_slice(*slice);
+    const Slice sl = to_slice(ev, *slice);
     const EvConst& ec = ev->ec;
     if (n == 0) {
         k_set_count<<<1, 1, 0, st>>>(count_dev);
         PE_HIP(hipGetLastError());
         return PE_OK;
     }
+    const int S = slice_dims(ev, *slice);
     if (ec.dim == 4) {
-        k_slice_count<4><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc);
+        k_slice_count<4, 4><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc);
         k_slice_scan<<<1, 1024, 0, st>>>(bc, nb, count_dev);
-        k_slice_write<4><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc, y_dev, theta_dev,
-                                                      logprior_dev);
+        k_slice_write<4, 4><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc, y_dev, theta_dev,
+                                                         logprior_dev);
+    } else if (S == 11) {
+        k_slice_count<11, 11><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc);
+        k_slice_scan<<<1, 1024, 0, st>>>(bc, nb, count_dev);
+        k_slice_write<11, 11><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc, y_dev, theta_dev,
+                                                           logprior_dev);
     } else {
-        k_slice_count<11><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc);
+        k_slice_count<4, 11><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc);
         k_slice_scan<<<1, 1024, 0, st>>>(bc, nb, count_dev);
-        k_slice_write<11><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc, y_dev, theta_dev,
-                                                       logprior_dev);
+        k_slice_write<4, 11><<<nblocks(n), 256, 0, st>>>(ec, sl, seed, stream_id, first, n, bc, y_dev, theta_dev,
+                                                          logprior_dev);
     }
     PE_HIP(hipGetLastError());
     return PE_OK;
@@ -684,29 +715,33 @@ extern "C" pe_status_t pe_tile_bank(pe_event_t ev, const pe_slice_t* slice, doub
     if (!tiles_y_dev || !tiles_theta_dev || !n_tiles || !consumed) return fail(PE_ERR_ARG, "NULL output");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int D = ev->ec.dim;
-    const Slice sl = to_slice(*slice);
+    const int S = slice_dims(ev, *slice);
+    const Slice sl = to_slice(ev, *slice);
     const double r2 = min_dist * min_dist;
     char* scr = nullptr;
-    const size_t cand_bytes = sizeof(double) * 2 * D * (size_t)batch;
+    const size_t cand_bytes = sizeof(double) * (S + D) * (size_t)batch;
     if ((s = scratch_for(st, cand_bytes + sizeof(int) * (size_t)batch, &scr)) != PE_OK) return s;
     double* cy = reinterpret_cast<double*>(scr);
-    double* cth = cy + (size_t)D * batch;
+    double* cth = cy + (size_t)S * batch;
     int* flag = reinterpret_cast<int*>(scr + cand_bytes);
-    std::vector<double> hy((size_t)D * batch), hth((size_t)D * batch);
+    std::vector<double> hy((size_t)S * batch), hth((size_t)D * batch);
     std::vector<int> hf(batch);
-    std::vector<double> ny, nth;  // this batch's new templates, [k][D]
+    std::vector<double> ny, nth;  // this batch's new templates, [k][S] and [k][D]
     int m = 0;
     int64_t used = 0;
     for (int b = 0; b < max_batches && m < max_tiles; ++b) {
         const int64_t b0 = (int64_t)b * batch;
         if (D == 4)
-            k_bank_cand<4><<<nblocks(batch), 256, 0, st>>>(ev->ec, sl, seed, stream_id, b0, batch, tiles_y_dev,
-                                                            max_tiles, m, r2, cy, cth, flag);
+            k_bank_cand<4, 4><<<nblocks(batch), 256, 0, st>>>(ev->ec, sl, seed, stream_id, b0, batch, tiles_y_dev,
+                                                               max_tiles, m, r2, cy, cth, flag);
+        else if (S == 11)
+            k_bank_cand<11, 11><<<nblocks(batch), 256, 0, st>>>(ev->ec, sl, seed, stream_id, b0, batch,
+                                                                 tiles_y_dev, max_tiles, m, r2, cy, cth, flag);
         else
-            k_bank_cand<11><<<nblocks(batch), 256, 0, st>>>(ev->ec, sl, seed, stream_id, b0, batch, tiles_y_dev,
-                                                             max_tiles, m, r2, cy, cth, flag);
+            k_bank_cand<4, 11><<<nblocks(batch), 256, 0, st>>>(ev->ec, sl, seed, stream_id, b0, batch, tiles_y_dev,
+                                                                max_tiles, m, r2, cy, cth, flag);
         PE_HIP(hipGetLastError());
-        PE_HIP(hipMemcpyAsync(hy.data(), cy, sizeof(double) * D * batch, hipMemcpyDeviceToHost, st));
+        PE_HIP(hipMemcpyAsync(hy.data(), cy, sizeof(double) * S * batch, hipMemcpyDeviceToHost, st));
         PE_HIP(hipMemcpyAsync(hth.data(), cth, sizeof(double) * D * batch, hipMemcpyDeviceToHost, st));
         PE_HIP(hipMemcpyAsync(hf.data(), flag, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
         PE_HIP(hipStreamSynchronize(st));
@@ -721,12 +756,10 @@ extern "C" pe_status_t pe_tile_bank(pe_event_t ev, const pe_slice_t* slice, doub
             if (hf[i] != 2) continue;
             bool ok = true;
             for (int j = 0; j < m - m0 && ok; ++j)
-                if (wdist2_rt(D, hy.data() + i, batch, ny.data() + (size_t)j * D, 1) < r2) ok = false;
+                if (wdist2_rt(S, hy.data() + i, batch, ny.data() + (size_t)j * S, 1) < r2) ok = false;
             if (!ok) continue;
-            for (int a = 0; a < D; ++a) {
-                ny.push_back(hy[(size_t)a * batch + i]);
-                nth.push_back(hth[(size_t)a * batch + i]);
-            }
+            for (int a = 0; a < S; ++a) ny.push_back(hy[(size_t)a * batch + i]);
+            for (int a = 0; a < D; ++a) nth.push_back(hth[(size_t)a * batch + i]);
             ++m;
             ++added;
         }
@@ -735,15 +768,17 @@ extern "C" pe_status_t pe_tile_bank(pe_event_t ev, const pe_slice_t* slice, doub
             std::vector<double> rowy(added), rowt(added);
             for (int a = 0; a < D; ++a) {
                 for (int64_t j = 0; j < added; ++j) {
-                    rowy[j] = ny[(size_t)j * D + a];
+                    if (a < S) rowy[j] = ny[(size_t)j * S + a];
                     rowt[j] = nth[(size_t)j * D + a];
                 }
-                PE_HIP(hipMemcpyAsync(tiles_y_dev + (size_t)a * max_tiles + m0, rowy.data(), sizeof(double) * added,
-                                      hipMemcpyHostToDevice, st));
+                if (a < S)
+                    PE_HIP(hipMemcpyAsync(tiles_y_dev + (size_t)a * max_tiles + m0, rowy.data(),
+                                          sizeof(double) * added, hipMemcpyHostToDevice, st));
                 PE_HIP(hipMemcpyAsync(tiles_theta_dev + (size_t)a * max_tiles + m0, rowt.data(),
                                       sizeof(double) * added, hipMemcpyHostToDevice, st));
+                // the copies read rowy and rowt: drain before the next row overwrites them
+                PE_HIP(hipStreamSynchronize(st));
             }
-            PE_HIP(hipStreamSynchronize(st));
         }
         if (m >= max_tiles || (double)added < stop_fraction * (double)kept) break;
     }

@@ -72,13 +72,17 @@ def test_proposal_update_and_refine_argument_errors_on_host():
 def test_tile_entry_points_reject_bad_arguments_on_host():
     L = binding.load()
     sl = binding.make_slice([1.0] * 4, [[1.0, 0, 0, 0], [0, 1.0, 0, 0], [0, 0, 1.0, 0], [0, 0, 0, 1.0]], 2.0)
-    assert ctypes.sizeof(binding.Slice) == (11 + 121 + 1) * 8
+    # pe_slice_t: 11 + 121 + 1 doubles, uint32 sub_mask, padded to 8 bytes
+    assert ctypes.sizeof(binding.Slice) == (11 + 121 + 1) * 8 + 8
+    assert binding.Slice.sub_mask.offset == (11 + 121 + 1) * 8
     assert L.pe_slice_sample(None, ctypes.byref(sl), 0, 0, 0, 10, None, None, None, None, None) == 1
     assert L.pe_tile_bank(None, ctypes.byref(sl), 1.0, 0, 0, 16, 16, 0.1, 4, None, None, None, None, None) == 1
     assert L.pe_tile_assign(5, 1, None, 1, 0, None, 0, None, None) == 1
     assert "dim" in binding.pe_last_error()
     assert L.pe_tile_assign(4, 0, None, 1, 0, None, 0, None, None) == 1
     assert L.pe_tile_draw(1, None, 1, None, None, 4, None, 1, 0, 0, 1, None, None, None, None, None) == 1
+    assert L.pe_tile_extrinsic(None, None, None, 0xF, 0, 0, 1, None, None, None, None) == 1
+    assert "event is NULL" in binding.pe_last_error()
 
 
 def test_batch_item_layout_matches_header():
