@@ -90,10 +90,9 @@ def parse():
     ap.add_argument("--itile-radius", type=float, default=4.0,
                     help="intrinsic tile leg (11-D): slice radius in the intrinsic marginal metric (whitened)")
     ap.add_argument("--itile-spacing", type=float, default=1.0, help="intrinsic tile leg: template spacing")
-    ap.add_argument("--itile-round2", choices=["tiles", "refined", "moments"], default="moments",
-                    help="intrinsic tile leg, second round: the other coordinates from the metric proposal at the "
-                         "injection (tiles), at the first round's weighted centre (refined), or from the weighted "
-                         "moments of the first round (moments)")
+    ap.add_argument("--itile-rounds", type=int, default=4,
+                    help="intrinsic tile leg: rounds per step (each later round reweights the tiles and takes the "
+                         "other coordinates from the previous round's weighted moments)")
     ap.add_argument("--itile-time", type=int, default=1,
                     help="intrinsic tile leg: 1 marginalises tc as well (as the time legs), 0 samples it")
     ap.add_argument("--itile-candidates", type=int, default=4000000,
@@ -717,12 +716,14 @@ def tile_leg(x, args, steps, prec):
 
 def intrinsic_tile_leg(x, args, steps, prec, time_marg=None):
     """Tile mixture over the intrinsic coordinates of the 11-D set (Sec. III: the intrinsic parameters
-    are tiled, the extrinsic ones partially decouple): the likelihood marginalised over the phase and
-    the distance (and the coalescence time with time_marg), a bank and prior samples in the ball of
-    the proposal's marginal metric over (Mc, q, chi1z, chi2z) about the injection, nearest-template
-    tiles; each step evaluates the templates (extrinsic coordinates at the injection), draws N
-    intrinsic points from the tiles and their remaining coordinates from the metric proposal's
-    marginal over them, evaluates and weights them; then a second round from the reweighted tiles.
+    are tiled, the extrinsic ones partially decouple), iterated (the proposal update the paper suggests
+    at the end of Sec. III.A): the likelihood marginalised over the phase and the distance (and the
+    coalescence time with time_marg); a bank and prior samples in the ball of the proposal's marginal
+    metric over (Mc, q, chi1z, chi2z) about the injection, nearest-template tiles. One step is a chain
+    of R rounds of N draws: round 1 weights the tiles by their template's likelihood (extrinsic
+    coordinates at the injection) and draws the other coordinates from the metric proposal's marginal;
+    each later round reweights the tiles by the previous round's weights and draws the other
+    coordinates from a Gaussian with the previous round's weighted centre and covariance over them.
     The injection-centred Gaussian on the same event is timed beside it."""
     import numpy as np
     import torch
@@ -734,6 +735,7 @@ def intrinsic_tile_leg(x, args, steps, prec, time_marg=None):
         common.update(time_marg=1, **time_marg)
     ev = binding.Event(x["data"], x["psd"], amp0=x["amp0"], distance=binding.PE_DIST_MARG, **common)
     N = x["N"]
+    R = max(1, args.itile_rounds)
     h_ = ev.handle
     th0 = x["theta0"]
     g = ev.metric(th0)
@@ -752,49 +754,42 @@ def intrinsic_tile_leg(x, args, steps, prec, time_marg=None):
     tth = tth.contiguous()
     M = tth.shape[1]
     ev.reserve(max(M, N))
-    llt = torch.empty(M, dtype=torch.float64, device="cuda")
-    ll = torch.empty(N, dtype=torch.float64, device="cuda")
-    w = torch.empty(N, dtype=torch.float64, device="cuda")
-    st = torch.empty((steps, 4), dtype=torch.float64, device="cuda")
-    st2 = torch.empty((steps, 4), dtype=torch.float64, device="cuda")
-    c2b = torch.empty(11, dtype=torch.float64, device="cuda")
-    cov = torch.empty((11, 11), dtype=torch.float64, device="cuda")
-    g2b = torch.empty((11, 11), dtype=torch.float64, device="cuda")
+    f64 = dict(dtype=torch.float64, device="cuda")
+    llt = torch.empty(M, **f64)
+    ll = torch.empty(N, **f64)
+    w = torch.empty(N, **f64)
+    st = torch.empty((steps, R, 4), **f64)
+    c2 = torch.empty(11, **f64)
+    cov = torch.empty((11, 11), **f64)
     ext = [4, 5, 6, 7] + ([] if time_marg else [9])  # the coordinates drawn besides the tiles
-    print(f"intrinsic tiles: {M} templates, {y.shape[1]} samples", file=sys.stderr, flush=True)
+    print(f"intrinsic tiles: {M} templates, {y.shape[1]} samples, {R} rounds", file=sys.stderr, flush=True)
+    t_rounds = np.zeros(R)
     for i in range(-1, steps):  # step -1: untimed warm-up
         if i == 0:
             torch.cuda.synchronize()
             ta = time.perf_counter()
+        s = max(i, 0)
         binding.pe_loglike_batch(h_, tth, M, prec, llt, None)
-        thd, lq, lpd, idx = binding.tile_draw(llt, to, lp, th, x["seed"] + 7, 2 * max(i, 0), N)
-        binding.pe_tile_extrinsic(h_, th0, g, 0xF, x["seed"] + 8, 2 * max(i, 0), N, thd, lq, lpd)
-        binding.pe_loglike_batch(h_, thd, N, prec, ll, None)
-        binding.pe_weights_ess(ll, lpd, lq, N, w, st[max(i, 0)])
-        # second round from the tiles reweighted by the first round's weights; the other coordinates
-        # from the metric proposal as before, or about the first round's weighted centre: with the metric
-        # there (refined) or with the weighted covariance of those coordinates (moments)
-        ell = binding.tile_reweight(llt, to, lp, idx, w, 0.1)
-        c2, g2 = th0, g
-        if args.itile_round2 != "tiles":
-            binding.pe_proposal_update(h_, thd, w, N, th0, c2b, cov)
-            c2 = c2b
-            if args.itile_round2 == "refined":
-                binding.pe_metric(h_, c2b, None, 0, g2b)
-            else:
-                ch = cov.cpu().numpy()
+        vals, c, gg = llt, th0, g
+        for r in range(R):
+            tr = time.perf_counter()
+            thd, lq, lpd, idx = binding.tile_draw(vals, to, lp, th, x["seed"] + 7, R * s + r, N)
+            binding.pe_tile_extrinsic(h_, c, gg, 0xF, x["seed"] + 8, R * s + r, N, thd, lq, lpd)
+            binding.pe_loglike_batch(h_, thd, N, prec, ll, None)
+            binding.pe_weights_ess(ll, lpd, lq, N, w, st[s, r])
+            if r + 1 < R:
+                vals = binding.tile_reweight(vals, to, lp, idx, w, 0.1)
+                binding.pe_proposal_update(h_, thd, w, N, c, c2, cov)
                 gm = np.eye(11)
-                gm[np.ix_(ext, ext)] = np.linalg.inv(ch[np.ix_(ext, ext)])
-                g2b.copy_(torch.from_numpy(gm))
-            g2 = g2b
-        thd, lq, lpd, idx = binding.tile_draw(ell, to, lp, th, x["seed"] + 7, 2 * max(i, 0) + 1, N)
-        binding.pe_tile_extrinsic(h_, c2, g2, 0xF, x["seed"] + 8, 2 * max(i, 0) + 1, N, thd, lq, lpd)
-        binding.pe_loglike_batch(h_, thd, N, prec, ll, None)
-        binding.pe_weights_ess(ll, lpd, lq, N, w, st2[max(i, 0)])
+                gm[np.ix_(ext, ext)] = np.linalg.inv(cov.cpu().numpy()[np.ix_(ext, ext)])
+                c, gg = c2.clone(), torch.from_numpy(gm).cuda()
+            if i >= 0:
+                torch.cuda.synchronize()
+                t_rounds[r] += time.perf_counter() - tr
     torch.cuda.synchronize()
     tb = time.perf_counter()
     # the injection-centred Gaussian on the same event
-    stg = torch.empty((steps, 4), dtype=torch.float64, device="cuda")
+    stg = torch.empty((steps, 4), **f64)
     for i in range(-1, steps):
         if i == 0:
             torch.cuda.synchronize()
@@ -806,22 +801,24 @@ def intrinsic_tile_leg(x, args, steps, prec, time_marg=None):
     td = time.perf_counter()
     ev.status()
     ev.close()
-    s, s2, sg = st.cpu().numpy(), st2.cpu().numpy(), stg.cpu().numpy()
+    s_, sg = st.cpu().numpy(), stg.cpu().numpy()
     t_step = (tb - ta) / steps
     t_g = (td - tc) / steps
-    e1, e2, eg = float(s[:, 0].mean()), float(s2[:, 0].mean()), float(sg[:, 0].mean())
+    ess = s_[:, :, 0].mean(0)
+    eg = float(sg[:, 0].mean())
+    t_last = t_rounds[-1] / steps
     return {
-        "kind": ("tile mixture over (Mc, q, chi1z, chi2z), the other coordinates from the metric proposal's "
-                 "marginal; likelihood marginalised over phase and distance" + (" and tc" if time_marg else "")),
+        "kind": ("tile mixture over (Mc, q, chi1z, chi2z), the other coordinates drawn apart; likelihood "
+                 "marginalised over phase and distance" + (" and tc" if time_marg else "") + f"; {R} rounds per "
+                 "step, each later round from the tiles reweighted by the previous one and the other coordinates "
+                 "from its weighted moments"),
         "slice_radius": args.itile_radius, "spacing": args.itile_spacing, "templates": M, "bank_candidates": used,
         "prior_samples": int(y.shape[1]), "bank_ms": 1e3 * (t1 - t0), "samples_and_assign_ms": 1e3 * (t2 - t1),
-        "steps": steps, "draws_per_round": N, "ms_per_step_two_rounds": 1e3 * t_step,
-        "round1": {"ess_per_event_mean": e1, "efficiency": e1 / N, "ess_per_event_min": float(s[:, 0].min()),
-                   "ess_per_event_max": float(s[:, 0].max())},
-        "round2_reweighted": {"extrinsic": args.itile_round2, "ess_per_event_mean": e2, "efficiency": e2 / N,
-                              "ess_per_event_min": float(s2[:, 0].min()),
-                              "ess_per_event_max": float(s2[:, 0].max())},
-        "ess_per_s": (e1 + e2) / t_step,
+        "steps": steps, "rounds": R, "draws_per_round": N, "ms_per_step": 1e3 * t_step,
+        "ms_per_round": [float(1e3 * t / steps) for t in t_rounds],
+        "ess_per_event_by_round": [float(e) for e in ess], "efficiency_last_round": float(ess[-1]) / N,
+        "ess_last_round_min": float(s_[:, -1, 0].min()), "ess_last_round_max": float(s_[:, -1, 0].max()),
+        "ess_per_s_last_round": float(ess[-1]) / t_last, "ess_per_s_chain": float(ess[-1]) / t_step,
         "gaussian_same_event": {"ms_per_step": 1e3 * t_g, "ess_per_event_mean": eg, "efficiency": eg / N,
                                 "ess_per_s": eg / t_g},
     }
