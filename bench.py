@@ -330,6 +330,21 @@ def main():
     for x in evs:
         x["ev"].close()
 
+    # the proposal with the highest ESS per second on this event (whole chains for the tile legs)
+    cands = {"gaussian_at_injection": out["ess_per_s"]}
+    for k in ("distance_marginalised", "phase_and_distance_marginalised", "time_phase_and_distance_marginalised",
+              "time_and_phase_marginalised"):
+        for cn, v in out.get(k, {}).items():
+            if isinstance(v, dict) and "ess_per_s" in v:
+                cands[f"{k}/{cn}"] = v["ess_per_s"]
+    if "refined" in out and "ess_per_s" in out["refined"]:
+        cands["refined"] = out["refined"]["ess_per_s"]
+    if "tiles" in out:
+        cands["tiles"] = out["tiles"]["ess_per_s"]
+    if "intrinsic_tiles" in out:
+        cands["intrinsic_tiles"] = out["intrinsic_tiles"]["ess_per_s_chain"]
+    best = max(cands, key=lambda k: cands[k])
+    out["ess_per_s_best"] = {"value": cands[best], "leg": best}
     if c == 1 and not args.no_batch_leg:
         out["config2"] = batch_leg(2, max(args.steps, 1), prec)
     if c == 1 and args.long_steps > 0:
