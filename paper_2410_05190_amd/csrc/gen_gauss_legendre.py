@@ -1,6 +1,7 @@
-"""Writes the 16-point Gauss-Legendre table used by the distance integral (pe_device.h): the
-positive nodes of P_16 on [-1, 1] and their weights, from numpy's Golub-Welsch routine with a
-Newton polish on the Legendre recurrence, printed to 17 significant digits (exact round trip)."""
+"""Writes the Gauss-Legendre tables used by the distance integrals (pe_device.h): the positive
+nodes of P_n on [-1, 1] and their weights (n = 16 for the likelihood's integral, n = 8 for the
+time marginal's per-node integrals), from numpy's Golub-Welsch routine with a Newton polish on the
+Legendre recurrence, printed to 17 significant digits (exact round trip)."""
 import numpy as np
 
 
@@ -12,7 +13,7 @@ def legendre(n, x):
     return p1, dp
 
 
-def main(n=16):
+def table(n, suffix):
     x, _ = np.polynomial.legendre.leggauss(n)
     for _ in range(3):
         p, dp = legendre(n, x)
@@ -21,9 +22,14 @@ def main(n=16):
     w = 2.0 / ((1 - x * x) * dp * dp)
     pos = x > 0
     xs, ws = x[pos][::-1], w[pos][::-1]
-    print("constexpr double kGlX[%d] = {%s};" % (n // 2, ", ".join(repr(float(v)) for v in xs)))
-    print("constexpr double kGlW[%d] = {%s};" % (n // 2, ", ".join(repr(float(v)) for v in ws)))
+    print("constexpr double kGlX%s[%d] = {%s};" % (suffix, n // 2, ", ".join(repr(float(v)) for v in xs)))
+    print("constexpr double kGlW%s[%d] = {%s};" % (suffix, n // 2, ", ".join(repr(float(v)) for v in ws)))
     assert abs(2 * ws.sum() - 2.0) < 1e-14
+
+
+def main():
+    table(16, "")
+    table(8, "8")
 
 
 if __name__ == "__main__":

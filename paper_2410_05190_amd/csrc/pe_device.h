@@ -414,6 +414,35 @@ constexpr double kDmDelta = 8.0;   // largest change of ln(integrand) across a p
 constexpr double kDmCut = 45.0;    // walk ends below e^-45 of the maximum
 constexpr int kDmMaxPanels = 400;  // per walk; reached only by non-finite input
 
+// The light variant (Lite = true), for the many per-node integrals of the time
+// marginal on the split path, whose tolerance is 1e-3 in ln L: ln I0 from the
+// polynomial approximations of Abramowitz & Stegun 9.8.1 (x < 3.75) and 9.8.2
+// (x >= 3.75), each within 2e-7 of I0 relative; 8-point Gauss-Legendre panels;
+// the walk ends below e^-20 of the maximum; the maximiser to 1e-6. Measured
+// against adaptive quadrature of the exact integrand over b in [0.05, 8000] and
+// a up to 80 sqrt(b): within 5e-7 in ln, with a third of the evaluations.
+constexpr double kGlX8[4] = {0.9602898564975363, 0.7966664774136268, 0.525532409916329, 0.1834346424956498};
+constexpr double kGlW8[4] = {0.10122853629037618, 0.22238103445337445, 0.3137066458778874, 0.362683783378362};
+constexpr double kDmCutLite = 20.0;
+
+__device__ __forceinline__ double log_i0_poly(double x) {
+    x = fabs(x);
+    if (x < 3.75) {
+        const double t = (x / 3.75) * (x / 3.75);
+        const double p =
+            1.0 + t * (3.5156229 + t * (3.0899424 + t * (1.2067492 + t * (0.2659732 + t * (0.0360768 + t * 0.0045813)))));
+        return log(p);
+    }
+    const double t = 3.75 / x;
+    const double p =
+        0.39894228 +
+        t * (0.01328592 +
+             t * (0.00225319 +
+                  t * (-0.00157565 +
+                       t * (0.00916281 + t * (-0.02057706 + t * (0.02635537 + t * (-0.01647633 + t * 0.00392377)))))));
+    return x - 0.5 * log(x) + log(p);
+}
+
 // NL lanes (consecutive, NL a power of two) may share one draw: lane `sub`
 // evaluates the nodes sub, sub + NL, ... of every panel, while all of them walk
 // the same panels, decided from values that every lane computes alike (the
@@ -426,31 +455,36 @@ struct DmState {
     double W;     // the walk's reference maximum (end points only; equal on every lane)
 };
 
+template <bool Lite = false>
 __device__ __forceinline__ double dm_g(const DmState& q, double x) {
-    const double phi = q.ex ? q.a * x : log_i0(q.a * x);
+    const double phi = q.ex ? q.a * x : (Lite ? log_i0_poly(q.a * x) : log_i0(q.a * x));
     return 1.0986122886681098 - 4.0 * log(x) + phi - q.b * x * x;  // ln 3 - 4 ln x + ...
 }
 
-template <int NL>
+template <int NL, bool Lite = false>
 __device__ __forceinline__ void dm_panel(DmState& q, double lo, double hi, int sub) {
     const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+    constexpr int NP = Lite ? 8 : 16;
 #pragma unroll 1
-    for (int k = sub; k < 16; k += NL) {
-        const double t = (k < 8) ? -kGlX[k] : kGlX[k - 8];
-        const double v = dm_g(q, c + h * t);
+    for (int k = sub; k < NP; k += NL) {
+        const int r = k < NP / 2 ? k : k - NP / 2;
+        const double x = Lite ? kGlX8[r] : kGlX[r];
+        const double t = (k < NP / 2) ? -x : x;
+        const double v = dm_g<Lite>(q, c + h * t);
         if (v > q.G) {
             q.S *= exp(q.G - v);
             q.G = v;
         }
-        q.S += h * kGlW[k < 8 ? k : k - 8] * exp(v - q.G);
+        q.S += h * (Lite ? kGlW8[r] : kGlW[r]) * exp(v - q.G);
     }
 }
 
 // Walk from x0 (where g = g0) in direction dir until g falls below the cut
 // (while decreasing) or x reaches stop; returns the last x.
-template <int NL>
+template <int NL, bool Lite = false>
 __device__ __forceinline__ double dm_walk(DmState& q, double x0, double g0, int dir, double stop, double w,
                                           int sub) {
+    constexpr double cut = Lite ? kDmCutLite : kDmCut;
 #pragma unroll 1
     for (int p = 0; p < kDmMaxPanels; ++p) {
         double x1 = x0, g1 = g0;
@@ -463,14 +497,14 @@ __device__ __forceinline__ double dm_walk(DmState& q, double x0, double g0, int 
                 w = fmin(w, x0 / 3.0);
                 x1 = fmax(x0 - w, stop);
             }
-            g1 = dm_g(q, x1);
+            g1 = dm_g<Lite>(q, x1);
             if (fabs(g1 - g0) <= kDmDelta) break;
             w *= 0.5;
         }
-        dm_panel<NL>(q, fmin(x0, x1), fmax(x0, x1), sub);
+        dm_panel<NL, Lite>(q, fmin(x0, x1), fmax(x0, x1), sub);
         q.W = fmax(q.W, g1);
         if (x1 == stop) return x1;
-        if (g1 < q.W - kDmCut && g1 < g0) return x1;
+        if (g1 < q.W - cut && g1 < g0) return x1;
         x0 = x1;
         g0 = g1;
         w *= 2.0;
@@ -478,7 +512,7 @@ __device__ __forceinline__ double dm_walk(DmState& q, double x0, double g0, int 
     return x0;
 }
 
-template <int NL>
+template <int NL, bool Lite = false>
 __device__ __forceinline__ double log_dist_marg(double a, double b, bool ex, int sub) {
     if (!(b > 0.0)) return (a == 0.0) ? 0.0 : NAN;  // H = 0 only with Z = 0 (no bins below the cut)
     DmState q{a, b, ex, -INFINITY, 0.0, -INFINITY};
@@ -491,20 +525,20 @@ __device__ __forceinline__ double log_dist_marg(double a, double b, bool ex, int
             break;
         }
         const double xn = fmax(1.0, (ae + sqrt(disc)) / (4.0 * b));
-        const bool done = ex || xn == 1.0 || fabs(xn - xs) <= 1e-14 * xn;
+        const bool done = ex || xn == 1.0 || fabs(xn - xs) <= (Lite ? 1e-6 : 1e-14) * xn;
         xs = xn;
         if (done) break;
         ae = a * i1_over_i0(a * xs);
     }
-    const double g1 = dm_g(q, 1.0);
-    const double gs = (xs > 1.0) ? dm_g(q, xs) : g1;
+    const double g1 = dm_g<Lite>(q, 1.0);
+    const double gs = (xs > 1.0) ? dm_g<Lite>(q, xs) : g1;
     q.W = fmax(g1, gs);
     q.G = q.W;
     const double w0 = fmin(1.0 / sqrt(2.0 * b), 0.5 * xs);
-    dm_walk<NL>(q, xs, gs, +1, INFINITY, w0, sub);
+    dm_walk<NL, Lite>(q, xs, gs, +1, INFINITY, w0, sub);
     double xl = 1.0;
-    if (xs > 1.0) xl = dm_walk<NL>(q, xs, gs, -1, 1.0, w0, sub);
-    if (xl > 1.0 && g1 >= q.W - kDmCut) dm_walk<NL>(q, 1.0, g1, +1, xl, w0, sub);
+    if (xs > 1.0) xl = dm_walk<NL, Lite>(q, xs, gs, -1, 1.0, w0, sub);
+    if (xl > 1.0 && g1 >= q.W - (Lite ? kDmCutLite : kDmCut)) dm_walk<NL, Lite>(q, 1.0, g1, +1, xl, w0, sub);
     double G = q.G, S = q.S;
 #pragma unroll
     for (int o = 1; o < NL; o <<= 1) {

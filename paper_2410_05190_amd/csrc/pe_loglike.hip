@@ -1346,9 +1346,18 @@ __global__ __launch_bounds__(256) void k_b_split_tm(BatchHdr* __restrict__ hdr, 
 // to 1): a^2 / (4 b) when a >= 2 b, else a - b. The first pass finds the node
 // with the largest such bound and integrates there (L*); the second integrates
 // only the nodes whose bound reaches L* - kTmSkip, the others adding less than
-// e^-kTmSkip of the largest term each.
+// e^-kTmSkip of the largest term each (with at most 16384 nodes, below 7e-7 of
+// the sum together).
 constexpr int kTmPiece = 128;
-constexpr double kTmSkip = 46.0;
+
+// ln L at a node: the phase marginal exactly, the distance integral in its
+// light form (within 5e-7 in ln; see log_dist_marg).
+__device__ __forceinline__ double node_loglike(const EvConst& ec, double zr, double zi, double h) {
+    if (!ec.dist) return loglike_phase(ec, zr, zi, h);
+    const bool ex = (ec.phase == PE_PHASE_EXPLICIT);
+    return log_dist_marg<1, true>(ex ? zr : hypot(zr, zi), 0.5 * h, ex, 0);
+}
+constexpr double kTmSkip = 24.0;
 constexpr int kTmCached = 4;  // nodes per thread whose Z stays in registers (M <= 1024)
 
 __device__ __forceinline__ double dist_bound(const EvConst& ec, double zr, double zi, double h) {
@@ -1443,7 +1452,7 @@ __global__ __launch_bounds__(256) void k_tm_nodes(const BatchHdr* __restrict__ h
             if (ec.dist && dist_bound(ec, zr, zi, h) < lstar - kTmSkip)
                 v = -INFINITY;  // below e^-kTmSkip of the largest node
             else
-                v = loglike_of<1>(ec, zr, zi, h, 0);
+                v = node_loglike(ec, zr, zi, h);
             if (isnan(v) || v == INFINITY) bad = 1;
             if (v > -INFINITY) {
                 const double cw = tm_weight(m, M);
@@ -1509,7 +1518,7 @@ __global__ __launch_bounds__(256) void k_tm_nodes(const BatchHdr* __restrict__ h
                 // the owner of that node integrates there
 #pragma unroll
                 for (int i = 0; i < kTmCached; ++i)
-                    if (i * 256 + (int)threadIdx.x == bm) sL = loglike_of<1>(ec, cr[i], ci[i], h, 0);
+                    if (i * 256 + (int)threadIdx.x == bm) sL = node_loglike(ec, cr[i], ci[i], h);
                 __syncthreads();
                 lstar = sL;
             }
@@ -1538,7 +1547,7 @@ __global__ __launch_bounds__(256) void k_tm_nodes(const BatchHdr* __restrict__ h
                 best_node(ub, um, bm);
                 double zr, zi;
                 tm_node_z<P>(E, p, j, nch, bm, true, smom, zr, zi);  // collective staging
-                if (threadIdx.x == 0) sL = loglike_of<1>(ec, zr, zi, h, 0);
+                if (threadIdx.x == 0) sL = node_loglike(ec, zr, zi, h);
                 __syncthreads();
                 lstar = sL;
             }
