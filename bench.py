@@ -922,6 +922,10 @@ def serve_bench(args):
 
     from paper_2410_05190_amd import binding, synth
 
+    # a long-lived server starts from a clean device: the earlier legs' cached blocks go back first, so
+    # that the server's slab is not placed among them
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     tr = synth.serving_trace(args.serve_events, args.serve_rate)
     n = args.serve_events
     keys = sorted({(int(tr["shape"][i]), int(tr["n_det"][i]), int(tr["pool"][i])) for i in range(n)})
