@@ -222,27 +222,31 @@ def test_match_assignment_against_the_oracle(n_cand):
 INTRINSIC = 0xF
 
 
-def _intrinsic_slices(b, radius):
+def _intrinsic_slices(b, radius, mask=INTRINSIC):
     g = b.ev.metric(b.theta_inj)
-    GI = np.linalg.inv(np.linalg.inv(g)[:4, :4])  # the proposal's marginal precision over Mc, q, chi1z, chi2z
+    sub = [a for a in range(11) if mask >> a & 1]
+    GI = np.linalg.inv(np.linalg.inv(g)[np.ix_(sub, sub)])  # the proposal's marginal precision over them
     L = np.linalg.cholesky(GI)
-    return (oracle.make_slice(b.theta_inj, L, radius, INTRINSIC),
-            binding.make_slice(b.theta_inj, L, radius, INTRINSIC), g)
+    return (oracle.make_slice(b.theta_inj, L, radius, mask),
+            binding.make_slice(b.theta_inj, L, radius, mask), g)
 
 
-def test_intrinsic_slice_and_bank_bit_exact():
+@pytest.mark.parametrize("mask", [INTRINSIC, (1 << 0) | (1 << 1) | (1 << 5) | (1 << 6)])
+def test_intrinsic_slice_and_bank_bit_exact(mask):
+    """Slices over four of the 11 coordinates (the intrinsic ones, and Mc, q, dec, iota: the
+    coordinates taken by index, not as a leading block): samples and bank bit for bit."""
     torch_cuda()
     b = build_event(1, 0, n_bins=2048)
     ev, data, psd = upload_event(b)
-    so, sg, g = _intrinsic_slices(b, 3.0)
+    so, sg, g = _intrinsic_slices(b, 3.0, mask)
     for first, n in ((0, 60000), (999, 333)):
-        note(f"intrinsic slice samples: first {first}, n {n}")
+        note(f"sub-slice samples: mask {mask:#x}, first {first}, n {n}")
         y, th, lp = ev.slice_sample(sg, 17, 2, first, n)
         yo, tho, lpo = b.ev.slice_sample(so, 17, 2, first, n)
         assert y.shape == yo.shape == (4, yo.shape[1]) and th.shape == tho.shape
         assert np.array_equal(host(y), yo) and np.array_equal(host(th), tho)
         np.testing.assert_allclose(host(lp), lpo, rtol=1e-14, atol=1e-14)
-    note("intrinsic bank")
+    note(f"sub-slice bank, mask {mask:#x}")
     ty, tth, used = ev.tile_bank(sg, 1.0, 5, 1, 2048, 3000, 0.002, 100)
     tyo, ttho, usedo = b.ev.tile_bank(so, 1.0, 5, 1, 2048, 3000, 0.002, 100)
     assert used == usedo and ty.shape == tyo.shape and ty.shape[0] == 4
@@ -304,11 +308,18 @@ def test_tile_extrinsic_rejects_bad_masks():
     for mask in (0, INTRINSIC | (1 << 4), 1 << 7, 1 << 11):
         with pytest.raises(binding.PeError):
             binding.tile_extrinsic(ev, dev(b.theta_inj), g, mask, th, z, z, 1, 0)
+    # slices take 0 or four coordinates below bit 11
+    for mask in (0x7, 0x1F, 0xF << 8):
+        sl = binding.make_slice(b.theta_inj, np.eye(bin(mask).count("1")), 1.0, mask)
+        with pytest.raises(binding.PeError):
+            ev.slice_sample(sl, 1, 0, 0, 16)
     ev.close()
     b4 = build_event(0, 0, n_bins=1024)
     ev4, data, psd = upload_event(b4)
     with pytest.raises(binding.PeError):
         binding.tile_extrinsic(ev4, dev(b4.theta_inj), dev(np.eye(4)), 1, dev(np.zeros((4, 4))), z, z, 1, 0)
+    with pytest.raises(binding.PeError):  # no sub-slices on a 4-D event
+        ev4.slice_sample(binding.make_slice(b4.theta_inj, np.eye(4), 1.0, 0xF), 1, 0, 0, 16)
     ev4.close()
 
 
