@@ -501,13 +501,20 @@ pe_status_t run_prep(const std::vector<PrepArg>& all, hipStream_t st) {
         if (v.empty()) continue;
         const int ne = (int)v.size();
         std::vector<int64_t> off(ne + 1, 0);
-        for (int e = 0; e < ne; ++e) off[e + 1] = off[e] + blocks256(v[e].ec.K + kTabPad);
+        int max_seg = 1, max_det = 1;  // the scan grid: the batch's most segments and detectors
+        for (int e = 0; e < ne; ++e) {
+            off[e + 1] = off[e] + blocks256(v[e].ec.K + kTabPad);
+            const int64_t K = v[e].ec.K;
+            const int64_t seg = std::max<int64_t>(1024, (K + kScanSeg - 1) / kScanSeg);
+            max_seg = std::max(max_seg, (int)((K + seg - 1) / seg));
+            max_det = std::max(max_det, (int)v[e].ec.n_det);
+        }
         Area& A = area_for(st, kAreaPrep);
         std::lock_guard<std::mutex> lk(A.mu);
         BatchPtrs b;
         pe_status_t s = upload_area(A, ne, off[ne], 0, v.data(), sizeof(PrepArg) * ne, off, nullptr, 0, st, b);
         if (s != PE_OK) return s;
-        PE_HIP(launch_prep_batch(b, ne, off[ne], cls >> 1, cls & 1, st));
+        PE_HIP(launch_prep_batch(b, ne, off[ne], cls >> 1, cls & 1, max_seg, max_det, st));
     }
     return PE_OK;
 }

@@ -221,7 +221,7 @@ struct BatchHdr {
     int pad0;
     int64_t total;         // flattened size (blocks)
     int64_t total2;        // second flattened size (blocks)
-    int qitems[kQueues];   // hot-loop items per queue (written by k_b_items, then k_r_items)
+    int qitems[kQueues];   // hot-loop items per queue (written by k_items<false>, then k_items<true>)
     int qnext[kQueues];    // queue counters
     double redo_budget;    // split path: |d ln L| estimate above which a draw is re-evaluated in FP64
 };
@@ -360,7 +360,7 @@ struct BatchPtrs {
 // log-likelihood prologue and finalize, weight normalisation) or kWBlock
 // draws (weight reduction).
 hipError_t launch_prep_batch(const BatchPtrs &b, int ne, int64_t total_blocks, int data_f32, int psd_f32,
-                             hipStream_t st);
+                             int max_seg, int max_det, hipStream_t st);
 hipError_t launch_metric_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
 hipError_t launch_draw_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st, bool ext = false);
 // any_dist: some event of the batch is distance-marginalised (adds k_b_dist).

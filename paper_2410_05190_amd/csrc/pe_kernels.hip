@@ -96,8 +96,8 @@ __global__ __launch_bounds__(256) void k_prep(const BatchHdr* __restrict__ hdr, 
 // two passes over contiguous segments: segment sums, then each segment adds
 // the sums before it (fixed order) and scans its bins in coalesced 256-wide
 // tiles (wave shuffle scan + LDS across the four waves).
-// Grid: (kScanSeg, PE_MAX_DET, events); blocks past the event's segment or
-// detector count return at once.
+// Grid: (the batch's most segments, its most detectors, events); blocks past
+// the event's segment or detector count return at once.
 // Segments of the scan: at least 1024 bins each, at most kScanSeg of them.
 __device__ __forceinline__ void scan_layout(int64_t K, int64_t& seg, int& nseg) {
     seg = max((int64_t)1024, (K + kScanSeg - 1) / kScanSeg);
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256) void k_seg_scan(const BatchHdr* __restrict__ h
 }
 
 hipError_t launch_prep_batch(const BatchPtrs& b, int ne, int64_t total_blocks, int data_f32, int psd_f32,
-                             hipStream_t st) {
+                             int max_seg, int max_det, hipStream_t st) {
     if (ne <= 0) return hipSuccess;
     const PrepArg* args = (const PrepArg*)b.args;
     const unsigned nb = stride_grid(total_blocks, 1);
@@ -320,7 +320,8 @@ hipError_t launch_prep_batch(const BatchPtrs& b, int ne, int64_t total_blocks, i
         k_prep<double, float><<<nb, 256, 0, st>>>(b.hdr, args, b.off);
     else
         k_prep<double, double><<<nb, 256, 0, st>>>(b.hdr, args, b.off);
-    const dim3 g(kScanSeg, PE_MAX_DET, event_grid(ne, 64));
+    // blocks past an event's segments or detectors return at once; the grid spans the batch's largest
+    const dim3 g((unsigned)std::min(max_seg, kScanSeg), (unsigned)std::min(max_det, PE_MAX_DET), event_grid(ne, 64));
     k_seg_sums<<<g, 256, 0, st>>>(b.hdr, args);
     k_seg_scan<<<g, 256, 0, st>>>(b.hdr, args);
     return hipGetLastError();

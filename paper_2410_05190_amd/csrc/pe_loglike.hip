@@ -4,7 +4,8 @@
 //   k_b_reset     clear the cut histograms and plans of the events starting here
 //   k_b_support   support mask, ISCO cut and cut bucket of every draw
 //   k_b_plan      per event: bucket offsets, live count, frequency decomposition
-//   k_b_items     offsets of every event's work items in the batch's queue
+//   k_items       offsets of every event's work items in the batch's queues
+//                 (<false>: the hot loop's; <true>: the re-evaluation's)
 //   k_b_scatter   live draws into their cut buckets
 //   k_b_coeffs    per live draw: phase polynomial, delays, responses, (h|h)
 //   k_b_split / k_b_f64   hot loop: persistent workgroups take (event, tile of
@@ -14,7 +15,7 @@
 //                 64 draws of a wave and the 256 of a workgroup
 //   k_b_finalize  fixed-order combine of the group partials, ln L; split path:
 //                 the draw's error estimate, and the draws to re-evaluate
-//   k_r_plan, k_r_scatter, k_r_items, k_r_f64, k_r_finalize
+//   k_r_plan, k_r_scatter, k_items<true>, k_r_f64, k_r_finalize
 //                 split path: FP64 re-evaluation of the listed draws on the hot
 //                 loop's own layout (tiles of 256 listed draws x groups of chunks)
 //   k_b_dist      distance-marginalised events: ln L integrated over dL
@@ -200,22 +201,62 @@ __device__ __forceinline__ int64_t queue_items(int64_t ntiles, int G, int x) {
 }
 
 // Per queue: offsets of every event's items (ioff[x][ne + 1]), the item
-// total, and the counter reset. Thread x serves queue x.
-__global__ void k_b_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs, int64_t* __restrict__ ioff) {
-    const int x = threadIdx.x;
-    if (x >= kQueues || blockIdx.x != 0) return;
-    const int ne = hdr->ne;
-    int64_t* o = ioff + (int64_t)x * (ne + 1);
-    int64_t acc = 0;
-    for (int e = 0; e < ne; ++e) {
-        o[e] = acc;
-        const EvPlan p = *evs[e].plan;
-        const int lo = max(0, evs[e].tile_lo), hi = min(p.tiles, evs[e].tile_hi);
-        if (hi > lo && p.n_groups > 0) acc += queue_items(hi - lo, p.n_groups, x);
+// total, and the counter reset. One workgroup of kItemThreads: its threads
+// first write every event's item count per queue (events spread over the
+// threads, their plans read in parallel), then wave x scans queue x's counts
+// in place, 64 events per step (shuffle scan, running carry).
+constexpr int kItemThreads = 64 * kQueues;
+
+template <bool Redo>
+__device__ __forceinline__ void items_of(const EvDev& E, int64_t (&c)[kQueues]) {
+#pragma unroll
+    for (int x = 0; x < kQueues; ++x) c[x] = 0;
+    if (Redo) {
+        if (!(E.flags & kLlFinalize)) return;
+        const EvPlan r = E.plan[1];
+        if (r.tiles > 0 && r.n_groups > 0)
+#pragma unroll
+            for (int x = 0; x < kQueues; ++x) c[x] = queue_items(r.tiles, r.n_groups, x);
+    } else {
+        const EvPlan p = *E.plan;
+        const int lo = max(0, E.tile_lo), hi = min(p.tiles, E.tile_hi);
+        if (hi > lo && p.n_groups > 0)
+#pragma unroll
+            for (int x = 0; x < kQueues; ++x) c[x] = queue_items(hi - lo, p.n_groups, x);
     }
-    o[ne] = acc;
-    hdr->qitems[x] = (int)acc;
-    hdr->qnext[x] = 0;
+}
+
+template <bool Redo>
+__global__ __launch_bounds__(kItemThreads) void k_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                                      int64_t* __restrict__ ioff) {
+    const int ne = hdr->ne, t = threadIdx.x;
+    for (int e = t; e < ne; e += kItemThreads) {
+        int64_t c[kQueues];
+        items_of<Redo>(evs[e], c);
+#pragma unroll
+        for (int x = 0; x < kQueues; ++x) ioff[(int64_t)x * (ne + 1) + e] = c[x];
+    }
+    __syncthreads();
+    const int x = t >> 6, lane = t & 63;
+    int64_t* o = ioff + (int64_t)x * (ne + 1);
+    int64_t carry = 0;
+    for (int e0 = 0; e0 < ne; e0 += 64) {
+        const int e = e0 + lane;
+        const int64_t v = (e < ne) ? o[e] : 0;
+        int64_t inc = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t u = __shfl_up(inc, off);
+            if (lane >= off) inc += u;
+        }
+        if (e < ne) o[e] = carry + inc - v;
+        carry += __shfl(inc, 63);
+    }
+    if (lane == 0) {
+        o[ne] = carry;
+        hdr->qitems[x] = (int)carry;
+        hdr->qnext[x] = 0;
+    }
 }
 
 // Live draws into their buckets; the order inside a bucket is immaterial. A
@@ -927,23 +968,6 @@ __global__ __launch_bounds__(256) void k_r_scatter(const BatchHdr* __restrict__ 
 
 // Per queue: offsets of every event's re-evaluation items, the item total and
 // the counter reset (the main hot loop has finished with the queues).
-__global__ void k_r_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs, int64_t* __restrict__ ioff) {
-    const int x = threadIdx.x;
-    if (x >= kQueues || blockIdx.x != 0) return;
-    const int ne = hdr->ne;
-    int64_t* o = ioff + (int64_t)x * (ne + 1);
-    int64_t acc = 0;
-    for (int e = 0; e < ne; ++e) {
-        o[e] = acc;
-        if (!(evs[e].flags & kLlFinalize)) continue;
-        const EvPlan r = evs[e].plan[1];
-        if (r.tiles > 0 && r.n_groups > 0) acc += queue_items(r.tiles, r.n_groups, x);
-    }
-    o[ne] = acc;
-    hdr->qitems[x] = (int)acc;
-    hdr->qnext[x] = 0;
-}
-
 __global__ __launch_bounds__(kRedoTile) void k_r_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
                                                const int64_t* __restrict__ ioff) {
     int items = 0;
@@ -1174,7 +1198,7 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
         k_b_plan<<<eg, 1024, 0, st>>>(b.hdr, evs);
         k_b_scatter<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
     }
-    k_b_items<<<1, 64, 0, st>>>(b.hdr, evs, ioff);
+    k_items<false><<<1, kItemThreads, 0, st>>>(b.hdr, evs, ioff);
     if (prologue_blocks > 0) k_b_coeffs<<<grid_for(prologue_blocks), 256, 0, st>>>(b.hdr, evs, b.off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1196,7 +1220,7 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
             // FP64 re-evaluation of the draws whose error estimate exceeds the budget
             k_r_plan<<<eg, 1024, 0, st>>>(b.hdr, evs);
             k_r_scatter<<<fg, 256, 0, st>>>(b.hdr, evs, b.off2);
-            k_r_items<<<1, 64, 0, st>>>(b.hdr, evs, ioff);
+            k_items<true><<<1, kItemThreads, 0, st>>>(b.hdr, evs, ioff);
             if (profile) prof_begin("loglike_redo", st);
             k_r_f64<<<redo_grid(), kRedoTile, 0, st>>>(b.hdr, evs, ioff);
             if (profile) prof_end("loglike_redo", st);
@@ -1618,7 +1642,7 @@ hipError_t launch_loglike_moments(const BatchPtrs& b, int ne, int64_t prologue_b
     k_b_support<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
     k_b_plan<<<eg, 1024, 0, st>>>(b.hdr, evs);
     k_b_scatter<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
-    k_b_items<<<1, 64, 0, st>>>(b.hdr, evs, ioff);
+    k_items<false><<<1, kItemThreads, 0, st>>>(b.hdr, evs, ioff);
     k_b_coeffs<<<nb, 256, 0, st>>>(b.hdr, evs, b.off);
     const unsigned ng = grid_for(node_blocks * 256);
     if (P == 8)
