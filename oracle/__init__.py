@@ -105,7 +105,7 @@ def lib():
         L.peo_slice_dims.restype = ctypes.c_int
         L.peo_slice_dims.argtypes = [ctypes.POINTER(_Event), _sp, _ip]
         L.peo_tile_extrinsic.restype = ctypes.c_int
-        L.peo_tile_extrinsic.argtypes = [ctypes.POINTER(_Event), _dp, _dp, ctypes.c_uint, ctypes.c_uint64,
+        L.peo_tile_extrinsic.argtypes = [ctypes.POINTER(_Event), _dp, _dp, ctypes.c_uint, ctypes.c_int, ctypes.c_uint64,
                                          ctypes.c_uint32, ctypes.c_long, _dp, _dp, _dp]
         L.peo_tile_bank.restype = ctypes.c_long
         L.peo_tile_bank.argtypes = [ctypes.POINTER(_Event), _sp, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
@@ -320,9 +320,10 @@ class Event:
                                 ctypes.byref(used))
         return ty[:, :m].copy(), tth[:, :m].copy(), int(used.value)
 
-    def tile_extrinsic(self, theta0, g, sub_mask, seed, stream, theta, logq, logprior):
-        """Tile draws completed by the proposal's marginal over the coordinates outside sub_mask
-        (peo_tile_extrinsic): (rc, theta [D, n], logq [n], logprior [n]), new arrays."""
+    def tile_extrinsic(self, theta0, g, sub_mask, seed, stream, theta, logq, logprior, conditional=False):
+        """Tile draws completed by the proposal's marginal over the coordinates outside sub_mask, or by
+        their conditional given the draw's sub_mask coordinates (peo_tile_extrinsic):
+        (rc, theta [D, n], logq [n], logprior [n]), new arrays."""
         th0 = _f64(theta0)
         gg = _f64(g)
         th = np.array(theta, dtype=np.float64, order="C", copy=True)
@@ -330,8 +331,8 @@ class Event:
         lp = np.array(logprior, dtype=np.float64, copy=True)
         n = th.shape[1]
         assert th.shape == (self.dim, n) and lq.shape == (n,) and lp.shape == (n,)
-        rc = lib().peo_tile_extrinsic(self.ref, _p(th0), _p(gg), ctypes.c_uint(int(sub_mask)), int(seed),
-                                      int(stream), int(n), _p(th), _p(lq), _p(lp))
+        rc = lib().peo_tile_extrinsic(self.ref, _p(th0), _p(gg), ctypes.c_uint(int(sub_mask)), int(bool(conditional)),
+                                      int(seed), int(stream), int(n), _p(th), _p(lq), _p(lp))
         return rc, th, lq, lp
 
     # ---- relative binning ----

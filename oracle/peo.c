@@ -1068,8 +1068,133 @@ int peo_draw(const peo_event *ev, const double *th0, const double *g, uint64_t s
 
 /* Extrinsic coordinates of tile draws: the coordinates outside sub_mask drawn
  * from the proposal's marginal over them (declaration in peo.h). */
-int peo_tile_extrinsic(const peo_event *ev, const double *th0, const double *g, unsigned sub_mask, uint64_t seed,
-                       uint32_t stream, long n, double *theta, double *logq, double *logprior)
+/* The conditional form: the kept coordinates E (outside sub_mask and the
+ * marginalised ones M) given the tiled ones I, from N(theta0, g^-1) with M
+ * integrated out. Over A = I + E the covariance is the block C_AA of C = g^-1;
+ * E given I has mean theta0_E + C_EI C_II^-1 (theta_I - theta0_I) and covariance
+ * S = C_EE - C_EI C_II^-1 C_IE. Draws: y_E = Lp^-T z_E with Lp the Cholesky
+ * factor of S^-1 over E in index order and z the normals of peo_draw at the
+ * coordinates of E. */
+static int tile_extrinsic_cond(const peo_event *ev, const double *th0, const double *g, const int *is_m,
+                               unsigned sub_mask, uint64_t seed, uint32_t stream, long n, double *theta, double *logq,
+                               double *logprior)
+{
+    const int D = peo_dim(ev->params);
+    double C[PEO_MAX_DIM * PEO_MAX_DIM], CII[PEO_MAX_DIM * PEO_MAX_DIM] = {0}, CIIi[PEO_MAX_DIM * PEO_MAX_DIM];
+    double B[PEO_MAX_DIM * PEO_MAX_DIM], S[PEO_MAX_DIM * PEO_MAX_DIM], P[PEO_MAX_DIM * PEO_MAX_DIM];
+    double Lp[PEO_MAX_DIM * PEO_MAX_DIM], c0[PEO_MAX_DIM], per[3], per_e[3];
+    int I[PEO_MAX_DIM], E[PEO_MAX_DIM], pidx[3], pidx_e[3], nI = 0, nE = 0, np, np_e = 0, a, b, k, rc;
+    long i;
+    np = periodic_dims(ev, pidx, per);
+    for (a = 0; a < D; a++) {
+        if (sub_mask >> a & 1u)
+            I[nI++] = a;
+        else if (!is_m[a])
+            E[nE++] = a;
+    }
+    rc = spd_inverse(g, D, C);
+    if (rc)
+        return rc;
+    for (a = 0; a < nI; a++)
+        for (b = 0; b < nI; b++)
+            CII[a * nI + b] = C[I[a] * D + I[b]];
+    rc = spd_inverse(CII, nI, CIIi);
+    if (rc)
+        return rc;
+    /* B = C_EI C_II^-1, S = C_EE - B C_IE */
+    for (a = 0; a < nE; a++)
+        for (b = 0; b < nI; b++) {
+            double t = 0.0;
+            for (k = 0; k < nI; k++)
+                t += C[E[a] * D + I[k]] * CIIi[k * nI + b];
+            B[a * nI + b] = t;
+        }
+    for (a = 0; a < nE; a++)
+        for (b = 0; b < nE; b++) {
+            double t = C[E[a] * D + E[b]];
+            for (k = 0; k < nI; k++)
+                t -= B[a * nI + k] * C[I[k] * D + E[b]];
+            S[a * nE + b] = t;
+        }
+    for (a = 0; a < nE; a++)
+        for (b = 0; b < a; b++)
+            S[a * nE + b] = S[b * nE + a] = 0.5 * (S[a * nE + b] + S[b * nE + a]);
+    rc = spd_inverse(S, nE, P);
+    if (!rc)
+        rc = cholesky(P, nE, Lp);
+    if (rc)
+        return rc;
+    for (k = 0; k < np; k++)
+        for (a = 0; a < nE; a++)
+            if (E[a] == pidx[k]) {
+                pidx_e[np_e] = a;
+                per_e[np_e++] = per[k];
+            }
+    wrap_centre(ev, th0, c0);
+    for (i = 0; i < n; i++) {
+        double z[PEO_MAX_DIM + 1], y[PEO_MAX_DIM], th[PEO_MAX_DIM], m[PEO_MAX_DIM], tE[PEO_MAX_DIM];
+        int j, r, c;
+        for (j = 0; 2 * j < D; j++) {
+            double ua, ub, rad;
+            block_uniforms(seed, stream, (uint64_t)i, (uint32_t)j, &ua, &ub);
+            rad = sqrt(-2.0 * log(ua));
+            z[2 * j] = rad * cos(2.0 * PI * ub);
+            z[2 * j + 1] = rad * sin(2.0 * PI * ub);
+        }
+        for (a = 0; a < D; a++)
+            th[a] = theta[(long)a * n + i];
+        /* conditional mean, then y = Lp^-T z_E */
+        for (a = 0; a < nE; a++) {
+            double t = th0[E[a]];
+            for (k = 0; k < nI; k++)
+                t += B[a * nI + k] * (th[I[k]] - th0[I[k]]);
+            m[a] = t;
+        }
+        for (r = nE - 1; r >= 0; r--) {
+            double s = z[E[r]];
+            for (c = r + 1; c < nE; c++)
+                s -= Lp[c * nE + r] * y[c];
+            y[r] = s / Lp[r * nE + r];
+        }
+        for (a = 0; a < nE; a++)
+            th[E[a]] = m[a] + y[a];
+        for (a = 0; a < D; a++)
+            if (is_m[a])
+                th[a] = th0[a];
+        for (a = 0; a < np; a++) {
+            double Pp = per[a], v = th[pidx[a]];
+            th[pidx[a]] = v - Pp * floor(v / Pp);
+        }
+        for (a = 0; a < np_e; a++) {
+            const double Pp = per_e[a];
+            m[pidx_e[a]] -= Pp * floor(m[pidx_e[a]] / Pp);
+        }
+        if (D == 11 && ev->time_marg) {
+            double mt = c0[9], dlt[PEO_MAX_DIM];
+            for (a = 0; a < D; a++)
+                dlt[a] = th[a] - c0[a];
+            for (a = 0; a < np; a++) {
+                const double Pp = per[a];
+                dlt[pidx[a]] -= Pp * floor(dlt[pidx[a]] / Pp + 0.5);
+            }
+            for (a = 0; a < D; a++)
+                if (a != 9)
+                    mt -= g[9 * D + a] / g[9 * D + 9] * dlt[a];
+            th[9] = mt;
+        }
+        for (a = 0; a < D; a++)
+            theta[(long)a * n + i] = th[a];
+        for (a = 0; a < nE; a++)
+            tE[a] = th[E[a]];
+        logq[i] += logq_one(nE, Lp, m, tE, np_e, pidx_e, per_e);
+        if (logprior[i] != -INFINITY)
+            logprior[i] = peo_logprior(ev, th);
+    }
+    return 0;
+}
+
+int peo_tile_extrinsic(const peo_event *ev, const double *th0, const double *g, unsigned sub_mask, int conditional,
+                       uint64_t seed, uint32_t stream, long n, double *theta, double *logq, double *logprior)
 {
     const int D = peo_dim(ev->params);
     double L[PEO_MAX_DIM * PEO_MAX_DIM], c0[PEO_MAX_DIM], per[3];
@@ -1089,6 +1214,15 @@ int peo_tile_extrinsic(const peo_event *ev, const double *th0, const double *g, 
     for (a = 0; a < D; a++)
         if (sub_mask >> a & 1u)
             is_m[a] = 1;
+    if (conditional) {
+        int ism[PEO_MAX_DIM] = {0};
+        for (a = 0; a < k; a++)
+            ism[mm[a]] = 1;
+        for (a = 0; a < D; a++)
+            if ((sub_mask >> a & 1u) && ism[a])
+                return 1;
+        return tile_extrinsic_cond(ev, th0, g, ism, sub_mask, seed, stream, n, theta, logq, logprior);
+    }
     for (a = 0; a < D; a++)
         if (is_m[a])
             marg[nm++] = a;

@@ -177,10 +177,13 @@ int peo_slice_dims(const peo_event *ev, const peo_slice *sl, int *idx);
  * of peo_draw (Philox blocks (seed, stream, i, pair)) and the metric decoupled
  * at the sub_mask coordinates as at the marginalised ones; logq[i] gains that
  * marginal's log density (wrapped on periodic coordinates); logprior[i]
- * becomes the log prior of the composed draw, or stays -inf. Returns 0, or
- * nonzero when g is not positive definite (nothing written then). */
-int peo_tile_extrinsic(const peo_event *ev, const double *theta0, const double *g, unsigned sub_mask, uint64_t seed,
-                       uint32_t stream, long n, double *theta, double *logq, double *logprior);
+ * becomes the log prior of the composed draw, or stays -inf. With conditional
+ * set, the kept coordinates come instead from their conditional given the
+ * draw's sub_mask coordinates (the marginalised ones integrated out), and logq
+ * gains that conditional density. Returns 0, or nonzero when g is not positive
+ * definite or the mask is not allowed (nothing written then). */
+int peo_tile_extrinsic(const peo_event *ev, const double *theta0, const double *g, unsigned sub_mask, int conditional,
+                       uint64_t seed, uint32_t stream, long n, double *theta, double *logq, double *logprior);
 
 int peo_slice_candidate(const peo_event *ev, const peo_slice *sl, uint64_t seed, uint32_t stream, uint64_t i,
                         double *y, double *theta);

@@ -180,3 +180,96 @@ def test_extrinsic_rejects_periodic_or_empty_masks():
     for mask in (0, 0xF | (1 << 4), 1 << 7, 1 << 11):
         rc, *_ = b.ev.tile_extrinsic(th0, g, mask, 1, 0, th, np.zeros(4), np.zeros(4))
         assert rc != 0
+
+
+def _conditional(th0, g, thI, I, E):
+    """Mean and covariance of the coordinates E given those of I = thI under N(th0, g^-1), the other
+    coordinates integrated out: the covariance blocks of g^-1 (the definition)."""
+    C = np.linalg.inv(g)
+    B = C[np.ix_(E, I)] @ np.linalg.inv(C[np.ix_(I, I)])
+    m = th0[E] + B @ (thI - th0[I])
+    S = C[np.ix_(E, E)] - B @ C[np.ix_(I, E)]
+    return m, S
+
+
+def _wrapped_logpdf(x, m, S, E):
+    pk = [(j, PERIODS[k]) for j, k in enumerate(E) if k in PERIODS]
+    mw = np.array(m, dtype=np.float64)
+    for j, P in pk:
+        mw[j] -= P * math.floor(mw[j] / P)
+    terms = []
+    for img in np.ndindex(*([5] * len(pk))):
+        s = np.array(x, dtype=np.float64)
+        for (j, P), t in zip(pk, img):
+            s[j] += (t - 2) * P
+        terms.append(stats.multivariate_normal.logpdf(s, mw, S))
+    return logsumexp(terms)
+
+
+def test_conditional_extrinsic_density_is_the_wrapped_conditional():
+    b = build_event(1, 0, n_bins=4000)
+    th0 = b.theta_inj
+    g = b.ev.metric(th0)
+    n = 60
+    th = _intrinsic_inputs(th0, n, seed=4)
+    rc, t2, lq, lp = b.ev.tile_extrinsic(th0, g, INTRINSIC, 7, 3, th, np.zeros(n), np.zeros(n), conditional=True)
+    assert rc == 0
+    assert np.array_equal(t2[:4], th[:4])
+    I, E = [0, 1, 2, 3], list(range(4, 11))
+    for i in range(n):
+        m, S = _conditional(th0, g, th[:4, i], I, E)
+        # 1e-8: both sides invert blocks of g^-1, whose condition number here is ~1e9 (tc)
+        assert abs(lq[i] - _wrapped_logpdf(t2[E, i], m, S, E)) < 1e-8
+    for k, P in PERIODS.items():
+        assert np.all((t2[k] >= 0) & (t2[k] < P))
+
+
+def test_conditional_extrinsic_moments_follow_the_tiled_draw():
+    # every draw with the same intrinsic point, a narrow proposal: the extrinsic offsets from the
+    # conditional mean have the conditional covariance, narrower than the marginal's
+    b = build_event(1, 0, n_bins=4000)
+    th0 = b.theta_inj
+    g = 100.0 * b.ev.metric(th0)
+    n = 20000
+    thI = th0[:4] + np.array([2e-5, 0.01, -0.01, 0.005])
+    th = np.tile(th0[:, None], (1, n))
+    th[:4] = thI[:, None]
+    rc, t2, lq, lp = b.ev.tile_extrinsic(th0, g, INTRINSIC, 13, 0, th, np.zeros(n), np.zeros(n), conditional=True)
+    assert rc == 0
+    I, E = [0, 1, 2, 3], list(range(4, 11))
+    m, S = _conditional(th0, g, thI, I, E)
+    off = t2[E] - m[:, None]
+    for j, k in enumerate(E):
+        if k in PERIODS:
+            P = PERIODS[k]
+            off[j] -= P * np.floor(off[j] / P + 0.5)
+    W = np.linalg.cholesky(np.linalg.inv(S))
+    w = W.T @ off
+    assert np.all(np.abs(w.mean(1)) < 5.0 / math.sqrt(n))
+    assert np.abs(np.cov(w) - np.eye(len(E))).max() < 6.0 * math.sqrt(2.0 / n)
+    Cm = np.linalg.inv(g)[np.ix_(E, E)]
+    assert np.all(np.diag(S) <= np.diag(Cm) * (1 + 1e-12))
+    assert np.linalg.det(S) < 0.9 * np.linalg.det(Cm)
+
+
+def test_conditional_extrinsic_with_the_likelihood_marginals():
+    # time-, phase- and distance-marginalised: ra, dec, iota, psi given the intrinsic point, with tc,
+    # phic and dL integrated out
+    b = build_event(1, 0, n_bins=4000, phase=oracle.PHASE_MARG, distance=1,
+                    time_marg={"tc_lo": -0.02, "tc_hi": 0.02, "tm_points": 64})
+    th0 = b.theta_inj
+    g = b.ev.metric(th0)
+    n = 40
+    th = _intrinsic_inputs(th0, n, seed=6)
+    rc, t2, lq, lp = b.ev.tile_extrinsic(th0, g, INTRINSIC, 3, 1, th, np.zeros(n), np.zeros(n), conditional=True)
+    assert rc == 0
+    I, E = [0, 1, 2, 3], [4, 5, 6, 7]
+    for i in range(n):
+        m, S = _conditional(th0, g, th[:4, i], I, E)
+        assert abs(lq[i] - _wrapped_logpdf(t2[E, i], m, S, E)) < 1e-9
+    # the draw with the intrinsic point at the centre has the conditional mean at the centre
+    th[:4, 0] = th0[:4]
+    rc, t3, lq3, _ = b.ev.tile_extrinsic(th0, g, INTRINSIC, 3, 1, th[:, :1], np.zeros(1), np.zeros(1),
+                                         conditional=True)
+    m, S = _conditional(th0, g, th0[:4], I, E)
+    np.testing.assert_allclose(m, th0[E], rtol=0, atol=1e-12)
