@@ -94,7 +94,8 @@ def parse():
                     help="intrinsic tile leg: rounds per step (each later round reweights the tiles and takes the "
                          "other coordinates from the previous round's weighted moments)")
     ap.add_argument("--itile-time", type=int, default=1,
-                    help="intrinsic tile leg: 1 marginalises tc as well (as the time legs), 0 samples it")
+                    help="intrinsic tile leg: 1 marginalises tc as well (as the time legs) and runs a second leg "
+                         "with tc sampled; 0 runs only the leg with tc sampled")
     ap.add_argument("--itile-candidates", type=int, default=4000000,
                     help="intrinsic tile leg: slice candidates for the prior samples (0 skips the leg)")
     ap.add_argument("--no-distance-leg", action="store_true",
@@ -327,6 +328,9 @@ def main():
               "tm_points": int(math.ceil((hi - lo) / (0.5 / math.sqrt(g_tt)))) + 1}
         out["intrinsic_tiles"] = intrinsic_tile_leg(first, args, max(args.steps // 4, 2), prec,
                                                     time_marg=tm if args.itile_time else None)
+        if args.itile_time:
+            # the same chain with tc drawn with the extrinsic coordinates (no time marginal)
+            out["intrinsic_tiles_tc_sampled"] = intrinsic_tile_leg(first, args, max(args.steps // 4, 2), prec)
     for x in evs:
         x["ev"].close()
 
@@ -341,8 +345,9 @@ def main():
         cands["refined"] = out["refined"]["ess_per_s"]
     if "tiles" in out:
         cands["tiles"] = out["tiles"]["ess_per_s"]
-    if "intrinsic_tiles" in out:
-        cands["intrinsic_tiles"] = out["intrinsic_tiles"]["ess_per_s_chain"]
+    for k in ("intrinsic_tiles", "intrinsic_tiles_tc_sampled"):
+        if k in out:
+            cands[k] = out[k]["ess_per_s_chain"]
     best = max(cands, key=lambda k: cands[k])
     out["ess_per_s_best"] = {"value": cands[best], "leg": best}
     if c == 1 and not args.no_batch_leg:
@@ -779,25 +784,33 @@ def intrinsic_tile_leg(x, args, steps, prec, time_marg=None):
     ext = [4, 5, 6, 7] + ([] if time_marg else [9])  # the coordinates drawn besides the tiles
     print(f"intrinsic tiles: {M} templates, {y.shape[1]} samples, {R} rounds", file=sys.stderr, flush=True)
     t_rounds = np.zeros(R)
+    modes = ["marginal"] * R  # of the extrinsic completion, by round (last step)
     for i in range(-1, steps):  # step -1: untimed warm-up
         if i == 0:
             torch.cuda.synchronize()
             ta = time.perf_counter()
         s = max(i, 0)
         binding.pe_loglike_batch(h_, tth, M, prec, llt, None)
-        vals, c, gg = llt, th0, g
+        vals, c, gg, flags = llt, th0, g, 0
         for r in range(R):
             tr = time.perf_counter()
             thd, lq, lpd, idx = binding.tile_draw(vals, to, lp, th, x["seed"] + 7, R * s + r, N)
-            binding.pe_tile_extrinsic(h_, c, gg, 0xF, x["seed"] + 8, R * s + r, N, thd, lq, lpd)
+            binding.pe_tile_extrinsic(h_, c, gg, 0xF, flags, x["seed"] + 8, R * s + r, N, thd, lq, lpd)
             binding.pe_loglike_batch(h_, thd, N, prec, ll, None)
             binding.pe_weights_ess(ll, lpd, lq, N, w, st[s, r])
             if r + 1 < R:
+                # the next round: the tiles reweighted; the other coordinates from the weighted Gaussian of
+                # this round, given each draw's intrinsic point once the round has the effective samples
+                # to estimate that regression (20 per coordinate), else from its marginal
                 vals = binding.tile_reweight(vals, to, lp, idx, w, 0.1)
                 binding.pe_proposal_update(h_, thd, w, N, c, c2, cov)
+                keep = [0, 1, 2, 3] + ext
+                cond = float(st[s, r, 0]) >= 20 * len(keep)
+                sel = keep if cond else ext
                 gm = np.eye(11)
-                gm[np.ix_(ext, ext)] = np.linalg.inv(cov.cpu().numpy()[np.ix_(ext, ext)])
-                c, gg = c2.clone(), torch.from_numpy(gm).cuda()
+                gm[np.ix_(sel, sel)] = np.linalg.inv(cov.cpu().numpy()[np.ix_(sel, sel)])
+                c, gg, flags = c2.clone(), torch.from_numpy(gm).cuda(), binding.PE_TILE_CONDITIONAL if cond else 0
+                modes[r + 1] = "conditional" if cond else "marginal"
             if i >= 0:
                 torch.cuda.synchronize()
                 t_rounds[r] += time.perf_counter() - tr
@@ -826,12 +839,14 @@ def intrinsic_tile_leg(x, args, steps, prec, time_marg=None):
         "kind": ("tile mixture over (Mc, q, chi1z, chi2z), the other coordinates drawn apart; likelihood "
                  "marginalised over phase and distance" + (" and tc" if time_marg else "") + f"; {R} rounds per "
                  "step, each later round from the tiles reweighted by the previous one and the other coordinates "
-                 "from its weighted moments"),
+                 "from the previous round's weighted Gaussian, given each draw's intrinsic point once that round "
+                 "has 20 effective samples per coordinate"),
         "slice_radius": args.itile_radius, "spacing": args.itile_spacing, "templates": M, "bank_candidates": used,
         "prior_samples": int(y.shape[1]), "bank_ms": 1e3 * (t1 - t0), "samples_and_assign_ms": 1e3 * (t2 - t1),
         "steps": steps, "rounds": R, "draws_per_round": N, "ms_per_step": 1e3 * t_step,
         "ms_per_round": [float(1e3 * t / steps) for t in t_rounds],
-        "ess_per_event_by_round": [float(e) for e in ess], "efficiency_last_round": float(ess[-1]) / N,
+        "ess_per_event_by_round": [float(e) for e in ess], "extrinsic_by_round": modes,
+        "efficiency_last_round": float(ess[-1]) / N,
         "ess_last_round_min": float(s_[:, -1, 0].min()), "ess_last_round_max": float(s_[:, -1, 0].max()),
         "ess_per_s_last_round": float(ess[-1]) / t_last, "ess_per_s_chain": float(ess[-1]) / t_step,
         "gaussian_same_event": {"ms_per_step": 1e3 * t_g, "ess_per_event_mean": eg, "efficiency": eg / N,

@@ -494,13 +494,20 @@ pe_status_t pe_tile_draw(int32_t n_tiles, const double *tile_loglike_dev, int64_
  *   theta0_dev [D], g_dev [D*D] (device): the metric proposal whose marginal
  *   is taken. sub_mask: nonzero, bits below 11, none of the periodic
  *   coordinates ra, psi, phic (bits 4, 7, 10). 11-D events only.
+ * flags: PE_TILE_CONDITIONAL draws the other coordinates from their
+ * conditional given each draw's sub_mask coordinates instead (the
+ * marginalised ones integrated out): mean theta0_E + C_EI C_II^-1
+ * (theta_I - theta0_I), covariance C_EE - C_EI C_II^-1 C_IE with C = g^-1; log
+ * q gains that conditional density. sub_mask must then leave out the
+ * marginalised coordinates.
  * If g is not positive definite every draw gets logprior -inf (theta and logq
  * as they were) and pe_event_status reports PE_ERR_SINGULAR.
  * Errors: PE_ERR_ARG, PE_ERR_HIP.
  */
+#define PE_TILE_CONDITIONAL 1
 pe_status_t pe_tile_extrinsic(pe_event_t ev, const double *theta0_dev, const double *g_dev, uint32_t sub_mask,
-                              uint64_t seed, uint32_t stream_id, int64_t n, double *theta_dev, double *logq_dev,
-                              double *logprior_dev, void *stream);
+                              int32_t flags, uint64_t seed, uint32_t stream_id, int64_t n, double *theta_dev,
+                              double *logq_dev, double *logprior_dev, void *stream);
 
 /*
  * Tile values for the next round (the iterative update of the proposal that

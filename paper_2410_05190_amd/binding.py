@@ -149,7 +149,7 @@ def load(path=LIB_PATH):
         "pe_event_destroy": (i32, [vp]),
         "pe_metric": (i32, [vp, dp, dp, i32, dp, vp]),
         "pe_draw": (i32, [vp, dp, dp, u64, u32, i64, dp, dp, dp, vp]),
-        "pe_tile_extrinsic": (i32, [vp, dp, dp, u32, u64, u32, i64, dp, dp, dp, vp]),
+        "pe_tile_extrinsic": (i32, [vp, dp, dp, u32, i32, u64, u32, i64, dp, dp, dp, vp]),
         "pe_loglike_batch": (i32, [vp, dp, i64, i32, dp, dp, vp]),
         "pe_loglike_multi": (i32, [i32, vp, vp, vp, i32, vp, vp, vp]),
         "pe_batch_run": (i32, [i32, vp, i32, i32, vp]),
@@ -303,11 +303,14 @@ def pe_draw(ev, theta0, g, seed, stream_id, n, theta, logq, logprior, stream=Non
                         _ptr(logprior, f64, "logprior"), _stream(stream)))
 
 
-def pe_tile_extrinsic(ev, theta0, g, sub_mask, seed, stream_id, n, theta, logq, logprior, stream=None):
+PE_TILE_CONDITIONAL = 1
+
+
+def pe_tile_extrinsic(ev, theta0, g, sub_mask, flags, seed, stream_id, n, theta, logq, logprior, stream=None):
     import torch
     f64 = torch.float64
     _check(load().pe_tile_extrinsic(ev, _ptr(theta0, f64, "theta0"), _ptr(g, f64, "g"), int(sub_mask) & 0xFFFFFFFF,
-                                    int(seed) & 0xFFFFFFFFFFFFFFFF, int(stream_id) & 0xFFFFFFFF, int(n),
+                                    int(flags), int(seed) & 0xFFFFFFFFFFFFFFFF, int(stream_id) & 0xFFFFFFFF, int(n),
                                     _ptr(theta, f64, "theta"), _ptr(logq, f64, "logq"),
                                     _ptr(logprior, f64, "logprior"), _stream(stream)))
 
@@ -682,14 +685,16 @@ def tile_draw(tile_loglike, tile_of, sample_logprior, samples_theta, seed, strea
     return th, lq, lp, idx
 
 
-def tile_extrinsic(ev, theta0, g, sub_mask, theta, logq, logprior, seed, stream_id, stream=None):
+def tile_extrinsic(ev, theta0, g, sub_mask, theta, logq, logprior, seed, stream_id, conditional=False, stream=None):
     """pe_tile_extrinsic on copies: (theta [D, n], logq, logprior) of the composed draws (the
-    coordinates outside sub_mask drawn from the proposal's marginal over them)."""
+    coordinates outside sub_mask drawn from the proposal's marginal over them, or from their
+    conditional given each draw's sub_mask coordinates)."""
     th = theta.contiguous().clone()
     lq = logq.clone()
     lp = logprior.clone()
     n = th.shape[1]
-    pe_tile_extrinsic(ev.handle, theta0, g, sub_mask, seed, stream_id, n, th, lq, lp, stream)
+    pe_tile_extrinsic(ev.handle, theta0, g, sub_mask, PE_TILE_CONDITIONAL if conditional else 0, seed, stream_id, n,
+                      th, lq, lp, stream)
     return th, lq, lp
 
 

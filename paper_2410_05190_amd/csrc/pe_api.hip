@@ -934,20 +934,25 @@ pe_status_t pe_draw(pe_event_t ev, const double* theta0_dev, const double* g_dev
 }
 
 pe_status_t pe_tile_extrinsic(pe_event_t ev, const double* theta0_dev, const double* g_dev, uint32_t sub_mask,
-                              uint64_t seed, uint32_t stream_id, int64_t n, double* theta_dev, double* logq_dev,
-                              double* logprior_dev, void* stream) {
+                              int32_t flags, uint64_t seed, uint32_t stream_id, int64_t n, double* theta_dev,
+                              double* logq_dev, double* logprior_dev, void* stream) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
     if (ev->ec.dim != 11) return fail(PE_ERR_ARG, "the extrinsic completion takes an 11-D event");
     constexpr uint32_t periodic = (1u << 4) | (1u << 7) | (1u << 10);
     if (sub_mask == 0 || (sub_mask >> 11) != 0 || (sub_mask & periodic) != 0)
         return fail(PE_ERR_ARG, "sub_mask must be nonzero, below bit 11 and without ra, psi, phic");
+    if (flags & ~PE_TILE_CONDITIONAL) return fail(PE_ERR_ARG, "unknown flags");
+    const bool cond = (flags & PE_TILE_CONDITIONAL) != 0;
+    const uint32_t marg = (ev->ec.dist ? 1u << 8 : 0u) | (ev->ec.tm ? 1u << 9 : 0u);
+    if (cond && (sub_mask & marg) != 0)
+        return fail(PE_ERR_ARG, "a conditional completion cannot condition on a marginalised coordinate");
     pe_status_t s = check_n(n);
     if (s != PE_OK) return s;
     if (!theta0_dev || !g_dev) return fail(PE_ERR_ARG, "theta0 and g must be device pointers");
     if (n > 0 && (!theta_dev || !logq_dev || !logprior_dev)) return fail(PE_ERR_ARG, "draw arrays are NULL");
     if (n == 0) return PE_OK;
     DrawArg a = draw_arg(ev, theta0_dev, g_dev, seed, stream_id, n, theta_dev, logq_dev, logprior_dev);
-    a.dmask = sub_mask;
+    a.dmask = sub_mask | (cond ? kDrawCond : 0u);
     return run_draw(std::vector<DrawArg>(1, a), as_stream(stream), true);
 }
 

@@ -135,7 +135,10 @@ struct MetricArg {
 };
 
 // dmask: coordinates decoupled besides the likelihood's marginalised ones
-// (the tiled coordinates of an extrinsic completion; 0 for plain draws).
+// (the tiled coordinates of an extrinsic completion; 0 for plain draws). With
+// kDrawCond set in it, the other coordinates are drawn given the tiled ones
+// instead (their rows conditioned on, not integrated out).
+constexpr uint32_t kDrawCond = 1u << 31;
 struct DrawArg {
     EvConst ec;
     const double *theta0, *g;
@@ -397,7 +400,10 @@ constexpr int kCholRdiag = kCholLogdet + 8;
 // time-marginalised events: g_{tc,j} / g_{tc,tc} of the metric as given (the
 // conditional mean of tc given the other coordinates)
 constexpr int kCholTm = kCholRdiag + PE_MAX_DIM;
-constexpr int kCholLen = kCholTm + PE_MAX_DIM;
+// conditional extrinsic completion: the metric's coupling of the kept to the
+// tiled coordinates (after the marginalised ones are decoupled), D x D row-major
+constexpr int kCholCond = kCholTm + PE_MAX_DIM;
+constexpr int kCholLen = kCholCond + PE_MAX_DIM * PE_MAX_DIM;
 constexpr int64_t kMwsScan = kMwsChol + kCholLen;  // segment sums [kSegSums][n_det][kScanSeg]
 // per segment: pw (prefix scan), whitened data power, L1 and L2 of w, max pw
 constexpr int kSegSums = 5;

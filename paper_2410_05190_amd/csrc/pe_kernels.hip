@@ -663,7 +663,8 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
     const bool dist = (D == 11) && A.ec.dist;
     const bool pmarg = (D == 11) && A.ec.phase == PE_PHASE_MARG;
     const bool tmarg = (D == 11) && A.ec.tm;
-    const uint32_t dmask = (D == 11) ? A.dmask : 0u;
+    const uint32_t dmask = (D == 11) ? (A.dmask & ~kDrawCond) : 0u;
+    const bool cond = (D == 11) && (A.dmask & kDrawCond);
     if constexpr (D == 11) {
         // time-marginalised likelihood: tc is not drawn but set to its mean
         // given the other coordinates, from g_{tc,j} / g_{tc,tc} of g as given
@@ -671,7 +672,8 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
         for (int j = 0; j < D; ++j) A.chol[kCholTm + j] = (tmarg && j != 9 && g[9][9] > 0.0) ? g[9][j] / g[9][9] : 0.0;
 #pragma unroll
         for (int il = 0; il < D; ++il) {
-            const bool dec = ((dmask >> il) & 1u) || (il == 8 && dist) || (il == 9 && tmarg) || (il == 10 && pmarg);
+            const bool dec = (((dmask >> il) & 1u) && !cond) || (il == 8 && dist) || (il == 9 && tmarg) ||
+                             (il == 10 && pmarg);
             if (!dec) continue;
             const double gll = g[il][il];
             ok = ok && gll > 0.0;
@@ -683,6 +685,18 @@ __device__ __forceinline__ void cholesky_one(const DrawArg& A) {
 #pragma unroll
                 for (int j = 0; j < D; ++j)
                     g[i][j] = (i == il || j == il) ? ((i == j) ? gll : 0.0) : (ok ? g[i][j] - cl[i] * cl[j] / gll : g[i][j]);
+        }
+        if (cond) {
+            // conditioning on the tiled coordinates: their coupling to the others
+            // kept for the draws' mean shift, then their rows and columns cleared
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const bool ti = (dmask >> i) & 1u, tj = (dmask >> j) & 1u;
+                    A.chol[kCholCond + i * D + j] = (!ti && tj) ? g[i][j] : 0.0;
+                    if ((ti || tj) && i != j) g[i][j] = 0.0;
+                }
         }
     }
 #pragma unroll
@@ -752,11 +766,19 @@ __global__ __launch_bounds__(64) void k_cholesky(const BatchHdr* __restrict__ hd
 // Ext (extrinsic completion of tile draws): the coordinates of A.dmask keep the
 // values theta holds on entry, log q is added to the entry's value, and the log
 // prior stays -inf where it was.
+//
+// Ext with kDrawCond: the other coordinates given the tiled ones. With L the
+// factor of the metric conditioned on them (their rows cleared after the
+// marginalised coordinates are decoupled), the draw's mean moves by
+// delta = -(L L^T)^-1 r, r = (coupling) (theta_tiled - theta0_tiled): u = -L^-1 r,
+// delta = L^-T u; theta = theta0 + delta + L^-T z, and log q is the wrapped
+// density about theta0 + delta (the whitened offset is z again).
 template <int D, bool Ext = false>
 __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int64_t i) {
     const EvConst& ev = A.ec;
     const int64_t n = A.n;
-    const uint32_t dmask = Ext ? A.dmask : 0u;
+    const uint32_t dmask = Ext ? (A.dmask & ~kDrawCond) : 0u;
+    const bool cond = Ext && (A.dmask & kDrawCond);
     double th0[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) th0[a] = A.theta0[a];
@@ -788,9 +810,38 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
         for (int c = r + 1; c < D; ++c) s -= lc[c * D + r] * y[c];
         y[r] = s * lc[kCholRdiag + r];
     }
+    const bool distm = (D == 11) && ev.dist, pmargm = (D == 11) && ev.phase == PE_PHASE_MARG;
+    double yu[D];  // the conditional mean's shift (0 unless cond)
+#pragma unroll
+    for (int a = 0; a < D; ++a) yu[a] = 0.0;
+    if (cond) {
+        double u[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            double t = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                if ((dmask >> j) & 1u) t = fma(lc[kCholCond + r * D + j], A.theta[(int64_t)j * n + i] - th0[j], t);
+            double sr = -t;
+#pragma unroll
+            for (int k = 0; k < r; ++k) sr -= lc[r * D + k] * u[k];
+            u[r] = sr * lc[kCholRdiag + r];
+        }
+#pragma unroll
+        for (int r = D - 1; r >= 0; --r) {
+            double sr = u[r];
+#pragma unroll
+            for (int c = r + 1; c < D; ++c) sr -= lc[c * D + r] * yu[c];
+            yu[r] = sr * lc[kCholRdiag + r];
+        }
+    }
     double th[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) th[a] = ((dmask >> a) & 1u) ? A.theta[(int64_t)a * n + i] : th0[a] + y[a];
+    for (int a = 0; a < D; ++a) {
+        const bool margd = (a == 8 && distm) || (a == 10 && pmargm);  // unused by the likelihood
+        th[a] = ((dmask >> a) & 1u) ? A.theta[(int64_t)a * n + i]
+                                    : ((cond && margd) ? th0[a] : th0[a] + yu[a] + y[a]);
+    }
     constexpr int NP = (D == 4) ? 0 : 3;
     constexpr int pidx[3] = {4, 7, 10};
     const double per[3] = {kTwoPi, kPi, kTwoPi};
@@ -801,7 +852,7 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
         const double v = th[pidx[p]];
         const double kw = floor(v / per[p]);
         th[pidx[p]] = v - per[p] * kw;
-        k0[p] = kw - floor(th0[pidx[p]] / per[p]);
+        k0[p] = kw - floor((th0[pidx[p]] + yu[pidx[p]]) / per[p]);
     }
     const bool tmarg = (D == 11) && ev.tm;
     if (tmarg) {

@@ -81,7 +81,7 @@ def test_tile_entry_points_reject_bad_arguments_on_host():
     assert "dim" in binding.pe_last_error()
     assert L.pe_tile_assign(4, 0, None, 1, 0, None, 0, None, None) == 1
     assert L.pe_tile_draw(1, None, 1, None, None, 4, None, 1, 0, 0, 1, None, None, None, None, None) == 1
-    assert L.pe_tile_extrinsic(None, None, None, 0xF, 0, 0, 1, None, None, None, None) == 1
+    assert L.pe_tile_extrinsic(None, None, None, 0xF, 0, 0, 0, 1, None, None, None, None) == 1
     assert "event is NULL" in binding.pe_last_error()
 
 

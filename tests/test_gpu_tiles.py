@@ -265,12 +265,15 @@ def _extrinsic_inputs(b, so, n, seed):
     return thd, lq, lpd
 
 
+@pytest.mark.parametrize("conditional", [False, True])
 @pytest.mark.parametrize("case", ["explicit", "time_phase_distance"])
-def test_tile_extrinsic_against_the_oracle(case):
-    """The extrinsic completion on the same tile draws: composed draws (Philox normals, the metric
-    decoupled at the tiled coordinates) within 1e-12 of the oracle's, log q within 1e-10 (the GPU
-    decouples by successive Schur complements, the oracle inverts the covariance block), log prior
-    within 1e-12; draws without a sample keep logprior -inf."""
+def test_tile_extrinsic_against_the_oracle(case, conditional):
+    """The extrinsic completion on the same tile draws, marginal or conditional on each draw's
+    intrinsic point: composed draws (Philox normals, the metric decoupled or conditioned at the tiled
+    coordinates) within 1e-12 of the oracle's (1e-9 conditional: the mean shift passes through the
+    metric's conditioning), log q within 1e-10 (1e-8) (the GPU works in the precision by successive
+    Schur complements, the oracle from covariance blocks), log prior within 1e-12; draws without a
+    sample keep logprior -inf."""
     torch_cuda()
     if case == "explicit":
         b = build_event(1, 0, n_bins=2048)
@@ -282,19 +285,26 @@ def test_tile_extrinsic_against_the_oracle(case):
     n = 5000
     thd, lq, lpd = _extrinsic_inputs(b, so, n, 23)
     lpd[7] = -np.inf
-    note(f"tile extrinsic: {case}, n {n}")
-    rc, tho, lqo, lpo = b.ev.tile_extrinsic(b.theta_inj, g, INTRINSIC, 31, 4, thd, lq, lpd)
+    note(f"tile extrinsic: {case}, conditional {conditional}, n {n}")
+    rc, tho, lqo, lpo = b.ev.tile_extrinsic(b.theta_inj, g, INTRINSIC, 31, 4, thd, lq, lpd, conditional=conditional)
     assert rc == 0
-    th, lqg, lpg = binding.tile_extrinsic(ev, dev(b.theta_inj), dev(g), INTRINSIC, dev(thd), dev(lq), dev(lpd), 31, 4)
+    th, lqg, lpg = binding.tile_extrinsic(ev, dev(b.theta_inj), dev(g), INTRINSIC, dev(thd), dev(lq), dev(lpd), 31, 4,
+                                          conditional=conditional)
     ev.status()
     th, lqg, lpg = host(th), host(lqg), host(lpg)
     assert np.array_equal(th[:4], thd[:4])
-    np.testing.assert_allclose(th, tho, rtol=1e-12, atol=1e-12)
-    np.testing.assert_allclose(lqg, lqo, rtol=0, atol=1e-10)
+    tol_th, tol_q = (1e-9, 1e-8) if conditional else (1e-12, 1e-10)
+    # periodic coordinates compared on the circle
+    d = th - tho
+    for k, P in ((4, 2 * math.pi), (7, math.pi), (10, 2 * math.pi)):
+        d[k] -= P * np.round(d[k] / P)
+    assert np.all(np.abs(d) <= tol_th * np.maximum(1.0, np.abs(tho)))
+    np.testing.assert_allclose(lqg, lqo, rtol=0, atol=tol_q)
     assert lpg[7] == -np.inf and lpo[7] == -np.inf
     fin = np.isfinite(lpo)
     assert np.array_equal(np.isfinite(lpg), fin)
-    np.testing.assert_allclose(lpg[fin], lpo[fin], rtol=0, atol=1e-12)
+    # the log prior follows theta: ln cos dec + ln sin iota move by tan(dec) d(dec) + cot(iota) d(iota)
+    np.testing.assert_allclose(lpg[fin], lpo[fin], rtol=0, atol=1e-9 if conditional else 1e-12)
     ev.close()
 
 
@@ -308,12 +318,24 @@ def test_tile_extrinsic_rejects_bad_masks():
     for mask in (0, INTRINSIC | (1 << 4), 1 << 7, 1 << 11):
         with pytest.raises(binding.PeError):
             binding.tile_extrinsic(ev, dev(b.theta_inj), g, mask, th, z, z, 1, 0)
+    with pytest.raises(binding.PeError):  # unknown flags
+        binding.pe_tile_extrinsic(ev.handle, dev(b.theta_inj), g, INTRINSIC, 6, 1, 0, 4, th.clone(), z.clone(),
+                                  z.clone())
     # slices take 0 or four coordinates below bit 11
     for mask in (0x7, 0x1F, 0xF << 8):
         sl = binding.make_slice(b.theta_inj, np.eye(bin(mask).count("1")), 1.0, mask)
         with pytest.raises(binding.PeError):
             ev.slice_sample(sl, 1, 0, 0, 16)
     ev.close()
+    # a conditional completion cannot condition on a marginalised coordinate (dL here)
+    bd = build_event(1, 0, n_bins=1024, phase=oracle.PHASE_MARG, distance=1)
+    evd, datad, psdd = upload_event(bd)
+    thd_ = dev(np.tile(bd.theta_inj[:, None], (1, 4)))
+    gd_ = dev(bd.ev.metric(bd.theta_inj))
+    with pytest.raises(binding.PeError):
+        binding.tile_extrinsic(evd, dev(bd.theta_inj), gd_, INTRINSIC | (1 << 8), thd_, z, z, 1, 0, conditional=True)
+    binding.tile_extrinsic(evd, dev(bd.theta_inj), gd_, INTRINSIC | (1 << 8), thd_, z, z, 1, 0)  # marginal: allowed
+    evd.close()
     b4 = build_event(0, 0, n_bins=1024)
     ev4, data, psd = upload_event(b4)
     with pytest.raises(binding.PeError):
@@ -328,8 +350,9 @@ def test_intrinsic_tile_chain_on_the_gpu():
     through the library alone: a bank and prior samples over (Mc, q, chi1z, chi2z) in the proposal's
     marginal metric, nearest tiles, template likelihoods, tile draws completed by the metric
     proposal's marginal over the other coordinates, weights; then a second round from the reweighted
-    tiles with the other coordinates from the first round's weighted moments. The injection-centred
-    Gaussian on the same event beside it."""
+    tiles with the other coordinates from the first round's weighted moments (the first round's
+    ESS is too small to regress them on the intrinsic point). The injection-centred Gaussian on the
+    same event beside it."""
     torch = torch_cuda()
     b = build_event(1, 0, n_bins=60000, phase=oracle.PHASE_MARG, distance=1)
     ev, data, psd = upload_event(b)
