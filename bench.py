@@ -937,8 +937,7 @@ def serve_bench(args):
 
     from paper_2410_05190_amd import binding, synth
 
-    # a long-lived server starts from a clean device: the earlier legs' cached blocks go back first, so
-    # that the server's slab is not placed among them
+    # a long-lived server starts from a clean device: the earlier legs' cached blocks go back first
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     tr = synth.serving_trace(args.serve_events, args.serve_rate)
