@@ -569,52 +569,87 @@ __device__ __forceinline__ void split_item(const EvDev& E, const EvPlan& p, int 
     double sr[NDET], si[NDET];
 #pragma unroll
     for (int d = 0; d < NDET; ++d) sr[d] = si[d] = 0.0;
-    for (int c = g; c < p.n_fine; c += p.n_groups) {
-        const int k0 = c * p.fine;
-        if (k0 >= gmax) break;  // uniform over the workgroup
-        const int k1 = min(k0 + p.fine, K);
-        const bool on = k0 < wmax;  // this wave has cuts above the chunk's start
-        const int kA = on ? k0 + (max(0, min(wmin, k1) - k0) / kBlk) * kBlk : k0;
-        const int kB = on ? max(kA, min(k1, wmax)) : k0;
-        const int kl = min(k1, gmax);
-        for (int ks = k0; ks < kl; ks += kStage) {
-            const int ke = min(ks + kStage, kl);
-            __syncthreads();  // the previous piece has been read
-            const uint4* src = (const uint4*)(tab + ks);
-            uint4* dst = (uint4*)srec;
-            for (int q = threadIdx.x; q < (ke - ks) * (int)(sizeof(Rec32) / 16); q += 256) dst[q] = src[q];
-            __syncthreads();
-            for (int kb = ks; kb < min(ke, kA); kb += kBlk) {
-                float br[NDET], bi[NDET];
+    // bins [ks, ke) of a chunk whose records sit at sp[0 ..): full blocks below kA,
+    // then the masked blocks up to kB
+    auto piece = [&](const Rec32* sp, int ks, int ke, int kA, int kB) {
+        for (int kb = ks; kb < min(ke, kA); kb += kBlk) {
+            float br[NDET], bi[NDET];
 #pragma unroll
-                for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
+            for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
 #pragma unroll 4
-                for (int q = 0; q < kBlk; ++q) {
-                    const Rec32 r = srec[kb - ks + q];
-                    bin_split<NDET, false>(r, row, tau, true, br, bi);
-                }
+            for (int q = 0; q < kBlk; ++q) {
+                const Rec32 r = sp[kb - ks + q];
+                bin_split<NDET, false>(r, row, tau, true, br, bi);
+            }
+#pragma unroll
+            for (int d = 0; d < NDET; ++d) {
+                sr[d] += (double)br[d];
+                si[d] += (double)bi[d];
+            }
+        }
+        for (int kb = max(ks, kA); kb < min(ke, kB); kb += kBlk) {
+            const int kq = min(kb + kBlk, kB);
+            float br[NDET], bi[NDET];
+#pragma unroll
+            for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
+            for (int k = kb; k < kq; ++k) {
+                const Rec32 r = sp[k - ks];
+                bin_split<NDET, true>(r, row, tau, k < kc, br, bi);
+            }
+            if (kb < kc) {
 #pragma unroll
                 for (int d = 0; d < NDET; ++d) {
                     sr[d] += (double)br[d];
                     si[d] += (double)bi[d];
                 }
             }
-            for (int kb = max(ks, kA); kb < min(ke, kB); kb += kBlk) {
-                const int kq = min(kb + kBlk, kB);
-                float br[NDET], bi[NDET];
-#pragma unroll
-                for (int d = 0; d < NDET; ++d) br[d] = bi[d] = 0.0f;
-                for (int k = kb; k < kq; ++k) {
-                    const Rec32 r = srec[k - ks];
-                    bin_split<NDET, true>(r, row, tau, k < kc, br, bi);
-                }
-                if (kb < kc) {
-#pragma unroll
-                    for (int d = 0; d < NDET; ++d) {
-                        sr[d] += (double)br[d];
-                        si[d] += (double)bi[d];
-                    }
-                }
+        }
+    };
+    // the wave's full and masked ranges of a chunk starting at k0
+    auto ranges = [&](int k0, int k1, int& kA, int& kB) {
+        const bool on = k0 < wmax;  // this wave has cuts above the chunk's start
+        kA = on ? k0 + (max(0, min(wmin, k1) - k0) / kBlk) * kBlk : k0;
+        kB = on ? max(kA, min(k1, wmax)) : k0;
+    };
+    int nci = 0;  // the item's chunks below the workgroup's largest cut
+    for (int c = g; c < p.n_fine && c * p.fine < gmax; c += p.n_groups) ++nci;
+    if (nci > 0 && nci * p.fine <= kStage) {
+        // short chunks (short bands, many groups): all of the item's chunks staged at
+        // once, chunk i at record i * fine, one pair of barriers for the item; the
+        // bins and their order per lane are those of the piecewise walk below
+        constexpr int kParts = (int)(sizeof(Rec32) / 16);
+        const int per = p.fine * kParts;
+        __syncthreads();  // the previous item's records have been read
+        for (int q = threadIdx.x; q < nci * per; q += 256) {
+            const int i = q / per, r = q - i * per;
+            const int k0 = (g + i * p.n_groups) * p.fine;
+            const int k = k0 + r / kParts;
+            if (k < min(min(k0 + p.fine, K), gmax)) ((uint4*)srec)[q] = ((const uint4*)(tab + k))[r % kParts];
+        }
+        __syncthreads();
+        for (int i = 0; i < nci; ++i) {
+            const int k0 = (g + i * p.n_groups) * p.fine;
+            const int k1 = min(k0 + p.fine, K);
+            int kA, kB;
+            ranges(k0, k1, kA, kB);
+            piece(srec + i * p.fine, k0, min(k1, gmax), kA, kB);
+        }
+    } else {
+        for (int c = g; c < p.n_fine; c += p.n_groups) {
+            const int k0 = c * p.fine;
+            if (k0 >= gmax) break;  // uniform over the workgroup
+            const int k1 = min(k0 + p.fine, K);
+            int kA, kB;
+            ranges(k0, k1, kA, kB);
+            const int kl = min(k1, gmax);
+            for (int ks = k0; ks < kl; ks += kStage) {
+                const int ke = min(ks + kStage, kl);
+                __syncthreads();  // the previous piece has been read
+                const uint4* src = (const uint4*)(tab + ks);
+                uint4* dst = (uint4*)srec;
+                for (int q = threadIdx.x; q < (ke - ks) * (int)(sizeof(Rec32) / 16); q += 256) dst[q] = src[q];
+                __syncthreads();
+                piece(srec, ks, ke, kA, kB);
             }
         }
     }
