@@ -116,14 +116,15 @@ __device__ __forceinline__ double f_isco(double M) { return 1.0 / (kSix32 * kPi 
 __device__ __forceinline__ int mass_and_support(const EvConst& ev, const double* th, double& M) {
     if (ev.params == PE_PARAMS_4D) {
         const double mc = th[0], eta = th[1], chi = th[2];
-        M = mc * pow(eta, -0.6);
+        M = mc * exp(-0.6 * log(eta));  // eta^(-3/5)
         return (mc > 0.0) && (eta > 0.0) && (eta <= 0.25) && (fabs(chi) <= ev.chi_max);
     }
     const double mc = th[0], q = th[1], c1 = th[2], c2 = th[3];
     const double dec = th[5], iota = th[6], dl = th[8];
-    // M = Mc (1+q)^(6/5) q^(-3/5) = Mc eta^(-3/5), eta = q/(1+q)^2: one pow
+    // M = Mc (1+q)^(6/5) q^(-3/5) = Mc eta^(-3/5), eta = q/(1+q)^2 (as exp and
+    // log: a third cheaper than pow, within a few ulp of it)
     const double opq = 1.0 + q;
-    M = mc * pow(q / (opq * opq), -0.6);
+    M = mc * exp(-0.6 * log(q / (opq * opq)));
     return (mc > 0.0) && (q > 0.0) && (q <= 1.0) && (fabs(c1) <= ev.chi_max) && (fabs(c2) <= ev.chi_max) &&
            (fabs(dec) <= 0.5 * kPi) && (iota >= 0.0) && (iota <= kPi) &&
            (ev.dist || ((dl > 0.0) && (dl <= ev.dl_max)));
@@ -179,8 +180,9 @@ __device__ __forceinline__ int source_from_theta(const EvConst& ev, const double
         s.tc = th[9];
         s.phic = (ev.phase == PE_PHASE_EXPLICIT) ? th[10] : 0.0;
         // Newtonian stationary-phase amplitude sqrt(5/24) pi^(-2/3) Mc^(5/6) / dL, times the unit scale
-        const double amp =
-            kAmpNewt * pow(mc * kTsun, 5.0 / 6.0) / (dl * (kMpc / kC)) * ev.scale;
+        // (Mc)^(5/6) = sqrt(Mc) cbrt(Mc): a quarter of pow's instructions
+        const double mct = mc * kTsun;
+        const double amp = kAmpNewt * (sqrt(mct) * cbrt(mct)) / (dl * (kMpc / kC)) * ev.scale;
         const double ci = cos(iota);
         const double hp = 0.5 * (1.0 + ci * ci), hx = ci;
         const SkyFrame fr = sky_frame(ev, ra, dec, psi);
@@ -310,8 +312,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
                                               uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        // each 32 x 32 -> 64-bit product as one instruction (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
@@ -334,6 +338,33 @@ __device__ __forceinline__ void block_uniforms(uint64_t seed, uint32_t stream, u
     ub = u53(c2, c3);
 }
 
+// Coefficients of the two Bessel series below, so that their terms follow by
+// products instead of divisions: 1/k^2 and 1/(k (k+1)) (power series, DLMF
+// 10.25.2: the ratio of term k to term k-1 is (x^2/4)/k^2), and (2k-1)^2/(8k)
+// and ((2k-1)^2 - 4)/(8k) (Hankel series of I0 and I1, DLMF 10.40.1, ratio to
+// the previous term over x). Each is the correctly rounded quotient.
+constexpr int kI0Pow = 400, kI0Hank = 64;
+struct BesselTab {
+    double ik2[kI0Pow];     // [k] = 1 / k^2 (k >= 1)
+    double ikk1[kI0Pow];    // [k] = 1 / (k (k + 1))
+    double h0[kI0Hank];     // [k] = (2k - 1)^2 / (8k)
+    double h1[kI0Hank];     // [k] = ((2k - 1)^2 - 4) / (8k)
+};
+constexpr BesselTab make_bessel_tab() {
+    BesselTab t{};
+    for (int k = 1; k < kI0Pow; ++k) {
+        t.ik2[k] = 1.0 / ((double)k * (double)k);
+        t.ikk1[k] = 1.0 / ((double)k * (double)(k + 1));
+    }
+    for (int k = 1; k < kI0Hank; ++k) {
+        const double m = (2.0 * k - 1.0) * (2.0 * k - 1.0);
+        t.h0[k] = m / (8.0 * k);
+        t.h1[k] = (m - 4.0) / (8.0 * k);
+    }
+    return t;
+}
+__constant__ constexpr BesselTab kBessel = make_bessel_tab();
+
 // ln I0(x): power series (DLMF 10.25.2) below 30, Hankel asymptotic series
 // (DLMF 10.40.1) above, where its smallest term is below e^-60.
 __device__ __forceinline__ double log_i0(double x) {
@@ -341,8 +372,8 @@ __device__ __forceinline__ double log_i0(double x) {
     if (x < 30.0) {
         const double y = 0.25 * x * x;
         double term = 1.0, sum = 1.0;
-        for (int k = 1; k < 400; ++k) {
-            term *= y / ((double)k * (double)k);
+        for (int k = 1; k < kI0Pow; ++k) {
+            term *= y * kBessel.ik2[k];
             sum += term;
             if (term < 1e-17 * sum) break;
         }
@@ -350,8 +381,8 @@ __device__ __forceinline__ double log_i0(double x) {
     }
     const double inv = 1.0 / x;
     double term = 1.0, sum = 1.0;
-    for (int k = 1; k < 64; ++k) {
-        const double tk = term * (2.0 * k - 1.0) * (2.0 * k - 1.0) / (8.0 * k) * inv;
+    for (int k = 1; k < kI0Hank; ++k) {
+        const double tk = term * kBessel.h0[k] * inv;
         if (tk > term) break;
         term = tk;
         sum += term;
@@ -366,9 +397,9 @@ __device__ __forceinline__ double i1_over_i0(double y) {
     if (y < 30.0) {
         const double q = 0.25 * y * y;
         double t0 = 1.0, s0 = 1.0, t1 = 1.0, s1 = 1.0;  // I0 = s0, I1 = (y/2) s1
-        for (int k = 1; k < 400; ++k) {
-            t0 *= q / ((double)k * (double)k);
-            t1 *= q / ((double)k * (double)(k + 1));
+        for (int k = 1; k < kI0Pow; ++k) {
+            t0 *= q * kBessel.ik2[k];
+            t1 *= q * kBessel.ikk1[k];
             s0 += t0;
             s1 += t1;
             if (t0 < 1e-17 * s0) break;
@@ -377,9 +408,8 @@ __device__ __forceinline__ double i1_over_i0(double y) {
     }
     const double inv = 1.0 / y;
     double t0 = 1.0, s0 = 1.0, t1 = 1.0, s1 = 1.0;
-    for (int k = 1; k < 64; ++k) {
-        const double m = (2.0 * k - 1.0) * (2.0 * k - 1.0);
-        const double n0 = t0 * m / (8.0 * k) * inv, n1 = t1 * (m - 4.0) / (8.0 * k) * inv;
+    for (int k = 1; k < kI0Hank; ++k) {
+        const double n0 = t0 * kBessel.h0[k] * inv, n1 = t1 * kBessel.h1[k] * inv;
         if (fabs(n0) > fabs(t0)) break;
         t0 = n0;
         t1 = n1;

@@ -920,47 +920,75 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
             const double C = zz + 2.0 * (o0 * a[0] + o1 * a[1] + o2 * a[2]) + (o0 * go0 + o1 * go1 + o2 * go2);
             const double b[3] = {a[0] + go0, a[1] + go1, a[2] + go2};
             const double gpp[3] = {g00, g11, g22};
+            // phic marginalised: its only image is t_2 = 0 (index 2), whose
+            // factor is exp(0) = 1 and whose pair factors are exp(0) = 1
+            const int np = pmarg ? 2 : 3;
             double f[3][5], V = 0.0;
 #pragma unroll
             for (int p = 0; p < 3; ++p) {
+                if (p >= np) break;
                 const double h = -0.5 * gpp[p] * per[p] * per[p];
                 double v[5], Vp = -INFINITY;
 #pragma unroll
                 for (int t = 0; t < 5; ++t) {
                     const double tt = (double)(t - 2);
                     v[t] = -per[p] * tt * b[p] + h * tt * tt;
-                    if (!(p == 2 && pmarg && t != 2)) Vp = fmax(Vp, v[t]);
+                    Vp = fmax(Vp, v[t]);
                 }
 #pragma unroll
-                for (int t = 0; t < 5; ++t) f[p][t] = (p == 2 && pmarg && t != 2) ? 0.0 : exp(v[t] - Vp);
+                for (int t = 0; t < 5; ++t) f[p][t] = exp(v[t] - Vp);
                 V += Vp;
             }
             // x_pq[j] = exp(-gam_pq (j - 4)), j - 4 = t_p t_q in -4..4
-            double x01[9], x02[9], x12[9];
-            const double e01 = exp(-gam01), e02 = exp(-gam02), e12 = exp(-gam12);
-            x01[4] = x02[4] = x12[4] = 1.0;
+            double x01[9];
+            const double e01 = exp(-gam01), i01 = 1.0 / e01;
+            x01[4] = 1.0;
 #pragma unroll
-            for (int j = 1; j <= 4; ++j) {
-                x01[4 + j] = x01[3 + j] * e01;
-                x02[4 + j] = x02[3 + j] * e02;
-                x12[4 + j] = x12[3 + j] * e12;
-            }
-            const double i01 = 1.0 / e01, i02 = 1.0 / e02, i12 = 1.0 / e12;
+            for (int j = 1; j <= 4; ++j) x01[4 + j] = x01[3 + j] * e01;
 #pragma unroll
-            for (int j = 1; j <= 4; ++j) {
-                x01[4 - j] = x01[5 - j] * i01;
-                x02[4 - j] = x02[5 - j] * i02;
-                x12[4 - j] = x12[5 - j] * i12;
-            }
+            for (int j = 1; j <= 4; ++j) x01[4 - j] = x01[5 - j] * i01;
+            if (pmarg) {
+                // sum over t_0, t_1 of f_0 f_1 x01, nested over t_1
 #pragma unroll
-            for (int t0 = 0; t0 < 5; ++t0)
+                for (int t0 = 0; t0 < 5; ++t0) {
+                    double s1 = 0.0;
 #pragma unroll
-                for (int t1 = 0; t1 < 5; ++t1) {
-                    const double f01 = f[0][t0] * f[1][t1] * x01[4 + (t0 - 2) * (t1 - 2)];
-#pragma unroll
-                    for (int t2 = 0; t2 < 5; ++t2)
-                        acc += f01 * f[2][t2] * x02[4 + (t0 - 2) * (t2 - 2)] * x12[4 + (t1 - 2) * (t2 - 2)];
+                    for (int t1 = 0; t1 < 5; ++t1) s1 = fma(f[1][t1], x01[4 + (t0 - 2) * (t1 - 2)], s1);
+                    acc = fma(f[0][t0], s1, acc);
                 }
+            } else {
+                double x02[9], x12[9];
+                const double e02 = exp(-gam02), e12 = exp(-gam12);
+                x02[4] = x12[4] = 1.0;
+#pragma unroll
+                for (int j = 1; j <= 4; ++j) {
+                    x02[4 + j] = x02[3 + j] * e02;
+                    x12[4 + j] = x12[3 + j] * e12;
+                }
+                const double i02 = 1.0 / e02, i12 = 1.0 / e12;
+#pragma unroll
+                for (int j = 1; j <= 4; ++j) {
+                    x02[4 - j] = x02[5 - j] * i02;
+                    x12[4 - j] = x12[5 - j] * i12;
+                }
+                // nested: for each t_0, y(t_2) = f_2 x02; for each t_1 the sum over
+                // t_2 of y x12, weighted by f_1 x01; then by f_0
+#pragma unroll
+                for (int t0 = 0; t0 < 5; ++t0) {
+                    double y[5];
+#pragma unroll
+                    for (int t2 = 0; t2 < 5; ++t2) y[t2] = f[2][t2] * x02[4 + (t0 - 2) * (t2 - 2)];
+                    double s1 = 0.0;
+#pragma unroll
+                    for (int t1 = 0; t1 < 5; ++t1) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int t2 = 0; t2 < 5; ++t2) s2 = fma(y[t2], x12[4 + (t1 - 2) * (t2 - 2)], s2);
+                        s1 = fma(f[1][t1] * x01[4 + (t0 - 2) * (t1 - 2)], s2, s1);
+                    }
+                    acc = fma(f[0][t0], s1, acc);
+                }
+            }
             mx = -0.5 * C + V;
         }
     }
