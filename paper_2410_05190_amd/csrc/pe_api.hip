@@ -629,10 +629,12 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     if (ne == 0) return PE_OK;
     std::vector<int64_t> poff(ne + 1, 0), foff(ne + 1, 0);
     bool any_dist = false;
+    int max_det = 0;
     for (int e = 0; e < ne; ++e) {
         poff[e + 1] = poff[e] + ((v[e].flags & kLlPrologue) ? blocks256(v[e].n) : 0);
         foff[e + 1] = foff[e] + ((v[e].flags & kLlFinalize) ? blocks256(v[e].n) : 0);
         any_dist = any_dist || v[e].ec.dist;
+        max_det = std::max(max_det, v[e].ec.n_det);
     }
     Area& A = area_for(st, kAreaLoglike);
     std::lock_guard<std::mutex> lk(A.mu);
@@ -640,7 +642,7 @@ pe_status_t run_loglike(const std::vector<EvDev>& v, int precision, hipStream_t 
     pe_status_t s = upload_area(A, ne, poff[ne], foff[ne], v.data(), sizeof(EvDev) * ne, poff, &foff,
                                 loglike_scratch_bytes(ne), st, b);
     if (s != PE_OK) return s;
-    PE_HIP(launch_loglike_batch(b, ne, poff[ne], foff[ne], precision, true, any_dist, st));
+    PE_HIP(launch_loglike_batch(b, ne, poff[ne], foff[ne], precision, true, any_dist, max_det, st));
     return PE_OK;
 }
 

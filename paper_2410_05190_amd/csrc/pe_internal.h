@@ -366,9 +366,11 @@ hipError_t launch_prep_batch(const BatchPtrs &b, int ne, int64_t total_blocks, i
                              int max_seg, int max_det, hipStream_t st);
 hipError_t launch_metric_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
 hipError_t launch_draw_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st, bool ext = false);
-// any_dist: some event of the batch is distance-marginalised (adds k_b_dist).
+// any_dist: some event of the batch is distance-marginalised (adds k_b_dist);
+// max_det: no event of the batch has more detectors (at most 2: the FP64
+// re-evaluation's two-detector kernel).
 hipError_t launch_loglike_batch(const BatchPtrs &b, int ne, int64_t prologue_blocks, int64_t finalize_blocks,
-                                int precision, bool profile, bool any_dist, hipStream_t st);
+                                int precision, bool profile, bool any_dist, int max_det, hipStream_t st);
 hipError_t launch_weights_batch(const BatchPtrs &b, int ne, int64_t total_blocks, int64_t total_draw_blocks,
                                 hipStream_t st);
 hipError_t launch_update_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);

@@ -1001,25 +1001,41 @@ __global__ __launch_bounds__(256) void k_r_scatter(const BatchHdr* __restrict__ 
     }
 }
 
-// Per queue: offsets of every event's re-evaluation items, the item total and
-// the counter reset (the main hot loop has finished with the queues).
-__global__ __launch_bounds__(kRedoTile) void k_r_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
-                                               const int64_t* __restrict__ ioff) {
+// The re-evaluation's persistent walk over the listed draws' items, for events of
+// up to MAXD detectors.
+template <int MAXD>
+__device__ __forceinline__ void redo_items(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                           const int64_t* __restrict__ ioff, Rec64* srec) {
     int items = 0;
 #pragma unroll
     for (int q = 0; q < kQueues; ++q) items += hdr->qitems[q];
     if (items == 0) return;  // nothing listed (uniform over the grid)
-    __shared__ Rec64 srec[kRedoTile];
     item_loop<true>(hdr, ioff, evs, [&](const Item& it) {
         const EvDev& E = evs[it.e];
         const EvPlan rp = load_const(E.plan + 1);
         switch (E.ec.n_det) {
             case 1: redo_item<1>(E, rp, it.tile, it.g, srec); break;
             case 2: redo_item<2>(E, rp, it.tile, it.g, srec); break;
-            case 3: redo_item<3>(E, rp, it.tile, it.g, srec); break;
-            default: redo_item<4>(E, rp, it.tile, it.g, srec); break;
+            case 3: if (MAXD >= 3) redo_item<3>(E, rp, it.tile, it.g, srec); break;
+            default: if (MAXD >= 4) redo_item<4>(E, rp, it.tile, it.g, srec); break;
         }
     });
+}
+
+__global__ __launch_bounds__(kRedoTile) void k_r_f64(BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs,
+                                               const int64_t* __restrict__ ioff) {
+    __shared__ Rec64 srec[kRedoTile];
+    redo_items<PE_MAX_DET>(hdr, evs, ioff, srec);
+}
+
+// Batches whose events have at most two detectors: without the three- and
+// four-detector bodies the walk fits 128 registers, four waves per SIMD instead
+// of three (the walk's FP64 sine/cosine chains are latency-bound). Same
+// arithmetic per draw as k_r_f64.
+__global__ __launch_bounds__(kRedoTile) __attribute__((amdgpu_waves_per_eu(4))) void k_r_f64_2det(
+    BatchHdr* __restrict__ hdr, const EvDev* __restrict__ evs, const int64_t* __restrict__ ioff) {
+    __shared__ Rec64 srec[kRedoTile];
+    redo_items<2>(hdr, evs, ioff, srec);
 }
 
 // ln L of the re-evaluated draws from their FP64 partials, combined exactly as
@@ -1211,6 +1227,10 @@ static unsigned redo_grid() {
     static const unsigned grid = resident_grid(k_r_f64, kRedoTile);
     return grid;
 }
+static unsigned redo_grid_2det() {
+    static const unsigned grid = resident_grid(k_r_f64_2det, kRedoTile);
+    return grid;
+}
 
 // Evaluates the hot loop's resident grids (device queries) ahead of any graph
 // capture.
@@ -1218,10 +1238,11 @@ void prime_hot_grids() {
     (void)split_grid();
     (void)f64_grid();
     (void)redo_grid();
+    (void)redo_grid_2det();
 }
 
 hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blocks, int64_t finalize_blocks,
-                                int precision, bool profile, bool any_dist, hipStream_t st) {
+                                int precision, bool profile, bool any_dist, int max_det, hipStream_t st) {
     if (ne <= 0) return hipSuccess;
     const EvDev* evs = (const EvDev*)b.args;
     int64_t* ioff = (int64_t*)b.scratch;
@@ -1257,7 +1278,10 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
             k_r_scatter<<<fg, 256, 0, st>>>(b.hdr, evs, b.off2);
             k_items<true><<<1, kItemThreads, 0, st>>>(b.hdr, evs, ioff);
             if (profile) prof_begin("loglike_redo", st);
-            k_r_f64<<<redo_grid(), kRedoTile, 0, st>>>(b.hdr, evs, ioff);
+            if (max_det <= 2)
+                k_r_f64_2det<<<redo_grid_2det(), kRedoTile, 0, st>>>(b.hdr, evs, ioff);
+            else
+                k_r_f64<<<redo_grid(), kRedoTile, 0, st>>>(b.hdr, evs, ioff);
             if (profile) prof_end("loglike_redo", st);
             k_r_finalize<<<fg, 256, 0, st>>>(b.hdr, evs, b.off2);
         } else {

@@ -330,7 +330,7 @@ pe_status_t pe_server_s::capture(const BatchPtrs& bll, const BatchPtrs& bw) {
     hipGraph_t g = nullptr;
     PE_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     // the captured slice serves every later mix of requests: it keeps the distance pass
-    hipError_t e = launch_loglike_batch(bll, cap_ne, 0, cap_fblocks, cfg.precision, false, true, st);
+    hipError_t e = launch_loglike_batch(bll, cap_ne, 0, cap_fblocks, cfg.precision, false, true, PE_MAX_DET, st);
     if (e == hipSuccess) e = launch_weights_batch(bw, cap_ne, cap_wblocks, cap_dblocks, st);
     hipError_t e2 = hipStreamEndCapture(st, &g);
     if (e != hipSuccess) return fail(PE_ERR_HIP, std::string("slice capture: ") + hipGetErrorString(e));
@@ -403,7 +403,7 @@ pe_status_t pe_server_s::slice() {
         PE_HIP(hipGraphLaunch(graph, st));
         ++n_replays;
     } else {
-        PE_HIP(launch_loglike_batch(bll, ne, 0, foff[ne], cfg.precision, false, true, st));
+        PE_HIP(launch_loglike_batch(bll, ne, 0, foff[ne], cfg.precision, false, true, PE_MAX_DET, st));
         PE_HIP(launch_weights_batch(bw, nw, boff[nw], doff[nw], st));
     }
     PE_HIP(hipEventRecord(ev_b, st));
