@@ -350,8 +350,10 @@ def main():
             cands[k] = out[k]["ess_per_s_chain"]
     best = max(cands, key=lambda k: cands[k])
     out["ess_per_s_best"] = {"value": cands[best], "leg": best}
+    c2_inputs = None
     if c == 1 and not args.no_batch_leg:
         out["config2"] = batch_leg(2, max(args.steps, 1), prec)
+        c2_inputs = out["config2"].pop("_cpu_inputs")
     if c == 1 and args.long_steps > 0:
         out["config4"] = long_leg(args.long_steps, args.long_loud_snr, prec)
     if args.serve_events > 0:
@@ -363,6 +365,8 @@ def main():
             out["cpu_baseline"]["config0_full"] = cpu_config0()
             if "config4" in out:
                 out["cpu_baseline"]["config4_sample"] = out["config4"]["snr_43"]["drift"]["oracle_rate"]
+            if c2_inputs:
+                out["cpu_baseline"]["config2_sample"] = cpu_config2(c2_inputs)
     print(json.dumps(out), flush=True)
 
 
@@ -427,9 +431,13 @@ def batch_leg(c, steps, prec):
     s = st.cpu().numpy()
     wall = t1 - t0
     redo = [binding.pe_loglike_counts(x["ev"]) for x in evs]
+    # the first four events' data and draw counts, for the oracle's timing of the same events
+    cpu_inputs = [dict(data=x["data"].cpu().numpy(), psd=x["psd"].cpu().numpy(), theta_inj=x["theta_inj"],
+                       amp0=x["amp0"], common=x["common"], N=x["N"]) for x in evs[:4]]
     for x in evs:
         x["ev"].close()
-    return {"workload": cfg["name"], "events_per_step": n_ev, "draws_per_step": int(sum(Ns)),
+    return {"_cpu_inputs": cpu_inputs,
+            "workload": cfg["name"], "events_per_step": n_ev, "draws_per_step": int(sum(Ns)),
             "n_bins": synth.grid(c)[2], "n_det": cfg["n_det"], "steps": steps, "ms_per_step": 1e3 * wall / steps,
             "evals_per_s": float(s[:, :, 3].sum()) / wall, "ess_per_s": float(s[:, :, 0].sum()) / wall,
             "ess_per_event_mean": float(s[:, :, 0].mean()), "hot_kernel_ms_avg": k_ms / max(k_n, 1),
@@ -1135,6 +1143,36 @@ def cpu_baseline(c, n_sample, data, psd_t, theta_inj, amp0, common):
             "terms_per_s_per_core": terms / (t3 - t2) / threads,
             "sample": f"{live.size} in-support draws of the benchmark event (oracle's own metric and draws); "
                       f"oracle metric {t1 - t0:.1f} s single-threaded, not in value"}
+
+
+def cpu_config2(inputs):
+    """The oracle on four events of config 2 (the batch leg's first four: same data, each event's own
+    draw count), its own metric and draws per event; every in-support draw's log-likelihood timed
+    on all host threads."""
+    import numpy as np
+
+    import oracle
+
+    threads = os.cpu_count() or 1
+    n_live, terms, t_ll = 0, 0.0, 0.0
+    for x in inputs:
+        d_h, p_h, cm = x["data"], x["psd"], x["common"]
+        ev = oracle.Event(d_h.shape[0], d_h.shape[1], cm["f_lo"], cm["df"], data=d_h, psd=p_h,
+                          strain_scale=cm["strain_scale"], params=cm["params"], phase=cm["phase"], amp0=x["amp0"],
+                          gmst=cm["gmst"], chi_max=cm["chi_max"], dl_max=cm["dl_max"], det_geom=cm["det_geom"])
+        g = ev.metric(x["theta_inj"])
+        rc, th, lq, lp = ev.draw(x["theta_inj"], g, 12345, 0, x["N"])
+        th = np.ascontiguousarray(th[:, np.isfinite(lp)])
+        t0 = time.perf_counter()
+        ev.loglike(th, n_threads=threads)
+        t_ll += time.perf_counter() - t0
+        n_live += th.shape[1]
+        terms += float(d_h.shape[0] * host_cut(th, cm, d_h.shape[1]).sum())
+    return {"value": n_live / t_ll, "unit": "likelihood evals/s", "cores": threads, "kind": "oracle",
+            "per_core": n_live / t_ll / threads, "terms_per_s": terms / t_ll,
+            "terms_per_s_per_core": terms / t_ll / threads,
+            "sample": f"4 events of config 2 (the batch's first four, their own metric and "
+                      f"{sum(x['N'] for x in inputs)} draws), {n_live} in-support draws timed"}
 
 
 def cpu_config0():
