@@ -90,6 +90,8 @@ def lib():
                                _dp, _dp, _dp]
         L.peo_logq_theta.restype = ctypes.c_int
         L.peo_logq_theta.argtypes = [ctypes.POINTER(_Event), _dp, _dp, _dp, ctypes.c_long, _dp]
+        L.peo_mixture_logq.restype = ctypes.c_int
+        L.peo_mixture_logq.argtypes = [ctypes.POINTER(_Event), ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_long, _dp]
         L.peo_logprior.restype = ctypes.c_double
         L.peo_logprior.argtypes = [ctypes.POINTER(_Event), _dp]
         L.peo_weights_ess.argtypes = [_dp, _dp, _dp, ctypes.c_long, _dp, _dp]
@@ -274,6 +276,19 @@ class Event:
         n = th.shape[1]
         lq = np.zeros(n)
         rc = lib().peo_logq_theta(self.ref, _p(th0), _p(gg), _p(th), n, _p(lq))
+        return rc, lq
+
+    def mixture_logq(self, weights, theta0s, gs, theta):
+        """ln of the mixture sum_m pi_m q_m(theta), pi = weights / sum(weights), q_m the wrapped
+        metric Gaussian of (theta0s[m], gs[m]) (peo_mixture_logq): returns (rc, logq [n])."""
+        ww = _f64(weights)
+        m = ww.shape[0]
+        th0 = _f64(theta0s).reshape(m, self.dim)
+        gg = _f64(gs).reshape(m, self.dim, self.dim)
+        th = _f64(theta)
+        n = th.shape[1]
+        lq = np.zeros(n)
+        rc = lib().peo_mixture_logq(self.ref, m, _p(ww), _p(th0), _p(gg), _p(th), n, _p(lq))
         return rc, lq
 
     def proposal_update(self, theta0, theta, w):

@@ -1302,6 +1302,62 @@ int peo_logq_theta(const peo_event *ev, const double *th0, const double *g, cons
     return 0;
 }
 
+/* Log-density of a mixture of the wrapped metric Gaussians of peo_draw (the
+ * paper's proposal is itself a mixture of local proposals, weighted by their
+ * share of the posterior, Sec. II.A; here the components are Gaussians in the
+ * local metric, e.g. the proposals of successive refinement rounds, Sec. III.A):
+ *   ln q(theta) = ln sum_m pi_m q_m(theta),  pi_m = weights_m / sum_k weights_k,
+ * with q_m the density peo_logq_theta gives for (theta0 + m D, g + m D D).
+ * Weights must be finite and >= 0 with a positive sum. Returns 0, -1 for bad
+ * weights, or a component's nonzero code (metric not positive definite). */
+int peo_mixture_logq(const peo_event *ev, int m, const double *weights, const double *theta0, const double *g,
+                     const double *theta, long n, double *logq)
+{
+    const int D = peo_dim(ev->params);
+    double wsum = 0.0;
+    double *lqm;
+    long i;
+    int k, rc = 0;
+    if (m < 1)
+        return -1;
+    for (k = 0; k < m; k++) {
+        if (!(weights[k] >= 0.0) || !isfinite(weights[k]))
+            return -1;
+        wsum += weights[k];
+    }
+    if (!(wsum > 0.0))
+        return -1;
+    lqm = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)m);
+    if (!lqm)
+        return -1;
+    for (k = 0; k < m && !rc; k++)
+        rc = peo_logq_theta(ev, theta0 + (long)k * D, g + (long)k * D * D, theta, n, lqm + (long)k * n);
+    if (!rc) {
+        for (i = 0; i < n; i++) {
+            /* log-sum-exp over the components with positive weight */
+            double mx = -INFINITY;
+            nsum acc = {0, 0};
+            for (k = 0; k < m; k++) {
+                if (weights[k] > 0.0) {
+                    const double t = log(weights[k] / wsum) + lqm[(long)k * n + i];
+                    if (t > mx)
+                        mx = t;
+                }
+            }
+            if (mx == -INFINITY) {
+                logq[i] = -INFINITY;
+                continue;
+            }
+            for (k = 0; k < m; k++)
+                if (weights[k] > 0.0)
+                    nadd(&acc, exp(log(weights[k] / wsum) + lqm[(long)k * n + i] - mx));
+            logq[i] = mx + log(acc.s + acc.c);
+        }
+    }
+    free(lqm);
+    return rc;
+}
+
 /* Eq. 5: w_i = L_i pi_i / g_i, in logs; Eq. 6: ESS = (sum w)^2 / sum w^2.
  * Weights are normalised; lnZ = ln mean(w). Draws with -inf log weight count in N. */
 void peo_weights_ess(const double *ll, const double *lp, const double *lq, long n, double *w, double *stats)

@@ -147,6 +147,11 @@ int peo_draw(const peo_event *ev, const double *theta0, const double *g, uint64_
 /* Proposal log-density of wrapped draws from theta alone (quadratic-form route). */
 int peo_logq_theta(const peo_event *ev, const double *theta0, const double *g, const double *theta,
                    long n, double *logq);
+/* Log-density of the mixture sum_m pi_m q_m of the wrapped metric Gaussians
+ * (theta0 [m][D], g [m][D*D]) with pi_m = weights_m / sum weights; q_m as in
+ * peo_logq_theta. Returns 0, -1 for bad weights, else a component's code. */
+int peo_mixture_logq(const peo_event *ev, int m, const double *weights, const double *theta0, const double *g,
+                     const double *theta, long n, double *logq);
 double peo_logprior(const peo_event *ev, const double *theta);
 
 /* stats = {ESS, lnZ, max log w, n_in_support}. w may be NULL. */
