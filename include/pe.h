@@ -58,6 +58,7 @@ extern "C" {
 #define PE_MAX_DET 4
 #define PE_MAX_DIM 11
 #define PE_MAX_TM_POINTS 16384 /* tc nodes of a time-marginalised event */
+#define PE_MIX_MAX 16          /* components of a mixture proposal (pe_mixture_logq) */
 
 typedef struct pe_event_s *pe_event_t;
 
@@ -194,6 +195,33 @@ pe_status_t pe_metric(pe_event_t ev, const double *theta0_dev, const double *fd_
  */
 pe_status_t pe_draw(pe_event_t ev, const double *theta0_dev, const double *g_dev, uint64_t seed, uint32_t stream_id,
                     int64_t n, double *theta_dev, double *logq_dev, double *logprior_dev, void *stream);
+
+/*
+ * Log-density of a mixture of pe_draw's proposals at given points (the paper
+ * proposes from a mixture of local proposals, each weighted by its share of
+ * the posterior, Sec. II.A; here the components are wrapped Gaussians in the
+ * local metric, e.g. the proposals of successive refinement rounds, Sec. III.A):
+ *   logq_dev[i] = ln sum_k pi_k q_k(theta_i),  pi_k = weights[k] / sum weights,
+ * q_k the density pe_draw reports for draws from (theta0_k, g_k): the wrapped
+ * Gaussian summed over the images -2 .. +2 of each periodic coordinate about
+ * theta0_k wrapped into [0, P), the event's marginalised coordinates (dL of
+ * PE_DIST_MARG events, tc of time-marginalised events, phic of 11-D
+ * phase-marginalised events) left out as pe_draw leaves them out. Draws from the
+ * mixture are pe_draw calls, one per component (any split of the n draws over
+ * the components, e.g. n pi_k each: stratified), with this log q in place of
+ * each call's own (the balance heuristic of multiple importance sampling).
+ *   weights: m doubles (HOST), finite, >= 0, positive sum; m in 1..PE_MIX_MAX.
+ *   theta0_dev [m][D], g_dev [m][D*D] (device): centres and metrics.
+ *   theta_dev [D][n] (device): the points, as pe_draw returns them (periodic
+ *   coordinates in [0, P); they are not wrapped again).
+ *   logq_dev [n] (device, caller-owned).
+ * Errors: PE_ERR_ARG (bad m, weights, pointers, n), PE_ERR_HIP. If a component's
+ * g is not positive definite, logq is NaN and pe_event_status reports
+ * PE_ERR_SINGULAR. The components' factors live in the event (one set per
+ * event): calls on one event must not overlap.
+ */
+pe_status_t pe_mixture_logq(pe_event_t ev, int32_t m, const double *weights, const double *theta0_dev,
+                            const double *g_dev, const double *theta_dev, int64_t n, double *logq_dev, void *stream);
 
 /*
  * Log-likelihood ratio (Eq. 3) of n draws. Per draw and detector the kernel

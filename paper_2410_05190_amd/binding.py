@@ -33,7 +33,7 @@ PE_F32 = 1
 MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
-           "pe_event_destroy", "pe_metric", "pe_draw", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_weights_ess_noalloc", "pe_proposal_update", "pe_refine", "pe_slice_sample", "pe_tile_bank",
+           "pe_event_destroy", "pe_metric", "pe_draw", "pe_mixture_logq", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_weights_ess_noalloc", "pe_proposal_update", "pe_refine", "pe_slice_sample", "pe_tile_bank",
            "pe_tile_assign", "pe_tile_assign_match", "pe_tile_draw", "pe_tile_extrinsic", "pe_tile_reweight", "pe_relbin_setup", "pe_relbin_edges",
            "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
@@ -150,6 +150,7 @@ def load(path=LIB_PATH):
         "pe_metric": (i32, [vp, dp, dp, i32, dp, vp]),
         "pe_draw": (i32, [vp, dp, dp, u64, u32, i64, dp, dp, dp, vp]),
         "pe_tile_extrinsic": (i32, [vp, dp, dp, u32, i32, u64, u32, i64, dp, dp, dp, vp]),
+        "pe_mixture_logq": (i32, [vp, i32, dp, dp, dp, dp, i64, dp, vp]),
         "pe_loglike_batch": (i32, [vp, dp, i64, i32, dp, dp, vp]),
         "pe_loglike_multi": (i32, [i32, vp, vp, vp, i32, vp, vp, vp]),
         "pe_batch_run": (i32, [i32, vp, i32, i32, vp]),
@@ -301,6 +302,20 @@ def pe_draw(ev, theta0, g, seed, stream_id, n, theta, logq, logprior, stream=Non
     _check(_lib.pe_draw(ev, _ptr(theta0, f64, "theta0"), _ptr(g, f64, "g"), int(seed) & 0xFFFFFFFFFFFFFFFF,
                         int(stream_id) & 0xFFFFFFFF, int(n), _ptr(theta, f64, "theta"), _ptr(logq, f64, "logq"),
                         _ptr(logprior, f64, "logprior"), _stream(stream)))
+
+
+PE_MIX_MAX = 16
+
+
+def pe_mixture_logq(ev, weights, theta0s, gs, theta, n, logq, stream=None):
+    """weights: m floats (host); theta0s [m, D], gs [m, D, D], theta [D, n], logq [n] (device, float64)."""
+    import torch
+    f64 = torch.float64
+    w = [float(x) for x in weights]
+    arr = (ctypes.c_double * max(len(w), 1))(*w)
+    _check(load().pe_mixture_logq(ev, len(w), ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)),
+                                  _ptr(theta0s, f64, "theta0s"), _ptr(gs, f64, "gs"), _ptr(theta, f64, "theta"),
+                                  int(n), _ptr(logq, f64, "logq"), _stream(stream)))
 
 
 PE_TILE_CONDITIONAL = 1
@@ -553,6 +568,13 @@ class Event:
         lp = torch.empty(n, dtype=torch.float64, device=dev)
         pe_draw(self.handle, theta0, g, seed, stream_id, n, theta, lq, lp, stream)
         return theta, lq, lp
+
+    def mixture_logq(self, weights, theta0s, gs, theta, stream=None):
+        import torch
+        n = theta.shape[1]
+        lq = torch.empty(n, dtype=torch.float64, device=theta.device)
+        pe_mixture_logq(self.handle, weights, theta0s, gs, theta, n, lq, stream)
+        return lq
 
     def proposal_update(self, theta, w, theta0, cov=False, stream=None):
         """pe_proposal_update: returns the new centre (and the weighted covariance if cov)."""

@@ -210,6 +210,7 @@ size_t layout_tables(pe_event_s* ev, char* base) {
     ev->guard = c.take<double>((size_t)kGuardLen);
     ev->status = c.take<int>(1);
     ev->mws = c.take<double>((size_t)kMwsTotal);
+    ev->mix_chol = c.take<double>((size_t)PE_MIX_MAX * kCholLen);
     return c.size();
 }
 
@@ -933,6 +934,48 @@ pe_status_t pe_draw(pe_event_t ev, const double* theta0_dev, const double* g_dev
     return run_draw(std::vector<DrawArg>(1, draw_arg(ev, theta0_dev, g_dev, seed, stream_id, n, theta_dev, logq_dev,
                                                      logprior_dev)),
                     as_stream(stream));
+}
+
+pe_status_t pe_mixture_logq(pe_event_t ev, int32_t m, const double* weights, const double* theta0_dev,
+                            const double* g_dev, const double* theta_dev, int64_t n, double* logq_dev, void* stream) {
+    if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (m < 1 || m > PE_MIX_MAX) return fail(PE_ERR_ARG, "m must be in 1..PE_MIX_MAX");
+    if (!weights) return fail(PE_ERR_ARG, "weights is NULL (a host array of m values)");
+    double wsum = 0.0;
+    for (int k = 0; k < m; ++k) {
+        if (!std::isfinite(weights[k]) || weights[k] < 0.0) return fail(PE_ERR_ARG, "weights must be finite and >= 0");
+        wsum += weights[k];
+    }
+    if (!(wsum > 0.0) || !std::isfinite(wsum)) return fail(PE_ERR_ARG, "weights must have a positive finite sum");
+    pe_status_t s = check_n(n);
+    if (s != PE_OK) return s;
+    if (!theta0_dev || !g_dev) return fail(PE_ERR_ARG, "theta0 and g must be device pointers");
+    if (n > 0 && (!theta_dev || !logq_dev)) return fail(PE_ERR_ARG, "theta and logq are NULL");
+    if (n == 0) return PE_OK;
+    hipStream_t st = as_stream(stream);
+    const int D = ev->ec.dim;
+    // the components' factors: k_cholesky's records, as pe_draw makes them
+    std::vector<DrawArg> v;
+    for (int k = 0; k < m; ++k) {
+        DrawArg a = draw_arg(ev, theta0_dev + (int64_t)k * D, g_dev + (int64_t)k * D * D, 0, 0, 0, nullptr, nullptr,
+                             nullptr);
+        a.chol = ev->mix_chol + (int64_t)k * kCholLen;
+        v.push_back(a);
+    }
+    if ((s = run_draw(v, st)) != PE_OK) return s;
+    MixArg a;
+    std::memset(&a, 0, sizeof(a));
+    a.ec = ev->ec;
+    a.chol = ev->mix_chol;
+    a.theta0 = theta0_dev;
+    a.theta = theta_dev;
+    a.logq = logq_dev;
+    a.status = ev->status;
+    a.n = n;
+    a.m = m;
+    for (int k = 0; k < m; ++k) a.lpi[k] = weights[k] > 0.0 ? std::log(weights[k] / wsum) : -INFINITY;
+    PE_HIP(launch_mix_logq(a, st));
+    return PE_OK;
 }
 
 pe_status_t pe_tile_extrinsic(pe_event_t ev, const double* theta0_dev, const double* g_dev, uint32_t sub_mask,

@@ -295,6 +295,7 @@ struct pe_event_s {
     double *guard = nullptr;  // [kGuardLen] noise statistics of the data
     int *status = nullptr;  // device status word
     double *mws = nullptr;  // metric + draw workspace
+    double *mix_chol = nullptr;  // [PE_MIX_MAX][kCholLen] factors of a mixture's component metrics
     // per-draw workspace
     int64_t npad = 0;
     int *kc_all = nullptr;  // [npad] cut per draw, -1 out of support
@@ -366,6 +367,20 @@ hipError_t launch_prep_batch(const BatchPtrs &b, int ne, int64_t total_blocks, i
                              int max_seg, int max_det, hipStream_t st);
 hipError_t launch_metric_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st);
 hipError_t launch_draw_batch(const BatchPtrs &b, int ne, int64_t total_blocks, hipStream_t st, bool ext = false);
+// Mixture log-density (pe_mixture_logq): the components' factors are in chol
+// (k_cholesky's records, one per component).
+struct MixArg {
+    EvConst ec;
+    const double *chol;    // [m][kCholLen]
+    const double *theta0;  // [m][D] component centres
+    const double *theta;   // [D][n]
+    double *logq;          // [n]
+    int *status;
+    int64_t n;
+    int m;
+    double lpi[PE_MIX_MAX];  // ln of each component's normalised weight (-inf: weight 0)
+};
+hipError_t launch_mix_logq(const MixArg &a, hipStream_t st);
 // any_dist: some event of the batch is distance-marginalised (adds k_b_dist);
 // max_det: no event of the batch has more detectors (at most 2: the FP64
 // re-evaluation's two-detector kernel).

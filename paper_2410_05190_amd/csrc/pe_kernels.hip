@@ -758,123 +758,20 @@ __global__ __launch_bounds__(64) void k_cholesky(const BatchHdr* __restrict__ hd
     }
 }
 
-// Draw i of an event: normals, theta = theta0 + L^-T z (wrapped), log q of the
-// wrapped Gaussian (images -2..2 of each periodic coordinate about theta0
-// wrapped into [0, P), summed with a running maximum), log prior. L
-// (row-major), its log det and the success flag are in LDS (lc).
-//
-// Ext (extrinsic completion of tile draws): the coordinates of A.dmask keep the
-// values theta holds on entry, log q is added to the entry's value, and the log
-// prior stays -inf where it was.
-//
-// Ext with kDrawCond: the other coordinates given the tiled ones. With L the
-// factor of the metric conditioned on them (their rows cleared after the
-// marginalised coordinates are decoupled), the draw's mean moves by
-// delta = -(L L^T)^-1 r, r = (coupling) (theta_tiled - theta0_tiled): u = -L^-1 r,
-// delta = L^-T u; theta = theta0 + delta + L^-T z, and log q is the wrapped
-// density about theta0 + delta (the whitened offset is z again).
-template <int D, bool Ext = false>
-__device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int64_t i) {
-    const EvConst& ev = A.ec;
-    const int64_t n = A.n;
-    const uint32_t dmask = Ext ? (A.dmask & ~kDrawCond) : 0u;
-    const bool cond = Ext && (A.dmask & kDrawCond);
-    double th0[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) th0[a] = A.theta0[a];
-    if (lc[kCholOk] == 0.0) {
-        if (!Ext) {
-#pragma unroll
-            for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th0[a];
-            A.logq[i] = 0.0;
-        }
-        A.logprior[i] = -INFINITY;
-        return;
-    }
-    double z[D + 1];
-#pragma unroll
-    for (int j = 0; 2 * j < D; ++j) {
-        double ua, ub, sn, cs;
-        block_uniforms(A.seed, A.stream_id, (uint64_t)i, (uint32_t)j, ua, ub);
-        const double rad = sqrt(-2.0 * log(ua));
-        sincos_turns(ub >= 1.0 ? 0.0 : ub, sn, cs);  // 2 pi ub
-        z[2 * j] = rad * cs;
-        z[2 * j + 1] = rad * sn;
-    }
-    // theta = theta0 + L^-T z (back substitution with L^T)
-    double y[D];
-#pragma unroll
-    for (int r = D - 1; r >= 0; --r) {
-        double s = z[r];
-#pragma unroll
-        for (int c = r + 1; c < D; ++c) s -= lc[c * D + r] * y[c];
-        y[r] = s * lc[kCholRdiag + r];
-    }
-    const bool distm = (D == 11) && ev.dist, pmargm = (D == 11) && ev.phase == PE_PHASE_MARG;
-    double yu[D];  // the conditional mean's shift (0 unless cond)
-#pragma unroll
-    for (int a = 0; a < D; ++a) yu[a] = 0.0;
-    if (cond) {
-        double u[D];
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            double t = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j)
-                if ((dmask >> j) & 1u) t = fma(lc[kCholCond + r * D + j], A.theta[(int64_t)j * n + i] - th0[j], t);
-            double sr = -t;
-#pragma unroll
-            for (int k = 0; k < r; ++k) sr -= lc[r * D + k] * u[k];
-            u[r] = sr * lc[kCholRdiag + r];
-        }
-#pragma unroll
-        for (int r = D - 1; r >= 0; --r) {
-            double sr = u[r];
-#pragma unroll
-            for (int c = r + 1; c < D; ++c) sr -= lc[c * D + r] * yu[c];
-            yu[r] = sr * lc[kCholRdiag + r];
-        }
-    }
-    double th[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        const bool margd = (a == 8 && distm) || (a == 10 && pmargm);  // unused by the likelihood
-        th[a] = ((dmask >> a) & 1u) ? A.theta[(int64_t)a * n + i]
-                                    : ((cond && margd) ? th0[a] : th0[a] + yu[a] + y[a]);
-    }
+// ln of the proposal's wrapped Gaussian density (images -2..2 of each periodic
+// coordinate about the wrapped centre, summed with a running maximum) for a
+// point whose whitened offset from the centre is z = L^T (theta - theta0) (D
+// entries) and which lies k0_p whole periods from the wrapped centre's cell at
+// the periodic coordinates. L (row-major), log det, G and the success flag are
+// in lc. The decoupled coordinates (marginalised by the likelihood, or in dmask)
+// are left out: the density is the marginal over the others.
+template <int D>
+__device__ __forceinline__ double wrapped_logq(const EvConst& ev, const double* lc, const double* z, double (&k0)[3],
+                                               uint32_t dmask) {
     constexpr int NP = (D == 4) ? 0 : 3;
     constexpr int pidx[3] = {4, 7, 10};
     const double per[3] = {kTwoPi, kPi, kTwoPi};
-    // k0_p: periods between the wrapped draw and the wrapped centre
-    double k0[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        const double v = th[pidx[p]];
-        const double kw = floor(v / per[p]);
-        th[pidx[p]] = v - per[p] * kw;
-        k0[p] = kw - floor((th0[pidx[p]] + yu[pidx[p]]) / per[p]);
-    }
     const bool tmarg = (D == 11) && ev.tm;
-    if (tmarg) {
-        // tc: its mean under the proposal given the other coordinates, from
-        // their offsets to the wrapped centre (periodic ones to the nearest image)
-        double dlt[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) dlt[a] = th[a] - th0[a];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const double c0 = th0[pidx[p]] - per[p] * floor(th0[pidx[p]] / per[p]);
-            const double d = th[pidx[p]] - c0;
-            dlt[pidx[p]] = d - per[p] * floor(d / per[p] + 0.5);
-        }
-        double m = th0[9 % D];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-            if (a != 9) m -= lc[kCholTm + a] * dlt[a];
-        th[9 % D] = m;
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th[a];
     // whitened offset of image m: L^T (x - c) = z + L^T s with c the wrapped
     // centre and s = (k - k0) P on the periodic rows, so its squared norm is
     // |z|^2 + 2 s.a + s^T G s with a_p = (L^T row pidx_p) . z and G = L L^T there.
@@ -1018,7 +915,127 @@ __device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int
     }
     const uint32_t margm = (dist ? 1u << 8 : 0u) | (tmarg ? 1u << 9 : 0u) | (pmarg ? 1u << 10 : 0u);
     const int dkeep = D - __builtin_popcount(margm | dmask);
-    const double lq = mx + log(acc) + lc[kCholLogdet] - 0.5 * dkeep * log(kTwoPi);
+    return mx + log(acc) + lc[kCholLogdet] - 0.5 * dkeep * log(kTwoPi);
+}
+
+// Draw i of an event: normals, theta = theta0 + L^-T z (wrapped), log q of the
+// wrapped Gaussian (images -2..2 of each periodic coordinate about theta0
+// wrapped into [0, P), summed with a running maximum), log prior. L
+// (row-major), its log det and the success flag are in LDS (lc).
+//
+// Ext (extrinsic completion of tile draws): the coordinates of A.dmask keep the
+// values theta holds on entry, log q is added to the entry's value, and the log
+// prior stays -inf where it was.
+//
+// Ext with kDrawCond: the other coordinates given the tiled ones. With L the
+// factor of the metric conditioned on them (their rows cleared after the
+// marginalised coordinates are decoupled), the draw's mean moves by
+// delta = -(L L^T)^-1 r, r = (coupling) (theta_tiled - theta0_tiled): u = -L^-1 r,
+// delta = L^-T u; theta = theta0 + delta + L^-T z, and log q is the wrapped
+// density about theta0 + delta (the whitened offset is z again).
+template <int D, bool Ext = false>
+__device__ __forceinline__ void draw_one(const DrawArg& A, const double* lc, int64_t i) {
+    const EvConst& ev = A.ec;
+    const int64_t n = A.n;
+    const uint32_t dmask = Ext ? (A.dmask & ~kDrawCond) : 0u;
+    const bool cond = Ext && (A.dmask & kDrawCond);
+    double th0[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) th0[a] = A.theta0[a];
+    if (lc[kCholOk] == 0.0) {
+        if (!Ext) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th0[a];
+            A.logq[i] = 0.0;
+        }
+        A.logprior[i] = -INFINITY;
+        return;
+    }
+    double z[D + 1];
+#pragma unroll
+    for (int j = 0; 2 * j < D; ++j) {
+        double ua, ub, sn, cs;
+        block_uniforms(A.seed, A.stream_id, (uint64_t)i, (uint32_t)j, ua, ub);
+        const double rad = sqrt(-2.0 * log(ua));
+        sincos_turns(ub >= 1.0 ? 0.0 : ub, sn, cs);  // 2 pi ub
+        z[2 * j] = rad * cs;
+        z[2 * j + 1] = rad * sn;
+    }
+    // theta = theta0 + L^-T z (back substitution with L^T)
+    double y[D];
+#pragma unroll
+    for (int r = D - 1; r >= 0; --r) {
+        double s = z[r];
+#pragma unroll
+        for (int c = r + 1; c < D; ++c) s -= lc[c * D + r] * y[c];
+        y[r] = s * lc[kCholRdiag + r];
+    }
+    const bool distm = (D == 11) && ev.dist, pmargm = (D == 11) && ev.phase == PE_PHASE_MARG;
+    double yu[D];  // the conditional mean's shift (0 unless cond)
+#pragma unroll
+    for (int a = 0; a < D; ++a) yu[a] = 0.0;
+    if (cond) {
+        double u[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            double t = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                if ((dmask >> j) & 1u) t = fma(lc[kCholCond + r * D + j], A.theta[(int64_t)j * n + i] - th0[j], t);
+            double sr = -t;
+#pragma unroll
+            for (int k = 0; k < r; ++k) sr -= lc[r * D + k] * u[k];
+            u[r] = sr * lc[kCholRdiag + r];
+        }
+#pragma unroll
+        for (int r = D - 1; r >= 0; --r) {
+            double sr = u[r];
+#pragma unroll
+            for (int c = r + 1; c < D; ++c) sr -= lc[c * D + r] * yu[c];
+            yu[r] = sr * lc[kCholRdiag + r];
+        }
+    }
+    double th[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const bool margd = (a == 8 && distm) || (a == 10 && pmargm);  // unused by the likelihood
+        th[a] = ((dmask >> a) & 1u) ? A.theta[(int64_t)a * n + i]
+                                    : ((cond && margd) ? th0[a] : th0[a] + yu[a] + y[a]);
+    }
+    constexpr int NP = (D == 4) ? 0 : 3;
+    constexpr int pidx[3] = {4, 7, 10};
+    const double per[3] = {kTwoPi, kPi, kTwoPi};
+    // k0_p: periods between the wrapped draw and the wrapped centre
+    double k0[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const double v = th[pidx[p]];
+        const double kw = floor(v / per[p]);
+        th[pidx[p]] = v - per[p] * kw;
+        k0[p] = kw - floor((th0[pidx[p]] + yu[pidx[p]]) / per[p]);
+    }
+    const bool tmarg = (D == 11) && ev.tm;
+    if (tmarg) {
+        // tc: its mean under the proposal given the other coordinates, from
+        // their offsets to the wrapped centre (periodic ones to the nearest image)
+        double dlt[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) dlt[a] = th[a] - th0[a];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const double c0 = th0[pidx[p]] - per[p] * floor(th0[pidx[p]] / per[p]);
+            const double d = th[pidx[p]] - c0;
+            dlt[pidx[p]] = d - per[p] * floor(d / per[p] + 0.5);
+        }
+        double m = th0[9 % D];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            if (a != 9) m -= lc[kCholTm + a] * dlt[a];
+        th[9 % D] = m;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) A.theta[(int64_t)a * n + i] = th[a];
+    const double lq = wrapped_logq<D>(ev, lc, z, k0, dmask);
     if (Ext) {
         A.logq[i] += lq;
         if (A.logprior[i] != -INFINITY) A.logprior[i] = log_prior_of(ev, th);
@@ -1077,6 +1094,95 @@ hipError_t launch_draw_batch(const BatchPtrs& b, int ne, int64_t total_blocks, h
         k_draw_ext<<<stride_grid(total_blocks, 1), 256, 0, st>>>(b.hdr, args, b.off);
     else
         k_draw<<<stride_grid(total_blocks, 1), 256, 0, st>>>(b.hdr, args, b.off);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Mixture log-density: ln sum_k pi_k q_k(theta) at given points, q_k the
+// wrapped density of component k (its factor from k_cholesky, as for pe_draw).
+// For point theta and centre c_k wrapped into [0, P): z = L_k^T (theta - c_k)
+// and k0 = 0 (the images are taken about the wrapped centre), then q_k as
+// draw_one evaluates it (wrapped_logq); components in order, running maximum.
+// ===========================================================================
+constexpr int kMixRec = kCholRdiag;  // the part of a component's record the density reads
+
+template <int D>
+__device__ __forceinline__ void mix_one(const MixArg& A, const double* lc_all, const double* cen_all, int64_t i) {
+    const int64_t n = A.n;
+    double th[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) th[a] = A.theta[(int64_t)a * n + i];
+    double mx = -INFINITY, acc = 0.0;
+    bool bad = false;
+    for (int k = 0; k < A.m; ++k) {
+        const double lpi = A.lpi[k];
+        if (lpi == -INFINITY) continue;
+        const double* lc = lc_all + k * kMixRec;
+        if (lc[kCholOk] == 0.0) {
+            bad = true;
+            continue;
+        }
+        const double* c = cen_all + k * PE_MAX_DIM;
+        double dl[D], z[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) dl[a] = th[a] - c[a];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            double t = 0.0;
+#pragma unroll
+            for (int a = r; a < D; ++a) t = fma(lc[a * D + r], dl[a], t);
+            z[r] = t;
+        }
+        double k0[3] = {0.0, 0.0, 0.0};
+        const double l = lpi + wrapped_logq<D>(A.ec, lc, z, k0, 0u);
+        if (l > mx) {
+            acc = (mx == -INFINITY) ? 1.0 : acc * exp(mx - l) + 1.0;
+            mx = l;
+        } else if (l > -INFINITY) {
+            acc += exp(l - mx);
+        }
+    }
+    A.logq[i] = bad ? NAN : ((mx == -INFINITY) ? -INFINITY : mx + log(acc));
+}
+
+// Blocks of 256 points; every block stages the components' records and wrapped
+// centres in LDS.
+template <int D>
+__global__ __launch_bounds__(256) void k_mix_logq(MixArg A) {
+    __shared__ double lc[PE_MIX_MAX * kMixRec];
+    __shared__ double cen[PE_MIX_MAX * PE_MAX_DIM];
+    for (int q = threadIdx.x; q < A.m * kMixRec; q += 256) {
+        const int k = q / kMixRec, r = q - k * kMixRec;
+        lc[q] = A.chol[(int64_t)k * kCholLen + r];
+    }
+    for (int q = threadIdx.x; q < A.m * PE_MAX_DIM; q += 256) {
+        const int k = q / PE_MAX_DIM, a = q - k * PE_MAX_DIM;
+        double v = (a < D) ? A.theta0[k * D + a] : 0.0;
+        if (D == 11 && (a == 4 || a == 7 || a == 10)) {
+            const double P = (a == 7) ? kPi : kTwoPi;
+            v -= P * floor(v / P);
+        }
+        cen[q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int k = 0; k < A.m; ++k)
+            if (A.lpi[k] != -INFINITY && lc[k * kMixRec + kCholOk] == 0.0) {
+                atomicOr(A.status, kStSingular);
+                break;
+            }
+    }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * 256)
+        mix_one<D>(A, lc, cen, i);
+}
+
+hipError_t launch_mix_logq(const MixArg& a, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    const unsigned grid = stride_grid((a.n + 255) / 256, 1);
+    if (a.ec.dim == 4)
+        k_mix_logq<4><<<grid, 256, 0, st>>>(a);
+    else
+        k_mix_logq<11><<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
