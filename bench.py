@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--refine-rounds", type=int, default=3,
                     help="rounds of proposal refinement before the refined-proposal leg (0 skips the leg)")
     ap.add_argument("--refine-draws", type=int, default=16384, help="draws per refinement round")
+    ap.add_argument("--mixture-k", type=int, default=6,
+                    help="mixture leg: components at the pilot round's k heaviest draws (0 skips the leg)")
     ap.add_argument("--relbin-eps", type=float, default=0.02,
                     help="relative-binning leg: envelope step between bin edges (0 skips the leg)")
     ap.add_argument("--tile-radius", type=float, default=6.0, help="tile-mixture leg: slice radius (whitened)")
@@ -282,6 +284,11 @@ def main():
         out["drift"] = drift_leg(first, n_drift, prec)
     if n_events == 1 and args.refine_rounds > 0:
         out["refined"] = refine_leg(first, args.refine_rounds, args.refine_draws, max(args.steps, 1), prec)
+    if n_events == 1 and args.mixture_k > 0:
+        start = first["theta0"]
+        if "refined" in out:
+            start = torch.tensor(out["refined"]["centre"], dtype=torch.float64, device="cuda")
+        out["mixture"] = mixture_leg(first, start, args.mixture_k, max(args.steps, 1), prec)
     if n_events == 1 and args.relbin_eps > 0:
         out["relbin"] = relbin_leg(first, args.relbin_eps, max(args.steps, 1), prec)
     if n_events == 1 and D == 11 and not args.no_distance_leg:
@@ -541,6 +548,90 @@ def refine_leg(x, rounds, n_round, steps, prec):
         "ess_per_s_with_refine": ess_f / (t_ref + t_step),
         "evals_per_s": float(sf[:, 3].sum()) / (tc - tb),
         "centre": [float(v) for v in t0.cpu().numpy()],
+    }
+
+
+def mixture_leg(x, centre, k, steps, prec, n_pilot=16384):
+    """A small mixture of metric Gaussians (pe_mixture_logq). A pilot round of the single Gaussian
+    at `centre` (metric there, n_pilot draws, likelihoods, weights) picks its k heaviest draws; each
+    becomes a component centred there with the metric at that point and a share of 3/4 in
+    proportion to its weight; the single Gaussian keeps 1/4, so the mixture still covers what the
+    pilot covered. Each step: the event's N draws stratified over the components (pe_draw per
+    component; N pi_m each), the mixture's log q at all of them (pe_mixture_logq), likelihoods and
+    weights. ESS per event and ESS/s, with and without the pilot and metrics, beside the pilot's."""
+    import numpy as np
+    import torch
+
+    from paper_2410_05190_amd import binding
+    h_ = x["ev"].handle
+    N, D = x["N"], x["ev"].dim
+    dev = centre.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    x["ev"].reserve(max(N, n_pilot))
+    tp = [torch.empty((D, n_pilot), **f64)] + [torch.empty(n_pilot, **f64) for _ in range(4)]
+    st_p = torch.empty(4, **f64)
+
+    def setup(seed):
+        g0 = torch.empty((D, D), **f64)
+        binding.pe_event_update(h_, x["data"], x["psd"])
+        binding.pe_metric(h_, centre, None, 0, g0)
+        binding.pe_draw(h_, centre, g0, seed, 0, n_pilot, tp[0], tp[1], tp[2])
+        binding.pe_loglike_batch(h_, tp[0], n_pilot, prec, tp[3], None)
+        binding.pe_weights_ess(tp[3], tp[2], tp[1], n_pilot, tp[4], st_p)
+        top = torch.topk(tp[4], k)
+        cens = torch.cat([centre[None, :], tp[0][:, top.indices].T]).contiguous()
+        gs = torch.empty((k + 1, D, D), **f64)
+        gs[0].copy_(g0)
+        for m in range(1, k + 1):
+            binding.pe_metric(h_, cens[m].contiguous(), None, 0, gs[m])
+        wt = top.values.cpu().numpy()
+        share = wt / wt.sum() if wt.sum() > 0 else np.full(k, 1.0 / k)
+        return cens, gs, np.concatenate([[0.25], 0.75 * share])
+
+    setup(x["seed"] + 21)  # untimed: first-use costs
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    cens, gs, pis = setup(x["seed"] + 23)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    counts = np.floor(N * pis).astype(int)
+    counts[int(np.argmax(pis))] += N - int(counts.sum())
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    part = [(torch.empty((D, max(int(c), 1)), **f64), torch.empty(max(int(c), 1), **f64),
+             torch.empty(max(int(c), 1), **f64)) for c in counts]
+    st_f = torch.empty((steps, 4), **f64)
+
+    def step(i, row):
+        for m, c in enumerate(counts):
+            if c == 0:
+                continue
+            th_m, lq_m, lp_m = part[m]
+            binding.pe_draw(h_, cens[m], gs[m], x["seed"] + 29, 16 * i + m, int(c), th_m, lq_m, lp_m)
+            x["theta"][:, offs[m]:offs[m + 1]].copy_(th_m[:, :c])
+            x["lp"][offs[m]:offs[m + 1]].copy_(lp_m[:c])
+        binding.pe_mixture_logq(h_, pis, cens, gs, x["theta"], N, x["lq"])
+        binding.pe_loglike_batch(h_, x["theta"], N, prec, x["ll"], None)
+        binding.pe_weights_ess(x["ll"], x["lp"], x["lq"], N, x["w"], row)
+
+    step(1000, st_f[0])  # untimed
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    for i in range(steps):
+        step(i, st_f[i])
+    torch.cuda.synchronize()
+    td = time.perf_counter()
+    x["ev"].status()
+    sf = st_f.cpu().numpy()
+    ess_f = float(sf[:, 0].mean())
+    t_setup, t_step = tb - ta, (td - tc) / steps
+    return {
+        "kind": "mixture of metric Gaussians at the pilot round's heaviest draws plus the pilot's own "
+                "(pe_mixture_logq; draws stratified over the components)",
+        "components": int(k + 1), "weights": [float(v) for v in pis], "pilot_draws": n_pilot,
+        "pilot_ess": float(st_p[0].item()), "setup_ms": 1e3 * t_setup, "steps": steps, "draws_per_step": N,
+        "ms_per_step": 1e3 * t_step, "ess_per_event_mean": ess_f, "efficiency": ess_f / N,
+        "ess_per_s": ess_f / t_step, "ess_per_s_with_setup": ess_f / (t_setup + t_step),
+        "evals_per_s": float(sf[:, 3].sum()) / (td - tc),
     }
 
 

@@ -101,6 +101,14 @@ def test_batch_run_argument_errors_on_host():
     assert "event is NULL" in binding.pe_last_error()
 
 
+def test_mixture_logq_argument_errors_on_host():
+    L = binding.load()
+    w = (ctypes.c_double * 2)(1.0, 1.0)
+    assert L.pe_mixture_logq(None, 2, ctypes.cast(w, ctypes.c_void_p), None, None, None, 0, None, None) == 1
+    assert "event is NULL" in binding.pe_last_error()
+    assert binding.PE_MIX_MAX == 16
+
+
 def test_server_structs_and_host_checks():
     # pe_server_config_t: int64, 2 int32, double, 4 int32
     assert ctypes.sizeof(binding.ServerConfig) == 8 + 8 + 8 + 16
