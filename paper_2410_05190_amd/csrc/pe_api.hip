@@ -92,6 +92,13 @@ pe_status_t ensure_moments(pe_event_s* ev, int64_t n) {
     pe_status_t s = dalloc_bytes(&ev->tm_mem, sizeof(double2) * (size_t)blocks * ev->ec.tm_P * (size_t)cols);
     if (s != PE_OK) return s;
     ev->tm_mom_cols = cols;
+    if (!ev->tm_pow && ev->ec.tm_fine <= kTmPowMaxBins) {
+        // the block's power table, once per event (the device is idle here)
+        s = dalloc_bytes(&ev->tm_pow, sizeof(float) * (size_t)ev->ec.tm_fine * ev->ec.tm_P);
+        if (s != PE_OK) return s;
+        PE_HIP(launch_tm_powers((float*)ev->tm_pow, ev->ec.tm_fine, ev->ec.tm_P, nullptr));
+        PE_HIP(hipDeviceSynchronize());
+    }
     return PE_OK;
 }
 
@@ -281,6 +288,7 @@ void free_event(pe_event_s* ev) {
     }
     dfree_bytes(ev->rb_mem);
     dfree_bytes(ev->tm_mem);
+    dfree_bytes(ev->tm_pow);
     delete ev;
 }
 
@@ -686,6 +694,7 @@ pe_status_t loglike_entry(pe_event_s* ev, const double* theta, int64_t n, double
         EvDev d = loglike_arg(ev, ev->tm_theta, n, loglike, nullptr);
         d.flags |= kLlMoments;
         d.tm_mom = (double2*)ev->tm_mem;
+        d.tm_pow = (const float*)ev->tm_pow;
         jobs.mom.push_back(d);
         return PE_OK;
     }

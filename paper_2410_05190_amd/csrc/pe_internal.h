@@ -170,6 +170,7 @@ struct EvDev {
     int *rpos;       // [npad] positions of the re-evaluated draws, ascending
     double2 *zd;     // [npad] Z of distance-marginalised events (read by k_b_dist)
     double2 *tm_mom; // time marginal from block moments: [n_fine][tm_P][npad] moments of each draw's integrand
+    const float *tm_pow;  // [tm_fine][tm_P] x^p of each bin's offset in its block (NULL: formed per bin)
     int *status;
     int64_t npad;
     int max_groups;      // cap on the groups of chunks (partial capacity / npad)
@@ -311,6 +312,7 @@ struct pe_event_s {
     double *tm_theta = nullptr;  // [PE_MAX_DIM][npad]
     double *tm_ll = nullptr;     // [npad]
     char *tm_mem = nullptr;      // block moments of the time marginal (own allocation, grown on demand)
+    char *tm_pow = nullptr;      // [tm_fine][tm_P] floats: the moment powers of a bin's offset (own allocation)
     int64_t tm_mom_cols = 0;     // draw columns tm_mem holds
     int64_t partial_cap = 0;  // double2 entries per detector
     double *coef = nullptr;   // [kNCoef][npad]
@@ -395,6 +397,10 @@ void prime_hot_grids();
 hipError_t launch_tm_expand(const double* theta, int64_t n, const EvConst& ec, double* out, hipStream_t st);
 hipError_t launch_tm_reduce(const double* ll, int64_t n, const EvConst& ec, double* out, hipStream_t st);
 hipError_t launch_tm_centre(const double* theta, int64_t n, const EvConst& ec, double* out, hipStream_t st);
+// The moment powers x^p (p < tm_P) of every offset i < tm_fine in a block of the
+// block-moment path, as the moment hot loop forms them per bin.
+hipError_t launch_tm_powers(float* out, int fine, int P, hipStream_t st);
+constexpr int kTmPowMaxBins = 1 << 16;  // wider blocks form the powers per bin
 hipError_t launch_loglike_moments(const BatchPtrs& b, int ne, int64_t prologue_blocks, int64_t node_blocks, int P,
                                   hipStream_t st);
 hipError_t launch_waveform(const EvConst &ec, int data_psd_dtype, const double *theta, const void *psd, double *h,

@@ -1193,6 +1193,28 @@ __global__ __launch_bounds__(256) void k_tm_centre(const double* __restrict__ th
         for (int a = 0; a < ec.dim; ++a) out[(int64_t)a * n + i] = (a == 9) ? ec.tm_tmid : theta[(int64_t)a * n + i];
 }
 
+// x^p of offset i in a block of `fine` bins: x = (i - (fine - 1) / 2) (2 / fine)
+// in FP32 and its powers by repeated products, exactly as the moment hot loop
+// forms them per bin (there (float)k - kmid is the same exact half-integer).
+__global__ __launch_bounds__(256) void k_tm_powers(float* __restrict__ out, int fine, int P) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= fine) return;
+    const float kmid = 0.5f * (float)(fine - 1);
+    const float inv_half = 2.0f / (float)fine;
+    const float x = ((float)i - kmid) * inv_half;
+    float xp = 1.0f;
+    for (int q = 0; q < P; ++q) {
+        out[(int64_t)i * P + q] = xp;
+        xp *= x;
+    }
+}
+
+hipError_t launch_tm_powers(float* out, int fine, int P, hipStream_t st) {
+    if (fine <= 0) return hipSuccess;
+    k_tm_powers<<<(fine + 255) / 256, 256, 0, st>>>(out, fine, P);
+    return hipGetLastError();
+}
+
 hipError_t launch_tm_centre(const double* theta, int64_t n, const EvConst& ec, double* out, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     k_tm_centre<<<tm_grid(blocks256(n)), 256, 0, st>>>(theta, n, ec, out);
@@ -1309,7 +1331,12 @@ hipError_t launch_loglike_batch(const BatchPtrs& b, int ne, int64_t prologue_blo
 // FP32 sums over kBlk bins folded into FP64, the same masking of bins past a
 // lane's cut), with the detector terms combined with the draw's responses and
 // summed into the P moments of each chunk, written to tm_mom[(c P + p) npad + j].
-template <int NDET, int P>
+template <int P>
+struct PowRow {
+    float v[P];
+};
+
+template <int NDET, int P, bool TAB>
 __device__ __forceinline__ void split_tm_item(const EvDev& E, const EvPlan& p, int tile, int g, Rec32* srec,
                                               int* sred) {
     int j, kc, wmin, wmax;
@@ -1372,13 +1399,23 @@ __device__ __forceinline__ void split_tm_item(const EvDev& E, const EvPlan& p, i
                         yr = fmaf(rr[d], tr, fmaf(-ri[d], ti, yr));
                         yi = fmaf(rr[d], ti, fmaf(ri[d], tr, yi));
                     }
-                    const float x = ((float)k - kmid) * inv_half;
-                    float xp = 1.0f;
+                    if constexpr (TAB) {
+                        // the same powers from the event's table (scalar loads: k is uniform)
+                        const PowRow<P> pw = load_const((const PowRow<P>*)(E.tm_pow + (int64_t)(k - k0) * P));
 #pragma unroll
-                    for (int q = 0; q < P; ++q) {
-                        br[q] = fmaf(yr, xp, br[q]);
-                        bi[q] = fmaf(yi, xp, bi[q]);
-                        xp *= x;
+                        for (int q = 0; q < P; ++q) {
+                            br[q] = fmaf(yr, pw.v[q], br[q]);
+                            bi[q] = fmaf(yi, pw.v[q], bi[q]);
+                        }
+                    } else {
+                        const float x = ((float)k - kmid) * inv_half;
+                        float xp = 1.0f;
+#pragma unroll
+                        for (int q = 0; q < P; ++q) {
+                            br[q] = fmaf(yr, xp, br[q]);
+                            bi[q] = fmaf(yi, xp, bi[q]);
+                            xp *= x;
+                        }
                     }
                 }
                 if (kb < kA || kb < kc) {
@@ -1406,11 +1443,20 @@ __global__ __launch_bounds__(256) void k_b_split_tm(BatchHdr* __restrict__ hdr, 
     item_loop<false>(hdr, ioff, evs, [&](const Item& it) {
         const EvDev& E = evs[it.e];
         const EvPlan p = load_const(E.plan);
-        switch (E.ec.n_det) {
-            case 1: split_tm_item<1, P>(E, p, it.tile, it.g, srec, sred); break;
-            case 2: split_tm_item<2, P>(E, p, it.tile, it.g, srec, sred); break;
-            case 3: split_tm_item<3, P>(E, p, it.tile, it.g, srec, sred); break;
-            default: split_tm_item<4, P>(E, p, it.tile, it.g, srec, sred); break;
+        if (E.tm_pow) {
+            switch (E.ec.n_det) {
+                case 1: split_tm_item<1, P, true>(E, p, it.tile, it.g, srec, sred); break;
+                case 2: split_tm_item<2, P, true>(E, p, it.tile, it.g, srec, sred); break;
+                case 3: split_tm_item<3, P, true>(E, p, it.tile, it.g, srec, sred); break;
+                default: split_tm_item<4, P, true>(E, p, it.tile, it.g, srec, sred); break;
+            }
+        } else {
+            switch (E.ec.n_det) {
+                case 1: split_tm_item<1, P, false>(E, p, it.tile, it.g, srec, sred); break;
+                case 2: split_tm_item<2, P, false>(E, p, it.tile, it.g, srec, sred); break;
+                case 3: split_tm_item<3, P, false>(E, p, it.tile, it.g, srec, sred); break;
+                default: split_tm_item<4, P, false>(E, p, it.tile, it.g, srec, sred); break;
+            }
         }
     });
 }
