@@ -38,7 +38,7 @@ FP64_OPS_PER_TERM = 2 + 26 + 4
 # groups), from rocprofv3 FETCH_SIZE x 1.9999 + WRITE_SIZE x 1.0 (KiB per dispatch), the
 # factors read off a 1 GiB device-to-device copy in the same runs (profiles/
 # loglike_split_config1.md); None when the kernel has changed since the counters were taken.
-SPLIT_TRAFFIC_BYTES = 539229080
+SPLIT_TRAFFIC_BYTES = 537122371
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 # Algorithmic floating-point work per term (draw, detector, bin) of the split path: the FP64
 # phase polynomial (about 24 flops with its log term and scaling) shared by the detectors plus

@@ -634,6 +634,21 @@ __device__ __forceinline__ void split_item(const EvDev& E, const EvPlan& p, int 
             ranges(k0, k1, kA, kB);
             piece(srec + i * p.fine, k0, min(k1, gmax), kA, kB);
         }
+    } else if (p.n_groups == 1) {
+        // one group: the item's chunks tile [0, gmax) end to end, so it is staged
+        // in full pieces across the chunk boundaries (the same 16-bin blocks, in
+        // the same order, as the walk chunk by chunk; fewer barrier pairs)
+        int kA, kB;
+        ranges(0, K, kA, kB);
+        for (int ks = 0; ks < gmax; ks += kStage) {
+            const int ke = min(ks + kStage, gmax);
+            __syncthreads();  // the previous piece has been read
+            const uint4* src = (const uint4*)(tab + ks);
+            uint4* dst = (uint4*)srec;
+            for (int q = threadIdx.x; q < (ke - ks) * (int)(sizeof(Rec32) / 16); q += 256) dst[q] = src[q];
+            __syncthreads();
+            piece(srec, ks, ke, kA, kB);
+        }
     } else {
         for (int c = g; c < p.n_fine; c += p.n_groups) {
             const int k0 = c * p.fine;
