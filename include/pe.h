@@ -463,19 +463,27 @@ pe_status_t pe_tile_assign(int32_t dim, int32_t n_tiles, const double *tiles_y_d
 /*
  * Tile of each sample by waveform similarity (App. A maps the prior volume to
  * the template nearest in match; Sec. III takes the plain overlap for aligned
- * spins), for the 4-D parameter set with one detector: among the sample's
- * n_cand (1, 2, 4 or 8) nearest templates in whitened coordinates, the one of
- * largest match
- *   m(s, t) = |sum_k pw_k exp(2 pi i (Psi_s(f_k) - Psi_t(f_k)))| / sqrt(P_s P_t),
- * the overlap maximised over a constant phase and normalised: pw = 4 df
- * f^(-7/3) / S from the event's tables, the sum over the bins below both
- * points' cuts, P a point's sum of pw below its cut, Psi the phase in turns
- * with its 2 pi f tc term (FP64 phases and sine/cosine). The lowest template
- * index among equal matches. tiles_y_dev, tiles_theta_dev [4][ld_tiles]
- * (n_tiles used); y_dev, theta_dev [4][ld] (n used); outputs tile_of_dev [n]
- * int32 and, if not NULL, match_dev [n] (the chosen template's match).
- * Allocates its scratch and synchronises the stream. Errors: PE_ERR_ARG (not a
- * one-detector 4-D event, bad sizes, NULL), PE_ERR_OOM, PE_ERR_HIP.
+ * spins): among the sample's n_cand (1, 2, 4 or 8) nearest templates in
+ * whitened coordinates, the one of largest match
+ *   m(s, t) = |sum_k W_k exp(2 pi i (Psi_s(f_k) - Psi_t(f_k)))| / sqrt(P_s P_t),
+ * the overlap maximised over a constant phase and normalised: W_k =
+ * sum_d w_d pw_dk with pw = 4 df f^(-7/3) / S from the event's tables and w_d =
+ * |R_d|^2 / sum_e |R_e|^2 the detector's share of the sample's response power
+ * (one detector: 1), the sum over the bins below both points' cuts, P a
+ * point's sum_d w_d (sum of pw_d below its cut), Psi the phase in turns with its
+ * 2 pi f tc term (FP64 phases and sine/cosine). The lowest template index among
+ * equal matches.
+ *   4-D parameter set: one detector; tiles_y_dev, tiles_theta_dev [4][ld_tiles]
+ *   (n_tiles used); y_dev, theta_dev [4][ld] (n used).
+ *   11-D set: tiles over the intrinsic coordinates (a slice with a 4-bit
+ *   sub_mask); the templates and samples share the other coordinates (the
+ *   slice's centre), so the responses and delays are common and m is the
+ *   network overlap of the two waveforms; tiles_y_dev, y_dev [4][..] (the
+ *   sliced coordinates), tiles_theta_dev [11][ld_tiles], theta_dev [11][ld].
+ * Outputs tile_of_dev [n] int32 and, if not NULL, match_dev [n] (the chosen
+ * template's match). Allocates its scratch and synchronises the stream.
+ * Errors: PE_ERR_ARG (a 4-D event with more than one detector, bad sizes,
+ * NULL), PE_ERR_OOM, PE_ERR_HIP.
  */
 pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, const double *tiles_y_dev,
                                  const double *tiles_theta_dev, int64_t ld_tiles, int64_t n, const double *y_dev,

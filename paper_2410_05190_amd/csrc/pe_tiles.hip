@@ -247,8 +247,10 @@ __global__ __launch_bounds__(256) void k_tile_assign(int m, const double* __rest
 // candidates are its n_cand nearest templates in whitened coordinates; the
 // match picks among them (the lowest template index among equal matches).
 
-// Coefficient rows of points: A0..A7, B5, B6, tc ([kMatchRow][n]), cut, norm.
-constexpr int kMatchRow = 11;
+// Coefficient rows of points: A0..A7, B5, B6, tc, and the detector weights
+// |R_d|^2 / sum_e |R_e|^2 ([kMatchRow][n]); cut; norm sum_d w_d P_d(cut).
+constexpr int kMatchW = 11;
+constexpr int kMatchRow = kMatchW + PE_MAX_DET;
 
 __global__ __launch_bounds__(256) void k_match_rows(EvConst ec, const double* __restrict__ th, int64_t ld, int64_t n,
                                                     const double* __restrict__ pfx, double* __restrict__ rows,
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(256) void k_match_rows(EvConst ec, const double* __
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         double t[PE_MAX_DIM];
 #pragma unroll
-        for (int a = 0; a < PE_MAX_DIM; ++a) t[a] = a < 4 ? th[a * ld + i] : 0.0;
+        for (int a = 0; a < PE_MAX_DIM; ++a) t[a] = a < ec.dim ? th[a * ld + i] : 0.0;
         Src s;
         const int ok = source_from_theta(ec, t, s);
         PhaseCoef pc;
@@ -267,8 +269,23 @@ __global__ __launch_bounds__(256) void k_match_rows(EvConst ec, const double* __
         rows[9 * n + i] = pc.B6;
         rows[10 * n + i] = s.tc + s.dt[0];
         const int k = ok ? (int)kcut_of(ec, s.fisco) : 0;
+        // detector weights: each detector's share of the point's response power
+        // (one detector: exactly 1)
+        double r2[PE_MAX_DET], tot = 0.0;
+#pragma unroll
+        for (int d = 0; d < PE_MAX_DET; ++d) {
+            r2[d] = (d < ec.n_det) ? s.rre[d] * s.rre[d] + s.rim[d] * s.rim[d] : 0.0;
+            tot += r2[d];
+        }
+        double nm = 0.0;
+#pragma unroll
+        for (int d = 0; d < PE_MAX_DET; ++d) {
+            const double w = (d >= ec.n_det) ? 0.0 : (tot > 0.0 ? r2[d] / tot : 1.0 / ec.n_det);
+            rows[(kMatchW + d) * n + i] = w;
+            if (d < ec.n_det) nm += w * pfx[(int64_t)d * (ec.K + 1) + k];
+        }
         kc[i] = k;
-        nrm[i] = pfx[k];
+        nrm[i] = nm;
     }
 }
 
@@ -319,9 +336,11 @@ __global__ __launch_bounds__(256) void k_tile_topc(int m, const double* __restri
         for (int c = 0; c < C; ++c) cand[(int64_t)c * n + s] = (c < m) ? bi[c] : bi[0];
 }
 
-template <int C>
+// MERGE: keep the better of this launch's choice and the one already in
+// tile_of/match (earlier launches took lower template indices).
+template <int C, bool MERGE = false>
 __global__ __launch_bounds__(256) void k_tile_match(const Rec64* __restrict__ tab, const double* __restrict__ pw,
-                                                    int64_t n, const double* __restrict__ srow,
+                                                    int n_det, int64_t K, int64_t n, const double* __restrict__ srow,
                                                     const int* __restrict__ skc, const double* __restrict__ snrm,
                                                     int64_t m, const double* __restrict__ trow,
                                                     const int* __restrict__ tkc, const double* __restrict__ tnrm,
@@ -336,6 +355,9 @@ __global__ __launch_bounds__(256) void k_tile_match(const Rec64* __restrict__ ta
     B5s = srow[8 * n + sl];
     B6s = srow[9 * n + sl];
     tcs = srow[10 * n + sl];
+    double wd[PE_MAX_DET];
+#pragma unroll
+    for (int d = 0; d < PE_MAX_DET; ++d) wd[d] = srow[(kMatchW + d) * n + sl];
     const int kcs = skc[sl];
     int ti[C], kl[C], kmax = 0;
 #pragma unroll
@@ -359,7 +381,9 @@ __global__ __launch_bounds__(256) void k_tile_match(const Rec64* __restrict__ ta
     for (int c = 0; c < C; ++c) ar[c] = ai[c] = 0.0;
     for (int k = 0; k < wk; ++k) {
         const Rec64 r = load_const(tab + k);
-        const double w = load_const(pw + k);
+        // the bin's weight over the detectors (the points share their responses)
+        double w = wd[0] * load_const(pw + k);
+        for (int d = 1; d < n_det; ++d) w = fma(wd[d], load_const(pw + (int64_t)d * K + k), w);
         const double ps = fma(r.f, tcs, psi_turns(As, B5s, B6s, r.x, r.xm5, r.lnx));
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -383,8 +407,17 @@ __global__ __launch_bounds__(256) void k_tile_match(const Rec64* __restrict__ ta
             best = ti[c];
         }
     }
+    if (MERGE && !(bm > match[s])) return;  // ties keep the lower index found before
     tile_of[s] = best;
     if (match) match[s] = bm;
+}
+
+// Candidates t0 .. t0 + 7 for every sample (the last template repeated past m).
+__global__ __launch_bounds__(256) void k_fill_cand(int* __restrict__ cand, int64_t n, int t0, int m) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) cand[(int64_t)c * n + s] = min(t0 + c, m - 1);
 }
 
 // ---------------------------------------------------------------------- draws
@@ -809,9 +842,10 @@ extern "C" pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, cons
                                             const double* y_dev, const double* theta_dev, int64_t ld, int32_t n_cand,
                                             int32_t* tile_of_dev, double* match_dev, void* stream) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
-    if (ev->desc.params != PE_PARAMS_4D || ev->desc.n_det != 1)
-        return fail(PE_ERR_ARG, "match-based tiles take the 4-D parameter set with one detector");
-    if (n_cand != 1 && n_cand != 2 && n_cand != 4 && n_cand != 8) return fail(PE_ERR_ARG, "n_cand must be 1, 2, 4 or 8");
+    if (ev->desc.params == PE_PARAMS_4D && ev->desc.n_det != 1)
+        return fail(PE_ERR_ARG, "match-based tiles of the 4-D parameter set take one detector");
+    if (n_cand != 0 && n_cand != 1 && n_cand != 2 && n_cand != 4 && n_cand != 8)
+        return fail(PE_ERR_ARG, "n_cand must be 0 (every template), 1, 2, 4 or 8");
     if (n_tiles < 1 || n_tiles > (1 << 24) || ld_tiles < n_tiles) return fail(PE_ERR_ARG, "bad n_tiles or ld_tiles");
     if (n < 0 || n > ((int64_t)1 << 30) || ld < n) return fail(PE_ERR_ARG, "bad n or ld");
     if (!tiles_y_dev || !tiles_theta_dev || (n > 0 && (!y_dev || !theta_dev || !tile_of_dev)))
@@ -821,7 +855,7 @@ extern "C" pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, cons
     // scratch: rows, cuts and norms of the templates and samples, the candidates
     const int64_t m = n_tiles;
     const size_t bytes = sizeof(double) * (size_t)(kMatchRow + 1) * (size_t)(m + n) +
-                         sizeof(int) * (size_t)(m + n + (int64_t)n_cand * n) + 1024;
+                         sizeof(int) * (size_t)(m + n + (int64_t)(n_cand ? n_cand : 8) * n) + 1024;
     char* mem = nullptr;
     pe_status_t s = dalloc_bytes(&mem, bytes);
     if (s != PE_OK) return s;
@@ -832,28 +866,46 @@ extern "C" pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, cons
     double* snrm = c.take<double>((size_t)n);
     int* tkc = c.take<int>((size_t)m);
     int* skc = c.take<int>((size_t)n);
-    int* cand = c.take<int>((size_t)n_cand * n);
+    int* cand = c.take<int>((size_t)(n_cand ? n_cand : 8) * n);
     k_match_rows<<<nblocks(m), 256, 0, st>>>(ev->ec, tiles_theta_dev, ld_tiles, m, ev->pfx, trow, tkc, tnrm);
     k_match_rows<<<nblocks(n), 256, 0, st>>>(ev->ec, theta_dev, ld, n, ev->pfx, srow, skc, snrm);
     switch (n_cand) {
+        case 0:
+            // every template, eight per launch, the best kept across launches
+            if (match_dev == nullptr) {
+                dfree_bytes(mem);
+                return fail(PE_ERR_ARG, "n_cand 0 needs match_dev");
+            }
+            for (int t0 = 0; t0 < n_tiles; t0 += 8) {
+                k_fill_cand<<<nblocks(n), 256, 0, st>>>(cand, n, t0, n_tiles);
+                if (t0 == 0)
+                    k_tile_match<8><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow,
+                                                                skc, snrm, m, trow, tkc, tnrm, cand, tile_of_dev,
+                                                                match_dev);
+                else
+                    k_tile_match<8, true><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n,
+                                                                      srow, skc, snrm, m, trow, tkc, tnrm, cand,
+                                                                      tile_of_dev, match_dev);
+            }
+            break;
         case 1:
             k_tile_topc<1><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand);
-            k_tile_match<1><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, n, srow, skc, snrm, m, trow, tkc, tnrm,
+            k_tile_match<1><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow, skc, snrm, m, trow, tkc, tnrm,
                                                         cand, tile_of_dev, match_dev);
             break;
         case 2:
             k_tile_topc<2><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand);
-            k_tile_match<2><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, n, srow, skc, snrm, m, trow, tkc, tnrm,
+            k_tile_match<2><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow, skc, snrm, m, trow, tkc, tnrm,
                                                         cand, tile_of_dev, match_dev);
             break;
         case 4:
             k_tile_topc<4><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand);
-            k_tile_match<4><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, n, srow, skc, snrm, m, trow, tkc, tnrm,
+            k_tile_match<4><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow, skc, snrm, m, trow, tkc, tnrm,
                                                         cand, tile_of_dev, match_dev);
             break;
         default:
             k_tile_topc<8><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand);
-            k_tile_match<8><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, n, srow, skc, snrm, m, trow, tkc, tnrm,
+            k_tile_match<8><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow, skc, snrm, m, trow, tkc, tnrm,
                                                         cand, tile_of_dev, match_dev);
             break;
     }

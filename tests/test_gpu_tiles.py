@@ -254,6 +254,41 @@ def test_intrinsic_slice_and_bank_bit_exact(mask):
     ev.close()
 
 
+@pytest.mark.parametrize("n_cand", [0, 1, 8])
+def test_intrinsic_match_assignment_against_the_oracle(n_cand):
+    """Tiles by waveform match over the intrinsic coordinates of the 11-D set (three detectors;
+    templates and samples share the slice centre's extrinsic coordinates, so the match is the
+    network overlap with the common responses): the chosen template's match equals the oracle's
+    match of that pair (1e-9), the oracle's best template is chosen wherever it is among the
+    candidates (unless another candidate matches within 1e-9; n_cand 0: every template, the
+    oracle's brute force), and one candidate is the nearest."""
+    torch_cuda()
+    b = build_event(1, 0, n_bins=4000)
+    so, sg, g = _intrinsic_slices(b, 3.0)
+    tyo, ttho, _ = b.ev.tile_bank(so, 1.0, 5, 1, 2048, 300, 0.002, 40)
+    yo, tho, lpo = b.ev.slice_sample(so, 5, 2, 0, 3000)
+    yo, tho = yo[:, :300], tho[:, :300]
+    ev, data, psd = upload_event(b)
+    note(f"intrinsic match tiles: {ttho.shape[1]} templates, {tho.shape[1]} samples, {n_cand} candidates")
+    to, mv = binding.tile_assign_match(ev, dev(tyo), dev(ttho), dev(yo), dev(tho), n_cand=n_cand)
+    to, mv = host(to), host(mv)
+    bo, mo = b.ev.tile_assign_match(ttho, tho)
+    d2 = ((yo[:, :, None] - tyo[:, None, :]) ** 2).sum(axis=0)
+    near = np.argsort(d2, axis=1, kind="stable")[:, :(n_cand or tyo.shape[1])]
+    if n_cand == 1:
+        assert np.array_equal(to, oracle.tile_assign(tyo, yo))
+    pair = np.array([b.ev.match(tho[:, s], ttho[:, to[s]]) for s in range(tho.shape[1])])
+    np.testing.assert_allclose(mv, pair, rtol=0, atol=1e-9)
+    inside = np.array([bo[s] in near[s] for s in range(tho.shape[1])])
+    same = to == bo
+    close = np.abs(mv - mo) <= 1e-9
+    note(f"  oracle's best among the candidates for {inside.sum()} of {inside.size}; same tile for {same.sum()}")
+    assert np.all(same[inside] | close[inside])
+    if n_cand == 0:
+        assert inside.all()
+    ev.close()
+
+
 def _extrinsic_inputs(b, so, n, seed):
     """Tile draws of the oracle over an intrinsic bank (arbitrary finite template values)."""
     tyo, ttho, _ = b.ev.tile_bank(so, 1.0, 5, 1, 2048, 500, 0.002, 30)

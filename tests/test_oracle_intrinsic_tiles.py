@@ -273,3 +273,29 @@ def test_conditional_extrinsic_with_the_likelihood_marginals():
                                          conditional=True)
     m, S = _conditional(th0, g, th0[:4], I, E)
     np.testing.assert_allclose(m, th0[E], rtol=0, atol=1e-12)
+
+
+def test_network_match_at_shared_extrinsics_is_the_intrinsic_match():
+    """The match of two 11-D points that share their extrinsic coordinates (as a slice over the
+    intrinsic ones makes them): with equal PSDs the detectors' common responses and delays factor
+    out, so the three-detector network match equals the one-detector match of the same points, does
+    not move when the shared extrinsic values change, and is 1 for a point with itself."""
+    b3 = build_event(1, 0, n_bins=3000)
+    b1 = build_event(1, 0, n_bins=3000, n_det=1)
+    a = b3.theta_inj.copy()
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        bpt = a.copy()
+        bpt[0] *= 1.0 + 2e-4 * rng.standard_normal()
+        bpt[1] = min(1.0, bpt[1] * (1.0 + 0.02 * rng.standard_normal()))
+        bpt[2] += 0.02 * rng.standard_normal()
+        bpt[3] += 0.02 * rng.standard_normal()
+        m3 = b3.ev.match(a, bpt)
+        m1 = b1.ev.match(a, bpt)
+        assert 0.0 < m3 < 1.0
+        assert abs(m3 - m1) <= 1e-12, (m3, m1)
+        a2, b2 = a.copy(), bpt.copy()
+        for k, v in ((4, 1.3), (5, -0.4), (6, 2.1), (7, 0.3), (8, 0.7 * a[8]), (9, a[9] + 1e-3), (10, 4.0)):
+            a2[k] = b2[k] = v
+        assert abs(b3.ev.match(a2, b2) - m3) <= 1e-12
+    assert abs(b3.ev.match(a, a) - 1.0) <= 1e-14
