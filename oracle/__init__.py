@@ -118,6 +118,11 @@ def lib():
         L.peo_match.argtypes = [ctypes.POINTER(_Event), _dp, _dp]
         L.peo_tile_assign_match.argtypes = [ctypes.POINTER(_Event), ctypes.c_long, _dp, ctypes.c_long,
                                             ctypes.c_long, _dp, ctypes.c_long, _ip, _dp]
+        L.peo_match_shift.restype = ctypes.c_double
+        L.peo_match_shift.argtypes = [ctypes.POINTER(_Event), _dp, _dp, ctypes.c_double, ctypes.c_int]
+        L.peo_tile_assign_match_shift.argtypes = [ctypes.POINTER(_Event), ctypes.c_long, _dp, ctypes.c_long,
+                                                  ctypes.c_long, _dp, ctypes.c_long, ctypes.c_double, ctypes.c_int,
+                                                  _ip, _dp]
         L.peo_tile_draw.restype = ctypes.c_int
         L.peo_tile_draw.argtypes = [ctypes.c_long, _dp, ctypes.c_long, _ip, _dp, ctypes.c_int, _dp, ctypes.c_long,
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_long, _dp, _dp, _dp, _lp]
@@ -376,6 +381,22 @@ class Event:
     def match(self, theta_a, theta_b):
         """Waveform match of two points (overlap maximised over a constant phase, normalised)."""
         return lib().peo_match(self.ref, _p(_f64(theta_a)), _p(_f64(theta_b)))
+
+    def match_shift(self, theta_a, theta_b, dt, n_shift):
+        """The match maximised over the time shifts j dt, |j| <= n_shift, too (peo_match_shift)."""
+        return lib().peo_match_shift(self.ref, _p(_f64(theta_a)), _p(_f64(theta_b)), float(dt), int(n_shift))
+
+    def tile_assign_match_shift(self, tiles_theta, theta, dt, n_shift):
+        """Template of largest shift-maximised match of every sample (brute force): (tile_of, match)."""
+        tt = _f64(tiles_theta)
+        th = _f64(theta)
+        m = tt.shape[1]
+        n = th.shape[1]
+        out = np.zeros(n, dtype=np.int32)
+        mv = np.zeros(n)
+        lib().peo_tile_assign_match_shift(self.ref, m, _p(tt), m, n, _p(th), n, float(dt), int(n_shift),
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(mv))
+        return out, mv
 
     def tile_assign_match(self, tiles_theta, theta):
         """Template of largest match of every sample (brute force): (tile_of, match)."""

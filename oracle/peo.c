@@ -1939,6 +1939,113 @@ static double match_pair(const peo_event *ev, const peo_source *sa, const peo_so
     return hypot(nval(&re), nval(&im)) / sqrt(nval(&na) * nval(&nb));
 }
 
+/* The match maximised over a grid of time shifts as well (App. A maps the prior
+ * volume to templates by their overlap maximised over the extrinsic time and
+ * phase): max over tau_j = j dt, |j| <= n_shift, of
+ *   |sum_d sum_k w_k conj(a_dk) b_dk exp(-2 pi i f_k tau_j)| / sqrt(<a,a> <b,b>),
+ * b shifted in time by tau_j (its tc moved by tau_j), each bin's rotation from
+ * the sine and cosine of the full angle. */
+static double match_pair_shift(const peo_event *ev, const peo_source *sa, const peo_source *sb, double dt,
+                               int n_shift)
+{
+    const int nj = 2 * n_shift + 1;
+    nsum na = {0, 0}, nb = {0, 0};
+    nsum *re = (nsum *)calloc((size_t)nj, sizeof(nsum)), *im = (nsum *)calloc((size_t)nj, sizeof(nsum));
+    double best = 0.0;
+    int d, j;
+    long k;
+    if (!re || !im) {
+        free(re);
+        free(im);
+        return -1.0;
+    }
+    for (d = 0; d < ev->n_det; d++) {
+        const double *S = ev->psd + (long)d * ev->n_bins;
+        for (k = 0; k < ev->n_bins && (k < sa->kcut || k < sb->kcut); k++) {
+            double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr, ci;
+            const double w = 4.0 * ev->df / S[k];
+            const double f = ev->f_lo + (double)k * ev->df;
+            if (k < sa->kcut)
+                wf_bin(ev, sa, d, k, &ar, &ai);
+            if (k < sb->kcut)
+                wf_bin(ev, sb, d, k, &br, &bi);
+            nadd(&na, w * (ar * ar + ai * ai));
+            nadd(&nb, w * (br * br + bi * bi));
+            cr = w * (ar * br + ai * bi); /* w conj(a) b */
+            ci = w * (ar * bi - ai * br);
+            for (j = 0; j < nj; j++) {
+                const double ang = -2.0 * PI * f * ((double)(j - n_shift) * dt);
+                const double c = cos(ang), sn = sin(ang);
+                nadd(&re[j], cr * c - ci * sn);
+                nadd(&im[j], cr * sn + ci * c);
+            }
+        }
+    }
+    if (nval(&na) > 0.0 && nval(&nb) > 0.0)
+        for (j = 0; j < nj; j++) {
+            const double m = hypot(nval(&re[j]), nval(&im[j])) / sqrt(nval(&na) * nval(&nb));
+            if (m > best)
+                best = m;
+        }
+    free(re);
+    free(im);
+    return best;
+}
+
+double peo_match_shift(const peo_event *ev, const double *theta_a, const double *theta_b, double dt, int n_shift)
+{
+    peo_source sa, sb;
+    double ta[PEO_MAX_DIM], tb[PEO_MAX_DIM];
+    likelihood_theta(ev, theta_a, ta);
+    likelihood_theta(ev, theta_b, tb);
+    if (!peo_source_from_theta(ev, ta, &sa) || !peo_source_from_theta(ev, tb, &sb))
+        return -1.0;
+    sa.kcut = peo_kcut(ev, sa.fisco);
+    sb.kcut = peo_kcut(ev, sb.fisco);
+    return match_pair_shift(ev, &sa, &sb, dt, n_shift);
+}
+
+/* Tile of each sample by the time-shift-maximised match (brute force over the
+ * templates and the shifts); as peo_tile_assign_match otherwise. */
+void peo_tile_assign_match_shift(const peo_event *ev, long n_tiles, const double *tth, long ld_t, long n,
+                                 const double *th, long ld_s, double dt, int n_shift, int *tile_of, double *match)
+{
+    const int D = ev->params == PEO_PARAMS_4D ? 4 : 11;
+    peo_source *st = (peo_source *)malloc(sizeof(peo_source) * (size_t)(n_tiles > 0 ? n_tiles : 1));
+    long j, s;
+    for (j = 0; j < n_tiles; j++) {
+        double t[PEO_MAX_DIM], tl[PEO_MAX_DIM];
+        int a;
+        for (a = 0; a < D; a++)
+            t[a] = tth[(long)a * ld_t + j];
+        likelihood_theta(ev, t, tl);
+        peo_source_from_theta(ev, tl, &st[j]);
+        st[j].kcut = peo_kcut(ev, st[j].fisco);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (s = 0; s < n; s++) {
+        double t[PEO_MAX_DIM], tl[PEO_MAX_DIM], bm = -1.0;
+        peo_source ss;
+        long best = 0, jj;
+        int a;
+        for (a = 0; a < D; a++)
+            t[a] = th[(long)a * ld_s + s];
+        likelihood_theta(ev, t, tl);
+        peo_source_from_theta(ev, tl, &ss);
+        ss.kcut = peo_kcut(ev, ss.fisco);
+        for (jj = 0; jj < n_tiles; jj++) {
+            const double m = match_pair_shift(ev, &ss, &st[jj], dt, n_shift);
+            if (m > bm) {
+                bm = m;
+                best = jj;
+            }
+        }
+        tile_of[s] = (int)best;
+        match[s] = bm;
+    }
+    free(st);
+}
+
 /* Match of two parameter points (see match_pair); -1 if either is outside the
  * support. */
 double peo_match(const peo_event *ev, const double *theta_a, const double *theta_b)

@@ -202,6 +202,11 @@ void peo_tile_assign(int D, long n_tiles, const double *ty, long ld_t, long n, c
 /* Waveform match of two points (the overlap maximised over a constant phase,
  * normalised); -1 outside the support. */
 double peo_match(const peo_event *ev, const double *theta_a, const double *theta_b);
+/* The match maximised over time shifts tau_j = j dt, |j| <= n_shift, as well. */
+double peo_match_shift(const peo_event *ev, const double *theta_a, const double *theta_b, double dt, int n_shift);
+/* Tile of each sample by the shift-maximised match (brute force). */
+void peo_tile_assign_match_shift(const peo_event *ev, long n_tiles, const double *tth, long ld_t, long n,
+                                 const double *th, long ld_s, double dt, int n_shift, int *tile_of, double *match);
 /* Tile of each sample by largest match (brute force over the templates). */
 void peo_tile_assign_match(const peo_event *ev, long n_tiles, const double *tth, long ld_t, long n,
                            const double *th, long ld_s, int *tile_of, double *match);

@@ -299,3 +299,56 @@ def test_network_match_at_shared_extrinsics_is_the_intrinsic_match():
             a2[k] = b2[k] = v
         assert abs(b3.ev.match(a2, b2) - m3) <= 1e-12
     assert abs(b3.ev.match(a, a) - 1.0) <= 1e-14
+
+
+def test_shift_maximised_match_pins():
+    """The match maximised over time shifts j dt (|j| <= J) as well: no shifts is the plain match;
+    a copy of a point moved in tc by an exact grid shift (any other coordinate shared) matches it to
+    1; the maximum over the grid is at least the unshifted match and grows with the grid; and the
+    maximum over a fine grid agrees with a scalar maximisation of the closed-form shifted overlap
+    (numpy, from the oracle's waveforms: |sum_k w conj(a_k) b_k e^(-2 pi i f_k t)|)."""
+    from scipy.optimize import minimize_scalar
+
+    b = build_event(1, 0, n_bins=3000)
+    a = b.theta_inj.copy()
+    rng = np.random.default_rng(6)
+    dt = 2e-4
+    for _ in range(3):
+        bpt = a.copy()
+        bpt[0] *= 1.0 + 3e-4 * rng.standard_normal()
+        bpt[2] += 0.02 * rng.standard_normal()
+        m0 = b.ev.match(a, bpt)
+        assert abs(b.ev.match_shift(a, bpt, dt, 0) - m0) <= 1e-13
+        m4 = b.ev.match_shift(a, bpt, dt, 4)
+        m16 = b.ev.match_shift(a, bpt, dt, 16)
+        assert m0 <= m4 + 1e-15 <= m16 + 2e-15
+        # the same point moved by +3 dt in tc: the shifts -3 dt bring it back
+        c = a.copy()
+        c[9] += 3 * dt
+        assert abs(b.ev.match_shift(a, c, dt, 4) - 1.0) <= 1e-11
+        assert b.ev.match_shift(a, c, dt, 2) < 1.0 - 1e-6
+    # the closed form of the shifted overlap (numpy on the oracle's waveforms) on the same grid, and
+    # a continuous maximisation about its best grid point
+    bpt = a.copy()
+    bpt[0] *= 1.0 + 2e-5
+    bpt[9] += 3.3e-4
+    f = b.f_lo + b.df * np.arange(b.n_bins)
+    ha = b.ev.waveform(a)
+    hb = b.ev.waveform(bpt)
+    w = 4 * b.df / b.psd.astype(np.float64)
+    c = (w * np.conj(ha) * hb).sum(axis=0)
+    na = float((w * np.abs(ha) ** 2).sum())
+    nb = float((w * np.abs(hb) ** 2).sum())
+
+    def ov(t):
+        return abs((c * np.exp(-2j * np.pi * f * t)).sum()) / math.sqrt(na * nb)
+
+    dt, J = 2e-5, 250
+    grid = np.array([ov(j * dt) for j in range(-J, J + 1)])
+    got = b.ev.match_shift(a, bpt, dt, J)
+    assert abs(got - grid.max()) <= 1e-12
+    jb = int(np.argmax(grid))
+    assert 0 < jb < 2 * J  # an interior maximum (the chirp mass's shift is absorbed by tc)
+    t0 = (jb - J) * dt
+    r = minimize_scalar(lambda t: -ov(t), bounds=(t0 - dt, t0 + dt), method="bounded", options={"xatol": 1e-10})
+    assert got <= -r.fun + 1e-12 and got >= -r.fun - 1e-3
