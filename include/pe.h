@@ -491,6 +491,23 @@ pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, const double *t
                                  double *match_dev, void *stream);
 
 /*
+ * pe_tile_assign_match with the match maximised over time shifts as well (App.
+ * A takes the overlap maximised over the extrinsic time and phase; for tiles
+ * over the 11-D set's intrinsic coordinates tc is one of the shared extrinsic
+ * coordinates):
+ *   m(s, t) = max_j |sum_k W_k exp(2 pi i (Psi_s - Psi_t - f_k tau_j))| / sqrt(P_s P_t),
+ * tau_j = j dt, j = -n_shift .. n_shift (the template moved in time by tau_j).
+ * dt > 0 (seconds), n_shift 1 .. 4096; match_dev is required; n_cand as for
+ * pe_tile_assign_match (0: every template). Costs about (2 n_shift + 1) / 8
+ * walks over the bins per candidate. Errors as pe_tile_assign_match.
+ */
+pe_status_t pe_tile_assign_match_shift(pe_event_t ev, int32_t n_tiles, const double *tiles_y_dev,
+                                       const double *tiles_theta_dev, int64_t ld_tiles, int64_t n,
+                                       const double *y_dev, const double *theta_dev, int64_t ld, int32_t n_cand,
+                                       double dt, int32_t n_shift, int32_t *tile_of_dev, double *match_dev,
+                                       void *stream);
+
+/*
  * Proposal draws from the tiles (Sec. II.A; App. A, the proposal): sample s
  * (of P) carries the mass m_s = exp(ll_t(s) - max ll + lp_s - max lp) (its
  * tile's template log-likelihood tile_loglike_dev[t(s)] and its log prior

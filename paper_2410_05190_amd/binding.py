@@ -34,7 +34,7 @@ MAX_DET = 4
 
 EXPORTS = ["pe_dim", "pe_event_create", "pe_event_update", "pe_event_status", "pe_event_reserve",
            "pe_event_destroy", "pe_metric", "pe_draw", "pe_mixture_logq", "pe_loglike_batch", "pe_loglike_multi", "pe_batch_run", "pe_weights_ess", "pe_weights_ess_noalloc", "pe_proposal_update", "pe_refine", "pe_slice_sample", "pe_tile_bank",
-           "pe_tile_assign", "pe_tile_assign_match", "pe_tile_draw", "pe_tile_extrinsic", "pe_tile_reweight", "pe_relbin_setup", "pe_relbin_edges",
+           "pe_tile_assign", "pe_tile_assign_match", "pe_tile_assign_match_shift", "pe_tile_draw", "pe_tile_extrinsic", "pe_tile_reweight", "pe_relbin_setup", "pe_relbin_edges",
            "pe_waveform",
            "pe_rng_uniforms", "pe_profile_enable", "pe_profile_read", "pe_set_chunks", "pe_set_plan", "pe_get_plan",
            "pe_autotune_plan", "pe_set_split_guard", "pe_get_split_guard", "pe_loglike_counts", "pe_last_error",
@@ -163,6 +163,8 @@ def load(path=LIB_PATH):
         "pe_tile_assign": (i32, [i32, i32, dp, i64, i64, dp, i64, vp, vp]),
         "pe_tile_draw": (i32, [i32, dp, i64, vp, dp, i32, dp, i64, u64, u32, i64, dp, dp, dp, vp, vp]),
         "pe_tile_assign_match": (i32, [vp, i32, dp, dp, i64, i64, dp, dp, i64, i32, vp, dp, vp]),
+        "pe_tile_assign_match_shift": (i32, [vp, i32, dp, dp, i64, i64, dp, dp, i64, i32, ctypes.c_double, i32, vp,
+                                              dp, vp]),
         "pe_tile_reweight": (i32, [i32, dp, i64, vp, dp, i64, vp, dp, ctypes.c_double, dp, vp]),
         "pe_relbin_setup": (i32, [vp, dp, ctypes.c_double, i32, vp]),
         "pe_relbin_edges": (i32, [vp, vp, i32, ctypes.POINTER(i32)]),
@@ -664,6 +666,27 @@ def tile_assign(tiles_y, y, stream=None):
                                  ctypes.c_void_p(yy.data_ptr()), int(yy.stride(0)), ctypes.c_void_p(out.data_ptr()),
                                  _stream(stream)))
     return out
+
+
+def tile_assign_match_shift(ev, tiles_y, tiles_theta, y, theta, dt, n_shift, n_cand=8, stream=None):
+    """pe_tile_assign_match_shift: as tile_assign_match, the match maximised over the time shifts
+    j dt (|j| <= n_shift) as well."""
+    import torch
+    m = tiles_y.shape[1]
+    n = y.shape[1]
+    ty = tiles_y.contiguous()
+    tt = tiles_theta.contiguous()
+    yy = y.contiguous()
+    th = theta.contiguous()
+    out = torch.empty(n, dtype=torch.int32, device=y.device)
+    mv = torch.empty(n, dtype=torch.float64, device=y.device)
+    h = ev.handle if isinstance(ev, Event) else ev
+    _check(load().pe_tile_assign_match_shift(h, int(m), ctypes.c_void_p(ty.data_ptr()),
+                                             ctypes.c_void_p(tt.data_ptr()), int(m), int(n),
+                                             ctypes.c_void_p(yy.data_ptr()), ctypes.c_void_p(th.data_ptr()), int(n),
+                                             int(n_cand), float(dt), int(n_shift), ctypes.c_void_p(out.data_ptr()),
+                                             ctypes.c_void_p(mv.data_ptr()), _stream(stream)))
+    return out, mv
 
 
 def tile_assign_match(ev, tiles_y, tiles_theta, y, theta, n_cand=8, stream=None):

@@ -412,6 +412,92 @@ __global__ __launch_bounds__(256) void k_tile_match(const Rec64* __restrict__ ta
     if (match) match[s] = bm;
 }
 
+// The match maximised over the time shifts tau_j = j dt (|j| <= n_shift) too:
+// for each candidate (one at a time) and each block of 8 shifts, a walk over
+// the bins accumulates O_j = sum_k W_k exp(2 pi i (Psi_s - Psi_t - f_k tau_j)),
+// the block's first rotation from its angle, the next ones by the bin's step
+// exp(-2 pi i f_k dt). MERGE as in k_tile_match.
+constexpr int kShiftBlock = 8;
+
+template <bool MERGE>
+__global__ __launch_bounds__(256) void k_tile_match_shift(const Rec64* __restrict__ tab, const double* __restrict__ pw,
+                                                          int n_det, int64_t K, int64_t n,
+                                                          const double* __restrict__ srow, const int* __restrict__ skc,
+                                                          const double* __restrict__ snrm, int64_t m,
+                                                          const double* __restrict__ trow, const int* __restrict__ tkc,
+                                                          const double* __restrict__ tnrm, const int* __restrict__ cand,
+                                                          int n_cand, double dt, int n_shift,
+                                                          int* __restrict__ tile_of, double* __restrict__ match) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = s < n;
+    const int64_t sl = valid ? s : n - 1;
+    double As[8], B5s, B6s, tcs;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) As[a] = srow[a * n + sl];
+    B5s = srow[8 * n + sl];
+    B6s = srow[9 * n + sl];
+    tcs = srow[10 * n + sl];
+    double wd[PE_MAX_DET];
+#pragma unroll
+    for (int d = 0; d < PE_MAX_DET; ++d) wd[d] = srow[(kMatchW + d) * n + sl];
+    const int kcs = skc[sl];
+    const int nj = 2 * n_shift + 1;
+    double bm = -1.0;
+    int best = cand[sl];
+    for (int c = 0; c < n_cand; ++c) {
+        const int ti = cand[(int64_t)c * n + sl];
+        double At[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) At[a] = trow[a * m + ti];
+        const double B5t = trow[8 * m + ti], B6t = trow[9 * m + ti], tct = trow[10 * m + ti];
+        const int kl = min(kcs, tkc[ti]);
+        int wk = kl;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) wk = max(wk, __shfl_xor(wk, o));
+        wk = __builtin_amdgcn_readfirstlane(wk);
+        double mc = 0.0;
+        for (int j0 = 0; j0 < nj; j0 += kShiftBlock) {
+            const double tau0 = (double)(j0 - n_shift) * dt;
+            double orr[kShiftBlock], oi[kShiftBlock];
+#pragma unroll
+            for (int q = 0; q < kShiftBlock; ++q) orr[q] = oi[q] = 0.0;
+            for (int k = 0; k < wk; ++k) {
+                const Rec64 r = load_const(tab + k);
+                double w = wd[0] * load_const(pw + k);
+                for (int d = 1; d < n_det; ++d) w = fma(wd[d], load_const(pw + (int64_t)d * K + k), w);
+                const double ps = fma(r.f, tcs, psi_turns(As, B5s, B6s, r.x, r.xm5, r.lnx));
+                const double pt = fma(r.f, tct, psi_turns(At, B5t, B6t, r.x, r.xm5, r.lnx));
+                double sn, cs, rs, rc;
+                sincos_turns(fract64(ps - pt - r.f * tau0), sn, cs);
+                sincos_turns(fract64(-r.f * dt), rs, rc);
+                const double wm = (k < kl) ? w : 0.0;
+                double zr = wm * cs, zi = wm * sn;
+#pragma unroll
+                for (int q = 0; q < kShiftBlock; ++q) {
+                    orr[q] += zr;
+                    oi[q] += zi;
+                    const double nr = zr * rc - zi * rs;
+                    zi = zr * rs + zi * rc;
+                    zr = nr;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kShiftBlock; ++q)
+                if (j0 + q < nj) mc = fmax(mc, hypot(orr[q], oi[q]));
+        }
+        const double den = snrm[sl] * tnrm[ti];
+        mc = den > 0.0 ? mc / sqrt(den) : 0.0;
+        if (mc > bm || (mc == bm && ti < best)) {
+            bm = mc;
+            best = ti;
+        }
+    }
+    if (!valid) return;
+    if (MERGE && !(bm > match[s])) return;
+    tile_of[s] = best;
+    match[s] = bm;
+}
+
 // Candidates t0 .. t0 + 7 for every sample (the last template repeated past m).
 __global__ __launch_bounds__(256) void k_fill_cand(int* __restrict__ cand, int64_t n, int t0, int m) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -837,11 +923,15 @@ extern "C" pe_status_t pe_tile_assign(int32_t dim, int32_t n_tiles, const double
     return PE_OK;
 }
 
-extern "C" pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, const double* tiles_y_dev,
-                                            const double* tiles_theta_dev, int64_t ld_tiles, int64_t n,
-                                            const double* y_dev, const double* theta_dev, int64_t ld, int32_t n_cand,
-                                            int32_t* tile_of_dev, double* match_dev, void* stream) {
+// pe_tile_assign_match (n_shift 0) and pe_tile_assign_match_shift.
+static pe_status_t assign_match(pe_event_t ev, int32_t n_tiles, const double* tiles_y_dev,
+                                const double* tiles_theta_dev, int64_t ld_tiles, int64_t n, const double* y_dev,
+                                const double* theta_dev, int64_t ld, int32_t n_cand, double dt, int32_t n_shift,
+                                int32_t* tile_of_dev, double* match_dev, void* stream) {
     if (!ev) return fail(PE_ERR_ARG, "event is NULL");
+    if (n_shift < 0 || n_shift > 4096) return fail(PE_ERR_ARG, "n_shift must be in 0..4096");
+    if (n_shift > 0 && !(dt > 0.0 && std::isfinite(dt))) return fail(PE_ERR_ARG, "dt must be positive and finite");
+    if (n_shift > 0 && match_dev == nullptr) return fail(PE_ERR_ARG, "the shift search needs match_dev");
     if (ev->desc.params == PE_PARAMS_4D && ev->desc.n_det != 1)
         return fail(PE_ERR_ARG, "match-based tiles of the 4-D parameter set take one detector");
     if (n_cand != 0 && n_cand != 1 && n_cand != 2 && n_cand != 4 && n_cand != 8)
@@ -869,7 +959,33 @@ extern "C" pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, cons
     int* cand = c.take<int>((size_t)(n_cand ? n_cand : 8) * n);
     k_match_rows<<<nblocks(m), 256, 0, st>>>(ev->ec, tiles_theta_dev, ld_tiles, m, ev->pfx, trow, tkc, tnrm);
     k_match_rows<<<nblocks(n), 256, 0, st>>>(ev->ec, theta_dev, ld, n, ev->pfx, srow, skc, snrm);
-    switch (n_cand) {
+    if (n_shift > 0) {
+        // candidates: the n_cand nearest, or every template eight per launch
+        if (n_cand > 0) {
+            switch (n_cand) {
+                case 1: k_tile_topc<1><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand); break;
+                case 2: k_tile_topc<2><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand); break;
+                case 4: k_tile_topc<4><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand); break;
+                default: k_tile_topc<8><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand); break;
+            }
+            k_tile_match_shift<false><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow,
+                                                                 skc, snrm, m, trow, tkc, tnrm, cand, n_cand, dt,
+                                                                 n_shift, tile_of_dev, match_dev);
+        } else {
+            for (int t0 = 0; t0 < n_tiles; t0 += 8) {
+                const int nc = std::min(8, n_tiles - t0);
+                k_fill_cand<<<nblocks(n), 256, 0, st>>>(cand, n, t0, n_tiles);
+                if (t0 == 0)
+                    k_tile_match_shift<false><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K,
+                                                                         n, srow, skc, snrm, m, trow, tkc, tnrm, cand,
+                                                                         nc, dt, n_shift, tile_of_dev, match_dev);
+                else
+                    k_tile_match_shift<true><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K,
+                                                                        n, srow, skc, snrm, m, trow, tkc, tnrm, cand,
+                                                                        nc, dt, n_shift, tile_of_dev, match_dev);
+            }
+        }
+    } else switch (n_cand) {
         case 0:
             // every template, eight per launch, the best kept across launches
             if (match_dev == nullptr) {
@@ -914,6 +1030,24 @@ extern "C" pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, cons
     dfree_bytes(mem);
     if (e != hipSuccess) return fail(PE_ERR_HIP, hipGetErrorString(e));
     return PE_OK;
+}
+
+extern "C" pe_status_t pe_tile_assign_match(pe_event_t ev, int32_t n_tiles, const double* tiles_y_dev,
+                                            const double* tiles_theta_dev, int64_t ld_tiles, int64_t n,
+                                            const double* y_dev, const double* theta_dev, int64_t ld, int32_t n_cand,
+                                            int32_t* tile_of_dev, double* match_dev, void* stream) {
+    return assign_match(ev, n_tiles, tiles_y_dev, tiles_theta_dev, ld_tiles, n, y_dev, theta_dev, ld, n_cand, 0.0, 0,
+                        tile_of_dev, match_dev, stream);
+}
+
+extern "C" pe_status_t pe_tile_assign_match_shift(pe_event_t ev, int32_t n_tiles, const double* tiles_y_dev,
+                                                  const double* tiles_theta_dev, int64_t ld_tiles, int64_t n,
+                                                  const double* y_dev, const double* theta_dev, int64_t ld,
+                                                  int32_t n_cand, double dt, int32_t n_shift, int32_t* tile_of_dev,
+                                                  double* match_dev, void* stream) {
+    if (n_shift < 1) return fail(PE_ERR_ARG, "n_shift must be at least 1");
+    return assign_match(ev, n_tiles, tiles_y_dev, tiles_theta_dev, ld_tiles, n, y_dev, theta_dev, ld, n_cand, dt,
+                        n_shift, tile_of_dev, match_dev, stream);
 }
 
 extern "C" pe_status_t pe_tile_draw(int32_t n_tiles, const double* tile_loglike_dev, int64_t n_samples,

@@ -289,6 +289,41 @@ def test_intrinsic_match_assignment_against_the_oracle(n_cand):
     ev.close()
 
 
+@pytest.mark.parametrize("n_cand", [0, 8])
+def test_intrinsic_match_with_time_shifts_against_the_oracle(n_cand):
+    """The intrinsic match tiles with the match maximised over a grid of time shifts too (App. A
+    maximises over the extrinsic time and phase): chosen template's match equals the oracle's
+    shift-maximised match of that pair (1e-9), the oracle's brute-force best is chosen wherever it is
+    among the candidates (n_cand 0: always), unless another candidate matches within 1e-9; the
+    shift-maximised match is never below the unshifted one of the same template."""
+    torch_cuda()
+    b = build_event(1, 0, n_bins=2000)
+    so, sg, g = _intrinsic_slices(b, 3.0)
+    tyo, ttho, _ = b.ev.tile_bank(so, 1.0, 5, 1, 2048, 120, 0.002, 30)
+    yo, tho, lpo = b.ev.slice_sample(so, 5, 2, 0, 2000)
+    yo, tho = yo[:, :120], tho[:, :120]
+    dt, J = 1e-4, 12
+    ev, data, psd = upload_event(b)
+    note(f"shift-maximised match tiles: {ttho.shape[1]} templates, {tho.shape[1]} samples, n_cand {n_cand}, "
+         f"shifts {2 * J + 1} of {dt} s")
+    to, mv = binding.tile_assign_match_shift(ev, dev(tyo), dev(ttho), dev(yo), dev(tho), dt, J, n_cand=n_cand)
+    to, mv = host(to), host(mv)
+    bo, mo = b.ev.tile_assign_match_shift(ttho, tho, dt, J)
+    pair = np.array([b.ev.match_shift(tho[:, s], ttho[:, to[s]], dt, J) for s in range(tho.shape[1])])
+    np.testing.assert_allclose(mv, pair, rtol=0, atol=1e-9)
+    plain = np.array([b.ev.match(tho[:, s], ttho[:, to[s]]) for s in range(tho.shape[1])])
+    assert np.all(mv >= plain - 1e-9)
+    d2 = ((yo[:, :, None] - tyo[:, None, :]) ** 2).sum(axis=0)
+    near = np.argsort(d2, axis=1, kind="stable")[:, :(n_cand or tyo.shape[1])]
+    inside = np.array([bo[s] in near[s] for s in range(tho.shape[1])])
+    same = to == bo
+    close = np.abs(mv - mo) <= 1e-9
+    assert np.all(same[inside] | close[inside])
+    if n_cand == 0:
+        assert inside.all()
+    ev.close()
+
+
 def _extrinsic_inputs(b, so, n, seed):
     """Tile draws of the oracle over an intrinsic bank (arbitrary finite template values)."""
     tyo, ttho, _ = b.ev.tile_bank(so, 1.0, 5, 1, 2048, 500, 0.002, 30)
