@@ -987,8 +987,6 @@ def intrinsic_match_leg(x, args, steps, prec):
     # the match maximised over the template's time shift too (+-16 steps of dt): the slice's whitening
     # comes from the proposal's marginal over the intrinsic coordinates, in which tc is free
     dt, J = args.imatch_dt, 16
-    binding.tile_assign_match_shift(ev, ty, tth, y[:, :256].contiguous(), th[:, :256].contiguous(), dt, J,
-                                    n_cand=8)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     to_match, mv = binding.tile_assign_match_shift(ev, ty, tth, y, th, dt, J, n_cand=8)

@@ -412,25 +412,26 @@ __global__ __launch_bounds__(256) void k_tile_match(const Rec64* __restrict__ ta
     if (match) match[s] = bm;
 }
 
-// The match maximised over the time shifts tau_j = j dt (|j| <= n_shift) too:
-// for each candidate (one at a time) and each block of 8 shifts, a walk over
-// the bins accumulates O_j = sum_k W_k exp(2 pi i (Psi_s - Psi_t - f_k tau_j)),
-// the block's first rotation from its angle, the next ones by the bin's step
-// exp(-2 pi i f_k dt). MERGE as in k_tile_match.
+// The match maximised over the time shifts tau_j = j dt (|j| <= n_shift) too,
+// one lane per (candidate c, sample s) pair p = c n + s: per block of 8 shifts,
+// a walk over the bins accumulates O_j = sum_k W_k exp(2 pi i (Psi_s - Psi_t -
+// f_k tau_j)), the block's first rotation from its angle, the next ones by the
+// bin's step exp(-2 pi i f_k dt); out[p] = max_j |O_j| / sqrt(P_s P_t).
+// k_pick_shift then takes each sample's best candidate.
 constexpr int kShiftBlock = 8;
 
-template <bool MERGE>
 __global__ __launch_bounds__(256) void k_tile_match_shift(const Rec64* __restrict__ tab, const double* __restrict__ pw,
                                                           int n_det, int64_t K, int64_t n,
                                                           const double* __restrict__ srow, const int* __restrict__ skc,
                                                           const double* __restrict__ snrm, int64_t m,
                                                           const double* __restrict__ trow, const int* __restrict__ tkc,
                                                           const double* __restrict__ tnrm, const int* __restrict__ cand,
-                                                          int n_cand, double dt, int n_shift,
-                                                          int* __restrict__ tile_of, double* __restrict__ match) {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool valid = s < n;
-    const int64_t sl = valid ? s : n - 1;
+                                                          int n_cand, double dt, int n_shift, double* __restrict__ out) {
+    const int64_t np = (int64_t)n_cand * n;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = p < np;
+    const int64_t pl = valid ? p : np - 1;
+    const int64_t sl = pl % n;
     double As[8], B5s, B6s, tcs;
 #pragma unroll
     for (int a = 0; a < 8; ++a) As[a] = srow[a * n + sl];
@@ -440,59 +441,70 @@ __global__ __launch_bounds__(256) void k_tile_match_shift(const Rec64* __restric
     double wd[PE_MAX_DET];
 #pragma unroll
     for (int d = 0; d < PE_MAX_DET; ++d) wd[d] = srow[(kMatchW + d) * n + sl];
-    const int kcs = skc[sl];
+    const int ti = cand[pl];
+    double At[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) At[a] = trow[a * m + ti];
+    const double B5t = trow[8 * m + ti], B6t = trow[9 * m + ti], tct = trow[10 * m + ti];
+    const int kl = min(skc[sl], tkc[ti]);
+    int wk = kl;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wk = max(wk, __shfl_xor(wk, o));
+    wk = __builtin_amdgcn_readfirstlane(wk);
     const int nj = 2 * n_shift + 1;
-    double bm = -1.0;
-    int best = cand[sl];
-    for (int c = 0; c < n_cand; ++c) {
-        const int ti = cand[(int64_t)c * n + sl];
-        double At[8];
+    double mc = 0.0;
+    for (int j0 = 0; j0 < nj; j0 += kShiftBlock) {
+        const double tau0 = (double)(j0 - n_shift) * dt;
+        double orr[kShiftBlock], oi[kShiftBlock];
 #pragma unroll
-        for (int a = 0; a < 8; ++a) At[a] = trow[a * m + ti];
-        const double B5t = trow[8 * m + ti], B6t = trow[9 * m + ti], tct = trow[10 * m + ti];
-        const int kl = min(kcs, tkc[ti]);
-        int wk = kl;
+        for (int q = 0; q < kShiftBlock; ++q) orr[q] = oi[q] = 0.0;
+        for (int k = 0; k < wk; ++k) {
+            const Rec64 r = load_const(tab + k);
+            double w = wd[0] * load_const(pw + k);
+            for (int d = 1; d < n_det; ++d) w = fma(wd[d], load_const(pw + (int64_t)d * K + k), w);
+            const double ps = fma(r.f, tcs, psi_turns(As, B5s, B6s, r.x, r.xm5, r.lnx));
+            const double pt = fma(r.f, tct, psi_turns(At, B5t, B6t, r.x, r.xm5, r.lnx));
+            double sn, cs, rs, rc;
+            sincos_turns(fract64(ps - pt - r.f * tau0), sn, cs);
+            sincos_turns(fract64(-r.f * dt), rs, rc);
+            const double wm = (k < kl) ? w : 0.0;
+            double zr = wm * cs, zi = wm * sn;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) wk = max(wk, __shfl_xor(wk, o));
-        wk = __builtin_amdgcn_readfirstlane(wk);
-        double mc = 0.0;
-        for (int j0 = 0; j0 < nj; j0 += kShiftBlock) {
-            const double tau0 = (double)(j0 - n_shift) * dt;
-            double orr[kShiftBlock], oi[kShiftBlock];
-#pragma unroll
-            for (int q = 0; q < kShiftBlock; ++q) orr[q] = oi[q] = 0.0;
-            for (int k = 0; k < wk; ++k) {
-                const Rec64 r = load_const(tab + k);
-                double w = wd[0] * load_const(pw + k);
-                for (int d = 1; d < n_det; ++d) w = fma(wd[d], load_const(pw + (int64_t)d * K + k), w);
-                const double ps = fma(r.f, tcs, psi_turns(As, B5s, B6s, r.x, r.xm5, r.lnx));
-                const double pt = fma(r.f, tct, psi_turns(At, B5t, B6t, r.x, r.xm5, r.lnx));
-                double sn, cs, rs, rc;
-                sincos_turns(fract64(ps - pt - r.f * tau0), sn, cs);
-                sincos_turns(fract64(-r.f * dt), rs, rc);
-                const double wm = (k < kl) ? w : 0.0;
-                double zr = wm * cs, zi = wm * sn;
-#pragma unroll
-                for (int q = 0; q < kShiftBlock; ++q) {
-                    orr[q] += zr;
-                    oi[q] += zi;
-                    const double nr = zr * rc - zi * rs;
-                    zi = zr * rs + zi * rc;
-                    zr = nr;
-                }
+            for (int q = 0; q < kShiftBlock; ++q) {
+                orr[q] += zr;
+                oi[q] += zi;
+                const double nr = zr * rc - zi * rs;
+                zi = zr * rs + zi * rc;
+                zr = nr;
             }
-#pragma unroll
-            for (int q = 0; q < kShiftBlock; ++q)
-                if (j0 + q < nj) mc = fmax(mc, hypot(orr[q], oi[q]));
         }
-        const double den = snrm[sl] * tnrm[ti];
-        mc = den > 0.0 ? mc / sqrt(den) : 0.0;
+#pragma unroll
+        for (int q = 0; q < kShiftBlock; ++q)
+            if (j0 + q < nj) mc = fmax(mc, hypot(orr[q], oi[q]));
+    }
+    if (!valid) return;
+    const double den = snrm[sl] * tnrm[ti];
+    out[p] = den > 0.0 ? mc / sqrt(den) : 0.0;
+}
+
+// Each sample's best of its n_cand candidates (ties: the lower index); MERGE
+// keeps the better of that and the choice already in tile_of/match.
+template <bool MERGE>
+__global__ __launch_bounds__(256) void k_pick_shift(int64_t n, int n_cand, const int* __restrict__ cand,
+                                                    const double* __restrict__ mcs, int* __restrict__ tile_of,
+                                                    double* __restrict__ match) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    double bm = -1.0;
+    int best = cand[s];
+    for (int c = 0; c < n_cand; ++c) {
+        const int ti = cand[(int64_t)c * n + s];
+        const double mc = mcs[(int64_t)c * n + s];
         if (mc > bm || (mc == bm && ti < best)) {
             bm = mc;
             best = ti;
         }
     }
-    if (!valid) return;
     if (MERGE && !(bm > match[s])) return;
     tile_of[s] = best;
     match[s] = bm;
@@ -945,6 +957,7 @@ static pe_status_t assign_match(pe_event_t ev, int32_t n_tiles, const double* ti
     // scratch: rows, cuts and norms of the templates and samples, the candidates
     const int64_t m = n_tiles;
     const size_t bytes = sizeof(double) * (size_t)(kMatchRow + 1) * (size_t)(m + n) +
+                         (n_shift > 0 ? sizeof(double) * (size_t)8 * (size_t)n : 0) +
                          sizeof(int) * (size_t)(m + n + (int64_t)(n_cand ? n_cand : 8) * n) + 1024;
     char* mem = nullptr;
     pe_status_t s = dalloc_bytes(&mem, bytes);
@@ -956,6 +969,7 @@ static pe_status_t assign_match(pe_event_t ev, int32_t n_tiles, const double* ti
     double* snrm = c.take<double>((size_t)n);
     int* tkc = c.take<int>((size_t)m);
     int* skc = c.take<int>((size_t)n);
+    double* pmc = n_shift > 0 ? c.take<double>((size_t)8 * n) : nullptr;  // matches of the (candidate, sample) pairs
     int* cand = c.take<int>((size_t)(n_cand ? n_cand : 8) * n);
     k_match_rows<<<nblocks(m), 256, 0, st>>>(ev->ec, tiles_theta_dev, ld_tiles, m, ev->pfx, trow, tkc, tnrm);
     k_match_rows<<<nblocks(n), 256, 0, st>>>(ev->ec, theta_dev, ld, n, ev->pfx, srow, skc, snrm);
@@ -968,21 +982,21 @@ static pe_status_t assign_match(pe_event_t ev, int32_t n_tiles, const double* ti
                 case 4: k_tile_topc<4><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand); break;
                 default: k_tile_topc<8><<<nblocks(n), 256, 0, st>>>(n_tiles, tiles_y_dev, ld_tiles, n, y_dev, ld, cand); break;
             }
-            k_tile_match_shift<false><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow,
-                                                                 skc, snrm, m, trow, tkc, tnrm, cand, n_cand, dt,
-                                                                 n_shift, tile_of_dev, match_dev);
+            k_tile_match_shift<<<nblocks((int64_t)n_cand * n), 256, 0, st>>>(
+                ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow, skc, snrm, m, trow, tkc, tnrm, cand, n_cand, dt,
+                n_shift, pmc);
+            k_pick_shift<false><<<nblocks(n), 256, 0, st>>>(n, n_cand, cand, pmc, tile_of_dev, match_dev);
         } else {
             for (int t0 = 0; t0 < n_tiles; t0 += 8) {
                 const int nc = std::min(8, n_tiles - t0);
                 k_fill_cand<<<nblocks(n), 256, 0, st>>>(cand, n, t0, n_tiles);
+                k_tile_match_shift<<<nblocks((int64_t)nc * n), 256, 0, st>>>(
+                    ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow, skc, snrm, m, trow, tkc, tnrm, cand, nc, dt,
+                    n_shift, pmc);
                 if (t0 == 0)
-                    k_tile_match_shift<false><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K,
-                                                                         n, srow, skc, snrm, m, trow, tkc, tnrm, cand,
-                                                                         nc, dt, n_shift, tile_of_dev, match_dev);
+                    k_pick_shift<false><<<nblocks(n), 256, 0, st>>>(n, nc, cand, pmc, tile_of_dev, match_dev);
                 else
-                    k_tile_match_shift<true><<<nblocks(n), 256, 0, st>>>(ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K,
-                                                                        n, srow, skc, snrm, m, trow, tkc, tnrm, cand,
-                                                                        nc, dt, n_shift, tile_of_dev, match_dev);
+                    k_pick_shift<true><<<nblocks(n), 256, 0, st>>>(n, nc, cand, pmc, tile_of_dev, match_dev);
             }
         }
     } else switch (n_cand) {
