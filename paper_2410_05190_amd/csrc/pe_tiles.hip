@@ -426,7 +426,8 @@ __global__ __launch_bounds__(256) void k_tile_match_shift(const Rec64* __restric
                                                           const double* __restrict__ snrm, int64_t m,
                                                           const double* __restrict__ trow, const int* __restrict__ tkc,
                                                           const double* __restrict__ tnrm, const int* __restrict__ cand,
-                                                          int n_cand, double dt, int n_shift, double* __restrict__ out) {
+                                                          int n_cand, double dt, int n_shift,
+                                                          const double2* __restrict__ step, double* __restrict__ out) {
     const int64_t np = (int64_t)n_cand * n;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool valid = p < np;
@@ -464,9 +465,10 @@ __global__ __launch_bounds__(256) void k_tile_match_shift(const Rec64* __restric
             for (int d = 1; d < n_det; ++d) w = fma(wd[d], load_const(pw + (int64_t)d * K + k), w);
             const double ps = fma(r.f, tcs, psi_turns(As, B5s, B6s, r.x, r.xm5, r.lnx));
             const double pt = fma(r.f, tct, psi_turns(At, B5t, B6t, r.x, r.xm5, r.lnx));
-            double sn, cs, rs, rc;
+            double sn, cs;
             sincos_turns(fract64(ps - pt - r.f * tau0), sn, cs);
-            sincos_turns(fract64(-r.f * dt), rs, rc);
+            const double2 rot = load_const(step + k);  // (cos, sin) of -2 pi f_k dt
+            const double rc = rot.x, rs = rot.y;
             const double wm = (k < kl) ? w : 0.0;
             double zr = wm * cs, zi = wm * sn;
 #pragma unroll
@@ -485,6 +487,17 @@ __global__ __launch_bounds__(256) void k_tile_match_shift(const Rec64* __restric
     if (!valid) return;
     const double den = snrm[sl] * tnrm[ti];
     out[p] = den > 0.0 ? mc / sqrt(den) : 0.0;
+}
+
+// The shift step of every bin: (cos, sin) of -2 pi f_k dt, as the walk would
+// form it per bin (the same function of the same argument).
+__global__ __launch_bounds__(256) void k_shift_step(const Rec64* __restrict__ tab, int64_t K, double dt,
+                                                    double2* __restrict__ step) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= K) return;
+    double rs, rc;
+    sincos_turns(fract64(-tab[k].f * dt), rs, rc);
+    step[k] = make_double2(rc, rs);
 }
 
 // Each sample's best of its n_cand candidates (ties: the lower index); MERGE
@@ -954,26 +967,37 @@ static pe_status_t assign_match(pe_event_t ev, int32_t n_tiles, const double* ti
         return fail(PE_ERR_ARG, "NULL pointer");
     if (n == 0) return PE_OK;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    // scratch: rows, cuts and norms of the templates and samples, the candidates
+    // scratch: rows, cuts and norms of the templates and samples, the pairs'
+    // matches and the bins' shift steps (shift search), the candidates; sized by
+    // a measuring pass of the same carving (each buffer 256-byte aligned)
     const int64_t m = n_tiles;
-    const size_t bytes = sizeof(double) * (size_t)(kMatchRow + 1) * (size_t)(m + n) +
-                         (n_shift > 0 ? sizeof(double) * (size_t)8 * (size_t)n : 0) +
-                         sizeof(int) * (size_t)(m + n + (int64_t)(n_cand ? n_cand : 8) * n) + 1024;
+    double *trow, *tnrm, *srow, *snrm, *pmc = nullptr;
+    double2* step = nullptr;
+    int *tkc, *skc, *cand;
+    auto carve = [&](Carver& c) {
+        trow = c.take<double>((size_t)kMatchRow * m);
+        tnrm = c.take<double>((size_t)m);
+        srow = c.take<double>((size_t)kMatchRow * n);
+        snrm = c.take<double>((size_t)n);
+        tkc = c.take<int>((size_t)m);
+        skc = c.take<int>((size_t)n);
+        if (n_shift > 0) {
+            pmc = c.take<double>((size_t)8 * n);
+            step = c.take<double2>((size_t)ev->ec.K);
+        }
+        cand = c.take<int>((size_t)(n_cand ? n_cand : 8) * n);
+    };
+    Carver meas(nullptr);
+    carve(meas);
     char* mem = nullptr;
-    pe_status_t s = dalloc_bytes(&mem, bytes);
+    pe_status_t s = dalloc_bytes(&mem, meas.size());
     if (s != PE_OK) return s;
     Carver c(mem);
-    double* trow = c.take<double>((size_t)kMatchRow * m);
-    double* tnrm = c.take<double>((size_t)m);
-    double* srow = c.take<double>((size_t)kMatchRow * n);
-    double* snrm = c.take<double>((size_t)n);
-    int* tkc = c.take<int>((size_t)m);
-    int* skc = c.take<int>((size_t)n);
-    double* pmc = n_shift > 0 ? c.take<double>((size_t)8 * n) : nullptr;  // matches of the (candidate, sample) pairs
-    int* cand = c.take<int>((size_t)(n_cand ? n_cand : 8) * n);
+    carve(c);
     k_match_rows<<<nblocks(m), 256, 0, st>>>(ev->ec, tiles_theta_dev, ld_tiles, m, ev->pfx, trow, tkc, tnrm);
     k_match_rows<<<nblocks(n), 256, 0, st>>>(ev->ec, theta_dev, ld, n, ev->pfx, srow, skc, snrm);
     if (n_shift > 0) {
+        k_shift_step<<<nblocks(ev->ec.K), 256, 0, st>>>(ev->rec64, ev->ec.K, dt, step);
         // candidates: the n_cand nearest, or every template eight per launch
         if (n_cand > 0) {
             switch (n_cand) {
@@ -984,7 +1008,7 @@ static pe_status_t assign_match(pe_event_t ev, int32_t n_tiles, const double* ti
             }
             k_tile_match_shift<<<nblocks((int64_t)n_cand * n), 256, 0, st>>>(
                 ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow, skc, snrm, m, trow, tkc, tnrm, cand, n_cand, dt,
-                n_shift, pmc);
+                n_shift, step, pmc);
             k_pick_shift<false><<<nblocks(n), 256, 0, st>>>(n, n_cand, cand, pmc, tile_of_dev, match_dev);
         } else {
             for (int t0 = 0; t0 < n_tiles; t0 += 8) {
@@ -992,7 +1016,7 @@ static pe_status_t assign_match(pe_event_t ev, int32_t n_tiles, const double* ti
                 k_fill_cand<<<nblocks(n), 256, 0, st>>>(cand, n, t0, n_tiles);
                 k_tile_match_shift<<<nblocks((int64_t)nc * n), 256, 0, st>>>(
                     ev->rec64, ev->pw, ev->ec.n_det, ev->ec.K, n, srow, skc, snrm, m, trow, tkc, tnrm, cand, nc, dt,
-                    n_shift, pmc);
+                    n_shift, step, pmc);
                 if (t0 == 0)
                     k_pick_shift<false><<<nblocks(n), 256, 0, st>>>(n, nc, cand, pmc, tile_of_dev, match_dev);
                 else
